@@ -1,0 +1,759 @@
+/*
+ * amplitudes.c -- oracle: tree-level |M|^2 for g g -> t tbar + (n_g - 2) g.
+ * Test infrastructure only (see mfo.h).
+ *
+ * Sec. 2.3 of the paper: the matrix element loops over the helicities of
+ * all external particles and adds up their contributions; external
+ * wavefunctions (spinors, polarisation vectors), vertices and propagators
+ * are the building blocks.  Here the amplitude of each helicity
+ * configuration is written in the colour-flow decomposition
+ *     M = g^n sum_sigma (T^{a_sigma1} ... T^{a_sigman})_{i_t j_tbar} A(sigma)
+ * (Mangano-Parke, Phys. Rept. 200 (1991) 301; T = lambda/2), the partial
+ * amplitudes A(sigma) are built by Berends-Giele recursion (Nucl. Phys.
+ * B306 (1988) 759) over ordered gluon subsets with colour-ordered rules
+ * derived from the QCD Lagrangian with D = d - i g T^a A^a, and the colour
+ * sum is  sum_col |M|^2 = g^(2n) A^dagger C A  with C computed by explicit
+ * summation over the Gell-Mann generators.
+ *
+ * Representation: Dirac gamma matrices, spinors quantised along z, gluon
+ * helicity eigenstates.  All particles are outgoing; a crossed incoming
+ * gluon carries momentum -p and the polarisation of the physical gluon.
+ */
+#include <complex.h>
+#include <math.h>
+#include <string.h>
+#include <stdlib.h>
+#include <pthread.h>
+#include "mfo.h"
+
+typedef double complex cplx;
+
+/* ------------------------------------------------------------------------ */
+/* Gell-Mann generators and the colour matrix                                */
+/* ------------------------------------------------------------------------ */
+
+static void gell_mann_T(cplx T[8][3][3])
+{
+    memset(T, 0, sizeof(cplx) * 8 * 9);
+    const double s3 = 1.0 / sqrt(3.0);
+    /* lambda_1 .. lambda_8, then T = lambda / 2 */
+    T[0][0][1] = 1; T[0][1][0] = 1;
+    T[1][0][1] = -I; T[1][1][0] = I;
+    T[2][0][0] = 1; T[2][1][1] = -1;
+    T[3][0][2] = 1; T[3][2][0] = 1;
+    T[4][0][2] = -I; T[4][2][0] = I;
+    T[5][1][2] = 1; T[5][2][1] = 1;
+    T[6][1][2] = -I; T[6][2][1] = I;
+    T[7][0][0] = s3; T[7][1][1] = s3; T[7][2][2] = -2.0 * s3;
+    for (int a = 0; a < 8; ++a)
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j)
+                T[a][i][j] *= 0.5;
+}
+
+static void mat3_mul(cplx A[3][3], cplx B[3][3], cplx C[3][3])
+{
+    cplx tmp[3][3];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            cplx s = 0;
+            for (int l = 0; l < 3; ++l)
+                s += A[i][l] * B[l][j];
+            tmp[i][j] = s;
+        }
+    memcpy(C, tmp, sizeof(tmp));
+}
+
+int mfo_n_orderings(int n_g)
+{
+    int f = 1;
+    for (int i = 2; i <= n_g; ++i)
+        f *= i;
+    return f;
+}
+
+/* All permutations of 0..n-1 in lexicographic order. */
+void mfo_orderings(int n_g, int *perm)
+{
+    int a[MFO_MAX_G + 1];
+    for (int i = 0; i < n_g; ++i)
+        a[i] = i;
+    int count = mfo_n_orderings(n_g);
+    for (int c = 0; c < count; ++c) {
+        memcpy(perm + c * n_g, a, sizeof(int) * n_g);
+        /* next permutation */
+        int i = n_g - 2;
+        while (i >= 0 && a[i] > a[i + 1]) --i;
+        if (i < 0) break;
+        int j = n_g - 1;
+        while (a[j] < a[i]) --j;
+        int t = a[i]; a[i] = a[j]; a[j] = t;
+        for (int l = i + 1, r = n_g - 1; l < r; ++l, --r) {
+            t = a[l]; a[l] = a[r]; a[r] = t;
+        }
+    }
+}
+
+/* C_{sigma sigma'} = sum over all adjoint indices and i, j of
+ * conj((T^sigma)_{ij}) (T^sigma')_{ij}, by brute force over the 8^n
+ * assignments of Gell-Mann generators.  The exact value is a rational
+ * number with denominator dividing 6^n; the sum is rounded to it once. */
+void mfo_colour_matrix(int n_g, double *C)
+{
+    cplx T[8][3][3];
+    gell_mann_T(T);
+    int nperm = mfo_n_orderings(n_g);
+    int *perm = malloc(sizeof(int) * nperm * n_g);
+    mfo_orderings(n_g, perm);
+    double *acc = calloc((size_t)nperm * nperm, sizeof(double));
+    cplx (*P)[3][3] = malloc(sizeof(cplx) * 9 * nperm);
+    int total = 1;
+    for (int i = 0; i < n_g; ++i)
+        total *= 8;
+    int a[MFO_MAX_G];
+    for (int code = 0; code < total; ++code) {
+        int c = code;
+        for (int i = 0; i < n_g; ++i) {
+            a[i] = c % 8;
+            c /= 8;
+        }
+        for (int s = 0; s < nperm; ++s) {
+            const int *sg = perm + s * n_g;
+            memcpy(P[s], T[a[sg[0]]], sizeof(cplx) * 9);
+            for (int l = 1; l < n_g; ++l)
+                mat3_mul(P[s], T[a[sg[l]]], P[s]);
+        }
+        for (int s = 0; s < nperm; ++s)
+            for (int t = 0; t < nperm; ++t) {
+                cplx tr = 0;
+                for (int i = 0; i < 3; ++i)
+                    for (int j = 0; j < 3; ++j)
+                        tr += conj(P[s][i][j]) * P[t][i][j];
+                acc[s * nperm + t] += creal(tr);
+            }
+    }
+    double den = pow(6.0, n_g);
+    for (int s = 0; s < nperm * nperm; ++s)
+        C[s] = nearbyint(acc[s] * den) / den;
+    free(P);
+    free(acc);
+    free(perm);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Dirac algebra                                                             */
+/* ------------------------------------------------------------------------ */
+
+static cplx G[4][4][4];          /* gamma^mu in the Dirac representation */
+static pthread_once_t gamma_once = PTHREAD_ONCE_INIT;
+
+static void fill_gamma(void)
+{
+    memset(G, 0, sizeof(G));
+    G[0][0][0] = 1; G[0][1][1] = 1; G[0][2][2] = -1; G[0][3][3] = -1;
+    /* gamma^k = [[0, sigma_k], [-sigma_k, 0]] */
+    cplx sig[3][2][2] = {
+        { { 0, 1 }, { 1, 0 } },
+        { { 0, -I }, { I, 0 } },
+        { { 1, 0 }, { 0, -1 } },
+    };
+    for (int k = 0; k < 3; ++k)
+        for (int i = 0; i < 2; ++i)
+            for (int j = 0; j < 2; ++j) {
+                G[k + 1][i][j + 2] = sig[k][i][j];
+                G[k + 1][i + 2][j] = -sig[k][i][j];
+            }
+}
+
+static void init_gamma(void)
+{
+    pthread_once(&gamma_once, fill_gamma);
+}
+
+static cplx mdot(const cplx *a, const cplx *b)
+{
+    return a[0] * b[0] - a[1] * b[1] - a[2] * b[2] - a[3] * b[3];
+}
+
+/* slash(a) = gamma^mu a_mu */
+static void slash(const cplx *a, cplx S[4][4])
+{
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j)
+            S[i][j] = a[0] * G[0][i][j] - a[1] * G[1][i][j] - a[2] * G[2][i][j] - a[3] * G[3][i][j];
+}
+
+static void row_times(const cplx *row, cplx M[4][4], cplx *out)
+{
+    cplx t[4];
+    for (int j = 0; j < 4; ++j) {
+        cplx s = 0;
+        for (int i = 0; i < 4; ++i)
+            s += row[i] * M[i][j];
+        t[j] = s;
+    }
+    memcpy(out, t, sizeof(t));
+}
+
+static cplx row_dot_col(const cplx *row, const cplx *col)
+{
+    cplx s = 0;
+    for (int i = 0; i < 4; ++i)
+        s += row[i] * col[i];
+    return s;
+}
+
+/* sigma . p as a 2x2 matrix */
+static void sigma_dot(const double *p, cplx m[2][2])
+{
+    m[0][0] = p[3];
+    m[0][1] = p[1] - I * p[2];
+    m[1][0] = p[1] + I * p[2];
+    m[1][1] = -p[3];
+}
+
+/* ubar(p, s) for an outgoing fermion: u = (sqrt(E+m) chi, (sigma.p) chi / sqrt(E+m)),
+ * ubar = u^dagger gamma^0, chi_0 = (1, 0), chi_1 = (0, 1). */
+static void spinor_ubar(const double *p, double m, int s, cplx *ub)
+{
+    double n = sqrt(p[0] + m);
+    cplx sp[2][2];
+    sigma_dot(p, sp);
+    cplx chi[2] = { s == 0 ? 1 : 0, s == 0 ? 0 : 1 };
+    cplx u[4];
+    u[0] = n * chi[0];
+    u[1] = n * chi[1];
+    u[2] = (sp[0][0] * chi[0] + sp[0][1] * chi[1]) / n;
+    u[3] = (sp[1][0] * chi[0] + sp[1][1] * chi[1]) / n;
+    ub[0] = conj(u[0]);
+    ub[1] = conj(u[1]);
+    ub[2] = -conj(u[2]);
+    ub[3] = -conj(u[3]);
+}
+
+/* v(p, s) for an outgoing antifermion: v = ((sigma.p) eta / sqrt(E+m), sqrt(E+m) eta). */
+static void spinor_v(const double *p, double m, int s, cplx *v)
+{
+    double n = sqrt(p[0] + m);
+    cplx sp[2][2];
+    sigma_dot(p, sp);
+    cplx eta[2] = { s == 0 ? 1 : 0, s == 0 ? 0 : 1 };
+    v[0] = (sp[0][0] * eta[0] + sp[0][1] * eta[1]) / n;
+    v[1] = (sp[1][0] * eta[0] + sp[1][1] * eta[1]) / n;
+    v[2] = n * eta[0];
+    v[3] = n * eta[1];
+}
+
+/* Helicity polarisation vectors transverse to the 3-momentum of p:
+ * eps_pm = (-/+ e1 - i e2)/sqrt(2) with e1 = (0, cos th cos ph, cos th sin ph, -sin th),
+ * e2 = (0, -sin ph, cos ph, 0).  hel 0 -> +, 1 -> -. */
+static void polarisation(const double *p, int hel, cplx *eps)
+{
+    double pt = sqrt(p[1] * p[1] + p[2] * p[2]);
+    double th = atan2(pt, p[3]);
+    double ph = pt > 0.0 ? atan2(p[2], p[1]) : 0.0;
+    double e1[4] = { 0.0, cos(th) * cos(ph), cos(th) * sin(ph), -sin(th) };
+    double e2[4] = { 0.0, -sin(ph), cos(ph), 0.0 };
+    double sgn = hel == 0 ? -1.0 : 1.0;
+    for (int mu = 0; mu < 4; ++mu)
+        eps[mu] = (sgn * e1[mu] - I * e2[mu]) / sqrt(2.0);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Colour-ordered Berends-Giele recursion                                    */
+/* ------------------------------------------------------------------------ */
+
+#define MAXCODE 625    /* codes of ordered gluon sequences, base n+1 <= 5 */
+
+typedef struct {
+    int n;
+    const double *p;           /* [n+2][4] all outgoing: t, tbar, g_1 .. g_n */
+    double m, width;
+    cplx eps[MFO_MAX_G][4];
+    cplx gcur[MAXCODE][4];
+    char gdone[MAXCODE];
+    cplx fcur[MAXCODE][4];
+    char fdone[MAXCODE];
+} bg_state;
+
+static int seq_code(const int *seq, int len, int n)
+{
+    int code = 0, base = 1;
+    for (int t = 0; t < len; ++t) {
+        code += (seq[t] + 1) * base;
+        base *= (n + 1);
+    }
+    return code;
+}
+
+static void seq_momentum(const bg_state *st, const int *seq, int len, double *P)
+{
+    P[0] = P[1] = P[2] = P[3] = 0.0;
+    for (int t = 0; t < len; ++t)
+        for (int mu = 0; mu < 4; ++mu)
+            P[mu] += st->p[4 * (2 + seq[t]) + mu];
+}
+
+static double rdot(const double *a, const double *b)
+{
+    return a[0] * b[0] - a[1] * b[1] - a[2] * b[2] - a[3] * b[3];
+}
+
+/* Colour-ordered gluon current j(seq), off-shell leg propagator included:
+ *   j = -(1/P^2) { sum over splits seq = s1 s2 of
+ *                    j1 ((2P1 + P2).j2) - j2 ((P1 + 2P2).j1) + (P2 - P1)(j1.j2)
+ *                  + sum over splits seq = s1 s2 s3 of
+ *                    j1 (j2.j3) - 2 j2 (j1.j3) + j3 (j1.j2) }            */
+static const cplx *gluon_current(bg_state *st, const int *seq, int len)
+{
+    int code = seq_code(seq, len, st->n);
+    if (st->gdone[code])
+        return st->gcur[code];
+    cplx *out = st->gcur[code];
+    if (len == 1) {
+        memcpy(out, st->eps[seq[0]], sizeof(cplx) * 4);
+        st->gdone[code] = 1;
+        return out;
+    }
+    cplx acc[4] = { 0, 0, 0, 0 };
+    for (int a = 1; a < len; ++a) {
+        const cplx *j1 = gluon_current(st, seq, a);
+        const cplx *j2 = gluon_current(st, seq + a, len - a);
+        double P1[4], P2[4];
+        seq_momentum(st, seq, a, P1);
+        seq_momentum(st, seq + a, len - a, P2);
+        cplx q1[4], q2[4];
+        for (int mu = 0; mu < 4; ++mu) {
+            q1[mu] = 2.0 * P1[mu] + P2[mu];
+            q2[mu] = P1[mu] + 2.0 * P2[mu];
+        }
+        cplx c1 = mdot(q1, j2), c2 = mdot(q2, j1), c12 = mdot(j1, j2);
+        for (int mu = 0; mu < 4; ++mu)
+            acc[mu] += j1[mu] * c1 - j2[mu] * c2 + (P2[mu] - P1[mu]) * c12;
+    }
+    for (int a = 1; a < len; ++a)
+        for (int b = a + 1; b < len; ++b) {
+            const cplx *j1 = gluon_current(st, seq, a);
+            const cplx *j2 = gluon_current(st, seq + a, b - a);
+            const cplx *j3 = gluon_current(st, seq + b, len - b);
+            cplx d23 = mdot(j2, j3), d13 = mdot(j1, j3), d12 = mdot(j1, j2);
+            for (int mu = 0; mu < 4; ++mu)
+                acc[mu] += j1[mu] * d23 - 2.0 * j2[mu] * d13 + j3[mu] * d12;
+        }
+    double P[4];
+    seq_momentum(st, seq, len, P);
+    double P2 = rdot(P, P);
+    for (int mu = 0; mu < 4; ++mu)
+        out[mu] = -acc[mu] / P2;
+    st->gdone[code] = 1;
+    return out;
+}
+
+/* i (P-slash + m) / (P^2 - m^2 + i m Gamma) applied from the right to a row spinor. */
+static void fermion_propagate(const bg_state *st, const double *P, const cplx *row, cplx *out)
+{
+    cplx Pc[4] = { P[0], P[1], P[2], P[3] };
+    cplx S[4][4];
+    slash(Pc, S);
+    for (int i = 0; i < 4; ++i)
+        S[i][i] += st->m;
+    cplx den = rdot(P, P) - st->m * st->m + I * st->m * st->width;
+    cplx t[4];
+    row_times(row, S, t);
+    for (int i = 0; i < 4; ++i)
+        out[i] = I * t[i] / den;
+}
+
+/* Row spinor ubar(k_t) with the ordered gluons seq attached (vertex i gamma.j),
+ * including the propagator of the top line after the last attachment.      */
+static const cplx *fermion_current(bg_state *st, const cplx *ubar, const int *seq, int len)
+{
+    if (len == 0)
+        return ubar;
+    int code = seq_code(seq, len, st->n);
+    if (st->fdone[code])
+        return st->fcur[code];
+    cplx acc[4] = { 0, 0, 0, 0 };
+    for (int a = 0; a < len; ++a) {
+        const cplx *left = fermion_current(st, ubar, seq, a);
+        const cplx *j = gluon_current(st, seq + a, len - a);
+        cplx S[4][4], t[4];
+        slash(j, S);
+        row_times(left, S, t);
+        for (int i = 0; i < 4; ++i)
+            acc[i] += I * t[i];
+    }
+    double P[4];
+    seq_momentum(st, seq, len, P);
+    for (int mu = 0; mu < 4; ++mu)
+        P[mu] += st->p[mu];                 /* + k_t */
+    fermion_propagate(st, P, acc, st->fcur[code]);
+    st->fdone[code] = 1;
+    return st->fcur[code];
+}
+
+static void partial_amplitudes_core(int n, const double *p, double m, double width,
+                                    const int *hel, int ward_gluon, cplx *A)
+{
+    init_gamma();
+    static __thread bg_state st_tls;
+    bg_state *st = &st_tls;
+    st->n = n;
+    st->p = p;
+    st->m = m;
+    st->width = width;
+    memset(st->gdone, 0, sizeof(st->gdone));
+    memset(st->fdone, 0, sizeof(st->fdone));
+    for (int g = 0; g < n; ++g) {
+        if (g == ward_gluon) {
+            for (int mu = 0; mu < 4; ++mu)
+                st->eps[g][mu] = p[4 * (2 + g) + mu];
+        } else {
+            polarisation(p + 4 * (2 + g), hel[2 + g], st->eps[g]);
+        }
+    }
+    cplx ubar[4], v[4];
+    spinor_ubar(p, m, hel[0], ubar);
+    spinor_v(p + 4, m, hel[1], v);
+
+    int nperm = mfo_n_orderings(n);
+    int perm[120 * MFO_MAX_G];
+    mfo_orderings(n, perm);
+    for (int s = 0; s < nperm; ++s) {
+        const int *sg = perm + s * n;
+        cplx amp = 0;
+        for (int a = 0; a < n; ++a) {
+            const cplx *left = fermion_current(st, ubar, sg, a);
+            const cplx *j = gluon_current(st, sg + a, n - a);
+            cplx S[4][4], t[4];
+            slash(j, S);
+            row_times(left, S, t);
+            amp += I * row_dot_col(t, v);
+        }
+        A[s] = amp;
+    }
+}
+
+void mfo_partial_amplitudes(int n_g, const double *p, double m, double width,
+                            const int *hel, int ward_gluon, double *A)
+{
+    cplx amp[120];
+    partial_amplitudes_core(n_g, p, m, width, hel, ward_gluon, amp);
+    for (int s = 0; s < mfo_n_orderings(n_g); ++s) {
+        A[2 * s] = creal(amp[s]);
+        A[2 * s + 1] = cimag(amp[s]);
+    }
+}
+
+static pthread_mutex_t colour_lock = PTHREAD_MUTEX_INITIALIZER;
+static double colour_cache[MFO_MAX_G + 1][24 * 24];
+static int colour_ready[MFO_MAX_G + 1];
+
+static const double *colour_matrix_cached(int n_g)
+{
+    pthread_mutex_lock(&colour_lock);
+    if (!colour_ready[n_g]) {
+        mfo_colour_matrix(n_g, colour_cache[n_g]);
+        colour_ready[n_g] = 1;
+    }
+    pthread_mutex_unlock(&colour_lock);
+    return colour_cache[n_g];
+}
+
+static void hel_from_index(int n_g, int h, int *hel)
+{
+    for (int i = 0; i < n_g + 2; ++i)
+        hel[i] = (h >> i) & 1;
+}
+
+double mfo_me2_sum_hel(int n_g, const double *p, double m, double width,
+                       int n_hel, const int *hel_list)
+{
+    int nperm = mfo_n_orderings(n_g);
+    const double *C = colour_matrix_cached(n_g);
+    double total = 0.0;
+    for (int h = 0; h < n_hel; ++h) {
+        cplx A[120];
+        partial_amplitudes_core(n_g, p, m, width, hel_list + h * (n_g + 2), -1, A);
+        double s = 0.0;
+        for (int a = 0; a < nperm; ++a)
+            for (int b = 0; b < nperm; ++b)
+                s += creal(conj(A[a]) * C[a * nperm + b] * A[b]);
+        total += s;
+    }
+    return total;
+}
+
+double mfo_me2_sum(int n_g, const double *p, double m, double width)
+{
+    int nh = 1 << (n_g + 2);
+    int hel[64 * (MFO_MAX_G + 2)];
+    for (int h = 0; h < nh; ++h)
+        hel_from_index(n_g, h, hel + h * (n_g + 2));
+    return mfo_me2_sum_hel(n_g, p, m, width, nh, hel);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Fully colour-dressed Feynman rules (pin for the colour decomposition)     */
+/* ------------------------------------------------------------------------ */
+/* Rules (Peskin-Schroeder conventions, D = d - i g A^a T^a, g = 1):
+ *   quark-gluon vertex      i gamma^mu T^a
+ *   quark propagator        i (p-slash + m) / (p^2 - m^2 + i m Gamma)
+ *   gluon propagator        -i g_{mu nu} delta^{ab} / p^2       (Feynman gauge)
+ *   3-gluon vertex          f^{abc} [g^{mu nu}(k-p)^rho + g^{nu rho}(p-q)^mu + g^{rho mu}(q-k)^nu]
+ *                           (all momenta incoming)
+ *   4-gluon vertex          -i [f^{abe} f^{cde} (g^{mu rho} g^{nu sigma} - g^{mu sigma} g^{nu rho})
+ *                               + f^{ace} f^{bde} (g^{mu nu} g^{rho sigma} - g^{mu sigma} g^{nu rho})
+ *                               + f^{ade} f^{bce} (g^{mu nu} g^{rho sigma} - g^{mu rho} g^{nu sigma})]
+ * Currents are over unordered gluon subsets, every external colour
+ * assignment is summed explicitly.                                          */
+
+typedef struct {
+    int n;
+    const double *p;
+    double m, width;
+    cplx T[8][3][3];
+    double f[8][8][8];
+    double ff[8][8][8][8];      /* sum_e f^{abe} f^{cde} */
+    cplx eps[MFO_MAX_G][4];
+    int col[MFO_MAX_G];
+    cplx J[1 << MFO_MAX_G][8][4];
+    char Jdone[1 << MFO_MAX_G];
+} fc_state;
+
+static void subset_momentum(const fc_state *st, int S, double *P)
+{
+    P[0] = P[1] = P[2] = P[3] = 0.0;
+    for (int g = 0; g < st->n; ++g)
+        if (S & (1 << g))
+            for (int mu = 0; mu < 4; ++mu)
+                P[mu] += st->p[4 * (2 + g) + mu];
+}
+
+static int is_zero4(const cplx *v)
+{
+    return v[0] == 0 && v[1] == 0 && v[2] == 0 && v[3] == 0;
+}
+
+static void fc_current(fc_state *st, int S)
+{
+    if (st->Jdone[S]) return;
+    cplx (*out)[4] = st->J[S];
+    memset(out, 0, sizeof(cplx) * 32);
+    if ((S & (S - 1)) == 0) {              /* single gluon */
+        int g = __builtin_ctz(S);
+        memcpy(out[st->col[g]], st->eps[g], sizeof(cplx) * 4);
+        st->Jdone[S] = 1;
+        return;
+    }
+    double P[4];
+    subset_momentum(st, S, P);
+    cplx acc[8][4];
+    memset(acc, 0, sizeof(acc));
+    /* 3-gluon vertex: ordered pairs (S1, S2), factor 1/2 */
+    for (int S1 = (S - 1) & S; S1 > 0; S1 = (S1 - 1) & S) {
+        int S2 = S & ~S1;
+        fc_current(st, S1);
+        fc_current(st, S2);
+        double P1[4], P2[4];
+        subset_momentum(st, S1, P1);
+        subset_momentum(st, S2, P2);
+        /* incoming momenta at the vertex: k = P, p = -P1, q = -P2 */
+        cplx kmp[4], qmk[4];
+        double pmq[4];
+        for (int mu = 0; mu < 4; ++mu) {
+            kmp[mu] = P[mu] + P1[mu];
+            pmq[mu] = -P1[mu] + P2[mu];
+            qmk[mu] = -P2[mu] - P[mu];
+        }
+        for (int b = 0; b < 8; ++b) {
+            const cplx *X = st->J[S1][b];
+            if (is_zero4(X)) continue;
+            for (int c = 0; c < 8; ++c) {
+                const cplx *Y = st->J[S2][c];
+                if (is_zero4(Y)) continue;
+                cplx ky = mdot(kmp, Y), xy = mdot(X, Y), qx = mdot(qmk, X);
+                for (int a = 0; a < 8; ++a) {
+                    double fabc = st->f[a][b][c];
+                    if (fabc == 0.0) continue;
+                    for (int mu = 0; mu < 4; ++mu)
+                        acc[a][mu] += 0.5 * fabc * (X[mu] * ky + xy * pmq[mu] + Y[mu] * qx);
+                }
+            }
+        }
+    }
+    /* 4-gluon vertex: ordered triples (S1, S2, S3), factor 1/6 */
+    for (int S1 = (S - 1) & S; S1 > 0; S1 = (S1 - 1) & S) {
+        int R = S & ~S1;
+        for (int S2 = (R - 1) & R; S2 > 0; S2 = (S2 - 1) & R) {
+            int S3 = R & ~S2;
+            fc_current(st, S1);
+            fc_current(st, S2);
+            fc_current(st, S3);
+            for (int b = 0; b < 8; ++b) {
+                const cplx *X = st->J[S1][b];
+                if (is_zero4(X)) continue;
+                for (int c = 0; c < 8; ++c) {
+                    const cplx *Y = st->J[S2][c];
+                    if (is_zero4(Y)) continue;
+                    for (int d = 0; d < 8; ++d) {
+                        const cplx *Z = st->J[S3][d];
+                        if (is_zero4(Z)) continue;
+                        cplx xz = mdot(X, Z), xy = mdot(X, Y), yz = mdot(Y, Z);
+                        for (int a = 0; a < 8; ++a) {
+                            double F1 = st->ff[a][b][c][d];
+                            double F2 = st->ff[a][c][b][d];
+                            double F3 = st->ff[a][d][b][c];
+                            if (F1 == 0.0 && F2 == 0.0 && F3 == 0.0) continue;
+                            for (int mu = 0; mu < 4; ++mu) {
+                                cplx v = F1 * (Y[mu] * xz - Z[mu] * xy)
+                                       + F2 * (X[mu] * yz - Z[mu] * xy)
+                                       + F3 * (X[mu] * yz - Y[mu] * xz);
+                                acc[a][mu] += -I * v / 6.0;
+                            }
+                        }
+                    }
+                }
+            }
+        }
+    }
+    double P2 = rdot(P, P);
+    for (int a = 0; a < 8; ++a)
+        for (int mu = 0; mu < 4; ++mu)
+            out[a][mu] = -I * acc[a][mu] / P2;
+    st->Jdone[S] = 1;
+}
+
+/* K_{c'c}(S) = sum_a (T^a)_{c'c} J^a(S) */
+static void colour_contract(const fc_state *st, int S, cplx K[3][3][4])
+{
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+            for (int mu = 0; mu < 4; ++mu) {
+                cplx s = 0;
+                for (int a = 0; a < 8; ++a)
+                    if (st->T[a][i][j] != 0)
+                        s += st->T[a][i][j] * st->J[S][a][mu];
+                K[i][j][mu] = s;
+            }
+}
+
+double mfo_me2_sum_fullcolour(int n_g, const double *p, double m, double width,
+                              int n_hel, const int *hel_list)
+{
+    init_gamma();
+    fc_state *st = malloc(sizeof(fc_state));
+    st->n = n_g;
+    st->p = p;
+    st->m = m;
+    st->width = width;
+    gell_mann_T(st->T);
+    /* f^{abc} = -2 i Tr([T^a, T^b] T^c) */
+    for (int a = 0; a < 8; ++a)
+        for (int b = 0; b < 8; ++b)
+            for (int c = 0; c < 8; ++c) {
+                cplx AB[3][3], BA[3][3], X[3][3];
+                mat3_mul(st->T[a], st->T[b], AB);
+                mat3_mul(st->T[b], st->T[a], BA);
+                for (int i = 0; i < 3; ++i)
+                    for (int j = 0; j < 3; ++j)
+                        X[i][j] = AB[i][j] - BA[i][j];
+                mat3_mul(X, st->T[c], X);
+                cplx tr = X[0][0] + X[1][1] + X[2][2];
+                double v = creal(-2.0 * I * tr);
+                st->f[a][b][c] = fabs(v) < 1e-14 ? 0.0 : v;
+            }
+    for (int a = 0; a < 8; ++a)
+        for (int b = 0; b < 8; ++b)
+            for (int c = 0; c < 8; ++c)
+                for (int d = 0; d < 8; ++d) {
+                    double s = 0.0;
+                    for (int e = 0; e < 8; ++e)
+                        s += st->f[a][b][e] * st->f[c][d][e];
+                    st->ff[a][b][c][d] = s;
+                }
+    int full = (1 << n_g) - 1;
+    int total_col = 1;
+    for (int i = 0; i < n_g; ++i)
+        total_col *= 8;
+    double total = 0.0;
+    for (int h = 0; h < n_hel; ++h) {
+        const int *hel = hel_list + h * (n_g + 2);
+        for (int g = 0; g < n_g; ++g)
+            polarisation(p + 4 * (2 + g), hel[2 + g], st->eps[g]);
+        cplx ubar[4], v[4];
+        spinor_ubar(p, m, hel[0], ubar);
+        spinor_v(p + 4, m, hel[1], v);
+        for (int code = 0; code < total_col; ++code) {
+            int c = code;
+            for (int g = 0; g < n_g; ++g) {
+                st->col[g] = c % 8;
+                c /= 8;
+            }
+            memset(st->Jdone, 0, sizeof(st->Jdone));
+            /* colour-dressed fermion currents U[S][top colour][line colour][4] */
+            cplx U[1 << MFO_MAX_G][3][3][4];
+            memset(U, 0, sizeof(U));
+            for (int it = 0; it < 3; ++it)
+                memcpy(U[0][it][it], ubar, sizeof(cplx) * 4);
+            /* subsets in increasing order: every proper subset of S precedes S */
+            for (int S = 1; S < full; ++S) {
+                double P[4];
+                subset_momentum(st, S, P);
+                for (int mu = 0; mu < 4; ++mu)
+                    P[mu] += p[mu];
+                cplx acc[3][3][4];
+                memset(acc, 0, sizeof(acc));
+                for (int S2 = S; S2 > 0; S2 = (S2 - 1) & S) {
+                    int S1 = S & ~S2;
+                    fc_current(st, S2);
+                    cplx K[3][3][4];
+                    colour_contract(st, S2, K);
+                    for (int cp = 0; cp < 3; ++cp)
+                        for (int cc = 0; cc < 3; ++cc) {
+                            if (is_zero4(K[cp][cc])) continue;
+                            cplx Sl[4][4];
+                            slash(K[cp][cc], Sl);
+                            for (int it = 0; it < 3; ++it) {
+                                cplx t[4];
+                                row_times(U[S1][it][cp], Sl, t);
+                                for (int i = 0; i < 4; ++i)
+                                    acc[it][cc][i] += I * t[i];
+                            }
+                        }
+                }
+                bg_state tmp;          /* only m, width used by the propagator */
+                tmp.m = m;
+                tmp.width = width;
+                for (int it = 0; it < 3; ++it)
+                    for (int cc = 0; cc < 3; ++cc)
+                        fermion_propagate(&tmp, P, acc[it][cc], U[S][it][cc]);
+            }
+            /* close the line on v(k_tbar) with antitop colour j */
+            cplx Mij[3][3];
+            memset(Mij, 0, sizeof(Mij));
+            for (int S2 = full; S2 > 0; S2 = (S2 - 1) & full) {
+                int S1 = full & ~S2;
+                fc_current(st, S2);
+                cplx K[3][3][4];
+                colour_contract(st, S2, K);
+                for (int cp = 0; cp < 3; ++cp)
+                    for (int jj = 0; jj < 3; ++jj) {
+                        if (is_zero4(K[cp][jj])) continue;
+                        cplx Sl[4][4];
+                        slash(K[cp][jj], Sl);
+                        for (int it = 0; it < 3; ++it) {
+                            cplx t[4];
+                            row_times(U[S1][it][cp], Sl, t);
+                            Mij[it][jj] += I * row_dot_col(t, v);
+                        }
+                    }
+            }
+            for (int it = 0; it < 3; ++it)
+                for (int jj = 0; jj < 3; ++jj)
+                    total += creal(Mij[it][jj] * conj(Mij[it][jj]));
+        }
+    }
+    free(st);
+    return total;
+}

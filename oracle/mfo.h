@@ -1,0 +1,157 @@
+/*
+ * mfo.h -- plain FP64 CPU oracle for the per-event MadFlow integrand
+ * (Carrazza, Cruz-Martinez, Rossi, Zaro, arXiv:2106.10279).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, loads or
+ * calls this code; only the test-suite, the smoke check and the CPU-baseline
+ * leg of the benchmark do.  It shares no source, header, table or constant
+ * with the GPU path.
+ *
+ * The oracle follows the event-generation pipeline of Sec. 2.2 (random
+ * numbers -> phase space -> PDFs -> matrix element -> accumulation), with
+ * VEGAS importance sampling for the integrator (Sec. 1, ingredient (i)), a
+ * flat phase-space generator of the RAMBO family (Sec. 2.4), log-bicubic
+ * PDF interpolation (PDFFlow's role, Sec. 1 ingredient (ii)) and tree-level
+ * helicity amplitudes summed over helicities (Sec. 2.3).  Every function is
+ * written one event at a time, in double precision, for clarity rather than
+ * speed; the library is compiled with -O2 -ffp-contract=off.
+ *
+ * Particle slots (all momenta are 4-vectors (E, px, py, pz), metric +---):
+ *   final state in the partonic centre-of-mass frame: 0 = t, 1 = tbar,
+ *   2.. = final-state gluons.  Amplitude routines take all momenta as
+ *   outgoing: [t, tbar, g_1, ..., g_n] where g_1, g_2 are the crossed
+ *   incoming gluons (momentum -p_a, -p_b).
+ */
+#ifndef MFO_H
+#define MFO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MFO_MAX_G   4          /* gluons in the process (2, 3 or 4)          */
+#define MFO_MAX_F   4          /* final-state particles                      */
+#define MFO_MAX_DIM 10         /* integration dimensions 2 + 3 n_f - 4       */
+
+typedef struct {
+    int    n_g;                /* total gluons: 2 (tt), 3 (ttg), 4 (ttgg)     */
+    double m_top, w_top;       /* GeV                                          */
+    double alpha_s;            /* fixed strong coupling                        */
+    double mu_f;               /* factorisation scale, GeV                     */
+    double ptmin_g;            /* gluon pT cut (GeV); <= 0 disables            */
+    double etamax_g;           /* gluon |eta| cut; <= 0 disables               */
+    double drmin_gg;           /* Delta R between final gluons; <= 0 disables  */
+} mfo_process;
+
+typedef struct {
+    int n_x, n_q2;
+    const double *log_x;       /* [n_x]  ascending ln x knots                  */
+    const double *log_q2;      /* [n_q2] ascending ln Q^2 knots                */
+    const double *xf;          /* [n_q2][n_x] row-major values of x g(x, Q^2)  */
+} mfo_pdf_grid;
+
+typedef struct {
+    double y[MFO_MAX_DIM];     /* uniforms in [0,1)                            */
+    int    bin[MFO_MAX_DIM];   /* VEGAS bin per dimension                      */
+    double x[MFO_MAX_DIM];     /* mapped variables                             */
+    double jac;                /* VEGAS Jacobian J_V                           */
+    double x1, x2, shat;
+    double ps_weight;          /* phase-space weight W (massive)               */
+    double f1, f2;             /* g(x1), g(x2) number densities                */
+    double me2;                /* averaged |M|^2 (with g_s powers)             */
+    double w;                  /* event weight in pb                           */
+    double k[MFO_MAX_F][4];    /* final-state momenta, partonic CM frame       */
+    int    pass_threshold;
+    int    pass_cuts;
+    int    newton_fail;
+    int    near_edge;          /* a cut variable lies within 1e-9 of its cut   */
+} mfo_event;
+
+typedef struct {
+    double sigma, sigma_err, chi2_dof, w_max;
+    int64_t n_pass, n_newton_fail, n_near_edge;
+} mfo_result;
+
+/* ---- random numbers (Philox4x32-10, Salmon et al. SC'11) ---------------- */
+void mfo_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+/* 53-bit integers k_d (uniform y_d = k_d 2^-53) for event e of iteration it. */
+void mfo_event_k53(uint64_t seed, uint32_t iter, uint64_t event, int n_dim, uint64_t *k53);
+void mfo_bin_from_k53(uint64_t k53, int n_bins, int *bin, double *delta);
+
+/* ---- VEGAS ------------------------------------------------------------- */
+double mfo_vegas_map(int n_dim, int n_bins, const double *grid,
+                     const int *bin, const double *delta, double *x);
+void mfo_vegas_refine(int n_dim, int n_bins, double alpha, const double *hist,
+                      const double *grid_in, double *grid_out);
+
+/* ---- phase space -------------------------------------------------------- */
+double mfo_massless_volume(int n_f, double shat);
+/* Returns 0 on success, 1 if the mass-rescaling Newton iteration failed.   */
+int mfo_phase_space(int n_f, const double *mass, double sqrt_shat,
+                    const double *r, int max_newton, double *k, double *weight);
+int mfo_cuts(const mfo_process *proc, int n_f, const double *k, double y_boost,
+             int *near_edge);
+
+/* ---- PDF ---------------------------------------------------------------- */
+double mfo_pdf_xf(const mfo_pdf_grid *g, double x, double q2);
+
+/* ---- colour and matrix element ----------------------------------------- */
+int  mfo_n_orderings(int n_g);
+void mfo_orderings(int n_g, int *perm);           /* [n_g!][n_g], 0-based     */
+void mfo_colour_matrix(int n_g, double *C);       /* [n_g!][n_g!]            */
+/* Colour-ordered partial amplitudes for one helicity configuration.
+ * p: [n_g+2][4] all-outgoing momenta; hel: [n_g+2] (0/1 for each slot);
+ * ward_gluon >= 0 replaces that gluon's polarisation by its momentum.
+ * A: [n_g!][2] (re, im), g_s = 1.                                           */
+void mfo_partial_amplitudes(int n_g, const double *p, double m, double width,
+                            const int *hel, int ward_gluon, double *A);
+/* Sum over helicities and colours of |M|^2 with g_s = 1.                   */
+double mfo_me2_sum(int n_g, const double *p, double m, double width);
+/* Same sum for the listed helicity configurations, computed with fully
+ * colour-dressed Feynman rules and an explicit loop over every external
+ * colour assignment.  Used only to pin the colour decomposition.          */
+double mfo_me2_sum_fullcolour(int n_g, const double *p, double m, double width,
+                              int n_hel, const int *hel_list);
+double mfo_me2_sum_hel(int n_g, const double *p, double m, double width,
+                       int n_hel, const int *hel_list);
+
+/* ---- per-event weight and integration ---------------------------------- */
+int mfo_n_dims(int n_g);
+double mfo_event_weight(const mfo_process *proc, double sqrt_s,
+                        const mfo_pdf_grid *pdf, int n_bins, const double *grid,
+                        uint64_t seed, int iter, uint64_t event, mfo_event *ev);
+/* Same with the uniforms given directly (bin = floor(y n_bins)).           */
+double mfo_event_weight_y(const mfo_process *proc, double sqrt_s,
+                          const mfo_pdf_grid *pdf, int n_bins, const double *grid,
+                          const double *y, mfo_event *ev);
+
+int mfo_integrate(const mfo_process *proc, double sqrt_s, const mfo_pdf_grid *pdf,
+                  uint64_t n_events, int n_iter, uint64_t seed, int start_iter,
+                  int n_bins, double alpha, int n_threads,
+                  double *grid,            /* in/out [n_dim][n_bins+1]           */
+                  double *iter_sigma,      /* [n_iter] or NULL                   */
+                  double *iter_var,        /* [n_iter] or NULL                   */
+                  double *hist_last,       /* [n_dim][n_bins] or NULL            */
+                  double *weights_last,    /* [n_events] or NULL                 */
+                  mfo_result *res);
+
+/* Per-iteration estimates and their inverse-variance combination.         */
+void mfo_combine(int n_iter, const double *est, const double *var,
+                 double *sigma, double *err, double *chi2_dof);
+double mfo_neumaier_sum(int n, const double *v);
+
+/* ---- gradients (g g -> t tbar only) ------------------------------------ */
+/* Analytic d w / d m_t of one event from the closed-form LO |M|^2 at zero
+ * top width, holding the uniforms, the VEGAS grid and mu_F fixed.          */
+double mfo_ttx_dweight_dmt_analytic(const mfo_process *proc, double sqrt_s,
+                                    const mfo_pdf_grid *pdf, int n_bins,
+                                    const double *grid, const double *y,
+                                    double *w_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,369 @@
+"""ctypes binding of oracle/libmfo.so (test infrastructure only)."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libmfo.so")
+_lib = None
+
+_dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int)
+_u32p = C.POINTER(C.c_uint32)
+_u64p = C.POINTER(C.c_uint64)
+
+
+class _Process(C.Structure):
+    _fields_ = [("n_g", C.c_int), ("m_top", C.c_double), ("w_top", C.c_double),
+                ("alpha_s", C.c_double), ("mu_f", C.c_double), ("ptmin_g", C.c_double),
+                ("etamax_g", C.c_double), ("drmin_gg", C.c_double)]
+
+
+class _Pdf(C.Structure):
+    _fields_ = [("n_x", C.c_int), ("n_q2", C.c_int), ("log_x", _dp), ("log_q2", _dp),
+                ("xf", _dp)]
+
+
+class _Event(C.Structure):
+    _fields_ = [("y", C.c_double * 10), ("bin", C.c_int * 10), ("x", C.c_double * 10),
+                ("jac", C.c_double), ("x1", C.c_double), ("x2", C.c_double),
+                ("shat", C.c_double), ("ps_weight", C.c_double), ("f1", C.c_double),
+                ("f2", C.c_double), ("me2", C.c_double), ("w", C.c_double),
+                ("k", C.c_double * 16), ("pass_threshold", C.c_int), ("pass_cuts", C.c_int),
+                ("newton_fail", C.c_int), ("near_edge", C.c_int)]
+
+
+class _Result(C.Structure):
+    _fields_ = [("sigma", C.c_double), ("sigma_err", C.c_double), ("chi2_dof", C.c_double),
+                ("w_max", C.c_double), ("n_pass", C.c_int64), ("n_newton_fail", C.c_int64),
+                ("n_near_edge", C.c_int64)]
+
+
+def build(force: bool = False) -> str:
+    """Compile libmfo.so with the oracle's Makefile (plain gcc)."""
+    if force or not os.path.exists(_LIB_PATH) or _stale():
+        subprocess.run(["make", "-C", _HERE, "-B" if force else "-s", "libmfo.so"],
+                       check=True, capture_output=True)
+    return _LIB_PATH
+
+
+def _stale() -> bool:
+    t = os.path.getmtime(_LIB_PATH)
+    for f in os.listdir(_HERE):
+        if f.endswith((".c", ".h")) and os.path.getmtime(os.path.join(_HERE, f)) > t:
+            return True
+    return False
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = C.CDLL(_LIB_PATH)
+        L.mfo_philox4x32_10.argtypes = [_u32p, _u32p, _u32p]
+        L.mfo_event_k53.argtypes = [C.c_uint64, C.c_uint32, C.c_uint64, C.c_int, _u64p]
+        L.mfo_bin_from_k53.argtypes = [C.c_uint64, C.c_int, _ip, _dp]
+        L.mfo_vegas_map.argtypes = [C.c_int, C.c_int, _dp, _ip, _dp, _dp]
+        L.mfo_vegas_map.restype = C.c_double
+        L.mfo_vegas_refine.argtypes = [C.c_int, C.c_int, C.c_double, _dp, _dp, _dp]
+        L.mfo_massless_volume.argtypes = [C.c_int, C.c_double]
+        L.mfo_massless_volume.restype = C.c_double
+        L.mfo_phase_space.argtypes = [C.c_int, _dp, C.c_double, _dp, C.c_int, _dp, _dp]
+        L.mfo_phase_space.restype = C.c_int
+        L.mfo_cuts.argtypes = [C.POINTER(_Process), C.c_int, _dp, C.c_double, _ip]
+        L.mfo_cuts.restype = C.c_int
+        L.mfo_pdf_xf.argtypes = [C.POINTER(_Pdf), C.c_double, C.c_double]
+        L.mfo_pdf_xf.restype = C.c_double
+        L.mfo_n_orderings.argtypes = [C.c_int]
+        L.mfo_n_orderings.restype = C.c_int
+        L.mfo_orderings.argtypes = [C.c_int, _ip]
+        L.mfo_colour_matrix.argtypes = [C.c_int, _dp]
+        L.mfo_partial_amplitudes.argtypes = [C.c_int, _dp, C.c_double, C.c_double, _ip,
+                                             C.c_int, _dp]
+        L.mfo_me2_sum.argtypes = [C.c_int, _dp, C.c_double, C.c_double]
+        L.mfo_me2_sum.restype = C.c_double
+        L.mfo_me2_sum_hel.argtypes = [C.c_int, _dp, C.c_double, C.c_double, C.c_int, _ip]
+        L.mfo_me2_sum_hel.restype = C.c_double
+        L.mfo_me2_sum_fullcolour.argtypes = [C.c_int, _dp, C.c_double, C.c_double, C.c_int, _ip]
+        L.mfo_me2_sum_fullcolour.restype = C.c_double
+        L.mfo_n_dims.argtypes = [C.c_int]
+        L.mfo_n_dims.restype = C.c_int
+        L.mfo_event_weight.argtypes = [C.POINTER(_Process), C.c_double, C.POINTER(_Pdf),
+                                       C.c_int, _dp, C.c_uint64, C.c_int, C.c_uint64,
+                                       C.POINTER(_Event)]
+        L.mfo_event_weight.restype = C.c_double
+        L.mfo_event_weight_y.argtypes = [C.POINTER(_Process), C.c_double, C.POINTER(_Pdf),
+                                         C.c_int, _dp, _dp, C.POINTER(_Event)]
+        L.mfo_event_weight_y.restype = C.c_double
+        L.mfo_integrate.argtypes = [C.POINTER(_Process), C.c_double, C.POINTER(_Pdf),
+                                    C.c_uint64, C.c_int, C.c_uint64, C.c_int, C.c_int,
+                                    C.c_double, C.c_int, _dp, _dp, _dp, _dp, _dp,
+                                    C.POINTER(_Result)]
+        L.mfo_integrate.restype = C.c_int
+        L.mfo_combine.argtypes = [C.c_int, _dp, _dp, _dp, _dp, _dp]
+        L.mfo_neumaier_sum.argtypes = [C.c_int, _dp]
+        L.mfo_neumaier_sum.restype = C.c_double
+        L.mfo_ttx_dweight_dmt_analytic.argtypes = [C.POINTER(_Process), C.c_double,
+                                                   C.POINTER(_Pdf), C.c_int, _dp, _dp, _dp]
+        L.mfo_ttx_dweight_dmt_analytic.restype = C.c_double
+        _lib = L
+    return _lib
+
+
+def _d(a):
+    return a.ctypes.data_as(_dp)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+@dataclass
+class Process:
+    n_g: int
+    m_top: float = 173.0
+    w_top: float = 1.5
+    alpha_s: float = 0.118
+    mu_f: float = 173.0
+    ptmin_g: float = 0.0
+    etamax_g: float = 0.0
+    drmin_gg: float = 0.0
+
+    def c(self):
+        return _Process(self.n_g, self.m_top, self.w_top, self.alpha_s, self.mu_f,
+                        self.ptmin_g, self.etamax_g, self.drmin_gg)
+
+
+class _PdfHandle:
+    """Keeps the numpy buffers alive while the C struct points into them."""
+
+    def __init__(self, table):
+        self.log_x = _f64(table.log_x)
+        self.log_q2 = _f64(table.log_q2)
+        self.xf = _f64(table.xf)
+        self.c = _Pdf(len(self.log_x), len(self.log_q2), _d(self.log_x), _d(self.log_q2),
+                      _d(self.xf))
+
+
+@dataclass
+class EventInfo:
+    y: np.ndarray
+    bins: np.ndarray
+    x: np.ndarray
+    jac: float
+    shat: float
+    ps_weight: float
+    f1: float
+    f2: float
+    me2: float
+    w: float
+    k: np.ndarray
+    pass_threshold: bool
+    pass_cuts: bool
+    newton_fail: bool
+    near_edge: bool
+
+
+def _event_info(ev, D):
+    return EventInfo(np.array(ev.y[:D]), np.array(ev.bin[:D]), np.array(ev.x[:D]), ev.jac,
+                     ev.shat, ev.ps_weight, ev.f1, ev.f2, ev.me2, ev.w,
+                     np.array(ev.k[:]).reshape(4, 4), bool(ev.pass_threshold),
+                     bool(ev.pass_cuts), bool(ev.newton_fail), bool(ev.near_edge))
+
+
+def n_dims(n_g: int) -> int:
+    return lib().mfo_n_dims(n_g)
+
+
+def philox4x32_10(ctr, key):
+    c = (C.c_uint32 * 4)(*ctr)
+    k = (C.c_uint32 * 2)(*key)
+    o = (C.c_uint32 * 4)()
+    lib().mfo_philox4x32_10(c, k, o)
+    return list(o)
+
+
+def event_k53(seed: int, it: int, event: int, D: int) -> np.ndarray:
+    out = (C.c_uint64 * D)()
+    lib().mfo_event_k53(seed, it, event, D, out)
+    return np.array(out[:], dtype=np.uint64)
+
+
+def bin_from_k53(k: int, n_bins: int):
+    b = C.c_int()
+    dl = C.c_double()
+    lib().mfo_bin_from_k53(int(k), n_bins, C.byref(b), C.byref(dl))
+    return b.value, dl.value
+
+
+def vegas_map(grid, bins, deltas):
+    grid = _f64(grid)
+    D, nb1 = grid.shape
+    b = np.ascontiguousarray(bins, dtype=np.int32)
+    dl = _f64(deltas)
+    x = np.zeros(D)
+    jac = lib().mfo_vegas_map(D, nb1 - 1, _d(grid), b.ctypes.data_as(_ip), _d(dl), _d(x))
+    return x, jac
+
+
+def vegas_refine(hist, grid, alpha=1.5):
+    grid = _f64(grid)
+    hist = _f64(hist)
+    D, nb1 = grid.shape
+    out = np.zeros_like(grid)
+    lib().mfo_vegas_refine(D, nb1 - 1, alpha, _d(hist), _d(grid), _d(out))
+    return out
+
+
+def massless_volume(n_f: int, shat: float) -> float:
+    return lib().mfo_massless_volume(n_f, shat)
+
+
+def phase_space(n_f, masses, sqrt_shat, r, max_newton=50):
+    m = _f64(masses)
+    r = _f64(r)
+    k = np.zeros((n_f, 4))
+    w = C.c_double()
+    st = lib().mfo_phase_space(n_f, _d(m), sqrt_shat, _d(r), max_newton, _d(k), C.byref(w))
+    return k, w.value, st
+
+
+def pdf_xf(table, x, q2):
+    h = _PdfHandle(table)
+    return lib().mfo_pdf_xf(C.byref(h.c), x, q2)
+
+
+def colour_matrix(n_g):
+    n = lib().mfo_n_orderings(n_g)
+    out = np.zeros((n, n))
+    lib().mfo_colour_matrix(n_g, _d(out))
+    return out
+
+
+def orderings(n_g):
+    n = lib().mfo_n_orderings(n_g)
+    out = np.zeros((n, n_g), dtype=np.int32)
+    lib().mfo_orderings(n_g, out.ctypes.data_as(_ip))
+    return out
+
+
+def partial_amplitudes(n_g, p, m, width, hel, ward_gluon=-1):
+    p = _f64(p)
+    h = np.ascontiguousarray(hel, dtype=np.int32)
+    n = lib().mfo_n_orderings(n_g)
+    out = np.zeros(2 * n)
+    lib().mfo_partial_amplitudes(n_g, _d(p), m, width, h.ctypes.data_as(_ip), ward_gluon,
+                                 _d(out))
+    return out[0::2] + 1j * out[1::2]
+
+
+def me2_sum(n_g, p, m, width):
+    p = _f64(p)
+    return lib().mfo_me2_sum(n_g, _d(p), m, width)
+
+
+def all_helicities(n_g):
+    nh = 1 << (n_g + 2)
+    return np.array([[(h >> i) & 1 for i in range(n_g + 2)] for h in range(nh)], dtype=np.int32)
+
+
+def me2_sum_hel(n_g, p, m, width, hels):
+    p = _f64(p)
+    h = np.ascontiguousarray(hels, dtype=np.int32)
+    return lib().mfo_me2_sum_hel(n_g, _d(p), m, width, len(h), h.ctypes.data_as(_ip))
+
+
+def me2_sum_fullcolour(n_g, p, m, width, hels):
+    p = _f64(p)
+    h = np.ascontiguousarray(hels, dtype=np.int32)
+    return lib().mfo_me2_sum_fullcolour(n_g, _d(p), m, width, len(h), h.ctypes.data_as(_ip))
+
+
+def event_weight(proc: Process, sqrt_s, table, grid, seed, it, event):
+    h = _PdfHandle(table)
+    grid = _f64(grid)
+    ev = _Event()
+    pc = proc.c()
+    w = lib().mfo_event_weight(C.byref(pc), sqrt_s, C.byref(h.c), grid.shape[1] - 1,
+                               _d(grid), seed, it, event, C.byref(ev))
+    return w, _event_info(ev, grid.shape[0])
+
+
+def event_weight_y(proc: Process, sqrt_s, table, grid, y):
+    h = _PdfHandle(table)
+    grid = _f64(grid)
+    y = _f64(y)
+    ev = _Event()
+    pc = proc.c()
+    w = lib().mfo_event_weight_y(C.byref(pc), sqrt_s, C.byref(h.c), grid.shape[1] - 1,
+                                 _d(grid), _d(y), C.byref(ev))
+    return w, _event_info(ev, grid.shape[0])
+
+
+@dataclass
+class IntegrationResult:
+    sigma: float
+    sigma_err: float
+    chi2_dof: float
+    w_max: float
+    n_pass: int
+    n_newton_fail: int
+    n_near_edge: int
+    iter_sigma: np.ndarray
+    iter_var: np.ndarray
+    grid: np.ndarray
+    hist_last: np.ndarray
+    weights_last: np.ndarray | None
+
+
+def integrate(proc: Process, sqrt_s, table, n_events, n_iter, seed, n_bins=50, alpha=1.5,
+              n_threads=None, grid=None, start_iter=0, keep_weights=True):
+    D = n_dims(proc.n_g)
+    if grid is None:
+        grid = np.tile(np.arange(n_bins + 1) / n_bins, (D, 1))
+    grid = np.array(grid, dtype=np.float64, copy=True, order="C")
+    if n_threads is None:
+        n_threads = max(1, min(os.cpu_count() or 1, 16))
+    h = _PdfHandle(table)
+    I = np.zeros(n_iter)
+    V = np.zeros(n_iter)
+    hist = np.zeros((D, n_bins))
+    w = np.zeros(n_events) if keep_weights else None
+    res = _Result()
+    pc = proc.c()
+    st = lib().mfo_integrate(C.byref(pc), sqrt_s, C.byref(h.c), n_events, n_iter, seed,
+                             start_iter, n_bins, alpha, n_threads, _d(grid), _d(I), _d(V),
+                             _d(hist), _d(w) if w is not None else None, C.byref(res))
+    if st != 0:
+        raise ValueError("oracle rejected the arguments")
+    return IntegrationResult(res.sigma, res.sigma_err, res.chi2_dof, res.w_max, res.n_pass,
+                             res.n_newton_fail, res.n_near_edge, I, V, grid, hist, w)
+
+
+def combine(I, V):
+    I = _f64(I)
+    V = _f64(V)
+    s, e, c = C.c_double(), C.c_double(), C.c_double()
+    lib().mfo_combine(len(I), _d(I), _d(V), C.byref(s), C.byref(e), C.byref(c))
+    return s.value, e.value, c.value
+
+
+def neumaier_sum(v):
+    v = _f64(v)
+    return lib().mfo_neumaier_sum(len(v), _d(v))
+
+
+def ttx_dweight_dmt_analytic(proc: Process, sqrt_s, table, grid, y):
+    h = _PdfHandle(table)
+    grid = _f64(grid)
+    y = _f64(y)
+    w = C.c_double()
+    pc = proc.c()
+    g = lib().mfo_ttx_dweight_dmt_analytic(C.byref(pc), sqrt_s, C.byref(h.c),
+                                           grid.shape[1] - 1, _d(grid), _d(y), C.byref(w))
+    return g, w.value

@@ -1,0 +1,99 @@
+"""Pins for the oracle's phase-space generator (RAMBO family, Sec. 2.4)."""
+import math
+
+import numpy as np
+import pytest
+from scipy import integrate as si
+
+import oracle as O
+
+M = 173.0
+
+
+def minkowski(a, b):
+    return a[0] * b[0] - a[1] * b[1] - a[2] * b[2] - a[3] * b[3]
+
+
+def test_massless_volume_closed_form():
+    # (2 pi)^(4-3n) (pi/2)^(n-1) s^(n-2) / ((n-1)! (n-2)!) evaluated by hand
+    assert abs(O.massless_volume(2, 7.0) - 1 / (8 * math.pi)) < 1e-17
+    assert abs(O.massless_volume(3, 1.0) - 1 / (256 * math.pi**3)) < 1e-19
+    assert abs(O.massless_volume(4, 1.0) - 1 / (24576 * math.pi**5)) < 1e-22
+    assert abs(O.massless_volume(3, 1.0) / 1.25983e-4 - 1) < 1e-5
+    assert abs(O.massless_volume(4, 2.0) / (1.32966e-7 * 4) - 1) < 1e-5
+
+
+@pytest.mark.parametrize("n_f", [2, 3, 4])
+def test_momentum_conservation_and_mass_shell(n_f):
+    rng = np.random.default_rng(n_f)
+    masses = [M, M] + [0.0] * (n_f - 2)
+    for _ in range(300):
+        rs = 2 * M + rng.exponential(400.0) + 1e-3
+        k, w, st = O.phase_space(n_f, masses, rs, rng.random(3 * n_f - 4))
+        assert st == 0 and w > 0
+        tot = k.sum(axis=0)
+        assert abs(tot[0] - rs) < 1e-12 * rs
+        assert np.all(np.abs(tot[1:]) < 1e-12 * rs)
+        for i in range(n_f):
+            assert abs(minkowski(k[i], k[i]) - masses[i] ** 2) < 1e-10 * rs**2
+            assert k[i][0] > 0
+
+
+def test_two_body_massive_weight_is_beta_over_8pi():
+    rng = np.random.default_rng(2)
+    for _ in range(200):
+        rs = 2 * M + rng.exponential(300.0) + 1e-6
+        k, w, st = O.phase_space(2, [M, M], rs, rng.random(2))
+        beta = math.sqrt(1 - 4 * M * M / rs**2)
+        assert abs(w / (beta / (8 * math.pi)) - 1) < 1e-13
+        assert abs(math.sqrt(k[0][1] ** 2 + k[0][2] ** 2 + k[0][3] ** 2) - beta * rs / 2) < 1e-12 * rs
+
+
+@pytest.mark.parametrize("n_f", [3, 4])
+def test_massless_generator_is_flat(n_f):
+    """Flat massless phase space: <s_ij> = 2 s/(n(n-1)) for every pair; for n = 3
+    the Dalitz plot is uniform so <s_ij^2> = s^2 / 6."""
+    rng = np.random.default_rng(10 + n_f)
+    N = 20000
+    s_ij = np.zeros((N, n_f, n_f))
+    for e in range(N):
+        k, w, st = O.phase_space(n_f, [0.0] * n_f, 1.0, rng.random(3 * n_f - 4))
+        assert abs(w - O.massless_volume(n_f, 1.0)) < 1e-18
+        for i in range(n_f):
+            for j in range(i + 1, n_f):
+                s_ij[e, i, j] = 2 * minkowski(k[i], k[j])
+    expect = 2.0 / (n_f * (n_f - 1))
+    for i in range(n_f):
+        for j in range(i + 1, n_f):
+            v = s_ij[:, i, j]
+            assert abs(v.mean() - expect) < 5 * v.std() / math.sqrt(N)
+            if n_f == 3:
+                assert abs((v**2).mean() - 1 / 6) < 5 * (v**2).std() / math.sqrt(N)
+
+
+def test_three_body_massive_volume_matches_dalitz_quadrature():
+    """Phi_3 = (1/(128 pi^3 s)) x (Dalitz-plot area in (m12^2, m23^2))."""
+    rs, m1, m2, m3 = 1000.0, M, M, 0.0
+    s = rs * rs
+
+    def m23_range(m12sq):
+        m12 = math.sqrt(m12sq)
+        e2 = (m12sq - m1 * m1 + m2 * m2) / (2 * m12)
+        e3 = (s - m12sq - m3 * m3) / (2 * m12)
+        p2 = math.sqrt(max(e2 * e2 - m2 * m2, 0.0))
+        p3 = math.sqrt(max(e3 * e3 - m3 * m3, 0.0))
+        return (e2 + e3) ** 2 - (p2 + p3) ** 2, (e2 + e3) ** 2 - (p2 - p3) ** 2
+
+    area, _ = si.quad(lambda m12sq: np.subtract(*m23_range(m12sq)[::-1]),
+                      (m1 + m2) ** 2, (rs - m3) ** 2, epsabs=0, epsrel=1e-12, limit=200)
+    exact = area / (128 * math.pi**3 * s)
+    rng = np.random.default_rng(99)
+    N = 40000
+    ws = np.array([O.phase_space(3, [m1, m2, m3], rs, rng.random(5))[1] for _ in range(N)])
+    assert abs(ws.mean() - exact) < 4 * ws.std() / math.sqrt(N)
+    assert abs(exact - 74.856) < 0.01
+
+
+def test_newton_failure_is_reported():
+    k, w, st = O.phase_space(3, [M, M, 0.0], 600.0, np.full(5, 0.3), max_newton=0)
+    assert st == 1 and w == 0.0
