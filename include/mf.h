@@ -1,0 +1,166 @@
+/*
+ * mf.h -- C ABI of libmadflow_mi355x: the per-event VEGAS / phase-space /
+ * PDF / |M|^2 integrand of MadFlow (Carrazza, Cruz-Martinez, Rossi, Zaro,
+ * arXiv:2106.10279) for g g -> t tbar + 0, 1, 2 gluons on one AMD MI355X.
+ *
+ * The paper's user-level operation (abstract; Fig. 1 of Sec. 2.2) is: take a
+ * process at a hadronic sqrt(s) with PDFs, integrate it with VEGAS and return
+ * the cross section and the events.  Each event runs the pipeline of
+ * Sec. 2.2: random numbers -> phase space (RAMBO family, Sec. 2.4) -> PDFs
+ * -> matrix element summed over helicities (Sec. 2.3) -> weight and
+ * histogram accumulation; the VEGAS grid is refined after every iteration.
+ *
+ * Conventions for every entry point:
+ *   - All functions are extern "C", never throw, and return mf_status.
+ *     On a non-OK status mf_last_error() returns a message (thread-local);
+ *     scalar outputs are then untouched and array contents are unspecified.
+ *   - "host" pointers are ordinary CPU memory, "device" pointers are HIP
+ *     device memory on the current device.  The caller owns every buffer;
+ *     the library keeps no pointer after returning.
+ *   - Work is enqueued on options->stream (a hipStream_t; NULL = the null
+ *     stream).  Calls that return host results synchronise that stream.
+ *   - Validation happens on the host before any device call, so argument
+ *     errors are reported without touching the GPU.
+ */
+#ifndef MF_H
+#define MF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MF_OK = 0,
+    MF_EINVAL = -1,          /* invalid argument                                   */
+    MF_ENOMEM = -2,          /* device allocation failed or size overflow          */
+    MF_EDEVICE = -3,         /* HIP runtime error / no device                      */
+    MF_ENOCONV = -4,         /* strict mode: mass-rescaling Newton did not converge */
+    MF_EUNSUPPORTED = -5     /* valid request the library does not implement       */
+} mf_status;
+
+/* Processes: g g -> t tbar + (n_g - 2) gluons. */
+typedef enum { MF_GG_TTX = 0, MF_GG_TTXG = 1, MF_GG_TTXGG = 2 } mf_process_id;
+
+/* Arithmetic of the helicity amplitudes and colour sum.  Everything else
+ * (VEGAS, phase space, PDF, accumulation, refinement) is FP64 in both. */
+typedef enum { MF_FP64 = 0, MF_FP32_KAHAN = 1 } mf_precision;
+
+typedef struct {
+    mf_process_id id;
+    double m_top;            /* GeV, > 0                                       */
+    double w_top;            /* GeV, >= 0; width in internal top propagators   */
+    double alpha_s;          /* fixed strong coupling, > 0                     */
+    double mu_f;             /* factorisation scale in GeV (mu_F^2 in the grid) */
+    double ptmin_g;          /* final-gluon pT cut in GeV; <= 0 disables       */
+    double etamax_g;         /* final-gluon |eta| (lab) cut; <= 0 disables     */
+    double drmin_gg;         /* Delta R between final gluons; <= 0 disables    */
+} mf_process;
+
+/* PDF table x g(x, Q^2) on knots ascending in ln x and ln Q^2 (host memory,
+ * copied to the device by every call that takes it). */
+typedef struct {
+    int n_x, n_q2;           /* 4 <= n_x <= 256, 4 <= n_q2 <= 4096            */
+    const double *log_x;     /* host [n_x]                                     */
+    const double *log_q2;    /* host [n_q2]                                    */
+    const double *xf;        /* host [n_q2][n_x], row-major                    */
+} mf_pdf_grid;
+
+typedef struct {
+    int n_bins;              /* VEGAS bins per dimension, 2 .. 1024 (50)        */
+    double alpha;            /* grid damping exponent, > 0 (1.5)                */
+    int start_iter;          /* first iteration index in the Philox counter (0) */
+    mf_precision precision;  /* MF_FP64 or MF_FP32_KAHAN                        */
+    int strict;              /* 1: any Newton failure returns MF_ENOCONV        */
+    int max_newton;          /* Newton step cap for the mass rescaling (50)     */
+    const double *grid_in;   /* host [D][n_bins+1] start grid, NULL = uniform   */
+    void *stream;            /* hipStream_t or NULL                             */
+} mf_options;
+
+typedef struct {
+    double sigma, sigma_err, chi2_dof;   /* combined estimate, pb               */
+    double w_max;                        /* largest weight, last iteration      */
+    double *iter_sigma;      /* host [n_iter] per-iteration I_j, may be NULL    */
+    double *iter_var;        /* host [n_iter] per-iteration V_j, may be NULL    */
+    double *grid;            /* host [D][n_bins+1] refined grid out, may be NULL */
+    double *hist;            /* host [D][n_bins] last-iteration sum w^2 per bin, may be NULL */
+    double *weights;         /* device [n_events] last-iteration weights, may be NULL */
+    int64_t n_pass;          /* events passing threshold and cuts, last iteration */
+    int64_t n_newton_fail;   /* Newton failures summed over all iterations      */
+} mf_result;
+
+/* Fills *opt with the defaults shown above. */
+void mf_default_options(mf_options *opt);
+
+/* Number of integration dimensions D = 2 + 3 n_f - 4 (4, 7, 10), or -1. */
+int mf_n_dims(int process_id);
+
+/*
+ * mf_integrate -- VEGAS integration of the hadronic cross section.
+ *   proc, pdf:  process and PDF table (host).
+ *   sqrt_s:     hadronic centre-of-mass energy in GeV, > 2 m_top.
+ *   n_events:   events per iteration, 2 .. 2^40.
+ *   n_iter:     iterations, 1 .. 256.  The grid is refined after each one.
+ *   seed:       Philox key.  Event e of iteration j uses the counter
+ *               (e mod 2^32, e >> 32, start_iter + j, block).
+ * Per iteration: I_j = mean weight, V_j = (mean w^2 - I_j^2)/(N - 1);
+ * combined: inverse-variance weighted mean, its error, chi^2/dof.
+ */
+mf_status mf_integrate(const mf_process *proc, double sqrt_s, const mf_pdf_grid *pdf,
+                       uint64_t n_events, int n_iter, uint64_t seed,
+                       const mf_options *opt, mf_result *res);
+
+/*
+ * mf_evaluate -- per-event weights for a fixed grid (no accumulation).
+ *   grid:      host [D][n_bins+1], NULL = uniform.
+ *   y:         device [n][D] uniforms in [0,1), or NULL to draw them from
+ *              Philox(seed, iter, event); with explicit y the bin is
+ *              floor(y n_bins) and the position inside it y n_bins - bin.
+ *   event_ids: device [n] event indices for the Philox counter, or NULL
+ *              for 0 .. n-1 (ignored when y is given).
+ *   w_out:     device [n] weights in pb.
+ *   k53_out:   device [n][D] 53-bit integers behind the uniforms, or NULL.
+ *   bins_out:  device [n][D] VEGAS bin indices, or NULL.
+ *   record_out: device [n][8 + 4 n_f] per-stage record, or NULL:
+ *              x1, x2, J_V, phase-space weight W, g(x1), g(x2),
+ *              sum over helicities and colours of |M|^2 at g_s = 1,
+ *              flags (bit 0: above threshold, bit 1: Newton failed,
+ *              bit 2: passed the cuts), then the final-state momenta
+ *              t, tbar, gluons in the partonic CM frame (zero when not
+ *              generated).
+ */
+mf_status mf_evaluate(const mf_process *proc, double sqrt_s, const mf_pdf_grid *pdf,
+                      const double *grid, const double *y, const uint64_t *event_ids,
+                      uint64_t n, uint64_t seed, int iter, const mf_options *opt,
+                      double *w_out, uint64_t *k53_out, int32_t *bins_out,
+                      double *record_out);
+
+/*
+ * mf_refine_grid -- one VEGAS refinement step on the device.
+ *   hist: device [D][n_bins] sum of w^2 per bin; grid_in, grid_out: device
+ *   [D][n_bins+1].  Smoothing with the neighbours, damping
+ *   ((1 - rho)/(-ln rho))^alpha, equal-share rebinning.
+ */
+mf_status mf_refine_grid(int n_dims, int n_bins, double alpha, const double *hist,
+                         const double *grid_in, double *grid_out, void *stream);
+
+/* Colour matrix C[s][t] (host out, [n!][n!]) of the process, orderings of the
+ * gluons in lexicographic order, generators T = lambda/2. */
+mf_status mf_colour_matrix(int process_id, double *C);
+
+/* Colour- and helicity-summed |M|^2 with g_s = 1 for explicit momenta:
+ *   mom: device [n][4 (t) + 4 (tbar) + 4 (n_g-2) (final gluons)] in the
+ *        partonic CM frame with the beams along +z/-z; eb: device [n] beam
+ *        energies sqrt(s_hat)/2.  out: device [n]. */
+mf_status mf_matrix_element(int process_id, mf_precision precision, const double *mom,
+                            const double *eb, uint64_t n, double m_top, double w_top,
+                            double *out, void *stream);
+
+/* Message for the last non-OK status on this thread. */
+const char *mf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MF_H */

@@ -63,6 +63,22 @@ static double factorial(int n)
     return f;
 }
 
+/* Where the interpolated x g(x) passes close to zero (the cubic overshoots
+ * below zero in the last interval towards x = 1) its relative value is
+ * ill-conditioned: |d ln(x g)/d ln x| above 1e3 means that a one-ulp change
+ * of ln x moves the result by more than ~1e-13.  Estimated by a central
+ * difference of the interpolant itself with relative step 1e-7 in x. */
+static int pdf_ill_conditioned(const mfo_pdf_grid *pdf, double x, double q2)
+{
+    double h = 1e-7;
+    double up = mfo_pdf_xf(pdf, x * (1.0 + h), q2);
+    double dn = mfo_pdf_xf(pdf, x * (1.0 - h), q2);
+    if (up == 0.0 || dn == 0.0 || (up > 0.0) != (dn > 0.0))
+        return 1;
+    double kappa = fabs(log(fabs(up)) - log(fabs(dn))) / (2.0 * h);
+    return kappa > 1e3;
+}
+
 /* Everything after the VEGAS map: x = mapped variables, jac = J_V. */
 static double weight_from_x(const mfo_process *proc, double sqrt_s,
                             const mfo_pdf_grid *pdf, double jac, mfo_event *ev)
@@ -78,6 +94,7 @@ static double weight_from_x(const mfo_process *proc, double sqrt_s,
     ev->pass_cuts = 0;
     ev->newton_fail = 0;
     ev->near_edge = 0;
+    ev->ill_conditioned = 0;
     ev->ps_weight = ev->f1 = ev->f2 = ev->me2 = 0.0;
     ev->w = 0.0;
     memset(ev->k, 0, sizeof(ev->k));
@@ -107,6 +124,7 @@ static double weight_from_x(const mfo_process *proc, double sqrt_s,
     double q2 = proc->mu_f * proc->mu_f;
     ev->f1 = mfo_pdf_xf(pdf, ev->x1, q2) / ev->x1;
     ev->f2 = mfo_pdf_xf(pdf, ev->x2, q2) / ev->x2;
+    ev->ill_conditioned = pdf_ill_conditioned(pdf, ev->x1, q2) || pdf_ill_conditioned(pdf, ev->x2, q2);
 
     /* All-outgoing momenta for the amplitude: t, tbar, -p_a, -p_b, gluons. */
     double p[(MFO_MAX_G + 2) * 4];

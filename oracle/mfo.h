@@ -68,6 +68,7 @@ typedef struct {
     int    pass_cuts;
     int    newton_fail;
     int    near_edge;          /* a cut variable lies within 1e-9 of its cut   */
+    int    ill_conditioned;    /* |d ln(x g) / d ln x| > 1e3 at x1 or x2      */
 } mfo_event;
 
 typedef struct {

@@ -35,7 +35,7 @@ class _Event(C.Structure):
                 ("shat", C.c_double), ("ps_weight", C.c_double), ("f1", C.c_double),
                 ("f2", C.c_double), ("me2", C.c_double), ("w", C.c_double),
                 ("k", C.c_double * 16), ("pass_threshold", C.c_int), ("pass_cuts", C.c_int),
-                ("newton_fail", C.c_int), ("near_edge", C.c_int)]
+                ("newton_fail", C.c_int), ("near_edge", C.c_int), ("ill_conditioned", C.c_int)]
 
 
 class _Result(C.Structure):
@@ -167,13 +167,15 @@ class EventInfo:
     pass_cuts: bool
     newton_fail: bool
     near_edge: bool
+    ill_conditioned: bool
 
 
 def _event_info(ev, D):
     return EventInfo(np.array(ev.y[:D]), np.array(ev.bin[:D]), np.array(ev.x[:D]), ev.jac,
                      ev.shat, ev.ps_weight, ev.f1, ev.f2, ev.me2, ev.w,
                      np.array(ev.k[:]).reshape(4, 4), bool(ev.pass_threshold),
-                     bool(ev.pass_cuts), bool(ev.newton_fail), bool(ev.near_edge))
+                     bool(ev.pass_cuts), bool(ev.newton_fail), bool(ev.near_edge),
+                     bool(ev.ill_conditioned))
 
 
 def n_dims(n_g: int) -> int:

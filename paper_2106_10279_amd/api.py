@@ -1,0 +1,193 @@
+"""Python API over the C ABI: torch tensors for device memory and streams.
+
+    integrate(...)          VEGAS integration (mf_integrate)
+    evaluate_weights(...)   per-event weights for a fixed grid (mf_evaluate)
+    matrix_element(...)     colour/helicity-summed |M|^2 for given momenta
+    refine_grid(...)        one VEGAS refinement step (mf_refine_grid)
+    colour_matrix(...)      the process colour matrix
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import MF_FP32_KAHAN, MF_FP64, check, lib
+
+PROCESS_IDS = {"gg_ttx": _lib.MF_GG_TTX, "gg_ttxg": _lib.MF_GG_TTXG, "gg_ttxgg": _lib.MF_GG_TTXGG,
+               2: _lib.MF_GG_TTX, 3: _lib.MF_GG_TTXG, 4: _lib.MF_GG_TTXGG}
+PRECISIONS = {"fp64": MF_FP64, "fp32_kahan": MF_FP32_KAHAN}
+
+_dp = C.POINTER(C.c_double)
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(_dp)
+
+
+def _stream(stream):
+    if stream is None:
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    return C.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+@dataclass
+class Process:
+    process: str | int = "gg_ttx"
+    m_top: float = 173.0
+    w_top: float = 1.5
+    alpha_s: float = 0.118
+    mu_f: float = 173.0
+    ptmin_g: float = 0.0
+    etamax_g: float = 0.0
+    drmin_gg: float = 0.0
+
+    @property
+    def id(self) -> int:
+        return PROCESS_IDS[self.process]
+
+    def c(self):
+        return _lib.mf_process(self.id, self.m_top, self.w_top, self.alpha_s, self.mu_f,
+                               self.ptmin_g, self.etamax_g, self.drmin_gg)
+
+
+class _Pdf:
+    def __init__(self, table):
+        self.log_x = np.ascontiguousarray(table.log_x, dtype=np.float64)
+        self.log_q2 = np.ascontiguousarray(table.log_q2, dtype=np.float64)
+        self.xf = np.ascontiguousarray(table.xf, dtype=np.float64)
+        self.c = _lib.mf_pdf_grid(len(self.log_x), len(self.log_q2), _ptr(self.log_x),
+                                  _ptr(self.log_q2), _ptr(self.xf))
+
+
+def n_dims(process) -> int:
+    return lib.mf_n_dims(PROCESS_IDS[process])
+
+
+def _options(n_bins, alpha, start_iter, precision, strict, max_newton, grid_in, stream):
+    o = _lib.mf_options()
+    lib.mf_default_options(C.byref(o))
+    o.n_bins = n_bins
+    o.alpha = alpha
+    o.start_iter = start_iter
+    o.precision = PRECISIONS.get(precision, precision)
+    o.strict = int(strict)
+    o.max_newton = max_newton
+    o.grid_in = _ptr(grid_in) if grid_in is not None else None
+    o.stream = _stream(stream)
+    return o
+
+
+@dataclass
+class IntegrationResult:
+    sigma: float
+    sigma_err: float
+    chi2_dof: float
+    w_max: float
+    n_pass: int
+    n_newton_fail: int
+    iter_sigma: np.ndarray
+    iter_var: np.ndarray
+    grid: np.ndarray
+    hist: np.ndarray
+    weights: torch.Tensor | None
+
+
+def integrate(proc: Process, sqrt_s: float, pdf_table, n_events: int, n_iter: int, seed: int,
+              n_bins: int = 50, alpha: float = 1.5, precision="fp64", start_iter: int = 0,
+              grid_in=None, keep_weights: bool = True, strict: bool = False,
+              max_newton: int = 50, stream=None, weights_out: torch.Tensor | None = None):
+    D = n_dims(proc.process)
+    pdf = _Pdf(pdf_table)
+    gin = None if grid_in is None else np.ascontiguousarray(grid_in, dtype=np.float64)
+    opt = _options(n_bins, alpha, start_iter, precision, strict, max_newton, gin, stream)
+    I = np.zeros(n_iter)
+    V = np.zeros(n_iter)
+    grid = np.zeros((D, n_bins + 1))
+    hist = np.zeros((D, n_bins))
+    w = weights_out
+    if w is None and keep_weights:
+        w = torch.empty(n_events, dtype=torch.float64, device="cuda")
+    res = _lib.mf_result()
+    res.iter_sigma = _ptr(I)
+    res.iter_var = _ptr(V)
+    res.grid = _ptr(grid)
+    res.hist = _ptr(hist)
+    res.weights = C.cast(C.c_void_p(w.data_ptr()), _dp) if w is not None else None
+    pc = proc.c()
+    check(lib.mf_integrate(C.byref(pc), sqrt_s, C.byref(pdf.c), n_events, n_iter, seed,
+                           C.byref(opt), C.byref(res)))
+    return IntegrationResult(res.sigma, res.sigma_err, res.chi2_dof, res.w_max, res.n_pass,
+                             res.n_newton_fail, I, V, grid, hist, w)
+
+
+def evaluate_weights(proc: Process, sqrt_s: float, pdf_table, n: int, seed: int = 0, it: int = 0,
+                     grid=None, y: torch.Tensor | None = None,
+                     event_ids: torch.Tensor | None = None, n_bins: int = 50,
+                     precision="fp64", max_newton: int = 50, return_k53: bool = False,
+                     return_bins: bool = False, return_record: bool = False, stream=None):
+    """Per-event weights (pb) for a fixed grid; optionally the Philox integers,
+    the bin indices and the per-stage record (see mf_evaluate in include/mf.h)."""
+    D = n_dims(proc.process)
+    pdf = _Pdf(pdf_table)
+    g = None if grid is None else np.ascontiguousarray(grid, dtype=np.float64)
+    opt = _options(n_bins, 1.5, 0, precision, False, max_newton, None, stream)
+    w = torch.empty(n, dtype=torch.float64, device="cuda")
+    k53 = torch.empty((n, D), dtype=torch.int64, device="cuda") if return_k53 else None
+    bins = torch.empty((n, D), dtype=torch.int32, device="cuda") if return_bins else None
+    n_f = {4: 2, 7: 3, 10: 4}[D]
+    rec = torch.empty((n, 8 + 4 * n_f), dtype=torch.float64, device="cuda") if return_record else None
+    if y is not None:
+        assert y.dtype == torch.float64 and y.is_cuda and y.is_contiguous() and y.shape == (n, D)
+    if event_ids is not None:
+        assert event_ids.dtype == torch.int64 and event_ids.is_cuda and event_ids.shape == (n,)
+    pc = proc.c()
+    check(lib.mf_evaluate(C.byref(pc), sqrt_s, C.byref(pdf.c), _ptr(g) if g is not None else None,
+                          C.c_void_p(y.data_ptr()) if y is not None else None,
+                          C.c_void_p(event_ids.data_ptr()) if event_ids is not None else None,
+                          n, seed, it, C.byref(opt), C.c_void_p(w.data_ptr()),
+                          C.c_void_p(k53.data_ptr()) if k53 is not None else None,
+                          C.c_void_p(bins.data_ptr()) if bins is not None else None,
+                          C.c_void_p(rec.data_ptr()) if rec is not None else None))
+    out = [w]
+    if return_k53:
+        out.append(k53)
+    if return_bins:
+        out.append(bins)
+    if return_record:
+        out.append(rec)
+    return out[0] if len(out) == 1 else tuple(out)
+
+
+def matrix_element(process, mom: torch.Tensor, eb: torch.Tensor, m_top=173.0, w_top=1.5,
+                   precision="fp64", stream=None):
+    """mom: [n, 4 n_f] (t, tbar, final gluons), eb: [n] beam energies; both float64 CUDA."""
+    pid = PROCESS_IDS[process]
+    assert mom.dtype == torch.float64 and mom.is_cuda and mom.is_contiguous()
+    assert eb.dtype == torch.float64 and eb.is_cuda and eb.is_contiguous()
+    n = eb.shape[0]
+    out = torch.empty(n, dtype=torch.float64, device="cuda")
+    check(lib.mf_matrix_element(pid, PRECISIONS.get(precision, precision),
+                                C.c_void_p(mom.data_ptr()), C.c_void_p(eb.data_ptr()), n, m_top,
+                                w_top, C.c_void_p(out.data_ptr()), _stream(stream)))
+    return out
+
+
+def refine_grid(hist: torch.Tensor, grid: torch.Tensor, alpha: float = 1.5, stream=None):
+    D, nb = hist.shape
+    out = torch.empty_like(grid)
+    check(lib.mf_refine_grid(D, nb, alpha, C.c_void_p(hist.data_ptr()),
+                             C.c_void_p(grid.data_ptr()), C.c_void_p(out.data_ptr()),
+                             _stream(stream)))
+    return out
+
+
+def colour_matrix(process) -> np.ndarray:
+    pid = PROCESS_IDS[process]
+    n = {0: 2, 1: 6, 2: 24}[pid]
+    C_ = np.zeros((n, n))
+    check(lib.mf_colour_matrix(pid, _ptr(C_)))
+    return C_

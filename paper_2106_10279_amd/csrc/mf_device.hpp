@@ -1,0 +1,238 @@
+// mf_device.hpp -- device building blocks for the MadFlow hot path on gfx950.
+//
+// Complex arithmetic, chiral-basis spinor algebra for the helicity
+// amplitudes (Sec. 2.3: external wavefunctions, vertices, propagators),
+// the counter-based Philox4x32-10 generator (Salmon et al., SC'11) and
+// compensated (Neumaier / TwoSum) accumulation.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mf {
+
+template <typename T>
+struct cplx {
+    T x, y;
+    __device__ __forceinline__ cplx() {}
+    __device__ __forceinline__ cplx(T a, T b) : x(a), y(b) {}
+};
+
+template <typename T>
+__device__ __forceinline__ cplx<T> cmul(cplx<T> a, cplx<T> b)
+{
+    return cplx<T>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// ---------------------------------------------------------------------------
+// Chiral representation: gamma^mu = [[0, sigma^mu], [sigmabar^mu, 0]],
+// spinor components (L0, L1, R0, R1).  For a real 4-vector j:
+//   j.sigma    = [[j0 - j3, -j1 + i j2], [-j1 - i j2, j0 + j3]]
+//   j.sigmabar = [[j0 + j3,  j1 - i j2], [ j1 + i j2, j0 - j3]]
+// ---------------------------------------------------------------------------
+
+// s += a x gamma.j for a row spinor a: (aR (j.sigmabar), aL (j.sigma)).
+template <typename T>
+__device__ __forceinline__ void rowslash_acc(const cplx<T>* a, const T* j, cplx<T>& s0, cplx<T>& s1,
+                                             cplx<T>& s2, cplx<T>& s3)
+{
+    const T jp = j[0] + j[3], jm = j[0] - j[3];
+    // s0 += aR0 (j0 + j3) + aR1 (j1 + i j2)
+    s0.x += a[2].x * jp + a[3].x * j[1] - a[3].y * j[2];
+    s0.y += a[2].y * jp + a[3].y * j[1] + a[3].x * j[2];
+    // s1 += aR0 (j1 - i j2) + aR1 (j0 - j3)
+    s1.x += a[2].x * j[1] + a[2].y * j[2] + a[3].x * jm;
+    s1.y += a[2].y * j[1] - a[2].x * j[2] + a[3].y * jm;
+    // s2 += aL0 (j0 - j3) + aL1 (-j1 - i j2)
+    s2.x += a[0].x * jm - a[1].x * j[1] + a[1].y * j[2];
+    s2.y += a[0].y * jm - a[1].y * j[1] - a[1].x * j[2];
+    // s3 += aL0 (-j1 + i j2) + aL1 (j0 + j3)
+    s3.x += -a[0].x * j[1] - a[0].y * j[2] + a[1].x * jp;
+    s3.y += -a[0].y * j[1] + a[0].x * j[2] + a[1].y * jp;
+}
+
+// out = s x (K-slash + m) x (fr + i fi) for a row spinor s.
+template <typename T>
+__device__ __forceinline__ void rowprop(cplx<T> s0, cplx<T> s1, cplx<T> s2, cplx<T> s3, const T* K, T m,
+                                        T fr, T fi, cplx<T>* out)
+{
+    const T kp = K[0] + K[3], km = K[0] - K[3];
+    cplx<T> t0, t1, t2, t3;
+    // t0 = m s0 + s2 (K0 + K3) + s3 (K1 + i K2)
+    t0.x = m * s0.x + s2.x * kp + s3.x * K[1] - s3.y * K[2];
+    t0.y = m * s0.y + s2.y * kp + s3.y * K[1] + s3.x * K[2];
+    // t1 = m s1 + s2 (K1 - i K2) + s3 (K0 - K3)
+    t1.x = m * s1.x + s2.x * K[1] + s2.y * K[2] + s3.x * km;
+    t1.y = m * s1.y + s2.y * K[1] - s2.x * K[2] + s3.y * km;
+    // t2 = s0 (K0 - K3) + s1 (-K1 - i K2) + m s2
+    t2.x = s0.x * km - s1.x * K[1] + s1.y * K[2] + m * s2.x;
+    t2.y = s0.y * km - s1.y * K[1] - s1.x * K[2] + m * s2.y;
+    // t3 = s0 (-K1 + i K2) + s1 (K0 + K3) + m s3
+    t3.x = -s0.x * K[1] - s0.y * K[2] + s1.x * kp + m * s3.x;
+    t3.y = -s0.y * K[1] + s0.x * K[2] + s1.y * kp + m * s3.y;
+    const cplx<T> f(fr, fi);
+    out[0] = cmul(t0, f);
+    out[1] = cmul(t1, f);
+    out[2] = cmul(t2, f);
+    out[3] = cmul(t3, f);
+}
+
+// c^mu = a gamma^mu v = aL sigma^mu vR + aR sigmabar^mu vL.
+template <typename T>
+__device__ __forceinline__ void bilinear(const cplx<T>* a, const cplx<T>* v, cplx<T>* c)
+{
+    const cplx<T> s0 = cmul(a[0], v[2]), s1 = cmul(a[1], v[3]);
+    const cplx<T> x01 = cmul(a[0], v[3]), x10 = cmul(a[1], v[2]);
+    const cplx<T> t0 = cmul(a[2], v[0]), t1 = cmul(a[3], v[1]);
+    const cplx<T> y01 = cmul(a[2], v[1]), y10 = cmul(a[3], v[0]);
+    c[0] = cplx<T>(s0.x + s1.x + t0.x + t1.x, s0.y + s1.y + t0.y + t1.y);
+    c[1] = cplx<T>(x01.x + x10.x - y01.x - y10.x, x01.y + x10.y - y01.y - y10.y);
+    // i (x10 - x01) - i (y10 - y01)
+    c[2] = cplx<T>(-(x10.y - x01.y) + (y10.y - y01.y), (x10.x - x01.x) - (y10.x - y01.x));
+    c[3] = cplx<T>(s0.x - s1.x - t0.x + t1.x, s0.y - s1.y - t0.y + t1.y);
+}
+
+// (ar, ai) += c^mu j_mu for complex c and real j.
+template <typename T>
+__device__ __forceinline__ void cdotj(const cplx<T>* c, const T* j, T& ar, T& ai)
+{
+    ar += c[0].x * j[0] - c[1].x * j[1] - c[2].x * j[2] - c[3].x * j[3];
+    ai += c[0].y * j[0] - c[1].y * j[1] - c[2].y * j[2] - c[3].y * j[3];
+}
+
+// W = gamma.e v = ((e.sigma) vR, (e.sigmabar) vL) for a real 4-vector e.
+template <typename T>
+__device__ __forceinline__ void slashcol(const T* e, const cplx<T>* v, cplx<T>* W)
+{
+    const T ep = e[0] + e[3], em = e[0] - e[3];
+    // W0 = (e0 - e3) v2 + (-e1 + i e2) v3
+    W[0] = cplx<T>(em * v[2].x - e[1] * v[3].x - e[2] * v[3].y, em * v[2].y - e[1] * v[3].y + e[2] * v[3].x);
+    // W1 = (-e1 - i e2) v2 + (e0 + e3) v3
+    W[1] = cplx<T>(-e[1] * v[2].x + e[2] * v[2].y + ep * v[3].x, -e[1] * v[2].y - e[2] * v[2].x + ep * v[3].y);
+    // W2 = (e0 + e3) v0 + (e1 - i e2) v1
+    W[2] = cplx<T>(ep * v[0].x + e[1] * v[1].x + e[2] * v[1].y, ep * v[0].y + e[1] * v[1].y - e[2] * v[1].x);
+    // W3 = (e1 + i e2) v0 + (e0 - e3) v1
+    W[3] = cplx<T>(e[1] * v[0].x - e[2] * v[0].y + em * v[1].x, e[1] * v[0].y + e[2] * v[0].x + em * v[1].y);
+}
+
+template <typename T>
+__device__ __forceinline__ void rowdotcol(const cplx<T>* a, const cplx<T>* b, T& ar, T& ai)
+{
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        ar += a[i].x * b[i].x - a[i].y * b[i].y;
+        ai += a[i].x * b[i].y + a[i].y * b[i].x;
+    }
+}
+
+// Real linear polarisations transverse to the 3-momentum of p (zero time
+// component): h = 0 -> (0, cos th cos ph, cos th sin ph, -sin th),
+// h = 1 -> (0, -sin ph, cos ph, 0).  Built in double from the momentum.
+template <typename T>
+__device__ __forceinline__ void linear_pol(const double* p, int h, T* e)
+{
+    const double pt2 = p[1] * p[1] + p[2] * p[2];
+    const double pt = sqrt(pt2);
+    const double kk = sqrt(pt2 + p[3] * p[3]);
+    const bool has_pt = pt > 0.0;
+    const double cph = has_pt ? p[1] / pt : 1.0;
+    const double sph = has_pt ? p[2] / pt : 0.0;
+    const double cth = p[3] / kk, sth = pt / kk;
+    e[0] = (T)0;
+    e[1] = (T)(h ? -sph : cth * cph);
+    e[2] = (T)(h ? cph : cth * sph);
+    e[3] = (T)(h ? 0.0 : -sth);
+}
+
+// Spinors with spin quantised along z in the rest frame, boosted:
+//   u = (sqrt(p.sigma) xi, sqrt(p.sigmabar) xi),  v = (sqrt(p.sigma) xi, -sqrt(p.sigmabar) xi),
+//   sqrt(p.sigma) = (p.sigma + m)/sqrt(2(E+m)),  xi_0 = (1, 0), xi_1 = (0, 1).
+__device__ __forceinline__ void sqrt_blocks(const double* p, double m, int s, double* A, double* B)
+{
+    const double n = 1.0 / sqrt(2.0 * (p[0] + m));
+    // columns s of (p.sigma + m) and (p.sigmabar + m), as (re, im) pairs
+    if (s == 0) {
+        A[0] = (p[0] - p[3] + m) * n; A[1] = 0.0;
+        A[2] = -p[1] * n;             A[3] = -p[2] * n;
+        B[0] = (p[0] + p[3] + m) * n; B[1] = 0.0;
+        B[2] = p[1] * n;              B[3] = p[2] * n;
+    } else {
+        A[0] = -p[1] * n;             A[1] = p[2] * n;
+        A[2] = (p[0] + p[3] + m) * n; A[3] = 0.0;
+        B[0] = p[1] * n;              B[1] = -p[2] * n;
+        B[2] = (p[0] - p[3] + m) * n; B[3] = 0.0;
+    }
+}
+
+// ubar = u^dagger gamma^0 = (conj(uR), conj(uL)).
+template <typename T>
+__device__ __forceinline__ void spinor_ubar(const double* p, double m, int s, cplx<T>* ub)
+{
+    double A[4], B[4];
+    sqrt_blocks(p, m, s, A, B);
+    ub[0] = cplx<T>((T)B[0], (T)-B[1]);
+    ub[1] = cplx<T>((T)B[2], (T)-B[3]);
+    ub[2] = cplx<T>((T)A[0], (T)-A[1]);
+    ub[3] = cplx<T>((T)A[2], (T)-A[3]);
+}
+
+template <typename T>
+__device__ __forceinline__ void spinor_v(const double* p, double m, int s, cplx<T>* v)
+{
+    double A[4], B[4];
+    sqrt_blocks(p, m, s, A, B);
+    v[0] = cplx<T>((T)A[0], (T)A[1]);
+    v[1] = cplx<T>((T)A[2], (T)A[3]);
+    v[2] = cplx<T>((T)-B[0], (T)-B[1]);
+    v[3] = cplx<T>((T)-B[2], (T)-B[3]);
+}
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10: 10 rounds of (c0..c3) -> (hi(M1 c2)^c1^k0, lo(M1 c2), hi(M0 c0)^c3^k1, lo(M0 c0)),
+// M0 = 0xD2511F53, M1 = 0xCD9E8D57, key bumped by (0x9E3779B9, 0xBB67AE85).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                                              uint32_t k1, uint32_t* r)
+{
+#pragma unroll
+    for (int i = 0; i < 10; ++i) {
+        const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
+        const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+        const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    r[0] = c0; r[1] = c1; r[2] = c2; r[3] = c3;
+}
+
+// ---------------------------------------------------------------------------
+// Compensated accumulation.
+// ---------------------------------------------------------------------------
+struct Neumaier {
+    double s, c;
+};
+
+__device__ __forceinline__ void nm_add(Neumaier& a, double v)
+{
+    const double t = a.s + v;
+    if (fabs(a.s) >= fabs(v))
+        a.c += (a.s - t) + v;
+    else
+        a.c += (v - t) + a.s;
+    a.s = t;
+}
+
+// Merge two compensated partial sums (TwoSum of the leading parts).
+__device__ __forceinline__ Neumaier nm_merge(Neumaier a, Neumaier b)
+{
+    const double s = a.s + b.s;
+    const double bb = s - a.s;
+    const double err = (a.s - (s - bb)) + (b.s - bb);
+    Neumaier r;
+    r.s = s;
+    r.c = a.c + b.c + err;
+    return r;
+}
+
+}  // namespace mf

@@ -1,0 +1,650 @@
+// mf_kernels.hpp -- gfx950 kernels of the per-event MadFlow integrand.
+//
+// One fused kernel evaluates chunks of 64 events per wavefront:
+//   phase 1 (one event per lane): Philox uniforms -> VEGAS map -> partonic
+//           kinematics -> flat phase space with massive rescaling -> cuts ->
+//           PDFs; momenta and the event prefactor go to the wave's LDS slot;
+//   phase 2 (one helicity configuration per lane): colour-summed |M_h|^2 of
+//           the chunk's events from LDS, reduced over the helicity lanes;
+//   phase 3 (one event per lane): weight, compensated sum w / w^2, per-bin
+//           w^2 histogram owned lane-per-bin (deterministic), weight store.
+// Each wave walks its chunks in a fixed order and writes one row of partial
+// sums; a single-workgroup kernel reduces the rows in a fixed order and
+// refines the VEGAS grid.  Sec. 2.2 (pipeline), 2.3 (matrix element), 2.4
+// (phase space).
+#pragma once
+
+#include "mf_device.hpp"
+
+namespace mf {
+
+#include "_gen/amp_ng2.inc"
+#include "_gen/amp_ng3.inc"
+#include "_gen/amp_ng4.inc"
+
+constexpr int kWave = 64;
+constexpr int kWavesPerBlock = 4;
+constexpr int kBlock = kWave * kWavesPerBlock;
+constexpr int kMaxDims = 10;
+constexpr int kPartialHead = 8;         // sw.s, sw.c, sw2.s, sw2.c, w_max, n_pass, n_fail, spare
+constexpr int kMaxPdfX = 256;
+constexpr double kGeV2ToPb = 0.3893793721e9;
+constexpr double kPi = 3.14159265358979323846;
+
+struct EventParams {
+    int n_g, n_dims, n_bins, max_newton;
+    uint64_t n_events;
+    uint64_t seed;
+    uint32_t iter;
+    const double* grid;              // [D][n_bins+1]
+    const double* y_in;              // [n][D] or null
+    const uint64_t* event_ids;       // [n] or null
+    // PDF table (device) and the Q^2 stencil rows staged in LDS
+    int n_x, n_q2, q2_first, q2_rows, q2_interval;
+    const double* log_x;
+    const double* log_q2;
+    const double* xf;
+    double log_muf2;
+    // physics
+    double sqrt_s, s_had, m_top, mw, ptmin, etamax, drmin;
+    double me_norm;                  // g^(2n) / (4 64 (n-2)!) x (hbar c)^2 in pb
+    double ps_const;                 // (2pi)^(4-3n) (pi/2)^(n-1) / ((n-1)! (n-2)!)
+    // outputs
+    double* weights;                 // [n] or null
+    uint64_t* k53_out;               // [n][D] or null
+    int32_t* bins_out;               // [n][D] or null
+    double* partials;                // [n_waves][stride] or null
+    double* record;                  // [n][8 + 4 NF] per-stage record or null
+    int stride;
+    int n_waves;
+};
+
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// ---------------------------------------------------------------------------
+// VEGAS map.  The bin index and the position in the bin come from the exact
+// integer product k n_bins; the map itself is evaluated without contraction
+// so that x, the bin index and J_V are reproducible operation by operation.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double vegas_map_dim(const double* __restrict__ e, int i, double delta, double& jd,
+                                                int n_bins)
+{
+#pragma clang fp contract(off)
+    const double lo = e[i], hi = e[i + 1];
+    const double width = hi - lo;
+    const double shift = delta * width;
+    jd = (double)n_bins * width;
+    return lo + shift;
+}
+
+// ---------------------------------------------------------------------------
+// Phase space, cuts and PDF are evaluated without FMA contraction: they cost
+// little next to |M|^2, and a fixed operation order keeps ill-conditioned
+// spots (sqrt(1 - cos^2), boosts, Hermite sums) reproducible.
+//
+// Flat n-body phase space with 3n-4 uniforms, then massive rescaling.
+// Slots: 0 = t, 1 = tbar (mass m), 2.. = gluons (massless).  Returns false
+// when the Newton iteration on xi does not converge within max_newton steps.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void boost_from_rest(const double* Q, double M, const double* v, double* out)
+{
+#pragma clang fp contract(off)
+    const double qv = Q[1] * v[1] + Q[2] * v[2] + Q[3] * v[3];
+    const double e = (Q[0] * v[0] + qv) / M;
+    const double c = (v[0] + e) / (Q[0] + M);
+    out[0] = e;
+    out[1] = v[1] + c * Q[1];
+    out[2] = v[2] + c * Q[2];
+    out[3] = v[3] + c * Q[3];
+}
+
+template <int NF>
+__device__ bool phase_space(const double* __restrict__ r, double rs, double m, int max_newton, double ps_const,
+                            double (&k)[NF][4], double& W)
+{
+#pragma clang fp contract(off)
+    double M[NF + 1];
+    double p[NF][4];
+    M[1] = rs;
+#pragma unroll
+    for (int i = 2; i <= NF - 1; ++i) {
+        const int power = NF - i;
+        const double ri = r[i - 2];
+        const double u = (power == 1) ? 1.0 - sqrt(1.0 - ri) : 0.5 - sin(asin(1.0 - 2.0 * ri) / 3.0);
+        M[i] = sqrt(u) * M[i - 1];
+    }
+    M[NF] = 0.0;
+    double Q[4] = {rs, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int i = 1; i <= NF - 1; ++i) {
+        const double cth = 2.0 * r[(NF - 2) + 2 * (i - 1)] - 1.0;
+        const double phi = 2.0 * kPi * r[(NF - 2) + 2 * (i - 1) + 1];
+        const double sth = sqrt(1.0 - cth * cth);
+        const double q = (M[i] * M[i] - M[i + 1] * M[i + 1]) / (2.0 * M[i]);
+        double sp, cp;
+        sincos(phi, &sp, &cp);
+        const double prest[4] = {q, q * sth * cp, q * sth * sp, q * cth};
+        const double qrest[4] = {sqrt(q * q + M[i + 1] * M[i + 1]), -prest[1], -prest[2], -prest[3]};
+        double Qn[4];
+        boost_from_rest(Q, M[i], prest, p[i - 1]);
+        boost_from_rest(Q, M[i], qrest, Qn);
+        Q[0] = Qn[0]; Q[1] = Qn[1]; Q[2] = Qn[2]; Q[3] = Qn[3];
+    }
+    p[NF - 1][0] = Q[0]; p[NF - 1][1] = Q[1]; p[NF - 1][2] = Q[2]; p[NF - 1][3] = Q[3];
+
+    double w0 = ps_const;
+#pragma unroll
+    for (int i = 0; i < NF - 2; ++i)
+        w0 *= rs * rs;
+
+    // xi such that sum_i sqrt(m_i^2 + xi^2 E_i^2) = sqrt(s)
+    const double msum = 2.0 * m;
+    double xi = sqrt(1.0 - (msum / rs) * (msum / rs));
+    const double floor_res = 2.0 * NF * 0x1p-52 * rs;
+    bool converged = false;
+    for (int it = 0; it < max_newton; ++it) {
+        double f = -rs, fp = 0.0;
+#pragma unroll
+        for (int i = 0; i < NF; ++i) {
+            const double mi = i < 2 ? m : 0.0;
+            const double e = sqrt(mi * mi + xi * xi * p[i][0] * p[i][0]);
+            f += e;
+            fp += xi * p[i][0] * p[i][0] / e;
+        }
+        if (fabs(f) <= floor_res) {
+            converged = true;
+            break;
+        }
+        const double step = f / fp;
+        xi = xi - step;
+        if (fabs(step) <= 1e-15 * xi) {
+            converged = true;
+            break;
+        }
+    }
+    if (!converged) {
+        W = 0.0;
+        return false;
+    }
+    double sum_abs = 0.0, prod_ratio = 1.0, sum_sq_over_e = 0.0;
+#pragma unroll
+    for (int i = 0; i < NF; ++i) {
+        const double mi = i < 2 ? m : 0.0;
+        const double e = sqrt(mi * mi + xi * xi * p[i][0] * p[i][0]);
+        k[i][0] = e;
+        k[i][1] = xi * p[i][1];
+        k[i][2] = xi * p[i][2];
+        k[i][3] = xi * p[i][3];
+        const double a = sqrt(k[i][1] * k[i][1] + k[i][2] * k[i][2] + k[i][3] * k[i][3]);
+        sum_abs += a;
+        prod_ratio *= a / e;
+        sum_sq_over_e += a * a / e;
+    }
+    double pw = 1.0;
+    const double ratio = sum_abs / rs;
+#pragma unroll
+    for (int i = 0; i < 2 * NF - 3; ++i)
+        pw *= ratio;
+    W = w0 * pw * prod_ratio * rs / sum_sq_over_e;
+    return true;
+}
+
+__device__ __forceinline__ double pseudorapidity(const double* k)
+{
+#pragma clang fp contract(off)
+    const double a = sqrt(k[1] * k[1] + k[2] * k[2] + k[3] * k[3]);
+    return 0.5 * log((a + k[3]) / (a - k[3]));
+}
+
+// Strict inequalities on the final-state gluons: pT, |eta_lab|, Delta R.
+template <int NF>
+__device__ __forceinline__ bool pass_cuts(const double (&k)[NF][4], double y_boost, double ptmin, double etamax,
+                                          double drmin)
+{
+#pragma clang fp contract(off)
+    bool pass = true;
+#pragma unroll
+    for (int i = 2; i < NF; ++i) {
+        if (ptmin > 0.0) {
+            const double pt = sqrt(k[i][1] * k[i][1] + k[i][2] * k[i][2]);
+            pass = pass && (pt > ptmin);
+        }
+        if (etamax > 0.0) {
+            const double eta = fabs(pseudorapidity(k[i]) + y_boost);
+            pass = pass && (eta < etamax);
+        }
+    }
+    if (drmin > 0.0) {
+#pragma unroll
+        for (int i = 2; i < NF; ++i)
+#pragma unroll
+            for (int j = i + 1; j < NF; ++j) {
+                const double deta = pseudorapidity(k[i]) - pseudorapidity(k[j]);
+                double dphi = fabs(atan2(k[i][2], k[i][1]) - atan2(k[j][2], k[j][1]));
+                if (dphi > kPi)
+                    dphi = 2.0 * kPi - dphi;
+                pass = pass && (sqrt(deta * deta + dphi * dphi) > drmin);
+            }
+    }
+    return pass;
+}
+
+// ---------------------------------------------------------------------------
+// PDF: cubic Hermite in ln x on each staged Q^2 row, then in ln Q^2.  Knot
+// slopes: mean of the adjacent secants inside, one-sided at the ends.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double knot_slope(const double* t, const double* f, int i, int last)
+{
+#pragma clang fp contract(off)
+    if (i == 0)
+        return (f[1] - f[0]) / (t[1] - t[0]);
+    if (i == last)
+        return (f[i] - f[i - 1]) / (t[i] - t[i - 1]);
+    return 0.5 * ((f[i] - f[i - 1]) / (t[i] - t[i - 1]) + (f[i + 1] - f[i]) / (t[i + 1] - t[i]));
+}
+
+__device__ __forceinline__ double hermite(const double* t, const double* f, int i, int last, double v)
+{
+#pragma clang fp contract(off)
+    const double h = t[i + 1] - t[i];
+    const double u = (v - t[i]) / h;
+    const double u2 = u * u, u3 = u2 * u;
+    const double h00 = 2.0 * u3 - 3.0 * u2 + 1.0;
+    const double h10 = u3 - 2.0 * u2 + u;
+    const double h01 = -2.0 * u3 + 3.0 * u2;
+    const double h11 = u3 - u2;
+    return h00 * f[i] + h10 * h * knot_slope(t, f, i, last) + h01 * f[i + 1] + h11 * h * knot_slope(t, f, i + 1, last);
+}
+
+__device__ __forceinline__ int find_interval(const double* knots, int n, double v)
+{
+    if (v < knots[0])
+        return 0;
+    if (v >= knots[n - 1])
+        return n - 2;
+    int lo = 0, hi = n - 1;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (knots[mid] <= v)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// rows: LDS [q2_rows][n_x]; lx_knots: LDS [n_x]; q2 knots of the staged rows: LDS.
+__device__ __forceinline__ double pdf_xg(const EventParams& P, const double* rows, const double* lx_knots,
+                                         const double* lq_knots, double x)
+{
+    const double lx = log(x);
+    const int k = find_interval(lx_knots, P.n_x, lx);
+    double rv[4];
+    for (int r = 0; r < P.q2_rows; ++r)
+        rv[r] = hermite(lx_knots, rows + r * P.n_x, k, P.n_x - 1, lx);
+    return hermite(lq_knots, rv, P.q2_interval - P.q2_first, P.q2_rows - 1, P.log_muf2);
+}
+
+// Reduce v over groups of `width` consecutive lanes; lane 0 of each group
+// receives the sum in a fixed association order.
+__device__ __forceinline__ double group_sum(double v, int width)
+{
+    for (int off = width >> 1; off > 0; off >>= 1)
+        v += __shfl_down(v, off, width);
+    return v;
+}
+
+template <int NG, typename T>
+__device__ __forceinline__ double colour_summed_me2(const double* mom, double eb, int hel, double mt, double mw)
+{
+    if constexpr (NG == 2)
+        return colour_summed_me2_ng2<T>(mom, eb, hel, mt, mw);
+    else if constexpr (NG == 3)
+        return colour_summed_me2_ng3<T>(mom, eb, hel, mt, mw);
+    else
+        return colour_summed_me2_ng4<T>(mom, eb, hel, mt, mw);
+}
+
+// Momenta stored per event: t[4], tbar[4], final gluons[4 each], beam energy.
+template <int NG>
+struct Layout {
+    static constexpr int kMom = 8 + 4 * (NG - 2) + 1;
+    static constexpr int kHel = 1 << (NG + 2);
+    static constexpr int kEventsPerPass = kWave / kHel;   // 4, 2, 1
+};
+
+template <int NG, typename T>
+__global__ void __launch_bounds__(kBlock) event_kernel(EventParams P)
+{
+    constexpr int NF = NG;
+    constexpr int D = 2 + 3 * NF - 4;
+    using L = Layout<NG>;
+    __shared__ double s_mom[kWavesPerBlock][kWave][L::kMom];
+    __shared__ double s_pref[kWavesPerBlock][kWave];
+    __shared__ double s_me[kWavesPerBlock][kWave];
+    __shared__ unsigned short s_bin[kWavesPerBlock][D][kWave];
+    __shared__ double s_lx[kMaxPdfX];
+    __shared__ double s_rows[4 * kMaxPdfX];
+    __shared__ double s_lq[4];
+    extern __shared__ double s_hist[];     // [kWavesPerBlock][D][n_bins]
+
+    const int tid = threadIdx.x;
+    const int wv = tid / kWave;
+    const int lane = tid % kWave;
+    const int wave_id = blockIdx.x * kWavesPerBlock + wv;
+    const int nb = P.n_bins;
+
+    // Stage ln x knots and the Q^2 stencil rows of the PDF table in LDS.
+    for (int i = tid; i < P.n_x; i += kBlock)
+        s_lx[i] = P.log_x[i];
+    for (int i = tid; i < P.q2_rows * P.n_x; i += kBlock)
+        s_rows[i] = P.xf[(size_t)P.q2_first * P.n_x + i];
+    if (tid < P.q2_rows)
+        s_lq[tid] = P.log_q2[P.q2_first + tid];
+    double* hist = s_hist + (size_t)wv * D * nb;
+    if (P.partials)
+        for (int i = lane; i < D * nb; i += kWave)
+            hist[i] = 0.0;
+    __syncthreads();
+
+    Neumaier sw{0.0, 0.0}, sw2{0.0, 0.0};
+    double wmax = 0.0, npass = 0.0, nfail = 0.0;
+    const uint64_t n_chunks = (P.n_events + kWave - 1) / kWave;
+    const uint32_t key0 = (uint32_t)P.seed, key1 = (uint32_t)(P.seed >> 32);
+
+    for (uint64_t chunk = wave_id; chunk < n_chunks; chunk += P.n_waves) {
+        // ---------------- phase 1: one event per lane ----------------------
+        const uint64_t ev = chunk * kWave + lane;
+        const bool active = ev < P.n_events;
+        double pref = 0.0;
+        double* mom = s_mom[wv][lane];
+        if (active) {
+            double x[D];
+            double jac = 1.0;
+            if (P.y_in) {
+#pragma unroll
+                for (int d = 0; d < D; ++d) {
+                    const double y = P.y_in[ev * D + d];
+                    const double t = y * (double)nb;
+                    int b = (int)floor(t);
+                    b = b > nb - 1 ? nb - 1 : (b < 0 ? 0 : b);
+                    double jd;
+                    x[d] = vegas_map_dim(P.grid + d * (nb + 1), b, t - (double)b, jd, nb);
+                    jac = jac * jd;
+                    s_bin[wv][d][lane] = (unsigned short)b;
+                    if (P.bins_out)
+                        P.bins_out[ev * D + d] = b;
+                }
+            } else {
+                const uint64_t eid = P.event_ids ? P.event_ids[ev] : ev;
+#pragma unroll
+                for (int blk = 0; blk < (D + 1) / 2; ++blk) {
+                    uint32_t r[4];
+                    philox4x32_10((uint32_t)eid, (uint32_t)(eid >> 32), P.iter, (uint32_t)blk, key0, key1, r);
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        const int d = 2 * blk + h;
+                        if (d < D) {
+                            const uint64_t kk = ((((uint64_t)r[2 * h]) << 32) | (uint64_t)r[2 * h + 1]) >> 11;
+                            const uint64_t prod = kk * (uint64_t)nb;
+                            const int b = (int)(prod >> 53);
+                            const double delta = (double)(prod & ((1ull << 53) - 1)) * 0x1p-53;
+                            double jd;
+                            x[d] = vegas_map_dim(P.grid + d * (nb + 1), b, delta, jd, nb);
+                            jac = jac * jd;
+                            s_bin[wv][d][lane] = (unsigned short)b;
+                            if (P.k53_out)
+                                P.k53_out[ev * D + d] = kk;
+                            if (P.bins_out)
+                                P.bins_out[ev * D + d] = b;
+                        }
+                    }
+                }
+            }
+            const double x1 = x[0], x2 = x[1];
+            const double shat = x1 * x2 * P.sqrt_s * P.sqrt_s;
+            const double thr = 2.0 * P.m_top;
+            double* rec = P.record ? P.record + ev * (8 + 4 * NF) : nullptr;
+            double W = 0.0, f1 = 0.0, f2 = 0.0;
+            int flags = 0;
+            double k[NF][4];
+            if (shat > thr * thr) {
+                flags |= 1;
+                const double rs = sqrt(shat);
+                if (phase_space<NF>(x + 2, rs, P.m_top, P.max_newton, P.ps_const, k, W)) {
+                    const double y_boost = 0.5 * log(x1 / x2);
+                    if (pass_cuts<NF>(k, y_boost, P.ptmin, P.etamax, P.drmin)) {
+                        flags |= 4;
+                        f1 = pdf_xg(P, s_rows, s_lx, s_lq, x1) / x1;
+                        f2 = pdf_xg(P, s_rows, s_lx, s_lq, x2) / x2;
+                        pref = jac * W * f1 * f2 / (2.0 * shat);
+#pragma unroll
+                        for (int i = 0; i < NF; ++i)
+#pragma unroll
+                            for (int mu = 0; mu < 4; ++mu)
+                                mom[4 * i + mu] = k[i][mu];
+                        mom[L::kMom - 1] = 0.5 * rs;
+                        npass += 1.0;
+                    }
+                } else {
+                    flags |= 2;
+                    nfail += 1.0;
+                }
+            }
+            if (rec) {
+                rec[0] = x1;
+                rec[1] = x2;
+                rec[2] = jac;
+                rec[3] = W;
+                rec[4] = f1;
+                rec[5] = f2;
+                rec[7] = (double)flags;
+#pragma unroll
+                for (int i = 0; i < NF; ++i)
+#pragma unroll
+                    for (int mu = 0; mu < 4; ++mu)
+                        rec[8 + 4 * i + mu] = (flags & 1) && !(flags & 2) ? k[i][mu] : 0.0;
+            }
+        }
+        s_pref[wv][lane] = pref;
+        wave_sync();
+
+        // ---------------- phase 2: one helicity configuration per lane -----
+        {
+            const int h = lane % L::kHel;
+            const int sub = lane / L::kHel;
+            for (int g = 0; g < kWave / L::kEventsPerPass; ++g) {
+                const int e = g * L::kEventsPerPass + sub;
+                const double* m_e = s_mom[wv][e];
+                double v = 0.0;
+                if (s_pref[wv][e] != 0.0)
+                    v = colour_summed_me2<NG, T>(m_e, m_e[L::kMom - 1], h, P.m_top, P.mw);
+                v = group_sum(v, L::kHel);
+                if (h == 0)
+                    s_me[wv][e] = v;
+            }
+        }
+        wave_sync();
+
+        // ---------------- phase 3: one event per lane ----------------------
+        const double w = pref * (s_me[wv][lane] * P.me_norm);
+        if (active) {
+            if (P.record)
+                P.record[ev * (8 + 4 * NF) + 6] = pref != 0.0 ? s_me[wv][lane] : 0.0;
+            if (P.weights)
+                P.weights[ev] = w;
+            nm_add(sw, w);
+            nm_add(sw2, w * w);
+            wmax = fmax(wmax, w);
+        }
+        if (P.partials) {
+            s_me[wv][lane] = active ? w * w : 0.0;
+            wave_sync();
+            for (int b = lane; b < nb; b += kWave) {
+                for (int d = 0; d < D; ++d) {
+                    double acc = hist[d * nb + b];
+                    for (int e = 0; e < kWave; ++e)
+                        if (s_bin[wv][d][e] == b)
+                            acc += s_me[wv][e];
+                    hist[d * nb + b] = acc;
+                }
+            }
+        }
+        wave_sync();
+    }
+
+    if (P.partials) {
+        // Fixed-order wave reduction of the lane partials.
+        for (int off = kWave >> 1; off > 0; off >>= 1) {
+            Neumaier o1{__shfl_down(sw.s, off), __shfl_down(sw.c, off)};
+            Neumaier o2{__shfl_down(sw2.s, off), __shfl_down(sw2.c, off)};
+            const double om = __shfl_down(wmax, off);
+            const double op = __shfl_down(npass, off);
+            const double of = __shfl_down(nfail, off);
+            sw = nm_merge(sw, o1);
+            sw2 = nm_merge(sw2, o2);
+            wmax = fmax(wmax, om);
+            npass += op;
+            nfail += of;
+        }
+        double* out = P.partials + (size_t)wave_id * P.stride;
+        if (lane == 0) {
+            out[0] = sw.s;
+            out[1] = sw.c;
+            out[2] = sw2.s;
+            out[3] = sw2.c;
+            out[4] = wmax;
+            out[5] = npass;
+            out[6] = nfail;
+            out[7] = 0.0;
+        }
+        for (int i = lane; i < D * nb; i += kWave)
+            out[kPartialHead + i] = hist[i];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Reduce the per-wave rows in wave order, estimate I_j and V_j, refine grid.
+// ---------------------------------------------------------------------------
+struct ReduceParams {
+    const double* partials;
+    int n_waves, stride, n_dims, n_bins;
+    double n_events, alpha;
+    const double* grid_in;
+    double* grid_out;
+    double* hist;            // [D][n_bins] out
+    double* iter_I;          // [n_iter]
+    double* iter_V;
+    double* stats;           // [4]: w_max (this iteration), n_pass, n_fail (cumulative)
+    int j;
+};
+
+__global__ void __launch_bounds__(256) reduce_refine_kernel(ReduceParams R)
+{
+    const int tid = threadIdx.x;
+    const int nh = R.n_dims * R.n_bins;
+    for (int i = tid; i < nh; i += blockDim.x) {
+        Neumaier a{0.0, 0.0};
+        for (int w = 0; w < R.n_waves; ++w)
+            nm_add(a, R.partials[(size_t)w * R.stride + kPartialHead + i]);
+        R.hist[i] = a.s + a.c;
+    }
+    if (tid == 0) {
+        Neumaier s1{0.0, 0.0}, s2{0.0, 0.0};
+        double wmax = 0.0, np = 0.0, nf = 0.0;
+        for (int w = 0; w < R.n_waves; ++w) {
+            const double* row = R.partials + (size_t)w * R.stride;
+            s1 = nm_merge(s1, Neumaier{row[0], row[1]});
+            s2 = nm_merge(s2, Neumaier{row[2], row[3]});
+            wmax = fmax(wmax, row[4]);
+            np += row[5];
+            nf += row[6];
+        }
+        const double N = R.n_events;
+        const double I = (s1.s + s1.c) / N;
+        const double V = ((s2.s + s2.c) / N - I * I) / (N - 1.0);
+        R.iter_I[R.j] = I;
+        R.iter_V[R.j] = V;
+        R.stats[0] = wmax;
+        R.stats[1] = np;
+        R.stats[2] += nf;
+    }
+    __syncthreads();
+    // One thread per dimension: smoothing, damping, equal-share rebinning.
+    for (int d = tid; d < R.n_dims; d += blockDim.x) {
+        const int n = R.n_bins;
+        const double* h = R.hist + d * n;
+        const double* e = R.grid_in + d * (n + 1);
+        double* en = R.grid_out + d * (n + 1);
+        auto smoothed = [&](int i) -> double {
+            if (i == 0)
+                return (h[0] + h[1]) / 2.0;
+            if (i == n - 1)
+                return (h[n - 2] + h[n - 1]) / 2.0;
+            return (h[i - 1] + h[i] + h[i + 1]) / 3.0;
+        };
+        double total = 0.0;
+        for (int i = 0; i < n; ++i)
+            total += smoothed(i);
+        if (total == 0.0) {
+            for (int i = 0; i <= n; ++i)
+                en[i] = e[i];
+            continue;
+        }
+        auto importance = [&](int i) -> double {
+            const double rho = smoothed(i) / total;
+            if (rho <= 0.0)
+                return 0.0;
+            if (rho >= 1.0)
+                return 1.0;
+            return pow((1.0 - rho) / (-log(rho)), R.alpha);
+        };
+        double rsum = 0.0;
+        for (int i = 0; i < n; ++i)
+            rsum += importance(i);
+        const double share = rsum / (double)n;
+        // grid_out never aliases grid_in, so the old edges stay readable.
+        en[0] = 0.0;
+        int i = 0;
+        double cum = 0.0;
+        double ri = importance(0);
+        for (int kk = 1; kk < n; ++kk) {
+            const double target = (double)kk * share;
+            while (i < n - 1 && (cum + ri < target || ri == 0.0)) {
+                cum += ri;
+                ++i;
+                ri = importance(i);
+            }
+            double frac = ri > 0.0 ? (target - cum) / ri : 1.0;
+            if (frac > 1.0)
+                frac = 1.0;
+            en[kk] = e[i] + frac * (e[i + 1] - e[i]);
+        }
+        en[n] = 1.0;
+    }
+}
+
+// Stand-alone |M|^2: one helicity per lane, events of the launch in groups.
+template <int NG, typename T>
+__global__ void __launch_bounds__(kBlock) me_kernel(const double* __restrict__ mom, const double* __restrict__ eb,
+                                                     uint64_t n, double mt, double mw, double* __restrict__ out)
+{
+    using L = Layout<NG>;
+    const int lane = threadIdx.x % kWave;
+    const uint64_t wave = (uint64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+    const uint64_t e = wave * L::kEventsPerPass + lane / L::kHel;
+    const int h = lane % L::kHel;
+    double v = 0.0;
+    if (e < n)
+        v = colour_summed_me2<NG, T>(mom + e * (L::kMom - 1), eb[e], h, mt, mw);
+    v = group_sum(v, L::kHel);
+    if (h == 0 && e < n)
+        out[e] = v;
+}
+
+}  // namespace mf

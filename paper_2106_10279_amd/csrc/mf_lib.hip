@@ -1,0 +1,619 @@
+// mf_lib.hip -- host runtime and C ABI of libmadflow_mi355x (see include/mf.h).
+//
+// The iteration loop of the VEGAS integration (Sec. 2.2) is enqueued on one
+// HIP stream without host round trips: per iteration one fused event kernel
+// and one reduce-and-refine kernel; the per-iteration estimates stay on the
+// device until the loop ends.  Argument checks run on the host before any
+// HIP call.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "mf.h"
+#include "mf_kernels.hpp"
+
+namespace {
+
+thread_local std::string g_error;
+
+mf_status fail(mf_status st, const std::string& msg)
+{
+    g_error = msg;
+    return st;
+}
+
+#define MF_HIP(call)                                                                      \
+    do {                                                                                  \
+        hipError_t e_ = (call);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return fail(MF_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_));   \
+    } while (0)
+
+int n_gluons(int id)
+{
+    switch (id) {
+    case MF_GG_TTX: return 2;
+    case MF_GG_TTXG: return 3;
+    case MF_GG_TTXGG: return 4;
+    default: return -1;
+    }
+}
+
+double factorial(int n)
+{
+    double f = 1.0;
+    for (int i = 2; i <= n; ++i)
+        f *= i;
+    return f;
+}
+
+// Device buffers reused across calls on one device (grow-only).
+struct Buffer {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+};
+
+struct Workspace {
+    std::mutex lock;
+    Buffer grid[2], log_x, log_q2, xf, partials, hist, iter_I, iter_V, stats;
+    int n_cu = 0;
+};
+
+Workspace g_ws[64];
+
+mf_status ensure(Buffer& b, size_t bytes)
+{
+    if (b.bytes >= bytes)
+        return MF_OK;
+    if (b.ptr) {
+        hipError_t e = hipFree(b.ptr);
+        b.ptr = nullptr;
+        b.bytes = 0;
+        if (e != hipSuccess)
+            return fail(MF_EDEVICE, std::string("hipFree: ") + hipGetErrorString(e));
+    }
+    size_t want = bytes < 256 ? 256 : bytes;
+    hipError_t e = hipMalloc(&b.ptr, want);
+    if (e != hipSuccess) {
+        b.ptr = nullptr;
+        return fail(MF_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    }
+    b.bytes = want;
+    return MF_OK;
+}
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+bool ascending(const double* v, int n)
+{
+    for (int i = 0; i < n; ++i)
+        if (!std::isfinite(v[i]))
+            return false;
+    for (int i = 1; i < n; ++i)
+        if (!(v[i] > v[i - 1]))
+            return false;
+    return true;
+}
+
+int host_interval(const double* knots, int n, double v)
+{
+    if (v < knots[0]) return 0;
+    if (v >= knots[n - 1]) return n - 2;
+    int lo = 0, hi = n - 1;
+    while (hi - lo > 1) {
+        int mid = (lo + hi) / 2;
+        if (knots[mid] <= v) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+mf_status validate_process(const mf_process* proc, double sqrt_s, int* ng)
+{
+    if (!proc)
+        return fail(MF_EINVAL, "process is NULL");
+    *ng = n_gluons(proc->id);
+    if (*ng < 0)
+        return fail(MF_EINVAL, "unknown process id");
+    if (!finite_pos(proc->m_top))
+        return fail(MF_EINVAL, "m_top must be finite and > 0");
+    if (!std::isfinite(proc->w_top) || proc->w_top < 0.0)
+        return fail(MF_EINVAL, "w_top must be finite and >= 0");
+    if (!finite_pos(proc->alpha_s))
+        return fail(MF_EINVAL, "alpha_s must be finite and > 0");
+    if (!finite_pos(proc->mu_f))
+        return fail(MF_EINVAL, "mu_f must be finite and > 0");
+    if (!std::isfinite(proc->ptmin_g) || !std::isfinite(proc->etamax_g) || !std::isfinite(proc->drmin_gg))
+        return fail(MF_EINVAL, "cut values must be finite");
+    if (!std::isfinite(sqrt_s) || !(sqrt_s > 2.0 * proc->m_top))
+        return fail(MF_EINVAL, "sqrt_s must exceed 2 m_top");
+    return MF_OK;
+}
+
+mf_status validate_pdf(const mf_pdf_grid* pdf, double mu_f)
+{
+    if (!pdf || !pdf->log_x || !pdf->log_q2 || !pdf->xf)
+        return fail(MF_EINVAL, "PDF grid or one of its arrays is NULL");
+    if (pdf->n_x < 4 || pdf->n_x > mf::kMaxPdfX)
+        return fail(MF_EINVAL, "n_x must be in [4, 256]");
+    if (pdf->n_q2 < 4 || pdf->n_q2 > 4096)
+        return fail(MF_EINVAL, "n_q2 must be in [4, 4096]");
+    if (!ascending(pdf->log_x, pdf->n_x) || !ascending(pdf->log_q2, pdf->n_q2))
+        return fail(MF_EINVAL, "PDF knots must be finite and strictly ascending");
+    const double lq = std::log(mu_f * mu_f);
+    if (lq < pdf->log_q2[0] || lq > pdf->log_q2[pdf->n_q2 - 1])
+        return fail(MF_EINVAL, "mu_f^2 lies outside the PDF Q^2 grid");
+    for (long i = 0; i < (long)pdf->n_x * pdf->n_q2; ++i)
+        if (!std::isfinite(pdf->xf[i]))
+            return fail(MF_EINVAL, "PDF values must be finite");
+    return MF_OK;
+}
+
+mf_status validate_options(const mf_options* opt, int D)
+{
+    if (!opt)
+        return fail(MF_EINVAL, "options are NULL");
+    if (opt->n_bins < 2 || opt->n_bins > 1024)
+        return fail(MF_EINVAL, "n_bins must be in [2, 1024]");
+    if ((long)D * opt->n_bins > 2048)
+        return fail(MF_EUNSUPPORTED, "n_dims * n_bins above 2048 does not fit the LDS histogram");
+    if (!finite_pos(opt->alpha))
+        return fail(MF_EINVAL, "alpha must be finite and > 0");
+    if (opt->precision != MF_FP64 && opt->precision != MF_FP32_KAHAN)
+        return fail(MF_EINVAL, "unknown precision");
+    if (opt->max_newton < 0 || opt->max_newton > 1000)
+        return fail(MF_EINVAL, "max_newton must be in [0, 1000]");
+    if (opt->start_iter < 0)
+        return fail(MF_EINVAL, "start_iter must be >= 0");
+    if (opt->grid_in) {
+        const int nb = opt->n_bins;
+        for (int d = 0; d < D; ++d) {
+            const double* e = opt->grid_in + (size_t)d * (nb + 1);
+            if (e[0] != 0.0 || e[nb] != 1.0 || !ascending(e, nb + 1))
+                return fail(MF_EINVAL, "grid rows must rise strictly from 0 to 1");
+        }
+    }
+    return MF_OK;
+}
+
+struct Setup {
+    int ng, D;
+    mf::EventParams P;
+    hipStream_t stream;
+    Workspace* ws;
+};
+
+// Upload the PDF table and fill the launch parameters shared by all modes.
+mf_status prepare(const mf_process* proc, double sqrt_s, const mf_pdf_grid* pdf, const mf_options* opt,
+                  Workspace& ws, Setup& S)
+{
+    const int nx = pdf->n_x, nq = pdf->n_q2;
+    mf_status st;
+    if ((st = ensure(ws.log_x, sizeof(double) * nx)) != MF_OK) return st;
+    if ((st = ensure(ws.log_q2, sizeof(double) * nq)) != MF_OK) return st;
+    if ((st = ensure(ws.xf, sizeof(double) * nx * (size_t)nq)) != MF_OK) return st;
+    MF_HIP(hipMemcpyAsync(ws.log_x.ptr, pdf->log_x, sizeof(double) * nx, hipMemcpyHostToDevice, S.stream));
+    MF_HIP(hipMemcpyAsync(ws.log_q2.ptr, pdf->log_q2, sizeof(double) * nq, hipMemcpyHostToDevice, S.stream));
+    MF_HIP(hipMemcpyAsync(ws.xf.ptr, pdf->xf, sizeof(double) * nx * (size_t)nq, hipMemcpyHostToDevice, S.stream));
+
+    mf::EventParams& P = S.P;
+    std::memset(&P, 0, sizeof(P));
+    P.n_g = S.ng;
+    P.n_dims = S.D;
+    P.n_bins = opt->n_bins;
+    P.max_newton = opt->max_newton;
+    P.n_x = nx;
+    P.n_q2 = nq;
+    P.log_muf2 = std::log(proc->mu_f * proc->mu_f);
+    const int mq = host_interval(pdf->log_q2, nq, P.log_muf2);
+    const int first = mq - 1 < 0 ? 0 : mq - 1;
+    const int last = mq + 2 > nq - 1 ? nq - 1 : mq + 2;
+    P.q2_first = first;
+    P.q2_rows = last - first + 1;
+    P.q2_interval = mq;
+    P.log_x = (const double*)ws.log_x.ptr;
+    P.log_q2 = (const double*)ws.log_q2.ptr;
+    P.xf = (const double*)ws.xf.ptr;
+    P.sqrt_s = sqrt_s;
+    P.s_had = sqrt_s * sqrt_s;
+    P.m_top = proc->m_top;
+    P.mw = proc->m_top * proc->w_top;
+    P.ptmin = proc->ptmin_g;
+    P.etamax = proc->etamax_g;
+    P.drmin = proc->drmin_gg;
+    const int n = S.ng;
+    const double gs2 = 4.0 * mf::kPi * proc->alpha_s;
+    P.me_norm = std::pow(gs2, n) / (4.0 * 64.0 * factorial(n - 2)) * mf::kGeV2ToPb;
+    P.ps_const = std::pow(2.0 * mf::kPi, 4 - 3 * n) * std::pow(mf::kPi / 2.0, n - 1) /
+                 (factorial(n - 1) * factorial(n - 2));
+    return MF_OK;
+}
+
+template <int NG, typename T>
+mf_status launch_event(const mf::EventParams& P, int blocks, hipStream_t stream)
+{
+    constexpr int D = 2 + 3 * NG - 4;
+    const size_t dyn = P.partials ? sizeof(double) * mf::kWavesPerBlock * D * P.n_bins : 0;
+    hipLaunchKernelGGL((mf::event_kernel<NG, T>), dim3(blocks), dim3(mf::kBlock), dyn, stream, P);
+    MF_HIP(hipGetLastError());
+    return MF_OK;
+}
+
+mf_status dispatch_event(int ng, mf_precision prec, const mf::EventParams& P, int blocks, hipStream_t s)
+{
+    const bool f32 = prec == MF_FP32_KAHAN;
+    switch (ng) {
+    case 2: return f32 ? launch_event<2, float>(P, blocks, s) : launch_event<2, double>(P, blocks, s);
+    case 3: return f32 ? launch_event<3, float>(P, blocks, s) : launch_event<3, double>(P, blocks, s);
+    default: return f32 ? launch_event<4, float>(P, blocks, s) : launch_event<4, double>(P, blocks, s);
+    }
+}
+
+mf_status device_workspace(Workspace** out)
+{
+    int dev = 0;
+    MF_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64)
+        return fail(MF_EDEVICE, "device index out of range");
+    Workspace& ws = g_ws[dev];
+    if (ws.n_cu == 0) {
+        hipDeviceProp_t prop;
+        MF_HIP(hipGetDeviceProperties(&prop, dev));
+        ws.n_cu = prop.multiProcessorCount;
+    }
+    *out = &ws;
+    return MF_OK;
+}
+
+// Waves launched for n_chunks chunks of 64 events: enough to cover every CU
+// several times over, fixed for a given device so the reduction order (and
+// hence the result) is reproducible.
+int waves_for(uint64_t n_chunks, int n_cu)
+{
+    uint64_t cap = (uint64_t)n_cu * 32;
+    uint64_t w = n_chunks < cap ? n_chunks : cap;
+    w = (w + mf::kWavesPerBlock - 1) / mf::kWavesPerBlock * mf::kWavesPerBlock;
+    return (int)(w < mf::kWavesPerBlock ? mf::kWavesPerBlock : w);
+}
+
+void combine(int n, const double* I, const double* V, double* sigma, double* err, double* chi2)
+{
+    // inverse-variance weighted mean with compensated sums
+    auto nsum = [](const std::vector<double>& v) {
+        double s = 0.0, c = 0.0;
+        for (double x : v) {
+            double t = s + x;
+            if (std::fabs(s) >= std::fabs(x)) c += (s - t) + x; else c += (x - t) + s;
+            s = t;
+        }
+        return s + c;
+    };
+    std::vector<double> num, den, chi;
+    for (int j = 0; j < n; ++j)
+        if (V[j] > 0.0) {
+            num.push_back(I[j] / V[j]);
+            den.push_back(1.0 / V[j]);
+        }
+    if (num.empty()) {
+        *sigma = n > 0 ? I[n - 1] : 0.0;
+        *err = 0.0;
+        *chi2 = 0.0;
+        return;
+    }
+    const double sden = nsum(den);
+    const double mean = nsum(num) / sden;
+    for (int j = 0; j < n; ++j)
+        if (V[j] > 0.0)
+            chi.push_back((I[j] - mean) * (I[j] - mean) / V[j]);
+    *sigma = mean;
+    *err = 1.0 / std::sqrt(sden);
+    *chi2 = num.size() > 1 ? nsum(chi) / (double)(num.size() - 1) : 0.0;
+}
+
+}  // namespace
+
+extern "C" {
+
+void mf_default_options(mf_options* opt)
+{
+    if (!opt) return;
+    std::memset(opt, 0, sizeof(*opt));
+    opt->n_bins = 50;
+    opt->alpha = 1.5;
+    opt->start_iter = 0;
+    opt->precision = MF_FP64;
+    opt->strict = 0;
+    opt->max_newton = 50;
+    opt->grid_in = nullptr;
+    opt->stream = nullptr;
+}
+
+int mf_n_dims(int process_id)
+{
+    const int n = n_gluons(process_id);
+    return n < 0 ? -1 : 2 + 3 * n - 4;
+}
+
+const char* mf_last_error(void) { return g_error.c_str(); }
+
+mf_status mf_integrate(const mf_process* proc, double sqrt_s, const mf_pdf_grid* pdf, uint64_t n_events,
+                       int n_iter, uint64_t seed, const mf_options* opt, mf_result* res)
+{
+    int ng = 0;
+    mf_status st;
+    if ((st = validate_process(proc, sqrt_s, &ng)) != MF_OK) return st;
+    if ((st = validate_pdf(pdf, proc->mu_f)) != MF_OK) return st;
+    const int D = 2 + 3 * ng - 4;
+    if ((st = validate_options(opt, D)) != MF_OK) return st;
+    if (!res)
+        return fail(MF_EINVAL, "result is NULL");
+    if (n_events < 2 || n_events > (1ull << 40))
+        return fail(MF_EINVAL, "n_events must be in [2, 2^40]");
+    if (n_iter < 1 || n_iter > 256)
+        return fail(MF_EINVAL, "n_iter must be in [1, 256]");
+    if ((uint64_t)opt->start_iter + (uint64_t)n_iter > 0xFFFFFFFFull)
+        return fail(MF_EINVAL, "iteration index exceeds the 32-bit Philox counter word");
+
+    Workspace* wsp = nullptr;
+    if ((st = device_workspace(&wsp)) != MF_OK) return st;
+    Workspace& ws = *wsp;
+    std::lock_guard<std::mutex> guard(ws.lock);
+
+    Setup S;
+    S.ng = ng;
+    S.D = D;
+    S.stream = (hipStream_t)opt->stream;
+    if ((st = prepare(proc, sqrt_s, pdf, opt, ws, S)) != MF_OK) return st;
+    mf::EventParams& P = S.P;
+
+    const int nb = opt->n_bins;
+    const uint64_t n_chunks = (n_events + mf::kWave - 1) / mf::kWave;
+    const int n_waves = waves_for(n_chunks, ws.n_cu);
+    const int stride = mf::kPartialHead + D * nb;
+    const size_t grid_bytes = sizeof(double) * D * (size_t)(nb + 1);
+    if ((st = ensure(ws.grid[0], grid_bytes)) != MF_OK) return st;
+    if ((st = ensure(ws.grid[1], grid_bytes)) != MF_OK) return st;
+    if ((st = ensure(ws.partials, sizeof(double) * (size_t)n_waves * stride)) != MF_OK) return st;
+    if ((st = ensure(ws.hist, sizeof(double) * D * (size_t)nb)) != MF_OK) return st;
+    if ((st = ensure(ws.iter_I, sizeof(double) * n_iter)) != MF_OK) return st;
+    if ((st = ensure(ws.iter_V, sizeof(double) * n_iter)) != MF_OK) return st;
+    if ((st = ensure(ws.stats, sizeof(double) * 4)) != MF_OK) return st;
+
+    std::vector<double> grid0((size_t)D * (nb + 1));
+    if (opt->grid_in)
+        std::memcpy(grid0.data(), opt->grid_in, grid_bytes);
+    else
+        for (int d = 0; d < D; ++d)
+            for (int i = 0; i <= nb; ++i)
+                grid0[(size_t)d * (nb + 1) + i] = (double)i / (double)nb;
+    MF_HIP(hipMemcpyAsync(ws.grid[0].ptr, grid0.data(), grid_bytes, hipMemcpyHostToDevice, S.stream));
+    MF_HIP(hipMemsetAsync(ws.stats.ptr, 0, sizeof(double) * 4, S.stream));
+
+    P.n_events = n_events;
+    P.seed = seed;
+    P.partials = (double*)ws.partials.ptr;
+    P.stride = stride;
+    P.n_waves = n_waves;
+    mf::ReduceParams R;
+    R.partials = P.partials;
+    R.n_waves = n_waves;
+    R.stride = stride;
+    R.n_dims = D;
+    R.n_bins = nb;
+    R.n_events = (double)n_events;
+    R.alpha = opt->alpha;
+    R.hist = (double*)ws.hist.ptr;
+    R.iter_I = (double*)ws.iter_I.ptr;
+    R.iter_V = (double*)ws.iter_V.ptr;
+    R.stats = (double*)ws.stats.ptr;
+
+    int cur = 0;
+    for (int j = 0; j < n_iter; ++j) {
+        P.iter = (uint32_t)(opt->start_iter + j);
+        P.grid = (const double*)ws.grid[cur].ptr;
+        P.weights = (j == n_iter - 1) ? res->weights : nullptr;
+        if ((st = dispatch_event(ng, opt->precision, P, n_waves / mf::kWavesPerBlock, S.stream)) != MF_OK)
+            return st;
+        R.grid_in = (const double*)ws.grid[cur].ptr;
+        R.grid_out = (double*)ws.grid[1 - cur].ptr;
+        R.j = j;
+        hipLaunchKernelGGL(mf::reduce_refine_kernel, dim3(1), dim3(256), 0, S.stream, R);
+        MF_HIP(hipGetLastError());
+        cur = 1 - cur;
+    }
+
+    std::vector<double> I(n_iter), V(n_iter), stats(4);
+    MF_HIP(hipMemcpyAsync(I.data(), ws.iter_I.ptr, sizeof(double) * n_iter, hipMemcpyDeviceToHost, S.stream));
+    MF_HIP(hipMemcpyAsync(V.data(), ws.iter_V.ptr, sizeof(double) * n_iter, hipMemcpyDeviceToHost, S.stream));
+    MF_HIP(hipMemcpyAsync(stats.data(), ws.stats.ptr, sizeof(double) * 4, hipMemcpyDeviceToHost, S.stream));
+    if (res->grid)
+        MF_HIP(hipMemcpyAsync(res->grid, ws.grid[cur].ptr, grid_bytes, hipMemcpyDeviceToHost, S.stream));
+    if (res->hist)
+        MF_HIP(hipMemcpyAsync(res->hist, ws.hist.ptr, sizeof(double) * D * (size_t)nb, hipMemcpyDeviceToHost,
+                              S.stream));
+    MF_HIP(hipStreamSynchronize(S.stream));
+
+    if (opt->strict && stats[2] > 0.0)
+        return fail(MF_ENOCONV, "mass-rescaling Newton iteration failed for " +
+                                    std::to_string((long long)stats[2]) + " events");
+    combine(n_iter, I.data(), V.data(), &res->sigma, &res->sigma_err, &res->chi2_dof);
+    res->w_max = stats[0];
+    res->n_pass = (int64_t)stats[1];
+    res->n_newton_fail = (int64_t)stats[2];
+    if (res->iter_sigma)
+        std::memcpy(res->iter_sigma, I.data(), sizeof(double) * n_iter);
+    if (res->iter_var)
+        std::memcpy(res->iter_var, V.data(), sizeof(double) * n_iter);
+    return MF_OK;
+}
+
+mf_status mf_evaluate(const mf_process* proc, double sqrt_s, const mf_pdf_grid* pdf, const double* grid,
+                      const double* y, const uint64_t* event_ids, uint64_t n, uint64_t seed, int iter,
+                      const mf_options* opt, double* w_out, uint64_t* k53_out, int32_t* bins_out,
+                      double* record_out)
+{
+    int ng = 0;
+    mf_status st;
+    if ((st = validate_process(proc, sqrt_s, &ng)) != MF_OK) return st;
+    if ((st = validate_pdf(pdf, proc->mu_f)) != MF_OK) return st;
+    const int D = 2 + 3 * ng - 4;
+    if ((st = validate_options(opt, D)) != MF_OK) return st;
+    if (!w_out)
+        return fail(MF_EINVAL, "w_out is NULL");
+    if (n < 1 || n > (1ull << 40))
+        return fail(MF_EINVAL, "n must be in [1, 2^40]");
+    if (iter < 0)
+        return fail(MF_EINVAL, "iter must be >= 0");
+    const int nb = opt->n_bins;
+    if (grid)
+        for (int d = 0; d < D; ++d) {
+            const double* e = grid + (size_t)d * (nb + 1);
+            if (e[0] != 0.0 || e[nb] != 1.0 || !ascending(e, nb + 1))
+                return fail(MF_EINVAL, "grid rows must rise strictly from 0 to 1");
+        }
+
+    Workspace* wsp = nullptr;
+    if ((st = device_workspace(&wsp)) != MF_OK) return st;
+    Workspace& ws = *wsp;
+    std::lock_guard<std::mutex> guard(ws.lock);
+    Setup S;
+    S.ng = ng;
+    S.D = D;
+    S.stream = (hipStream_t)opt->stream;
+    if ((st = prepare(proc, sqrt_s, pdf, opt, ws, S)) != MF_OK) return st;
+    mf::EventParams& P = S.P;
+    const size_t grid_bytes = sizeof(double) * D * (size_t)(nb + 1);
+    if ((st = ensure(ws.grid[0], grid_bytes)) != MF_OK) return st;
+    std::vector<double> g((size_t)D * (nb + 1));
+    if (grid)
+        std::memcpy(g.data(), grid, grid_bytes);
+    else
+        for (int d = 0; d < D; ++d)
+            for (int i = 0; i <= nb; ++i)
+                g[(size_t)d * (nb + 1) + i] = (double)i / (double)nb;
+    MF_HIP(hipMemcpyAsync(ws.grid[0].ptr, g.data(), grid_bytes, hipMemcpyHostToDevice, S.stream));
+    const uint64_t n_chunks = (n + mf::kWave - 1) / mf::kWave;
+    const int n_waves = waves_for(n_chunks, ws.n_cu);
+    P.n_events = n;
+    P.seed = seed;
+    P.iter = (uint32_t)iter;
+    P.grid = (const double*)ws.grid[0].ptr;
+    P.y_in = y;
+    P.event_ids = event_ids;
+    P.weights = w_out;
+    P.k53_out = k53_out;
+    P.bins_out = bins_out;
+    P.record = record_out;
+    P.partials = nullptr;
+    P.n_waves = n_waves;
+    if ((st = dispatch_event(ng, opt->precision, P, n_waves / mf::kWavesPerBlock, S.stream)) != MF_OK)
+        return st;
+    MF_HIP(hipStreamSynchronize(S.stream));
+    return MF_OK;
+}
+
+mf_status mf_refine_grid(int n_dims, int n_bins, double alpha, const double* hist, const double* grid_in,
+                         double* grid_out, void* stream)
+{
+    if (n_dims < 1 || n_dims > mf::kMaxDims)
+        return fail(MF_EINVAL, "n_dims must be in [1, 10]");
+    if (n_bins < 2 || n_bins > 1024)
+        return fail(MF_EINVAL, "n_bins must be in [2, 1024]");
+    if (!finite_pos(alpha))
+        return fail(MF_EINVAL, "alpha must be finite and > 0");
+    if (!hist || !grid_in || !grid_out || grid_in == grid_out)
+        return fail(MF_EINVAL, "hist, grid_in, grid_out must be distinct non-NULL device pointers");
+    Workspace* wsp = nullptr;
+    mf_status st;
+    if ((st = device_workspace(&wsp)) != MF_OK) return st;
+    Workspace& ws = *wsp;
+    std::lock_guard<std::mutex> guard(ws.lock);
+    if ((st = ensure(ws.partials, sizeof(double) * (mf::kPartialHead + n_dims * (size_t)n_bins))) != MF_OK)
+        return st;
+    if ((st = ensure(ws.iter_I, sizeof(double))) != MF_OK) return st;
+    if ((st = ensure(ws.iter_V, sizeof(double))) != MF_OK) return st;
+    if ((st = ensure(ws.stats, sizeof(double) * 4)) != MF_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    // a single partial row holding the given histogram
+    MF_HIP(hipMemsetAsync(ws.partials.ptr, 0, sizeof(double) * mf::kPartialHead, s));
+    MF_HIP(hipMemcpyAsync((double*)ws.partials.ptr + mf::kPartialHead, hist,
+                          sizeof(double) * n_dims * (size_t)n_bins, hipMemcpyDeviceToDevice, s));
+    mf::ReduceParams R;
+    R.partials = (const double*)ws.partials.ptr;
+    R.n_waves = 1;
+    R.stride = mf::kPartialHead + n_dims * n_bins;
+    R.n_dims = n_dims;
+    R.n_bins = n_bins;
+    R.n_events = 2.0;
+    R.alpha = alpha;
+    R.grid_in = grid_in;
+    R.grid_out = grid_out;
+    // the reduced histogram is written to a workspace buffer
+    if ((st = ensure(ws.hist, sizeof(double) * n_dims * (size_t)n_bins)) != MF_OK) return st;
+    R.hist = (double*)ws.hist.ptr;
+    R.iter_I = (double*)ws.iter_I.ptr;
+    R.iter_V = (double*)ws.iter_V.ptr;
+    R.stats = (double*)ws.stats.ptr;
+    R.j = 0;
+    hipLaunchKernelGGL(mf::reduce_refine_kernel, dim3(1), dim3(256), 0, s, R);
+    MF_HIP(hipGetLastError());
+    MF_HIP(hipStreamSynchronize(s));
+    return MF_OK;
+}
+
+mf_status mf_colour_matrix(int process_id, double* C)
+{
+    const int n = n_gluons(process_id);
+    if (n < 0)
+        return fail(MF_EINVAL, "unknown process id");
+    if (!C)
+        return fail(MF_EINVAL, "C is NULL");
+    const int* num = n == 2 ? mf::COLOUR_NUM_NG2 : (n == 3 ? mf::COLOUR_NUM_NG3 : mf::COLOUR_NUM_NG4);
+    const double den = n == 2 ? mf::COLOUR_DEN_NG2 : (n == 3 ? mf::COLOUR_DEN_NG3 : mf::COLOUR_DEN_NG4);
+    const int np = n == 2 ? 2 : (n == 3 ? 6 : 24);
+    for (int i = 0; i < np * np; ++i)
+        C[i] = (double)num[i] / den;
+    return MF_OK;
+}
+
+mf_status mf_matrix_element(int process_id, mf_precision precision, const double* mom, const double* eb,
+                            uint64_t n, double m_top, double w_top, double* out, void* stream)
+{
+    const int ng = n_gluons(process_id);
+    if (ng < 0)
+        return fail(MF_EINVAL, "unknown process id");
+    if (precision != MF_FP64 && precision != MF_FP32_KAHAN)
+        return fail(MF_EINVAL, "unknown precision");
+    if (!mom || !eb || !out)
+        return fail(MF_EINVAL, "mom, eb and out must be device pointers");
+    if (n < 1 || n > (1ull << 40))
+        return fail(MF_EINVAL, "n must be in [1, 2^40]");
+    if (!finite_pos(m_top) || !std::isfinite(w_top) || w_top < 0.0)
+        return fail(MF_EINVAL, "m_top must be > 0 and w_top >= 0");
+    hipStream_t s = (hipStream_t)stream;
+    const int epp = mf::kWave >> (ng + 2);              // events per wave
+    const uint64_t per_block = (uint64_t)epp * mf::kWavesPerBlock;
+    const uint64_t blocks = (n + per_block - 1) / per_block;
+    if (blocks > 0x7FFFFFFFull)
+        return fail(MF_EINVAL, "too many events for one launch");
+    const double mw = m_top * w_top;
+    const bool f32 = precision == MF_FP32_KAHAN;
+#define MF_ME_LAUNCH(NG)                                                                                   \
+    if (f32)                                                                                               \
+        hipLaunchKernelGGL((mf::me_kernel<NG, float>), dim3((unsigned)blocks), dim3(mf::kBlock), 0, s, mom, \
+                           eb, n, m_top, mw, out);                                                         \
+    else                                                                                                   \
+        hipLaunchKernelGGL((mf::me_kernel<NG, double>), dim3((unsigned)blocks), dim3(mf::kBlock), 0, s,    \
+                           mom, eb, n, m_top, mw, out);
+    if (ng == 2) { MF_ME_LAUNCH(2) } else if (ng == 3) { MF_ME_LAUNCH(3) } else { MF_ME_LAUNCH(4) }
+#undef MF_ME_LAUNCH
+    MF_HIP(hipGetLastError());
+    MF_HIP(hipStreamSynchronize(s));
+    return MF_OK;
+}
+
+}  // extern "C"

@@ -51,3 +51,21 @@ def test_interpolation_error_is_small_over_the_physical_range(pdf_table):
     for x in np.geomspace(7e-4, 0.3, 200):
         exact = x**-0.2 * (1 - x) ** 5 * (1 + 0.1 * math.log(q2))
         assert abs(O.pdf_xf(pdf_table, x, q2) / exact - 1) < 5e-4
+
+
+def test_interpolant_overshoot_is_flagged_ill_conditioned(pdf_table):
+    """The cubic in the last x interval overshoots below zero (the one-sided
+    end slope misses the (1 - x)^5 flatness at x = 1); near its zero crossing
+    the relative value is ill-conditioned and the event is flagged."""
+    q2 = 173.0**2
+    xs = np.linspace(0.70, 0.999, 3000)
+    vals = np.array([O.pdf_xf(pdf_table, x, q2) for x in xs])
+    assert vals.min() < 0 < vals.max()
+    x0 = xs[np.argmin(np.abs(vals))]
+    grid = np.tile(np.arange(51) / 50, (4, 1))
+    y_bad = np.array([0.1, x0, 0.3, 0.4])
+    y_bad[0] = 0.5
+    _, ev = O.event_weight_y(O.Process(n_g=2), 13000.0, pdf_table, grid, y_bad)
+    assert ev.pass_cuts and ev.ill_conditioned
+    _, ev = O.event_weight_y(O.Process(n_g=2), 13000.0, pdf_table, grid, np.array([0.05, 0.1, 0.3, 0.4]))
+    assert ev.pass_cuts and not ev.ill_conditioned
