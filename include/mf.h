@@ -76,6 +76,7 @@ typedef struct {
     int max_newton;          /* Newton step cap for the mass rescaling (50)     */
     const double *grid_in;   /* host [D][n_bins+1] start grid, NULL = uniform   */
     void *stream;            /* hipStream_t or NULL                             */
+    int profile;             /* 1: time every kernel with HIP events (0)        */
 } mf_options;
 
 typedef struct {
@@ -88,6 +89,8 @@ typedef struct {
     double *weights;         /* device [n_events] last-iteration weights, may be NULL */
     int64_t n_pass;          /* events passing threshold and cuts, last iteration */
     int64_t n_newton_fail;   /* Newton failures summed over all iterations      */
+    double event_kernel_ms;  /* profile = 1: summed event-kernel time, ms       */
+    double reduce_kernel_ms; /* profile = 1: summed reduce/refine time, ms      */
 } mf_result;
 
 /* Fills *opt with the defaults shown above. */

@@ -33,14 +33,15 @@ class mf_pdf_grid(C.Structure):
 class mf_options(C.Structure):
     _fields_ = [("n_bins", C.c_int), ("alpha", C.c_double), ("start_iter", C.c_int),
                 ("precision", C.c_int), ("strict", C.c_int), ("max_newton", C.c_int),
-                ("grid_in", _dp), ("stream", C.c_void_p)]
+                ("grid_in", _dp), ("stream", C.c_void_p), ("profile", C.c_int)]
 
 
 class mf_result(C.Structure):
     _fields_ = [("sigma", C.c_double), ("sigma_err", C.c_double), ("chi2_dof", C.c_double),
                 ("w_max", C.c_double), ("iter_sigma", _dp), ("iter_var", _dp), ("grid", _dp),
                 ("hist", _dp), ("weights", _dp), ("n_pass", C.c_int64),
-                ("n_newton_fail", C.c_int64)]
+                ("n_newton_fail", C.c_int64), ("event_kernel_ms", C.c_double),
+                ("reduce_kernel_ms", C.c_double)]
 
 
 EXPORTS = ("mf_default_options", "mf_n_dims", "mf_integrate", "mf_evaluate", "mf_refine_grid",

@@ -67,7 +67,7 @@ def n_dims(process) -> int:
     return lib.mf_n_dims(PROCESS_IDS[process])
 
 
-def _options(n_bins, alpha, start_iter, precision, strict, max_newton, grid_in, stream):
+def _options(n_bins, alpha, start_iter, precision, strict, max_newton, grid_in, stream, profile=False):
     o = _lib.mf_options()
     lib.mf_default_options(C.byref(o))
     o.n_bins = n_bins
@@ -78,6 +78,7 @@ def _options(n_bins, alpha, start_iter, precision, strict, max_newton, grid_in, 
     o.max_newton = max_newton
     o.grid_in = _ptr(grid_in) if grid_in is not None else None
     o.stream = _stream(stream)
+    o.profile = int(profile)
     return o
 
 
@@ -94,16 +95,19 @@ class IntegrationResult:
     grid: np.ndarray
     hist: np.ndarray
     weights: torch.Tensor | None
+    event_kernel_ms: float = 0.0
+    reduce_kernel_ms: float = 0.0
 
 
 def integrate(proc: Process, sqrt_s: float, pdf_table, n_events: int, n_iter: int, seed: int,
               n_bins: int = 50, alpha: float = 1.5, precision="fp64", start_iter: int = 0,
               grid_in=None, keep_weights: bool = True, strict: bool = False,
-              max_newton: int = 50, stream=None, weights_out: torch.Tensor | None = None):
+              max_newton: int = 50, stream=None, weights_out: torch.Tensor | None = None,
+              profile: bool = False):
     D = n_dims(proc.process)
     pdf = _Pdf(pdf_table)
     gin = None if grid_in is None else np.ascontiguousarray(grid_in, dtype=np.float64)
-    opt = _options(n_bins, alpha, start_iter, precision, strict, max_newton, gin, stream)
+    opt = _options(n_bins, alpha, start_iter, precision, strict, max_newton, gin, stream, profile)
     I = np.zeros(n_iter)
     V = np.zeros(n_iter)
     grid = np.zeros((D, n_bins + 1))
@@ -121,7 +125,8 @@ def integrate(proc: Process, sqrt_s: float, pdf_table, n_events: int, n_iter: in
     check(lib.mf_integrate(C.byref(pc), sqrt_s, C.byref(pdf.c), n_events, n_iter, seed,
                            C.byref(opt), C.byref(res)))
     return IntegrationResult(res.sigma, res.sigma_err, res.chi2_dof, res.w_max, res.n_pass,
-                             res.n_newton_fail, I, V, grid, hist, w)
+                             res.n_newton_fail, I, V, grid, hist, w, res.event_kernel_ms,
+                             res.reduce_kernel_ms)
 
 
 def evaluate_weights(proc: Process, sqrt_s: float, pdf_table, n: int, seed: int = 0, it: int = 0,

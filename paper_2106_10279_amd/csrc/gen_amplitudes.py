@@ -88,36 +88,60 @@ def mask(seq):
     return m
 
 
-class Emitter:
+class Layout:
+    """Offsets of the per-event table (doubles) shared by the helicity lanes:
+    subset momenta P[m], -1/P[m]^2, top-line momenta K[m] = k_t + P[m] and
+    propagator factors -1/(K^2 - m^2 + i m Gamma), ubar and v for both spins,
+    polarisation vectors of the final-state gluons for both states."""
+
     def __init__(self, n):
         self.n = n
+        off = 0
+        self.P = {}
+        for m in range(1, 1 << n):
+            self.P[m] = off
+            off += 4
+        self.ninv = {}
+        for m in range(1, 1 << n):
+            if bin(m).count("1") >= 2:
+                self.ninv[m] = off
+                off += 1
+        self.K = {}
+        for m in range(1, (1 << n) - 1):
+            self.K[m] = off          # K[0..3], fr, fi
+            off += 6
+        self.ub = off
+        off += 16
+        self.v = off
+        off += 16
+        self.eps = {}
+        for g in range(2, n):
+            self.eps[g] = off
+            off += 8
+        self.size = off
+
+
+class Emitter:
+    # Flop accounting (+, -, x = 1; fused multiply-add = 2; sqrt and divide
+    # = 1 each): `hel` counts the arithmetic that depends on the helicity
+    # configuration (done by every helicity lane), `mom` the arithmetic that
+    # depends on the momenta only (done once per event into the table).
+    def __init__(self, n, lay):
+        self.n = n
+        self.lay = lay
         self.lines = []
         self.done = set()
+        self.hel = 0
+        self.mom = 0
 
     def w(self, s=""):
         self.lines.append("    " + s)
 
-    # -- momenta (double) ----------------------------------------------------
-    def psum(self, m):
-        key = ("P", m)
-        if key in self.done:
-            return f"P{m}"
-        self.done.add(key)
-        gl = [g for g in range(self.n) if m >> g & 1]
-        for mu in range(4):
-            self.w(f"const double P{m}_{mu} = " + " + ".join(f"pg[{g}][{mu}]" for g in gl) + ";")
-        return f"P{m}"
-
-    def p2(self, m):
-        key = ("P2", m)
-        if key not in self.done:
-            self.done.add(key)
-            P = self.psum(m)
-            self.w(f"const T ninvP2_{m} = (T)(-1.0 / ({P}_0 * {P}_0 - {P}_1 * {P}_1 - {P}_2 * {P}_2 - {P}_3 * {P}_3));")
-        return f"ninvP2_{m}"
+    def pvec(self, m):
+        return f"(tab + {self.lay.P[m]})"
 
     # -- gluon currents (real 4-vectors) ---------------------------------------
-    def gcur(self, seq):
+    def gcur(self, seq, memo=True):
         seq = tuple(seq)
         if len(seq) == 1:
             return f"eps{seq[0]}"
@@ -126,10 +150,9 @@ class Emitter:
             return f"j{name(seq)}"
         rev = tuple(reversed(seq))
         if ("j", rev) in self.done:
+            # j(reverse s) = (-1)^(|s|+1) j(s): a signed view, no copy
             sign = "" if (len(seq) + 1) % 2 == 0 else "-"
-            self.done.add(key)
-            self.w(f"const T j{name(seq)}[4] = {{{', '.join(f'{sign}j{name(rev)}[{mu}]' for mu in range(4))}}};")
-            return f"j{name(seq)}"
+            return f"{sign}j{name(rev)}"
         L = len(seq)
         subs = []
         for a in range(1, L):
@@ -138,28 +161,31 @@ class Emitter:
         for a in range(1, L):
             for b in range(a + 1, L):
                 trip.append((self.gcur(seq[:a]), self.gcur(seq[a:b]), self.gcur(seq[b:])))
-        for (_, _, m1, m2) in subs:
-            self.psum(m1)
-            self.psum(m2)
-        f = self.p2(mask(seq))
         nm = f"j{name(seq)}"
-        self.done.add(key)
+        if memo:
+            self.done.add(key)
+        else:
+            nm = f"jq{name(seq)}"
         self.w(f"T {nm}[4];")
         self.w("{")
         self.w("    T a0 = 0, a1 = 0, a2 = 0, a3 = 0;")
         for (j1, j2, m1, m2) in subs:
-            P1, P2 = f"P{m1}", f"P{m2}"
-            q1 = [f"(T)(2.0 * {P1}_{mu} + {P2}_{mu})" for mu in range(4)]
-            q2 = [f"(T)({P1}_{mu} + 2.0 * {P2}_{mu})" for mu in range(4)]
-            d = [f"(T)({P2}_{mu} - {P1}_{mu})" for mu in range(4)]
+            # conserved currents (P1.j1 = P2.j2 = 0): bracket
+            # 2 (P1.j2) j1 - 2 (P2.j1) j2 + (j1.j2) (P2 - P1)
+            self.hel += 21 + 28
+            P1, P2 = self.pvec(m1), self.pvec(m2)
             self.w("    {")
-            self.w(f"        const T c1 = {q1[0]} * {j2}[0] - {q1[1]} * {j2}[1] - {q1[2]} * {j2}[2] - {q1[3]} * {j2}[3];")
-            self.w(f"        const T c2 = {q2[0]} * {j1}[0] - {q2[1]} * {j1}[1] - {q2[2]} * {j1}[2] - {q2[3]} * {j1}[3];")
+            self.w(f"        const double* p1 = {P1}; const double* p2 = {P2};")
+            self.w("        T q1[4], q2[4];")
+            self.w("        for (int mu = 0; mu < 4; ++mu) { q1[mu] = (T)p1[mu]; q2[mu] = (T)p2[mu]; }")
+            self.w(f"        const T c1 = (T)2 * (q1[0] * {j2}[0] - q1[1] * {j2}[1] - q1[2] * {j2}[2] - q1[3] * {j2}[3]);")
+            self.w(f"        const T c2 = (T)2 * (q2[0] * {j1}[0] - q2[1] * {j1}[1] - q2[2] * {j1}[2] - q2[3] * {j1}[3]);")
             self.w(f"        const T c12 = {j1}[0] * {j2}[0] - {j1}[1] * {j2}[1] - {j1}[2] * {j2}[2] - {j1}[3] * {j2}[3];")
             for mu in range(4):
-                self.w(f"        a{mu} += {j1}[{mu}] * c1 - {j2}[{mu}] * c2 + {d[mu]} * c12;")
+                self.w(f"        a{mu} += {j1}[{mu}] * c1 - {j2}[{mu}] * c2 + c12 * (q2[{mu}] - q1[{mu}]);")
             self.w("    }")
         for (j1, j2, j3) in trip:
+            self.hel += 21 + 28
             self.w("    {")
             self.w(f"        const T d23 = {j2}[0] * {j3}[0] - {j2}[1] * {j3}[1] - {j2}[2] * {j3}[2] - {j2}[3] * {j3}[3];")
             self.w(f"        const T d13 = {j1}[0] * {j3}[0] - {j1}[1] * {j3}[1] - {j1}[2] * {j3}[2] - {j1}[3] * {j3}[3];")
@@ -167,27 +193,12 @@ class Emitter:
             for mu in range(4):
                 self.w(f"        a{mu} += {j1}[{mu}] * d23 - (T)2 * {j2}[{mu}] * d13 + {j3}[{mu}] * d12;")
             self.w("    }")
+        self.hel += 4
+        self.w(f"    const T f = (T)tab[{self.lay.ninv[mask(seq)]}];")
         for mu in range(4):
-            self.w(f"    {nm}[{mu}] = a{mu} * {f};")
+            self.w(f"    {nm}[{mu}] = a{mu} * f;")
         self.w("}")
         return nm
-
-    # -- top-line propagator factor -(1/D) -----------------------------------
-    def topprop(self, m):
-        key = ("D", m)
-        if key not in self.done:
-            self.done.add(key)
-            P = self.psum(m)
-            self.w(f"const double K{m}_0 = kt[0] + {P}_0, K{m}_1 = kt[1] + {P}_1, "
-                   f"K{m}_2 = kt[2] + {P}_2, K{m}_3 = kt[3] + {P}_3;")
-            self.w(f"T fr{m}, fi{m};")
-            self.w("{")
-            self.w(f"    const double re = K{m}_0 * K{m}_0 - K{m}_1 * K{m}_1 - K{m}_2 * K{m}_2 - K{m}_3 * K{m}_3 - m2;")
-            self.w("    const double inv = 1.0 / (re * re + mw * mw);")
-            self.w(f"    fr{m} = (T)(-re * inv);")
-            self.w(f"    fi{m} = (T)(mw * inv);")
-            self.w("}")
-        return m
 
     # -- fermion prefix currents (row spinors) --------------------------------
     def fcur(self, seq):
@@ -201,17 +212,21 @@ class Emitter:
         for a in range(len(seq)):
             terms.append((self.fcur(seq[:a]), self.gcur(seq[a:])))
         m = mask(seq)
-        self.topprop(m)
         nm = f"U{name(seq)}"
         self.done.add(key)
         self.w(f"cT {nm}[4];")
         self.w("{")
         self.w("    cT s0 = cT(0, 0), s1 = cT(0, 0), s2 = cT(0, 0), s3 = cT(0, 0);")
+        self.hel += 50 * len(terms) + 80
         for (U, j) in terms:
             # row (aL, aR) x gamma.j = (aR (j.sigmabar), aL (j.sigma))
-            self.w(f"    rowslash_acc({U}, {j}, s0, s1, s2, s3);")
-        self.w(f"    const T Kc[4] = {{(T)K{m}_0, (T)K{m}_1, (T)K{m}_2, (T)K{m}_3}};")
-        self.w(f"    rowprop(s0, s1, s2, s3, Kc, (T)mt, fr{m}, fi{m}, {nm});")
+            if j.startswith("-"):
+                self.w(f"    rowslash_acc<-1>({U}, {j[1:]}, s0, s1, s2, s3);")
+            else:
+                self.w(f"    rowslash_acc({U}, {j}, s0, s1, s2, s3);")
+        o = self.lay.K[m]
+        self.w(f"    const T Kc[4] = {{(T)tab[{o}], (T)tab[{o + 1}], (T)tab[{o + 2}], (T)tab[{o + 3}]}};")
+        self.w(f"    rowprop(s0, s1, s2, s3, Kc, (T)mt, (T)tab[{o + 4}], (T)tab[{o + 5}], {nm});")
         self.w("}")
         return nm
 
@@ -224,42 +239,88 @@ class Emitter:
             return nm
         U = self.fcur(seq)
         self.done.add(key)
+        self.hel += 74
         self.w(f"cT {nm}[4];")
         self.w(f"bilinear(" + U + ", v, " + nm + ");")
         return nm
 
-    def wspin(self, g):
-        key = ("W", g)
-        nm = f"W{g}"
-        if key not in self.done:
-            self.done.add(key)
-            self.w(f"cT {nm}[4];")
-            self.w(f"slashcol(eps{g}, v, {nm});")
-        return nm
+
+def emit_table_fill(n, lay):
+    """Per-event table, filled by the lanes of one wave: lane m (1 .. 2^n - 1)
+    handles subset m; lanes 2^n .. 2^n + 3 the spinors; the next ones the
+    polarisation vectors."""
+    L = []
+    w = L.append
+    nsub = (1 << n) - 1
+    w("    const double m2 = mt * mt;")
+    w(f"    if (lane >= 1 && lane <= {nsub}) {{")
+    w("        const int m = lane;")
+    w("        double P0 = 0.0, P1 = 0.0, P2 = 0.0, P3 = 0.0;")
+    for g in range(n):
+        if g == 0:
+            pv = ["-eb", "0.0", "0.0", "-eb"]
+        elif g == 1:
+            pv = ["-eb", "0.0", "0.0", "eb"]
+        else:
+            pv = [f"mom[{8 + 4 * (g - 2) + mu}]" for mu in range(4)]
+        w(f"        if (m & {1 << g}) {{ P0 += {pv[0]}; P1 += {pv[1]}; P2 += {pv[2]}; P3 += {pv[3]}; }}")
+    w("        const int off_p = 4 * (m - 1);")
+    w("        tab[off_p + 0] = P0; tab[off_p + 1] = P1; tab[off_p + 2] = P2; tab[off_p + 3] = P3;")
+    # -1/P^2 for |m| >= 2
+    ninv_offsets = ", ".join(str(lay.ninv.get(m, -1)) for m in range(1, 1 << n))
+    w(f"        const int ninv_off[{nsub}] = {{{ninv_offsets}}};")
+    w("        if (ninv_off[m - 1] >= 0)")
+    w("            tab[ninv_off[m - 1]] = -1.0 / (P0 * P0 - P1 * P1 - P2 * P2 - P3 * P3);")
+    k_offsets = ", ".join(str(lay.K.get(m, -1)) for m in range(1, 1 << n))
+    w(f"        const int k_off[{nsub}] = {{{k_offsets}}};")
+    w("        if (k_off[m - 1] >= 0) {")
+    w("            const double K0 = mom[0] + P0, K1 = mom[1] + P1, K2 = mom[2] + P2, K3 = mom[3] + P3;")
+    w("            const double re = K0 * K0 - K1 * K1 - K2 * K2 - K3 * K3 - m2;")
+    w("            const double inv = 1.0 / (re * re + mw * mw);")
+    w("            double* k = tab + k_off[m - 1];")
+    w("            k[0] = K0; k[1] = K1; k[2] = K2; k[3] = K3;")
+    w("            k[4] = -re * inv;")
+    w("            k[5] = mw * inv;")
+    w("        }")
+    w("    }")
+    w(f"    if (lane >= {nsub + 1} && lane < {nsub + 5}) {{")
+    w(f"        const int t = lane - {nsub + 1};     // 0, 1: ubar spins; 2, 3: v spins")
+    w("        cplx<double> sp[4];")
+    w("        if (t < 2)")
+    w("            spinor_ubar<double>(mom, mt, t, sp);")
+    w("        else")
+    w("            spinor_v<double>(mom + 4, mt, t - 2, sp);")
+    w(f"        double* o = tab + (t < 2 ? {lay.ub} + 8 * t : {lay.v} + 8 * (t - 2));")
+    w("        for (int i = 0; i < 4; ++i) { o[2 * i] = sp[i].x; o[2 * i + 1] = sp[i].y; }")
+    w("    }")
+    if n > 2:
+        w(f"    if (lane >= {nsub + 5} && lane < {nsub + 5 + 2 * (n - 2)}) {{")
+        w(f"        const int t = lane - {nsub + 5};")
+        w("        const int g = 2 + t / 2, h = t & 1;")
+        w("        double e[4];")
+        w("        linear_pol<double>(mom + 8 + 4 * (g - 2), h, e);")
+        w(f"        double* o = tab + {lay.eps[2]} + 8 * (g - 2) + 4 * h;")
+        w("        for (int mu = 0; mu < 4; ++mu) o[mu] = e[mu];")
+        w("    }")
+    return "\n".join(L)
 
 
 def generate(n):
     perms, K, den = colour_matrix(n)
-    e = Emitter(n)
+    lay = Layout(n)
+    e = Emitter(n, lay)
     nperm = len(perms)
     e.w("const int sT = hel & 1, sB = (hel >> 1) & 1;")
-    e.w(f"double pg[{n}][4];")
-    e.w("pg[0][0] = -eb; pg[0][1] = 0.0; pg[0][2] = 0.0; pg[0][3] = -eb;")
-    e.w("pg[1][0] = -eb; pg[1][1] = 0.0; pg[1][2] = 0.0; pg[1][3] = eb;")
-    for g in range(2, n):
-        e.w(f"for (int mu = 0; mu < 4; ++mu) pg[{g}][mu] = mom[{8 + 4 * (g - 2)} + mu];")
-    e.w("const double kt[4] = {mom[0], mom[1], mom[2], mom[3]};")
-    e.w("const double kb[4] = {mom[4], mom[5], mom[6], mom[7]};")
-    e.w("const double m2 = mt * mt;")
     for g in range(n):
         if g < 2:
             e.w(f"const T eps{g}[4] = {{(T)0, (T)(((hel >> {2 + g}) & 1) ? 0 : 1), (T)(((hel >> {2 + g}) & 1) ? 1 : 0), (T)0}};")
         else:
             e.w(f"T eps{g}[4];")
-            e.w(f"linear_pol(pg[{g}], (hel >> {2 + g}) & 1, eps{g});")
+            e.w(f"{{ const double* q = tab + {lay.eps[g]} + 4 * ((hel >> {2 + g}) & 1); "
+                f"for (int mu = 0; mu < 4; ++mu) eps{g}[mu] = (T)q[mu]; }}")
     e.w("cT ub[4], v[4];")
-    e.w("spinor_ubar(kt, mt, sT, ub);")
-    e.w("spinor_v(kb, mt, sB, v);")
+    e.w(f"{{ const double* q = tab + {lay.ub} + 8 * sT; for (int i = 0; i < 4; ++i) ub[i] = cT((T)q[2 * i], (T)q[2 * i + 1]); }}")
+    e.w(f"{{ const double* q = tab + {lay.v} + 8 * sB; for (int i = 0; i < 4; ++i) v[i] = cT((T)q[2 * i], (T)q[2 * i + 1]); }}")
     e.w(f"cT A[{nperm}];")
     e.w("T me = 0;")
     for idx, sg in enumerate(perms):
@@ -267,15 +328,24 @@ def generate(n):
         parts = []
         for k in range(n - 1):
             c = e.bilinear(sg[:k])
-            j = e.gcur(sg[k:])
-            parts.append(("cj", c, j))
+            # the full-length current is used by one ordering only: computed
+            # here and dropped, instead of being kept for its reflection
+            j = e.gcur(sg[k:], memo=(k > 0))
+            parts.append((c, j))
         U = e.fcur(sg[:n - 1])
-        W = e.wspin(sg[n - 1])
+        e.hel += 42                  # W = gamma.eps v for the last gluon
+        e.hel += 16 * len(parts) + 32 + 2 + 4
+        e.hel += 4 * sum(1 for t in range(idx) if K[idx][t] != 0)
         e.w("{")
         e.w("    T ar = 0, ai = 0;")
-        for (_, c, j) in parts:
-            e.w(f"    cdotj({c}, {j}, ar, ai);")
-        e.w(f"    rowdotcol({U}, {W}, ar, ai);")
+        for (c, j) in parts:
+            if j.startswith("-"):
+                e.w(f"    cdotj<-1>({c}, {j[1:]}, ar, ai);")
+            else:
+                e.w(f"    cdotj({c}, {j}, ar, ai);")
+        e.w("    cT W[4];")
+        e.w(f"    slashcol(eps{sg[n - 1]}, v, W);")
+        e.w(f"    rowdotcol({U}, W, ar, ai);")
         e.w(f"    A[{idx}] = cT(ar, ai);")
         # incremental colour sum: K_ss |A_s|^2 + 2 Re(conj(A_s) sum_{t<s} K_st A_t)
         e.w(f"    T tr = {K[idx][idx]} * ar, ti = {K[idx][idx]} * ai;")
@@ -284,27 +354,57 @@ def generate(n):
                 e.w(f"    tr += (T)({2 * K[idx][t]}) * A[{t}].x; ti += (T)({2 * K[idx][t]}) * A[{t}].y;")
         e.w("    me += ar * tr + ai * ti;")
         e.w("}")
+    # momentum-only work, done once per event for the table
+    nsub = (1 << n) - 1
+    e.mom = sum(4 * (bin(m).count("1") - 1) for m in range(1, 1 << n)) + 8 * len(lay.ninv) \
+        + (4 + 8 + 3 + 2) * len(lay.K) + 4 * 24 + (n - 2) * 2 * 16 + 2
     body = "\n".join(e.lines)
+    fill = emit_table_fill(n, lay)
+    global _LAST_COUNT
+    _LAST_COUNT = {"per_helicity": e.hel, "momentum_only": e.mom, "n_hel": 1 << (n + 2),
+                   "n_orderings": nperm, "table_doubles": lay.size}
     kdecl = ", ".join(str(v) for row in K for v in row)
     return f"""// Generated by gen_amplitudes.py for g g -> t tbar + {n - 2} gluon(s): {nperm} colour orderings,
 // {1 << (n + 2)} helicity configurations.  Do not edit.
+// Arithmetic per helicity configuration: {e.hel} flops; per event (table): {e.mom} flops.
+static constexpr int FLOPS_PER_HEL_NG{n} = {e.hel};
+static constexpr int FLOPS_MOMENTUM_NG{n} = {e.mom};
 static constexpr int NPERM_NG{n} = {nperm};
+static constexpr int TABLE_NG{n} = {lay.size};
 static constexpr double COLOUR_DEN_NG{n} = {den}.0;
 static constexpr int COLOUR_NUM_NG{n}[{nperm * nperm}] = {{{kdecl}}};
 
-// Sum over colours of |M|^2 for helicity configuration `hel` (bit 0: top
-// spin, bit 1: antitop spin, bit 2+g: gluon g polarisation), g_s = 1.
+// Per-event table of momentum-only quantities, written by the lanes of one
+// wave (lane index `lane`); the caller synchronises the wave afterwards.
 // mom: t[4], tbar[4], final gluons[4 each]; eb: beam energy sqrt(s_hat)/2;
 // mt: top mass; mw: m_t * Gamma_t.
+__device__ __forceinline__ void fill_table_ng{n}(const double* __restrict__ mom, double eb, double mt,
+                                                double mw, double* __restrict__ tab, int lane)
+{{
+{fill}
+}}
+
+// Sum over colours of |M|^2 for helicity configuration `hel` (bit 0: top
+// spin, bit 1: antitop spin, bit 2+g: gluon g polarisation), g_s = 1,
+// from the event's table.
 template <typename T>
-__device__ __forceinline__ double colour_summed_me2_ng{n}(const double* __restrict__ mom, double eb,
-                                                         int hel, double mt, double mw)
+__device__ __forceinline__ double colour_summed_me2_ng{n}(const double* __restrict__ tab_in, int hel, double mt)
 {{
     using cT = cplx<T>;
+    const double* __restrict__ tab = tab_in;
 {body}
     return (double)me / COLOUR_DEN_NG{n};
 }}
 """
+
+
+_LAST_COUNT = None
+
+
+def flop_count(n):
+    """Algorithmic flops of the generated |M|^2 code for n gluons."""
+    generate(n)
+    return dict(_LAST_COUNT)
 
 
 def main():

@@ -31,11 +31,12 @@ __device__ __forceinline__ cplx<T> cmul(cplx<T> a, cplx<T> b)
 //   j.sigmabar = [[j0 + j3,  j1 - i j2], [ j1 + i j2, j0 - j3]]
 // ---------------------------------------------------------------------------
 
-// s += a x gamma.j for a row spinor a: (aR (j.sigmabar), aL (j.sigma)).
-template <typename T>
-__device__ __forceinline__ void rowslash_acc(const cplx<T>* a, const T* j, cplx<T>& s0, cplx<T>& s1,
+// s += a x gamma.(SGN j) for a row spinor a: (aR (j.sigmabar), aL (j.sigma)).
+template <int SGN = 1, typename T>
+__device__ __forceinline__ void rowslash_acc(const cplx<T>* a, const T* jin, cplx<T>& s0, cplx<T>& s1,
                                              cplx<T>& s2, cplx<T>& s3)
 {
+    const T j[4] = {(T)SGN * jin[0], (T)SGN * jin[1], (T)SGN * jin[2], (T)SGN * jin[3]};
     const T jp = j[0] + j[3], jm = j[0] - j[3];
     // s0 += aR0 (j0 + j3) + aR1 (j1 + i j2)
     s0.x += a[2].x * jp + a[3].x * j[1] - a[3].y * j[2];
@@ -92,12 +93,14 @@ __device__ __forceinline__ void bilinear(const cplx<T>* a, const cplx<T>* v, cpl
     c[3] = cplx<T>(s0.x - s1.x - t0.x + t1.x, s0.y - s1.y - t0.y + t1.y);
 }
 
-// (ar, ai) += c^mu j_mu for complex c and real j.
-template <typename T>
+// (ar, ai) += SGN c^mu j_mu for complex c and real j.
+template <int SGN = 1, typename T>
 __device__ __forceinline__ void cdotj(const cplx<T>* c, const T* j, T& ar, T& ai)
 {
-    ar += c[0].x * j[0] - c[1].x * j[1] - c[2].x * j[2] - c[3].x * j[3];
-    ai += c[0].y * j[0] - c[1].y * j[1] - c[2].y * j[2] - c[3].y * j[3];
+    const T r = c[0].x * j[0] - c[1].x * j[1] - c[2].x * j[2] - c[3].x * j[3];
+    const T i = c[0].y * j[0] - c[1].y * j[1] - c[2].y * j[2] - c[3].y * j[3];
+    ar += (T)SGN * r;
+    ai += (T)SGN * i;
 }
 
 // W = gamma.e v = ((e.sigma) vR, (e.sigmabar) vL) for a real 4-vector e.

@@ -299,15 +299,26 @@ __device__ __forceinline__ double group_sum(double v, int width)
     return v;
 }
 
-template <int NG, typename T>
-__device__ __forceinline__ double colour_summed_me2(const double* mom, double eb, int hel, double mt, double mw)
+template <int NG>
+__device__ __forceinline__ void fill_table(const double* mom, double eb, double mt, double mw, double* tab, int lane)
 {
     if constexpr (NG == 2)
-        return colour_summed_me2_ng2<T>(mom, eb, hel, mt, mw);
+        fill_table_ng2(mom, eb, mt, mw, tab, lane);
     else if constexpr (NG == 3)
-        return colour_summed_me2_ng3<T>(mom, eb, hel, mt, mw);
+        fill_table_ng3(mom, eb, mt, mw, tab, lane);
     else
-        return colour_summed_me2_ng4<T>(mom, eb, hel, mt, mw);
+        fill_table_ng4(mom, eb, mt, mw, tab, lane);
+}
+
+template <int NG, typename T>
+__device__ __forceinline__ double colour_summed_me2(const double* tab, int hel, double mt)
+{
+    if constexpr (NG == 2)
+        return colour_summed_me2_ng2<T>(tab, hel, mt);
+    else if constexpr (NG == 3)
+        return colour_summed_me2_ng3<T>(tab, hel, mt);
+    else
+        return colour_summed_me2_ng4<T>(tab, hel, mt);
 }
 
 // Momenta stored per event: t[4], tbar[4], final gluons[4 each], beam energy.
@@ -316,6 +327,7 @@ struct Layout {
     static constexpr int kMom = 8 + 4 * (NG - 2) + 1;
     static constexpr int kHel = 1 << (NG + 2);
     static constexpr int kEventsPerPass = kWave / kHel;   // 4, 2, 1
+    static constexpr int kTable = NG == 2 ? TABLE_NG2 : (NG == 3 ? TABLE_NG3 : TABLE_NG4);
 };
 
 template <int NG, typename T>
@@ -331,6 +343,7 @@ __global__ void __launch_bounds__(kBlock) event_kernel(EventParams P)
     __shared__ double s_lx[kMaxPdfX];
     __shared__ double s_rows[4 * kMaxPdfX];
     __shared__ double s_lq[4];
+    __shared__ double s_tab[kWavesPerBlock][L::kEventsPerPass][L::kTable];
     extern __shared__ double s_hist[];     // [kWavesPerBlock][D][n_bins]
 
     const int tid = threadIdx.x;
@@ -455,18 +468,26 @@ __global__ void __launch_bounds__(kBlock) event_kernel(EventParams P)
         wave_sync();
 
         // ---------------- phase 2: one helicity configuration per lane -----
+        // The lanes of each event first fill its table of momentum-only
+        // quantities, then every lane evaluates one helicity configuration.
         {
             const int h = lane % L::kHel;
             const int sub = lane / L::kHel;
+            double* tab = s_tab[wv][sub];
             for (int g = 0; g < kWave / L::kEventsPerPass; ++g) {
                 const int e = g * L::kEventsPerPass + sub;
                 const double* m_e = s_mom[wv][e];
+                const bool live = s_pref[wv][e] != 0.0;
+                if (live)
+                    fill_table<NG>(m_e, m_e[L::kMom - 1], P.m_top, P.mw, tab, h);
+                wave_sync();
                 double v = 0.0;
-                if (s_pref[wv][e] != 0.0)
-                    v = colour_summed_me2<NG, T>(m_e, m_e[L::kMom - 1], h, P.m_top, P.mw);
+                if (live)
+                    v = colour_summed_me2<NG, T>(tab, h, P.m_top);
                 v = group_sum(v, L::kHel);
                 if (h == 0)
                     s_me[wv][e] = v;
+                wave_sync();
             }
         }
         wave_sync();
@@ -512,69 +533,99 @@ __global__ void __launch_bounds__(kBlock) event_kernel(EventParams P)
             npass += op;
             nfail += of;
         }
-        double* out = P.partials + (size_t)wave_id * P.stride;
+        // entry-major rows: entry k of wave w at partials[k * n_waves + w]
+        double* out = P.partials + wave_id;
+        const size_t nw = (size_t)P.n_waves;
         if (lane == 0) {
-            out[0] = sw.s;
-            out[1] = sw.c;
-            out[2] = sw2.s;
-            out[3] = sw2.c;
-            out[4] = wmax;
-            out[5] = npass;
-            out[6] = nfail;
-            out[7] = 0.0;
+            out[0 * nw] = sw.s;
+            out[1 * nw] = sw.c;
+            out[2 * nw] = sw2.s;
+            out[3 * nw] = sw2.c;
+            out[4 * nw] = wmax;
+            out[5 * nw] = npass;
+            out[6 * nw] = nfail;
+            out[7 * nw] = 0.0;
         }
         for (int i = lane; i < D * nb; i += kWave)
-            out[kPartialHead + i] = hist[i];
+            out[(kPartialHead + i) * nw] = hist[i];
     }
 }
 
 // ---------------------------------------------------------------------------
-// Reduce the per-wave rows in wave order, estimate I_j and V_j, refine grid.
+// Reduce the per-wave partials: one workgroup per entry (entry-major layout,
+// coalesced), each thread a fixed strided subset of waves with compensated
+// sums, then a fixed-shape tree in LDS -- the result does not depend on
+// scheduling.  Then one workgroup estimates I_j, V_j and refines the grid.
 // ---------------------------------------------------------------------------
 struct ReduceParams {
-    const double* partials;
+    const double* partials;  // [stride][n_waves]
     int n_waves, stride, n_dims, n_bins;
     double n_events, alpha;
     const double* grid_in;
     double* grid_out;
-    double* hist;            // [D][n_bins] out
+    double* entries;         // [stride] reduced entries
+    const double* hist;      // [D][n_bins] reduced histogram (read by refine)
     double* iter_I;          // [n_iter]
     double* iter_V;
     double* stats;           // [4]: w_max (this iteration), n_pass, n_fail (cumulative)
     int j;
 };
 
-__global__ void __launch_bounds__(256) reduce_refine_kernel(ReduceParams R)
+constexpr int kReduceBlock = 256;
+
+__global__ void __launch_bounds__(kReduceBlock) reduce_entries_kernel(ReduceParams R)
+{
+    __shared__ double s_s[kReduceBlock], s_c[kReduceBlock];
+    const int k = blockIdx.x;            // entry
+    const int tid = threadIdx.x;
+    const double* row = R.partials + (size_t)k * R.n_waves;
+    Neumaier a{0.0, 0.0};
+    double mx = 0.0;
+    if (k == 0 || k == 2) {
+        // compensated pairs (s, c) of sum w and sum w^2
+        const double* crow = row + R.n_waves;
+        for (int w = tid; w < R.n_waves; w += kReduceBlock)
+            a = nm_merge(a, Neumaier{row[w], crow[w]});
+    } else if (k == 4) {
+        for (int w = tid; w < R.n_waves; w += kReduceBlock)
+            mx = fmax(mx, row[w]);
+        a.s = mx;
+    } else {
+        for (int w = tid; w < R.n_waves; w += kReduceBlock)
+            nm_add(a, row[w]);
+    }
+    s_s[tid] = a.s;
+    s_c[tid] = a.c;
+    __syncthreads();
+    for (int off = kReduceBlock / 2; off > 0; off >>= 1) {
+        if (tid < off) {
+            if (k == 4) {
+                s_s[tid] = fmax(s_s[tid], s_s[tid + off]);
+            } else {
+                const Neumaier m = nm_merge(Neumaier{s_s[tid], s_c[tid]}, Neumaier{s_s[tid + off], s_c[tid + off]});
+                s_s[tid] = m.s;
+                s_c[tid] = m.c;
+            }
+        }
+        __syncthreads();
+    }
+    if (tid == 0)
+        R.entries[k] = (k == 4) ? s_s[0] : s_s[0] + s_c[0];
+}
+
+__global__ void __launch_bounds__(256) refine_kernel(ReduceParams R)
 {
     const int tid = threadIdx.x;
-    const int nh = R.n_dims * R.n_bins;
-    for (int i = tid; i < nh; i += blockDim.x) {
-        Neumaier a{0.0, 0.0};
-        for (int w = 0; w < R.n_waves; ++w)
-            nm_add(a, R.partials[(size_t)w * R.stride + kPartialHead + i]);
-        R.hist[i] = a.s + a.c;
-    }
     if (tid == 0) {
-        Neumaier s1{0.0, 0.0}, s2{0.0, 0.0};
-        double wmax = 0.0, np = 0.0, nf = 0.0;
-        for (int w = 0; w < R.n_waves; ++w) {
-            const double* row = R.partials + (size_t)w * R.stride;
-            s1 = nm_merge(s1, Neumaier{row[0], row[1]});
-            s2 = nm_merge(s2, Neumaier{row[2], row[3]});
-            wmax = fmax(wmax, row[4]);
-            np += row[5];
-            nf += row[6];
-        }
         const double N = R.n_events;
-        const double I = (s1.s + s1.c) / N;
-        const double V = ((s2.s + s2.c) / N - I * I) / (N - 1.0);
+        const double I = R.entries[0] / N;
+        const double V = (R.entries[2] / N - I * I) / (N - 1.0);
         R.iter_I[R.j] = I;
         R.iter_V[R.j] = V;
-        R.stats[0] = wmax;
-        R.stats[1] = np;
-        R.stats[2] += nf;
+        R.stats[0] = R.entries[4];
+        R.stats[1] = R.entries[5];
+        R.stats[2] += R.entries[6];
     }
-    __syncthreads();
     // One thread per dimension: smoothing, damping, equal-share rebinning.
     for (int d = tid; d < R.n_dims; d += blockDim.x) {
         const int n = R.n_bins;
@@ -635,13 +686,19 @@ __global__ void __launch_bounds__(kBlock) me_kernel(const double* __restrict__ m
                                                      uint64_t n, double mt, double mw, double* __restrict__ out)
 {
     using L = Layout<NG>;
+    __shared__ double s_tab[kWavesPerBlock][L::kEventsPerPass][L::kTable];
     const int lane = threadIdx.x % kWave;
-    const uint64_t wave = (uint64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+    const int wv = threadIdx.x / kWave;
+    const uint64_t wave = (uint64_t)blockIdx.x * kWavesPerBlock + wv;
     const uint64_t e = wave * L::kEventsPerPass + lane / L::kHel;
     const int h = lane % L::kHel;
+    double* tab = s_tab[wv][lane / L::kHel];
+    if (e < n)
+        fill_table<NG>(mom + e * (L::kMom - 1), eb[e], mt, mw, tab, h);
+    wave_sync();
     double v = 0.0;
     if (e < n)
-        v = colour_summed_me2<NG, T>(mom + e * (L::kMom - 1), eb[e], h, mt, mw);
+        v = colour_summed_me2<NG, T>(tab, h, mt);
     v = group_sum(v, L::kHel);
     if (h == 0 && e < n)
         out[e] = v;

@@ -60,7 +60,7 @@ struct Buffer {
 
 struct Workspace {
     std::mutex lock;
-    Buffer grid[2], log_x, log_q2, xf, partials, hist, iter_I, iter_V, stats;
+    Buffer grid[2], log_x, log_q2, xf, partials, entries, iter_I, iter_V, stats;
     int n_cu = 0;
 };
 
@@ -330,6 +330,7 @@ void mf_default_options(mf_options* opt)
     opt->max_newton = 50;
     opt->grid_in = nullptr;
     opt->stream = nullptr;
+    opt->profile = 0;
 }
 
 int mf_n_dims(int process_id)
@@ -378,7 +379,7 @@ mf_status mf_integrate(const mf_process* proc, double sqrt_s, const mf_pdf_grid*
     if ((st = ensure(ws.grid[0], grid_bytes)) != MF_OK) return st;
     if ((st = ensure(ws.grid[1], grid_bytes)) != MF_OK) return st;
     if ((st = ensure(ws.partials, sizeof(double) * (size_t)n_waves * stride)) != MF_OK) return st;
-    if ((st = ensure(ws.hist, sizeof(double) * D * (size_t)nb)) != MF_OK) return st;
+    if ((st = ensure(ws.entries, sizeof(double) * (size_t)stride)) != MF_OK) return st;
     if ((st = ensure(ws.iter_I, sizeof(double) * n_iter)) != MF_OK) return st;
     if ((st = ensure(ws.iter_V, sizeof(double) * n_iter)) != MF_OK) return st;
     if ((st = ensure(ws.stats, sizeof(double) * 4)) != MF_OK) return st;
@@ -406,23 +407,40 @@ mf_status mf_integrate(const mf_process* proc, double sqrt_s, const mf_pdf_grid*
     R.n_bins = nb;
     R.n_events = (double)n_events;
     R.alpha = opt->alpha;
-    R.hist = (double*)ws.hist.ptr;
+    R.entries = (double*)ws.entries.ptr;
+    R.hist = R.entries + mf::kPartialHead;
     R.iter_I = (double*)ws.iter_I.ptr;
     R.iter_V = (double*)ws.iter_V.ptr;
     R.stats = (double*)ws.stats.ptr;
 
+    // Optional per-kernel timing: events recorded on the stream around every
+    // launch (marks[3j] .. marks[3j+2]).
+    std::vector<hipEvent_t> marks;
+    if (opt->profile) {
+        marks.resize(3 * (size_t)n_iter);
+        for (auto& ev : marks)
+            MF_HIP(hipEventCreate(&ev));
+    }
     int cur = 0;
     for (int j = 0; j < n_iter; ++j) {
         P.iter = (uint32_t)(opt->start_iter + j);
         P.grid = (const double*)ws.grid[cur].ptr;
         P.weights = (j == n_iter - 1) ? res->weights : nullptr;
+        if (opt->profile)
+            MF_HIP(hipEventRecord(marks[3 * j], S.stream));
         if ((st = dispatch_event(ng, opt->precision, P, n_waves / mf::kWavesPerBlock, S.stream)) != MF_OK)
             return st;
+        if (opt->profile)
+            MF_HIP(hipEventRecord(marks[3 * j + 1], S.stream));
         R.grid_in = (const double*)ws.grid[cur].ptr;
         R.grid_out = (double*)ws.grid[1 - cur].ptr;
         R.j = j;
-        hipLaunchKernelGGL(mf::reduce_refine_kernel, dim3(1), dim3(256), 0, S.stream, R);
+        hipLaunchKernelGGL(mf::reduce_entries_kernel, dim3(stride), dim3(mf::kReduceBlock), 0, S.stream, R);
         MF_HIP(hipGetLastError());
+        hipLaunchKernelGGL(mf::refine_kernel, dim3(1), dim3(256), 0, S.stream, R);
+        MF_HIP(hipGetLastError());
+        if (opt->profile)
+            MF_HIP(hipEventRecord(marks[3 * j + 2], S.stream));
         cur = 1 - cur;
     }
 
@@ -433,9 +451,22 @@ mf_status mf_integrate(const mf_process* proc, double sqrt_s, const mf_pdf_grid*
     if (res->grid)
         MF_HIP(hipMemcpyAsync(res->grid, ws.grid[cur].ptr, grid_bytes, hipMemcpyDeviceToHost, S.stream));
     if (res->hist)
-        MF_HIP(hipMemcpyAsync(res->hist, ws.hist.ptr, sizeof(double) * D * (size_t)nb, hipMemcpyDeviceToHost,
-                              S.stream));
+        MF_HIP(hipMemcpyAsync(res->hist, (double*)ws.entries.ptr + mf::kPartialHead, sizeof(double) * D * (size_t)nb,
+                              hipMemcpyDeviceToHost, S.stream));
     MF_HIP(hipStreamSynchronize(S.stream));
+    res->event_kernel_ms = 0.0;
+    res->reduce_kernel_ms = 0.0;
+    if (opt->profile) {
+        for (int j = 0; j < n_iter; ++j) {
+            float a = 0.f, b = 0.f;
+            MF_HIP(hipEventElapsedTime(&a, marks[3 * j], marks[3 * j + 1]));
+            MF_HIP(hipEventElapsedTime(&b, marks[3 * j + 1], marks[3 * j + 2]));
+            res->event_kernel_ms += a;
+            res->reduce_kernel_ms += b;
+        }
+        for (auto& ev : marks)
+            (void)hipEventDestroy(ev);
+    }
 
     if (opt->strict && stats[2] > 0.0)
         return fail(MF_ENOCONV, "mass-rescaling Newton iteration failed for " +
@@ -532,34 +563,27 @@ mf_status mf_refine_grid(int n_dims, int n_bins, double alpha, const double* his
     if ((st = device_workspace(&wsp)) != MF_OK) return st;
     Workspace& ws = *wsp;
     std::lock_guard<std::mutex> guard(ws.lock);
-    if ((st = ensure(ws.partials, sizeof(double) * (mf::kPartialHead + n_dims * (size_t)n_bins))) != MF_OK)
-        return st;
+    if ((st = ensure(ws.entries, sizeof(double) * mf::kPartialHead)) != MF_OK) return st;
     if ((st = ensure(ws.iter_I, sizeof(double))) != MF_OK) return st;
     if ((st = ensure(ws.iter_V, sizeof(double))) != MF_OK) return st;
     if ((st = ensure(ws.stats, sizeof(double) * 4)) != MF_OK) return st;
     hipStream_t s = (hipStream_t)stream;
-    // a single partial row holding the given histogram
-    MF_HIP(hipMemsetAsync(ws.partials.ptr, 0, sizeof(double) * mf::kPartialHead, s));
-    MF_HIP(hipMemcpyAsync((double*)ws.partials.ptr + mf::kPartialHead, hist,
-                          sizeof(double) * n_dims * (size_t)n_bins, hipMemcpyDeviceToDevice, s));
+    MF_HIP(hipMemsetAsync(ws.entries.ptr, 0, sizeof(double) * mf::kPartialHead, s));
     mf::ReduceParams R;
-    R.partials = (const double*)ws.partials.ptr;
-    R.n_waves = 1;
-    R.stride = mf::kPartialHead + n_dims * n_bins;
+    std::memset(&R, 0, sizeof(R));
     R.n_dims = n_dims;
     R.n_bins = n_bins;
     R.n_events = 2.0;
     R.alpha = alpha;
     R.grid_in = grid_in;
     R.grid_out = grid_out;
-    // the reduced histogram is written to a workspace buffer
-    if ((st = ensure(ws.hist, sizeof(double) * n_dims * (size_t)n_bins)) != MF_OK) return st;
-    R.hist = (double*)ws.hist.ptr;
+    R.entries = (double*)ws.entries.ptr;
+    R.hist = hist;
     R.iter_I = (double*)ws.iter_I.ptr;
     R.iter_V = (double*)ws.iter_V.ptr;
     R.stats = (double*)ws.stats.ptr;
     R.j = 0;
-    hipLaunchKernelGGL(mf::reduce_refine_kernel, dim3(1), dim3(256), 0, s, R);
+    hipLaunchKernelGGL(mf::refine_kernel, dim3(1), dim3(256), 0, s, R);
     MF_HIP(hipGetLastError());
     MF_HIP(hipStreamSynchronize(s));
     return MF_OK;
