@@ -49,8 +49,7 @@ def me_flops(n_g):
     spec = importlib.util.spec_from_file_location("gen_amplitudes", path)
     mod = importlib.util.module_from_spec(spec)
     spec.loader.exec_module(mod)
-    c = mod.flop_count(n_g)
-    return c["per_helicity"] * c["n_hel"] + c["momentum_only"]
+    return mod.flop_count(n_g)["per_event"]
 
 
 def timed_run(api, torch, proc, pdf, n_events, steps, warmup, precision, seed):

@@ -110,12 +110,17 @@ class Layout:
         for m in range(1, (1 << n) - 1):
             self.K[m] = off          # K[0..3], fr, fi
             off += 6
+        self.Kv = {}
+        for m in range(1, 1 << n):
+            if 1 <= bin(m).count("1") <= n - 2:
+                self.Kv[m] = off     # -k_tbar - P[m], and -1/(Kv^2 - m^2 + i m Gamma)
+                off += 6
         self.ub = off
         off += 16
         self.v = off
         off += 16
         self.eps = {}
-        for g in range(2, n):
+        for g in range(n):
             self.eps[g] = off
             off += 8
         self.size = off
@@ -282,6 +287,17 @@ def emit_table_fill(n, lay):
     w("            k[4] = -re * inv;")
     w("            k[5] = mw * inv;")
     w("        }")
+    kv_offsets = ", ".join(str(lay.Kv.get(m, -1)) for m in range(1, 1 << n))
+    w(f"        const int kv_off[{nsub}] = {{{kv_offsets}}};")
+    w("        if (kv_off[m - 1] >= 0) {")
+    w("            const double K0 = -mom[4] - P0, K1 = -mom[5] - P1, K2 = -mom[6] - P2, K3 = -mom[7] - P3;")
+    w("            const double re = K0 * K0 - K1 * K1 - K2 * K2 - K3 * K3 - m2;")
+    w("            const double inv = 1.0 / (re * re + mw * mw);")
+    w("            double* k = tab + kv_off[m - 1];")
+    w("            k[0] = K0; k[1] = K1; k[2] = K2; k[3] = K3;")
+    w("            k[4] = -re * inv;")
+    w("            k[5] = mw * inv;")
+    w("        }")
     w("    }")
     w(f"    if (lane >= {nsub + 1} && lane < {nsub + 5}) {{")
     w(f"        const int t = lane - {nsub + 1};     // 0, 1: ubar spins; 2, 3: v spins")
@@ -293,13 +309,19 @@ def emit_table_fill(n, lay):
     w(f"        double* o = tab + (t < 2 ? {lay.ub} + 8 * t : {lay.v} + 8 * (t - 2));")
     w("        for (int i = 0; i < 4; ++i) { o[2 * i] = sp[i].x; o[2 * i + 1] = sp[i].y; }")
     w("    }")
+    # incoming gluons along the beams: (0, 1, 0, 0) and (0, 0, 1, 0)
+    w(f"    if (lane == 0) {{")
+    w(f"        double* o = tab + {lay.eps[0]};")
+    w("        for (int i = 0; i < 16; ++i) o[i] = 0.0;")
+    w("        o[1] = 1.0; o[6] = 1.0; o[9] = 1.0; o[14] = 1.0;")
+    w("    }")
     if n > 2:
         w(f"    if (lane >= {nsub + 5} && lane < {nsub + 5 + 2 * (n - 2)}) {{")
         w(f"        const int t = lane - {nsub + 5};")
         w("        const int g = 2 + t / 2, h = t & 1;")
         w("        double e[4];")
         w("        linear_pol<double>(mom + 8 + 4 * (g - 2), h, e);")
-        w(f"        double* o = tab + {lay.eps[2]} + 8 * (g - 2) + 4 * h;")
+        w(f"        double* o = tab + {lay.eps[0]} + 8 * g + 4 * h;")
         w("        for (int mu = 0; mu < 4; ++mu) o[mu] = e[mu];")
         w("    }")
     return "\n".join(L)
@@ -364,6 +386,11 @@ def generate(n):
     _LAST_COUNT = {"per_helicity": e.hel, "momentum_only": e.mom, "n_hel": 1 << (n + 2),
                    "n_orderings": nperm, "table_doubles": lay.size}
     kdecl = ", ".join(str(v) for row in K for v in row)
+    coop_text = generate_coop(n) if n >= 3 else ""
+    structs = """
+struct GPair { int b1, b2; signed char s1, s2, m1, m2; short p1, p2; };
+struct GTrip { int b1, b2, b3; signed char s1, s2, s3, m1, m2, m3; };
+""" if n == 2 else ""
     return f"""// Generated by gen_amplitudes.py for g g -> t tbar + {n - 2} gluon(s): {nperm} colour orderings,
 // {1 << (n + 2)} helicity configurations.  Do not edit.
 // Arithmetic per helicity configuration: {e.hel} flops; per event (table): {e.mom} flops.
@@ -395,16 +422,389 @@ __device__ __forceinline__ double colour_summed_me2_ng{n}(const double* __restri
 {body}
     return (double)me / COLOUR_DEN_NG{n};
 }}
+{structs}{coop_text}"""
+
+
+
+# ----------------------------------------------------------------------------
+# Cooperative evaluation (n >= 3): helicity-recycled objects built once per
+# event in LDS by the wave's lanes, then one lane per helicity configuration.
+# ----------------------------------------------------------------------------
+def canon(seq):
+    """Canonical representative of a gluon sequence under reflection and the
+    sign j(seq) = sign * j(canon)."""
+    seq = tuple(seq)
+    if len(seq) == 1 or seq[0] < seq[-1]:
+        return seq, 1
+    return tuple(reversed(seq)), (1 if (len(seq) + 1) % 2 == 0 else -1)
+
+
+class CoopLayout:
+    """Object store of one event, in units of T:
+       gluon currents j(s; hm) for every canonical ordered sequence s of
+       length 1 .. n and helicity pattern hm of its gluons (sorted labels),
+       4 T each; Ubar(a; s_t, h_a) and V(d; s_tbar, h_d), V(cd; s_tbar, h_c,
+       h_d), 8 T each (complex 4-spinors, re/im interleaved)."""
+
+    def __init__(self, n):
+        self.n = n
+        self.levels = {}
+        self.base = {}
+        off = 0
+        for L in range(1, n + 1):
+            seqs = sorted(sq for sq in itertools.permutations(range(n), L) if canon(sq)[0] == sq)
+            self.levels[L] = seqs
+            for sq in seqs:
+                self.base[sq] = off
+                off += 1 << L
+        self.n_gj = off
+        self.gj = 0
+        self.u1 = 4 * off
+        self.v1 = self.u1 + 8 * 4 * n
+        self.pairs = sorted(itertools.permutations(range(n), 2)) if n >= 4 else []
+        self.v2 = self.v1 + 8 * 4 * n
+        self.size = self.v2 + 8 * 8 * len(self.pairs)
+
+    def obj(self, seq):
+        c, sg = canon(seq)
+        return self.base[c], sg, c
+
+
+def posmask(part, whole):
+    srt = sorted(whole)
+    m = 0
+    for g in part:
+        m |= 1 << srt.index(g)
+    return m
+
+
+def emit_coop(n, lay, co, K, perms):
+    L_ = []
+    w = L_.append
+    flops_stage = 0
+    # ---- constant tables of the gluon-current levels ----
+    tables = []
+    for L in range(2, n + 1):
+        seqs = co.levels[L]
+        pr, tr, ni, bs = [], [], [], []
+        for sq in seqs:
+            for k in range(1, L):
+                p1, p2 = sq[:k], sq[k:]
+                b1, s1, _ = co.obj(p1)
+                b2, s2, _ = co.obj(p2)
+                pr.append(f"{{{b1}, {b2}, {s1}, {s2}, {posmask(p1, sq)}, {posmask(p2, sq)}, "
+                          f"{lay.P[mask(p1)]}, {lay.P[mask(p2)]}}}")
+            for a in range(1, L):
+                for b in range(a + 1, L):
+                    q1, q2, q3 = sq[:a], sq[a:b], sq[b:]
+                    o1, o2, o3 = co.obj(q1), co.obj(q2), co.obj(q3)
+                    tr.append(f"{{{o1[0]}, {o2[0]}, {o3[0]}, {o1[1]}, {o2[1]}, {o3[1]}, "
+                              f"{posmask(q1, sq)}, {posmask(q2, sq)}, {posmask(q3, sq)}}}")
+            ni.append(str(lay.ninv[mask(sq)]))
+            bs.append(str(co.base[sq]))
+        npair, ntrip = L - 1, (L - 1) * (L - 2) // 2
+        tables.append(f"static constexpr GPair GJ{n}_L{L}_PAIR[{len(pr)}] = {{{', '.join(pr)}}};")
+        if tr:
+            tables.append(f"static constexpr GTrip GJ{n}_L{L}_TRIP[{len(tr)}] = {{{', '.join(tr)}}};")
+        tables.append(f"static constexpr short GJ{n}_L{L}_NINV[{len(ni)}] = {{{', '.join(ni)}}};")
+        tables.append(f"static constexpr int GJ{n}_L{L}_BASE[{len(bs)}] = {{{', '.join(bs)}}};")
+    pairs = co.pairs
+    if pairs:
+        pc, pjb, pjs, pjm, pkv = [], [], [], [], []
+        for (c, d) in pairs:
+            b, sg, cs = co.obj((c, d))
+            pc.append(f"{c}, {d}")
+            pjb.append(str(b))
+            pjs.append(str(sg))
+            # helicity pattern of j(cd) over sorted {c, d}: bit order by label
+            pjm.append("1" if c < d else "0")
+            pkv.append(str(lay.Kv[(1 << c) | (1 << d)]))
+        tables.append(f"static constexpr signed char V2_{n}_CD[{2 * len(pairs)}] = {{{', '.join(pc)}}};")
+        tables.append(f"static constexpr int V2_{n}_JB[{len(pairs)}] = {{{', '.join(pjb)}}};")
+        tables.append(f"static constexpr signed char V2_{n}_JS[{len(pairs)}] = {{{', '.join(pjs)}}};")
+        tables.append(f"static constexpr signed char V2_{n}_CLOW[{len(pairs)}] = {{{', '.join(pjm)}}};")
+        tables.append(f"static constexpr short V2_{n}_KV[{len(pairs)}] = {{{', '.join(pkv)}}};")
+    kt_off = ", ".join(str(lay.K[1 << g]) for g in range(n))
+    kv_off = ", ".join(str(lay.Kv[1 << g]) for g in range(n))
+    tables.append(f"static constexpr short KT1_{n}[{n}] = {{{kt_off}}};")
+    tables.append(f"static constexpr short KV1_{n}[{n}] = {{{kv_off}}};")
+
+    # ---- stages ----
+    w("    const double mtd = mt;")
+    w("    // level 1: polarisation vectors j(g; h) = eps_g(h)")
+    w(f"    for (int it = lane; it < {2 * n}; it += nl) {{")
+    w(f"        const double* q = tab + {lay.eps[0]} + 4 * it;")
+    w(f"        T* o = obj + {co.gj} + 4 * it;")
+    w("        for (int mu = 0; mu < 4; ++mu) o[mu] = (T)q[mu];")
+    w("    }")
+    w("    wave_sync();")
+    for L in range(2, n + 1):
+        nseq = len(co.levels[L])
+        npair, ntrip = L - 1, (L - 1) * (L - 2) // 2
+        flops_stage += nseq * (1 << L) * (npair * 51 + ntrip * 49 + 4)
+        w(f"    // level {L}: {nseq} canonical sequences x {1 << L} helicity patterns")
+        w(f"    for (int it = lane; it < {nseq << L}; it += nl) {{")
+        w(f"        const int si = it >> {L}, hm = it & {(1 << L) - 1};")
+        w("        T a0 = 0, a1 = 0, a2 = 0, a3 = 0;")
+        w("#pragma unroll")
+        w(f"        for (int k = 0; k < {npair}; ++k) {{")
+        w(f"            const GPair sp = GJ{n}_L{L}_PAIR[si * {npair} + k];")
+        w(f"            const T* q1 = obj + {co.gj} + 4 * (sp.b1 + pext4(hm, sp.m1));")
+        w(f"            const T* q2 = obj + {co.gj} + 4 * (sp.b2 + pext4(hm, sp.m2));")
+        w("            const T g1 = (T)sp.s1, g2 = (T)sp.s2;")
+        w("            const T j1[4] = {g1 * q1[0], g1 * q1[1], g1 * q1[2], g1 * q1[3]};")
+        w("            const T j2[4] = {g2 * q2[0], g2 * q2[1], g2 * q2[2], g2 * q2[3]};")
+        w("            const double* p1 = tab + sp.p1; const double* p2 = tab + sp.p2;")
+        w("            const T P1[4] = {(T)p1[0], (T)p1[1], (T)p1[2], (T)p1[3]};")
+        w("            const T P2[4] = {(T)p2[0], (T)p2[1], (T)p2[2], (T)p2[3]};")
+        w("            const T c1 = (T)2 * (P1[0] * j2[0] - P1[1] * j2[1] - P1[2] * j2[2] - P1[3] * j2[3]);")
+        w("            const T c2 = (T)2 * (P2[0] * j1[0] - P2[1] * j1[1] - P2[2] * j1[2] - P2[3] * j1[3]);")
+        w("            const T c12 = j1[0] * j2[0] - j1[1] * j2[1] - j1[2] * j2[2] - j1[3] * j2[3];")
+        for mu in range(4):
+            w(f"            a{mu} += j1[{mu}] * c1 - j2[{mu}] * c2 + c12 * (P2[{mu}] - P1[{mu}]);")
+        w("        }")
+        if ntrip:
+            w("#pragma unroll")
+            w(f"        for (int k = 0; k < {ntrip}; ++k) {{")
+            w(f"            const GTrip tp = GJ{n}_L{L}_TRIP[si * {ntrip} + k];")
+            w(f"            const T* q1 = obj + {co.gj} + 4 * (tp.b1 + pext4(hm, tp.m1));")
+            w(f"            const T* q2 = obj + {co.gj} + 4 * (tp.b2 + pext4(hm, tp.m2));")
+            w(f"            const T* q3 = obj + {co.gj} + 4 * (tp.b3 + pext4(hm, tp.m3));")
+            w("            const T g1 = (T)tp.s1, g2 = (T)tp.s2, g3 = (T)tp.s3;")
+            w("            const T j1[4] = {g1 * q1[0], g1 * q1[1], g1 * q1[2], g1 * q1[3]};")
+            w("            const T j2[4] = {g2 * q2[0], g2 * q2[1], g2 * q2[2], g2 * q2[3]};")
+            w("            const T j3[4] = {g3 * q3[0], g3 * q3[1], g3 * q3[2], g3 * q3[3]};")
+            w("            const T d23 = j2[0] * j3[0] - j2[1] * j3[1] - j2[2] * j3[2] - j2[3] * j3[3];")
+            w("            const T d13 = j1[0] * j3[0] - j1[1] * j3[1] - j1[2] * j3[2] - j1[3] * j3[3];")
+            w("            const T d12 = j1[0] * j2[0] - j1[1] * j2[1] - j1[2] * j2[2] - j1[3] * j2[3];")
+            for mu in range(4):
+                w(f"            a{mu} += j1[{mu}] * d23 - (T)2 * j2[{mu}] * d13 + j3[{mu}] * d12;")
+            w("        }")
+        w(f"        const T f = (T)tab[GJ{n}_L{L}_NINV[si]];")
+        w(f"        T* o = obj + {co.gj} + 4 * (GJ{n}_L{L}_BASE[si] + hm);")
+        w("        o[0] = a0 * f; o[1] = a1 * f; o[2] = a2 * f; o[3] = a3 * f;")
+        w("    }")
+        w("    wave_sync();")
+    # top line from the top side: Ubar(a; s_t, h_a)
+    flops_stage += 4 * n * (50 + 80) + 4 * n * (42 + 80)
+    w("    // Ubar(a; s_t, h) = -[ubar gamma.eps_a] (K-slash + m) / D,   V(d; s_tbar, h) = -(K'-slash + m) [gamma.eps_d v] / D'")
+    w(f"    for (int it = lane; it < {8 * n}; it += nl) {{")
+    w(f"        const int side = it >= {4 * n}, r = it - side * {4 * n};")
+    w("        const int g = r >> 2, sp = (r >> 1) & 1, h = r & 1;")
+    w(f"        const T* e = obj + {co.gj} + 4 * (2 * g + h);")
+    w(f"        const double* q = tab + (side ? {lay.v} : {lay.ub}) + 8 * sp;")
+    w("        cplx<T> x[4];")
+    w("        for (int i = 0; i < 4; ++i) x[i] = cplx<T>((T)q[2 * i], (T)q[2 * i + 1]);")
+    w(f"        const double* k = tab + (side ? KV1_{n}[g] : KT1_{n}[g]);")
+    w("        const T Kc[4] = {(T)k[0], (T)k[1], (T)k[2], (T)k[3]};")
+    w("        cplx<T> out[4];")
+    w("        if (!side) {")
+    w("            cplx<T> s0 = cplx<T>(0, 0), s1 = cplx<T>(0, 0), s2 = cplx<T>(0, 0), s3 = cplx<T>(0, 0);")
+    w("            rowslash_acc(x, e, s0, s1, s2, s3);")
+    w("            rowprop(s0, s1, s2, s3, Kc, (T)mtd, (T)k[4], (T)k[5], out);")
+    w("        } else {")
+    w("            cplx<T> W[4] = {cplx<T>(0, 0), cplx<T>(0, 0), cplx<T>(0, 0), cplx<T>(0, 0)};")
+    w("            slashcol_acc(e, x, W);")
+    w("            colprop(W, Kc, (T)mtd, (T)k[4], (T)k[5], out);")
+    w("        }")
+    w(f"        T* o = obj + (side ? {co.v1} : {co.u1}) + 8 * r;")
+    w("        for (int i = 0; i < 4; ++i) { o[2 * i] = out[i].x; o[2 * i + 1] = out[i].y; }")
+    w("    }")
+    w("    wave_sync();")
+    if pairs:
+        flops_stage += 8 * len(pairs) * (42 + 42 + 80)
+        w("    // V(cd; s_tbar, h_c, h_d) = -(K'-slash + m) [gamma.eps_c V(d) + gamma.j(cd) v] / D'")
+        w(f"    for (int it = lane; it < {8 * len(pairs)}; it += nl) {{")
+        w("        const int pi = it >> 3, sb = (it >> 2) & 1, hc = (it >> 1) & 1, hd = it & 1;")
+        w(f"        const int c = V2_{n}_CD[2 * pi], d = V2_{n}_CD[2 * pi + 1];")
+        w(f"        const T* ec = obj + {co.gj} + 4 * (2 * c + hc);")
+        w(f"        const T* vd = obj + {co.v1} + 8 * (4 * d + 2 * sb + hd);")
+        w("        cplx<T> y[4];")
+        w("        for (int i = 0; i < 4; ++i) y[i] = cplx<T>(vd[2 * i], vd[2 * i + 1]);")
+        w("        cplx<T> W[4] = {cplx<T>(0, 0), cplx<T>(0, 0), cplx<T>(0, 0), cplx<T>(0, 0)};")
+        w("        slashcol_acc(ec, y, W);")
+        w(f"        const int hm = V2_{n}_CLOW[pi] ? (hc | (hd << 1)) : (hd | (hc << 1));")
+        w(f"        const T* q = obj + {co.gj} + 4 * (V2_{n}_JB[pi] + hm);")
+        w(f"        const T gs = (T)V2_{n}_JS[pi];")
+        w("        const T jcd[4] = {gs * q[0], gs * q[1], gs * q[2], gs * q[3]};")
+        w(f"        const double* qv = tab + {lay.v} + 8 * sb;")
+        w("        cplx<T> x[4];")
+        w("        for (int i = 0; i < 4; ++i) x[i] = cplx<T>((T)qv[2 * i], (T)qv[2 * i + 1]);")
+        w("        slashcol_acc(jcd, x, W);")
+        w(f"        const double* k = tab + V2_{n}_KV[pi];")
+        w("        const T Kc[4] = {(T)k[0], (T)k[1], (T)k[2], (T)k[3]};")
+        w("        cplx<T> out[4];")
+        w("        colprop(W, Kc, (T)mtd, (T)k[4], (T)k[5], out);")
+        w(f"        T* o = obj + {co.v2} + 8 * it;")
+        w("        for (int i = 0; i < 4; ++i) { o[2 * i] = out[i].x; o[2 * i + 1] = out[i].y; }")
+        w("    }")
+        w("    wave_sync();")
+    stages = "\n".join(L_)
+
+    # ---- amplitude phase: one lane per helicity configuration ----
+    # A(sigma) = sum over the blocks beta of sigma that contain its second
+    # gluon of  Xbar gamma.j(beta) Y,  Xbar in {ubar, Ubar(sigma_1)},
+    # Y in {v, V(last), V(last two)}.  Each bilinear d^mu = Xbar gamma^mu Y is
+    # formed once, contracted with the gluon currents it meets and scattered
+    # (with the reflection signs) into the amplitude accumulators; only the
+    # accumulators stay live.
+    A = []
+    a = A.append
+    a("    const int sT = hel & 1, sB = (hel >> 1) & 1, hg = hel >> 2;")
+    a("    cplx<T> ub[4], v[4];")
+    a(f"    {{ const double* q = tab + {lay.ub} + 8 * sT; for (int i = 0; i < 4; ++i) ub[i] = cplx<T>((T)q[2 * i], (T)q[2 * i + 1]); }}")
+    a(f"    {{ const double* q = tab + {lay.v} + 8 * sB; for (int i = 0; i < 4; ++i) v[i] = cplx<T>((T)q[2 * i], (T)q[2 * i + 1]); }}")
+    hel_flops = 0
+    lex = {sq: i for i, sq in enumerate(perms)}
+    nperm_ = len(perms)
+    a(f"    T Ar[{nperm_}], Ai[{nperm_}];")
+    a(f"    for (int i = 0; i < {nperm_}; ++i) {{ Ar[i] = 0; Ai[i] = 0; }}")
+
+    def hexpr(block):
+        srt = sorted(block)
+        return " | ".join(f"(((hg >> {g}) & 1) << {i})" for i, g in enumerate(srt))
+
+    def gj_ptr(block):
+        b, sg, cs = co.obj(block)
+        return f"(ob + {co.gj} + 4 * ({b} + ({hexpr(cs)})))", sg
+
+    def load_row(X, nm):
+        if not X:
+            return "ub"
+        a(f"        cplx<T> {nm}[4];")
+        a(f"        {{ const T* q = ob + {co.u1} + 8 * (4 * {X[0]} + 2 * sT + ((hg >> {X[0]}) & 1)); "
+          f"for (int i = 0; i < 4; ++i) {nm}[i] = cplx<T>(q[2 * i], q[2 * i + 1]); }}")
+        return nm
+
+    def load_col(Y, nm):
+        if not Y:
+            return "v"
+        if len(Y) == 1:
+            d = Y[0]
+            idx = f"{co.v1} + 8 * (4 * {d} + 2 * sB + ((hg >> {d}) & 1))"
+        else:
+            c, d = Y
+            pi = co.pairs.index((c, d))
+            idx = f"{co.v2} + 8 * ({8 * pi} + 4 * sB + 2 * ((hg >> {c}) & 1) + ((hg >> {d}) & 1))"
+        a(f"        cplx<T> {nm}[4];")
+        a(f"        {{ const T* q = ob + {idx}; for (int i = 0; i < 4; ++i) {nm}[i] = cplx<T>(q[2 * i], q[2 * i + 1]); }}")
+        return nm
+
+    # group the terms by bilinear: key (X, Y) -> list of (beta, ordering)
+    groups = {}
+    for sg in perms:
+        for i in (0, 1):
+            for j in range(2, n + 1):
+                X, beta, Y = sg[:i], sg[i:j], sg[j:]
+                groups.setdefault((X, Y), []).append((beta, sg))
+    # Y-major order so that a loaded V is used by all its bilinears in a row
+    keys = sorted(groups, key=lambda k: (len(k[1]), k[1], k[0]))
+    for (X, Y) in keys:
+        a("    {")
+        # an opaque zero produced here keeps this group's LDS reads from
+        # being hoisted above it (every hoisted read would hold registers)
+        a("        int z = 0;")
+        a('        asm volatile("" : "+v"(z));')
+        a("        const T* ob = obj + z;")
+        r = load_row(X, "xr")
+        c = load_col(Y, "yc")
+        a("        cplx<T> d[4];")
+        a(f"        bilinear({r}, {c}, d);")
+        hel_flops += 74
+        # distinct currents (up to reflection) met by this bilinear
+        byc = {}
+        for (beta, sg) in groups[(X, Y)]:
+            b, sgn, cs = co.obj(beta)
+            byc.setdefault(cs, []).append((sgn, sg))
+        for cs, uses in byc.items():
+            ptr, _ = gj_ptr(cs)
+            a("        {")
+            a("            T sr = 0, si = 0;")
+            a(f"            cdotj<1>(d, {ptr}, sr, si);")
+            hel_flops += 16
+            for (sgn, sg) in uses:
+                k = lex[sg]
+                op = "+=" if sgn > 0 else "-="
+                a(f"            Ar[{k}] {op} sr; Ai[{k}] {op} si;")
+                hel_flops += 2
+            a("        }")
+        a("    }")
+    # colour sum: sum_s K_ss |A_s|^2 + 2 sum_{t<s} K_st Re(conj(A_s) A_t)
+    a("    T me = 0;")
+    for sidx in range(nperm_):
+        a("    {")
+        a(f"        T tr = {K[sidx][sidx]} * Ar[{sidx}], ti = {K[sidx][sidx]} * Ai[{sidx}];")
+        hel_flops += 4
+        for t in range(sidx):
+            if K[sidx][t]:
+                a(f"        tr += (T)({2 * K[sidx][t]}) * Ar[{t}]; ti += (T)({2 * K[sidx][t]}) * Ai[{t}];")
+                hel_flops += 4
+        a(f"        me += Ar[{sidx}] * tr + Ai[{sidx}] * ti;")
+        hel_flops += 4
+        a("    }")
+    amp = "\n".join(A)
+    return "\n".join(tables), stages, amp, flops_stage, hel_flops
+
+
+def generate_coop(n):
+    perms, K, den = colour_matrix(n)
+    lay = Layout(n)
+    co = CoopLayout(n)
+    tables, stages, amp, fst, fhel = emit_coop(n, lay, co, K, perms)
+    global _COOP_COUNT
+    _COOP_COUNT = {"stages": fst, "per_helicity": fhel, "object_store": co.size}
+    return f"""
+// ---- cooperative evaluation (helicity-recycled objects in LDS) ----
+// Object store: {co.size} T per event.  Stage flops per event: {fst}; per
+// helicity lane: {fhel}.
+static constexpr int COOP_OBJ_NG{n} = {co.size};
+static constexpr int COOP_FLOPS_STAGES_NG{n} = {fst};
+static constexpr int COOP_FLOPS_HEL_NG{n} = {fhel};
+{tables}
+
+// Builds the event's object store `obj` from its table: lanes 0 .. nl-1 of
+// the wave serve this event; every level ends with a wave synchronisation.
+template <typename T>
+__device__ __forceinline__ void coop_stages_ng{n}(const double* __restrict__ tab, T* __restrict__ obj, double mt,
+                                                 int lane, int nl)
+{{
+{stages}
+}}
+
+// Colour-summed |M|^2 (g_s = 1) of helicity configuration `hel` from the
+// object store: meet-in-the-middle at the vertex that carries the second
+// gluon of each colour ordering, A = sum Xbar gamma.j(block) Y.
+template <typename T>
+__device__ __forceinline__ double coop_me2_ng{n}(const double* __restrict__ tab, const T* __restrict__ obj, int hel)
+{{
+{amp}
+    return (double)me / COLOUR_DEN_NG{n};
+}}
 """
 
 
 _LAST_COUNT = None
+_COOP_COUNT = None
 
 
 def flop_count(n):
-    """Algorithmic flops of the generated |M|^2 code for n gluons."""
+    """Algorithmic flops per event of the |M|^2 code the kernels run for n
+    gluons: the momentum table, plus either 2^(n+2) independent helicity
+    evaluations (n = 2) or the shared object stages and the per-helicity
+    meet-in-the-middle contractions (n >= 3)."""
     generate(n)
-    return dict(_LAST_COUNT)
+    c = dict(_LAST_COUNT)
+    if n >= 3:
+        c["algorithm"] = "helicity-recycled objects"
+        c["stages"] = _COOP_COUNT["stages"]
+        c["per_helicity"] = _COOP_COUNT["per_helicity"]
+        c["object_store"] = _COOP_COUNT["object_store"]
+        c["per_event"] = c["momentum_only"] + c["stages"] + c["n_hel"] * c["per_helicity"]
+    else:
+        c["algorithm"] = "independent helicities"
+        c["stages"] = 0
+        c["per_event"] = c["momentum_only"] + c["n_hel"] * c["per_helicity"]
+    return c
 
 
 def main():

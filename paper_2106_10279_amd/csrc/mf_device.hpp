@@ -78,6 +78,71 @@ __device__ __forceinline__ void rowprop(cplx<T> s0, cplx<T> s1, cplx<T> s2, cplx
     out[3] = cmul(t3, f);
 }
 
+// out = (K-slash + m) w x (fr + i fi) for a column spinor w:
+// ((m wL + (K.sigma) wR), ((K.sigmabar) wL + m wR)).
+template <typename T>
+__device__ __forceinline__ void colprop(const cplx<T>* w, const T* K, T m, T fr, T fi, cplx<T>* out)
+{
+    const T kp = K[0] + K[3], km = K[0] - K[3];
+    cplx<T> t0, t1, t2, t3;
+    // t0 = m w0 + (K0 - K3) w2 + (-K1 + i K2) w3
+    t0.x = m * w[0].x + km * w[2].x - K[1] * w[3].x - K[2] * w[3].y;
+    t0.y = m * w[0].y + km * w[2].y - K[1] * w[3].y + K[2] * w[3].x;
+    // t1 = m w1 + (-K1 - i K2) w2 + (K0 + K3) w3
+    t1.x = m * w[1].x - K[1] * w[2].x + K[2] * w[2].y + kp * w[3].x;
+    t1.y = m * w[1].y - K[1] * w[2].y - K[2] * w[2].x + kp * w[3].y;
+    // t2 = (K0 + K3) w0 + (K1 - i K2) w1 + m w2
+    t2.x = kp * w[0].x + K[1] * w[1].x + K[2] * w[1].y + m * w[2].x;
+    t2.y = kp * w[0].y + K[1] * w[1].y - K[2] * w[1].x + m * w[2].y;
+    // t3 = (K1 + i K2) w0 + (K0 - K3) w1 + m w3
+    t3.x = K[1] * w[0].x - K[2] * w[0].y + km * w[1].x + m * w[3].x;
+    t3.y = K[1] * w[0].y + K[2] * w[0].x + km * w[1].y + m * w[3].y;
+    const cplx<T> f(fr, fi);
+    out[0] = cmul(t0, f);
+    out[1] = cmul(t1, f);
+    out[2] = cmul(t2, f);
+    out[3] = cmul(t3, f);
+}
+
+// acc += gamma.(SGN e) w for a real 4-vector e and a complex column w.
+template <int SGN = 1, typename T>
+__device__ __forceinline__ void slashcol_acc(const T* ein, const cplx<T>* v, cplx<T>* W)
+{
+    const T e[4] = {(T)SGN * ein[0], (T)SGN * ein[1], (T)SGN * ein[2], (T)SGN * ein[3]};
+    const T ep = e[0] + e[3], em = e[0] - e[3];
+    W[0].x += em * v[2].x - e[1] * v[3].x - e[2] * v[3].y;
+    W[0].y += em * v[2].y - e[1] * v[3].y + e[2] * v[3].x;
+    W[1].x += -e[1] * v[2].x + e[2] * v[2].y + ep * v[3].x;
+    W[1].y += -e[1] * v[2].y - e[2] * v[2].x + ep * v[3].y;
+    W[2].x += ep * v[0].x + e[1] * v[1].x + e[2] * v[1].y;
+    W[2].y += ep * v[0].y + e[1] * v[1].y - e[2] * v[1].x;
+    W[3].x += e[1] * v[0].x - e[2] * v[0].y + em * v[1].x;
+    W[3].y += e[1] * v[0].y + e[2] * v[0].x + em * v[1].y;
+}
+
+// Orders the LDS traffic of the lanes of one wavefront (no hardware barrier:
+// a wavefront executes in lockstep; the fences keep the compiler and the
+// memory model from reordering the accesses across this point).
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Bits of x at the set positions of m, packed in order (m < 16).
+__device__ __forceinline__ int pext4(int x, int m)
+{
+    int r = 0, k = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        if ((m >> i) & 1) {
+            r |= ((x >> i) & 1) << k;
+            ++k;
+        }
+    return r;
+}
+
 // c^mu = a gamma^mu v = aL sigma^mu vR + aR sigmabar^mu vL.
 template <typename T>
 __device__ __forceinline__ void bilinear(const cplx<T>* a, const cplx<T>* v, cplx<T>* c)

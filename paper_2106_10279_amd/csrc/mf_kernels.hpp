@@ -59,13 +59,6 @@ struct EventParams {
     int n_waves;
 };
 
-__device__ __forceinline__ void wave_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 // ---------------------------------------------------------------------------
 // VEGAS map.  The bin index and the position in the bin come from the exact
 // integer product k n_bins; the map itself is evaluated without contraction
@@ -328,7 +321,35 @@ struct Layout {
     static constexpr int kHel = 1 << (NG + 2);
     static constexpr int kEventsPerPass = kWave / kHel;   // 4, 2, 1
     static constexpr int kTable = NG == 2 ? TABLE_NG2 : (NG == 3 ? TABLE_NG3 : TABLE_NG4);
+    // helicity-recycled object store per event (units of the amplitude type)
+    static constexpr bool kCoop = NG >= 3;
+    static constexpr int kObj = NG == 2 ? 1 : (NG == 3 ? COOP_OBJ_NG3 : COOP_OBJ_NG4);
 };
+
+// Colour-summed |M|^2 of helicity `h` for the event whose table is `tab`:
+// lanes of the event (h = 0 .. 2^(NG+2) - 1) build the object store first
+// (n_g >= 3).  `any_live` must be uniform over the wave.
+template <int NG, typename T>
+__device__ __forceinline__ double event_me2(const double* tab, T* obj, int h, double mt, bool live, bool any_live)
+{
+    using L = Layout<NG>;
+    if constexpr (L::kCoop) {
+        if (any_live) {
+            if constexpr (NG == 3)
+                coop_stages_ng3<T>(tab, obj, mt, h, L::kHel);
+            else
+                coop_stages_ng4<T>(tab, obj, mt, h, L::kHel);
+        }
+        if (!live)
+            return 0.0;
+        if constexpr (NG == 3)
+            return coop_me2_ng3<T>(tab, obj, h);
+        else
+            return coop_me2_ng4<T>(tab, obj, h);
+    } else {
+        return live ? colour_summed_me2<NG, T>(tab, h, mt) : 0.0;
+    }
+}
 
 template <int NG, typename T>
 __global__ void __launch_bounds__(kBlock) event_kernel(EventParams P)
@@ -344,6 +365,7 @@ __global__ void __launch_bounds__(kBlock) event_kernel(EventParams P)
     __shared__ double s_rows[4 * kMaxPdfX];
     __shared__ double s_lq[4];
     __shared__ double s_tab[kWavesPerBlock][L::kEventsPerPass][L::kTable];
+    __shared__ T s_obj[kWavesPerBlock][L::kEventsPerPass][L::kObj];
     extern __shared__ double s_hist[];     // [kWavesPerBlock][D][n_bins]
 
     const int tid = threadIdx.x;
@@ -474,16 +496,16 @@ __global__ void __launch_bounds__(kBlock) event_kernel(EventParams P)
             const int h = lane % L::kHel;
             const int sub = lane / L::kHel;
             double* tab = s_tab[wv][sub];
+            T* obj = s_obj[wv][sub];
             for (int g = 0; g < kWave / L::kEventsPerPass; ++g) {
                 const int e = g * L::kEventsPerPass + sub;
                 const double* m_e = s_mom[wv][e];
                 const bool live = s_pref[wv][e] != 0.0;
+                const bool any_live = __any(live);
                 if (live)
                     fill_table<NG>(m_e, m_e[L::kMom - 1], P.m_top, P.mw, tab, h);
                 wave_sync();
-                double v = 0.0;
-                if (live)
-                    v = colour_summed_me2<NG, T>(tab, h, P.m_top);
+                double v = event_me2<NG, T>(tab, obj, h, P.m_top, live, any_live);
                 v = group_sum(v, L::kHel);
                 if (h == 0)
                     s_me[wv][e] = v;
@@ -687,18 +709,19 @@ __global__ void __launch_bounds__(kBlock) me_kernel(const double* __restrict__ m
 {
     using L = Layout<NG>;
     __shared__ double s_tab[kWavesPerBlock][L::kEventsPerPass][L::kTable];
+    __shared__ T s_obj[kWavesPerBlock][L::kEventsPerPass][L::kObj];
     const int lane = threadIdx.x % kWave;
     const int wv = threadIdx.x / kWave;
     const uint64_t wave = (uint64_t)blockIdx.x * kWavesPerBlock + wv;
     const uint64_t e = wave * L::kEventsPerPass + lane / L::kHel;
     const int h = lane % L::kHel;
     double* tab = s_tab[wv][lane / L::kHel];
-    if (e < n)
+    T* obj = s_obj[wv][lane / L::kHel];
+    const bool live = e < n;
+    if (live)
         fill_table<NG>(mom + e * (L::kMom - 1), eb[e], mt, mw, tab, h);
     wave_sync();
-    double v = 0.0;
-    if (e < n)
-        v = colour_summed_me2<NG, T>(tab, h, mt);
+    double v = event_me2<NG, T>(tab, obj, h, mt, live, __any(live));
     v = group_sum(v, L::kHel);
     if (h == 0 && e < n)
         out[e] = v;
