@@ -650,6 +650,9 @@ def emit_coop(n, lay, co, K, perms):
     # accumulators stay live.
     A = []
     a = A.append
+    # an opaque copy of the helicity index: offsets derived from it are then
+    # recomputed per event instead of being hoisted out of the event loop
+    a('    asm volatile("" : "+v"(hel));')
     a("    const int sT = hel & 1, sB = (hel >> 1) & 1, hg = hel >> 2;")
     a("    cplx<T> ub[4], v[4];")
     a(f"    {{ const double* q = tab + {lay.ub} + 8 * sT; for (int i = 0; i < 4; ++i) ub[i] = cplx<T>((T)q[2 * i], (T)q[2 * i + 1]); }}")
@@ -716,6 +719,7 @@ def emit_coop(n, lay, co, K, perms):
         for (beta, sg) in groups[(X, Y)]:
             b, sgn, cs = co.obj(beta)
             byc.setdefault(cs, []).append((sgn, sg))
+        touched = []
         for cs, uses in byc.items():
             ptr, _ = gj_ptr(cs)
             a("        {")
@@ -727,7 +731,16 @@ def emit_coop(n, lay, co, K, perms):
                 op = "+=" if sgn > 0 else "-="
                 a(f"            Ar[{k}] {op} sr; Ai[{k}] {op} si;")
                 hel_flops += 2
+                if k not in touched:
+                    touched.append(k)
             a("        }")
+        # the accumulators this group updated pass through an opaque point
+        # before the next group starts, so that the group's arithmetic is not
+        # deferred to the colour sum with its operands held in registers
+        touched.sort()
+        for c0 in range(0, len(touched), 4):
+            ops = ", ".join(f'"+v"(Ar[{k}]), "+v"(Ai[{k}])' for k in touched[c0:c0 + 4])
+            a(f'        asm volatile("" : {ops});')
         a("    }")
     # colour sum: sum_s K_ss |A_s|^2 + 2 sum_{t<s} K_st Re(conj(A_s) A_t)
     a("    T me = 0;")

@@ -493,11 +493,15 @@ __global__ void __launch_bounds__(kBlock) event_kernel(EventParams P)
         // The lanes of each event first fill its table of momentum-only
         // quantities, then every lane evaluates one helicity configuration.
         {
-            const int h = lane % L::kHel;
+            const int h0 = lane % L::kHel;
             const int sub = lane / L::kHel;
             double* tab = s_tab[wv][sub];
             T* obj = s_obj[wv][sub];
             for (int g = 0; g < kWave / L::kEventsPerPass; ++g) {
+                // opaque per iteration, so that lane-dependent addresses of the
+                // table and object store are not hoisted out of this loop
+                int h = h0;
+                asm volatile("" : "+v"(h));
                 const int e = g * L::kEventsPerPass + sub;
                 const double* m_e = s_mom[wv][e];
                 const bool live = s_pref[wv][e] != 0.0;
