@@ -160,6 +160,47 @@ mf_status mf_matrix_element(int process_id, mf_precision precision, const double
                             const double *eb, uint64_t n, double m_top, double w_top,
                             double *out, void *stream);
 
+/*
+ * Gradients of the g g -> t tbar cross section (MF_GG_TTX only, FP64 only;
+ * other processes or MF_FP32_KAHAN return MF_EUNSUPPORTED).  Not part of the
+ * paper: an adjoint of the integrand of Fig. 1 (the weight of Sec. 2.2 with
+ * the phase space of Sec. 2.4 and the amplitudes of Sec. 2.3).  For every
+ * event the kernel recomputes the forward pass and runs a hand-written
+ * reverse sweep; no helicity amplitude is stored.  d/dm_t differentiates the
+ * phase space (through the mass-rescaling root), the spinors and the top
+ * propagators; mu_F and the grid are held fixed.  d/dalpha_s = n_g w/alpha_s.
+ */
+typedef struct {
+    double dsigma_dmt;       /* combined d sigma / d m_t, pb/GeV                */
+    double dsigma_dalphas;   /* combined d sigma / d alpha_s, pb                */
+    double *iter_dmt;        /* host [n_iter] per-iteration mean dw/dm_t, may be NULL     */
+    double *iter_dalphas;    /* host [n_iter] per-iteration mean dw/dalpha_s, may be NULL */
+    double *dw_dy;           /* device [n_events][D] last iteration dw/dy, may be NULL    */
+    double *dw_dmt;          /* device [n_events] last iteration dw/dm_t, may be NULL     */
+} mf_grad_result;
+
+/*
+ * mf_integrate_grad -- mf_integrate plus the gradient.  The integration
+ * (grids, I_j, V_j, res) is exactly that of mf_integrate with the same
+ * arguments.  Iteration j's gradient g_j is the mean of dw/dtheta over its
+ * events on its own (frozen) grid; the combined gradient is
+ * sum_j (g_j / V_j) / sum_j (1 / V_j) with the estimate's V_j held fixed.
+ */
+mf_status mf_integrate_grad(const mf_process *proc, double sqrt_s, const mf_pdf_grid *pdf,
+                            uint64_t n_events, int n_iter, uint64_t seed,
+                            const mf_options *opt, mf_result *res, mf_grad_result *grad);
+
+/*
+ * mf_evaluate_grad -- per-event weight and its gradient for a fixed grid;
+ * arguments as mf_evaluate.  Outputs (device, may be NULL except w_out):
+ *   w_out [n] weights in pb, dw_dy [n][D] derivative in the uniforms y (inside
+ *   the event's VEGAS bins, dx_d/dy_d = J_d), dw_dmt [n] derivative in m_t.
+ */
+mf_status mf_evaluate_grad(const mf_process *proc, double sqrt_s, const mf_pdf_grid *pdf,
+                           const double *grid, const double *y, const uint64_t *event_ids,
+                           uint64_t n, uint64_t seed, int iter, const mf_options *opt,
+                           double *w_out, double *dw_dy, double *dw_dmt);
+
 /* Message for the last non-OK status on this thread. */
 const char *mf_last_error(void);
 

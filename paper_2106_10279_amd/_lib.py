@@ -44,8 +44,14 @@ class mf_result(C.Structure):
                 ("reduce_kernel_ms", C.c_double)]
 
 
+class mf_grad_result(C.Structure):
+    _fields_ = [("dsigma_dmt", C.c_double), ("dsigma_dalphas", C.c_double), ("iter_dmt", _dp),
+                ("iter_dalphas", _dp), ("dw_dy", _dp), ("dw_dmt", _dp)]
+
+
 EXPORTS = ("mf_default_options", "mf_n_dims", "mf_integrate", "mf_evaluate", "mf_refine_grid",
-           "mf_colour_matrix", "mf_matrix_element", "mf_last_error")
+           "mf_colour_matrix", "mf_matrix_element", "mf_integrate_grad", "mf_evaluate_grad",
+           "mf_last_error")
 
 
 class MFError(RuntimeError):
@@ -72,6 +78,14 @@ def load():
                               C.POINTER(mf_options), C.c_void_p, C.c_void_p, C.c_void_p,
                               C.c_void_p]
     L.mf_evaluate.restype = C.c_int
+    L.mf_integrate_grad.argtypes = [C.POINTER(mf_process), C.c_double, C.POINTER(mf_pdf_grid),
+                                    C.c_uint64, C.c_int, C.c_uint64, C.POINTER(mf_options),
+                                    C.POINTER(mf_result), C.POINTER(mf_grad_result)]
+    L.mf_integrate_grad.restype = C.c_int
+    L.mf_evaluate_grad.argtypes = [C.POINTER(mf_process), C.c_double, C.POINTER(mf_pdf_grid), _dp,
+                                   C.c_void_p, C.c_void_p, C.c_uint64, C.c_uint64, C.c_int,
+                                   C.POINTER(mf_options), C.c_void_p, C.c_void_p, C.c_void_p]
+    L.mf_evaluate_grad.restype = C.c_int
     L.mf_refine_grid.argtypes = [C.c_int, C.c_int, C.c_double, C.c_void_p, C.c_void_p,
                                  C.c_void_p, C.c_void_p]
     L.mf_refine_grid.restype = C.c_int

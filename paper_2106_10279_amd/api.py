@@ -5,11 +5,15 @@
     matrix_element(...)     colour/helicity-summed |M|^2 for given momenta
     refine_grid(...)        one VEGAS refinement step (mf_refine_grid)
     colour_matrix(...)      the process colour matrix
+    integrate_grad(...)     integration plus d sigma/d m_t, d sigma/d alpha_s (mf_integrate_grad)
+    evaluate_weights_grad(...)  per-event weights with dw/dy and dw/dm_t (mf_evaluate_grad)
+    CrossSection            torch.autograd.Function: sigma(m_t, alpha_s)
+    EventWeights            torch.autograd.Function: w(y, m_t) per event
 """
 from __future__ import annotations
 
 import ctypes as C
-from dataclasses import dataclass
+from dataclasses import dataclass, replace
 
 import numpy as np
 import torch
@@ -196,3 +200,120 @@ def colour_matrix(process) -> np.ndarray:
     C_ = np.zeros((n, n))
     check(lib.mf_colour_matrix(pid, _ptr(C_)))
     return C_
+
+
+@dataclass
+class GradResult:
+    dsigma_dmt: float
+    dsigma_dalphas: float
+    iter_dmt: np.ndarray
+    iter_dalphas: np.ndarray
+    dw_dy: torch.Tensor | None
+    dw_dmt: torch.Tensor | None
+
+
+def integrate_grad(proc: Process, sqrt_s: float, pdf_table, n_events: int, n_iter: int, seed: int,
+                   n_bins: int = 50, alpha: float = 1.5, start_iter: int = 0, grid_in=None,
+                   keep_weights: bool = False, keep_event_grads: bool = False, max_newton: int = 50,
+                   stream=None):
+    """mf_integrate_grad: the integration of `integrate` (same grids and
+    estimates) plus the gradient; g g -> t tbar, FP64 only."""
+    D = n_dims(proc.process)
+    pdf = _Pdf(pdf_table)
+    gin = None if grid_in is None else np.ascontiguousarray(grid_in, dtype=np.float64)
+    opt = _options(n_bins, alpha, start_iter, "fp64", False, max_newton, gin, stream)
+    I = np.zeros(n_iter)
+    V = np.zeros(n_iter)
+    grid = np.zeros((D, n_bins + 1))
+    hist = np.zeros((D, n_bins))
+    w = torch.empty(n_events, dtype=torch.float64, device="cuda") if keep_weights else None
+    res = _lib.mf_result()
+    res.iter_sigma = _ptr(I)
+    res.iter_var = _ptr(V)
+    res.grid = _ptr(grid)
+    res.hist = _ptr(hist)
+    res.weights = C.cast(C.c_void_p(w.data_ptr()), _dp) if w is not None else None
+    gm = np.zeros(n_iter)
+    ga = np.zeros(n_iter)
+    dy = torch.empty((n_events, D), dtype=torch.float64, device="cuda") if keep_event_grads else None
+    dm = torch.empty(n_events, dtype=torch.float64, device="cuda") if keep_event_grads else None
+    g = _lib.mf_grad_result()
+    g.iter_dmt = _ptr(gm)
+    g.iter_dalphas = _ptr(ga)
+    g.dw_dy = C.cast(C.c_void_p(dy.data_ptr()), _dp) if dy is not None else None
+    g.dw_dmt = C.cast(C.c_void_p(dm.data_ptr()), _dp) if dm is not None else None
+    pc = proc.c()
+    check(lib.mf_integrate_grad(C.byref(pc), sqrt_s, C.byref(pdf.c), n_events, n_iter, seed,
+                                C.byref(opt), C.byref(res), C.byref(g)))
+    r = IntegrationResult(res.sigma, res.sigma_err, res.chi2_dof, res.w_max, res.n_pass,
+                          res.n_newton_fail, I, V, grid, hist, w)
+    return r, GradResult(g.dsigma_dmt, g.dsigma_dalphas, gm, ga, dy, dm)
+
+
+def evaluate_weights_grad(proc: Process, sqrt_s: float, pdf_table, n: int, seed: int = 0, it: int = 0,
+                          grid=None, y: torch.Tensor | None = None,
+                          event_ids: torch.Tensor | None = None, n_bins: int = 50,
+                          max_newton: int = 50, stream=None):
+    """mf_evaluate_grad: (w, dw/dy [n, D], dw/dm_t [n]) for a fixed grid."""
+    D = n_dims(proc.process)
+    pdf = _Pdf(pdf_table)
+    g = None if grid is None else np.ascontiguousarray(grid, dtype=np.float64)
+    opt = _options(n_bins, 1.5, 0, "fp64", False, max_newton, None, stream)
+    w = torch.empty(n, dtype=torch.float64, device="cuda")
+    dy = torch.empty((n, D), dtype=torch.float64, device="cuda")
+    dm = torch.empty(n, dtype=torch.float64, device="cuda")
+    if y is not None:
+        assert y.dtype == torch.float64 and y.is_cuda and y.is_contiguous() and y.shape == (n, D)
+    if event_ids is not None:
+        assert event_ids.dtype == torch.int64 and event_ids.is_cuda and event_ids.shape == (n,)
+    pc = proc.c()
+    check(lib.mf_evaluate_grad(C.byref(pc), sqrt_s, C.byref(pdf.c), _ptr(g) if g is not None else None,
+                               C.c_void_p(y.data_ptr()) if y is not None else None,
+                               C.c_void_p(event_ids.data_ptr()) if event_ids is not None else None,
+                               n, seed, it, C.byref(opt), C.c_void_p(w.data_ptr()),
+                               C.c_void_p(dy.data_ptr()), C.c_void_p(dm.data_ptr())))
+    return w, dy, dm
+
+
+class CrossSection(torch.autograd.Function):
+    """sigma(m_t, alpha_s) in pb for g g -> t tbar.  Forward runs mf_integrate;
+    backward runs mf_integrate_grad with the same arguments, which replays the
+    same iterations (and so the same grids) and returns the adjoint gradient."""
+
+    @staticmethod
+    def forward(ctx, m_t, alpha_s, proc, sqrt_s, pdf_table, n_events, n_iter, seed):
+        p = replace(proc, m_top=float(m_t), alpha_s=float(alpha_s))
+        r = integrate(p, sqrt_s, pdf_table, n_events, n_iter, seed, keep_weights=False)
+        ctx.args = (p, sqrt_s, pdf_table, n_events, n_iter, seed)
+        return torch.tensor(r.sigma, dtype=torch.float64, device=m_t.device)
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        p, sqrt_s, pdf_table, n_events, n_iter, seed = ctx.args
+        _, g = integrate_grad(p, sqrt_s, pdf_table, n_events, n_iter, seed)
+        go = grad_out.detach().to(torch.float64)
+        return go * g.dsigma_dmt, go * g.dsigma_dalphas, None, None, None, None, None, None
+
+
+class EventWeights(torch.autograd.Function):
+    """Per-event weights w(y, m_t) of g g -> t tbar for uniforms y [n, 4]
+    (float64, CUDA) on a fixed grid; backward gives dL/dy and dL/dm_t from
+    mf_evaluate_grad."""
+
+    @staticmethod
+    def forward(ctx, y, m_t, proc, sqrt_s, pdf_table, grid):
+        p = replace(proc, m_top=float(m_t))
+        yc = y.detach().contiguous()
+        w = evaluate_weights(p, sqrt_s, pdf_table, yc.shape[0], grid=grid, y=yc)
+        ctx.args = (p, sqrt_s, pdf_table, grid)
+        ctx.mt_device = m_t.device
+        ctx.save_for_backward(yc)
+        return w
+
+    @staticmethod
+    def backward(ctx, grad_w):
+        (yc,) = ctx.saved_tensors
+        p, sqrt_s, pdf_table, grid = ctx.args
+        _, dy, dm = evaluate_weights_grad(p, sqrt_s, pdf_table, yc.shape[0], grid=grid, y=yc)
+        g = grad_w.detach().to(torch.float64)
+        return g[:, None] * dy, (g * dm).sum().to(ctx.mt_device), None, None, None, None

@@ -14,12 +14,12 @@ namespace mf {
 template <typename T>
 struct cplx {
     T x, y;
-    __device__ __forceinline__ cplx() {}
-    __device__ __forceinline__ cplx(T a, T b) : x(a), y(b) {}
+    __host__ __device__ __forceinline__ cplx() {}
+    __host__ __device__ __forceinline__ cplx(T a, T b) : x(a), y(b) {}
 };
 
 template <typename T>
-__device__ __forceinline__ cplx<T> cmul(cplx<T> a, cplx<T> b)
+__host__ __device__ __forceinline__ cplx<T> cmul(cplx<T> a, cplx<T> b)
 {
     return cplx<T>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
@@ -33,7 +33,7 @@ __device__ __forceinline__ cplx<T> cmul(cplx<T> a, cplx<T> b)
 
 // s += a x gamma.(SGN j) for a row spinor a: (aR (j.sigmabar), aL (j.sigma)).
 template <int SGN = 1, typename T>
-__device__ __forceinline__ void rowslash_acc(const cplx<T>* a, const T* jin, cplx<T>& s0, cplx<T>& s1,
+__host__ __device__ __forceinline__ void rowslash_acc(const cplx<T>* a, const T* jin, cplx<T>& s0, cplx<T>& s1,
                                              cplx<T>& s2, cplx<T>& s3)
 {
     const T j[4] = {(T)SGN * jin[0], (T)SGN * jin[1], (T)SGN * jin[2], (T)SGN * jin[3]};
@@ -54,7 +54,7 @@ __device__ __forceinline__ void rowslash_acc(const cplx<T>* a, const T* jin, cpl
 
 // out = s x (K-slash + m) x (fr + i fi) for a row spinor s.
 template <typename T>
-__device__ __forceinline__ void rowprop(cplx<T> s0, cplx<T> s1, cplx<T> s2, cplx<T> s3, const T* K, T m,
+__host__ __device__ __forceinline__ void rowprop(cplx<T> s0, cplx<T> s1, cplx<T> s2, cplx<T> s3, const T* K, T m,
                                         T fr, T fi, cplx<T>* out)
 {
     const T kp = K[0] + K[3], km = K[0] - K[3];
@@ -81,7 +81,7 @@ __device__ __forceinline__ void rowprop(cplx<T> s0, cplx<T> s1, cplx<T> s2, cplx
 // out = (K-slash + m) w x (fr + i fi) for a column spinor w:
 // ((m wL + (K.sigma) wR), ((K.sigmabar) wL + m wR)).
 template <typename T>
-__device__ __forceinline__ void colprop(const cplx<T>* w, const T* K, T m, T fr, T fi, cplx<T>* out)
+__host__ __device__ __forceinline__ void colprop(const cplx<T>* w, const T* K, T m, T fr, T fi, cplx<T>* out)
 {
     const T kp = K[0] + K[3], km = K[0] - K[3];
     cplx<T> t0, t1, t2, t3;
@@ -106,7 +106,7 @@ __device__ __forceinline__ void colprop(const cplx<T>* w, const T* K, T m, T fr,
 
 // acc += gamma.(SGN e) w for a real 4-vector e and a complex column w.
 template <int SGN = 1, typename T>
-__device__ __forceinline__ void slashcol_acc(const T* ein, const cplx<T>* v, cplx<T>* W)
+__host__ __device__ __forceinline__ void slashcol_acc(const T* ein, const cplx<T>* v, cplx<T>* W)
 {
     const T e[4] = {(T)SGN * ein[0], (T)SGN * ein[1], (T)SGN * ein[2], (T)SGN * ein[3]};
     const T ep = e[0] + e[3], em = e[0] - e[3];
@@ -145,7 +145,7 @@ __device__ __forceinline__ int pext4(int x, int m)
 
 // c^mu = a gamma^mu v = aL sigma^mu vR + aR sigmabar^mu vL.
 template <typename T>
-__device__ __forceinline__ void bilinear(const cplx<T>* a, const cplx<T>* v, cplx<T>* c)
+__host__ __device__ __forceinline__ void bilinear(const cplx<T>* a, const cplx<T>* v, cplx<T>* c)
 {
     const cplx<T> s0 = cmul(a[0], v[2]), s1 = cmul(a[1], v[3]);
     const cplx<T> x01 = cmul(a[0], v[3]), x10 = cmul(a[1], v[2]);
@@ -160,7 +160,7 @@ __device__ __forceinline__ void bilinear(const cplx<T>* a, const cplx<T>* v, cpl
 
 // (ar, ai) += SGN c^mu j_mu for complex c and real j.
 template <int SGN = 1, typename T>
-__device__ __forceinline__ void cdotj(const cplx<T>* c, const T* j, T& ar, T& ai)
+__host__ __device__ __forceinline__ void cdotj(const cplx<T>* c, const T* j, T& ar, T& ai)
 {
     const T r = c[0].x * j[0] - c[1].x * j[1] - c[2].x * j[2] - c[3].x * j[3];
     const T i = c[0].y * j[0] - c[1].y * j[1] - c[2].y * j[2] - c[3].y * j[3];
@@ -170,7 +170,7 @@ __device__ __forceinline__ void cdotj(const cplx<T>* c, const T* j, T& ar, T& ai
 
 // W = gamma.e v = ((e.sigma) vR, (e.sigmabar) vL) for a real 4-vector e.
 template <typename T>
-__device__ __forceinline__ void slashcol(const T* e, const cplx<T>* v, cplx<T>* W)
+__host__ __device__ __forceinline__ void slashcol(const T* e, const cplx<T>* v, cplx<T>* W)
 {
     const T ep = e[0] + e[3], em = e[0] - e[3];
     // W0 = (e0 - e3) v2 + (-e1 + i e2) v3
@@ -184,7 +184,7 @@ __device__ __forceinline__ void slashcol(const T* e, const cplx<T>* v, cplx<T>* 
 }
 
 template <typename T>
-__device__ __forceinline__ void rowdotcol(const cplx<T>* a, const cplx<T>* b, T& ar, T& ai)
+__host__ __device__ __forceinline__ void rowdotcol(const cplx<T>* a, const cplx<T>* b, T& ar, T& ai)
 {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -215,7 +215,7 @@ __device__ __forceinline__ void linear_pol(const double* p, int h, T* e)
 // Spinors with spin quantised along z in the rest frame, boosted:
 //   u = (sqrt(p.sigma) xi, sqrt(p.sigmabar) xi),  v = (sqrt(p.sigma) xi, -sqrt(p.sigmabar) xi),
 //   sqrt(p.sigma) = (p.sigma + m)/sqrt(2(E+m)),  xi_0 = (1, 0), xi_1 = (0, 1).
-__device__ __forceinline__ void sqrt_blocks(const double* p, double m, int s, double* A, double* B)
+__host__ __device__ __forceinline__ void sqrt_blocks(const double* p, double m, int s, double* A, double* B)
 {
     const double n = 1.0 / sqrt(2.0 * (p[0] + m));
     // columns s of (p.sigma + m) and (p.sigmabar + m), as (re, im) pairs
@@ -234,7 +234,7 @@ __device__ __forceinline__ void sqrt_blocks(const double* p, double m, int s, do
 
 // ubar = u^dagger gamma^0 = (conj(uR), conj(uL)).
 template <typename T>
-__device__ __forceinline__ void spinor_ubar(const double* p, double m, int s, cplx<T>* ub)
+__host__ __device__ __forceinline__ void spinor_ubar(const double* p, double m, int s, cplx<T>* ub)
 {
     double A[4], B[4];
     sqrt_blocks(p, m, s, A, B);
@@ -245,7 +245,7 @@ __device__ __forceinline__ void spinor_ubar(const double* p, double m, int s, cp
 }
 
 template <typename T>
-__device__ __forceinline__ void spinor_v(const double* p, double m, int s, cplx<T>* v)
+__host__ __device__ __forceinline__ void spinor_v(const double* p, double m, int s, cplx<T>* v)
 {
     double A[4], B[4];
     sqrt_blocks(p, m, s, A, B);

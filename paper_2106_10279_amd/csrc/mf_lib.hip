@@ -15,6 +15,7 @@
 #include <vector>
 
 #include "mf.h"
+#include "mf_grad.hpp"
 #include "mf_kernels.hpp"
 
 namespace {
@@ -60,7 +61,7 @@ struct Buffer {
 
 struct Workspace {
     std::mutex lock;
-    Buffer grid[2], log_x, log_q2, xf, partials, entries, iter_I, iter_V, stats;
+    Buffer grid[2], log_x, log_q2, xf, partials, entries, iter_I, iter_V, stats, gpartials, gsum;
     int n_cu = 0;
 };
 
@@ -314,6 +315,26 @@ void combine(int n, const double* I, const double* V, double* sigma, double* err
     *chi2 = num.size() > 1 ? nsum(chi) / (double)(num.size() - 1) : 0.0;
 }
 
+// sum_j (g_j / V_j) / sum_j (1 / V_j) over iterations with V_j > 0 (the
+// same weights as the estimate), compensated.
+void combine_fixed(int n, const double* g, const double* V, double* out)
+{
+    double ns = 0.0, nc = 0.0, ds = 0.0, dc = 0.0;
+    auto add = [](double& s, double& c, double x) {
+        const double t = s + x;
+        if (std::fabs(s) >= std::fabs(x)) c += (s - t) + x; else c += (x - t) + s;
+        s = t;
+    };
+    int used = 0;
+    for (int j = 0; j < n; ++j)
+        if (V[j] > 0.0) {
+            add(ns, nc, g[j] / V[j]);
+            add(ds, dc, 1.0 / V[j]);
+            ++used;
+        }
+    *out = used ? (ns + nc) / (ds + dc) : (n > 0 ? g[n - 1] : 0.0);
+}
+
 }  // namespace
 
 extern "C" {
@@ -341,8 +362,14 @@ int mf_n_dims(int process_id)
 
 const char* mf_last_error(void) { return g_error.c_str(); }
 
-mf_status mf_integrate(const mf_process* proc, double sqrt_s, const mf_pdf_grid* pdf, uint64_t n_events,
-                       int n_iter, uint64_t seed, const mf_options* opt, mf_result* res)
+}  // extern "C"
+
+namespace {
+
+// The iteration loop of mf_integrate; with `grad`, every iteration also runs
+// the adjoint kernel on the grid that iteration used.
+mf_status integrate_impl(const mf_process* proc, double sqrt_s, const mf_pdf_grid* pdf, uint64_t n_events,
+                         int n_iter, uint64_t seed, const mf_options* opt, mf_result* res, mf_grad_result* grad)
 {
     int ng = 0;
     mf_status st;
@@ -358,6 +385,12 @@ mf_status mf_integrate(const mf_process* proc, double sqrt_s, const mf_pdf_grid*
         return fail(MF_EINVAL, "n_iter must be in [1, 256]");
     if ((uint64_t)opt->start_iter + (uint64_t)n_iter > 0xFFFFFFFFull)
         return fail(MF_EINVAL, "iteration index exceeds the 32-bit Philox counter word");
+    if (grad) {
+        if (ng != 2)
+            return fail(MF_EUNSUPPORTED, "gradients are implemented for g g -> t tbar only");
+        if (opt->precision != MF_FP64)
+            return fail(MF_EUNSUPPORTED, "gradients are computed in FP64 only");
+    }
 
     Workspace* wsp = nullptr;
     if ((st = device_workspace(&wsp)) != MF_OK) return st;
@@ -383,6 +416,10 @@ mf_status mf_integrate(const mf_process* proc, double sqrt_s, const mf_pdf_grid*
     if ((st = ensure(ws.iter_I, sizeof(double) * n_iter)) != MF_OK) return st;
     if ((st = ensure(ws.iter_V, sizeof(double) * n_iter)) != MF_OK) return st;
     if ((st = ensure(ws.stats, sizeof(double) * 4)) != MF_OK) return st;
+    if (grad) {
+        if ((st = ensure(ws.gpartials, sizeof(double) * 4 * (size_t)n_waves)) != MF_OK) return st;
+        if ((st = ensure(ws.gsum, sizeof(double) * 4 * (size_t)n_iter)) != MF_OK) return st;
+    }
 
     std::vector<double> grid0((size_t)D * (nb + 1));
     if (opt->grid_in)
@@ -430,6 +467,27 @@ mf_status mf_integrate(const mf_process* proc, double sqrt_s, const mf_pdf_grid*
             MF_HIP(hipEventRecord(marks[3 * j], S.stream));
         if ((st = dispatch_event(ng, opt->precision, P, n_waves / mf::kWavesPerBlock, S.stream)) != MF_OK)
             return st;
+        if (grad) {
+            mf::GradParams G;
+            G.P = P;
+            G.P.weights = nullptr;
+            G.P.partials = nullptr;
+            G.alpha_s = proc->alpha_s;
+            G.w_top = proc->w_top;
+            G.dw_dy = (j == n_iter - 1) ? grad->dw_dy : nullptr;
+            G.dw_dmt = (j == n_iter - 1) ? grad->dw_dmt : nullptr;
+            G.w_out = nullptr;
+            G.partials = (double*)ws.gpartials.ptr;
+            hipLaunchKernelGGL(mf::grad_kernel_ttx, dim3(n_waves / mf::kWavesPerBlock), dim3(mf::kBlock), 0, S.stream,
+                               G);
+            MF_HIP(hipGetLastError());
+            mf::ReduceParams RG = R;
+            RG.partials = G.partials;
+            RG.stride = 4;
+            RG.entries = (double*)ws.gsum.ptr + 4 * (size_t)j;
+            hipLaunchKernelGGL(mf::reduce_entries_kernel, dim3(4), dim3(mf::kReduceBlock), 0, S.stream, RG);
+            MF_HIP(hipGetLastError());
+        }
         if (opt->profile)
             MF_HIP(hipEventRecord(marks[3 * j + 1], S.stream));
         R.grid_in = (const double*)ws.grid[cur].ptr;
@@ -444,7 +502,9 @@ mf_status mf_integrate(const mf_process* proc, double sqrt_s, const mf_pdf_grid*
         cur = 1 - cur;
     }
 
-    std::vector<double> I(n_iter), V(n_iter), stats(4);
+    std::vector<double> I(n_iter), V(n_iter), stats(4), gs(grad ? 4 * (size_t)n_iter : 0);
+    if (grad)
+        MF_HIP(hipMemcpyAsync(gs.data(), ws.gsum.ptr, sizeof(double) * gs.size(), hipMemcpyDeviceToHost, S.stream));
     MF_HIP(hipMemcpyAsync(I.data(), ws.iter_I.ptr, sizeof(double) * n_iter, hipMemcpyDeviceToHost, S.stream));
     MF_HIP(hipMemcpyAsync(V.data(), ws.iter_V.ptr, sizeof(double) * n_iter, hipMemcpyDeviceToHost, S.stream));
     MF_HIP(hipMemcpyAsync(stats.data(), ws.stats.ptr, sizeof(double) * 4, hipMemcpyDeviceToHost, S.stream));
@@ -479,13 +539,51 @@ mf_status mf_integrate(const mf_process* proc, double sqrt_s, const mf_pdf_grid*
         std::memcpy(res->iter_sigma, I.data(), sizeof(double) * n_iter);
     if (res->iter_var)
         std::memcpy(res->iter_var, V.data(), sizeof(double) * n_iter);
+    if (grad) {
+        // Per-iteration means of dw/dtheta on frozen grids, combined with the
+        // inverse-variance weights of the estimate (V_j held fixed).
+        std::vector<double> gm(n_iter), ga(n_iter);
+        for (int j = 0; j < n_iter; ++j) {
+            gm[j] = gs[4 * (size_t)j + 0] / (double)n_events;
+            ga[j] = gs[4 * (size_t)j + 2] / (double)n_events;
+        }
+        combine_fixed(n_iter, gm.data(), V.data(), &grad->dsigma_dmt);
+        combine_fixed(n_iter, ga.data(), V.data(), &grad->dsigma_dalphas);
+        if (grad->iter_dmt)
+            std::memcpy(grad->iter_dmt, gm.data(), sizeof(double) * n_iter);
+        if (grad->iter_dalphas)
+            std::memcpy(grad->iter_dalphas, ga.data(), sizeof(double) * n_iter);
+    }
     return MF_OK;
 }
 
-mf_status mf_evaluate(const mf_process* proc, double sqrt_s, const mf_pdf_grid* pdf, const double* grid,
-                      const double* y, const uint64_t* event_ids, uint64_t n, uint64_t seed, int iter,
-                      const mf_options* opt, double* w_out, uint64_t* k53_out, int32_t* bins_out,
-                      double* record_out)
+}  // namespace
+
+extern "C" {
+
+mf_status mf_integrate(const mf_process* proc, double sqrt_s, const mf_pdf_grid* pdf, uint64_t n_events,
+                       int n_iter, uint64_t seed, const mf_options* opt, mf_result* res)
+{
+    return integrate_impl(proc, sqrt_s, pdf, n_events, n_iter, seed, opt, res, nullptr);
+}
+
+mf_status mf_integrate_grad(const mf_process* proc, double sqrt_s, const mf_pdf_grid* pdf, uint64_t n_events,
+                            int n_iter, uint64_t seed, const mf_options* opt, mf_result* res, mf_grad_result* grad)
+{
+    if (!grad)
+        return fail(MF_EINVAL, "grad is NULL");
+    return integrate_impl(proc, sqrt_s, pdf, n_events, n_iter, seed, opt, res, grad);
+}
+
+}  // extern "C"
+
+namespace {
+
+// Validation, PDF and grid upload for the fixed-grid entry points; the
+// workspace stays locked through `lock` until the caller's launch is done.
+mf_status fixed_grid_setup(const mf_process* proc, double sqrt_s, const mf_pdf_grid* pdf, const double* grid,
+                           uint64_t n, uint64_t seed, int iter, const mf_options* opt, const double* y,
+                           const uint64_t* event_ids, std::unique_lock<std::mutex>& lock, Setup& S)
 {
     int ng = 0;
     mf_status st;
@@ -493,8 +591,6 @@ mf_status mf_evaluate(const mf_process* proc, double sqrt_s, const mf_pdf_grid* 
     if ((st = validate_pdf(pdf, proc->mu_f)) != MF_OK) return st;
     const int D = 2 + 3 * ng - 4;
     if ((st = validate_options(opt, D)) != MF_OK) return st;
-    if (!w_out)
-        return fail(MF_EINVAL, "w_out is NULL");
     if (n < 1 || n > (1ull << 40))
         return fail(MF_EINVAL, "n must be in [1, 2^40]");
     if (iter < 0)
@@ -506,14 +602,13 @@ mf_status mf_evaluate(const mf_process* proc, double sqrt_s, const mf_pdf_grid* 
             if (e[0] != 0.0 || e[nb] != 1.0 || !ascending(e, nb + 1))
                 return fail(MF_EINVAL, "grid rows must rise strictly from 0 to 1");
         }
-
     Workspace* wsp = nullptr;
     if ((st = device_workspace(&wsp)) != MF_OK) return st;
     Workspace& ws = *wsp;
-    std::lock_guard<std::mutex> guard(ws.lock);
-    Setup S;
+    lock = std::unique_lock<std::mutex>(ws.lock);
     S.ng = ng;
     S.D = D;
+    S.ws = wsp;
     S.stream = (hipStream_t)opt->stream;
     if ((st = prepare(proc, sqrt_s, pdf, opt, ws, S)) != MF_OK) return st;
     mf::EventParams& P = S.P;
@@ -527,22 +622,72 @@ mf_status mf_evaluate(const mf_process* proc, double sqrt_s, const mf_pdf_grid* 
             for (int i = 0; i <= nb; ++i)
                 g[(size_t)d * (nb + 1) + i] = (double)i / (double)nb;
     MF_HIP(hipMemcpyAsync(ws.grid[0].ptr, g.data(), grid_bytes, hipMemcpyHostToDevice, S.stream));
+    // the staged host vector must outlive the copy
+    MF_HIP(hipStreamSynchronize(S.stream));
     const uint64_t n_chunks = (n + mf::kWave - 1) / mf::kWave;
-    const int n_waves = waves_for(n_chunks, ws.n_cu);
     P.n_events = n;
     P.seed = seed;
     P.iter = (uint32_t)iter;
     P.grid = (const double*)ws.grid[0].ptr;
     P.y_in = y;
     P.event_ids = event_ids;
+    P.partials = nullptr;
+    P.n_waves = waves_for(n_chunks, ws.n_cu);
+    return MF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+mf_status mf_evaluate(const mf_process* proc, double sqrt_s, const mf_pdf_grid* pdf, const double* grid,
+                      const double* y, const uint64_t* event_ids, uint64_t n, uint64_t seed, int iter,
+                      const mf_options* opt, double* w_out, uint64_t* k53_out, int32_t* bins_out,
+                      double* record_out)
+{
+    if (!w_out)
+        return fail(MF_EINVAL, "w_out is NULL");
+    std::unique_lock<std::mutex> lock;
+    Setup S;
+    mf_status st;
+    if ((st = fixed_grid_setup(proc, sqrt_s, pdf, grid, n, seed, iter, opt, y, event_ids, lock, S)) != MF_OK)
+        return st;
+    mf::EventParams& P = S.P;
     P.weights = w_out;
     P.k53_out = k53_out;
     P.bins_out = bins_out;
     P.record = record_out;
-    P.partials = nullptr;
-    P.n_waves = n_waves;
-    if ((st = dispatch_event(ng, opt->precision, P, n_waves / mf::kWavesPerBlock, S.stream)) != MF_OK)
+    if ((st = dispatch_event(S.ng, opt->precision, P, P.n_waves / mf::kWavesPerBlock, S.stream)) != MF_OK)
         return st;
+    MF_HIP(hipStreamSynchronize(S.stream));
+    return MF_OK;
+}
+
+mf_status mf_evaluate_grad(const mf_process* proc, double sqrt_s, const mf_pdf_grid* pdf, const double* grid,
+                           const double* y, const uint64_t* event_ids, uint64_t n, uint64_t seed, int iter,
+                           const mf_options* opt, double* w_out, double* dw_dy, double* dw_dmt)
+{
+    if (!w_out)
+        return fail(MF_EINVAL, "w_out is NULL");
+    if (proc && proc->id != MF_GG_TTX)
+        return fail(MF_EUNSUPPORTED, "gradients are implemented for g g -> t tbar only");
+    if (opt && opt->precision != MF_FP64)
+        return fail(MF_EUNSUPPORTED, "gradients are computed in FP64 only");
+    std::unique_lock<std::mutex> lock;
+    Setup S;
+    mf_status st;
+    if ((st = fixed_grid_setup(proc, sqrt_s, pdf, grid, n, seed, iter, opt, y, event_ids, lock, S)) != MF_OK)
+        return st;
+    mf::GradParams G;
+    G.P = S.P;
+    G.alpha_s = proc->alpha_s;
+    G.w_top = proc->w_top;
+    G.dw_dy = dw_dy;
+    G.dw_dmt = dw_dmt;
+    G.w_out = w_out;
+    G.partials = nullptr;
+    hipLaunchKernelGGL(mf::grad_kernel_ttx, dim3(G.P.n_waves / mf::kWavesPerBlock), dim3(mf::kBlock), 0, S.stream, G);
+    MF_HIP(hipGetLastError());
     MF_HIP(hipStreamSynchronize(S.stream));
     return MF_OK;
 }
