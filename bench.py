@@ -14,12 +14,15 @@ form with its measured error, and the CPU oracle timed on the host cores.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import importlib.util
 import json
 import math
 import os
 import sys
 import time
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -69,30 +72,87 @@ def timed_run(api, torch, proc, pdf, n_events, steps, warmup, precision, seed):
     return r, wall, e0.elapsed_time(e1) / 1e3
 
 
-def roofline(flops_per_event, n_events, kernel_ms_total, steps, peak):
-    per_launch_s = kernel_ms_total / steps / 1e3
-    achieved = flops_per_event * n_events / per_launch_s / 1e12
+# Sources of the event kernel; HBM traffic measured with rocprofv3 counters is
+# reported only while their hash matches the one recorded with the counters.
+KERNEL_SOURCES = ("mf_kernels.hpp", "mf_device.hpp", "gen_amplitudes.py")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "event_kernel_traffic.txt")
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2106_10279_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(key):
+    """HBM bytes per launch (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, scaled by the
+    copy-kernel calibration) for `key`, or None if not measured for the current
+    kernel sources."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    with open(TRAFFIC_FILE) as fh:
+        for line in fh:
+            if "=" in line and not line.lstrip().startswith("#"):
+                k, v = line.split("=", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("source_hash") != kernel_source_hash() or key not in vals:
+        return None
+    return int(float(vals[key]))
+
+
+def roofline(me_flops_event, other_flops_event, n_events, r, peak, traffic_key=None):
+    """Algorithmic flops of the timed event-kernel launches over their
+    HIP-event durations: the amplitude code runs only for events that pass
+    threshold and cuts (n_pass of each iteration), phase space, PDF and
+    accumulation for every event."""
+    t_s = float(np.sum(r.iter_event_ms)) / 1e3
+    launches = len(r.iter_event_ms)
+    flops = float(np.sum(r.iter_pass)) * me_flops_event + launches * n_events * other_flops_event
+    achieved = flops / t_s / 1e12
     return {"bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-            "frac": round(achieved / peak, 4), "traffic": None,
-            "kernel": "event_kernel", "avg_launch_ms": round(kernel_ms_total / steps, 3),
-            "flops_per_event": flops_per_event}
+            "frac": round(achieved / peak, 4),
+            "traffic": measured_traffic(traffic_key) if traffic_key else None,
+            "kernel": "event_kernel", "avg_launch_ms": round(t_s * 1e3 / launches, 3),
+            "flops_per_passing_event": me_flops_event + other_flops_event,
+            "pass_fraction": round(float(np.sum(r.iter_pass)) / (launches * n_events), 4)}
 
 
 def precision_error(api, torch, proc, pdf, grid, n, seed):
-    """FP32 amplitudes vs FP64 on the same events and grid."""
+    """FP32 amplitudes vs FP64 on the same n events and grid, on the device."""
     w64 = api.evaluate_weights(proc, 13000.0, pdf, n, seed=seed, it=0, grid=grid)
     w32 = api.evaluate_weights(proc, 13000.0, pdf, n, seed=seed, it=0, grid=grid,
                                precision="fp32_kahan")
-    w64 = w64.cpu().double()
-    w32 = w32.cpu().double()
     nz = w64 != 0
     rel = ((w32[nz] - w64[nz]) / w64[nz]).abs()
+    srt = torch.sort(rel).values
+    k = srt.numel()
     I64 = w64.sum().item()
     I32 = w32.sum().item()
-    return {"events": n, "event_rel_max": float(rel.max()),
-            "event_rel_p999": float(rel.quantile(0.999)) if rel.numel() < 2**24 else None,
-            "event_rel_median": float(rel.median()),
-            "integral_rel": abs(I32 / I64 - 1.0)}
+    out = {"events": n, "nonzero": k, "event_rel_max": float(srt[-1]),
+           "event_rel_p999": float(srt[min(k - 1, int(0.999 * k))]),
+           "event_rel_median": float(srt[k // 2]), "integral_rel": abs(I32 / I64 - 1.0)}
+    del w64, w32, rel, srt
+    torch.cuda.empty_cache()
+    return out
+
+
+def adjoint_run(api, torch, pdf, n_events, n_iter, seed):
+    """g g -> t tbar forward integration plus the adjoint (d sigma / d m_t,
+    d sigma / d alpha_s); events/s counts forward + adjoint per event."""
+    proc = api.Process("gg_ttx")
+    api.integrate_grad(proc, 13000.0, pdf, n_events, 1, seed)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r, g = api.integrate_grad(proc, 13000.0, pdf, n_events, n_iter, seed)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return {"workload": f"gg_ttx LO + adjoint, {n_events} events x {n_iter} iterations, FP64",
+            "value": round(n_events * n_iter / dt, 2), "unit": "events/s (forward + adjoint)",
+            "sigma_pb": r.sigma, "sigma_err_pb": r.sigma_err, "dsigma_dmt_pb_per_gev": g.dsigma_dmt,
+            "dsigma_dalphas_pb": g.dsigma_dalphas}
 
 
 def cpu_baseline(wl, pdf, budget_s):
@@ -123,6 +183,11 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--fp32-events", type=int, default=100_000_000,
+                    help="events per iteration of the FP32-amplitude leg (gg_ttxgg at 1e8)")
+    ap.add_argument("--fp32-steps", type=int, default=3)
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--adjoint-events", type=int, default=10_000_000)
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device-to-device copy of this many bytes (3 times), "
                          "the reference kernel for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE")
@@ -150,7 +215,7 @@ def main():
     n_events = args.events or wl["events"]
     pdf = W.synthetic_pdf()
     proc = api.Process(wl["process"], **wl["cuts"])
-    flops = me_flops(wl["n_g"]) + OTHER_FLOPS[wl["n_g"]]
+    f_me, f_other = me_flops(wl["n_g"]), OTHER_FLOPS[wl["n_g"]]
 
     log(f"[bench] {wl['process']} fp64: {args.warmup} warm-up + {args.steps} timed iterations "
         f"x {n_events} events")
@@ -168,23 +233,34 @@ def main():
                    "process": wl["process"], "events_per_step": n_events, "cuts": wl["cuts"],
                    "sqrt_s_gev": 13000.0, "m_top": 173.0, "w_top": 1.5, "alpha_s": 0.118,
                    "seed": args.seed, "amplitude_precision": "fp64"},
-        "roofline": roofline(flops, n_events, r64.event_kernel_ms, args.steps, PEAK_FP64_TFLOPS),
+        "roofline": roofline(f_me, f_other, n_events, r64, PEAK_FP64_TFLOPS,
+                             f"{args.workload}_fp64_{n_events}"),
         "result_pb": {"sigma": r64.sigma, "sigma_err": r64.sigma_err, "chi2_dof": r64.chi2_dof},
         "stream_timed_s": round(ev64, 4),
     }
     if not args.no_fp32:
-        log("[bench] fp32 amplitudes with fp64 compensated accumulation")
-        r32, wall32, _ = timed_run(api, torch, proc, pdf, n_events, args.steps, args.warmup,
+        n32 = args.fp32_events if args.workload == "ttxgg" else n_events
+        log(f"[bench] fp32 amplitudes with fp64 compensated accumulation: {args.warmup} warm-up + "
+            f"{args.fp32_steps} timed iterations x {n32} events")
+        r32, wall32, _ = timed_run(api, torch, proc, pdf, n32, args.fp32_steps, args.warmup,
                                    "fp32_kahan", args.seed)
-        v32 = args.steps * n_events / wall32
-        err = precision_error(api, torch, proc, pdf, r64.grid, min(n_events, 1 << 20), args.seed + 1)
+        v32 = args.fp32_steps * n32 / wall32
+        log(f"[bench] fp32 done: {v32:.4g} events/s; error vs fp64 on {n32} events")
+        err = precision_error(api, torch, proc, pdf, r64.grid, n32, args.seed + 1)
         out["fp32_kahan"] = {
-            "value": round(v32, 2), "unit": "events/s",
-            "ms_per_step": round(wall32 / args.steps * 1e3, 3),
-            "roofline": roofline(flops, n_events, r32.event_kernel_ms, args.steps, PEAK_FP32_TFLOPS),
-            "sigma": r32.sigma, "sigma_err": r32.sigma_err, "error_vs_fp64": err,
+            "value": round(v32, 2), "unit": "events/s", "events_per_step": n32,
+            "steps": args.fp32_steps, "ms_per_step": round(wall32 / args.fp32_steps * 1e3, 3),
+            "roofline": roofline(f_me, f_other, n32, r32, PEAK_FP32_TFLOPS,
+                                 f"{args.workload}_fp32_{n32}"),
+            "sigma": r32.sigma, "sigma_err": r32.sigma_err,
+            "error_vs_fp64": err,
+            "note": "packed FP32 disabled at compile time: FP32 issues at the FP64 vector rate",
         }
-        log(f"[bench] fp32 done: {v32:.4g} events/s, integral rel err {err['integral_rel']:.2e}")
+        log(f"[bench] fp32 integral rel err {err['integral_rel']:.2e}, event max {err['event_rel_max']:.2e}")
+    if not args.no_adjoint:
+        log(f"[bench] adjoint: gg_ttx forward + gradient, {args.adjoint_events} events x 3 iterations")
+        out["adjoint"] = adjoint_run(api, torch, pdf, args.adjoint_events, 3, args.seed)
+        log(f"[bench] adjoint done: {out['adjoint']['value']:.4g} events/s")
     if not args.no_cpu_baseline:
         log(f"[bench] CPU oracle baseline (~{args.cpu_seconds:.0f} s)")
         out["cpu_baseline"] = cpu_baseline(wl, pdf, args.cpu_seconds)

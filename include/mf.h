@@ -91,6 +91,8 @@ typedef struct {
     int64_t n_newton_fail;   /* Newton failures summed over all iterations      */
     double event_kernel_ms;  /* profile = 1: summed event-kernel time, ms       */
     double reduce_kernel_ms; /* profile = 1: summed reduce/refine time, ms      */
+    double *iter_pass;       /* host [n_iter] events passing threshold and cuts per iteration, may be NULL */
+    double *iter_event_ms;   /* host [n_iter] profile = 1: event-kernel time per iteration, ms, may be NULL */
 } mf_result;
 
 /* Fills *opt with the defaults shown above. */

@@ -41,7 +41,7 @@ class mf_result(C.Structure):
                 ("w_max", C.c_double), ("iter_sigma", _dp), ("iter_var", _dp), ("grid", _dp),
                 ("hist", _dp), ("weights", _dp), ("n_pass", C.c_int64),
                 ("n_newton_fail", C.c_int64), ("event_kernel_ms", C.c_double),
-                ("reduce_kernel_ms", C.c_double)]
+                ("reduce_kernel_ms", C.c_double), ("iter_pass", _dp), ("iter_event_ms", _dp)]
 
 
 class mf_grad_result(C.Structure):

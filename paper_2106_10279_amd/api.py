@@ -101,6 +101,8 @@ class IntegrationResult:
     weights: torch.Tensor | None
     event_kernel_ms: float = 0.0
     reduce_kernel_ms: float = 0.0
+    iter_pass: np.ndarray | None = None
+    iter_event_ms: np.ndarray | None = None
 
 
 def integrate(proc: Process, sqrt_s: float, pdf_table, n_events: int, n_iter: int, seed: int,
@@ -125,12 +127,16 @@ def integrate(proc: Process, sqrt_s: float, pdf_table, n_events: int, n_iter: in
     res.grid = _ptr(grid)
     res.hist = _ptr(hist)
     res.weights = C.cast(C.c_void_p(w.data_ptr()), _dp) if w is not None else None
+    npass = np.zeros(n_iter)
+    tms = np.zeros(n_iter)
+    res.iter_pass = _ptr(npass)
+    res.iter_event_ms = _ptr(tms)
     pc = proc.c()
     check(lib.mf_integrate(C.byref(pc), sqrt_s, C.byref(pdf.c), n_events, n_iter, seed,
                            C.byref(opt), C.byref(res)))
     return IntegrationResult(res.sigma, res.sigma_err, res.chi2_dof, res.w_max, res.n_pass,
                              res.n_newton_fail, I, V, grid, hist, w, res.event_kernel_ms,
-                             res.reduce_kernel_ms)
+                             res.reduce_kernel_ms, npass, tms if profile else None)
 
 
 def evaluate_weights(proc: Process, sqrt_s: float, pdf_table, n: int, seed: int = 0, it: int = 0,

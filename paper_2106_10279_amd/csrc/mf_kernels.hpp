@@ -593,6 +593,7 @@ struct ReduceParams {
     const double* hist;      // [D][n_bins] reduced histogram (read by refine)
     double* iter_I;          // [n_iter]
     double* iter_V;
+    double* iter_pass;       // [n_iter] events passing threshold and cuts, or null
     double* stats;           // [4]: w_max (this iteration), n_pass, n_fail (cumulative)
     int j;
 };
@@ -648,6 +649,8 @@ __global__ void __launch_bounds__(256) refine_kernel(ReduceParams R)
         const double V = (R.entries[2] / N - I * I) / (N - 1.0);
         R.iter_I[R.j] = I;
         R.iter_V[R.j] = V;
+        if (R.iter_pass)
+            R.iter_pass[R.j] = R.entries[5];
         R.stats[0] = R.entries[4];
         R.stats[1] = R.entries[5];
         R.stats[2] += R.entries[6];

@@ -61,7 +61,7 @@ struct Buffer {
 
 struct Workspace {
     std::mutex lock;
-    Buffer grid[2], log_x, log_q2, xf, partials, entries, iter_I, iter_V, stats, gpartials, gsum;
+    Buffer grid[2], log_x, log_q2, xf, partials, entries, iter_I, iter_V, iter_pass, stats, gpartials, gsum;
     int n_cu = 0;
 };
 
@@ -415,6 +415,7 @@ mf_status integrate_impl(const mf_process* proc, double sqrt_s, const mf_pdf_gri
     if ((st = ensure(ws.entries, sizeof(double) * (size_t)stride)) != MF_OK) return st;
     if ((st = ensure(ws.iter_I, sizeof(double) * n_iter)) != MF_OK) return st;
     if ((st = ensure(ws.iter_V, sizeof(double) * n_iter)) != MF_OK) return st;
+    if ((st = ensure(ws.iter_pass, sizeof(double) * n_iter)) != MF_OK) return st;
     if ((st = ensure(ws.stats, sizeof(double) * 4)) != MF_OK) return st;
     if (grad) {
         if ((st = ensure(ws.gpartials, sizeof(double) * 4 * (size_t)n_waves)) != MF_OK) return st;
@@ -448,6 +449,7 @@ mf_status integrate_impl(const mf_process* proc, double sqrt_s, const mf_pdf_gri
     R.hist = R.entries + mf::kPartialHead;
     R.iter_I = (double*)ws.iter_I.ptr;
     R.iter_V = (double*)ws.iter_V.ptr;
+    R.iter_pass = (double*)ws.iter_pass.ptr;
     R.stats = (double*)ws.stats.ptr;
 
     // Optional per-kernel timing: events recorded on the stream around every
@@ -502,7 +504,8 @@ mf_status integrate_impl(const mf_process* proc, double sqrt_s, const mf_pdf_gri
         cur = 1 - cur;
     }
 
-    std::vector<double> I(n_iter), V(n_iter), stats(4), gs(grad ? 4 * (size_t)n_iter : 0);
+    std::vector<double> I(n_iter), V(n_iter), npass(n_iter), stats(4), gs(grad ? 4 * (size_t)n_iter : 0);
+    MF_HIP(hipMemcpyAsync(npass.data(), ws.iter_pass.ptr, sizeof(double) * n_iter, hipMemcpyDeviceToHost, S.stream));
     if (grad)
         MF_HIP(hipMemcpyAsync(gs.data(), ws.gsum.ptr, sizeof(double) * gs.size(), hipMemcpyDeviceToHost, S.stream));
     MF_HIP(hipMemcpyAsync(I.data(), ws.iter_I.ptr, sizeof(double) * n_iter, hipMemcpyDeviceToHost, S.stream));
@@ -523,6 +526,8 @@ mf_status integrate_impl(const mf_process* proc, double sqrt_s, const mf_pdf_gri
             MF_HIP(hipEventElapsedTime(&b, marks[3 * j + 1], marks[3 * j + 2]));
             res->event_kernel_ms += a;
             res->reduce_kernel_ms += b;
+            if (res->iter_event_ms)
+                res->iter_event_ms[j] = a;
         }
         for (auto& ev : marks)
             (void)hipEventDestroy(ev);
@@ -539,6 +544,8 @@ mf_status integrate_impl(const mf_process* proc, double sqrt_s, const mf_pdf_gri
         std::memcpy(res->iter_sigma, I.data(), sizeof(double) * n_iter);
     if (res->iter_var)
         std::memcpy(res->iter_var, V.data(), sizeof(double) * n_iter);
+    if (res->iter_pass)
+        std::memcpy(res->iter_pass, npass.data(), sizeof(double) * n_iter);
     if (grad) {
         // Per-iteration means of dw/dtheta on frozen grids, combined with the
         // inverse-variance weights of the estimate (V_j held fixed).
