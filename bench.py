@@ -75,7 +75,7 @@ def timed_run(api, torch, proc, pdf, n_events, steps, warmup, precision, seed):
 # Sources of the event kernel; HBM traffic measured with rocprofv3 counters is
 # reported only while their hash matches the one recorded with the counters.
 KERNEL_SOURCES = ("mf_kernels.hpp", "mf_device.hpp", "gen_amplitudes.py")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "event_kernel_traffic.txt")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "amp_kernel_gg_ttxgg_traffic.txt")
 
 
 def kernel_source_hash():
@@ -103,21 +103,33 @@ def measured_traffic(key):
     return int(float(vals[key]))
 
 
-def roofline(me_flops_event, other_flops_event, n_events, r, peak, traffic_key=None):
-    """Algorithmic flops of the timed event-kernel launches over their
-    HIP-event durations: the amplitude code runs only for events that pass
-    threshold and cuts (n_pass of each iteration), phase space, PDF and
-    accumulation for every event."""
-    t_s = float(np.sum(r.iter_event_ms)) / 1e3
-    launches = len(r.iter_event_ms)
-    flops = float(np.sum(r.iter_pass)) * me_flops_event + launches * n_events * other_flops_event
+def roofline(n_g, me_flops_event, other_flops_event, n_events, r, peak, traffic_key=None):
+    """Roofline of the dominant kernel over the timed iterations, from its
+    HIP-event durations recorded on the library's stream.  For n_g >= 3 that
+    is amp_kernel (helicity amplitudes and colour sum of the events that pass
+    threshold and cuts); for n_g = 2 the fused event kernel (amplitudes of the
+    passing events plus phase space, PDF and accumulation of all events)."""
+    launches = len(r.iter_event_ms) * (r.n_batches if n_g >= 3 else 1)
+    n_pass = float(np.sum(r.iter_pass))
+    if n_g >= 3:
+        t_s = float(np.sum(r.iter_amp_ms)) / 1e3
+        flops = n_pass * me_flops_event
+        kernel = "amp_kernel"
+    else:
+        t_s = float(np.sum(r.iter_event_ms)) / 1e3
+        flops = n_pass * me_flops_event + len(r.iter_event_ms) * n_events * other_flops_event
+        kernel = "event_kernel"
     achieved = flops / t_s / 1e12
+    t_all = float(np.sum(r.iter_event_ms)) / 1e3
+    all_flops = n_pass * me_flops_event + len(r.iter_event_ms) * n_events * other_flops_event
     return {"bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
             "frac": round(achieved / peak, 4),
             "traffic": measured_traffic(traffic_key) if traffic_key else None,
-            "kernel": "event_kernel", "avg_launch_ms": round(t_s * 1e3 / launches, 3),
-            "flops_per_passing_event": me_flops_event + other_flops_event,
-            "pass_fraction": round(float(np.sum(r.iter_pass)) / (launches * n_events), 4)}
+            "kernel": kernel, "launches": launches, "avg_launch_ms": round(t_s * 1e3 / launches, 3),
+            "flops_per_passing_event": me_flops_event if n_g >= 3 else me_flops_event + other_flops_event,
+            "pass_fraction": round(n_pass / (len(r.iter_event_ms) * n_events), 4),
+            "per_event_kernels": {"ms_per_iteration": round(t_all * 1e3 / len(r.iter_event_ms), 3),
+                                  "achieved_tflops": round(all_flops / t_all / 1e12, 3)}}
 
 
 def precision_error(api, torch, proc, pdf, grid, n, seed):
@@ -233,7 +245,7 @@ def main():
                    "process": wl["process"], "events_per_step": n_events, "cuts": wl["cuts"],
                    "sqrt_s_gev": 13000.0, "m_top": 173.0, "w_top": 1.5, "alpha_s": 0.118,
                    "seed": args.seed, "amplitude_precision": "fp64"},
-        "roofline": roofline(f_me, f_other, n_events, r64, PEAK_FP64_TFLOPS,
+        "roofline": roofline(wl["n_g"], f_me, f_other, n_events, r64, PEAK_FP64_TFLOPS,
                              f"{args.workload}_fp64_{n_events}"),
         "result_pb": {"sigma": r64.sigma, "sigma_err": r64.sigma_err, "chi2_dof": r64.chi2_dof},
         "stream_timed_s": round(ev64, 4),
@@ -250,7 +262,7 @@ def main():
         out["fp32_kahan"] = {
             "value": round(v32, 2), "unit": "events/s", "events_per_step": n32,
             "steps": args.fp32_steps, "ms_per_step": round(wall32 / args.fp32_steps * 1e3, 3),
-            "roofline": roofline(f_me, f_other, n32, r32, PEAK_FP32_TFLOPS,
+            "roofline": roofline(wl["n_g"], f_me, f_other, n32, r32, PEAK_FP32_TFLOPS,
                                  f"{args.workload}_fp32_{n32}"),
             "sigma": r32.sigma, "sigma_err": r32.sigma_err,
             "error_vs_fp64": err,

@@ -77,6 +77,8 @@ typedef struct {
     const double *grid_in;   /* host [D][n_bins+1] start grid, NULL = uniform   */
     void *stream;            /* hipStream_t or NULL                             */
     int profile;             /* 1: time every kernel with HIP events (0)        */
+    uint64_t max_batch;      /* n_g >= 3: events per batch of the per-event device
+                                buffers (about 170 B per event), 0 = 2^27 (0)   */
 } mf_options;
 
 typedef struct {
@@ -92,7 +94,10 @@ typedef struct {
     double event_kernel_ms;  /* profile = 1: summed event-kernel time, ms       */
     double reduce_kernel_ms; /* profile = 1: summed reduce/refine time, ms      */
     double *iter_pass;       /* host [n_iter] events passing threshold and cuts per iteration, may be NULL */
-    double *iter_event_ms;   /* host [n_iter] profile = 1: event-kernel time per iteration, ms, may be NULL */
+    double *iter_event_ms;   /* host [n_iter] profile = 1: time of the per-event kernels per iteration, ms, may be NULL */
+    double *iter_amp_ms;     /* host [n_iter] profile = 1: of which the helicity-amplitude code, ms, may be NULL
+                                (n_g >= 3 run it as a kernel of its own; for n_g = 2 it equals iter_event_ms) */
+    uint64_t n_batches;      /* event batches per iteration (n_g >= 3: up to 2^27 events each), else 1 */
 } mf_result;
 
 /* Fills *opt with the defaults shown above. */

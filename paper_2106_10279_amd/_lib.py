@@ -33,7 +33,8 @@ class mf_pdf_grid(C.Structure):
 class mf_options(C.Structure):
     _fields_ = [("n_bins", C.c_int), ("alpha", C.c_double), ("start_iter", C.c_int),
                 ("precision", C.c_int), ("strict", C.c_int), ("max_newton", C.c_int),
-                ("grid_in", _dp), ("stream", C.c_void_p), ("profile", C.c_int)]
+                ("grid_in", _dp), ("stream", C.c_void_p), ("profile", C.c_int),
+                ("max_batch", C.c_uint64)]
 
 
 class mf_result(C.Structure):
@@ -41,7 +42,8 @@ class mf_result(C.Structure):
                 ("w_max", C.c_double), ("iter_sigma", _dp), ("iter_var", _dp), ("grid", _dp),
                 ("hist", _dp), ("weights", _dp), ("n_pass", C.c_int64),
                 ("n_newton_fail", C.c_int64), ("event_kernel_ms", C.c_double),
-                ("reduce_kernel_ms", C.c_double), ("iter_pass", _dp), ("iter_event_ms", _dp)]
+                ("reduce_kernel_ms", C.c_double), ("iter_pass", _dp), ("iter_event_ms", _dp),
+                ("iter_amp_ms", _dp), ("n_batches", C.c_uint64)]
 
 
 class mf_grad_result(C.Structure):

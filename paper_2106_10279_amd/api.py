@@ -71,7 +71,8 @@ def n_dims(process) -> int:
     return lib.mf_n_dims(PROCESS_IDS[process])
 
 
-def _options(n_bins, alpha, start_iter, precision, strict, max_newton, grid_in, stream, profile=False):
+def _options(n_bins, alpha, start_iter, precision, strict, max_newton, grid_in, stream, profile=False,
+             max_batch=0):
     o = _lib.mf_options()
     lib.mf_default_options(C.byref(o))
     o.n_bins = n_bins
@@ -83,6 +84,7 @@ def _options(n_bins, alpha, start_iter, precision, strict, max_newton, grid_in, 
     o.grid_in = _ptr(grid_in) if grid_in is not None else None
     o.stream = _stream(stream)
     o.profile = int(profile)
+    o.max_batch = int(max_batch)
     return o
 
 
@@ -103,17 +105,20 @@ class IntegrationResult:
     reduce_kernel_ms: float = 0.0
     iter_pass: np.ndarray | None = None
     iter_event_ms: np.ndarray | None = None
+    iter_amp_ms: np.ndarray | None = None
+    n_batches: int = 1
 
 
 def integrate(proc: Process, sqrt_s: float, pdf_table, n_events: int, n_iter: int, seed: int,
               n_bins: int = 50, alpha: float = 1.5, precision="fp64", start_iter: int = 0,
               grid_in=None, keep_weights: bool = True, strict: bool = False,
               max_newton: int = 50, stream=None, weights_out: torch.Tensor | None = None,
-              profile: bool = False):
+              profile: bool = False, max_batch: int = 0):
     D = n_dims(proc.process)
     pdf = _Pdf(pdf_table)
     gin = None if grid_in is None else np.ascontiguousarray(grid_in, dtype=np.float64)
-    opt = _options(n_bins, alpha, start_iter, precision, strict, max_newton, gin, stream, profile)
+    opt = _options(n_bins, alpha, start_iter, precision, strict, max_newton, gin, stream, profile,
+                   max_batch)
     I = np.zeros(n_iter)
     V = np.zeros(n_iter)
     grid = np.zeros((D, n_bins + 1))
@@ -129,14 +134,17 @@ def integrate(proc: Process, sqrt_s: float, pdf_table, n_events: int, n_iter: in
     res.weights = C.cast(C.c_void_p(w.data_ptr()), _dp) if w is not None else None
     npass = np.zeros(n_iter)
     tms = np.zeros(n_iter)
+    ams = np.zeros(n_iter)
     res.iter_pass = _ptr(npass)
     res.iter_event_ms = _ptr(tms)
+    res.iter_amp_ms = _ptr(ams)
     pc = proc.c()
     check(lib.mf_integrate(C.byref(pc), sqrt_s, C.byref(pdf.c), n_events, n_iter, seed,
                            C.byref(opt), C.byref(res)))
     return IntegrationResult(res.sigma, res.sigma_err, res.chi2_dof, res.w_max, res.n_pass,
                              res.n_newton_fail, I, V, grid, hist, w, res.event_kernel_ms,
-                             res.reduce_kernel_ms, npass, tms if profile else None)
+                             res.reduce_kernel_ms, npass, tms if profile else None,
+                             ams if profile else None, res.n_batches)
 
 
 def evaluate_weights(proc: Process, sqrt_s: float, pdf_table, n: int, seed: int = 0, it: int = 0,

@@ -351,6 +351,109 @@ __device__ __forceinline__ double event_me2(const double* tab, T* obj, int h, do
     }
 }
 
+// Phase 1 of one event (one lane): Philox words or caller uniforms, integer
+// bins, the VEGAS map, threshold, phase space with the massive rescaling,
+// cuts and the two PDFs.  Returns the flags (bit 0 above threshold, bit 1
+// Newton failed, bit 2 passed the cuts).  For a passing event the momenta
+// and the beam energy go to mom[0 .. 4 NF] and pref = J_V W f1 f2 / (2 s_hat);
+// otherwise pref = 0 and mom is untouched.  bins[d * bin_stride] receives the
+// bin of dimension d; k53_out, bins_out and record of P are written if set.
+template <int NF>
+__device__ __forceinline__ int event_kinematics(const EventParams& P, uint64_t ev, const double* s_rows,
+                                                const double* s_lx, const double* s_lq, unsigned short* bins,
+                                                size_t bin_stride, double* mom, double& pref)
+{
+    constexpr int D = 2 + 3 * NF - 4;
+    const int nb = P.n_bins;
+    const uint32_t key0 = (uint32_t)P.seed, key1 = (uint32_t)(P.seed >> 32);
+    pref = 0.0;
+    double x[D];
+    double jac = 1.0;
+    if (P.y_in) {
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            const double y = P.y_in[ev * D + d];
+            const double t = y * (double)nb;
+            int b = (int)floor(t);
+            b = b > nb - 1 ? nb - 1 : (b < 0 ? 0 : b);
+            double jd;
+            x[d] = vegas_map_dim(P.grid + d * (nb + 1), b, t - (double)b, jd, nb);
+            jac = jac * jd;
+            bins[d * bin_stride] = (unsigned short)b;
+            if (P.bins_out)
+                P.bins_out[ev * D + d] = b;
+        }
+    } else {
+        const uint64_t eid = P.event_ids ? P.event_ids[ev] : ev;
+#pragma unroll
+        for (int blk = 0; blk < (D + 1) / 2; ++blk) {
+            uint32_t r[4];
+            philox4x32_10((uint32_t)eid, (uint32_t)(eid >> 32), P.iter, (uint32_t)blk, key0, key1, r);
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int d = 2 * blk + h;
+                if (d < D) {
+                    const uint64_t kk = ((((uint64_t)r[2 * h]) << 32) | (uint64_t)r[2 * h + 1]) >> 11;
+                    const uint64_t prod = kk * (uint64_t)nb;
+                    const int b = (int)(prod >> 53);
+                    const double delta = (double)(prod & ((1ull << 53) - 1)) * 0x1p-53;
+                    double jd;
+                    x[d] = vegas_map_dim(P.grid + d * (nb + 1), b, delta, jd, nb);
+                    jac = jac * jd;
+                    bins[d * bin_stride] = (unsigned short)b;
+                    if (P.k53_out)
+                        P.k53_out[ev * D + d] = kk;
+                    if (P.bins_out)
+                        P.bins_out[ev * D + d] = b;
+                }
+            }
+        }
+    }
+    const double x1 = x[0], x2 = x[1];
+    const double shat = x1 * x2 * P.sqrt_s * P.sqrt_s;
+    const double thr = 2.0 * P.m_top;
+    double* rec = P.record ? P.record + ev * (8 + 4 * NF) : nullptr;
+    double W = 0.0, f1 = 0.0, f2 = 0.0;
+    int flags = 0;
+    double k[NF][4];
+    if (shat > thr * thr) {
+        flags |= 1;
+        const double rs = sqrt(shat);
+        if (phase_space<NF>(x + 2, rs, P.m_top, P.max_newton, P.ps_const, k, W)) {
+            const double y_boost = 0.5 * log(x1 / x2);
+            if (pass_cuts<NF>(k, y_boost, P.ptmin, P.etamax, P.drmin)) {
+                flags |= 4;
+                f1 = pdf_xg(P, s_rows, s_lx, s_lq, x1) / x1;
+                f2 = pdf_xg(P, s_rows, s_lx, s_lq, x2) / x2;
+                pref = jac * W * f1 * f2 / (2.0 * shat);
+#pragma unroll
+                for (int i = 0; i < NF; ++i)
+#pragma unroll
+                    for (int mu = 0; mu < 4; ++mu)
+                        mom[4 * i + mu] = k[i][mu];
+                mom[4 * NF] = 0.5 * rs;
+            }
+        } else {
+            flags |= 2;
+        }
+    }
+    if (rec) {
+        rec[0] = x1;
+        rec[1] = x2;
+        rec[2] = jac;
+        rec[3] = W;
+        rec[4] = f1;
+        rec[5] = f2;
+        rec[7] = (double)flags;
+#pragma unroll
+        for (int i = 0; i < NF; ++i)
+#pragma unroll
+            for (int mu = 0; mu < 4; ++mu)
+                rec[8 + 4 * i + mu] = (flags & 1) && !(flags & 2) ? k[i][mu] : 0.0;
+    }
+    return flags;
+}
+
 template <int NG, typename T>
 __global__ void __launch_bounds__(kBlock) event_kernel(EventParams P)
 {
@@ -399,92 +502,11 @@ __global__ void __launch_bounds__(kBlock) event_kernel(EventParams P)
         double pref = 0.0;
         double* mom = s_mom[wv][lane];
         if (active) {
-            double x[D];
-            double jac = 1.0;
-            if (P.y_in) {
-#pragma unroll
-                for (int d = 0; d < D; ++d) {
-                    const double y = P.y_in[ev * D + d];
-                    const double t = y * (double)nb;
-                    int b = (int)floor(t);
-                    b = b > nb - 1 ? nb - 1 : (b < 0 ? 0 : b);
-                    double jd;
-                    x[d] = vegas_map_dim(P.grid + d * (nb + 1), b, t - (double)b, jd, nb);
-                    jac = jac * jd;
-                    s_bin[wv][d][lane] = (unsigned short)b;
-                    if (P.bins_out)
-                        P.bins_out[ev * D + d] = b;
-                }
-            } else {
-                const uint64_t eid = P.event_ids ? P.event_ids[ev] : ev;
-#pragma unroll
-                for (int blk = 0; blk < (D + 1) / 2; ++blk) {
-                    uint32_t r[4];
-                    philox4x32_10((uint32_t)eid, (uint32_t)(eid >> 32), P.iter, (uint32_t)blk, key0, key1, r);
-#pragma unroll
-                    for (int h = 0; h < 2; ++h) {
-                        const int d = 2 * blk + h;
-                        if (d < D) {
-                            const uint64_t kk = ((((uint64_t)r[2 * h]) << 32) | (uint64_t)r[2 * h + 1]) >> 11;
-                            const uint64_t prod = kk * (uint64_t)nb;
-                            const int b = (int)(prod >> 53);
-                            const double delta = (double)(prod & ((1ull << 53) - 1)) * 0x1p-53;
-                            double jd;
-                            x[d] = vegas_map_dim(P.grid + d * (nb + 1), b, delta, jd, nb);
-                            jac = jac * jd;
-                            s_bin[wv][d][lane] = (unsigned short)b;
-                            if (P.k53_out)
-                                P.k53_out[ev * D + d] = kk;
-                            if (P.bins_out)
-                                P.bins_out[ev * D + d] = b;
-                        }
-                    }
-                }
-            }
-            const double x1 = x[0], x2 = x[1];
-            const double shat = x1 * x2 * P.sqrt_s * P.sqrt_s;
-            const double thr = 2.0 * P.m_top;
-            double* rec = P.record ? P.record + ev * (8 + 4 * NF) : nullptr;
-            double W = 0.0, f1 = 0.0, f2 = 0.0;
-            int flags = 0;
-            double k[NF][4];
-            if (shat > thr * thr) {
-                flags |= 1;
-                const double rs = sqrt(shat);
-                if (phase_space<NF>(x + 2, rs, P.m_top, P.max_newton, P.ps_const, k, W)) {
-                    const double y_boost = 0.5 * log(x1 / x2);
-                    if (pass_cuts<NF>(k, y_boost, P.ptmin, P.etamax, P.drmin)) {
-                        flags |= 4;
-                        f1 = pdf_xg(P, s_rows, s_lx, s_lq, x1) / x1;
-                        f2 = pdf_xg(P, s_rows, s_lx, s_lq, x2) / x2;
-                        pref = jac * W * f1 * f2 / (2.0 * shat);
-#pragma unroll
-                        for (int i = 0; i < NF; ++i)
-#pragma unroll
-                            for (int mu = 0; mu < 4; ++mu)
-                                mom[4 * i + mu] = k[i][mu];
-                        mom[L::kMom - 1] = 0.5 * rs;
-                        npass += 1.0;
-                    }
-                } else {
-                    flags |= 2;
-                    nfail += 1.0;
-                }
-            }
-            if (rec) {
-                rec[0] = x1;
-                rec[1] = x2;
-                rec[2] = jac;
-                rec[3] = W;
-                rec[4] = f1;
-                rec[5] = f2;
-                rec[7] = (double)flags;
-#pragma unroll
-                for (int i = 0; i < NF; ++i)
-#pragma unroll
-                    for (int mu = 0; mu < 4; ++mu)
-                        rec[8 + 4 * i + mu] = (flags & 1) && !(flags & 2) ? k[i][mu] : 0.0;
-            }
+            const int flags = event_kinematics<NF>(P, ev, s_rows, s_lx, s_lq, &s_bin[wv][0][lane], kWave, mom, pref);
+            if (flags & 4)
+                npass += 1.0;
+            if (flags & 2)
+                nfail += 1.0;
         }
         s_pref[wv][lane] = pref;
         wave_sync();
@@ -575,6 +597,188 @@ __global__ void __launch_bounds__(kBlock) event_kernel(EventParams P)
         for (int i = lane; i < D * nb; i += kWave)
             out[(kPartialHead + i) * nw] = hist[i];
     }
+}
+
+// ---------------------------------------------------------------------------
+// Three-kernel form for the amplitude-heavy processes (g g -> t tbar g and
+// t tbar g g).  The fused event kernel needs phase 1's registers and LDS
+// (momenta of 64 events, PDF rows, histogram) next to the amplitude stages,
+// which leaves one wave per SIMD.  Here phase 1 and phase 3 run as their own
+// kernels and hand over per-event data through HBM (about 170 B per event),
+// and the amplitude kernel runs one wave per workgroup with only the table
+// and the object store in LDS, so several waves share each SIMD.  Per-event
+// values are those of the fused kernel, operation for operation.
+// ---------------------------------------------------------------------------
+struct StageParams {
+    EventParams P;           // forward parameters; P.n_waves = waves of kin/acc
+    uint64_t first, count;   // global index of the batch's first event, events in the batch
+    double* mom;             // [count][4 NF + 1] momenta and beam energy (passing events)
+    double* pref;            // [count] J_V W f1 f2 / (2 s_hat), 0 for rejected events
+    double* me;              // [count] sum over helicities and colours of |M|^2 (passing events)
+    unsigned short* bins;    // [D][count]
+    unsigned char* flags;    // [count] event_kinematics flags
+    int first_batch;         // acc: 1 = start the per-wave partials from zero
+};
+
+template <int NF>
+__global__ void __launch_bounds__(kBlock) kin_kernel(StageParams S)
+{
+    const EventParams& P = S.P;
+    __shared__ double s_lx[kMaxPdfX];
+    __shared__ double s_rows[4 * kMaxPdfX];
+    __shared__ double s_lq[4];
+    const int tid = threadIdx.x;
+    const int lane = tid % kWave;
+    const int wave_id = blockIdx.x * kWavesPerBlock + tid / kWave;
+    for (int i = tid; i < P.n_x; i += kBlock)
+        s_lx[i] = P.log_x[i];
+    for (int i = tid; i < P.q2_rows * P.n_x; i += kBlock)
+        s_rows[i] = P.xf[(size_t)P.q2_first * P.n_x + i];
+    if (tid < P.q2_rows)
+        s_lq[tid] = P.log_q2[P.q2_first + tid];
+    __syncthreads();
+    const uint64_t n_chunks = (S.count + kWave - 1) / kWave;
+    for (uint64_t chunk = wave_id; chunk < n_chunks; chunk += P.n_waves) {
+        const uint64_t e = chunk * kWave + lane;
+        if (e >= S.count)
+            continue;
+        double pref;
+        const int flags = event_kinematics<NF>(P, S.first + e, s_rows, s_lx, s_lq, S.bins + e, S.count,
+                                               S.mom + e * (4 * NF + 1), pref);
+        S.pref[e] = pref;
+        S.flags[e] = (unsigned char)flags;
+    }
+}
+
+// One wave per workgroup; a persistent loop over groups of events (one event
+// per pass for t tbar g g, two for t tbar g).  Groups without a passing event
+// are skipped whole.
+template <int NG, typename T>
+__global__ void __launch_bounds__(kWave) amp_kernel(StageParams S)
+{
+    using L = Layout<NG>;
+    __shared__ double s_tab[L::kEventsPerPass][L::kTable];
+    __shared__ T s_obj[L::kEventsPerPass][L::kObj];
+    const int lane = threadIdx.x;
+    const int h0 = lane % L::kHel;
+    const int sub = lane / L::kHel;
+    double* tab = s_tab[sub];
+    T* obj = s_obj[sub];
+    const uint64_t n_groups = (S.count + L::kEventsPerPass - 1) / L::kEventsPerPass;
+    for (uint64_t g = blockIdx.x; g < n_groups; g += gridDim.x) {
+        int h = h0;
+        asm volatile("" : "+v"(h));
+        const uint64_t e = g * L::kEventsPerPass + sub;
+        const bool live = e < S.count && S.pref[e] != 0.0;
+        const bool any_live = __any(live);
+        if (!any_live)
+            continue;
+        const double* m_e = S.mom + e * L::kMom;
+        if (live)
+            fill_table<NG>(m_e, m_e[L::kMom - 1], S.P.m_top, S.P.mw, tab, h);
+        wave_sync();
+        double v = event_me2<NG, T>(tab, obj, h, S.P.m_top, live, any_live);
+        v = group_sum(v, L::kHel);
+        if (h == 0 && live)
+            S.me[e] = v;
+        wave_sync();
+    }
+}
+
+// Phase 3 over a batch: weights, compensated sums, w_max, counts and the
+// deterministic lane-per-bin histogram, continuing each wave's partials
+// across the batches of an iteration.
+template <int NF>
+__global__ void __launch_bounds__(kBlock) acc_kernel(StageParams S)
+{
+    constexpr int D = 2 + 3 * NF - 4;
+    const EventParams& P = S.P;
+    __shared__ double s_w2[kWavesPerBlock][kWave];
+    __shared__ unsigned short s_bin[kWavesPerBlock][D][kWave];
+    extern __shared__ double s_hist[];     // [kWavesPerBlock][D][n_bins]
+    const int tid = threadIdx.x;
+    const int wv = tid / kWave;
+    const int lane = tid % kWave;
+    const int wave_id = blockIdx.x * kWavesPerBlock + wv;
+    const int nb = P.n_bins;
+    double* hist = s_hist + (size_t)wv * D * nb;
+    double* out = P.partials + wave_id;
+    const size_t nw = (size_t)P.n_waves;
+    Neumaier sw{0.0, 0.0}, sw2{0.0, 0.0};
+    double wmax = 0.0, npass = 0.0, nfail = 0.0;
+    if (S.first_batch) {
+        for (int i = lane; i < D * nb; i += kWave)
+            hist[i] = 0.0;
+    } else {
+        for (int i = lane; i < D * nb; i += kWave)
+            hist[i] = out[(kPartialHead + i) * nw];
+        if (lane == 0) {
+            sw = Neumaier{out[0 * nw], out[1 * nw]};
+            sw2 = Neumaier{out[2 * nw], out[3 * nw]};
+            wmax = out[4 * nw];
+            npass = out[5 * nw];
+            nfail = out[6 * nw];
+        }
+    }
+    wave_sync();
+    const uint64_t n_chunks = (S.count + kWave - 1) / kWave;
+    for (uint64_t chunk = wave_id; chunk < n_chunks; chunk += P.n_waves) {
+        const uint64_t e = chunk * kWave + lane;
+        const bool active = e < S.count;
+        double w = 0.0;
+        if (active) {
+            const double pref = S.pref[e];
+            const int flags = S.flags[e];
+            if (pref != 0.0)
+                w = pref * (S.me[e] * P.me_norm);
+            if (P.weights)
+                P.weights[S.first + e] = w;
+            nm_add(sw, w);
+            nm_add(sw2, w * w);
+            wmax = fmax(wmax, w);
+            npass += (flags & 4) ? 1.0 : 0.0;
+            nfail += (flags & 2) ? 1.0 : 0.0;
+        }
+        s_w2[wv][lane] = active ? w * w : 0.0;
+#pragma unroll
+        for (int d = 0; d < D; ++d)
+            s_bin[wv][d][lane] = active ? S.bins[(size_t)d * S.count + e] : (unsigned short)0;
+        wave_sync();
+        for (int b = lane; b < nb; b += kWave) {
+            for (int d = 0; d < D; ++d) {
+                double acc = hist[d * nb + b];
+                for (int q = 0; q < kWave; ++q)
+                    if (s_bin[wv][d][q] == b)
+                        acc += s_w2[wv][q];
+                hist[d * nb + b] = acc;
+            }
+        }
+        wave_sync();
+    }
+    for (int off = kWave >> 1; off > 0; off >>= 1) {
+        Neumaier o1{__shfl_down(sw.s, off), __shfl_down(sw.c, off)};
+        Neumaier o2{__shfl_down(sw2.s, off), __shfl_down(sw2.c, off)};
+        const double om = __shfl_down(wmax, off);
+        const double op = __shfl_down(npass, off);
+        const double of = __shfl_down(nfail, off);
+        sw = nm_merge(sw, o1);
+        sw2 = nm_merge(sw2, o2);
+        wmax = fmax(wmax, om);
+        npass += op;
+        nfail += of;
+    }
+    if (lane == 0) {
+        out[0 * nw] = sw.s;
+        out[1 * nw] = sw.c;
+        out[2 * nw] = sw2.s;
+        out[3 * nw] = sw2.c;
+        out[4 * nw] = wmax;
+        out[5 * nw] = npass;
+        out[6 * nw] = nfail;
+        out[7 * nw] = 0.0;
+    }
+    for (int i = lane; i < D * nb; i += kWave)
+        out[(kPartialHead + i) * nw] = hist[i];
 }
 
 // ---------------------------------------------------------------------------

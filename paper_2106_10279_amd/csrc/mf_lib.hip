@@ -59,9 +59,14 @@ struct Buffer {
     size_t bytes = 0;
 };
 
+// Events per batch of the three-kernel form (per-event buffers of about
+// 170 B for t tbar g g: 23 GB at the cap, sized for a 288 GB device).
+constexpr uint64_t kStageBatch = 1ull << 27;
+
 struct Workspace {
     std::mutex lock;
     Buffer grid[2], log_x, log_q2, xf, partials, entries, iter_I, iter_V, iter_pass, stats, gpartials, gsum;
+    Buffer st_mom, st_pref, st_me, st_bins, st_flags;   // per-event hand-over of the three-kernel form
     int n_cu = 0;
 };
 
@@ -166,6 +171,8 @@ mf_status validate_options(const mf_options* opt, int D)
         return fail(MF_EINVAL, "alpha must be finite and > 0");
     if (opt->precision != MF_FP64 && opt->precision != MF_FP32_KAHAN)
         return fail(MF_EINVAL, "unknown precision");
+    if (opt->max_batch > kStageBatch)
+        return fail(MF_EINVAL, "max_batch must be at most 2^27");
     if (opt->max_newton < 0 || opt->max_newton > 1000)
         return fail(MF_EINVAL, "max_newton must be in [0, 1000]");
     if (opt->start_iter < 0)
@@ -252,6 +259,56 @@ mf_status dispatch_event(int ng, mf_precision prec, const mf::EventParams& P, in
     case 3: return f32 ? launch_event<3, float>(P, blocks, s) : launch_event<3, double>(P, blocks, s);
     default: return f32 ? launch_event<4, float>(P, blocks, s) : launch_event<4, double>(P, blocks, s);
     }
+}
+
+// Amplitude-kernel workgroups (one wave each) for the persistent loop: as
+// many as can be resident at once, so that every workgroup runs from start to
+// end alongside all the others (the groups of events are assigned statically).
+template <int NG, typename T>
+mf_status amp_grid_for(uint64_t n_groups, int n_cu, int* grid)
+{
+    int per_cu = 0;
+    MF_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, mf::amp_kernel<NG, T>, mf::kWave, 0));
+    if (per_cu < 1)
+        per_cu = 1;
+    const uint64_t cap = (uint64_t)n_cu * per_cu;
+    *grid = (int)(n_groups < cap ? (n_groups < 1 ? 1 : n_groups) : cap);
+    return MF_OK;
+}
+
+template <int NG, typename T>
+mf_status launch_stages(const mf::StageParams& S, int kin_blocks, int n_cu, hipStream_t stream,
+                        hipEvent_t amp_begin, hipEvent_t amp_end)
+{
+    constexpr int D = 2 + 3 * NG - 4;
+    int amp_grid = 1;
+    mf_status st = amp_grid_for<NG, T>((S.count + mf::Layout<NG>::kEventsPerPass - 1) / mf::Layout<NG>::kEventsPerPass,
+                                       n_cu, &amp_grid);
+    if (st != MF_OK)
+        return st;
+    hipLaunchKernelGGL((mf::kin_kernel<NG>), dim3(kin_blocks), dim3(mf::kBlock), 0, stream, S);
+    MF_HIP(hipGetLastError());
+    if (amp_begin)
+        MF_HIP(hipEventRecord(amp_begin, stream));
+    hipLaunchKernelGGL((mf::amp_kernel<NG, T>), dim3(amp_grid), dim3(mf::kWave), 0, stream, S);
+    MF_HIP(hipGetLastError());
+    if (amp_end)
+        MF_HIP(hipEventRecord(amp_end, stream));
+    const size_t dyn = sizeof(double) * mf::kWavesPerBlock * D * S.P.n_bins;
+    hipLaunchKernelGGL((mf::acc_kernel<NG>), dim3(kin_blocks), dim3(mf::kBlock), dyn, stream, S);
+    MF_HIP(hipGetLastError());
+    return MF_OK;
+}
+
+mf_status dispatch_stages(int ng, mf_precision prec, const mf::StageParams& S, int kin_blocks, int n_cu,
+                          hipStream_t s, hipEvent_t a, hipEvent_t b)
+{
+    const bool f32 = prec == MF_FP32_KAHAN;
+    if (ng == 3)
+        return f32 ? launch_stages<3, float>(S, kin_blocks, n_cu, s, a, b)
+                   : launch_stages<3, double>(S, kin_blocks, n_cu, s, a, b);
+    return f32 ? launch_stages<4, float>(S, kin_blocks, n_cu, s, a, b)
+               : launch_stages<4, double>(S, kin_blocks, n_cu, s, a, b);
 }
 
 mf_status device_workspace(Workspace** out)
@@ -352,6 +409,7 @@ void mf_default_options(mf_options* opt)
     opt->grid_in = nullptr;
     opt->stream = nullptr;
     opt->profile = 0;
+    opt->max_batch = 0;
 }
 
 int mf_n_dims(int process_id)
@@ -417,6 +475,18 @@ mf_status integrate_impl(const mf_process* proc, double sqrt_s, const mf_pdf_gri
     if ((st = ensure(ws.iter_V, sizeof(double) * n_iter)) != MF_OK) return st;
     if ((st = ensure(ws.iter_pass, sizeof(double) * n_iter)) != MF_OK) return st;
     if ((st = ensure(ws.stats, sizeof(double) * 4)) != MF_OK) return st;
+    const bool staged = ng >= 3;
+    const uint64_t cap = opt->max_batch ? opt->max_batch : kStageBatch;
+    const uint64_t batch = n_events < cap ? n_events : cap;
+    const uint64_t n_batches = (n_events + batch - 1) / batch;
+    if (staged) {
+        const int nf = ng;
+        if ((st = ensure(ws.st_mom, sizeof(double) * (4 * nf + 1) * batch)) != MF_OK) return st;
+        if ((st = ensure(ws.st_pref, sizeof(double) * batch)) != MF_OK) return st;
+        if ((st = ensure(ws.st_me, sizeof(double) * batch)) != MF_OK) return st;
+        if ((st = ensure(ws.st_bins, sizeof(unsigned short) * D * batch)) != MF_OK) return st;
+        if ((st = ensure(ws.st_flags, batch)) != MF_OK) return st;
+    }
     if (grad) {
         if ((st = ensure(ws.gpartials, sizeof(double) * 4 * (size_t)n_waves)) != MF_OK) return st;
         if ((st = ensure(ws.gsum, sizeof(double) * 4 * (size_t)n_iter)) != MF_OK) return st;
@@ -454,11 +524,16 @@ mf_status integrate_impl(const mf_process* proc, double sqrt_s, const mf_pdf_gri
 
     // Optional per-kernel timing: events recorded on the stream around every
     // launch (marks[3j] .. marks[3j+2]).
-    std::vector<hipEvent_t> marks;
+    std::vector<hipEvent_t> marks, amp_marks;
     if (opt->profile) {
         marks.resize(3 * (size_t)n_iter);
         for (auto& ev : marks)
             MF_HIP(hipEventCreate(&ev));
+        if (staged) {
+            amp_marks.resize(2 * (size_t)n_iter * n_batches);
+            for (auto& ev : amp_marks)
+                MF_HIP(hipEventCreate(&ev));
+        }
     }
     int cur = 0;
     for (int j = 0; j < n_iter; ++j) {
@@ -467,8 +542,30 @@ mf_status integrate_impl(const mf_process* proc, double sqrt_s, const mf_pdf_gri
         P.weights = (j == n_iter - 1) ? res->weights : nullptr;
         if (opt->profile)
             MF_HIP(hipEventRecord(marks[3 * j], S.stream));
-        if ((st = dispatch_event(ng, opt->precision, P, n_waves / mf::kWavesPerBlock, S.stream)) != MF_OK)
+        if (staged) {
+            for (uint64_t bi = 0; bi < n_batches; ++bi) {
+                mf::StageParams SP;
+                SP.P = P;
+                SP.first = bi * batch;
+                SP.count = (bi + 1 == n_batches) ? n_events - SP.first : batch;
+                SP.mom = (double*)ws.st_mom.ptr;
+                SP.pref = (double*)ws.st_pref.ptr;
+                SP.me = (double*)ws.st_me.ptr;
+                SP.bins = (unsigned short*)ws.st_bins.ptr;
+                SP.flags = (unsigned char*)ws.st_flags.ptr;
+                SP.first_batch = bi == 0;
+                hipEvent_t a = nullptr, b = nullptr;
+                if (opt->profile) {
+                    a = amp_marks[2 * ((size_t)j * n_batches + bi)];
+                    b = amp_marks[2 * ((size_t)j * n_batches + bi) + 1];
+                }
+                if ((st = dispatch_stages(ng, opt->precision, SP, n_waves / mf::kWavesPerBlock, ws.n_cu, S.stream, a,
+                                          b)) != MF_OK)
+                    return st;
+            }
+        } else if ((st = dispatch_event(ng, opt->precision, P, n_waves / mf::kWavesPerBlock, S.stream)) != MF_OK) {
             return st;
+        }
         if (grad) {
             mf::GradParams G;
             G.P = P;
@@ -528,8 +625,22 @@ mf_status integrate_impl(const mf_process* proc, double sqrt_s, const mf_pdf_gri
             res->reduce_kernel_ms += b;
             if (res->iter_event_ms)
                 res->iter_event_ms[j] = a;
+            double amp = a;
+            if (staged) {
+                amp = 0.0;
+                for (uint64_t bi = 0; bi < n_batches; ++bi) {
+                    float c = 0.f;
+                    MF_HIP(hipEventElapsedTime(&c, amp_marks[2 * ((size_t)j * n_batches + bi)],
+                                               amp_marks[2 * ((size_t)j * n_batches + bi) + 1]));
+                    amp += c;
+                }
+            }
+            if (res->iter_amp_ms)
+                res->iter_amp_ms[j] = amp;
         }
         for (auto& ev : marks)
+            (void)hipEventDestroy(ev);
+        for (auto& ev : amp_marks)
             (void)hipEventDestroy(ev);
     }
 
@@ -538,6 +649,7 @@ mf_status integrate_impl(const mf_process* proc, double sqrt_s, const mf_pdf_gri
                                     std::to_string((long long)stats[2]) + " events");
     combine(n_iter, I.data(), V.data(), &res->sigma, &res->sigma_err, &res->chi2_dof);
     res->w_max = stats[0];
+    res->n_batches = staged ? n_batches : 1;
     res->n_pass = (int64_t)stats[1];
     res->n_newton_fail = (int64_t)stats[2];
     if (res->iter_sigma)

@@ -107,3 +107,12 @@ def test_gradient_rejects_fp32_without_device(L, pdf_table):
                                  C.byref(res), C.byref(g))
     assert st == L.MF_EUNSUPPORTED
     assert b"FP64" in L.lib.mf_last_error()
+
+
+def test_max_batch_above_the_cap_rejected_without_device(L, pdf_table):
+    from paper_2106_10279_amd import api
+    with pytest.raises(L.MFError) as e:
+        api.integrate(api.Process("gg_ttxgg"), 13000.0, pdf_table, 1000, 1, 0, keep_weights=False,
+                      stream=0, max_batch=(1 << 27) + 1)
+    assert e.value.status == L.MF_EINVAL
+    assert b"max_batch" in L.lib.mf_last_error()

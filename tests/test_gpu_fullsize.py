@@ -1,0 +1,91 @@
+"""Parity at the full workload sizes, in the launch configuration bench.py
+times: g g -> t tbar g g at 1e7 events per iteration (FP64) and 1e8 (FP32
+amplitudes).  The oracle cannot replay every event, so sampled event indices
+spread over the whole range are recomputed one by one with the GPU's grid of
+that iteration (counter-based Philox makes any event reachable), and
+properties that hold at any size are checked on all events."""
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+SQRT_S = 13000.0
+
+
+@pytest.fixture(scope="module")
+def api():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2106_10279_amd import api as A
+    return A
+
+
+def _cuts():
+    return dict(ptmin_g=20.0, drmin_gg=0.4)
+
+
+def _spot_check(api, oracle_lib, pdf_table, w_gpu, grid, it, n, k, seed, rtol):
+    O = oracle_lib
+    rng = np.random.default_rng(seed)
+    ids = np.sort(rng.choice(n, size=k, replace=False))
+    op = O.Process(n_g=4, **_cuts())
+    worst, used, skipped = 0.0, 0, 0
+    w_gpu = w_gpu[ids].cpu().numpy()
+    for e, wg in zip(ids, w_gpu):
+        w_o, info = O.event_weight(op, SQRT_S, pdf_table, grid, 0, it, int(e))
+        if info.near_edge or info.ill_conditioned:
+            skipped += 1
+            continue
+        if w_o == 0.0:
+            assert wg == 0.0, (e, wg)
+            continue
+        worst = max(worst, abs(wg / w_o - 1.0))
+        used += 1
+    return worst, used, skipped, ids
+
+
+def test_ttxgg_fp64_1e7_sampled_events_and_properties(api, oracle_lib, pdf_table):
+    import torch
+    proc = api.Process("gg_ttxgg", **_cuts())
+    N = 10_000_000
+    # grid of iteration 1 (after one refinement), then iteration 1 itself
+    g1 = api.integrate(proc, SQRT_S, pdf_table, N, 1, 0, keep_weights=False).grid
+    r = api.integrate(proc, SQRT_S, pdf_table, N, 2, 0, keep_weights=True)
+    w = r.weights
+    assert torch.isfinite(w).all() and (w >= 0).all()
+    nz = int((w != 0).sum())
+    assert nz == r.n_pass
+    mean = float(w.sum().item()) / N
+    assert mean == pytest.approx(r.iter_sigma[-1], rel=1e-12)
+    worst, used, skipped, ids = _spot_check(api, oracle_lib, pdf_table, w, g1, 1, N, 96, 21, 1e-12)
+    print(f"\n  1e7 FP64: {used} sampled events up to id {ids.max()}, max rel {worst:.2e}, "
+          f"{skipped} at a cut edge or ill-conditioned; n_pass {nz}")
+    assert used > 40
+    assert worst < 1e-12
+
+
+def test_ttxgg_fp32_1e8_sampled_events_and_integral(api, oracle_lib, pdf_table):
+    """The FP32-amplitude form at 1e8 events: sampled events against the FP64
+    oracle at FP32 tolerance, and the integral against the FP64 GPU path on the
+    same 1e8 events and grid (target <= 1e-6)."""
+    import torch
+    proc = api.Process("gg_ttxgg", **_cuts())
+    N = 100_000_000
+    grid = api.integrate(proc, SQRT_S, pdf_table, 10_000_000, 2, 0, keep_weights=False).grid
+    w32 = api.evaluate_weights(proc, SQRT_S, pdf_table, N, seed=0, it=0, grid=grid, precision="fp32_kahan")
+    assert torch.isfinite(w32).all() and (w32 >= 0).all()
+    worst, used, skipped, ids = _spot_check(api, oracle_lib, pdf_table, w32, grid, 0, N, 64, 22, 1e-4)
+    print(f"\n  1e8 FP32: {used} sampled events up to id {ids.max()}, max rel vs FP64 oracle {worst:.2e}")
+    assert used > 25
+    assert worst < 2e-4
+    I32 = float(w32.sum().item())
+    del w32
+    torch.cuda.empty_cache()
+    w64 = api.evaluate_weights(proc, SQRT_S, pdf_table, N, seed=0, it=0, grid=grid)
+    I64 = float(w64.sum().item())
+    del w64
+    torch.cuda.empty_cache()
+    print(f"  integral FP32 vs FP64 over 1e8 events: rel {abs(I32 / I64 - 1):.2e}")
+    assert abs(I32 / I64 - 1.0) < 1e-6

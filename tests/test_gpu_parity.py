@@ -217,3 +217,30 @@ def test_newton_failure_counted_and_strict(api, pdf_table):
     with pytest.raises(_lib.MFError) as e:
         api.integrate(gproc(api, 3), SQRT_S, pdf_table, 1000, 1, seed=0, max_newton=0, strict=True)
     assert e.value.status == _lib.MF_ENOCONV
+
+
+@pytest.mark.parametrize("n_g", [3, 4])
+def test_three_kernel_integration_weights_equal_the_fused_kernel(api, pdf_table, n_g):
+    """For t tbar g and t tbar g g the integration runs phase space, amplitudes
+    and accumulation as three kernels; its per-event weights are bit for bit
+    those of the fused event kernel (mf_evaluate) on the same events and grid,
+    also when the iteration is split into many batches."""
+    import torch
+    proc = api.Process({3: "gg_ttxg", 4: "gg_ttxgg"}[n_g], ptmin_g=20.0,
+                       etamax_g=2.5 if n_g == 3 else 0.0, drmin_gg=0.4 if n_g == 4 else 0.0)
+    N = 5000
+    g1 = api.integrate(proc, SQRT_S, pdf_table, N, 1, 0, keep_weights=False).grid
+    r = api.integrate(proc, SQRT_S, pdf_table, N, 2, 0, keep_weights=True)
+    assert r.n_batches == 1
+    w_fused = api.evaluate_weights(proc, SQRT_S, pdf_table, N, seed=0, it=1, grid=g1)
+    assert torch.equal(r.weights, w_fused)
+    # many batches: same events, sums continued across batches in another order
+    r1 = api.integrate(proc, SQRT_S, pdf_table, N, 1, 0, keep_weights=True)
+    rb = api.integrate(proc, SQRT_S, pdf_table, N, 1, 0, keep_weights=True, max_batch=777)
+    assert rb.n_batches == (N + 776) // 777
+    assert torch.equal(rb.weights, r1.weights)
+    assert rb.iter_sigma[0] == pytest.approx(r1.iter_sigma[0], rel=1e-13)
+    assert rb.iter_var[0] == pytest.approx(r1.iter_var[0], rel=1e-11)
+    assert np.allclose(rb.hist, r1.hist, rtol=1e-13, atol=0)
+    assert np.allclose(rb.grid, r1.grid, rtol=0, atol=1e-13)
+    assert rb.n_pass == r1.n_pass
