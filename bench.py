@@ -168,14 +168,20 @@ def adjoint_run(api, torch, pdf, n_events, n_iter, seed):
 
 
 def cpu_baseline(wl, pdf, budget_s):
+    """The oracle on a bounded sample of the same workload: one iteration on a
+    uniform grid, sized by two calibration runs to about budget_s seconds."""
     import oracle as O
     threads = max(1, min(os.cpu_count() or 1, 16))
     proc = O.Process(n_g=wl["n_g"], **wl["cuts"])
-    n0 = 8 * threads
-    t0 = time.perf_counter()
-    O.integrate(proc, 13000.0, pdf, n0, 1, 0, n_threads=threads, keep_weights=False)
-    dt = time.perf_counter() - t0
-    n = max(n0, int(n0 * budget_s / max(dt, 1e-3)))
+    n = 8 * threads
+    for _ in range(2):
+        t0 = time.perf_counter()
+        O.integrate(proc, 13000.0, pdf, n, 1, 0, n_threads=threads, keep_weights=False)
+        dt = time.perf_counter() - t0
+        if dt > 0.3 * budget_s:
+            break
+        n = max(n, int(n * 0.5 * budget_s / max(dt, 1e-3)))
+    n = max(n, int(n * budget_s / max(dt, 1e-3)))
     t0 = time.perf_counter()
     O.integrate(proc, 13000.0, pdf, n, 1, 0, n_threads=threads, keep_weights=False)
     dt = time.perf_counter() - t0
