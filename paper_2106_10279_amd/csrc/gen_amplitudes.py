@@ -126,6 +126,129 @@ class Layout:
         self.size = off
 
 
+class CoopTable:
+    """Per-event table of the cooperative evaluation (n >= 3), in units of the
+    amplitude type: subset momenta P[m] (1 <= |m| <= n-1), -1/P[m]^2
+    (2 <= |m| <= n), the top-line momenta and propagator factors of single
+    gluons K[g] = k_t + p_g, the antitop-line ones Kv[m] (1 <= |m| <= n-2),
+    ubar and v for both spins.  The gluon polarisation vectors go straight
+    into the level-1 currents of the object store."""
+
+    def __init__(self, n):
+        self.n = n
+        off = 0
+        self.P = {}
+        for m in range(1, 1 << n):
+            if bin(m).count("1") <= n - 1:
+                self.P[m] = off
+                off += 4
+        self.ninv = {}
+        for m in range(1, 1 << n):
+            if bin(m).count("1") >= 2:
+                self.ninv[m] = off
+                off += 1
+        self.K1 = {}
+        for g in range(n):
+            self.K1[g] = off           # K[0..3], fr, fi
+            off += 6
+        self.Kv = {}
+        for m in range(1, 1 << n):
+            if 1 <= bin(m).count("1") <= n - 2:
+                self.Kv[m] = off       # -k_tbar - P[m], and -1/(Kv^2 - m^2 + i m Gamma)
+                off += 6
+        self.ub = off
+        off += 16
+        self.v = off
+        off += 16
+        self.size = off
+
+    def mom_flops(self):
+        n = self.n
+        return (sum(4 * (bin(m).count("1") - 1) for m in range(1, 1 << n)) + 8 * len(self.ninv)
+                + 17 * (len(self.K1) + len(self.Kv)) + 4 * 24 + (n - 2) * 2 * 16 + 2)
+
+
+def emit_coop_fill(n, tl, co):
+    """Fill of the cooperative table by the lanes of one event: lane m
+    (1 .. 2^n - 1) handles subset m, the next four the spinors, lane 0 the
+    incoming polarisations, the following ones the outgoing ones (written as
+    level-1 gluon currents j(g; h) = eps_g(h) into the object store)."""
+    L = []
+    w = L.append
+    nsub = (1 << n) - 1
+    w("    const double m2 = mt * mt;")
+    w(f"    if (lane >= 1 && lane <= {nsub}) {{")
+    w("        const int m = lane;")
+    w("        double P0 = 0.0, P1 = 0.0, P2 = 0.0, P3 = 0.0;")
+    for g in range(n):
+        if g == 0:
+            pv = ["-eb", "0.0", "0.0", "-eb"]
+        elif g == 1:
+            pv = ["-eb", "0.0", "0.0", "eb"]
+        else:
+            pv = [f"mom[{8 + 4 * (g - 2) + mu}]" for mu in range(4)]
+        w(f"        if (m & {1 << g}) {{ P0 += {pv[0]}; P1 += {pv[1]}; P2 += {pv[2]}; P3 += {pv[3]}; }}")
+    p_off = ", ".join(str(tl.P.get(m, -1)) for m in range(1, 1 << n))
+    w(f"        const short p_off[{nsub}] = {{{p_off}}};")
+    w("        if (p_off[m - 1] >= 0) {")
+    w("            T* o = tab + p_off[m - 1];")
+    w("            o[0] = (T)P0; o[1] = (T)P1; o[2] = (T)P2; o[3] = (T)P3;")
+    w("        }")
+    ninv_offsets = ", ".join(str(tl.ninv.get(m, -1)) for m in range(1, 1 << n))
+    w(f"        const short ninv_off[{nsub}] = {{{ninv_offsets}}};")
+    w("        if (ninv_off[m - 1] >= 0)")
+    w("            tab[ninv_off[m - 1]] = (T)(-1.0 / (P0 * P0 - P1 * P1 - P2 * P2 - P3 * P3));")
+    k_offsets = ", ".join(str(tl.K1[(m.bit_length() - 1)]) if bin(m).count("1") == 1 else "-1"
+                          for m in range(1, 1 << n))
+    w(f"        const short k_off[{nsub}] = {{{k_offsets}}};")
+    w("        if (k_off[m - 1] >= 0) {")
+    w("            const double K0 = mom[0] + P0, K1 = mom[1] + P1, K2 = mom[2] + P2, K3 = mom[3] + P3;")
+    w("            const double re = K0 * K0 - K1 * K1 - K2 * K2 - K3 * K3 - m2;")
+    w("            const double inv = 1.0 / (re * re + mw * mw);")
+    w("            T* k = tab + k_off[m - 1];")
+    w("            k[0] = (T)K0; k[1] = (T)K1; k[2] = (T)K2; k[3] = (T)K3;")
+    w("            k[4] = (T)(-re * inv);")
+    w("            k[5] = (T)(mw * inv);")
+    w("        }")
+    kv_offsets = ", ".join(str(tl.Kv.get(m, -1)) for m in range(1, 1 << n))
+    w(f"        const short kv_off[{nsub}] = {{{kv_offsets}}};")
+    w("        if (kv_off[m - 1] >= 0) {")
+    w("            const double K0 = -mom[4] - P0, K1 = -mom[5] - P1, K2 = -mom[6] - P2, K3 = -mom[7] - P3;")
+    w("            const double re = K0 * K0 - K1 * K1 - K2 * K2 - K3 * K3 - m2;")
+    w("            const double inv = 1.0 / (re * re + mw * mw);")
+    w("            T* k = tab + kv_off[m - 1];")
+    w("            k[0] = (T)K0; k[1] = (T)K1; k[2] = (T)K2; k[3] = (T)K3;")
+    w("            k[4] = (T)(-re * inv);")
+    w("            k[5] = (T)(mw * inv);")
+    w("        }")
+    w("    }")
+    w(f"    if (lane >= {nsub + 1} && lane < {nsub + 5}) {{")
+    w(f"        const int t = lane - {nsub + 1};     // 0, 1: ubar spins; 2, 3: v spins")
+    w("        cplx<double> sp[4];")
+    w("        if (t < 2)")
+    w("            spinor_ubar<double>(mom, mt, t, sp);")
+    w("        else")
+    w("            spinor_v<double>(mom + 4, mt, t - 2, sp);")
+    w(f"        T* o = tab + (t < 2 ? {tl.ub} + 8 * t : {tl.v} + 8 * (t - 2));")
+    w("        for (int i = 0; i < 4; ++i) { o[2 * i] = (T)sp[i].x; o[2 * i + 1] = (T)sp[i].y; }")
+    w("    }")
+    # incoming gluons along the beams: (0, 1, 0, 0) and (0, 0, 1, 0)
+    w("    if (lane == 0) {")
+    w(f"        T* o = obj + {co.gj};")
+    w("        for (int i = 0; i < 16; ++i) o[i] = (T)0;")
+    w("        o[1] = (T)1; o[6] = (T)1; o[9] = (T)1; o[14] = (T)1;")
+    w("    }")
+    w(f"    if (lane >= {nsub + 5} && lane < {nsub + 5 + 2 * (n - 2)}) {{")
+    w(f"        const int t = lane - {nsub + 5};")
+    w("        const int g = 2 + t / 2, h = t & 1;")
+    w("        double e[4];")
+    w("        linear_pol<double>(mom + 8 + 4 * (g - 2), h, e);")
+    w(f"        T* o = obj + {co.gj} + 4 * (2 * g + h);")
+    w("        for (int mu = 0; mu < 4; ++mu) o[mu] = (T)e[mu];")
+    w("    }")
+    return "\n".join(L)
+
+
 class Emitter:
     # Flop accounting (+, -, x = 1; fused multiply-add = 2; sqrt and divide
     # = 1 each): `hel` counts the arithmetic that depends on the helicity
@@ -329,6 +452,21 @@ def emit_table_fill(n, lay):
 
 def generate(n):
     perms, K, den = colour_matrix(n)
+    global _LAST_COUNT
+    if n >= 3:
+        # cooperative evaluation only: table, object store and helicity lanes
+        nperm = len(perms)
+        coop_text = generate_coop(n)
+        _LAST_COUNT = {"per_helicity": _COOP_COUNT["per_helicity"],
+                       "momentum_only": _COOP_COUNT["momentum_only"], "n_hel": 1 << (n + 2),
+                       "n_orderings": nperm, "table_doubles": _COOP_COUNT["table"]}
+        kdecl = ", ".join(str(v) for row in K for v in row)
+        return f"""// Generated by gen_amplitudes.py for g g -> t tbar + {n - 2} gluon(s): {nperm} colour orderings,
+// {1 << (n + 2)} helicity configurations.  Do not edit.
+static constexpr int NPERM_NG{n} = {nperm};
+static constexpr double COLOUR_DEN_NG{n} = {den}.0;
+static constexpr int COLOUR_NUM_NG{n}[{nperm * nperm}] = {{{kdecl}}};
+{coop_text}"""
     lay = Layout(n)
     e = Emitter(n, lay)
     nperm = len(perms)
@@ -382,15 +520,13 @@ def generate(n):
         + (4 + 8 + 3 + 2) * len(lay.K) + 4 * 24 + (n - 2) * 2 * 16 + 2
     body = "\n".join(e.lines)
     fill = emit_table_fill(n, lay)
-    global _LAST_COUNT
     _LAST_COUNT = {"per_helicity": e.hel, "momentum_only": e.mom, "n_hel": 1 << (n + 2),
                    "n_orderings": nperm, "table_doubles": lay.size}
     kdecl = ", ".join(str(v) for row in K for v in row)
-    coop_text = generate_coop(n) if n >= 3 else ""
     structs = """
 struct GPair { int b1, b2; signed char s1, s2, m1, m2; short p1, p2; };
 struct GTrip { int b1, b2, b3; signed char s1, s2, s3, m1, m2, m3; };
-""" if n == 2 else ""
+"""
     return f"""// Generated by gen_amplitudes.py for g g -> t tbar + {n - 2} gluon(s): {nperm} colour orderings,
 // {1 << (n + 2)} helicity configurations.  Do not edit.
 // Arithmetic per helicity configuration: {e.hel} flops; per event (table): {e.mom} flops.
@@ -422,7 +558,7 @@ __device__ __forceinline__ double colour_summed_me2_ng{n}(const double* __restri
 {body}
     return (double)me / COLOUR_DEN_NG{n};
 }}
-{structs}{coop_text}"""
+{structs}"""
 
 
 
@@ -479,6 +615,7 @@ def posmask(part, whole):
 
 
 def emit_coop(n, lay, co, K, perms):
+    # lay: CoopTable (offsets in units of T)
     L_ = []
     w = L_.append
     flops_stage = 0
@@ -524,20 +661,14 @@ def emit_coop(n, lay, co, K, perms):
         tables.append(f"static constexpr signed char V2_{n}_JS[{len(pairs)}] = {{{', '.join(pjs)}}};")
         tables.append(f"static constexpr signed char V2_{n}_CLOW[{len(pairs)}] = {{{', '.join(pjm)}}};")
         tables.append(f"static constexpr short V2_{n}_KV[{len(pairs)}] = {{{', '.join(pkv)}}};")
-    kt_off = ", ".join(str(lay.K[1 << g]) for g in range(n))
+    kt_off = ", ".join(str(lay.K1[g]) for g in range(n))
     kv_off = ", ".join(str(lay.Kv[1 << g]) for g in range(n))
     tables.append(f"static constexpr short KT1_{n}[{n}] = {{{kt_off}}};")
     tables.append(f"static constexpr short KV1_{n}[{n}] = {{{kv_off}}};")
 
     # ---- stages ----
     w("    const double mtd = mt;")
-    w("    // level 1: polarisation vectors j(g; h) = eps_g(h)")
-    w(f"    for (int it = lane; it < {2 * n}; it += nl) {{")
-    w(f"        const double* q = tab + {lay.eps[0]} + 4 * it;")
-    w(f"        T* o = obj + {co.gj} + 4 * it;")
-    w("        for (int mu = 0; mu < 4; ++mu) o[mu] = (T)q[mu];")
-    w("    }")
-    w("    wave_sync();")
+    w("    // level 1 (the polarisation vectors j(g; h) = eps_g(h)) is written by the table fill")
     for L in range(2, n + 1):
         nseq = len(co.levels[L])
         npair, ntrip = L - 1, (L - 1) * (L - 2) // 2
@@ -554,7 +685,7 @@ def emit_coop(n, lay, co, K, perms):
         w("            const T g1 = (T)sp.s1, g2 = (T)sp.s2;")
         w("            const T j1[4] = {g1 * q1[0], g1 * q1[1], g1 * q1[2], g1 * q1[3]};")
         w("            const T j2[4] = {g2 * q2[0], g2 * q2[1], g2 * q2[2], g2 * q2[3]};")
-        w("            const double* p1 = tab + sp.p1; const double* p2 = tab + sp.p2;")
+        w("            const T* p1 = tab + sp.p1; const T* p2 = tab + sp.p2;")
         w("            const T P1[4] = {(T)p1[0], (T)p1[1], (T)p1[2], (T)p1[3]};")
         w("            const T P2[4] = {(T)p2[0], (T)p2[1], (T)p2[2], (T)p2[3]};")
         w("            const T c1 = (T)2 * (P1[0] * j2[0] - P1[1] * j2[1] - P1[2] * j2[2] - P1[3] * j2[3]);")
@@ -592,10 +723,10 @@ def emit_coop(n, lay, co, K, perms):
     w(f"        const int side = it >= {4 * n}, r = it - side * {4 * n};")
     w("        const int g = r >> 2, sp = (r >> 1) & 1, h = r & 1;")
     w(f"        const T* e = obj + {co.gj} + 4 * (2 * g + h);")
-    w(f"        const double* q = tab + (side ? {lay.v} : {lay.ub}) + 8 * sp;")
+    w(f"        const T* q = tab + (side ? {lay.v} : {lay.ub}) + 8 * sp;")
     w("        cplx<T> x[4];")
     w("        for (int i = 0; i < 4; ++i) x[i] = cplx<T>((T)q[2 * i], (T)q[2 * i + 1]);")
-    w(f"        const double* k = tab + (side ? KV1_{n}[g] : KT1_{n}[g]);")
+    w(f"        const T* k = tab + (side ? KV1_{n}[g] : KT1_{n}[g]);")
     w("        const T Kc[4] = {(T)k[0], (T)k[1], (T)k[2], (T)k[3]};")
     w("        cplx<T> out[4];")
     w("        if (!side) {")
@@ -627,11 +758,11 @@ def emit_coop(n, lay, co, K, perms):
         w(f"        const T* q = obj + {co.gj} + 4 * (V2_{n}_JB[pi] + hm);")
         w(f"        const T gs = (T)V2_{n}_JS[pi];")
         w("        const T jcd[4] = {gs * q[0], gs * q[1], gs * q[2], gs * q[3]};")
-        w(f"        const double* qv = tab + {lay.v} + 8 * sb;")
+        w(f"        const T* qv = tab + {lay.v} + 8 * sb;")
         w("        cplx<T> x[4];")
         w("        for (int i = 0; i < 4; ++i) x[i] = cplx<T>((T)qv[2 * i], (T)qv[2 * i + 1]);")
         w("        slashcol_acc(jcd, x, W);")
-        w(f"        const double* k = tab + V2_{n}_KV[pi];")
+        w(f"        const T* k = tab + V2_{n}_KV[pi];")
         w("        const T Kc[4] = {(T)k[0], (T)k[1], (T)k[2], (T)k[3]};")
         w("        cplx<T> out[4];")
         w("        colprop(W, Kc, (T)mtd, (T)k[4], (T)k[5], out);")
@@ -655,8 +786,8 @@ def emit_coop(n, lay, co, K, perms):
     a('    asm volatile("" : "+v"(hel));')
     a("    const int sT = hel & 1, sB = (hel >> 1) & 1, hg = hel >> 2;")
     a("    cplx<T> ub[4], v[4];")
-    a(f"    {{ const double* q = tab + {lay.ub} + 8 * sT; for (int i = 0; i < 4; ++i) ub[i] = cplx<T>((T)q[2 * i], (T)q[2 * i + 1]); }}")
-    a(f"    {{ const double* q = tab + {lay.v} + 8 * sB; for (int i = 0; i < 4; ++i) v[i] = cplx<T>((T)q[2 * i], (T)q[2 * i + 1]); }}")
+    a(f"    {{ const T* q = tab + {lay.ub} + 8 * sT; for (int i = 0; i < 4; ++i) ub[i] = cplx<T>(q[2 * i], q[2 * i + 1]); }}")
+    a(f"    {{ const T* q = tab + {lay.v} + 8 * sB; for (int i = 0; i < 4; ++i) v[i] = cplx<T>(q[2 * i], q[2 * i + 1]); }}")
     hel_flops = 0
     lex = {sq: i for i, sq in enumerate(perms)}
     nperm_ = len(perms)
@@ -761,24 +892,39 @@ def emit_coop(n, lay, co, K, perms):
 
 def generate_coop(n):
     perms, K, den = colour_matrix(n)
-    lay = Layout(n)
+    tl = CoopTable(n)
     co = CoopLayout(n)
-    tables, stages, amp, fst, fhel = emit_coop(n, lay, co, K, perms)
+    tables, stages, amp, fst, fhel = emit_coop(n, tl, co, K, perms)
+    fill = emit_coop_fill(n, tl, co)
     global _COOP_COUNT
-    _COOP_COUNT = {"stages": fst, "per_helicity": fhel, "object_store": co.size}
+    _COOP_COUNT = {"stages": fst, "per_helicity": fhel, "object_store": co.size, "table": tl.size,
+                   "momentum_only": tl.mom_flops()}
     return f"""
 // ---- cooperative evaluation (helicity-recycled objects in LDS) ----
-// Object store: {co.size} T per event.  Stage flops per event: {fst}; per
+// Table: {tl.size} T per event; object store: {co.size} T per event.  Table
+// flops per event: {tl.mom_flops()}; stage flops per event: {fst}; per
 // helicity lane: {fhel}.
+static constexpr int COOP_TABLE_NG{n} = {tl.size};
 static constexpr int COOP_OBJ_NG{n} = {co.size};
 static constexpr int COOP_FLOPS_STAGES_NG{n} = {fst};
 static constexpr int COOP_FLOPS_HEL_NG{n} = {fhel};
 {tables}
 
+// Per-event table of momentum-only quantities (type T) and the level-1
+// gluon currents in the object store, written by the lanes of one event;
+// the caller synchronises the wave afterwards.  mom: t[4], tbar[4], final
+// gluons[4 each]; eb: beam energy sqrt(s_hat)/2; mt: top mass; mw: m_t Gamma_t.
+template <typename T>
+__device__ __forceinline__ void fill_table_coop_ng{n}(const double* __restrict__ mom, double eb, double mt, double mw,
+                                                     T* __restrict__ tab, T* __restrict__ obj, int lane)
+{{
+{fill}
+}}
+
 // Builds the event's object store `obj` from its table: lanes 0 .. nl-1 of
 // the wave serve this event; every level ends with a wave synchronisation.
 template <typename T>
-__device__ __forceinline__ void coop_stages_ng{n}(const double* __restrict__ tab, T* __restrict__ obj, double mt,
+__device__ __forceinline__ void coop_stages_ng{n}(const T* __restrict__ tab, T* __restrict__ obj, double mt,
                                                  int lane, int nl)
 {{
 {stages}
@@ -788,7 +934,7 @@ __device__ __forceinline__ void coop_stages_ng{n}(const double* __restrict__ tab
 // object store: meet-in-the-middle at the vertex that carries the second
 // gluon of each colour ordering, A = sum Xbar gamma.j(block) Y.
 template <typename T>
-__device__ __forceinline__ double coop_me2_ng{n}(const double* __restrict__ tab, const T* __restrict__ obj, int hel)
+__device__ __forceinline__ double coop_me2_ng{n}(const T* __restrict__ tab, const T* __restrict__ obj, int hel)
 {{
 {amp}
     return (double)me / COLOUR_DEN_NG{n};

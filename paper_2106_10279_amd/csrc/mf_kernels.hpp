@@ -14,6 +14,8 @@
 // (phase space).
 #pragma once
 
+#include <type_traits>
+
 #include "mf_device.hpp"
 
 namespace mf {
@@ -292,26 +294,24 @@ __device__ __forceinline__ double group_sum(double v, int width)
     return v;
 }
 
-template <int NG>
-__device__ __forceinline__ void fill_table(const double* mom, double eb, double mt, double mw, double* tab, int lane)
+// Table element type: double for the per-lane evaluation (n_g = 2), the
+// amplitude type for the cooperative one (its table entries are only ever
+// read converted to that type).
+template <int NG, typename T>
+using TabT = std::conditional_t<(NG >= 3), T, double>;
+
+// Per-event table (and, for n_g >= 3, the level-1 currents of the object
+// store) from the momenta, written by the lanes of one event.
+template <int NG, typename T>
+__device__ __forceinline__ void fill_table(const double* mom, double eb, double mt, double mw, TabT<NG, T>* tab,
+                                           T* obj, int lane)
 {
     if constexpr (NG == 2)
         fill_table_ng2(mom, eb, mt, mw, tab, lane);
     else if constexpr (NG == 3)
-        fill_table_ng3(mom, eb, mt, mw, tab, lane);
+        fill_table_coop_ng3<T>(mom, eb, mt, mw, tab, obj, lane);
     else
-        fill_table_ng4(mom, eb, mt, mw, tab, lane);
-}
-
-template <int NG, typename T>
-__device__ __forceinline__ double colour_summed_me2(const double* tab, int hel, double mt)
-{
-    if constexpr (NG == 2)
-        return colour_summed_me2_ng2<T>(tab, hel, mt);
-    else if constexpr (NG == 3)
-        return colour_summed_me2_ng3<T>(tab, hel, mt);
-    else
-        return colour_summed_me2_ng4<T>(tab, hel, mt);
+        fill_table_coop_ng4<T>(mom, eb, mt, mw, tab, obj, lane);
 }
 
 // Momenta stored per event: t[4], tbar[4], final gluons[4 each], beam energy.
@@ -320,7 +320,7 @@ struct Layout {
     static constexpr int kMom = 8 + 4 * (NG - 2) + 1;
     static constexpr int kHel = 1 << (NG + 2);
     static constexpr int kEventsPerPass = kWave / kHel;   // 4, 2, 1
-    static constexpr int kTable = NG == 2 ? TABLE_NG2 : (NG == 3 ? TABLE_NG3 : TABLE_NG4);
+    static constexpr int kTable = NG == 2 ? TABLE_NG2 : (NG == 3 ? COOP_TABLE_NG3 : COOP_TABLE_NG4);
     // helicity-recycled object store per event (units of the amplitude type)
     static constexpr bool kCoop = NG >= 3;
     static constexpr int kObj = NG == 2 ? 1 : (NG == 3 ? COOP_OBJ_NG3 : COOP_OBJ_NG4);
@@ -330,7 +330,7 @@ struct Layout {
 // lanes of the event (h = 0 .. 2^(NG+2) - 1) build the object store first
 // (n_g >= 3).  `any_live` must be uniform over the wave.
 template <int NG, typename T>
-__device__ __forceinline__ double event_me2(const double* tab, T* obj, int h, double mt, bool live, bool any_live)
+__device__ __forceinline__ double event_me2(const TabT<NG, T>* tab, T* obj, int h, double mt, bool live, bool any_live)
 {
     using L = Layout<NG>;
     if constexpr (L::kCoop) {
@@ -347,7 +347,7 @@ __device__ __forceinline__ double event_me2(const double* tab, T* obj, int h, do
         else
             return coop_me2_ng4<T>(tab, obj, h);
     } else {
-        return live ? colour_summed_me2<NG, T>(tab, h, mt) : 0.0;
+        return live ? colour_summed_me2_ng2<T>(tab, h, mt) : 0.0;
     }
 }
 
@@ -467,7 +467,7 @@ __global__ void __launch_bounds__(kBlock) event_kernel(EventParams P)
     __shared__ double s_lx[kMaxPdfX];
     __shared__ double s_rows[4 * kMaxPdfX];
     __shared__ double s_lq[4];
-    __shared__ double s_tab[kWavesPerBlock][L::kEventsPerPass][L::kTable];
+    __shared__ TabT<NG, T> s_tab[kWavesPerBlock][L::kEventsPerPass][L::kTable];
     __shared__ T s_obj[kWavesPerBlock][L::kEventsPerPass][L::kObj];
     extern __shared__ double s_hist[];     // [kWavesPerBlock][D][n_bins]
 
@@ -517,7 +517,7 @@ __global__ void __launch_bounds__(kBlock) event_kernel(EventParams P)
         {
             const int h0 = lane % L::kHel;
             const int sub = lane / L::kHel;
-            double* tab = s_tab[wv][sub];
+            TabT<NG, T>* tab = s_tab[wv][sub];
             T* obj = s_obj[wv][sub];
             for (int g = 0; g < kWave / L::kEventsPerPass; ++g) {
                 // opaque per iteration, so that lane-dependent addresses of the
@@ -529,7 +529,7 @@ __global__ void __launch_bounds__(kBlock) event_kernel(EventParams P)
                 const bool live = s_pref[wv][e] != 0.0;
                 const bool any_live = __any(live);
                 if (live)
-                    fill_table<NG>(m_e, m_e[L::kMom - 1], P.m_top, P.mw, tab, h);
+                    fill_table<NG, T>(m_e, m_e[L::kMom - 1], P.m_top, P.mw, tab, obj, h);
                 wave_sync();
                 double v = event_me2<NG, T>(tab, obj, h, P.m_top, live, any_live);
                 v = group_sum(v, L::kHel);
@@ -657,12 +657,12 @@ template <int NG, typename T>
 __global__ void __launch_bounds__(kWave) amp_kernel(StageParams S)
 {
     using L = Layout<NG>;
-    __shared__ double s_tab[L::kEventsPerPass][L::kTable];
+    __shared__ TabT<NG, T> s_tab[L::kEventsPerPass][L::kTable];
     __shared__ T s_obj[L::kEventsPerPass][L::kObj];
     const int lane = threadIdx.x;
     const int h0 = lane % L::kHel;
     const int sub = lane / L::kHel;
-    double* tab = s_tab[sub];
+    TabT<NG, T>* tab = s_tab[sub];
     T* obj = s_obj[sub];
     const uint64_t n_groups = (S.count + L::kEventsPerPass - 1) / L::kEventsPerPass;
     for (uint64_t g = blockIdx.x; g < n_groups; g += gridDim.x) {
@@ -675,7 +675,7 @@ __global__ void __launch_bounds__(kWave) amp_kernel(StageParams S)
             continue;
         const double* m_e = S.mom + e * L::kMom;
         if (live)
-            fill_table<NG>(m_e, m_e[L::kMom - 1], S.P.m_top, S.P.mw, tab, h);
+            fill_table<NG, T>(m_e, m_e[L::kMom - 1], S.P.m_top, S.P.mw, tab, obj, h);
         wave_sync();
         double v = event_me2<NG, T>(tab, obj, h, S.P.m_top, live, any_live);
         v = group_sum(v, L::kHel);
@@ -919,18 +919,18 @@ __global__ void __launch_bounds__(kBlock) me_kernel(const double* __restrict__ m
                                                      uint64_t n, double mt, double mw, double* __restrict__ out)
 {
     using L = Layout<NG>;
-    __shared__ double s_tab[kWavesPerBlock][L::kEventsPerPass][L::kTable];
+    __shared__ TabT<NG, T> s_tab[kWavesPerBlock][L::kEventsPerPass][L::kTable];
     __shared__ T s_obj[kWavesPerBlock][L::kEventsPerPass][L::kObj];
     const int lane = threadIdx.x % kWave;
     const int wv = threadIdx.x / kWave;
     const uint64_t wave = (uint64_t)blockIdx.x * kWavesPerBlock + wv;
     const uint64_t e = wave * L::kEventsPerPass + lane / L::kHel;
     const int h = lane % L::kHel;
-    double* tab = s_tab[wv][lane / L::kHel];
+    TabT<NG, T>* tab = s_tab[wv][lane / L::kHel];
     T* obj = s_obj[wv][lane / L::kHel];
     const bool live = e < n;
     if (live)
-        fill_table<NG>(mom + e * (L::kMom - 1), eb[e], mt, mw, tab, h);
+        fill_table<NG, T>(mom + e * (L::kMom - 1), eb[e], mt, mw, tab, obj, h);
     wave_sync();
     double v = event_me2<NG, T>(tab, obj, h, mt, live, __any(live));
     v = group_sum(v, L::kHel);
