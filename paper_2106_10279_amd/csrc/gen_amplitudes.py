@@ -367,7 +367,7 @@ class Emitter:
             return nm
         U = self.fcur(seq)
         self.done.add(key)
-        self.hel += 74
+        self.hel += 64
         self.w(f"cT {nm}[4];")
         self.w(f"bilinear(" + U + ", v, " + nm + ");")
         return nm
@@ -680,11 +680,12 @@ def emit_coop(n, lay, co, K, perms):
         w("#pragma unroll")
         w(f"        for (int k = 0; k < {npair}; ++k) {{")
         w(f"            const GPair sp = GJ{n}_L{L}_PAIR[si * {npair} + k];")
-        w(f"            const T* q1 = obj + {co.gj} + 4 * (sp.b1 + pext4(hm, sp.m1));")
-        w(f"            const T* q2 = obj + {co.gj} + 4 * (sp.b2 + pext4(hm, sp.m2));")
+        w(f"            const T* q1 = al16(obj + {co.gj} + 4 * (sp.b1 + pext4(hm, sp.m1)));")
+        w(f"            const T* q2 = al16(obj + {co.gj} + 4 * (sp.b2 + pext4(hm, sp.m2)));")
         w("            const T g1 = (T)sp.s1, g2 = (T)sp.s2;")
-        w("            const T j1[4] = {g1 * q1[0], g1 * q1[1], g1 * q1[2], g1 * q1[3]};")
-        w("            const T j2[4] = {g2 * q2[0], g2 * q2[1], g2 * q2[2], g2 * q2[3]};")
+        w("            T j1[4], j2[4];")
+        w("            ld4(q1, j1); ld4(q2, j2);")
+        w("            for (int i = 0; i < 4; ++i) { j1[i] *= g1; j2[i] *= g2; }")
         w("            const T* p1 = tab + sp.p1; const T* p2 = tab + sp.p2;")
         w("            const T P1[4] = {(T)p1[0], (T)p1[1], (T)p1[2], (T)p1[3]};")
         w("            const T P2[4] = {(T)p2[0], (T)p2[1], (T)p2[2], (T)p2[3]};")
@@ -698,13 +699,13 @@ def emit_coop(n, lay, co, K, perms):
             w("#pragma unroll")
             w(f"        for (int k = 0; k < {ntrip}; ++k) {{")
             w(f"            const GTrip tp = GJ{n}_L{L}_TRIP[si * {ntrip} + k];")
-            w(f"            const T* q1 = obj + {co.gj} + 4 * (tp.b1 + pext4(hm, tp.m1));")
-            w(f"            const T* q2 = obj + {co.gj} + 4 * (tp.b2 + pext4(hm, tp.m2));")
-            w(f"            const T* q3 = obj + {co.gj} + 4 * (tp.b3 + pext4(hm, tp.m3));")
+            w(f"            const T* q1 = al16(obj + {co.gj} + 4 * (tp.b1 + pext4(hm, tp.m1)));")
+            w(f"            const T* q2 = al16(obj + {co.gj} + 4 * (tp.b2 + pext4(hm, tp.m2)));")
+            w(f"            const T* q3 = al16(obj + {co.gj} + 4 * (tp.b3 + pext4(hm, tp.m3)));")
             w("            const T g1 = (T)tp.s1, g2 = (T)tp.s2, g3 = (T)tp.s3;")
-            w("            const T j1[4] = {g1 * q1[0], g1 * q1[1], g1 * q1[2], g1 * q1[3]};")
-            w("            const T j2[4] = {g2 * q2[0], g2 * q2[1], g2 * q2[2], g2 * q2[3]};")
-            w("            const T j3[4] = {g3 * q3[0], g3 * q3[1], g3 * q3[2], g3 * q3[3]};")
+            w("            T j1[4], j2[4], j3[4];")
+            w("            ld4(q1, j1); ld4(q2, j2); ld4(q3, j3);")
+            w("            for (int i = 0; i < 4; ++i) { j1[i] *= g1; j2[i] *= g2; j3[i] *= g3; }")
             w("            const T d23 = j2[0] * j3[0] - j2[1] * j3[1] - j2[2] * j3[2] - j2[3] * j3[3];")
             w("            const T d13 = j1[0] * j3[0] - j1[1] * j3[1] - j1[2] * j3[2] - j1[3] * j3[3];")
             w("            const T d12 = j1[0] * j2[0] - j1[1] * j2[1] - j1[2] * j2[2] - j1[3] * j2[3];")
@@ -712,8 +713,8 @@ def emit_coop(n, lay, co, K, perms):
                 w(f"            a{mu} += j1[{mu}] * d23 - (T)2 * j2[{mu}] * d13 + j3[{mu}] * d12;")
             w("        }")
         w(f"        const T f = (T)tab[GJ{n}_L{L}_NINV[si]];")
-        w(f"        T* o = obj + {co.gj} + 4 * (GJ{n}_L{L}_BASE[si] + hm);")
-        w("        o[0] = a0 * f; o[1] = a1 * f; o[2] = a2 * f; o[3] = a3 * f;")
+        w(f"        T* o = al16(obj + {co.gj} + 4 * (GJ{n}_L{L}_BASE[si] + hm));")
+        w("        st4(o, a0 * f, a1 * f, a2 * f, a3 * f);")
         w("    }")
         w("    wave_sync();")
     # top line from the top side: Ubar(a; s_t, h_a)
@@ -722,7 +723,8 @@ def emit_coop(n, lay, co, K, perms):
     w(f"    for (int it = lane; it < {8 * n}; it += nl) {{")
     w(f"        const int side = it >= {4 * n}, r = it - side * {4 * n};")
     w("        const int g = r >> 2, sp = (r >> 1) & 1, h = r & 1;")
-    w(f"        const T* e = obj + {co.gj} + 4 * (2 * g + h);")
+    w(f"        T e[4];")
+    w(f"        ld4(al16(obj + {co.gj} + 4 * (2 * g + h)), e);")
     w(f"        const T* q = tab + (side ? {lay.v} : {lay.ub}) + 8 * sp;")
     w("        cplx<T> x[4];")
     w("        for (int i = 0; i < 4; ++i) x[i] = cplx<T>((T)q[2 * i], (T)q[2 * i + 1]);")
@@ -738,8 +740,7 @@ def emit_coop(n, lay, co, K, perms):
     w("            slashcol_acc(e, x, W);")
     w("            colprop(W, Kc, (T)mtd, (T)k[4], (T)k[5], out);")
     w("        }")
-    w(f"        T* o = obj + (side ? {co.v1} : {co.u1}) + 8 * r;")
-    w("        for (int i = 0; i < 4; ++i) { o[2 * i] = out[i].x; o[2 * i + 1] = out[i].y; }")
+    w(f"        stspin(al16(obj + (side ? {co.v1} : {co.u1}) + 8 * r), out);")
     w("    }")
     w("    wave_sync();")
     if pairs:
@@ -748,16 +749,17 @@ def emit_coop(n, lay, co, K, perms):
         w(f"    for (int it = lane; it < {8 * len(pairs)}; it += nl) {{")
         w("        const int pi = it >> 3, sb = (it >> 2) & 1, hc = (it >> 1) & 1, hd = it & 1;")
         w(f"        const int c = V2_{n}_CD[2 * pi], d = V2_{n}_CD[2 * pi + 1];")
-        w(f"        const T* ec = obj + {co.gj} + 4 * (2 * c + hc);")
-        w(f"        const T* vd = obj + {co.v1} + 8 * (4 * d + 2 * sb + hd);")
+        w("        T ec[4];")
+        w(f"        ld4(al16(obj + {co.gj} + 4 * (2 * c + hc)), ec);")
         w("        cplx<T> y[4];")
-        w("        for (int i = 0; i < 4; ++i) y[i] = cplx<T>(vd[2 * i], vd[2 * i + 1]);")
+        w(f"        ldspin(al16(obj + {co.v1} + 8 * (4 * d + 2 * sb + hd)), y);")
         w("        cplx<T> W[4] = {cplx<T>(0, 0), cplx<T>(0, 0), cplx<T>(0, 0), cplx<T>(0, 0)};")
         w("        slashcol_acc(ec, y, W);")
         w(f"        const int hm = V2_{n}_CLOW[pi] ? (hc | (hd << 1)) : (hd | (hc << 1));")
-        w(f"        const T* q = obj + {co.gj} + 4 * (V2_{n}_JB[pi] + hm);")
         w(f"        const T gs = (T)V2_{n}_JS[pi];")
-        w("        const T jcd[4] = {gs * q[0], gs * q[1], gs * q[2], gs * q[3]};")
+        w("        T jcd[4];")
+        w(f"        ld4(al16(obj + {co.gj} + 4 * (V2_{n}_JB[pi] + hm)), jcd);")
+        w("        for (int i = 0; i < 4; ++i) jcd[i] *= gs;")
         w(f"        const T* qv = tab + {lay.v} + 8 * sb;")
         w("        cplx<T> x[4];")
         w("        for (int i = 0; i < 4; ++i) x[i] = cplx<T>((T)qv[2 * i], (T)qv[2 * i + 1]);")
@@ -766,8 +768,7 @@ def emit_coop(n, lay, co, K, perms):
         w("        const T Kc[4] = {(T)k[0], (T)k[1], (T)k[2], (T)k[3]};")
         w("        cplx<T> out[4];")
         w("        colprop(W, Kc, (T)mtd, (T)k[4], (T)k[5], out);")
-        w(f"        T* o = obj + {co.v2} + 8 * it;")
-        w("        for (int i = 0; i < 4; ++i) { o[2 * i] = out[i].x; o[2 * i + 1] = out[i].y; }")
+        w(f"        stspin(al16(obj + {co.v2} + 8 * it), out);")
         w("    }")
         w("    wave_sync();")
     stages = "\n".join(L_)
@@ -791,8 +792,12 @@ def emit_coop(n, lay, co, K, perms):
     hel_flops = 0
     lex = {sq: i for i, sq in enumerate(perms)}
     nperm_ = len(perms)
+    # Each accumulator holds sig[k] * A_k, with the sign fixed by its first
+    # contribution (written, not added to zero); the colour sum absorbs the
+    # signs into its coefficients.
     a(f"    T Ar[{nperm_}], Ai[{nperm_}];")
-    a(f"    for (int i = 0; i < {nperm_}; ++i) {{ Ar[i] = 0; Ai[i] = 0; }}")
+    acc_decl = len(A) - 1
+    sig = {}
 
     def hexpr(block):
         srt = sorted(block)
@@ -800,14 +805,13 @@ def emit_coop(n, lay, co, K, perms):
 
     def gj_ptr(block):
         b, sg, cs = co.obj(block)
-        return f"(ob + {co.gj} + 4 * ({b} + ({hexpr(cs)})))", sg
+        return f"al16(ob + {co.gj} + 4 * ({b} + ({hexpr(cs)})))", sg
 
     def load_row(X, nm):
         if not X:
             return "ub"
         a(f"        cplx<T> {nm}[4];")
-        a(f"        {{ const T* q = ob + {co.u1} + 8 * (4 * {X[0]} + 2 * sT + ((hg >> {X[0]}) & 1)); "
-          f"for (int i = 0; i < 4; ++i) {nm}[i] = cplx<T>(q[2 * i], q[2 * i + 1]); }}")
+        a(f"        ldspin(al16(ob + {co.u1} + 8 * (4 * {X[0]} + 2 * sT + ((hg >> {X[0]}) & 1))), {nm});")
         return nm
 
     def load_col(Y, nm):
@@ -821,7 +825,7 @@ def emit_coop(n, lay, co, K, perms):
             pi = co.pairs.index((c, d))
             idx = f"{co.v2} + 8 * ({8 * pi} + 4 * sB + 2 * ((hg >> {c}) & 1) + ((hg >> {d}) & 1))"
         a(f"        cplx<T> {nm}[4];")
-        a(f"        {{ const T* q = ob + {idx}; for (int i = 0; i < 4; ++i) {nm}[i] = cplx<T>(q[2 * i], q[2 * i + 1]); }}")
+        a(f"        ldspin(al16(ob + {idx}), {nm});")
         return nm
 
     # group the terms by bilinear: key (X, Y) -> list of (beta, ordering)
@@ -844,7 +848,7 @@ def emit_coop(n, lay, co, K, perms):
         c = load_col(Y, "yc")
         a("        cplx<T> d[4];")
         a(f"        bilinear({r}, {c}, d);")
-        hel_flops += 74
+        hel_flops += 64
         # distinct currents (up to reflection) met by this bilinear
         byc = {}
         for (beta, sg) in groups[(X, Y)]:
@@ -853,15 +857,33 @@ def emit_coop(n, lay, co, K, perms):
         touched = []
         for cs, uses in byc.items():
             ptr, _ = gj_ptr(cs)
+            if len(uses) == 1:
+                # one ordering meets this current: multiply-add into its accumulator
+                sgn, sg = uses[0]
+                k = lex[sg]
+                if k not in sig:
+                    sig[k] = sgn
+                    a(f"        cdotj_set(d, {ptr}, Ar[{k}], Ai[{k}]);")
+                    hel_flops += 14
+                else:
+                    a(f"        cdotj_fma<{sgn * sig[k]}>(d, {ptr}, Ar[{k}], Ai[{k}]);")
+                    hel_flops += 16
+                if k not in touched:
+                    touched.append(k)
+                continue
             a("        {")
-            a("            T sr = 0, si = 0;")
-            a(f"            cdotj<1>(d, {ptr}, sr, si);")
-            hel_flops += 16
+            a("            T sr, si;")
+            a(f"            cdotj_set(d, {ptr}, sr, si);")
+            hel_flops += 14
             for (sgn, sg) in uses:
                 k = lex[sg]
-                op = "+=" if sgn > 0 else "-="
-                a(f"            Ar[{k}] {op} sr; Ai[{k}] {op} si;")
-                hel_flops += 2
+                if k not in sig:
+                    sig[k] = sgn
+                    a(f"            Ar[{k}] = sr; Ai[{k}] = si;")
+                else:
+                    op = "+=" if sgn * sig[k] > 0 else "-="
+                    a(f"            Ar[{k}] {op} sr; Ai[{k}] {op} si;")
+                    hel_flops += 2
                 if k not in touched:
                     touched.append(k)
             a("        }")
@@ -873,18 +895,31 @@ def emit_coop(n, lay, co, K, perms):
             ops = ", ".join(f'"+v"(Ar[{k}]), "+v"(Ai[{k}])' for k in touched[c0:c0 + 4])
             a(f'        asm volatile("" : {ops});')
         a("    }")
-    # colour sum: sum_s K_ss |A_s|^2 + 2 sum_{t<s} K_st Re(conj(A_s) A_t)
-    a("    T me = 0;")
+    untouched = [k for k in range(nperm_) if k not in sig]
+    if untouched:
+        A[acc_decl] += " " + " ".join(f"Ar[{k}] = 0; Ai[{k}] = 0;" for k in untouched)
+        for k in untouched:
+            sig[k] = 1
+    # colour sum: sum_s K_ss |A_s|^2 + 2 sum_{t<s} K_st Re(conj(A_s) A_t), on
+    # the accumulators (sig[s] A_s): K_st enters as sig[s] sig[t] K_st
+    a("    T me;")
     for sidx in range(nperm_):
         a("    {")
         a(f"        T tr = {K[sidx][sidx]} * Ar[{sidx}], ti = {K[sidx][sidx]} * Ai[{sidx}];")
-        hel_flops += 4
+        hel_flops += 2
         for t in range(sidx):
             if K[sidx][t]:
-                a(f"        tr += (T)({2 * K[sidx][t]}) * Ar[{t}]; ti += (T)({2 * K[sidx][t]}) * Ai[{t}];")
+                kst = 2 * K[sidx][t] * sig[sidx] * sig[t]
+                a(f"        tr += (T)({kst}) * Ar[{t}]; ti += (T)({kst}) * Ai[{t}];")
                 hel_flops += 4
-        a(f"        me += Ar[{sidx}] * tr + Ai[{sidx}] * ti;")
-        hel_flops += 4
+        if sidx == 0:
+            a(f"        me = Ar[{sidx}] * tr;")
+            hel_flops += 1
+        else:
+            a(f"        me += Ar[{sidx}] * tr;")
+            hel_flops += 2
+        a(f"        me += Ai[{sidx}] * ti;")
+        hel_flops += 2
         a("    }")
     amp = "\n".join(A)
     return "\n".join(tables), stages, amp, flops_stage, hel_flops

@@ -143,19 +143,25 @@ __device__ __forceinline__ int pext4(int x, int m)
     return r;
 }
 
-// c^mu = a gamma^mu v = aL sigma^mu vR + aR sigmabar^mu vL.
+// c^mu = a gamma^mu v = aL sigma^mu vR + aR sigmabar^mu vL.  The four
+// components are sums and differences of four two-term products,
+//   P = a0 v2 + a3 v1,  Q = a1 v3 + a2 v0,  R = a0 v3 - a2 v1,  S = a1 v2 - a3 v0:
+//   c0 = P + Q,  c3 = P - Q,  c1 = R + S,  c2 = i (S - R).
 template <typename T>
 __host__ __device__ __forceinline__ void bilinear(const cplx<T>* a, const cplx<T>* v, cplx<T>* c)
 {
-    const cplx<T> s0 = cmul(a[0], v[2]), s1 = cmul(a[1], v[3]);
-    const cplx<T> x01 = cmul(a[0], v[3]), x10 = cmul(a[1], v[2]);
-    const cplx<T> t0 = cmul(a[2], v[0]), t1 = cmul(a[3], v[1]);
-    const cplx<T> y01 = cmul(a[2], v[1]), y10 = cmul(a[3], v[0]);
-    c[0] = cplx<T>(s0.x + s1.x + t0.x + t1.x, s0.y + s1.y + t0.y + t1.y);
-    c[1] = cplx<T>(x01.x + x10.x - y01.x - y10.x, x01.y + x10.y - y01.y - y10.y);
-    // i (x10 - x01) - i (y10 - y01)
-    c[2] = cplx<T>(-(x10.y - x01.y) + (y10.y - y01.y), (x10.x - x01.x) - (y10.x - y01.x));
-    c[3] = cplx<T>(s0.x - s1.x - t0.x + t1.x, s0.y - s1.y - t0.y + t1.y);
+    const T Px = a[0].x * v[2].x - a[0].y * v[2].y + a[3].x * v[1].x - a[3].y * v[1].y;
+    const T Py = a[0].x * v[2].y + a[0].y * v[2].x + a[3].x * v[1].y + a[3].y * v[1].x;
+    const T Qx = a[1].x * v[3].x - a[1].y * v[3].y + a[2].x * v[0].x - a[2].y * v[0].y;
+    const T Qy = a[1].x * v[3].y + a[1].y * v[3].x + a[2].x * v[0].y + a[2].y * v[0].x;
+    const T Rx = a[0].x * v[3].x - a[0].y * v[3].y - a[2].x * v[1].x + a[2].y * v[1].y;
+    const T Ry = a[0].x * v[3].y + a[0].y * v[3].x - a[2].x * v[1].y - a[2].y * v[1].x;
+    const T Sx = a[1].x * v[2].x - a[1].y * v[2].y - a[3].x * v[0].x + a[3].y * v[0].y;
+    const T Sy = a[1].x * v[2].y + a[1].y * v[2].x - a[3].x * v[0].y - a[3].y * v[0].x;
+    c[0] = cplx<T>(Px + Qx, Py + Qy);
+    c[3] = cplx<T>(Px - Qx, Py - Qy);
+    c[1] = cplx<T>(Rx + Sx, Ry + Sy);
+    c[2] = cplx<T>(Ry - Sy, Sx - Rx);
 }
 
 // (ar, ai) += SGN c^mu j_mu for complex c and real j.
@@ -166,6 +172,91 @@ __host__ __device__ __forceinline__ void cdotj(const cplx<T>* c, const T* j, T& 
     const T i = c[0].y * j[0] - c[1].y * j[1] - c[2].y * j[2] - c[3].y * j[3];
     ar += (T)SGN * r;
     ai += (T)SGN * i;
+}
+
+// A pointer into the object store, declared 16-byte aligned.
+template <typename T>
+__device__ __forceinline__ const T* al16(const T* p)
+{
+    return static_cast<const T*>(__builtin_assume_aligned(p, 16));
+}
+template <typename T>
+__device__ __forceinline__ T* al16(T* p)
+{
+    return static_cast<T*>(__builtin_assume_aligned(p, 16));
+}
+
+// 128-bit LDS accesses to the object store: every 4-vector and spinor there
+// starts on a 16-byte boundary, and the 16-bit immediate offset of a 128-bit
+// access reaches every object of an event's store from one base address.
+typedef double mf_d2 __attribute__((ext_vector_type(2), __may_alias__));
+typedef float mf_f4 __attribute__((ext_vector_type(4), __may_alias__));
+
+__device__ __forceinline__ void ld4(const double* p, double* o)
+{
+    const mf_d2 a = reinterpret_cast<const mf_d2*>(p)[0], b = reinterpret_cast<const mf_d2*>(p)[1];
+    o[0] = a.x; o[1] = a.y; o[2] = b.x; o[3] = b.y;
+}
+__device__ __forceinline__ void ld4(const float* p, float* o)
+{
+    const mf_f4 a = *reinterpret_cast<const mf_f4*>(p);
+    o[0] = a.x; o[1] = a.y; o[2] = a.z; o[3] = a.w;
+}
+__device__ __forceinline__ void st4(double* p, double a0, double a1, double a2, double a3)
+{
+    mf_d2 a, b;
+    a.x = a0; a.y = a1; b.x = a2; b.y = a3;
+    reinterpret_cast<mf_d2*>(p)[0] = a;
+    reinterpret_cast<mf_d2*>(p)[1] = b;
+}
+__device__ __forceinline__ void st4(float* p, float a0, float a1, float a2, float a3)
+{
+    mf_f4 a;
+    a.x = a0; a.y = a1; a.z = a2; a.w = a3;
+    *reinterpret_cast<mf_f4*>(p) = a;
+}
+// complex 4-spinor, re/im interleaved
+template <typename T>
+__device__ __forceinline__ void ldspin(const T* p, cplx<T>* s)
+{
+    T a[4], b[4];
+    ld4(p, a);
+    ld4(p + 4, b);
+    s[0] = cplx<T>(a[0], a[1]); s[1] = cplx<T>(a[2], a[3]);
+    s[2] = cplx<T>(b[0], b[1]); s[3] = cplx<T>(b[2], b[3]);
+}
+template <typename T>
+__device__ __forceinline__ void stspin(T* p, const cplx<T>* s)
+{
+    st4(p, s[0].x, s[0].y, s[1].x, s[1].y);
+    st4(p + 4, s[2].x, s[2].y, s[3].x, s[3].y);
+}
+
+// (ar, ai) = c^mu j_mu for complex c and a real 4-vector j of the object store.
+template <typename T>
+__device__ __forceinline__ void cdotj_set(const cplx<T>* c, const T* jp, T& ar, T& ai)
+{
+    T j[4];
+    ld4(jp, j);
+    ar = c[0].x * j[0] - c[1].x * j[1] - c[2].x * j[2] - c[3].x * j[3];
+    ai = c[0].y * j[0] - c[1].y * j[1] - c[2].y * j[2] - c[3].y * j[3];
+}
+
+// (ar, ai) += SGN c^mu j_mu as one multiply-add chain per component.
+template <int SGN, typename T>
+__device__ __forceinline__ void cdotj_fma(const cplx<T>* c, const T* jp, T& ar, T& ai)
+{
+    T j[4];
+    ld4(jp, j);
+    const T s = (T)SGN;
+    ar += (s * c[0].x) * j[0];
+    ar -= (s * c[1].x) * j[1];
+    ar -= (s * c[2].x) * j[2];
+    ar -= (s * c[3].x) * j[3];
+    ai += (s * c[0].y) * j[0];
+    ai -= (s * c[1].y) * j[1];
+    ai -= (s * c[2].y) * j[2];
+    ai -= (s * c[3].y) * j[3];
 }
 
 // W = gamma.e v = ((e.sigma) vR, (e.sigmabar) vL) for a real 4-vector e.

@@ -324,6 +324,8 @@ struct Layout {
     // helicity-recycled object store per event (units of the amplitude type)
     static constexpr bool kCoop = NG >= 3;
     static constexpr int kObj = NG == 2 ? 1 : (NG == 3 ? COOP_OBJ_NG3 : COOP_OBJ_NG4);
+    // objects sit at multiples of 4 elements: 16-byte aligned in every event's store
+    static_assert(!kCoop || kObj % 4 == 0, "object store rows must keep 16-byte alignment");
 };
 
 // Colour-summed |M|^2 of helicity `h` for the event whose table is `tab`:
@@ -468,7 +470,7 @@ __global__ void __launch_bounds__(kBlock) event_kernel(EventParams P)
     __shared__ double s_rows[4 * kMaxPdfX];
     __shared__ double s_lq[4];
     __shared__ TabT<NG, T> s_tab[kWavesPerBlock][L::kEventsPerPass][L::kTable];
-    __shared__ T s_obj[kWavesPerBlock][L::kEventsPerPass][L::kObj];
+    __shared__ __align__(16) T s_obj[kWavesPerBlock][L::kEventsPerPass][L::kObj];
     extern __shared__ double s_hist[];     // [kWavesPerBlock][D][n_bins]
 
     const int tid = threadIdx.x;
@@ -658,7 +660,7 @@ __global__ void __launch_bounds__(kWave) amp_kernel(StageParams S)
 {
     using L = Layout<NG>;
     __shared__ TabT<NG, T> s_tab[L::kEventsPerPass][L::kTable];
-    __shared__ T s_obj[L::kEventsPerPass][L::kObj];
+    __shared__ __align__(16) T s_obj[L::kEventsPerPass][L::kObj];
     const int lane = threadIdx.x;
     const int h0 = lane % L::kHel;
     const int sub = lane / L::kHel;
@@ -920,7 +922,7 @@ __global__ void __launch_bounds__(kBlock) me_kernel(const double* __restrict__ m
 {
     using L = Layout<NG>;
     __shared__ TabT<NG, T> s_tab[kWavesPerBlock][L::kEventsPerPass][L::kTable];
-    __shared__ T s_obj[kWavesPerBlock][L::kEventsPerPass][L::kObj];
+    __shared__ __align__(16) T s_obj[kWavesPerBlock][L::kEventsPerPass][L::kObj];
     const int lane = threadIdx.x % kWave;
     const int wv = threadIdx.x / kWave;
     const uint64_t wave = (uint64_t)blockIdx.x * kWavesPerBlock + wv;
