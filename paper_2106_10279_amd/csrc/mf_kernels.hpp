@@ -654,30 +654,57 @@ __global__ void __launch_bounds__(kBlock) kin_kernel(StageParams S)
 
 // One wave per workgroup; a persistent loop over groups of events (one event
 // per pass for t tbar g g, two for t tbar g).  Groups without a passing event
-// are skipped whole.
+// are skipped whole.  The prefactor and momenta of the wave's next group are
+// loaded while the current one is evaluated (lane h < kMom of each event
+// holds one stored momentum component), so that their memory latency overlaps
+// the amplitude arithmetic.
 template <int NG, typename T>
-__global__ void __launch_bounds__(kWave) amp_kernel(StageParams S)
+__global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2))) amp_kernel(StageParams S)
 {
     using L = Layout<NG>;
     __shared__ TabT<NG, T> s_tab[L::kEventsPerPass][L::kTable];
     __shared__ __align__(16) T s_obj[L::kEventsPerPass][L::kObj];
+    __shared__ double s_mom[L::kEventsPerPass][L::kMom];
     const int lane = threadIdx.x;
     const int h0 = lane % L::kHel;
     const int sub = lane / L::kHel;
     TabT<NG, T>* tab = s_tab[sub];
     T* obj = s_obj[sub];
+    double* mom = s_mom[sub];
     const uint64_t n_groups = (S.count + L::kEventsPerPass - 1) / L::kEventsPerPass;
+    double pref_next = 0.0, mc_next = 0.0;
+    {
+        const uint64_t e = (uint64_t)blockIdx.x * L::kEventsPerPass + sub;
+        if (e < S.count) {
+            pref_next = S.pref[e];
+            if (h0 < L::kMom)
+                mc_next = S.mom[e * L::kMom + h0];
+        }
+    }
     for (uint64_t g = blockIdx.x; g < n_groups; g += gridDim.x) {
+        const double pref = pref_next, mc = mc_next;
+        {
+            const uint64_t e = (g + gridDim.x) * L::kEventsPerPass + sub;
+            pref_next = 0.0;
+            mc_next = 0.0;
+            if (e < S.count) {
+                pref_next = S.pref[e];
+                if (h0 < L::kMom)
+                    mc_next = S.mom[e * L::kMom + h0];
+            }
+        }
         int h = h0;
         asm volatile("" : "+v"(h));
         const uint64_t e = g * L::kEventsPerPass + sub;
-        const bool live = e < S.count && S.pref[e] != 0.0;
+        const bool live = e < S.count && pref != 0.0;
         const bool any_live = __any(live);
         if (!any_live)
             continue;
-        const double* m_e = S.mom + e * L::kMom;
+        if (h0 < L::kMom)
+            mom[h0] = mc;
+        wave_sync();
         if (live)
-            fill_table<NG, T>(m_e, m_e[L::kMom - 1], S.P.m_top, S.P.mw, tab, obj, h);
+            fill_table<NG, T>(mom, mom[L::kMom - 1], S.P.m_top, S.P.mw, tab, obj, h);
         wave_sync();
         double v = event_me2<NG, T>(tab, obj, h, S.P.m_top, live, any_live);
         v = group_sum(v, L::kHel);
