@@ -174,14 +174,16 @@ def cpu_baseline(wl, pdf, budget_s):
     threads = max(1, min(os.cpu_count() or 1, 16))
     proc = O.Process(n_g=wl["n_g"], **wl["cuts"])
     n = 8 * threads
+    rate = None
     for _ in range(2):
         t0 = time.perf_counter()
         O.integrate(proc, 13000.0, pdf, n, 1, 0, n_threads=threads, keep_weights=False)
         dt = time.perf_counter() - t0
+        rate = n / max(dt, 1e-3)
         if dt > 0.3 * budget_s:
             break
-        n = max(n, int(n * 0.5 * budget_s / max(dt, 1e-3)))
-    n = max(n, int(n * budget_s / max(dt, 1e-3)))
+        n = max(n, int(0.1 * budget_s * rate))
+    n = max(n, int(budget_s * rate))
     t0 = time.perf_counter()
     O.integrate(proc, 13000.0, pdf, n, 1, 0, n_threads=threads, keep_weights=False)
     dt = time.perf_counter() - t0
