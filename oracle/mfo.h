@@ -129,6 +129,19 @@ double mfo_event_weight_y(const mfo_process *proc, double sqrt_s,
                           const mfo_pdf_grid *pdf, int n_bins, const double *grid,
                           const double *y, mfo_event *ev);
 
+/* ---- hit-or-miss unweighting (Sec. 2.5) --------------------------------- */
+/* u_e: first 53-bit uniform of Philox block 0x80000000 of event e.         */
+double mfo_unweight_uniform(uint64_t seed, uint32_t iter, uint64_t event);
+/* keep[e] = sign(w_e) if u_e w_max < |w_e|, else 0; returns the number kept;
+ * *n_over (may be NULL) counts |w_e| > w_max.                               */
+uint64_t mfo_unweight(uint64_t n, const double *w, double w_max, uint64_t seed, uint32_t iter,
+                      signed char *keep, uint64_t *n_over);
+/* p: [n_f + 2][4] lab-frame (E, px, py, pz) of gluon a (+z), gluon b (-z),
+ * t, tbar, final gluons.  Returns 0, or 1 below threshold, 2 if the
+ * mass-rescaling Newton iteration failed (p is then zero).                 */
+int mfo_lab_event(const mfo_process *proc, double sqrt_s, int n_bins, const double *grid,
+                  uint64_t seed, int iter, uint64_t event, double *p);
+
 int mfo_integrate(const mfo_process *proc, double sqrt_s, const mfo_pdf_grid *pdf,
                   uint64_t n_events, int n_iter, uint64_t seed, int start_iter,
                   int n_bins, double alpha, int n_threads,

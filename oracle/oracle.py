@@ -111,6 +111,14 @@ def lib():
         L.mfo_ttx_dweight_dmt_analytic.argtypes = [C.POINTER(_Process), C.c_double,
                                                    C.POINTER(_Pdf), C.c_int, _dp, _dp, _dp]
         L.mfo_ttx_dweight_dmt_analytic.restype = C.c_double
+        L.mfo_unweight_uniform.argtypes = [C.c_uint64, C.c_uint32, C.c_uint64]
+        L.mfo_unweight_uniform.restype = C.c_double
+        L.mfo_unweight.argtypes = [C.c_uint64, _dp, C.c_double, C.c_uint64, C.c_uint32,
+                                   C.POINTER(C.c_byte), _u64p]
+        L.mfo_unweight.restype = C.c_uint64
+        L.mfo_lab_event.argtypes = [C.POINTER(_Process), C.c_double, C.c_int, _dp, C.c_uint64,
+                                    C.c_int, C.c_uint64, _dp]
+        L.mfo_lab_event.restype = C.c_int
         _lib = L
     return _lib
 
@@ -369,3 +377,28 @@ def ttx_dweight_dmt_analytic(proc: Process, sqrt_s, table, grid, y):
     g = lib().mfo_ttx_dweight_dmt_analytic(C.byref(pc), sqrt_s, C.byref(h.c),
                                            grid.shape[1] - 1, _d(grid), _d(y), C.byref(w))
     return g, w.value
+
+
+def unweight_uniform(seed: int, it: int, event: int) -> float:
+    """u_e of the hit-or-miss step: Philox block 0x80000000 of event e."""
+    return lib().mfo_unweight_uniform(seed, it, event)
+
+
+def unweight(w, w_max, seed, it):
+    """keep[e] = sign(w_e) if u_e w_max < |w_e| else 0; returns (keep, n_kept, n_over)."""
+    w = _f64(w)
+    keep = np.zeros(len(w), dtype=np.int8)
+    over = C.c_uint64()
+    n = lib().mfo_unweight(len(w), _d(w), w_max, seed, it,
+                           keep.ctypes.data_as(C.POINTER(C.c_byte)), C.byref(over))
+    return keep, int(n), int(over.value)
+
+
+def lab_event(proc: Process, sqrt_s, grid, seed, it, event):
+    """Lab-frame momenta [n_f + 2][4] of event e (beams, t, tbar, gluons) and a
+    status: 0, 1 below threshold, 2 Newton failure."""
+    grid = _f64(grid)
+    p = np.zeros((proc.n_g + 2, 4))
+    pc = proc.c()
+    st = lib().mfo_lab_event(C.byref(pc), sqrt_s, grid.shape[1] - 1, _d(grid), seed, it, event, _d(p))
+    return p, st

@@ -3,59 +3,12 @@
 Philox4x32-10 is fixed by its published definition (Salmon, Moraes, Dror,
 Shaw, SC'11).  The oracle's rounds are compared with an independent
 open-source implementation, PyTorch's header-only ATen/core/PhiloxRNGEngine.h,
-compiled here as a test-only reference.
+compiled as a test-only reference (the torch_philox fixture of conftest.py).
 """
-import os
-import shutil
-import subprocess
-import tempfile
-
 import numpy as np
 import pytest
 
 import oracle as O
-
-TORCH_INC = None
-try:
-    import torch
-    TORCH_INC = os.path.join(os.path.dirname(torch.__file__), "include")
-except Exception:  # pragma: no cover
-    pass
-
-REF_SRC = r"""
-#include <ATen/core/PhiloxRNGEngine.h>
-#include <cstdio>
-#include <cinttypes>
-int main() {
-  unsigned long long seed, ev, sub;
-  while (std::scanf("%llu %llu %llu", &seed, &ev, &sub) == 3) {
-    at::Philox4_32 eng(seed, sub, ev);   /* counter = (ev_lo, ev_hi, sub_lo, sub_hi) */
-    uint32_t a = eng(), b = eng(), c = eng(), d = eng();
-    std::printf("%u %u %u %u\n", a, b, c, d);
-  }
-}
-"""
-
-
-@pytest.fixture(scope="module")
-def torch_philox(tmp_path_factory):
-    if TORCH_INC is None or not os.path.exists(os.path.join(TORCH_INC, "ATen/core/PhiloxRNGEngine.h")):
-        pytest.skip("PyTorch Philox header not available")
-    if shutil.which("g++") is None:
-        pytest.skip("g++ not available")
-    d = tmp_path_factory.mktemp("philox")
-    src = d / "ref.cpp"
-    src.write_text(REF_SRC)
-    exe = d / "ref"
-    subprocess.run(["g++", "-std=c++17", "-O1", f"-I{TORCH_INC}", str(src), "-o", str(exe)],
-                   check=True, capture_output=True)
-
-    def run(triples):
-        inp = "\n".join(f"{s} {e} {b}" for s, e, b in triples) + "\n"
-        out = subprocess.run([str(exe)], input=inp, capture_output=True, text=True, check=True)
-        return [list(map(int, l.split())) for l in out.stdout.strip().splitlines()]
-    return run
-
 
 def test_philox_matches_independent_implementation(torch_philox):
     rng = np.random.default_rng(7)
