@@ -98,6 +98,8 @@ typedef struct {
     double *iter_amp_ms;     /* host [n_iter] profile = 1: of which the helicity-amplitude code, ms, may be NULL
                                 (n_g >= 3 run it as a kernel of its own; for n_g = 2 it equals iter_event_ms) */
     uint64_t n_batches;      /* event batches per iteration (n_g >= 3: up to 2^27 events each), else 1 */
+    double *grid_last;       /* host [D][n_bins+1] the grid the last iteration ran on (the one
+                                its weights belong to), may be NULL */
 } mf_result;
 
 /* Fills *opt with the defaults shown above. */
@@ -207,6 +209,52 @@ mf_status mf_evaluate_grad(const mf_process *proc, double sqrt_s, const mf_pdf_g
                            const double *grid, const double *y, const uint64_t *event_ids,
                            uint64_t n, uint64_t seed, int iter, const mf_options *opt,
                            double *w_out, double *dw_dy, double *dw_dmt);
+
+/*
+ * Hit-or-miss unweighting (Sec. 2.5: the weighted events of an iteration
+ * become unit-weight events for the LHE output).  Not a step of the
+ * integration itself: it runs on the weights one iteration left behind.
+ *
+ * Event e (0 <= e < n) of weight w[e] is kept when u_e * w_max < |w[e]|
+ * (FP64 product, then comparison), with u_e = k 2^-53 and k the top 53 bits
+ * of the first two words of the Philox4x32-10 block with counter
+ * (e mod 2^32, e >> 32, iter, 0x80000000) and key seed; the integrand uses
+ * blocks 0 .. ceil(D/2) - 1 of the same counters only.  A kept event
+ * carries the sign of w[e] (unit weight in units of w_max).  Zero and NaN
+ * weights are never kept; |w[e]| >= w_max is always kept.  Kept events are
+ * written in increasing e.
+ */
+typedef struct {
+    uint64_t capacity;       /* records the arrays below can hold (0: count only)       */
+    uint64_t *event;         /* device [capacity] event indices; required if capacity > 0 */
+    double *p;               /* device [capacity][n_f + 2][4] (E, px, py, pz) in GeV in the
+                                hadronic frame: gluon a (+z, x1 sqrt(s)/2), gluon b (-z,
+                                x2 sqrt(s)/2), t, tbar, final gluons; may be NULL        */
+    int8_t *sign;            /* device [capacity] sign of the kept weight, may be NULL  */
+    uint64_t n_kept;         /* out: events kept (only the first `capacity` are written) */
+    uint64_t n_over;         /* out: events with |w| > w_max                             */
+} mf_events;
+
+/*
+ * mf_unweight -- keep events of one iteration by hit-or-miss.
+ *   proc, sqrt_s: as in mf_integrate (the cuts are not re-applied: an event
+ *                 with w = 0 is never kept).
+ *   grid:   host [D][n_bins+1], the grid the weights were computed on
+ *           (mf_result.grid_last after mf_integrate), NULL = uniform.
+ *   w:      device [n] weights in pb (mf_result.weights); n <= 2^40, n = 0
+ *           returns no events.
+ *   seed, iter: the Philox key and the iteration index the weights were
+ *           drawn with (mf_integrate: start_iter + n_iter - 1 for its last
+ *           iteration).
+ *   w_max:  finite, > 0 (mf_result.w_max).
+ *   opt:    n_bins and max_newton as for the integration; stream.
+ * The kinematics of each kept event are regenerated from its counter with
+ * the same draw, VEGAS map and phase space as the integration.  Synchronises
+ * the stream.
+ */
+mf_status mf_unweight(const mf_process *proc, double sqrt_s, const double *grid, const double *w,
+                      uint64_t n, uint64_t seed, int iter, double w_max, const mf_options *opt,
+                      mf_events *out);
 
 /* Message for the last non-OK status on this thread. */
 const char *mf_last_error(void);

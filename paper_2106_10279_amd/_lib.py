@@ -43,7 +43,7 @@ class mf_result(C.Structure):
                 ("hist", _dp), ("weights", _dp), ("n_pass", C.c_int64),
                 ("n_newton_fail", C.c_int64), ("event_kernel_ms", C.c_double),
                 ("reduce_kernel_ms", C.c_double), ("iter_pass", _dp), ("iter_event_ms", _dp),
-                ("iter_amp_ms", _dp), ("n_batches", C.c_uint64)]
+                ("iter_amp_ms", _dp), ("n_batches", C.c_uint64), ("grid_last", _dp)]
 
 
 class mf_grad_result(C.Structure):
@@ -51,9 +51,14 @@ class mf_grad_result(C.Structure):
                 ("iter_dalphas", _dp), ("dw_dy", _dp), ("dw_dmt", _dp)]
 
 
+class mf_events(C.Structure):
+    _fields_ = [("capacity", C.c_uint64), ("event", C.c_void_p), ("p", C.c_void_p),
+                ("sign", C.c_void_p), ("n_kept", C.c_uint64), ("n_over", C.c_uint64)]
+
+
 EXPORTS = ("mf_default_options", "mf_n_dims", "mf_integrate", "mf_evaluate", "mf_refine_grid",
            "mf_colour_matrix", "mf_matrix_element", "mf_integrate_grad", "mf_evaluate_grad",
-           "mf_last_error")
+           "mf_unweight", "mf_last_error")
 
 
 class MFError(RuntimeError):
@@ -96,6 +101,10 @@ def load():
     L.mf_matrix_element.argtypes = [C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_uint64,
                                     C.c_double, C.c_double, C.c_void_p, C.c_void_p]
     L.mf_matrix_element.restype = C.c_int
+    L.mf_unweight.argtypes = [C.POINTER(mf_process), C.c_double, _dp, C.c_void_p, C.c_uint64,
+                              C.c_uint64, C.c_int, C.c_double, C.POINTER(mf_options),
+                              C.POINTER(mf_events)]
+    L.mf_unweight.restype = C.c_int
     L.mf_last_error.argtypes = []
     L.mf_last_error.restype = C.c_char_p
     return L

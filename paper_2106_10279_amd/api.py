@@ -9,6 +9,7 @@
     evaluate_weights_grad(...)  per-event weights with dw/dy and dw/dm_t (mf_evaluate_grad)
     CrossSection            torch.autograd.Function: sigma(m_t, alpha_s)
     EventWeights            torch.autograd.Function: w(y, m_t) per event
+    unweight(...)           hit-or-miss unweighting of an iteration's weights (mf_unweight)
 """
 from __future__ import annotations
 
@@ -107,6 +108,7 @@ class IntegrationResult:
     iter_event_ms: np.ndarray | None = None
     iter_amp_ms: np.ndarray | None = None
     n_batches: int = 1
+    grid_last: np.ndarray | None = None
 
 
 def integrate(proc: Process, sqrt_s: float, pdf_table, n_events: int, n_iter: int, seed: int,
@@ -138,13 +140,15 @@ def integrate(proc: Process, sqrt_s: float, pdf_table, n_events: int, n_iter: in
     res.iter_pass = _ptr(npass)
     res.iter_event_ms = _ptr(tms)
     res.iter_amp_ms = _ptr(ams)
+    grid_last = np.zeros((D, n_bins + 1))
+    res.grid_last = _ptr(grid_last)
     pc = proc.c()
     check(lib.mf_integrate(C.byref(pc), sqrt_s, C.byref(pdf.c), n_events, n_iter, seed,
                            C.byref(opt), C.byref(res)))
     return IntegrationResult(res.sigma, res.sigma_err, res.chi2_dof, res.w_max, res.n_pass,
                              res.n_newton_fail, I, V, grid, hist, w, res.event_kernel_ms,
                              res.reduce_kernel_ms, npass, tms if profile else None,
-                             ams if profile else None, res.n_batches)
+                             ams if profile else None, res.n_batches, grid_last)
 
 
 def evaluate_weights(proc: Process, sqrt_s: float, pdf_table, n: int, seed: int = 0, it: int = 0,
@@ -331,3 +335,49 @@ class EventWeights(torch.autograd.Function):
         _, dy, dm = evaluate_weights_grad(p, sqrt_s, pdf_table, yc.shape[0], grid=grid, y=yc)
         g = grad_w.detach().to(torch.float64)
         return g[:, None] * dy, (g * dm).sum().to(ctx.mt_device), None, None, None, None
+
+
+@dataclass
+class UnweightedEvents:
+    event: torch.Tensor        # int64 [n_kept] event indices, ascending
+    p: torch.Tensor | None     # float64 [n_kept, n_f + 2, 4] lab-frame (E, px, py, pz): beams, t, tbar, gluons
+    sign: torch.Tensor         # int8 [n_kept] sign of the kept weight
+    n_kept: int
+    n_over: int                # events with |w| > w_max
+
+
+def unweight(proc: Process, sqrt_s: float, weights: torch.Tensor, w_max: float, seed: int, it: int,
+             grid=None, n_bins: int = 50, max_newton: int = 50, stream=None,
+             momenta: bool = True, capacity: int | None = None) -> UnweightedEvents:
+    """Hit-or-miss unweighting (mf_unweight): event e is kept when
+    u_e w_max < |w_e| with u_e from Philox block 0x80000000 of its counter.
+    `grid` is the grid the weights were computed on (IntegrationResult.grid_last)
+    and `it` their Philox iteration index.  With capacity=None a counting
+    call sizes the output first."""
+    assert weights.is_cuda and weights.dtype == torch.float64 and weights.is_contiguous()
+    n = weights.numel()
+    n_f = n_dims(proc.process)
+    n_f = {4: 2, 7: 3, 10: 4}[n_f]
+    g = None if grid is None else np.ascontiguousarray(grid, dtype=np.float64)
+    opt = _options(n_bins, 1.5, 0, "fp64", False, max_newton, None, stream)
+    pc = proc.c()
+    wp = C.c_void_p(weights.data_ptr())
+    if capacity is None:
+        ev = _lib.mf_events()
+        check(lib.mf_unweight(C.byref(pc), sqrt_s, _ptr(g) if g is not None else None, wp, n, seed, it,
+                              w_max, C.byref(opt), C.byref(ev)))
+        capacity = int(ev.n_kept)
+    dev = weights.device
+    event = torch.empty(capacity, dtype=torch.int64, device=dev)
+    sign = torch.empty(capacity, dtype=torch.int8, device=dev)
+    p = torch.empty((capacity, n_f + 2, 4), dtype=torch.float64, device=dev) if momenta else None
+    ev = _lib.mf_events()
+    ev.capacity = capacity
+    ev.event = C.c_void_p(event.data_ptr()) if capacity else None
+    ev.sign = C.c_void_p(sign.data_ptr()) if capacity else None
+    ev.p = C.c_void_p(p.data_ptr()) if (p is not None and capacity) else None
+    check(lib.mf_unweight(C.byref(pc), sqrt_s, _ptr(g) if g is not None else None, wp, n, seed, it,
+                          w_max, C.byref(opt), C.byref(ev)))
+    k = min(capacity, int(ev.n_kept))
+    return UnweightedEvents(event[:k], p[:k] if p is not None else None, sign[:k], int(ev.n_kept),
+                            int(ev.n_over))

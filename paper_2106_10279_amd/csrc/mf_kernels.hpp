@@ -353,23 +353,16 @@ __device__ __forceinline__ double event_me2(const TabT<NG, T>* tab, T* obj, int 
     }
 }
 
-// Phase 1 of one event (one lane): Philox words or caller uniforms, integer
-// bins, the VEGAS map, threshold, phase space with the massive rescaling,
-// cuts and the two PDFs.  Returns the flags (bit 0 above threshold, bit 1
-// Newton failed, bit 2 passed the cuts).  For a passing event the momenta
-// and the beam energy go to mom[0 .. 4 NF] and pref = J_V W f1 f2 / (2 s_hat);
-// otherwise pref = 0 and mom is untouched.  bins[d * bin_stride] receives the
-// bin of dimension d; k53_out, bins_out and record of P are written if set.
-template <int NF>
-__device__ __forceinline__ int event_kinematics(const EventParams& P, uint64_t ev, const double* s_rows,
-                                                const double* s_lx, const double* s_lq, unsigned short* bins,
-                                                size_t bin_stride, double* mom, double& pref)
+// The point of one event in the unit hypercube and its VEGAS map: Philox
+// words (or the caller's uniforms), integer bins, x and J_V (returned).
+// bins[d * bin_stride] receives the bin of dimension d; k53_out and bins_out
+// of P are written if set.
+template <int D>
+__device__ __forceinline__ double draw_point(const EventParams& P, uint64_t ev, double (&x)[D],
+                                             unsigned short* bins, size_t bin_stride)
 {
-    constexpr int D = 2 + 3 * NF - 4;
     const int nb = P.n_bins;
     const uint32_t key0 = (uint32_t)P.seed, key1 = (uint32_t)(P.seed >> 32);
-    pref = 0.0;
-    double x[D];
     double jac = 1.0;
     if (P.y_in) {
 #pragma unroll
@@ -411,6 +404,25 @@ __device__ __forceinline__ int event_kinematics(const EventParams& P, uint64_t e
             }
         }
     }
+    return jac;
+}
+
+// Phase 1 of one event (one lane): the point and its VEGAS map, threshold,
+// phase space with the massive rescaling, cuts and the two PDFs.  Returns
+// the flags (bit 0 above threshold, bit 1 Newton failed, bit 2 passed the
+// cuts).  For a passing event the momenta and the beam energy go to
+// mom[0 .. 4 NF] and pref = J_V W f1 f2 / (2 s_hat); otherwise pref = 0 and
+// mom is untouched.  bins[d * bin_stride] receives the bin of dimension d;
+// k53_out, bins_out and record of P are written if set.
+template <int NF>
+__device__ __forceinline__ int event_kinematics(const EventParams& P, uint64_t ev, const double* s_rows,
+                                                const double* s_lx, const double* s_lq, unsigned short* bins,
+                                                size_t bin_stride, double* mom, double& pref)
+{
+    constexpr int D = 2 + 3 * NF - 4;
+    pref = 0.0;
+    double x[D];
+    const double jac = draw_point<D>(P, ev, x, bins, bin_stride);
     const double x1 = x[0], x2 = x[1];
     const double shat = x1 * x2 * P.sqrt_s * P.sqrt_s;
     const double thr = 2.0 * P.m_top;

@@ -17,6 +17,7 @@
 #include "mf.h"
 #include "mf_grad.hpp"
 #include "mf_kernels.hpp"
+#include "mf_unweight.hpp"
 
 namespace {
 
@@ -67,6 +68,7 @@ struct Workspace {
     std::mutex lock;
     Buffer grid[2], log_x, log_q2, xf, partials, entries, iter_I, iter_V, iter_pass, stats, gpartials, gsum;
     Buffer st_mom, st_pref, st_me, st_bins, st_flags;   // per-event hand-over of the three-kernel form
+    Buffer uw_counts, uw_offsets;                        // unweighting: per-workgroup counts and offsets
     int n_cu = 0;
 };
 
@@ -610,6 +612,8 @@ mf_status integrate_impl(const mf_process* proc, double sqrt_s, const mf_pdf_gri
     MF_HIP(hipMemcpyAsync(stats.data(), ws.stats.ptr, sizeof(double) * 4, hipMemcpyDeviceToHost, S.stream));
     if (res->grid)
         MF_HIP(hipMemcpyAsync(res->grid, ws.grid[cur].ptr, grid_bytes, hipMemcpyDeviceToHost, S.stream));
+    if (res->grid_last)
+        MF_HIP(hipMemcpyAsync(res->grid_last, ws.grid[1 - cur].ptr, grid_bytes, hipMemcpyDeviceToHost, S.stream));
     if (res->hist)
         MF_HIP(hipMemcpyAsync(res->hist, (double*)ws.entries.ptr + mf::kPartialHead, sizeof(double) * D * (size_t)nb,
                               hipMemcpyDeviceToHost, S.stream));
@@ -850,6 +854,119 @@ mf_status mf_refine_grid(int n_dims, int n_bins, double alpha, const double* his
     hipLaunchKernelGGL(mf::refine_kernel, dim3(1), dim3(256), 0, s, R);
     MF_HIP(hipGetLastError());
     MF_HIP(hipStreamSynchronize(s));
+    return MF_OK;
+}
+
+mf_status mf_unweight(const mf_process* proc, double sqrt_s, const double* grid, const double* w, uint64_t n,
+                      uint64_t seed, int iter, double w_max, const mf_options* opt, mf_events* out)
+{
+    int ng = 0;
+    mf_status st;
+    if (!out)
+        return fail(MF_EINVAL, "out is NULL");
+    if ((st = validate_process(proc, sqrt_s, &ng)) != MF_OK) return st;
+    const int D = 2 + 3 * ng - 4;
+    if ((st = validate_options(opt, D)) != MF_OK) return st;
+    if (n > (1ull << 40))
+        return fail(MF_EINVAL, "n must be at most 2^40");
+    if (n > 0 && !w)
+        return fail(MF_EINVAL, "w is NULL");
+    if (iter < 0)
+        return fail(MF_EINVAL, "iter must be >= 0");
+    if (!finite_pos(w_max))
+        return fail(MF_EINVAL, "w_max must be finite and > 0");
+    if (out->capacity > 0 && !out->event)
+        return fail(MF_EINVAL, "event is NULL while capacity > 0");
+    const int nb = opt->n_bins;
+    if (grid)
+        for (int d = 0; d < D; ++d) {
+            const double* e = grid + (size_t)d * (nb + 1);
+            if (e[0] != 0.0 || e[nb] != 1.0 || !ascending(e, nb + 1))
+                return fail(MF_EINVAL, "grid rows must rise strictly from 0 to 1");
+        }
+    if (n == 0) {
+        out->n_kept = 0;
+        out->n_over = 0;
+        return MF_OK;
+    }
+    Workspace* wsp = nullptr;
+    if ((st = device_workspace(&wsp)) != MF_OK) return st;
+    Workspace& ws = *wsp;
+    std::lock_guard<std::mutex> lock(ws.lock);
+    hipStream_t stream = (hipStream_t)opt->stream;
+
+    mf::UnweightParams U;
+    std::memset(&U, 0, sizeof(U));
+    mf::EventParams& P = U.P;
+    P.n_g = ng;
+    P.n_dims = D;
+    P.n_bins = nb;
+    P.max_newton = opt->max_newton;
+    P.n_events = n;
+    P.seed = seed;
+    P.iter = (uint32_t)iter;
+    P.sqrt_s = sqrt_s;
+    P.s_had = sqrt_s * sqrt_s;
+    P.m_top = proc->m_top;
+    P.ps_const = std::pow(2.0 * mf::kPi, 4 - 3 * ng) * std::pow(mf::kPi / 2.0, ng - 1) /
+                 (factorial(ng - 1) * factorial(ng - 2));
+    const size_t grid_bytes = sizeof(double) * D * (size_t)(nb + 1);
+    if ((st = ensure(ws.grid[0], grid_bytes)) != MF_OK) return st;
+    std::vector<double> g((size_t)D * (nb + 1));
+    if (grid)
+        std::memcpy(g.data(), grid, grid_bytes);
+    else
+        for (int d = 0; d < D; ++d)
+            for (int i = 0; i <= nb; ++i)
+                g[(size_t)d * (nb + 1) + i] = (double)i / (double)nb;
+    MF_HIP(hipMemcpyAsync(ws.grid[0].ptr, g.data(), grid_bytes, hipMemcpyHostToDevice, stream));
+    P.grid = (const double*)ws.grid[0].ptr;
+
+    // contiguous event ranges of at least 16 chunks, at most 65536 workgroups
+    const uint64_t chunk = mf::kBlock;
+    uint64_t per = (n + 65535) / 65536;
+    per = (per + chunk - 1) / chunk * chunk;
+    if (per < 16 * chunk)
+        per = 16 * chunk;
+    const uint64_t n_blocks = (n + per - 1) / per;
+    U.w = w;
+    U.n = n;
+    U.w_max = w_max;
+    U.per_block = per;
+    if ((st = ensure(ws.uw_counts, sizeof(uint64_t) * 2 * n_blocks)) != MF_OK) return st;
+    if ((st = ensure(ws.uw_offsets, sizeof(uint64_t) * n_blocks)) != MF_OK) return st;
+    U.counts = (uint64_t*)ws.uw_counts.ptr;
+    hipLaunchKernelGGL(mf::unweight_count_kernel, dim3((unsigned)n_blocks), dim3(mf::kBlock), 0, stream, U);
+    MF_HIP(hipGetLastError());
+    std::vector<uint64_t> counts(2 * n_blocks), offsets(n_blocks);
+    MF_HIP(hipMemcpyAsync(counts.data(), ws.uw_counts.ptr, sizeof(uint64_t) * 2 * n_blocks, hipMemcpyDeviceToHost,
+                          stream));
+    MF_HIP(hipStreamSynchronize(stream));
+    uint64_t kept = 0, over = 0;
+    for (uint64_t b = 0; b < n_blocks; ++b) {
+        offsets[b] = kept;
+        kept += counts[2 * b];
+        over += counts[2 * b + 1];
+    }
+    if (out->capacity > 0 && kept > 0) {
+        MF_HIP(hipMemcpyAsync(ws.uw_offsets.ptr, offsets.data(), sizeof(uint64_t) * n_blocks, hipMemcpyHostToDevice,
+                              stream));
+        U.offsets = (const uint64_t*)ws.uw_offsets.ptr;
+        U.capacity = out->capacity;
+        U.ev_out = out->event;
+        U.p_out = out->p;
+        U.sign_out = out->sign;
+        switch (ng) {
+        case 2: hipLaunchKernelGGL(mf::unweight_write_kernel<2>, dim3((unsigned)n_blocks), dim3(mf::kBlock), 0, stream, U); break;
+        case 3: hipLaunchKernelGGL(mf::unweight_write_kernel<3>, dim3((unsigned)n_blocks), dim3(mf::kBlock), 0, stream, U); break;
+        default: hipLaunchKernelGGL(mf::unweight_write_kernel<4>, dim3((unsigned)n_blocks), dim3(mf::kBlock), 0, stream, U); break;
+        }
+        MF_HIP(hipGetLastError());
+        // the host offsets must outlive the copy
+        MF_HIP(hipStreamSynchronize(stream));
+    }
+    out->n_kept = kept;
+    out->n_over = over;
     return MF_OK;
 }
 

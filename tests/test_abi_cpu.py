@@ -27,7 +27,7 @@ def test_header_declares_the_expected_entry_points():
     names = declared_functions()
     for n in ("mf_integrate", "mf_evaluate", "mf_refine_grid", "mf_colour_matrix",
               "mf_matrix_element", "mf_last_error", "mf_n_dims", "mf_default_options",
-              "mf_integrate_grad", "mf_evaluate_grad"):
+              "mf_integrate_grad", "mf_evaluate_grad", "mf_unweight"):
         assert n in names
 
 
@@ -116,3 +116,42 @@ def test_max_batch_above_the_cap_rejected_without_device(L, pdf_table):
                       stream=0, max_batch=(1 << 27) + 1)
     assert e.value.status == L.MF_EINVAL
     assert b"max_batch" in L.lib.mf_last_error()
+
+
+def _unweight_call(L, process="gg_ttxgg", sqrt_s=13000.0, grid=None, w=None, n=10, it=0, w_max=1.0,
+                   capacity=0, event=None):
+    from paper_2106_10279_amd import api
+    o = L.mf_options()
+    L.lib.mf_default_options(C.byref(o))
+    proc = api.Process(process).c()
+    ev = L.mf_events()
+    ev.capacity = capacity
+    ev.event = event
+    g = None if grid is None else np.ascontiguousarray(grid, dtype=np.float64)
+    st = L.lib.mf_unweight(C.byref(proc), sqrt_s, g.ctypes.data_as(C.POINTER(C.c_double)) if g is not None
+                           else None, w, n, 0, it, w_max, C.byref(o), C.byref(ev))
+    return st, ev
+
+
+@pytest.mark.parametrize("bad", [dict(w_max=0.0), dict(w_max=float("inf")), dict(w_max=float("nan")),
+                                 dict(it=-1), dict(sqrt_s=300.0), dict(n=(1 << 40) + 1),
+                                 dict(w=None), dict(capacity=5)])
+def test_unweight_validation_without_device(L, bad):
+    kw = dict(w=C.c_void_p(16))   # never dereferenced: every case fails validation first
+    kw.update(bad)
+    st, _ = _unweight_call(L, **kw)
+    assert st == L.MF_EINVAL, L.lib.mf_last_error()
+
+
+def test_unweight_rejects_bad_grid_without_device(L):
+    grid = np.tile(np.arange(51) / 50, (10, 1))
+    grid[3, 7] = grid[3, 6]
+    st, _ = _unweight_call(L, w=C.c_void_p(16), grid=grid)
+    assert st == L.MF_EINVAL
+    assert b"grid" in L.lib.mf_last_error()
+
+
+def test_unweight_of_no_events_returns_nothing_without_device(L):
+    st, ev = _unweight_call(L, w=None, n=0)
+    assert st == L.MF_OK
+    assert ev.n_kept == 0 and ev.n_over == 0

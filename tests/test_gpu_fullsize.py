@@ -106,3 +106,59 @@ def test_ttxgg_fp32_1e8_sampled_events_and_integral(api, oracle_lib, pdf_table):
     torch.cuda.empty_cache()
     print(f"  integral FP32 vs FP64 over 1e8 events: rel {abs(I32 / I64 - 1):.2e}")
     assert abs(I32 / I64 - 1.0) < 1e-6
+
+
+def test_ttxgg_1e7_unweighting_sampled_events_and_properties(api, oracle_lib, pdf_table):
+    """Hit-or-miss unweighting of the second 1e7-event iteration: the kept count
+    against its binomial expectation, order and signs on all events, and
+    sampled kept and rejected events against the oracle's own weight, uniform
+    and lab record (w_max, the largest of the 1e7 weights, and the grid of the
+    iteration are the step's inputs that the oracle takes from the run)."""
+    import math
+    import torch
+    O = oracle_lib
+    proc = api.Process("gg_ttxgg", **_cuts())
+    N = 10_000_000
+    r = api.integrate(proc, SQRT_S, pdf_table, N, 2, 0, keep_weights=True)
+    w = r.weights
+    ev = api.unweight(proc, SQRT_S, w, r.w_max, 0, 1, grid=r.grid_last)
+    a = (w.abs() / r.w_max).clamp(max=1.0)
+    mean, var = float(a.sum().item()), float((a * (1 - a)).sum().item())
+    print(f"\n  1e7 unweighting: kept {ev.n_kept}, expected {mean:.1f} +- {math.sqrt(var):.1f}, "
+          f"over w_max {ev.n_over}")
+    assert abs(ev.n_kept - mean) < 5 * math.sqrt(var) + 1
+    e = ev.event
+    assert bool((e[1:] > e[:-1]).all())
+    assert torch.equal(ev.sign.to(torch.float64), torch.sign(w[e]))
+    op = O.Process(n_g=4, **_cuts())
+    rng = np.random.default_rng(31)
+    kept = e.cpu().numpy()
+    p = ev.p.cpu().numpy()
+    worst, checked, border = 0.0, 0, 0
+    for i in rng.choice(len(kept), size=min(64, len(kept)), replace=False):
+        k = int(kept[i])
+        w_o, info = O.event_weight(op, SQRT_S, pdf_table, r.grid_last, 0, 1, k)
+        u = O.unweight_uniform(0, 1, k)
+        if info.near_edge or info.ill_conditioned or abs(u * r.w_max - abs(w_o)) <= 1e-9 * abs(w_o):
+            border += 1
+            continue
+        assert u * r.w_max < abs(w_o)
+        q, st = O.lab_event(op, SQRT_S, r.grid_last, 0, 1, k)
+        assert st == 0
+        worst = max(worst, np.abs(p[i] - q).max() / (0.5 * SQRT_S))
+        checked += 1
+    kept_set = set(kept.tolist())
+    rejected = 0
+    for k in rng.choice(N, size=64, replace=False):
+        if int(k) in kept_set:
+            continue
+        w_o, info = O.event_weight(op, SQRT_S, pdf_table, r.grid_last, 0, 1, int(k))
+        u = O.unweight_uniform(0, 1, int(k))
+        if info.near_edge or info.ill_conditioned or abs(u * r.w_max - abs(w_o)) <= 1e-9 * max(abs(w_o), 1e-300):
+            continue
+        assert not (u * r.w_max < abs(w_o))
+        rejected += 1
+    print(f"  {checked} kept events checked (records max |dp|/E_beam {worst:.1e}), {border} borderline; "
+          f"{rejected} rejected events confirmed")
+    assert checked > 40 and rejected > 40
+    assert worst < 1e-12
