@@ -167,6 +167,47 @@ def adjoint_run(api, torch, pdf, n_events, n_iter, seed):
             "dsigma_dalphas_pb": g.dsigma_dalphas}
 
 
+PEAK_HBM_GBS = 8000.0        # MI355X HBM3E
+
+
+def unweight_run(api, torch, proc, pdf, grid, n_events, seed, n_f, reps=5):
+    """Hit-or-miss unweighting (mf_unweight: count pass, host scan, ordered
+    write pass with lab-frame records) of one extra iteration's weights on the
+    refined grid, timed with HIP events on the call's stream (median of reps).
+    Algorithmic bytes: the 8-byte weight of every event, and per kept event
+    its record (8-byte index, 1-byte sign, (n_f + 2) x 4 doubles)."""
+    it = 1000
+    r = api.integrate(proc, 13000.0, pdf, n_events, 1, seed, grid_in=grid, start_iter=it,
+                      keep_weights=True)
+    w = r.weights
+    first = api.unweight(proc, 13000.0, w, r.w_max, seed, it, grid=r.grid_last)
+    cap = first.n_kept
+    stream = torch.cuda.current_stream()
+    times = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        ev = api.unweight(proc, 13000.0, w, r.w_max, seed, it, grid=r.grid_last, capacity=cap)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+        assert ev.n_kept == cap
+    t = float(np.median(times)) / 1e3
+    rec = 8 + 1 + (n_f + 2) * 32
+    alg = n_events * 8 + cap * rec
+    achieved = alg / t / 1e9
+    del w, r, first, ev
+    torch.cuda.empty_cache()
+    return {"workload": f"hit-or-miss unweighting of {n_events} {proc.process} weights (one "
+                        f"iteration on the refined grid) with lab-frame records",
+            "value": round(n_events / t, 2), "unit": "events/s", "kept": cap,
+            "efficiency": round(cap / n_events, 6), "ms_per_call": round(t * 1e3, 4),
+            "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": PEAK_HBM_GBS,
+                         "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+                         "kernel": "mf_unweight (count + write kernels, host scan between)",
+                         "bytes_per_call": alg}}
+
+
 def cpu_baseline(wl, pdf, budget_s):
     """The oracle on a bounded sample of the same workload: one iteration on a
     uniform grid, sized by two calibration runs to about budget_s seconds."""
@@ -207,6 +248,7 @@ def main():
                     help="events per iteration of the FP32-amplitude leg (gg_ttxgg at 1e8)")
     ap.add_argument("--fp32-steps", type=int, default=3)
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-unweight", action="store_true")
     ap.add_argument("--adjoint-events", type=int, default=10_000_000)
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device-to-device copy of this many bytes (3 times), "
@@ -258,6 +300,12 @@ def main():
         "result_pb": {"sigma": r64.sigma, "sigma_err": r64.sigma_err, "chi2_dof": r64.chi2_dof},
         "stream_timed_s": round(ev64, 4),
     }
+    if not args.no_unweight:
+        log(f"[bench] unweighting {n_events} weights")
+        out["unweight"] = unweight_run(api, torch, proc, pdf, r64.grid, n_events, args.seed,
+                                       wl["n_g"])
+        log(f"[bench] unweighting done: {out['unweight']['ms_per_call']} ms per call, "
+            f"{out['unweight']['kept']} kept")
     if not args.no_fp32:
         n32 = args.fp32_events if args.workload == "ttxgg" else n_events
         log(f"[bench] fp32 amplitudes with fp64 compensated accumulation: {args.warmup} warm-up + "

@@ -68,7 +68,7 @@ struct Workspace {
     std::mutex lock;
     Buffer grid[2], log_x, log_q2, xf, partials, entries, iter_I, iter_V, iter_pass, stats, gpartials, gsum;
     Buffer st_mom, st_pref, st_me, st_bins, st_flags;   // per-event hand-over of the three-kernel form
-    Buffer uw_counts, uw_offsets;                        // unweighting: per-workgroup counts and offsets
+    Buffer uw_counts, uw_flags, uw_totals;               // unweighting: per-workgroup counts, keep flags, totals
     int n_cu = 0;
 };
 
@@ -922,49 +922,47 @@ mf_status mf_unweight(const mf_process* proc, double sqrt_s, const double* grid,
     MF_HIP(hipMemcpyAsync(ws.grid[0].ptr, g.data(), grid_bytes, hipMemcpyHostToDevice, stream));
     P.grid = (const double*)ws.grid[0].ptr;
 
-    // contiguous event ranges of at least 16 chunks, at most 65536 workgroups
-    const uint64_t chunk = mf::kBlock;
-    uint64_t per = (n + 65535) / 65536;
-    per = (per + chunk - 1) / chunk * chunk;
-    if (per < 16 * chunk)
-        per = 16 * chunk;
+    // contiguous event ranges of whole write tiles, at most 2048 workgroups
+    // (each write workgroup sums the counts of those before it)
+    const uint64_t tile = mf::kUnweightTile;
+    uint64_t per = (n + 2047) / 2048;
+    per = (per + tile - 1) / tile * tile;
     const uint64_t n_blocks = (n + per - 1) / per;
     U.w = w;
     U.n = n;
     U.w_max = w_max;
     U.per_block = per;
     if ((st = ensure(ws.uw_counts, sizeof(uint64_t) * 2 * n_blocks)) != MF_OK) return st;
-    if ((st = ensure(ws.uw_offsets, sizeof(uint64_t) * n_blocks)) != MF_OK) return st;
+    if ((st = ensure(ws.uw_flags, (n + 15) / 16 * 16)) != MF_OK) return st;
+    if ((st = ensure(ws.uw_totals, sizeof(uint64_t) * 2)) != MF_OK) return st;
     U.counts = (uint64_t*)ws.uw_counts.ptr;
+    U.flags = (signed char*)ws.uw_flags.ptr;
+    U.totals = (uint64_t*)ws.uw_totals.ptr;
+    U.n_blocks = n_blocks;
     hipLaunchKernelGGL(mf::unweight_count_kernel, dim3((unsigned)n_blocks), dim3(mf::kBlock), 0, stream, U);
     MF_HIP(hipGetLastError());
-    std::vector<uint64_t> counts(2 * n_blocks), offsets(n_blocks);
-    MF_HIP(hipMemcpyAsync(counts.data(), ws.uw_counts.ptr, sizeof(uint64_t) * 2 * n_blocks, hipMemcpyDeviceToHost,
-                          stream));
-    MF_HIP(hipStreamSynchronize(stream));
-    uint64_t kept = 0, over = 0;
-    for (uint64_t b = 0; b < n_blocks; ++b) {
-        offsets[b] = kept;
-        kept += counts[2 * b];
-        over += counts[2 * b + 1];
-    }
-    if (out->capacity > 0 && kept > 0) {
-        MF_HIP(hipMemcpyAsync(ws.uw_offsets.ptr, offsets.data(), sizeof(uint64_t) * n_blocks, hipMemcpyHostToDevice,
-                              stream));
-        U.offsets = (const uint64_t*)ws.uw_offsets.ptr;
-        U.capacity = out->capacity;
-        U.ev_out = out->event;
-        U.p_out = out->p;
-        U.sign_out = out->sign;
+    U.capacity = out->capacity;
+    U.ev_out = out->event;
+    U.p_out = out->p;
+    U.sign_out = out->sign;
+    hipLaunchKernelGGL(mf::unweight_write_kernel, dim3((unsigned)n_blocks), dim3(mf::kBlock), 0, stream, U);
+    MF_HIP(hipGetLastError());
+    if (out->p && out->capacity > 0) {
+        const uint64_t recs = out->capacity < n ? out->capacity : n;
+        const uint64_t rb = (recs + mf::kBlock - 1) / mf::kBlock;
+        const dim3 grid((unsigned)(rb < 65536 ? rb : 65536));
+        const uint64_t* tot = (const uint64_t*)ws.uw_totals.ptr;
         switch (ng) {
-        case 2: hipLaunchKernelGGL(mf::unweight_write_kernel<2>, dim3((unsigned)n_blocks), dim3(mf::kBlock), 0, stream, U); break;
-        case 3: hipLaunchKernelGGL(mf::unweight_write_kernel<3>, dim3((unsigned)n_blocks), dim3(mf::kBlock), 0, stream, U); break;
-        default: hipLaunchKernelGGL(mf::unweight_write_kernel<4>, dim3((unsigned)n_blocks), dim3(mf::kBlock), 0, stream, U); break;
+        case 2: hipLaunchKernelGGL(mf::unweight_record_kernel<2>, grid, dim3(mf::kBlock), 0, stream, U, tot); break;
+        case 3: hipLaunchKernelGGL(mf::unweight_record_kernel<3>, grid, dim3(mf::kBlock), 0, stream, U, tot); break;
+        default: hipLaunchKernelGGL(mf::unweight_record_kernel<4>, grid, dim3(mf::kBlock), 0, stream, U, tot); break;
         }
         MF_HIP(hipGetLastError());
-        // the host offsets must outlive the copy
-        MF_HIP(hipStreamSynchronize(stream));
     }
+    uint64_t totals[2] = {0, 0};
+    MF_HIP(hipMemcpyAsync(totals, ws.uw_totals.ptr, sizeof(totals), hipMemcpyDeviceToHost, stream));
+    MF_HIP(hipStreamSynchronize(stream));
+    const uint64_t kept = totals[0], over = totals[1];
     out->n_kept = kept;
     out->n_over = over;
     return MF_OK;

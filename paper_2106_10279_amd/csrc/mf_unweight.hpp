@@ -7,10 +7,12 @@
 // (e mod 2^32, e >> 32, iter, 0x80000000); the integrand draws only from
 // blocks 0 .. ceil(D/2) - 1.  A kept event carries the sign of w_e.
 //
-// Two passes over contiguous event ranges, one range per workgroup: a count
-// pass (kept and above-w_max events per workgroup), a host-side exclusive
-// scan, and a write pass that ranks the kept events of each 256-event chunk
-// with wave ballots, so that records come out in increasing event index.
+// Kernels over contiguous event ranges, one range per workgroup: a count
+// pass that forms the keep flag (the sign, or 0) of every event and counts
+// kept and above-w_max events per workgroup, and a write pass in which every
+// thread reads 16 consecutive flags and places its kept events after a
+// workgroup scan, so that records come out in increasing event index.  A
+// last kernel, one thread per written record, adds the lab-frame momenta.
 // For each kept event the write pass regenerates the phase-space point from
 // its counter (the same draw and map as the integration) and stores the
 // lab-frame momenta.
@@ -27,17 +29,18 @@ struct UnweightParams {
     double w_max;
     uint64_t per_block;      // events per workgroup, a multiple of kBlock
     uint64_t* counts;        // [n_blocks][2]: kept, above w_max (count pass)
-    const uint64_t* offsets; // [n_blocks] first record of each workgroup (write pass)
+    signed char* flags;      // [n] sign of each kept event, 0 for the others (count pass)
+    uint64_t* totals;        // [2]: kept, above w_max over all events (write pass)
+    uint64_t n_blocks;
     uint64_t capacity;
     uint64_t* ev_out;        // [capacity]
     double* p_out;           // [capacity][NF + 2][4] or null
     signed char* sign_out;   // [capacity] or null
 };
 
-__device__ __forceinline__ bool keep_event(const UnweightParams& U, uint64_t e, bool& over, signed char& sign)
+__device__ __forceinline__ bool keep_w(const UnweightParams& U, uint64_t e, double w, bool& over, signed char& sign)
 {
 #pragma clang fp contract(off)
-    const double w = U.w[e];
     const double a = fabs(w);
     const uint32_t key0 = (uint32_t)U.P.seed, key1 = (uint32_t)(U.P.seed >> 32);
     uint32_t r[4];
@@ -48,6 +51,9 @@ __device__ __forceinline__ bool keep_event(const UnweightParams& U, uint64_t e, 
     sign = w > 0.0 ? 1 : -1;
     return u * U.w_max < a;
 }
+
+constexpr int kUnweightTile = 16 * kBlock;   // events per tile of a workgroup's range
+constexpr int kUnweightSeg = kUnweightTile / kBlock;
 
 __device__ __forceinline__ uint64_t block_sum_u64(uint64_t v, uint64_t* s_red)
 {
@@ -70,11 +76,25 @@ __global__ void __launch_bounds__(kBlock) unweight_count_kernel(UnweightParams U
     const uint64_t start = (uint64_t)blockIdx.x * U.per_block;
     const uint64_t end = start + U.per_block < U.n ? start + U.per_block : U.n;
     uint64_t kept = 0, over = 0;
-    for (uint64_t e = start + threadIdx.x; e < end; e += kBlock) {
-        bool ov;
-        signed char sg;
-        kept += keep_event(U, e, ov, sg) ? 1 : 0;
-        over += ov ? 1 : 0;
+    for (uint64_t t0 = start; t0 < end; t0 += kUnweightTile) {
+        double wv[kUnweightSeg];
+#pragma unroll
+        for (int i = 0; i < kUnweightSeg; ++i) {
+            const uint64_t e = t0 + (uint64_t)(i * kBlock) + threadIdx.x;
+            wv[i] = e < end ? U.w[e] : 0.0;
+        }
+#pragma unroll
+        for (int i = 0; i < kUnweightSeg; ++i) {
+            const uint64_t e = t0 + (uint64_t)(i * kBlock) + threadIdx.x;
+            if (e < end) {
+                bool ov;
+                signed char sg;
+                const bool k = keep_w(U, e, wv[i], ov, sg);
+                U.flags[e] = k ? sg : 0;
+                kept += k ? 1 : 0;
+                over += ov ? 1 : 0;
+            }
+        }
     }
     kept = block_sum_u64(kept, s_red);
     over = block_sum_u64(over, s_red);
@@ -120,45 +140,106 @@ __device__ bool lab_momenta(const EventParams& P, uint64_t e, double* out)
     return true;
 }
 
-template <int NF>
+// Exclusive prefix sum over the threads of a workgroup (wave scans, then the
+// wave totals through LDS); *total receives the workgroup's sum.
+__device__ __forceinline__ uint64_t block_exclusive_scan(uint64_t v, uint64_t* s_wave, uint64_t* total)
+{
+    const int wv = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    uint64_t incl = v;
+    for (int off = 1; off < kWave; off <<= 1) {
+        const uint64_t o = __shfl_up(incl, off, kWave);
+        if (lane >= off)
+            incl += o;
+    }
+    if (lane == kWave - 1)
+        s_wave[wv] = incl;
+    __syncthreads();
+    uint64_t before = 0, all = 0;
+    for (int i = 0; i < kWavesPerBlock; ++i) {
+        before += i < wv ? s_wave[i] : 0;
+        all += s_wave[i];
+    }
+    __syncthreads();
+    *total = all;
+    return before + incl - v;
+}
+
+// The workgroup's range in tiles of 4096 events; each thread reads the
+// flags of 16 consecutive events (one 16-byte load), and after a workgroup
+// scan writes the index and sign of its kept events in event order.  The
+// workgroup's first record follows the kept events of all workgroups before
+// it (summed here from the count pass); workgroup 0 also writes the totals.
 __global__ void __launch_bounds__(kBlock) unweight_write_kernel(UnweightParams U)
 {
-    __shared__ uint64_t s_cnt[kWavesPerBlock];
-    const int wv = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    const uint64_t start = (uint64_t)blockIdx.x * U.per_block;
-    const uint64_t end = start + U.per_block < U.n ? start + U.per_block : U.n;
-    uint64_t base = U.offsets[blockIdx.x];
-    for (uint64_t c0 = start; c0 < end; c0 += kBlock) {
-        const uint64_t e = c0 + threadIdx.x;
-        bool over = false;
-        signed char sign = 0;
-        const bool keep = e < end && keep_event(U, e, over, sign);
-        const uint64_t mask = __ballot(keep);
-        if (lane == 0)
-            s_cnt[wv] = (uint64_t)__popcll(mask);
-        __syncthreads();
-        uint64_t before = 0, total = 0;
-        for (int i = 0; i < kWavesPerBlock; ++i) {
-            before += i < wv ? s_cnt[i] : 0;
-            total += s_cnt[i];
+    __shared__ uint64_t s_wave[kWavesPerBlock];
+    const uint64_t b = blockIdx.x;
+    uint64_t pre = 0;
+    for (uint64_t i = threadIdx.x; i < b; i += kBlock)
+        pre += U.counts[2 * i];
+    uint64_t base = block_sum_u64(pre, s_wave);
+    if (b == 0) {
+        uint64_t k = 0, o = 0;
+        for (uint64_t i = threadIdx.x; i < U.n_blocks; i += kBlock) {
+            k += U.counts[2 * i];
+            o += U.counts[2 * i + 1];
         }
-        const uint64_t below = mask & ((1ull << lane) - 1ull);
-        const uint64_t slot = base + before + (uint64_t)__popcll(below);
-        if (keep && slot < U.capacity) {
-            U.ev_out[slot] = e;
-            if (U.sign_out)
-                U.sign_out[slot] = sign;
-            if (U.p_out) {
-                double q[4 * (NF + 2)];
-                if (!lab_momenta<NF>(U.P, e, q))
-                    for (int i = 0; i < 4 * (NF + 2); ++i)
-                        q[i] = 0.0;
-                for (int i = 0; i < 4 * (NF + 2); ++i)
-                    U.p_out[slot * (4 * (NF + 2)) + i] = q[i];
+        k = block_sum_u64(k, s_wave);
+        o = block_sum_u64(o, s_wave);
+        if (threadIdx.x == 0) {
+            U.totals[0] = k;
+            U.totals[1] = o;
+        }
+    }
+    const uint64_t start = b * U.per_block;
+    const uint64_t end = start + U.per_block < U.n ? start + U.per_block : U.n;
+    for (uint64_t t0 = start; t0 < end; t0 += kUnweightTile) {
+        const uint64_t e0 = t0 + (uint64_t)kUnweightSeg * threadIdx.x;
+        signed char f[kUnweightSeg];
+        if (e0 + kUnweightSeg <= end) {
+            const int4 v = *reinterpret_cast<const int4*>(U.flags + e0);
+            const int words[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int j = 0; j < kUnweightSeg; ++j)
+                f[j] = (signed char)((unsigned)words[j / 4] >> (8 * (j % 4)));
+        } else {
+#pragma unroll
+            for (int j = 0; j < kUnweightSeg; ++j)
+                f[j] = e0 + j < end ? U.flags[e0 + j] : 0;
+        }
+        uint64_t cnt = 0;
+#pragma unroll
+        for (int j = 0; j < kUnweightSeg; ++j)
+            cnt += f[j] != 0 ? 1 : 0;
+        uint64_t total;
+        uint64_t slot = base + block_exclusive_scan(cnt, s_wave, &total);
+#pragma unroll
+        for (int j = 0; j < kUnweightSeg; ++j) {
+            if (f[j] == 0)
+                continue;
+            if (slot < U.capacity) {
+                U.ev_out[slot] = e0 + j;
+                if (U.sign_out)
+                    U.sign_out[slot] = f[j];
             }
+            ++slot;
         }
         base += total;
-        __syncthreads();
+    }
+}
+
+// Lab-frame record of every written event (slots below min(capacity, kept)).
+template <int NF>
+__global__ void __launch_bounds__(kBlock) unweight_record_kernel(UnweightParams U, const uint64_t* totals)
+{
+    const uint64_t kept = totals[0] < U.capacity ? totals[0] : U.capacity;
+    for (uint64_t slot = (uint64_t)blockIdx.x * kBlock + threadIdx.x; slot < kept;
+         slot += (uint64_t)gridDim.x * kBlock) {
+        double q[4 * (NF + 2)];
+        if (!lab_momenta<NF>(U.P, U.ev_out[slot], q))
+            for (int i = 0; i < 4 * (NF + 2); ++i)
+                q[i] = 0.0;
+        for (int i = 0; i < 4 * (NF + 2); ++i)
+            U.p_out[slot * (4 * (NF + 2)) + i] = q[i];
     }
 }
 
