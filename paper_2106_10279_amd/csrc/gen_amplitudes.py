@@ -606,6 +606,16 @@ class CoopLayout:
         return self.base[c], sg, c
 
 
+def pext_py(x, m):
+    """Bits of x at the set positions of m, packed in order (as pext4)."""
+    r, k = 0, 0
+    for i in range(4):
+        if (m >> i) & 1:
+            r |= ((x >> i) & 1) << k
+            k += 1
+    return r
+
+
 def posmask(part, whole):
     srt = sorted(whole)
     m = 0
@@ -623,26 +633,44 @@ def emit_coop(n, lay, co, K, perms):
     tables = []
     for L in range(2, n + 1):
         seqs = co.levels[L]
-        pr, tr, ni, bs = [], [], [], []
+        ni, bs = [], []
         for sq in seqs:
-            for k in range(1, L):
-                p1, p2 = sq[:k], sq[k:]
-                b1, s1, _ = co.obj(p1)
-                b2, s2, _ = co.obj(p2)
-                pr.append(f"{{{b1}, {b2}, {s1}, {s2}, {posmask(p1, sq)}, {posmask(p2, sq)}, "
-                          f"{lay.P[mask(p1)]}, {lay.P[mask(p2)]}}}")
-            for a in range(1, L):
-                for b in range(a + 1, L):
-                    q1, q2, q3 = sq[:a], sq[a:b], sq[b:]
-                    o1, o2, o3 = co.obj(q1), co.obj(q2), co.obj(q3)
-                    tr.append(f"{{{o1[0]}, {o2[0]}, {o3[0]}, {o1[1]}, {o2[1]}, {o3[1]}, "
-                              f"{posmask(q1, sq)}, {posmask(q2, sq)}, {posmask(q3, sq)}}}")
             ni.append(str(lay.ninv[mask(sq)]))
             bs.append(str(co.base[sq]))
         npair, ntrip = L - 1, (L - 1) * (L - 2) // 2
-        tables.append(f"static constexpr GPair GJ{n}_L{L}_PAIR[{len(pr)}] = {{{', '.join(pr)}}};")
-        if tr:
-            tables.append(f"static constexpr GTrip GJ{n}_L{L}_TRIP[{len(tr)}] = {{{', '.join(tr)}}};")
+        # per stage item (sequence si, helicity pattern hm) and operand split:
+        # the object indices of the sub-currents with their signs, and for the
+        # two-current splits the table offsets of the two momenta, packed as
+        #   pairs:   off1 | off2 << 9 | neg << 18 | p1 << 32 | p2 << 48
+        #   triples: off1 | off2 << 9 | off3 << 18 | neg << 27
+        # where neg is the sign of the product of the sub-current signs: the
+        # three- and four-gluon vertices are linear in each sub-current, so
+        # the split's contribution carries that product once
+        px, tx = [], []
+        for si, sq in enumerate(seqs):
+            for hm in range(1 << L):
+                for k in range(1, L):
+                    p1, p2 = sq[:k], sq[k:]
+                    b1, s1, _ = co.obj(p1)
+                    b2, s2, _ = co.obj(p2)
+                    o1 = b1 + pext_py(hm, posmask(p1, sq))
+                    o2 = b2 + pext_py(hm, posmask(p2, sq))
+                    P1, P2 = lay.P[mask(p1)], lay.P[mask(p2)]
+                    assert o1 < 512 and o2 < 512 and P1 < 65536 and P2 < 65536
+                    px.append(o1 | o2 << 9 | ((s1 * s2) < 0) << 18 | P1 << 32 | P2 << 48)
+                for a in range(1, L):
+                    for b in range(a + 1, L):
+                        q1, q2, q3 = sq[:a], sq[a:b], sq[b:]
+                        ob = [co.obj(q) for q in (q1, q2, q3)]
+                        offs = [ob[i][0] + pext_py(hm, posmask(q, sq)) for i, q in enumerate((q1, q2, q3))]
+                        assert max(offs) < 512
+                        tx.append(offs[0] | offs[1] << 9 | offs[2] << 18
+                                  | ((ob[0][1] * ob[1][1] * ob[2][1]) < 0) << 27)
+        tables.append(f"static constexpr unsigned long long GJ{n}_L{L}_PAIRX[{len(px)}] = "
+                      f"{{{', '.join(f'{v}ull' for v in px)}}};")
+        if tx:
+            tables.append(f"static constexpr unsigned int GJ{n}_L{L}_TRIPX[{len(tx)}] = "
+                          f"{{{', '.join(f'{v}u' for v in tx)}}};")
         tables.append(f"static constexpr short GJ{n}_L{L}_NINV[{len(ni)}] = {{{', '.join(ni)}}};")
         tables.append(f"static constexpr int GJ{n}_L{L}_BASE[{len(bs)}] = {{{', '.join(bs)}}};")
     pairs = co.pairs
@@ -679,38 +707,37 @@ def emit_coop(n, lay, co, K, perms):
         w("        T a0 = 0, a1 = 0, a2 = 0, a3 = 0;")
         w("#pragma unroll")
         w(f"        for (int k = 0; k < {npair}; ++k) {{")
-        w(f"            const GPair sp = GJ{n}_L{L}_PAIR[si * {npair} + k];")
-        w(f"            const T* q1 = al16(obj + {co.gj} + 4 * (sp.b1 + pext4(hm, sp.m1)));")
-        w(f"            const T* q2 = al16(obj + {co.gj} + 4 * (sp.b2 + pext4(hm, sp.m2)));")
-        w("            const T g1 = (T)sp.s1, g2 = (T)sp.s2;")
+        w(f"            const unsigned long long sp = GJ{n}_L{L}_PAIRX[it * {npair} + k];")
+        w("            const unsigned lo = (unsigned)sp, hi = (unsigned)(sp >> 32);")
+        w(f"            const T* q1 = al16(obj + {co.gj} + 4 * (int)(lo & 511u));")
+        w(f"            const T* q2 = al16(obj + {co.gj} + 4 * (int)((lo >> 9) & 511u));")
+        w("            const T g = (lo >> 18) & 1u ? (T)-1 : (T)1;")
         w("            T j1[4], j2[4];")
         w("            ld4(q1, j1); ld4(q2, j2);")
-        w("            for (int i = 0; i < 4; ++i) { j1[i] *= g1; j2[i] *= g2; }")
-        w("            const T* p1 = tab + sp.p1; const T* p2 = tab + sp.p2;")
+        w("            const T* p1 = tab + (hi & 0xffffu); const T* p2 = tab + (hi >> 16);")
         w("            const T P1[4] = {(T)p1[0], (T)p1[1], (T)p1[2], (T)p1[3]};")
         w("            const T P2[4] = {(T)p2[0], (T)p2[1], (T)p2[2], (T)p2[3]};")
         w("            const T c1 = (T)2 * (P1[0] * j2[0] - P1[1] * j2[1] - P1[2] * j2[2] - P1[3] * j2[3]);")
         w("            const T c2 = (T)2 * (P2[0] * j1[0] - P2[1] * j1[1] - P2[2] * j1[2] - P2[3] * j1[3]);")
         w("            const T c12 = j1[0] * j2[0] - j1[1] * j2[1] - j1[2] * j2[2] - j1[3] * j2[3];")
         for mu in range(4):
-            w(f"            a{mu} += j1[{mu}] * c1 - j2[{mu}] * c2 + c12 * (P2[{mu}] - P1[{mu}]);")
+            w(f"            a{mu} += g * (j1[{mu}] * c1 - j2[{mu}] * c2 + c12 * (P2[{mu}] - P1[{mu}]));")
         w("        }")
         if ntrip:
             w("#pragma unroll")
             w(f"        for (int k = 0; k < {ntrip}; ++k) {{")
-            w(f"            const GTrip tp = GJ{n}_L{L}_TRIP[si * {ntrip} + k];")
-            w(f"            const T* q1 = al16(obj + {co.gj} + 4 * (tp.b1 + pext4(hm, tp.m1)));")
-            w(f"            const T* q2 = al16(obj + {co.gj} + 4 * (tp.b2 + pext4(hm, tp.m2)));")
-            w(f"            const T* q3 = al16(obj + {co.gj} + 4 * (tp.b3 + pext4(hm, tp.m3)));")
-            w("            const T g1 = (T)tp.s1, g2 = (T)tp.s2, g3 = (T)tp.s3;")
+            w(f"            const unsigned tp = GJ{n}_L{L}_TRIPX[it * {ntrip} + k];")
+            w(f"            const T* q1 = al16(obj + {co.gj} + 4 * (int)(tp & 511u));")
+            w(f"            const T* q2 = al16(obj + {co.gj} + 4 * (int)((tp >> 9) & 511u));")
+            w(f"            const T* q3 = al16(obj + {co.gj} + 4 * (int)((tp >> 18) & 511u));")
+            w("            const T g = (tp >> 27) & 1u ? (T)-1 : (T)1;")
             w("            T j1[4], j2[4], j3[4];")
             w("            ld4(q1, j1); ld4(q2, j2); ld4(q3, j3);")
-            w("            for (int i = 0; i < 4; ++i) { j1[i] *= g1; j2[i] *= g2; j3[i] *= g3; }")
             w("            const T d23 = j2[0] * j3[0] - j2[1] * j3[1] - j2[2] * j3[2] - j2[3] * j3[3];")
             w("            const T d13 = j1[0] * j3[0] - j1[1] * j3[1] - j1[2] * j3[2] - j1[3] * j3[3];")
             w("            const T d12 = j1[0] * j2[0] - j1[1] * j2[1] - j1[2] * j2[2] - j1[3] * j2[3];")
             for mu in range(4):
-                w(f"            a{mu} += j1[{mu}] * d23 - (T)2 * j2[{mu}] * d13 + j3[{mu}] * d12;")
+                w(f"            a{mu} += g * (j1[{mu}] * d23 - (T)2 * j2[{mu}] * d13 + j3[{mu}] * d12);")
             w("        }")
         w(f"        const T f = (T)tab[GJ{n}_L{L}_NINV[si]];")
         w(f"        T* o = al16(obj + {co.gj} + 4 * (GJ{n}_L{L}_BASE[si] + hm));")
