@@ -74,7 +74,7 @@ def timed_run(api, torch, proc, pdf, n_events, steps, warmup, precision, seed):
 
 # Sources of the event kernel; HBM traffic measured with rocprofv3 counters is
 # reported only while their hash matches the one recorded with the counters.
-KERNEL_SOURCES = ("mf_kernels.hpp", "mf_device.hpp", "gen_amplitudes.py")
+KERNEL_SOURCES = ("mf_kernels.hpp", "mf_device.hpp", "gen_amplitudes.py", "mf_unweight.hpp")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "amp_kernel_gg_ttxgg_traffic.txt")
 
 
@@ -171,11 +171,12 @@ PEAK_HBM_GBS = 8000.0        # MI355X HBM3E
 
 
 def unweight_run(api, torch, proc, pdf, grid, n_events, seed, n_f, reps=5):
-    """Hit-or-miss unweighting (mf_unweight: count pass, host scan, ordered
-    write pass with lab-frame records) of one extra iteration's weights on the
-    refined grid, timed with HIP events on the call's stream (median of reps).
-    Algorithmic bytes: the 8-byte weight of every event, and per kept event
-    its record (8-byte index, 1-byte sign, (n_f + 2) x 4 doubles)."""
+    """Hit-or-miss unweighting (mf_unweight: count, write and record kernels)
+    of one extra iteration's weights on the refined grid.  The call is timed
+    with HIP events on its stream (median of reps); the roofline is that of its
+    dominant kernel, the count pass (Philox uniform and decision per event),
+    from the library's HIP-event timing of that kernel: algorithmic bytes are
+    the 8-byte weight of every event."""
     it = 1000
     r = api.integrate(proc, 13000.0, pdf, n_events, 1, seed, grid_in=grid, start_iter=it,
                       keep_weights=True)
@@ -183,29 +184,35 @@ def unweight_run(api, torch, proc, pdf, grid, n_events, seed, n_f, reps=5):
     first = api.unweight(proc, 13000.0, w, r.w_max, seed, it, grid=r.grid_last)
     cap = first.n_kept
     stream = torch.cuda.current_stream()
-    times = []
+    times, kms = [], []
     for _ in range(reps):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
-        ev = api.unweight(proc, 13000.0, w, r.w_max, seed, it, grid=r.grid_last, capacity=cap)
+        ev = api.unweight(proc, 13000.0, w, r.w_max, seed, it, grid=r.grid_last, capacity=cap,
+                          profile=True)
         e1.record(stream)
         torch.cuda.synchronize()
         times.append(e0.elapsed_time(e1))
+        kms.append(ev.kernel_ms)
         assert ev.n_kept == cap
     t = float(np.median(times)) / 1e3
-    rec = 8 + 1 + (n_f + 2) * 32
-    alg = n_events * 8 + cap * rec
-    achieved = alg / t / 1e9
+    kms = np.array(kms)
+    tc = float(kms[:, 0].mean()) / 1e3
+    alg = n_events * 8
+    achieved = alg / tc / 1e9
     del w, r, first, ev
     torch.cuda.empty_cache()
     return {"workload": f"hit-or-miss unweighting of {n_events} {proc.process} weights (one "
                         f"iteration on the refined grid) with lab-frame records",
             "value": round(n_events / t, 2), "unit": "events/s", "kept": cap,
             "efficiency": round(cap / n_events, 6), "ms_per_call": round(t * 1e3, 4),
+            "kernel_ms": {"count": round(tc * 1e3, 4), "write": round(float(kms[:, 1].mean()), 4),
+                          "record": round(float(kms[:, 2].mean()), 4)},
             "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": PEAK_HBM_GBS,
-                         "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
-                         "kernel": "mf_unweight (count + write kernels, host scan between)",
-                         "bytes_per_call": alg}}
+                         "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
+                         "traffic": measured_traffic(f"unweight_count_{n_events}"),
+                         "kernel": "unweight_count_kernel", "launches": reps,
+                         "avg_launch_ms": round(tc * 1e3, 4), "bytes_per_launch": alg}}
 
 
 def cpu_baseline(wl, pdf, budget_s):

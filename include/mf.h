@@ -233,6 +233,8 @@ typedef struct {
     int8_t *sign;            /* device [capacity] sign of the kept weight, may be NULL  */
     uint64_t n_kept;         /* out: events kept (only the first `capacity` are written) */
     uint64_t n_over;         /* out: events with |w| > w_max                             */
+    double kernel_ms[3];     /* out, options->profile = 1: durations of the count, write
+                                and record kernels in ms (0 when not run)                */
 } mf_events;
 
 /*

@@ -53,7 +53,8 @@ class mf_grad_result(C.Structure):
 
 class mf_events(C.Structure):
     _fields_ = [("capacity", C.c_uint64), ("event", C.c_void_p), ("p", C.c_void_p),
-                ("sign", C.c_void_p), ("n_kept", C.c_uint64), ("n_over", C.c_uint64)]
+                ("sign", C.c_void_p), ("n_kept", C.c_uint64), ("n_over", C.c_uint64),
+                ("kernel_ms", C.c_double * 3)]
 
 
 EXPORTS = ("mf_default_options", "mf_n_dims", "mf_integrate", "mf_evaluate", "mf_refine_grid",

@@ -344,11 +344,12 @@ class UnweightedEvents:
     sign: torch.Tensor         # int8 [n_kept] sign of the kept weight
     n_kept: int
     n_over: int                # events with |w| > w_max
+    kernel_ms: tuple | None = None   # profile=True: count, write, record kernel durations
 
 
 def unweight(proc: Process, sqrt_s: float, weights: torch.Tensor, w_max: float, seed: int, it: int,
              grid=None, n_bins: int = 50, max_newton: int = 50, stream=None,
-             momenta: bool = True, capacity: int | None = None) -> UnweightedEvents:
+             momenta: bool = True, capacity: int | None = None, profile: bool = False) -> UnweightedEvents:
     """Hit-or-miss unweighting (mf_unweight): event e is kept when
     u_e w_max < |w_e| with u_e from Philox block 0x80000000 of its counter.
     `grid` is the grid the weights were computed on (IntegrationResult.grid_last)
@@ -359,7 +360,7 @@ def unweight(proc: Process, sqrt_s: float, weights: torch.Tensor, w_max: float, 
     n_f = n_dims(proc.process)
     n_f = {4: 2, 7: 3, 10: 4}[n_f]
     g = None if grid is None else np.ascontiguousarray(grid, dtype=np.float64)
-    opt = _options(n_bins, 1.5, 0, "fp64", False, max_newton, None, stream)
+    opt = _options(n_bins, 1.5, 0, "fp64", False, max_newton, None, stream, profile)
     pc = proc.c()
     wp = C.c_void_p(weights.data_ptr())
     if capacity is None:
@@ -380,4 +381,4 @@ def unweight(proc: Process, sqrt_s: float, weights: torch.Tensor, w_max: float, 
                           w_max, C.byref(opt), C.byref(ev)))
     k = min(capacity, int(ev.n_kept))
     return UnweightedEvents(event[:k], p[:k] if p is not None else None, sign[:k], int(ev.n_kept),
-                            int(ev.n_over))
+                            int(ev.n_over), tuple(ev.kernel_ms) if profile else None)

@@ -939,15 +939,33 @@ mf_status mf_unweight(const mf_process* proc, double sqrt_s, const double* grid,
     U.flags = (signed char*)ws.uw_flags.ptr;
     U.totals = (uint64_t*)ws.uw_totals.ptr;
     U.n_blocks = n_blocks;
+    // profile: events around the count, write and record kernels
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    struct EventGuard {
+        hipEvent_t* e;
+        ~EventGuard() { for (int i = 0; i < 4; ++i) if (e[i]) (void)hipEventDestroy(e[i]); }
+    } guard{ev};
+    if (opt->profile)
+        for (int i = 0; i < 4; ++i)
+            MF_HIP(hipEventCreate(&ev[i]));
+    for (int i = 0; i < 3; ++i)
+        out->kernel_ms[i] = 0.0;
+    if (opt->profile)
+        MF_HIP(hipEventRecord(ev[0], stream));
     hipLaunchKernelGGL(mf::unweight_count_kernel, dim3((unsigned)n_blocks), dim3(mf::kBlock), 0, stream, U);
     MF_HIP(hipGetLastError());
+    if (opt->profile)
+        MF_HIP(hipEventRecord(ev[1], stream));
     U.capacity = out->capacity;
     U.ev_out = out->event;
     U.p_out = out->p;
     U.sign_out = out->sign;
     hipLaunchKernelGGL(mf::unweight_write_kernel, dim3((unsigned)n_blocks), dim3(mf::kBlock), 0, stream, U);
     MF_HIP(hipGetLastError());
-    if (out->p && out->capacity > 0) {
+    if (opt->profile)
+        MF_HIP(hipEventRecord(ev[2], stream));
+    const bool records = out->p && out->capacity > 0;
+    if (records) {
         const uint64_t recs = out->capacity < n ? out->capacity : n;
         const uint64_t rb = (recs + mf::kBlock - 1) / mf::kBlock;
         const dim3 grid((unsigned)(rb < 65536 ? rb : 65536));
@@ -959,9 +977,22 @@ mf_status mf_unweight(const mf_process* proc, double sqrt_s, const double* grid,
         }
         MF_HIP(hipGetLastError());
     }
+    if (opt->profile)
+        MF_HIP(hipEventRecord(ev[3], stream));
     uint64_t totals[2] = {0, 0};
     MF_HIP(hipMemcpyAsync(totals, ws.uw_totals.ptr, sizeof(totals), hipMemcpyDeviceToHost, stream));
     MF_HIP(hipStreamSynchronize(stream));
+    if (opt->profile) {
+        float t = 0.f;
+        MF_HIP(hipEventElapsedTime(&t, ev[0], ev[1]));
+        out->kernel_ms[0] = t;
+        MF_HIP(hipEventElapsedTime(&t, ev[1], ev[2]));
+        out->kernel_ms[1] = t;
+        if (records) {
+            MF_HIP(hipEventElapsedTime(&t, ev[2], ev[3]));
+            out->kernel_ms[2] = t;
+        }
+    }
     const uint64_t kept = totals[0], over = totals[1];
     out->n_kept = kept;
     out->n_over = over;
