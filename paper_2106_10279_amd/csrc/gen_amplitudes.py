@@ -136,7 +136,10 @@ class CoopTable:
 
     def __init__(self, n):
         self.n = n
-        off = 0
+        # the spinors first: 16-byte aligned for 128-bit LDS reads
+        self.ub = 0
+        self.v = 16
+        off = 32
         self.P = {}
         for m in range(1, 1 << n):
             if bin(m).count("1") <= n - 1:
@@ -156,11 +159,8 @@ class CoopTable:
             if 1 <= bin(m).count("1") <= n - 2:
                 self.Kv[m] = off       # -k_tbar - P[m], and -1/(Kv^2 - m^2 + i m Gamma)
                 off += 6
-        self.ub = off
-        off += 16
-        self.v = off
-        off += 16
-        self.size = off
+        # a multiple of 4 elements, so that every event's table starts aligned
+        self.size = (off + 3) // 4 * 4
 
     def mom_flops(self):
         n = self.n
@@ -813,9 +813,6 @@ def emit_coop(n, lay, co, K, perms):
     # recomputed per event instead of being hoisted out of the event loop
     a('    asm volatile("" : "+v"(hel));')
     a("    const int sT = hel & 1, sB = (hel >> 1) & 1, hg = hel >> 2;")
-    a("    cplx<T> ub[4], v[4];")
-    a(f"    {{ const T* q = tab + {lay.ub} + 8 * sT; for (int i = 0; i < 4; ++i) ub[i] = cplx<T>(q[2 * i], q[2 * i + 1]); }}")
-    a(f"    {{ const T* q = tab + {lay.v} + 8 * sB; for (int i = 0; i < 4; ++i) v[i] = cplx<T>(q[2 * i], q[2 * i + 1]); }}")
     hel_flops = 0
     lex = {sq: i for i, sq in enumerate(perms)}
     nperm_ = len(perms)
@@ -830,20 +827,21 @@ def emit_coop(n, lay, co, K, perms):
         srt = sorted(block)
         return " | ".join(f"(((hg >> {g}) & 1) << {i})" for i, g in enumerate(srt))
 
-    def gj_ptr(block):
+    def gj_ptr(block, ob):
         b, sg, cs = co.obj(block)
-        return f"al16(ob + {co.gj} + 4 * ({b} + ({hexpr(cs)})))", sg
+        return f"al16({ob} + {co.gj} + 4 * ({b} + ({hexpr(cs)})))", sg
 
-    def load_row(X, nm):
+    def row_load(X, nm, ob):
         if not X:
-            return "ub"
-        a(f"        cplx<T> {nm}[4];")
-        a(f"        ldspin(al16(ob + {co.u1} + 8 * (4 * {X[0]} + 2 * sT + ((hg >> {X[0]}) & 1))), {nm});")
-        return nm
+            tb = ob.replace("ob", "tb")
+            return nm, [f"    cplx<T> {nm}[4];", f"    ldspin(al16({tb} + {lay.ub} + 8 * sT), {nm});"]
+        return nm, [f"    cplx<T> {nm}[4];",
+                    f"    ldspin(al16({ob} + {co.u1} + 8 * (4 * {X[0]} + 2 * sT + ((hg >> {X[0]}) & 1))), {nm});"]
 
-    def load_col(Y, nm):
+    def col_load(Y, nm, ob):
         if not Y:
-            return "v"
+            tb = ob.replace("ob", "tb")
+            return nm, [f"    cplx<T> {nm}[4];", f"    ldspin(al16({tb} + {lay.v} + 8 * sB), {nm});"]
         if len(Y) == 1:
             d = Y[0]
             idx = f"{co.v1} + 8 * (4 * {d} + 2 * sB + ((hg >> {d}) & 1))"
@@ -851,9 +849,7 @@ def emit_coop(n, lay, co, K, perms):
             c, d = Y
             pi = co.pairs.index((c, d))
             idx = f"{co.v2} + 8 * ({8 * pi} + 4 * sB + 2 * ((hg >> {c}) & 1) + ((hg >> {d}) & 1))"
-        a(f"        cplx<T> {nm}[4];")
-        a(f"        ldspin(al16(ob + {idx}), {nm});")
-        return nm
+        return nm, [f"    cplx<T> {nm}[4];", f"    ldspin(al16({ob} + {idx}), {nm});"]
 
     # group the terms by bilinear: key (X, Y) -> list of (beta, ordering)
     groups = {}
@@ -864,17 +860,24 @@ def emit_coop(n, lay, co, K, perms):
                 groups.setdefault((X, Y), []).append((beta, sg))
     # Y-major order so that a loaded V is used by all its bilinears in a row
     keys = sorted(groups, key=lambda k: (len(k[1]), k[1], k[0]))
-    for (X, Y) in keys:
-        a("    {")
-        # an opaque zero produced here keeps this group's LDS reads from
-        # being hoisted above it (every hoisted read would hold registers)
-        a("        int z = 0;")
-        a('        asm volatile("" : "+v"(z));')
-        a("        const T* ob = obj + z;")
-        r = load_row(X, "xr")
-        c = load_col(Y, "yc")
-        a("        cplx<T> d[4];")
-        a(f"        bilinear({r}, {c}, d);")
+    # Each group's LDS reads are issued one group ahead: group g + 1's reads
+    # follow an opaque zero produced just before group g's arithmetic, so they
+    # overlap it, while no read can be hoisted further up (each hoisted read
+    # would hold registers).
+    loads, computes = [], []
+    for gi, (X, Y) in enumerate(keys):
+        ob = f"ob{gi}"
+        L = [f"    int z{gi} = 0;", f'    asm volatile("" : "+v"(z{gi}));', f"    const T* {ob} = obj + z{gi};"]
+        if not X or not Y:
+            L.append(f"    const T* tb{gi} = tab + z{gi};")
+        r, lr = row_load(X, f"xr{gi}", ob)
+        c, lc = col_load(Y, f"yc{gi}", ob)
+        L += lr + lc
+        # the currents are read at the start of the group itself (behind a
+        # second opaque zero), in the shadow of the bilinear
+        Cc = ["    {", "        int y = 0;", '        asm volatile("" : "+v"(y));', "        const T* oc = obj + y;"]
+        cur_at = len(Cc)
+        Cc += ["        cplx<T> d[4];", f"        bilinear({r}, {c}, d);"]
         hel_flops += 64
         # distinct currents (up to reflection) met by this bilinear
         byc = {}
@@ -882,46 +885,65 @@ def emit_coop(n, lay, co, K, perms):
             b, sgn, cs = co.obj(beta)
             byc.setdefault(cs, []).append((sgn, sg))
         touched = []
-        for cs, uses in byc.items():
-            ptr, _ = gj_ptr(cs)
+        cur_loads = []
+        for ci, (cs, uses) in enumerate(byc.items()):
+            ptr, _ = gj_ptr(cs, "oc")
+            jn = f"j{ci}"
+            Cc += [f"        T {jn}[4];", f"        ld4({ptr}, {jn});"]
             if len(uses) == 1:
                 # one ordering meets this current: multiply-add into its accumulator
                 sgn, sg = uses[0]
                 k = lex[sg]
                 if k not in sig:
                     sig[k] = sgn
-                    a(f"        cdotj_set(d, {ptr}, Ar[{k}], Ai[{k}]);")
+                    Cc.append(f"        cdot_set({jn}, d, Ar[{k}], Ai[{k}]);")
                     hel_flops += 14
                 else:
-                    a(f"        cdotj_fma<{sgn * sig[k]}>(d, {ptr}, Ar[{k}], Ai[{k}]);")
+                    Cc.append(f"        cdot_fma<{sgn * sig[k]}>({jn}, d, Ar[{k}], Ai[{k}]);")
                     hel_flops += 16
                 if k not in touched:
                     touched.append(k)
                 continue
-            a("        {")
-            a("            T sr, si;")
-            a(f"            cdotj_set(d, {ptr}, sr, si);")
+            Cc.append("        {")
+            Cc.append("            T sr, si;")
+            Cc.append(f"            cdot_set({jn}, d, sr, si);")
             hel_flops += 14
             for (sgn, sg) in uses:
                 k = lex[sg]
                 if k not in sig:
                     sig[k] = sgn
-                    a(f"            Ar[{k}] = sr; Ai[{k}] = si;")
+                    Cc.append(f"            Ar[{k}] = sr; Ai[{k}] = si;")
                 else:
                     op = "+=" if sgn * sig[k] > 0 else "-="
-                    a(f"            Ar[{k}] {op} sr; Ai[{k}] {op} si;")
+                    Cc.append(f"            Ar[{k}] {op} sr; Ai[{k}] {op} si;")
                     hel_flops += 2
                 if k not in touched:
                     touched.append(k)
-            a("        }")
+            Cc.append("        }")
         # the accumulators this group updated pass through an opaque point
         # before the next group starts, so that the group's arithmetic is not
         # deferred to the colour sum with its operands held in registers
         touched.sort()
         for c0 in range(0, len(touched), 4):
             ops = ", ".join(f'"+v"(Ar[{k}]), "+v"(Ai[{k}])' for k in touched[c0:c0 + 4])
-            a(f'        asm volatile("" : {ops});')
-        a("    }")
+            Cc.append(f'        asm volatile("" : {ops});')
+        Cc.append("    }")
+        Cc[cur_at:cur_at] = cur_loads
+        loads.append(L)
+        computes.append(Cc)
+    # two orders of the same statements: spinor reads one group ahead, or
+    # each group's reads at its own start (fewer live registers)
+    head = list(A)
+    A_seq = list(head)
+    A.extend(loads[0])
+    for gi in range(len(keys)):
+        if gi + 1 < len(keys):
+            A.extend(loads[gi + 1])
+        A.extend(computes[gi])
+    for gi in range(len(keys)):
+        A_seq.extend(loads[gi])
+        A_seq.extend(computes[gi])
+    tail_start = len(A)
     untouched = [k for k in range(nperm_) if k not in sig]
     if untouched:
         A[acc_decl] += " " + " ".join(f"Ar[{k}] = 0; Ai[{k}] = 0;" for k in untouched)
@@ -948,7 +970,9 @@ def emit_coop(n, lay, co, K, perms):
         a(f"        me += Ai[{sidx}] * ti;")
         hel_flops += 2
         a("    }")
-    amp = "\n".join(A)
+    A_seq[acc_decl] = A[acc_decl]
+    A_seq.extend(A[tail_start:])
+    amp = ("\n".join(A), "\n".join(A_seq))
     return "\n".join(tables), stages, amp, flops_stage, hel_flops
 
 
@@ -996,10 +1020,28 @@ __device__ __forceinline__ void coop_stages_ng{n}(const T* __restrict__ tab, T* 
 // object store: meet-in-the-middle at the vertex that carries the second
 // gluon of each colour ordering, A = sum Xbar gamma.j(block) Y.
 template <typename T>
+__device__ __forceinline__ double coop_me2_ng{n}_ahead(const T* __restrict__ tab, const T* __restrict__ obj, int hel)
+{{
+{amp[0]}
+    return (double)me / COLOUR_DEN_NG{n};
+}}
+
+template <typename T>
+__device__ __forceinline__ double coop_me2_ng{n}_inplace(const T* __restrict__ tab, const T* __restrict__ obj, int hel)
+{{
+{amp[1]}
+    return (double)me / COLOUR_DEN_NG{n};
+}}
+
+// The spinor reads go one group ahead where the registers allow it without
+// spilling or losing occupancy: FP64 with four final-state partons.
+template <typename T>
 __device__ __forceinline__ double coop_me2_ng{n}(const T* __restrict__ tab, const T* __restrict__ obj, int hel)
 {{
-{amp}
-    return (double)me / COLOUR_DEN_NG{n};
+    if constexpr (sizeof(T) == 8 && {n} == 4)
+        return coop_me2_ng{n}_ahead<T>(tab, obj, hel);
+    else
+        return coop_me2_ng{n}_inplace<T>(tab, obj, hel);
 }}
 """
 

@@ -232,6 +232,29 @@ __device__ __forceinline__ void stspin(T* p, const cplx<T>* s)
     st4(p + 4, s[2].x, s[2].y, s[3].x, s[3].y);
 }
 
+// (ar, ai) = c^mu j_mu for complex c and a real 4-vector j held in registers.
+template <typename T>
+__device__ __forceinline__ void cdot_set(const T* j, const cplx<T>* c, T& ar, T& ai)
+{
+    ar = c[0].x * j[0] - c[1].x * j[1] - c[2].x * j[2] - c[3].x * j[3];
+    ai = c[0].y * j[0] - c[1].y * j[1] - c[2].y * j[2] - c[3].y * j[3];
+}
+
+// (ar, ai) += SGN c^mu j_mu as one multiply-add chain per component.
+template <int SGN, typename T>
+__device__ __forceinline__ void cdot_fma(const T* j, const cplx<T>* c, T& ar, T& ai)
+{
+    const T s = (T)SGN;
+    ar += (s * c[0].x) * j[0];
+    ar -= (s * c[1].x) * j[1];
+    ar -= (s * c[2].x) * j[2];
+    ar -= (s * c[3].x) * j[3];
+    ai += (s * c[0].y) * j[0];
+    ai -= (s * c[1].y) * j[1];
+    ai -= (s * c[2].y) * j[2];
+    ai -= (s * c[3].y) * j[3];
+}
+
 // (ar, ai) = c^mu j_mu for complex c and a real 4-vector j of the object store.
 template <typename T>
 __device__ __forceinline__ void cdotj_set(const cplx<T>* c, const T* jp, T& ar, T& ai)

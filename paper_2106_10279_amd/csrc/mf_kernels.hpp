@@ -481,7 +481,7 @@ __global__ void __launch_bounds__(kBlock) event_kernel(EventParams P)
     __shared__ double s_lx[kMaxPdfX];
     __shared__ double s_rows[4 * kMaxPdfX];
     __shared__ double s_lq[4];
-    __shared__ TabT<NG, T> s_tab[kWavesPerBlock][L::kEventsPerPass][L::kTable];
+    __shared__ __align__(16) TabT<NG, T> s_tab[kWavesPerBlock][L::kEventsPerPass][L::kTable];
     __shared__ __align__(16) T s_obj[kWavesPerBlock][L::kEventsPerPass][L::kObj];
     extern __shared__ double s_hist[];     // [kWavesPerBlock][D][n_bins]
 
@@ -674,7 +674,7 @@ template <int NG, typename T>
 __global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2))) amp_kernel(StageParams S)
 {
     using L = Layout<NG>;
-    __shared__ TabT<NG, T> s_tab[L::kEventsPerPass][L::kTable];
+    __shared__ __align__(16) TabT<NG, T> s_tab[L::kEventsPerPass][L::kTable];
     __shared__ __align__(16) T s_obj[L::kEventsPerPass][L::kObj];
     __shared__ double s_mom[L::kEventsPerPass][L::kMom];
     const int lane = threadIdx.x;
@@ -960,7 +960,7 @@ __global__ void __launch_bounds__(kBlock) me_kernel(const double* __restrict__ m
                                                      uint64_t n, double mt, double mw, double* __restrict__ out)
 {
     using L = Layout<NG>;
-    __shared__ TabT<NG, T> s_tab[kWavesPerBlock][L::kEventsPerPass][L::kTable];
+    __shared__ __align__(16) TabT<NG, T> s_tab[kWavesPerBlock][L::kEventsPerPass][L::kTable];
     __shared__ __align__(16) T s_obj[kWavesPerBlock][L::kEventsPerPass][L::kObj];
     const int lane = threadIdx.x % kWave;
     const int wv = threadIdx.x / kWave;
