@@ -523,10 +523,6 @@ static constexpr int COLOUR_NUM_NG{n}[{nperm * nperm}] = {{{kdecl}}};
     _LAST_COUNT = {"per_helicity": e.hel, "momentum_only": e.mom, "n_hel": 1 << (n + 2),
                    "n_orderings": nperm, "table_doubles": lay.size}
     kdecl = ", ".join(str(v) for row in K for v in row)
-    structs = """
-struct GPair { int b1, b2; signed char s1, s2, m1, m2; short p1, p2; };
-struct GTrip { int b1, b2, b3; signed char s1, s2, s3, m1, m2, m3; };
-"""
     return f"""// Generated by gen_amplitudes.py for g g -> t tbar + {n - 2} gluon(s): {nperm} colour orderings,
 // {1 << (n + 2)} helicity configurations.  Do not edit.
 // Arithmetic per helicity configuration: {e.hel} flops; per event (table): {e.mom} flops.
@@ -558,7 +554,7 @@ __device__ __forceinline__ double colour_summed_me2_ng{n}(const double* __restri
 {body}
     return (double)me / COLOUR_DEN_NG{n};
 }}
-{structs}"""
+"""
 
 
 
@@ -607,7 +603,7 @@ class CoopLayout:
 
 
 def pext_py(x, m):
-    """Bits of x at the set positions of m, packed in order (as pext4)."""
+    """Bits of x at the set positions of m, packed in order."""
     r, k = 0, 0
     for i in range(4):
         if (m >> i) & 1:

@@ -130,19 +130,6 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Bits of x at the set positions of m, packed in order (m < 16).
-__device__ __forceinline__ int pext4(int x, int m)
-{
-    int r = 0, k = 0;
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-        if ((m >> i) & 1) {
-            r |= ((x >> i) & 1) << k;
-            ++k;
-        }
-    return r;
-}
-
 // c^mu = a gamma^mu v = aL sigma^mu vR + aR sigmabar^mu vL.  The four
 // components are sums and differences of four two-term products,
 //   P = a0 v2 + a3 v1,  Q = a1 v3 + a2 v0,  R = a0 v3 - a2 v1,  S = a1 v2 - a3 v0:
@@ -244,33 +231,6 @@ __device__ __forceinline__ void cdot_set(const T* j, const cplx<T>* c, T& ar, T&
 template <int SGN, typename T>
 __device__ __forceinline__ void cdot_fma(const T* j, const cplx<T>* c, T& ar, T& ai)
 {
-    const T s = (T)SGN;
-    ar += (s * c[0].x) * j[0];
-    ar -= (s * c[1].x) * j[1];
-    ar -= (s * c[2].x) * j[2];
-    ar -= (s * c[3].x) * j[3];
-    ai += (s * c[0].y) * j[0];
-    ai -= (s * c[1].y) * j[1];
-    ai -= (s * c[2].y) * j[2];
-    ai -= (s * c[3].y) * j[3];
-}
-
-// (ar, ai) = c^mu j_mu for complex c and a real 4-vector j of the object store.
-template <typename T>
-__device__ __forceinline__ void cdotj_set(const cplx<T>* c, const T* jp, T& ar, T& ai)
-{
-    T j[4];
-    ld4(jp, j);
-    ar = c[0].x * j[0] - c[1].x * j[1] - c[2].x * j[2] - c[3].x * j[3];
-    ai = c[0].y * j[0] - c[1].y * j[1] - c[2].y * j[2] - c[3].y * j[3];
-}
-
-// (ar, ai) += SGN c^mu j_mu as one multiply-add chain per component.
-template <int SGN, typename T>
-__device__ __forceinline__ void cdotj_fma(const cplx<T>* c, const T* jp, T& ar, T& ai)
-{
-    T j[4];
-    ld4(jp, j);
     const T s = (T)SGN;
     ar += (s * c[0].x) * j[0];
     ar -= (s * c[1].x) * j[1];

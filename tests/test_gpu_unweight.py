@@ -56,15 +56,18 @@ def _check_records(n_g, ev, grid, seed, it, idx):
     return worst
 
 
-@pytest.mark.parametrize("n_g", [2, 3, 4])
-def test_keep_decisions_bit_exact_on_identical_weights(api, n_g):
+@pytest.mark.parametrize("n_g,n", [(2, 300_000), (3, 300_000), (4, 300_000), (4, 300_001), (3, 8195),
+                                   (2, 4097), (4, 13), (2, 1)])
+def test_keep_decisions_bit_exact_on_identical_weights(api, n_g, n):
+    """Identical weights on both sides; sizes with ragged 16-event segments,
+    tiles and workgroup ranges, and below one segment."""
     import torch
-    say(f"unweight identical weights n_g={n_g}")
-    rng = np.random.default_rng(40 + n_g)
-    n = 300_000
+    say(f"unweight identical weights n_g={n_g} n={n}")
+    rng = np.random.default_rng(40 + n_g + n)
     w = rng.exponential(1.0, n) * np.where(rng.random(n) < 0.1, -1.0, 1.0)
     w[rng.random(n) < 0.2] = 0.0
-    w[:5] = [np.nan, 0.0, 3.0, -3.0, 1e-300]
+    w[:5] = [np.nan, 0.0, 3.0, -3.0, 1e-300][:n]
+    w[-1] = 2.5                      # the last event is always kept
     w_max = 2.0
     seed, it = 7, 3
     keep_o, n_o, over_o = O.unweight(w, w_max, seed, it)
@@ -73,8 +76,9 @@ def test_keep_decisions_bit_exact_on_identical_weights(api, n_g):
     kept_idx = np.flatnonzero(keep_o)
     assert np.array_equal(ev.event.cpu().numpy(), kept_idx)
     assert np.array_equal(ev.sign.cpu().numpy(), keep_o[kept_idx])
+    assert int(ev.event[-1]) == n - 1
     grid = np.tile(np.arange(51) / 50, (2 + 3 * n_g - 4, 1))
-    sel = np.linspace(0, ev.n_kept - 1, 200).astype(int)
+    sel = np.unique(np.linspace(0, ev.n_kept - 1, 200).astype(int))
     worst = _check_records(n_g, ev, grid, seed, it, sel)
     say(f"  kept {ev.n_kept} of {n}, records max |dp|/E_beam {worst:.1e}")
     assert worst < 1e-12
