@@ -322,6 +322,64 @@ int mfo_integrate(const mfo_process *proc, double sqrt_s, const mfo_pdf_grid *pd
     return 0;
 }
 
+/* Weights of a list of events, split over threads (each event is
+ * independent; the results do not depend on the split). */
+typedef struct {
+    const mfo_process *proc;
+    double sqrt_s;
+    const mfo_pdf_grid *pdf;
+    int n_bins, iter;
+    uint64_t seed, i0, i1;
+    const double *grid;
+    const uint64_t *ids;
+    double *w;
+    int *flags;
+} list_worker;
+
+static void *run_list(void *arg)
+{
+    list_worker *lw = (list_worker *)arg;
+    mfo_event ev;
+    for (uint64_t i = lw->i0; i < lw->i1; ++i) {
+        lw->w[i] = mfo_event_weight(lw->proc, lw->sqrt_s, lw->pdf, lw->n_bins, lw->grid, lw->seed,
+                                    lw->iter, lw->ids[i], &ev);
+        lw->flags[i] = ev.pass_threshold | ev.newton_fail << 1 | ev.pass_cuts << 2 | ev.near_edge << 3
+                       | ev.ill_conditioned << 4;
+    }
+    return NULL;
+}
+
+int mfo_event_weights(const mfo_process *proc, double sqrt_s, const mfo_pdf_grid *pdf, int n_bins,
+                      const double *grid, uint64_t seed, int iter, uint64_t n, const uint64_t *ids,
+                      int n_threads, double *w, int *flags)
+{
+    if (n_threads < 1)
+        return -1;
+    list_worker *lw = calloc((size_t)n_threads, sizeof(list_worker));
+    pthread_t *th = calloc((size_t)n_threads, sizeof(pthread_t));
+    for (int t = 0; t < n_threads; ++t) {
+        list_worker *x = &lw[t];
+        x->proc = proc;
+        x->sqrt_s = sqrt_s;
+        x->pdf = pdf;
+        x->n_bins = n_bins;
+        x->iter = iter;
+        x->seed = seed;
+        x->i0 = n * (uint64_t)t / (uint64_t)n_threads;
+        x->i1 = n * (uint64_t)(t + 1) / (uint64_t)n_threads;
+        x->grid = grid;
+        x->ids = ids;
+        x->w = w;
+        x->flags = flags;
+        pthread_create(&th[t], NULL, run_list, x);
+    }
+    for (int t = 0; t < n_threads; ++t)
+        pthread_join(th[t], NULL);
+    free(lw);
+    free(th);
+    return 0;
+}
+
 /* Closed-form LO g g -> t tbar (zero width), averaged |M|^2 / g^4 in terms of
  * tau_{1,2} = (1 -/+ beta cos theta)/2 and rho = 4 m^2 / s:
  *   (1/(6 tau1 tau2) - 3/8) (tau1^2 + tau2^2 + rho - rho^2/(4 tau1 tau2))

@@ -142,6 +142,13 @@ uint64_t mfo_unweight(uint64_t n, const double *w, double w_max, uint64_t seed, 
 int mfo_lab_event(const mfo_process *proc, double sqrt_s, int n_bins, const double *grid,
                   uint64_t seed, int iter, uint64_t event, double *p);
 
+/* Weights w[i] of events ids[i] of iteration iter on n_threads threads;
+ * flags[i]: bit 0 above threshold, bit 1 Newton failed, bit 2 passed the
+ * cuts, bit 3 near a cut edge, bit 4 ill-conditioned PDF value.           */
+int mfo_event_weights(const mfo_process *proc, double sqrt_s, const mfo_pdf_grid *pdf, int n_bins,
+                      const double *grid, uint64_t seed, int iter, uint64_t n, const uint64_t *ids,
+                      int n_threads, double *w, int *flags);
+
 int mfo_integrate(const mfo_process *proc, double sqrt_s, const mfo_pdf_grid *pdf,
                   uint64_t n_events, int n_iter, uint64_t seed, int start_iter,
                   int n_bins, double alpha, int n_threads,

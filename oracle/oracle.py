@@ -119,6 +119,9 @@ def lib():
         L.mfo_lab_event.argtypes = [C.POINTER(_Process), C.c_double, C.c_int, _dp, C.c_uint64,
                                     C.c_int, C.c_uint64, _dp]
         L.mfo_lab_event.restype = C.c_int
+        L.mfo_event_weights.argtypes = [C.POINTER(_Process), C.c_double, C.POINTER(_Pdf), C.c_int, _dp,
+                                        C.c_uint64, C.c_int, C.c_uint64, _u64p, C.c_int, _dp, _ip]
+        L.mfo_event_weights.restype = C.c_int
         _lib = L
     return _lib
 
@@ -402,3 +405,21 @@ def lab_event(proc: Process, sqrt_s, grid, seed, it, event):
     pc = proc.c()
     st = lib().mfo_lab_event(C.byref(pc), sqrt_s, grid.shape[1] - 1, _d(grid), seed, it, event, _d(p))
     return p, st
+
+
+def event_weights(proc: Process, sqrt_s, table, grid, seed, it, ids, n_threads=None):
+    """Weights of the events `ids` of iteration `it`, threaded; returns (w, flags)
+    with flags bit 0 above threshold, 1 Newton failed, 2 passed the cuts,
+    3 near a cut edge, 4 ill-conditioned PDF value."""
+    h = _PdfHandle(table)
+    grid = _f64(grid)
+    ids = np.ascontiguousarray(ids, dtype=np.uint64)
+    if n_threads is None:
+        n_threads = max(1, min(os.cpu_count() or 1, 16))
+    w = np.zeros(len(ids))
+    flags = np.zeros(len(ids), dtype=np.int32)
+    pc = proc.c()
+    lib().mfo_event_weights(C.byref(pc), sqrt_s, C.byref(h.c), grid.shape[1] - 1, _d(grid), seed, it,
+                            len(ids), ids.ctypes.data_as(_u64p), n_threads, _d(w),
+                            flags.ctypes.data_as(_ip))
+    return w, flags

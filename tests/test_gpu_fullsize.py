@@ -40,23 +40,21 @@ def _check_signs(w):
 
 
 def _spot_check(api, oracle_lib, pdf_table, w_gpu, grid, it, n, k, seed, rtol):
+    """k event indices drawn uniformly from [0, n), recomputed by the oracle
+    (threaded) on the grid of the iteration; returns the per-event relative
+    differences of the usable events and the counts."""
     O = oracle_lib
     rng = np.random.default_rng(seed)
     ids = np.sort(rng.choice(n, size=k, replace=False))
     op = O.Process(n_g=4, **_cuts())
-    worst, used, skipped = 0.0, 0, 0
-    w_gpu = w_gpu[ids].cpu().numpy()
-    for e, wg in zip(ids, w_gpu):
-        w_o, info = O.event_weight(op, SQRT_S, pdf_table, grid, 0, it, int(e))
-        if info.near_edge or info.ill_conditioned:
-            skipped += 1
-            continue
-        if w_o == 0.0:
-            assert wg == 0.0, (e, wg)
-            continue
-        worst = max(worst, abs(wg / w_o - 1.0))
-        used += 1
-    return worst, used, skipped, ids
+    w_o, flags = O.event_weights(op, SQRT_S, pdf_table, grid, 0, it, ids)
+    wg = w_gpu[ids].cpu().numpy()
+    skip = (flags & (8 | 16)) != 0          # near a cut edge, ill-conditioned PDF value
+    zero = (w_o == 0.0) & ~skip
+    assert np.all(wg[zero] == 0.0)
+    use = ~skip & ~zero
+    rel = np.abs(wg[use] / w_o[use] - 1.0)
+    return rel, int(use.sum()), int(skip.sum()), ids
 
 
 def test_ttxgg_fp64_1e7_sampled_events_and_properties(api, oracle_lib, pdf_table):
@@ -72,11 +70,11 @@ def test_ttxgg_fp64_1e7_sampled_events_and_properties(api, oracle_lib, pdf_table
     assert nz == r.n_pass
     mean = float(w.sum().item()) / N
     assert mean == pytest.approx(r.iter_sigma[-1], rel=1e-12)
-    worst, used, skipped, ids = _spot_check(api, oracle_lib, pdf_table, w, g1, 1, N, 96, 21, 1e-12)
-    print(f"\n  1e7 FP64: {used} sampled events up to id {ids.max()}, max rel {worst:.2e}, "
+    rel, used, skipped, ids = _spot_check(api, oracle_lib, pdf_table, w, g1, 1, N, 10_000, 21, 1e-12)
+    print(f"\n  1e7 FP64: {used} of 10000 sampled events up to id {ids.max()}, max rel {rel.max():.2e}, "
           f"{skipped} at a cut edge or ill-conditioned; n_pass {nz}")
-    assert used > 40
-    assert worst < 1e-12
+    assert used > 7000
+    assert rel.max() < 1e-12
 
 
 def test_ttxgg_fp32_1e8_sampled_events_and_integral(api, oracle_lib, pdf_table):
@@ -93,10 +91,12 @@ def test_ttxgg_fp32_1e8_sampled_events_and_integral(api, oracle_lib, pdf_table):
     w32 = r32.weights
     _check_signs(w32)
     assert float(w32.sum().item()) / N == pytest.approx(r32.iter_sigma[0], rel=1e-12)
-    worst, used, skipped, ids = _spot_check(api, oracle_lib, pdf_table, w32, grid, 0, N, 64, 22, 1e-4)
-    print(f"\n  1e8 FP32: {used} sampled events up to id {ids.max()}, max rel vs FP64 oracle {worst:.2e}")
-    assert used > 25
-    assert worst < 2e-4
+    rel, used, skipped, ids = _spot_check(api, oracle_lib, pdf_table, w32, grid, 0, N, 10_000, 22, 1e-4)
+    srt = np.sort(rel)
+    print(f"\n  1e8 FP32 against the FP64 oracle on {used} of 10000 sampled events up to id {ids.max()}: "
+          f"max {srt[-1]:.2e}, p99.9 {srt[int(0.999 * len(srt))]:.2e}, median {srt[len(srt) // 2]:.2e}")
+    assert used > 7000
+    assert srt[-1] < 2e-4
     I32 = float(w32.sum().item())
     del w32
     torch.cuda.empty_cache()
@@ -134,31 +134,25 @@ def test_ttxgg_1e7_unweighting_sampled_events_and_properties(api, oracle_lib, pd
     rng = np.random.default_rng(31)
     kept = e.cpu().numpy()
     p = ev.p.cpu().numpy()
-    worst, checked, border = 0.0, 0, 0
-    for i in rng.choice(len(kept), size=min(64, len(kept)), replace=False):
-        k = int(kept[i])
-        w_o, info = O.event_weight(op, SQRT_S, pdf_table, r.grid_last, 0, 1, k)
-        u = O.unweight_uniform(0, 1, k)
-        if info.near_edge or info.ill_conditioned or abs(u * r.w_max - abs(w_o)) <= 1e-9 * abs(w_o):
-            border += 1
-            continue
-        assert u * r.w_max < abs(w_o)
-        q, st = O.lab_event(op, SQRT_S, r.grid_last, 0, 1, k)
+    # kept events: the oracle's own weight and uniform keep them, and its lab record matches
+    sel = rng.choice(len(kept), size=min(1000, len(kept)), replace=False)
+    w_o, flags = O.event_weights(op, SQRT_S, pdf_table, r.grid_last, 0, 1, kept[sel])
+    u = np.array([O.unweight_uniform(0, 1, int(k)) for k in kept[sel]])
+    border = ((flags & (8 | 16)) != 0) | (np.abs(u * r.w_max - np.abs(w_o)) <= 1e-9 * np.abs(w_o))
+    assert np.all(u[~border] * r.w_max < np.abs(w_o[~border]))
+    worst = 0.0
+    for i in sel[~border][:200]:
+        q, st = O.lab_event(op, SQRT_S, r.grid_last, 0, 1, int(kept[i]))
         assert st == 0
         worst = max(worst, np.abs(p[i] - q).max() / (0.5 * SQRT_S))
-        checked += 1
-    kept_set = set(kept.tolist())
-    rejected = 0
-    for k in rng.choice(N, size=64, replace=False):
-        if int(k) in kept_set:
-            continue
-        w_o, info = O.event_weight(op, SQRT_S, pdf_table, r.grid_last, 0, 1, int(k))
-        u = O.unweight_uniform(0, 1, int(k))
-        if info.near_edge or info.ill_conditioned or abs(u * r.w_max - abs(w_o)) <= 1e-9 * max(abs(w_o), 1e-300):
-            continue
-        assert not (u * r.w_max < abs(w_o))
-        rejected += 1
-    print(f"  {checked} kept events checked (records max |dp|/E_beam {worst:.1e}), {border} borderline; "
-          f"{rejected} rejected events confirmed")
-    assert checked > 40 and rejected > 40
+    # rejected events: the oracle rejects them too
+    cand = rng.choice(N, size=3000, replace=False)
+    rej = np.setdiff1d(cand, kept)
+    w_r, flags_r = O.event_weights(op, SQRT_S, pdf_table, r.grid_last, 0, 1, rej)
+    u_r = np.array([O.unweight_uniform(0, 1, int(k)) for k in rej])
+    clear = ((flags_r & (8 | 16)) == 0) & (np.abs(u_r * r.w_max - np.abs(w_r)) > 1e-9 * np.maximum(np.abs(w_r), 1e-300))
+    assert not np.any(u_r[clear] * r.w_max < np.abs(w_r[clear]))
+    print(f"  {int((~border).sum())} kept events confirmed by the oracle ({int(border.sum())} borderline), "
+          f"records max |dp|/E_beam {worst:.1e}; {int(clear.sum())} rejected events confirmed")
+    assert (~border).sum() > 0.9 * len(sel) and clear.sum() > 2500
     assert worst < 1e-12

@@ -129,3 +129,18 @@ def test_lab_record_kinematics(pdf_table, n_g, cuts):
                     assert abs(eta) < proc.etamax_g + 1e-9
         checked += 1
     assert checked > 100
+
+
+def test_threaded_event_weights_equal_single_evaluations(pdf_table):
+    """The threaded batch form used by the full-size checks returns what the
+    single-event evaluation returns, flags included."""
+    proc = O.Process(n_g=4, ptmin_g=20.0, drmin_gg=0.4)
+    grid = _uniform_grid(10)
+    ids = np.array([0, 3, 77, 5000, 123457, 2**33 + 1], dtype=np.uint64)
+    w, flags = O.event_weights(proc, SQRT_S, pdf_table, grid, 0, 2, ids, n_threads=3)
+    for i, e in enumerate(ids):
+        w1, info = O.event_weight(proc, SQRT_S, pdf_table, grid, 0, 2, int(e))
+        assert w[i] == w1
+        assert bool(flags[i] & 1) == info.pass_threshold and bool(flags[i] & 2) == info.newton_fail
+        assert bool(flags[i] & 4) == info.pass_cuts and bool(flags[i] & 8) == info.near_edge
+        assert bool(flags[i] & 16) == info.ill_conditioned
