@@ -632,6 +632,7 @@ struct StageParams {
     unsigned short* bins;    // [D][count]
     unsigned char* flags;    // [count] event_kinematics flags
     int first_batch;         // acc: 1 = start the per-wave partials from zero
+    unsigned long long* next_group;  // amp: work counter, cleared by kin_kernel
 };
 
 template <int NF>
@@ -644,6 +645,8 @@ __global__ void __launch_bounds__(kBlock) kin_kernel(StageParams S)
     const int tid = threadIdx.x;
     const int lane = tid % kWave;
     const int wave_id = blockIdx.x * kWavesPerBlock + tid / kWave;
+    if (blockIdx.x == 0 && tid == 0)
+        *S.next_group = 0ull;
     for (int i = tid; i < P.n_x; i += kBlock)
         s_lx[i] = P.log_x[i];
     for (int i = tid; i < P.q2_rows * P.n_x; i += kBlock)
@@ -665,11 +668,16 @@ __global__ void __launch_bounds__(kBlock) kin_kernel(StageParams S)
 }
 
 // One wave per workgroup; a persistent loop over groups of events (one event
-// per pass for t tbar g g, two for t tbar g).  Groups without a passing event
-// are skipped whole.  The prefactor and momenta of the wave's next group are
-// loaded while the current one is evaluated (lane h < kMom of each event
-// holds one stored momentum component), so that their memory latency overlaps
-// the amplitude arithmetic.
+// per pass for t tbar g g, two for t tbar g).  The waves take chunks of
+// kAmpChunk groups from a device counter (cleared by kin_kernel), so that
+// they all finish within about one chunk of each other; each event's |M|^2
+// is written by whichever wave evaluates it, so the results do not depend on
+// the order.  The chunk after the current one is claimed one chunk ahead,
+// and the prefactor and momenta of the next group are loaded while the
+// current one is evaluated (lane h < kMom of each event holds one stored
+// momentum component).  Groups without a passing event are skipped whole.
+constexpr int kAmpChunk = 16;
+
 template <int NG, typename T>
 __global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2))) amp_kernel(StageParams S)
 {
@@ -684,45 +692,59 @@ __global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(size
     T* obj = s_obj[sub];
     double* mom = s_mom[sub];
     const uint64_t n_groups = (S.count + L::kEventsPerPass - 1) / L::kEventsPerPass;
-    double pref_next = 0.0, mc_next = 0.0;
-    {
-        const uint64_t e = (uint64_t)blockIdx.x * L::kEventsPerPass + sub;
-        if (e < S.count) {
-            pref_next = S.pref[e];
+    // one lane claims a chunk with a vector atomic; the wave reads its value
+    auto claim = [&]() -> uint64_t {
+        unsigned long long c = 0;
+        if (lane == 0)
+            c = atomicAdd(S.next_group, (unsigned long long)kAmpChunk);
+        return (uint64_t)__shfl(c, 0);
+    };
+    auto load = [&](uint64_t g, double& pref, double& mc) {
+        const uint64_t e = g * L::kEventsPerPass + sub;
+        pref = 0.0;
+        mc = 0.0;
+        if (g < n_groups && e < S.count) {
+            pref = S.pref[e];
             if (h0 < L::kMom)
-                mc_next = S.mom[e * L::kMom + h0];
+                mc = S.mom[e * L::kMom + h0];
         }
-    }
-    for (uint64_t g = blockIdx.x; g < n_groups; g += gridDim.x) {
+    };
+    uint64_t cur = claim();
+    uint64_t nxt = claim();
+    double pref_next, mc_next;
+    load(cur, pref_next, mc_next);
+    int j = 0;
+    while (cur < n_groups) {
+        const uint64_t g = cur + j;
         const double pref = pref_next, mc = mc_next;
-        {
-            const uint64_t e = (g + gridDim.x) * L::kEventsPerPass + sub;
-            pref_next = 0.0;
-            mc_next = 0.0;
-            if (e < S.count) {
-                pref_next = S.pref[e];
-                if (h0 < L::kMom)
-                    mc_next = S.mom[e * L::kMom + h0];
-            }
-        }
+        // the group after this one: in this chunk, or the first of the next
+        const bool last_in_chunk = j + 1 == kAmpChunk || g + 1 >= n_groups;
+        load(last_in_chunk ? nxt : g + 1, pref_next, mc_next);
         int h = h0;
         asm volatile("" : "+v"(h));
         const uint64_t e = g * L::kEventsPerPass + sub;
         const bool live = e < S.count && pref != 0.0;
         const bool any_live = __any(live);
-        if (!any_live)
-            continue;
-        if (h0 < L::kMom)
-            mom[h0] = mc;
-        wave_sync();
-        if (live)
-            fill_table<NG, T>(mom, mom[L::kMom - 1], S.P.m_top, S.P.mw, tab, obj, h);
-        wave_sync();
-        double v = event_me2<NG, T>(tab, obj, h, S.P.m_top, live, any_live);
-        v = group_sum(v, L::kHel);
-        if (h == 0 && live)
-            S.me[e] = v;
-        wave_sync();
+        if (any_live) {
+            if (h0 < L::kMom)
+                mom[h0] = mc;
+            wave_sync();
+            if (live)
+                fill_table<NG, T>(mom, mom[L::kMom - 1], S.P.m_top, S.P.mw, tab, obj, h);
+            wave_sync();
+            double v = event_me2<NG, T>(tab, obj, h, S.P.m_top, live, any_live);
+            v = group_sum(v, L::kHel);
+            if (h == 0 && live)
+                S.me[e] = v;
+            wave_sync();
+        }
+        if (last_in_chunk) {
+            cur = nxt;
+            nxt = claim();
+            j = 0;
+        } else {
+            ++j;
+        }
     }
 }
 

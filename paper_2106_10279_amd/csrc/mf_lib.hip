@@ -68,6 +68,7 @@ struct Workspace {
     std::mutex lock;
     Buffer grid[2], log_x, log_q2, xf, partials, entries, iter_I, iter_V, iter_pass, stats, gpartials, gsum;
     Buffer st_mom, st_pref, st_me, st_bins, st_flags;   // per-event hand-over of the three-kernel form
+    Buffer amp_counter;                                  // work counter of amp_kernel (8 bytes)
     Buffer uw_counts, uw_flags, uw_totals;               // unweighting: per-workgroup counts, keep flags, totals
     int n_cu = 0;
 };
@@ -488,6 +489,7 @@ mf_status integrate_impl(const mf_process* proc, double sqrt_s, const mf_pdf_gri
         if ((st = ensure(ws.st_me, sizeof(double) * batch)) != MF_OK) return st;
         if ((st = ensure(ws.st_bins, sizeof(unsigned short) * D * batch)) != MF_OK) return st;
         if ((st = ensure(ws.st_flags, batch)) != MF_OK) return st;
+        if ((st = ensure(ws.amp_counter, sizeof(unsigned long long))) != MF_OK) return st;
     }
     if (grad) {
         if ((st = ensure(ws.gpartials, sizeof(double) * 4 * (size_t)n_waves)) != MF_OK) return st;
@@ -556,6 +558,7 @@ mf_status integrate_impl(const mf_process* proc, double sqrt_s, const mf_pdf_gri
                 SP.bins = (unsigned short*)ws.st_bins.ptr;
                 SP.flags = (unsigned char*)ws.st_flags.ptr;
                 SP.first_batch = bi == 0;
+                SP.next_group = (unsigned long long*)ws.amp_counter.ptr;
                 hipEvent_t a = nullptr, b = nullptr;
                 if (opt->profile) {
                     a = amp_marks[2 * ((size_t)j * n_batches + bi)];
