@@ -739,7 +739,7 @@ def emit_coop(n, lay, co, K, perms):
         w(f"        T* o = al16(obj + {co.gj} + 4 * (GJ{n}_L{L}_BASE[si] + hm));")
         w("        st4(o, a0 * f, a1 * f, a2 * f, a3 * f);")
         w("    }")
-        w("    wave_sync();")
+        w(f"//@@END L{L}")
     # top line from the top side: Ubar(a; s_t, h_a)
     flops_stage += 4 * n * (50 + 80) + 4 * n * (42 + 80)
     w("    // Ubar(a; s_t, h) = -[ubar gamma.eps_a] (K-slash + m) / D,   V(d; s_tbar, h) = -(K'-slash + m) [gamma.eps_d v] / D'")
@@ -765,7 +765,7 @@ def emit_coop(n, lay, co, K, perms):
     w("        }")
     w(f"        stspin(al16(obj + (side ? {co.v1} : {co.u1}) + 8 * r), out);")
     w("    }")
-    w("    wave_sync();")
+    w("//@@END U1V1")
     if pairs:
         flops_stage += 8 * len(pairs) * (42 + 42 + 80)
         w("    // V(cd; s_tbar, h_c, h_d) = -(K'-slash + m) [gamma.eps_c V(d) + gamma.j(cd) v] / D'")
@@ -793,8 +793,31 @@ def emit_coop(n, lay, co, K, perms):
         w("        colprop(W, Kc, (T)mtd, (T)k[4], (T)k[5], out);")
         w(f"        stspin(al16(obj + {co.v2} + 8 * it), out);")
         w("    }")
-        w("    wave_sync();")
-    stages = "\n".join(L_)
+        w("//@@END V2")
+    # Order of the stages: level 2 and the single-gluon spinor chains depend
+    # only on level 1, level 3 and the two-gluon chains only on those, each
+    # further level on the one before; a wave synchronisation separates only
+    # dependent groups.
+    chunks, buf = {}, []
+    for line in L_:
+        if line.startswith("//@@END "):
+            chunks[line[len("//@@END "):]] = buf
+            buf = []
+        else:
+            buf.append(line)
+    # the lines ahead of level 2 (shared declarations) open the function
+    rest = chunks["L2"]
+    cut = next(i for i, line in enumerate(rest) if line.startswith("    // level 2"))
+    pre, chunks["L2"] = rest[:cut], rest[cut:]
+    order = [["L2", "U1V1"], ["L3"] + (["V2"] if "V2" in chunks else [])] + \
+        [[f"L{k}"] for k in range(4, n + 1)]
+    out = list(pre)
+    for grp in order:
+        for name in grp:
+            out.extend(chunks.pop(name))
+        out.append("    wave_sync();")
+    assert not chunks, chunks.keys()
+    stages = "\n".join(out)
 
     # ---- amplitude phase: one lane per helicity configuration ----
     # A(sigma) = sum over the blocks beta of sigma that contain its second
