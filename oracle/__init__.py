@@ -9,5 +9,5 @@ from .oracle import (  # noqa: F401
     colour_matrix, orderings, partial_amplitudes, me2_sum, me2_sum_hel,
     me2_sum_fullcolour, event_weight, event_weight_y, integrate, combine,
     neumaier_sum, ttx_dweight_dmt_analytic, n_dims, all_helicities,
-    unweight_uniform, unweight, lab_event, event_weights,
+    unweight_uniform, unweight, lab_event, event_weights, colour_lc, me2_sum_lc,
 )

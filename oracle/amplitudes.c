@@ -484,6 +484,28 @@ double mfo_me2_sum_hel(int n_g, const double *p, double m, double width,
     return total;
 }
 
+double mfo_colour_lc(int n_g)
+{
+    const double N = 3.0;
+    return (N * N - 1.0) * pow(N, n_g - 1) / pow(2.0, n_g);
+}
+
+double mfo_me2_sum_lc(int n_g, const double *p, double m, double width)
+{
+    int nperm = mfo_n_orderings(n_g);
+    int nh = 1 << (n_g + 2);
+    double total = 0.0;
+    for (int h = 0; h < nh; ++h) {
+        int hel[MFO_MAX_G + 2];
+        hel_from_index(n_g, h, hel);
+        cplx A[120];
+        partial_amplitudes_core(n_g, p, m, width, hel, -1, A);
+        for (int a = 0; a < nperm; ++a)
+            total += creal(A[a]) * creal(A[a]) + cimag(A[a]) * cimag(A[a]);
+    }
+    return mfo_colour_lc(n_g) * total;
+}
+
 double mfo_me2_sum(int n_g, const double *p, double m, double width)
 {
     int nh = 1 << (n_g + 2);

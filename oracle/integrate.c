@@ -139,7 +139,8 @@ static double weight_from_x(const mfo_process *proc, double sqrt_s,
         memcpy(p + 4 * (2 + i), ev->k[i], sizeof(double) * 4);
 
     double gs2 = 4.0 * PI * proc->alpha_s;
-    double sum = mfo_me2_sum(n_g, p, m, proc->w_top);
+    double sum = proc->colour == 1 ? mfo_me2_sum_lc(n_g, p, m, proc->w_top)
+                                   : mfo_me2_sum(n_g, p, m, proc->w_top);
     /* average over 2 x 2 initial helicities and 8 x 8 initial colours,
      * symmetry factor 1/(n_g - 2)! for identical final-state gluons */
     ev->me2 = pow(gs2, n_g) * sum / (4.0 * 64.0 * factorial(n_g - 2));

@@ -44,6 +44,7 @@ typedef struct {
     double ptmin_g;            /* gluon pT cut (GeV); <= 0 disables            */
     double etamax_g;           /* gluon |eta| cut; <= 0 disables               */
     double drmin_gg;           /* Delta R between final gluons; <= 0 disables  */
+    int    colour;             /* 0: full colour sum; 1: leading colour        */
 } mfo_process;
 
 typedef struct {
@@ -118,6 +119,14 @@ double mfo_me2_sum_fullcolour(int n_g, const double *p, double m, double width,
                               int n_hel, const int *hel_list);
 double mfo_me2_sum_hel(int n_g, const double *p, double m, double width,
                        int n_hel, const int *hel_list);
+/* Leading-colour approximation (the paper names it, Sec. 3.3, as a way to
+ * cheapen high-multiplicity matrix elements): the colour matrix replaced by
+ * c_LC times the identity, c_LC = (N^2 - 1) N^(n_g - 1) / 2^n_g with N = 3,
+ * the leading power of N in every diagonal element N C_F^n_g (T = lambda/2;
+ * Mangano-Parke, Phys. Rept. 200 (1991) 301).  mfo_colour_lc returns c_LC;
+ * mfo_me2_sum_lc the helicity sum of c_LC sum_sigma |A(sigma)|^2, g_s = 1. */
+double mfo_colour_lc(int n_g);
+double mfo_me2_sum_lc(int n_g, const double *p, double m, double width);
 
 /* ---- per-event weight and integration ---------------------------------- */
 int mfo_n_dims(int n_g);

@@ -21,7 +21,7 @@ _u64p = C.POINTER(C.c_uint64)
 class _Process(C.Structure):
     _fields_ = [("n_g", C.c_int), ("m_top", C.c_double), ("w_top", C.c_double),
                 ("alpha_s", C.c_double), ("mu_f", C.c_double), ("ptmin_g", C.c_double),
-                ("etamax_g", C.c_double), ("drmin_gg", C.c_double)]
+                ("etamax_g", C.c_double), ("drmin_gg", C.c_double), ("colour", C.c_int)]
 
 
 class _Pdf(C.Structure):
@@ -89,6 +89,10 @@ def lib():
         L.mfo_me2_sum.restype = C.c_double
         L.mfo_me2_sum_hel.argtypes = [C.c_int, _dp, C.c_double, C.c_double, C.c_int, _ip]
         L.mfo_me2_sum_hel.restype = C.c_double
+        L.mfo_colour_lc.argtypes = [C.c_int]
+        L.mfo_colour_lc.restype = C.c_double
+        L.mfo_me2_sum_lc.argtypes = [C.c_int, _dp, C.c_double, C.c_double]
+        L.mfo_me2_sum_lc.restype = C.c_double
         L.mfo_me2_sum_fullcolour.argtypes = [C.c_int, _dp, C.c_double, C.c_double, C.c_int, _ip]
         L.mfo_me2_sum_fullcolour.restype = C.c_double
         L.mfo_n_dims.argtypes = [C.c_int]
@@ -144,10 +148,13 @@ class Process:
     ptmin_g: float = 0.0
     etamax_g: float = 0.0
     drmin_gg: float = 0.0
+    colour: str = "full"        # "full" or "leading" (leading-colour approximation)
 
     def c(self):
+        if self.colour not in ("full", "leading"):
+            raise ValueError(f"colour must be 'full' or 'leading', not {self.colour!r}")
         return _Process(self.n_g, self.m_top, self.w_top, self.alpha_s, self.mu_f,
-                        self.ptmin_g, self.etamax_g, self.drmin_gg)
+                        self.ptmin_g, self.etamax_g, self.drmin_gg, int(self.colour == "leading"))
 
 
 class _PdfHandle:
@@ -278,6 +285,17 @@ def partial_amplitudes(n_g, p, m, width, hel, ward_gluon=-1):
 def me2_sum(n_g, p, m, width):
     p = _f64(p)
     return lib().mfo_me2_sum(n_g, _d(p), m, width)
+
+
+def colour_lc(n_g):
+    """Leading-colour coefficient (N^2 - 1) N^(n_g - 1) / 2^n_g, N = 3."""
+    return lib().mfo_colour_lc(n_g)
+
+
+def me2_sum_lc(n_g, p, m, width):
+    """Helicity sum of c_LC sum_sigma |A(sigma)|^2 (leading colour), g_s = 1."""
+    p = _f64(p)
+    return lib().mfo_me2_sum_lc(n_g, _d(p), m, width)
 
 
 def all_helicities(n_g):
