@@ -47,25 +47,25 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def me_flops(n_g):
+def me_flops(n_g, colour="full"):
     path = os.path.join(ROOT, "paper_2106_10279_amd", "csrc", "gen_amplitudes.py")
     spec = importlib.util.spec_from_file_location("gen_amplitudes", path)
     mod = importlib.util.module_from_spec(spec)
     spec.loader.exec_module(mod)
-    return mod.flop_count(n_g)["per_event"]
+    return mod.flop_count(n_g, colour)["per_event"]
 
 
-def timed_run(api, torch, proc, pdf, n_events, steps, warmup, precision, seed):
+def timed_run(api, torch, proc, pdf, n_events, steps, warmup, precision, seed, colour="full"):
     if warmup > 0:
         api.integrate(proc, 13000.0, pdf, n_events, warmup, seed, precision=precision,
-                      keep_weights=False)
+                      keep_weights=False, colour=colour)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
     e0.record(stream)
     r = api.integrate(proc, 13000.0, pdf, n_events, steps, seed, precision=precision,
-                      keep_weights=False, profile=True, start_iter=warmup)
+                      keep_weights=False, profile=True, start_iter=warmup, colour=colour)
     e1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -258,6 +258,7 @@ def main():
     ap.add_argument("--fp32-steps", type=int, default=3)
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-unweight", action="store_true")
+    ap.add_argument("--no-leading-colour", action="store_true")
     ap.add_argument("--adjoint-events", type=int, default=10_000_000)
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device-to-device copy of this many bytes (3 times), "
@@ -334,6 +335,24 @@ def main():
             "note": "packed FP32 disabled at compile time: FP32 issues at the FP64 vector rate",
         }
         log(f"[bench] fp32 integral rel err {err['integral_rel']:.2e}, event max {err['event_rel_max']:.2e}")
+    if not args.no_leading_colour:
+        log(f"[bench] leading-colour approximation, fp64: {args.warmup} warm-up + {args.steps} timed "
+            f"iterations x {n_events} events")
+        rlc, walllc, _ = timed_run(api, torch, proc, pdf, n_events, args.steps, args.warmup, "fp64",
+                                   args.seed, colour="leading")
+        vlc = args.steps * n_events / walllc
+        f_lc = me_flops(wl["n_g"], "leading")
+        out["leading_colour"] = {
+            "value": round(vlc, 2), "unit": "events/s", "events_per_step": n_events,
+            "steps": args.steps, "ms_per_step": round(walllc / args.steps * 1e3, 3),
+            "roofline": roofline(wl["n_g"], f_lc, f_other, n_events, rlc, PEAK_FP64_TFLOPS),
+            "sigma": rlc.sigma, "sigma_err": rlc.sigma_err,
+            "sigma_over_full_colour": rlc.sigma / r64.sigma,
+            "note": "colour matrix replaced by (N^2-1) N^(n-1)/2^n times the identity: a different "
+                    "integrand; same seed as the fp64 line, its VEGAS grid adapts to this integrand",
+        }
+        log(f"[bench] leading colour done: {vlc:.4g} events/s, sigma / sigma_full = "
+            f"{rlc.sigma / r64.sigma:.4f}")
     if not args.no_adjoint:
         log(f"[bench] adjoint: gg_ttx forward + gradient, {args.adjoint_events} events x 3 iterations")
         out["adjoint"] = adjoint_run(api, torch, pdf, args.adjoint_events, 3, args.seed)

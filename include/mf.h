@@ -47,6 +47,14 @@ typedef enum { MF_GG_TTX = 0, MF_GG_TTXG = 1, MF_GG_TTXGG = 2 } mf_process_id;
  * (VEGAS, phase space, PDF, accumulation, refinement) is FP64 in both. */
 typedef enum { MF_FP64 = 0, MF_FP32_KAHAN = 1 } mf_precision;
 
+/* Colour sum of |M|^2.  MF_COLOUR_LEADING is the leading-colour
+ * approximation that Sec. 3.3 names for high multiplicities: in the colour
+ * basis (T^{a_s1} ... T^{a_sn})_{i_t j_tbar}, T = lambda/2, the colour matrix
+ * is replaced by c_LC = (N^2 - 1) N^(n_g - 1) / 2^n_g (N = 3: 6, 9, 13.5)
+ * times the identity, the leading power of N of its diagonal; it changes the
+ * integrand (by O(1/N^2)), not only its variance. */
+typedef enum { MF_COLOUR_FULL = 0, MF_COLOUR_LEADING = 1 } mf_colour;
+
 typedef struct {
     mf_process_id id;
     double m_top;            /* GeV, > 0                                       */
@@ -79,6 +87,8 @@ typedef struct {
     int profile;             /* 1: time every kernel with HIP events (0)        */
     uint64_t max_batch;      /* n_g >= 3: events per batch of the per-event device
                                 buffers (about 170 B per event), 0 = 2^27 (0)   */
+    mf_colour colour;        /* MF_COLOUR_FULL or MF_COLOUR_LEADING (FULL); the
+                                gradient entry points take MF_COLOUR_FULL only */
 } mf_options;
 
 typedef struct {

@@ -25,6 +25,8 @@ from ._lib import MF_FP32_KAHAN, MF_FP64, check, lib
 PROCESS_IDS = {"gg_ttx": _lib.MF_GG_TTX, "gg_ttxg": _lib.MF_GG_TTXG, "gg_ttxgg": _lib.MF_GG_TTXGG,
                2: _lib.MF_GG_TTX, 3: _lib.MF_GG_TTXG, 4: _lib.MF_GG_TTXGG}
 PRECISIONS = {"fp64": MF_FP64, "fp32_kahan": MF_FP32_KAHAN}
+# colour sum: the full colour matrix, or the leading-colour approximation
+COLOURS = {"full": 0, "leading": 1}
 
 _dp = C.POINTER(C.c_double)
 
@@ -73,7 +75,7 @@ def n_dims(process) -> int:
 
 
 def _options(n_bins, alpha, start_iter, precision, strict, max_newton, grid_in, stream, profile=False,
-             max_batch=0):
+             max_batch=0, colour="full"):
     o = _lib.mf_options()
     lib.mf_default_options(C.byref(o))
     o.n_bins = n_bins
@@ -86,6 +88,7 @@ def _options(n_bins, alpha, start_iter, precision, strict, max_newton, grid_in, 
     o.stream = _stream(stream)
     o.profile = int(profile)
     o.max_batch = int(max_batch)
+    o.colour = COLOURS.get(colour, colour)
     return o
 
 
@@ -115,12 +118,12 @@ def integrate(proc: Process, sqrt_s: float, pdf_table, n_events: int, n_iter: in
               n_bins: int = 50, alpha: float = 1.5, precision="fp64", start_iter: int = 0,
               grid_in=None, keep_weights: bool = True, strict: bool = False,
               max_newton: int = 50, stream=None, weights_out: torch.Tensor | None = None,
-              profile: bool = False, max_batch: int = 0):
+              profile: bool = False, max_batch: int = 0, colour="full"):
     D = n_dims(proc.process)
     pdf = _Pdf(pdf_table)
     gin = None if grid_in is None else np.ascontiguousarray(grid_in, dtype=np.float64)
     opt = _options(n_bins, alpha, start_iter, precision, strict, max_newton, gin, stream, profile,
-                   max_batch)
+                   max_batch, colour)
     I = np.zeros(n_iter)
     V = np.zeros(n_iter)
     grid = np.zeros((D, n_bins + 1))
@@ -155,13 +158,14 @@ def evaluate_weights(proc: Process, sqrt_s: float, pdf_table, n: int, seed: int 
                      grid=None, y: torch.Tensor | None = None,
                      event_ids: torch.Tensor | None = None, n_bins: int = 50,
                      precision="fp64", max_newton: int = 50, return_k53: bool = False,
-                     return_bins: bool = False, return_record: bool = False, stream=None):
+                     return_bins: bool = False, return_record: bool = False, stream=None,
+                     colour="full"):
     """Per-event weights (pb) for a fixed grid; optionally the Philox integers,
     the bin indices and the per-stage record (see mf_evaluate in include/mf.h)."""
     D = n_dims(proc.process)
     pdf = _Pdf(pdf_table)
     g = None if grid is None else np.ascontiguousarray(grid, dtype=np.float64)
-    opt = _options(n_bins, 1.5, 0, precision, False, max_newton, None, stream)
+    opt = _options(n_bins, 1.5, 0, precision, False, max_newton, None, stream, colour=colour)
     w = torch.empty(n, dtype=torch.float64, device="cuda")
     k53 = torch.empty((n, D), dtype=torch.int64, device="cuda") if return_k53 else None
     bins = torch.empty((n, D), dtype=torch.int32, device="cuda") if return_bins else None

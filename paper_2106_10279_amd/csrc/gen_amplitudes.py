@@ -74,6 +74,17 @@ def colour_matrix(n):
     return perms, K, den
 
 
+def lc_numerator(n, den):
+    """Leading-colour approximation: the colour matrix replaced by
+    c_LC = (N^2 - 1) N^(n - 1) / 2^n times the identity (N = 3), the leading
+    power of N of its diagonal N C_F^n; returned over the common denominator
+    of the full matrix (an integer for n = 2, 3, 4)."""
+    from fractions import Fraction
+    v = Fraction(8 * 3 ** (n - 1), 2 ** n) * den
+    assert v.denominator == 1
+    return int(v)
+
+
 # ----------------------------------------------------------------------------
 # code emission helpers
 # ----------------------------------------------------------------------------
@@ -469,6 +480,8 @@ static constexpr int COLOUR_NUM_NG{n}[{nperm * nperm}] = {{{kdecl}}};
 {coop_text}"""
     lay = Layout(n)
     e = Emitter(n, lay)
+    e.hel_full = 0
+    lc = lc_numerator(n, den)
     nperm = len(perms)
     e.w("const int sT = hel & 1, sB = (hel >> 1) & 1;")
     for g in range(n):
@@ -495,7 +508,7 @@ static constexpr int COLOUR_NUM_NG{n}[{nperm * nperm}] = {{{kdecl}}};
         U = e.fcur(sg[:n - 1])
         e.hel += 42                  # W = gamma.eps v for the last gluon
         e.hel += 16 * len(parts) + 32 + 2 + 4
-        e.hel += 4 * sum(1 for t in range(idx) if K[idx][t] != 0)
+        e.hel_full += 4 * sum(1 for t in range(idx) if K[idx][t] != 0)
         e.w("{")
         e.w("    T ar = 0, ai = 0;")
         for (c, j) in parts:
@@ -507,11 +520,16 @@ static constexpr int COLOUR_NUM_NG{n}[{nperm * nperm}] = {{{kdecl}}};
         e.w(f"    slashcol(eps{sg[n - 1]}, v, W);")
         e.w(f"    rowdotcol({U}, W, ar, ai);")
         e.w(f"    A[{idx}] = cT(ar, ai);")
-        # incremental colour sum: K_ss |A_s|^2 + 2 Re(conj(A_s) sum_{t<s} K_st A_t)
-        e.w(f"    T tr = {K[idx][idx]} * ar, ti = {K[idx][idx]} * ai;")
-        for t in range(idx):
-            if K[idx][t] != 0:
-                e.w(f"    tr += (T)({2 * K[idx][t]}) * A[{t}].x; ti += (T)({2 * K[idx][t]}) * A[{t}].y;")
+        # incremental colour sum: K_ss |A_s|^2 + 2 Re(conj(A_s) sum_{t<s} K_st A_t);
+        # leading colour (COL = 1) keeps c_LC |A_s|^2 only
+        e.w(f"    const T kss = (T)(COL == 0 ? {K[idx][idx]} : {lc});")
+        e.w("    T tr = kss * ar, ti = kss * ai;")
+        off = [t for t in range(idx) if K[idx][t] != 0]
+        if off:
+            e.w("    if constexpr (COL == 0) {")
+            for t in off:
+                e.w(f"        tr += (T)({2 * K[idx][t]}) * A[{t}].x; ti += (T)({2 * K[idx][t]}) * A[{t}].y;")
+            e.w("    }")
         e.w("    me += ar * tr + ai * ti;")
         e.w("}")
     # momentum-only work, done once per event for the table
@@ -520,13 +538,14 @@ static constexpr int COLOUR_NUM_NG{n}[{nperm * nperm}] = {{{kdecl}}};
         + (4 + 8 + 3 + 2) * len(lay.K) + 4 * 24 + (n - 2) * 2 * 16 + 2
     body = "\n".join(e.lines)
     fill = emit_table_fill(n, lay)
-    _LAST_COUNT = {"per_helicity": e.hel, "momentum_only": e.mom, "n_hel": 1 << (n + 2),
-                   "n_orderings": nperm, "table_doubles": lay.size}
+    _LAST_COUNT = {"per_helicity": e.hel + e.hel_full, "per_helicity_lc": e.hel, "momentum_only": e.mom,
+                   "n_hel": 1 << (n + 2), "n_orderings": nperm, "table_doubles": lay.size}
     kdecl = ", ".join(str(v) for row in K for v in row)
     return f"""// Generated by gen_amplitudes.py for g g -> t tbar + {n - 2} gluon(s): {nperm} colour orderings,
 // {1 << (n + 2)} helicity configurations.  Do not edit.
-// Arithmetic per helicity configuration: {e.hel} flops; per event (table): {e.mom} flops.
-static constexpr int FLOPS_PER_HEL_NG{n} = {e.hel};
+// Arithmetic per helicity configuration: {e.hel + e.hel_full} flops ({e.hel} in leading colour);
+// per event (table): {e.mom} flops.
+static constexpr int FLOPS_PER_HEL_NG{n} = {e.hel + e.hel_full};
 static constexpr int FLOPS_MOMENTUM_NG{n} = {e.mom};
 static constexpr int NPERM_NG{n} = {nperm};
 static constexpr int TABLE_NG{n} = {lay.size};
@@ -545,8 +564,9 @@ __device__ __forceinline__ void fill_table_ng{n}(const double* __restrict__ mom,
 
 // Sum over colours of |M|^2 for helicity configuration `hel` (bit 0: top
 // spin, bit 1: antitop spin, bit 2+g: gluon g polarisation), g_s = 1,
-// from the event's table.
-template <typename T>
+// from the event's table.  COL = 0: full colour matrix; COL = 1: leading
+// colour, {lc}/{den} times the identity.
+template <typename T, int COL>
 __device__ __forceinline__ double colour_summed_me2_ng{n}(const double* __restrict__ tab_in, int hel, double mt)
 {{
     using cT = cplx<T>;
@@ -620,7 +640,7 @@ def posmask(part, whole):
     return m
 
 
-def emit_coop(n, lay, co, K, perms):
+def emit_coop(n, lay, co, K, den, perms):
     # lay: CoopTable (offsets in units of T)
     L_ = []
     w = L_.append
@@ -969,46 +989,60 @@ def emit_coop(n, lay, co, K, perms):
         for k in untouched:
             sig[k] = 1
     # colour sum: sum_s K_ss |A_s|^2 + 2 sum_{t<s} K_st Re(conj(A_s) A_t), on
-    # the accumulators (sig[s] A_s): K_st enters as sig[s] sig[t] K_st
+    # the accumulators (sig[s] A_s): K_st enters as sig[s] sig[t] K_st.
+    # Leading colour (COL = 1): c_LC sum_s |A_s|^2, where the signs drop out.
     a("    T me;")
+    a("    if constexpr (COL == 0) {")
+    full_flops = 0
     for sidx in range(nperm_):
         a("    {")
         a(f"        T tr = {K[sidx][sidx]} * Ar[{sidx}], ti = {K[sidx][sidx]} * Ai[{sidx}];")
-        hel_flops += 2
+        full_flops += 2
         for t in range(sidx):
             if K[sidx][t]:
                 kst = 2 * K[sidx][t] * sig[sidx] * sig[t]
                 a(f"        tr += (T)({kst}) * Ar[{t}]; ti += (T)({kst}) * Ai[{t}];")
-                hel_flops += 4
+                full_flops += 4
         if sidx == 0:
             a(f"        me = Ar[{sidx}] * tr;")
-            hel_flops += 1
+            full_flops += 1
         else:
             a(f"        me += Ar[{sidx}] * tr;")
-            hel_flops += 2
+            full_flops += 2
         a(f"        me += Ai[{sidx}] * ti;")
-        hel_flops += 2
+        full_flops += 2
         a("    }")
+    a("    } else {")
+    a("        T s2 = Ar[0] * Ar[0];")
+    a("        s2 += Ai[0] * Ai[0];")
+    lc_flops = 3
+    for sidx in range(1, nperm_):
+        a(f"        s2 += Ar[{sidx}] * Ar[{sidx}];")
+        a(f"        s2 += Ai[{sidx}] * Ai[{sidx}];")
+        lc_flops += 4
+    a(f"        me = (T){lc_numerator(n, den)} * s2;")
+    lc_flops += 1
+    a("    }")
     A_seq[acc_decl] = A[acc_decl]
     A_seq.extend(A[tail_start:])
     amp = ("\n".join(A), "\n".join(A_seq))
-    return "\n".join(tables), stages, amp, flops_stage, hel_flops
+    return "\n".join(tables), stages, amp, flops_stage, (hel_flops + full_flops, hel_flops + lc_flops)
 
 
 def generate_coop(n):
     perms, K, den = colour_matrix(n)
     tl = CoopTable(n)
     co = CoopLayout(n)
-    tables, stages, amp, fst, fhel = emit_coop(n, tl, co, K, perms)
+    tables, stages, amp, fst, (fhel, fhel_lc) = emit_coop(n, tl, co, K, den, perms)
     fill = emit_coop_fill(n, tl, co)
     global _COOP_COUNT
-    _COOP_COUNT = {"stages": fst, "per_helicity": fhel, "object_store": co.size, "table": tl.size,
-                   "momentum_only": tl.mom_flops()}
+    _COOP_COUNT = {"stages": fst, "per_helicity": fhel, "per_helicity_lc": fhel_lc, "object_store": co.size,
+                   "table": tl.size, "momentum_only": tl.mom_flops()}
     return f"""
 // ---- cooperative evaluation (helicity-recycled objects in LDS) ----
 // Table: {tl.size} T per event; object store: {co.size} T per event.  Table
 // flops per event: {tl.mom_flops()}; stage flops per event: {fst}; per
-// helicity lane: {fhel}.
+// helicity lane: {fhel} ({fhel_lc} in leading colour).
 static constexpr int COOP_TABLE_NG{n} = {tl.size};
 static constexpr int COOP_OBJ_NG{n} = {co.size};
 static constexpr int COOP_FLOPS_STAGES_NG{n} = {fst};
@@ -1037,15 +1071,16 @@ __device__ __forceinline__ void coop_stages_ng{n}(const T* __restrict__ tab, T* 
 
 // Colour-summed |M|^2 (g_s = 1) of helicity configuration `hel` from the
 // object store: meet-in-the-middle at the vertex that carries the second
-// gluon of each colour ordering, A = sum Xbar gamma.j(block) Y.
-template <typename T>
+// gluon of each colour ordering, A = sum Xbar gamma.j(block) Y.  COL = 0:
+// full colour matrix; COL = 1: leading colour, {lc_numerator(n, den)}/{den} times the identity.
+template <typename T, int COL>
 __device__ __forceinline__ double coop_me2_ng{n}_ahead(const T* __restrict__ tab, const T* __restrict__ obj, int hel)
 {{
 {amp[0]}
     return (double)me / COLOUR_DEN_NG{n};
 }}
 
-template <typename T>
+template <typename T, int COL>
 __device__ __forceinline__ double coop_me2_ng{n}_inplace(const T* __restrict__ tab, const T* __restrict__ obj, int hel)
 {{
 {amp[1]}
@@ -1054,13 +1089,13 @@ __device__ __forceinline__ double coop_me2_ng{n}_inplace(const T* __restrict__ t
 
 // The spinor reads go one group ahead where the registers allow it without
 // spilling or losing occupancy: FP64 with four final-state partons.
-template <typename T>
+template <typename T, int COL>
 __device__ __forceinline__ double coop_me2_ng{n}(const T* __restrict__ tab, const T* __restrict__ obj, int hel)
 {{
     if constexpr (sizeof(T) == 8 && {n} == 4)
-        return coop_me2_ng{n}_ahead<T>(tab, obj, hel);
+        return coop_me2_ng{n}_ahead<T, COL>(tab, obj, hel);
     else
-        return coop_me2_ng{n}_inplace<T>(tab, obj, hel);
+        return coop_me2_ng{n}_inplace<T, COL>(tab, obj, hel);
 }}
 """
 
@@ -1069,22 +1104,27 @@ _LAST_COUNT = None
 _COOP_COUNT = None
 
 
-def flop_count(n):
+def flop_count(n, colour="full"):
     """Algorithmic flops per event of the |M|^2 code the kernels run for n
     gluons: the momentum table, plus either 2^(n+2) independent helicity
     evaluations (n = 2) or the shared object stages and the per-helicity
-    meet-in-the-middle contractions (n >= 3)."""
+    meet-in-the-middle contractions (n >= 3).  colour = "leading" counts the
+    leading-colour sum in place of the full colour matrix."""
+    assert colour in ("full", "leading")
     generate(n)
     c = dict(_LAST_COUNT)
+    lc = colour == "leading"
     if n >= 3:
         c["algorithm"] = "helicity-recycled objects"
         c["stages"] = _COOP_COUNT["stages"]
-        c["per_helicity"] = _COOP_COUNT["per_helicity"]
+        c["per_helicity"] = _COOP_COUNT["per_helicity_lc" if lc else "per_helicity"]
         c["object_store"] = _COOP_COUNT["object_store"]
         c["per_event"] = c["momentum_only"] + c["stages"] + c["n_hel"] * c["per_helicity"]
     else:
         c["algorithm"] = "independent helicities"
         c["stages"] = 0
+        if lc:
+            c["per_helicity"] = c["per_helicity_lc"]
         c["per_event"] = c["momentum_only"] + c["n_hel"] * c["per_helicity"]
     return c
 

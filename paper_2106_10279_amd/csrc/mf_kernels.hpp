@@ -330,8 +330,9 @@ struct Layout {
 
 // Colour-summed |M|^2 of helicity `h` for the event whose table is `tab`:
 // lanes of the event (h = 0 .. 2^(NG+2) - 1) build the object store first
-// (n_g >= 3).  `any_live` must be uniform over the wave.
-template <int NG, typename T>
+// (n_g >= 3).  `any_live` must be uniform over the wave.  COL = 0: full
+// colour matrix; COL = 1: leading-colour approximation (Sec. 3.3 names it).
+template <int NG, typename T, int COL = 0>
 __device__ __forceinline__ double event_me2(const TabT<NG, T>* tab, T* obj, int h, double mt, bool live, bool any_live)
 {
     using L = Layout<NG>;
@@ -345,11 +346,11 @@ __device__ __forceinline__ double event_me2(const TabT<NG, T>* tab, T* obj, int 
         if (!live)
             return 0.0;
         if constexpr (NG == 3)
-            return coop_me2_ng3<T>(tab, obj, h);
+            return coop_me2_ng3<T, COL>(tab, obj, h);
         else
-            return coop_me2_ng4<T>(tab, obj, h);
+            return coop_me2_ng4<T, COL>(tab, obj, h);
     } else {
-        return live ? colour_summed_me2_ng2<T>(tab, h, mt) : 0.0;
+        return live ? colour_summed_me2_ng2<T, COL>(tab, h, mt) : 0.0;
     }
 }
 
@@ -468,7 +469,7 @@ __device__ __forceinline__ int event_kinematics(const EventParams& P, uint64_t e
     return flags;
 }
 
-template <int NG, typename T>
+template <int NG, typename T, int COL = 0>
 __global__ void __launch_bounds__(kBlock) event_kernel(EventParams P)
 {
     constexpr int NF = NG;
@@ -545,7 +546,7 @@ __global__ void __launch_bounds__(kBlock) event_kernel(EventParams P)
                 if (live)
                     fill_table<NG, T>(m_e, m_e[L::kMom - 1], P.m_top, P.mw, tab, obj, h);
                 wave_sync();
-                double v = event_me2<NG, T>(tab, obj, h, P.m_top, live, any_live);
+                double v = event_me2<NG, T, COL>(tab, obj, h, P.m_top, live, any_live);
                 v = group_sum(v, L::kHel);
                 if (h == 0)
                     s_me[wv][e] = v;
@@ -678,7 +679,7 @@ __global__ void __launch_bounds__(kBlock) kin_kernel(StageParams S)
 // momentum component).  Groups without a passing event are skipped whole.
 constexpr int kAmpChunk = 16;
 
-template <int NG, typename T>
+template <int NG, typename T, int COL = 0>
 __global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2))) amp_kernel(StageParams S)
 {
     using L = Layout<NG>;
@@ -732,7 +733,7 @@ __global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(size
             if (live)
                 fill_table<NG, T>(mom, mom[L::kMom - 1], S.P.m_top, S.P.mw, tab, obj, h);
             wave_sync();
-            double v = event_me2<NG, T>(tab, obj, h, S.P.m_top, live, any_live);
+            double v = event_me2<NG, T, COL>(tab, obj, h, S.P.m_top, live, any_live);
             v = group_sum(v, L::kHel);
             if (h == 0 && live)
                 S.me[e] = v;

@@ -174,6 +174,8 @@ mf_status validate_options(const mf_options* opt, int D)
         return fail(MF_EINVAL, "alpha must be finite and > 0");
     if (opt->precision != MF_FP64 && opt->precision != MF_FP32_KAHAN)
         return fail(MF_EINVAL, "unknown precision");
+    if (opt->colour != MF_COLOUR_FULL && opt->colour != MF_COLOUR_LEADING)
+        return fail(MF_EINVAL, "unknown colour mode");
     if (opt->max_batch > kStageBatch)
         return fail(MF_EINVAL, "max_batch must be at most 2^27");
     if (opt->max_newton < 0 || opt->max_newton > 1000)
@@ -244,34 +246,42 @@ mf_status prepare(const mf_process* proc, double sqrt_s, const mf_pdf_grid* pdf,
     return MF_OK;
 }
 
-template <int NG, typename T>
+template <int NG, typename T, int COL>
 mf_status launch_event(const mf::EventParams& P, int blocks, hipStream_t stream)
 {
     constexpr int D = 2 + 3 * NG - 4;
     const size_t dyn = P.partials ? sizeof(double) * mf::kWavesPerBlock * D * P.n_bins : 0;
-    hipLaunchKernelGGL((mf::event_kernel<NG, T>), dim3(blocks), dim3(mf::kBlock), dyn, stream, P);
+    hipLaunchKernelGGL((mf::event_kernel<NG, T, COL>), dim3(blocks), dim3(mf::kBlock), dyn, stream, P);
     MF_HIP(hipGetLastError());
     return MF_OK;
 }
 
-mf_status dispatch_event(int ng, mf_precision prec, const mf::EventParams& P, int blocks, hipStream_t s)
+template <int NG, int COL>
+mf_status launch_event_prec(mf_precision prec, const mf::EventParams& P, int blocks, hipStream_t s)
 {
-    const bool f32 = prec == MF_FP32_KAHAN;
+    return prec == MF_FP32_KAHAN ? launch_event<NG, float, COL>(P, blocks, s)
+                                 : launch_event<NG, double, COL>(P, blocks, s);
+}
+
+mf_status dispatch_event(int ng, mf_precision prec, mf_colour col, const mf::EventParams& P, int blocks,
+                         hipStream_t s)
+{
+    const bool lc = col == MF_COLOUR_LEADING;
     switch (ng) {
-    case 2: return f32 ? launch_event<2, float>(P, blocks, s) : launch_event<2, double>(P, blocks, s);
-    case 3: return f32 ? launch_event<3, float>(P, blocks, s) : launch_event<3, double>(P, blocks, s);
-    default: return f32 ? launch_event<4, float>(P, blocks, s) : launch_event<4, double>(P, blocks, s);
+    case 2: return lc ? launch_event_prec<2, 1>(prec, P, blocks, s) : launch_event_prec<2, 0>(prec, P, blocks, s);
+    case 3: return lc ? launch_event_prec<3, 1>(prec, P, blocks, s) : launch_event_prec<3, 0>(prec, P, blocks, s);
+    default: return lc ? launch_event_prec<4, 1>(prec, P, blocks, s) : launch_event_prec<4, 0>(prec, P, blocks, s);
     }
 }
 
 // Amplitude-kernel workgroups (one wave each) for the persistent loop: as
 // many as can be resident at once, so that every workgroup runs from start to
 // end alongside all the others (the groups of events are assigned statically).
-template <int NG, typename T>
+template <int NG, typename T, int COL>
 mf_status amp_grid_for(uint64_t n_groups, int n_cu, int* grid)
 {
     int per_cu = 0;
-    MF_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, mf::amp_kernel<NG, T>, mf::kWave, 0));
+    MF_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, mf::amp_kernel<NG, T, COL>, mf::kWave, 0));
     if (per_cu < 1)
         per_cu = 1;
     const uint64_t cap = (uint64_t)n_cu * per_cu;
@@ -279,13 +289,13 @@ mf_status amp_grid_for(uint64_t n_groups, int n_cu, int* grid)
     return MF_OK;
 }
 
-template <int NG, typename T>
+template <int NG, typename T, int COL>
 mf_status launch_stages(const mf::StageParams& S, int kin_blocks, int n_cu, hipStream_t stream,
                         hipEvent_t amp_begin, hipEvent_t amp_end)
 {
     constexpr int D = 2 + 3 * NG - 4;
     int amp_grid = 1;
-    mf_status st = amp_grid_for<NG, T>((S.count + mf::Layout<NG>::kEventsPerPass - 1) / mf::Layout<NG>::kEventsPerPass,
+    mf_status st = amp_grid_for<NG, T, COL>((S.count + mf::Layout<NG>::kEventsPerPass - 1) / mf::Layout<NG>::kEventsPerPass,
                                        n_cu, &amp_grid);
     if (st != MF_OK)
         return st;
@@ -293,7 +303,7 @@ mf_status launch_stages(const mf::StageParams& S, int kin_blocks, int n_cu, hipS
     MF_HIP(hipGetLastError());
     if (amp_begin)
         MF_HIP(hipEventRecord(amp_begin, stream));
-    hipLaunchKernelGGL((mf::amp_kernel<NG, T>), dim3(amp_grid), dim3(mf::kWave), 0, stream, S);
+    hipLaunchKernelGGL((mf::amp_kernel<NG, T, COL>), dim3(amp_grid), dim3(mf::kWave), 0, stream, S);
     MF_HIP(hipGetLastError());
     if (amp_end)
         MF_HIP(hipEventRecord(amp_end, stream));
@@ -303,15 +313,23 @@ mf_status launch_stages(const mf::StageParams& S, int kin_blocks, int n_cu, hipS
     return MF_OK;
 }
 
-mf_status dispatch_stages(int ng, mf_precision prec, const mf::StageParams& S, int kin_blocks, int n_cu,
-                          hipStream_t s, hipEvent_t a, hipEvent_t b)
+template <int NG, int COL>
+mf_status launch_stages_prec(mf_precision prec, const mf::StageParams& S, int kin_blocks, int n_cu, hipStream_t s,
+                             hipEvent_t a, hipEvent_t b)
 {
-    const bool f32 = prec == MF_FP32_KAHAN;
+    return prec == MF_FP32_KAHAN ? launch_stages<NG, float, COL>(S, kin_blocks, n_cu, s, a, b)
+                                 : launch_stages<NG, double, COL>(S, kin_blocks, n_cu, s, a, b);
+}
+
+mf_status dispatch_stages(int ng, mf_precision prec, mf_colour col, const mf::StageParams& S, int kin_blocks,
+                          int n_cu, hipStream_t s, hipEvent_t a, hipEvent_t b)
+{
+    const bool lc = col == MF_COLOUR_LEADING;
     if (ng == 3)
-        return f32 ? launch_stages<3, float>(S, kin_blocks, n_cu, s, a, b)
-                   : launch_stages<3, double>(S, kin_blocks, n_cu, s, a, b);
-    return f32 ? launch_stages<4, float>(S, kin_blocks, n_cu, s, a, b)
-               : launch_stages<4, double>(S, kin_blocks, n_cu, s, a, b);
+        return lc ? launch_stages_prec<3, 1>(prec, S, kin_blocks, n_cu, s, a, b)
+                  : launch_stages_prec<3, 0>(prec, S, kin_blocks, n_cu, s, a, b);
+    return lc ? launch_stages_prec<4, 1>(prec, S, kin_blocks, n_cu, s, a, b)
+              : launch_stages_prec<4, 0>(prec, S, kin_blocks, n_cu, s, a, b);
 }
 
 mf_status device_workspace(Workspace** out)
@@ -413,6 +431,7 @@ void mf_default_options(mf_options* opt)
     opt->stream = nullptr;
     opt->profile = 0;
     opt->max_batch = 0;
+    opt->colour = MF_COLOUR_FULL;
 }
 
 int mf_n_dims(int process_id)
@@ -451,6 +470,8 @@ mf_status integrate_impl(const mf_process* proc, double sqrt_s, const mf_pdf_gri
             return fail(MF_EUNSUPPORTED, "gradients are implemented for g g -> t tbar only");
         if (opt->precision != MF_FP64)
             return fail(MF_EUNSUPPORTED, "gradients are computed in FP64 only");
+        if (opt->colour != MF_COLOUR_FULL)
+            return fail(MF_EUNSUPPORTED, "gradients are computed with the full colour sum only");
     }
 
     Workspace* wsp = nullptr;
@@ -564,11 +585,12 @@ mf_status integrate_impl(const mf_process* proc, double sqrt_s, const mf_pdf_gri
                     a = amp_marks[2 * ((size_t)j * n_batches + bi)];
                     b = amp_marks[2 * ((size_t)j * n_batches + bi) + 1];
                 }
-                if ((st = dispatch_stages(ng, opt->precision, SP, n_waves / mf::kWavesPerBlock, ws.n_cu, S.stream, a,
-                                          b)) != MF_OK)
+                if ((st = dispatch_stages(ng, opt->precision, opt->colour, SP, n_waves / mf::kWavesPerBlock,
+                                          ws.n_cu, S.stream, a, b)) != MF_OK)
                     return st;
             }
-        } else if ((st = dispatch_event(ng, opt->precision, P, n_waves / mf::kWavesPerBlock, S.stream)) != MF_OK) {
+        } else if ((st = dispatch_event(ng, opt->precision, opt->colour, P, n_waves / mf::kWavesPerBlock,
+                                        S.stream)) != MF_OK) {
             return st;
         }
         if (grad) {
@@ -783,7 +805,7 @@ mf_status mf_evaluate(const mf_process* proc, double sqrt_s, const mf_pdf_grid* 
     P.k53_out = k53_out;
     P.bins_out = bins_out;
     P.record = record_out;
-    if ((st = dispatch_event(S.ng, opt->precision, P, P.n_waves / mf::kWavesPerBlock, S.stream)) != MF_OK)
+    if ((st = dispatch_event(S.ng, opt->precision, opt->colour, P, P.n_waves / mf::kWavesPerBlock, S.stream)) != MF_OK)
         return st;
     MF_HIP(hipStreamSynchronize(S.stream));
     return MF_OK;
@@ -799,6 +821,8 @@ mf_status mf_evaluate_grad(const mf_process* proc, double sqrt_s, const mf_pdf_g
         return fail(MF_EUNSUPPORTED, "gradients are implemented for g g -> t tbar only");
     if (opt && opt->precision != MF_FP64)
         return fail(MF_EUNSUPPORTED, "gradients are computed in FP64 only");
+    if (opt && opt->colour != MF_COLOUR_FULL)
+        return fail(MF_EUNSUPPORTED, "gradients are computed with the full colour sum only");
     std::unique_lock<std::mutex> lock;
     Setup S;
     mf_status st;

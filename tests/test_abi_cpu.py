@@ -155,3 +155,34 @@ def test_unweight_of_no_events_returns_nothing_without_device(L):
     st, ev = _unweight_call(L, w=None, n=0)
     assert st == L.MF_OK
     assert ev.n_kept == 0 and ev.n_over == 0
+
+
+def test_colour_mode_default_and_validation_without_device(L, pdf_table):
+    from paper_2106_10279_amd import api
+    o = L.mf_options()
+    L.lib.mf_default_options(C.byref(o))
+    assert o.colour == 0                      # MF_COLOUR_FULL
+    with pytest.raises(L.MFError) as e:
+        api.integrate(api.Process("gg_ttxgg"), 13000.0, pdf_table, 1000, 1, 0, keep_weights=False,
+                      stream=0, colour=2)
+    assert e.value.status == L.MF_EINVAL
+    assert b"colour" in L.lib.mf_last_error()
+
+
+def test_gradient_rejects_leading_colour_without_device(L, pdf_table):
+    from paper_2106_10279_amd import api
+    o = L.mf_options()
+    L.lib.mf_default_options(C.byref(o))
+    o.colour = 1                              # MF_COLOUR_LEADING
+    proc = api.Process("gg_ttx").c()
+    pdf = api._Pdf(pdf_table)
+    res = L.mf_result()
+    g = L.mf_grad_result()
+    st = L.lib.mf_integrate_grad(C.byref(proc), 13000.0, C.byref(pdf.c), 1000, 1, 0, C.byref(o),
+                                 C.byref(res), C.byref(g))
+    assert st == L.MF_EUNSUPPORTED
+    assert b"colour" in L.lib.mf_last_error()
+    w = C.c_void_p(16)                         # never dereferenced: rejected before any device call
+    st = L.lib.mf_evaluate_grad(C.byref(proc), 13000.0, C.byref(pdf.c), None, None, None, 10, 0, 0,
+                                C.byref(o), w, None, None)
+    assert st == L.MF_EUNSUPPORTED

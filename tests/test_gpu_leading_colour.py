@@ -1,0 +1,139 @@
+"""GPU parity of the leading-colour variant (colour = "leading": the colour
+matrix replaced by (N^2 - 1) N^(n - 1) / 2^n times the identity) against the
+oracle's leading-colour sum, through the C ABI."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+SQRT_S = 13000.0
+CONF = {
+    2: dict(process="gg_ttx"),
+    3: dict(process="gg_ttxg", ptmin_g=20.0, etamax_g=2.5),
+    4: dict(process="gg_ttxgg", ptmin_g=20.0, drmin_gg=0.4),
+}
+
+
+@pytest.fixture(scope="module")
+def api():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2106_10279_amd import api
+    return api
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def gproc(api, n_g):
+    return api.Process(**CONF[n_g])
+
+
+def oproc(n_g):
+    c = {k: v for k, v in CONF[n_g].items() if k != "process"}
+    return O.Process(n_g=n_g, colour="leading", **c)
+
+
+def uniform_grid(D, nb=50):
+    return np.tile(np.arange(nb + 1) / nb, (D, 1))
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32_kahan", 2e-4)])
+@pytest.mark.parametrize("n_g,n", [(2, 3000), (3, 1500), (4, 300)])
+def test_lc_event_weights_match_oracle(api, pdf_table, n_g, n, precision, tol):
+    """Per-event leading-colour weights of the fused event kernel on a
+    uniform and a refined grid (FP32 amplitudes at FP32 tolerance)."""
+    say(f"lc weights n_g={n_g} n={n} {precision}")
+    D = 2 + 3 * n_g - 4
+    rng = np.random.default_rng(40 + n_g)
+    grids = [uniform_grid(D), O.vegas_refine(rng.exponential(size=(D, 50)) ** 2, uniform_grid(D))]
+    for gi, grid in enumerate(grids):
+        w = api.evaluate_weights(gproc(api, n_g), SQRT_S, pdf_table, n, seed=3, it=1, grid=grid,
+                                 precision=precision, colour="leading").cpu().numpy()
+        worst, used = 0.0, 0
+        for e in range(n):
+            ref, ev = O.event_weight(oproc(n_g), SQRT_S, pdf_table, grid, 3, 1, e)
+            if ev.near_edge or ev.ill_conditioned:
+                continue
+            if ref == 0.0:
+                assert w[e] == 0.0, e
+                continue
+            worst = max(worst, abs(w[e] / ref - 1))
+            used += 1
+        say(f"  grid {gi}: {used} nonzero weights, max rel {worst:.2e}")
+        assert used > n // 4
+        assert worst < tol
+
+
+@pytest.mark.parametrize("n_g,n,iters", [(2, 20_000, 3), (3, 3_000, 2), (4, 700, 2)])
+def test_lc_integration_matches_oracle(api, pdf_table, n_g, n, iters):
+    """Integration with the leading-colour sum (three-kernel form for n_g >= 3):
+    per-iteration estimates, grids and last-iteration weights."""
+    say(f"lc integrate n_g={n_g} n={n} iters={iters}")
+    g = api.integrate(gproc(api, n_g), SQRT_S, pdf_table, n, iters, seed=0, colour="leading")
+    o = O.integrate(oproc(n_g), SQRT_S, pdf_table, n, iters, seed=0)
+    say("  gpu", g.sigma, g.sigma_err, "oracle", o.sigma, o.sigma_err)
+    np.testing.assert_allclose(g.iter_sigma, o.iter_sigma, rtol=1e-10, atol=0)
+    np.testing.assert_allclose(g.iter_var, o.iter_var, rtol=1e-8, atol=0)
+    assert abs(g.sigma / o.sigma - 1) < 1e-10
+    np.testing.assert_allclose(g.grid, o.grid, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(g.weights.cpu().numpy(), o.weights_last, rtol=1e-11, atol=0)
+    assert g.n_pass == o.n_pass
+
+
+@pytest.mark.parametrize("n_g", [3, 4])
+def test_lc_three_kernel_weights_equal_the_fused_kernel(api, pdf_table, n_g):
+    import torch
+    proc = gproc(api, n_g)
+    N = 5000
+    g1 = api.integrate(proc, SQRT_S, pdf_table, N, 1, 0, keep_weights=False, colour="leading").grid
+    r = api.integrate(proc, SQRT_S, pdf_table, N, 2, 0, keep_weights=True, colour="leading")
+    w_fused = api.evaluate_weights(proc, SQRT_S, pdf_table, N, seed=0, it=1, grid=g1, colour="leading")
+    assert torch.equal(r.weights, w_fused)
+
+
+def test_lc_over_full_ttx_per_event_bound_at_1e6(api, pdf_table):
+    """g g -> t tbar: the leading-colour / full-colour ratio of |M|^2 at zero
+    width is (3/16)(1/(tau1 tau2) - 2) / (1/(6 tau1 tau2) - 3/8), which lies in
+    (9/8, 9/7] for tau1 tau2 in (0, 1/4]; the 1.5 GeV width moves it by
+    O(1e-5).  Checked on all 1e6 events of one launch."""
+    import torch
+    proc = gproc(api, 2)
+    n = 1_000_000
+    wf = api.evaluate_weights(proc, SQRT_S, pdf_table, n, seed=9, it=0)
+    wl = api.evaluate_weights(proc, SQRT_S, pdf_table, n, seed=9, it=0, colour="leading")
+    nz = wf != 0
+    assert torch.equal(nz, wl != 0)
+    r = (wl[nz] / wf[nz]).cpu().numpy()
+    say(f"  {r.size} nonzero events, LC / full in [{r.min():.6f}, {r.max():.6f}]")
+    assert r.size > 0.9 * n
+    assert r.min() > 9 / 8 - 1e-4 and r.max() < 9 / 7 + 1e-4
+    assert r.max() - r.min() > 0.1       # the bound is approached from both ends
+
+
+def test_lc_ttxgg_1e7_sampled_events(api, oracle_lib, pdf_table):
+    """Leading colour at the full t tbar g g size (1e7 events per iteration):
+    2000 sampled events of the second iteration against the oracle."""
+    proc = gproc(api, 4)
+    N = 10_000_000
+    r = api.integrate(proc, SQRT_S, pdf_table, N, 2, 0, keep_weights=True, colour="leading")
+    rng = np.random.default_rng(51)
+    ids = np.sort(rng.choice(N, size=2000, replace=False))
+    w_o, flags = oracle_lib.event_weights(oproc(4), SQRT_S, pdf_table, r.grid_last, 0, 1, ids)
+    wg = r.weights[ids].cpu().numpy()
+    skip = (flags & (8 | 16)) != 0
+    zero = (w_o == 0.0) & ~skip
+    assert np.all(wg[zero] == 0.0)
+    use = ~skip & ~zero
+    rel = np.abs(wg[use] / w_o[use] - 1.0)
+    say(f"  1e7 leading colour: {int(use.sum())} of 2000 sampled events, max rel {rel.max():.2e}")
+    assert use.sum() > 1400
+    assert rel.max() < 1e-12
