@@ -906,15 +906,17 @@ def emit_coop(n, lay, co, K, den, perms):
     loads, computes = [], []
     for gi, (X, Y) in enumerate(keys):
         ob = f"ob{gi}"
-        L = [f"    int z{gi} = 0;", f'    asm volatile("" : "+v"(z{gi}));', f"    const T* {ob} = obj + z{gi};"]
+        L = [f"    int z{gi} = 0;", f'    asm volatile("" : "+s"(z{gi}));',
+             f"    const T* {ob} = (const T*)((const char*)obj + z{gi});"]
         if not X or not Y:
-            L.append(f"    const T* tb{gi} = tab + z{gi};")
+            L.append(f"    const T* tb{gi} = (const T*)((const char*)tab + z{gi});")
         r, lr = row_load(X, f"xr{gi}", ob)
         c, lc = col_load(Y, f"yc{gi}", ob)
         L += lr + lc
         # the currents are read at the start of the group itself (behind a
         # second opaque zero), in the shadow of the bilinear
-        Cc = ["    {", "        int y = 0;", '        asm volatile("" : "+v"(y));', "        const T* oc = obj + y;"]
+        Cc = ["    {", "        int y = 0;", '        asm volatile("" : "+s"(y));',
+              "        const T* oc = (const T*)((const char*)obj + y);"]
         cur_at = len(Cc)
         Cc += ["        cplx<T> d[4];", f"        bilinear({r}, {c}, d);"]
         hel_flops += 64
