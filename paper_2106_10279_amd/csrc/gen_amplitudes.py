@@ -124,7 +124,7 @@ class Layout:
         self.Kv = {}
         for m in range(1, 1 << n):
             if 1 <= bin(m).count("1") <= n - 2:
-                self.Kv[m] = off     # -k_tbar - P[m], and -1/(Kv^2 - m^2 + i m Gamma)
+                self.Kv[m] = off     # -k_tbar - P[m] (= k_t + P[complement]), -1/(Kv^2 - m^2 + i m Gamma)
                 off += 6
         self.ub = off
         off += 16
@@ -168,14 +168,16 @@ class CoopTable:
         self.Kv = {}
         for m in range(1, 1 << n):
             if 1 <= bin(m).count("1") <= n - 2:
-                self.Kv[m] = off       # -k_tbar - P[m], and -1/(Kv^2 - m^2 + i m Gamma)
+                self.Kv[m] = off       # -k_tbar - P[m] (= k_t + P[complement]), -1/(Kv^2 - m^2 + i m Gamma)
                 off += 6
         # a multiple of 4 elements, so that every event's table starts aligned
         self.size = (off + 3) // 4 * 4
 
     def mom_flops(self):
         n = self.n
+        # subset sums, plus the complement sums of the antitop-line momenta
         return (sum(4 * (bin(m).count("1") - 1) for m in range(1, 1 << n)) + 8 * len(self.ninv)
+                + sum(4 * (n - bin(m).count("1") - 1) for m in self.Kv)
                 + 17 * (len(self.K1) + len(self.Kv)) + 4 * 24 + (n - 2) * 2 * 16 + 2)
 
 
@@ -190,7 +192,8 @@ def emit_coop_fill(n, tl, co):
     w("    const double m2 = mt * mt;")
     w(f"    if (lane >= 1 && lane <= {nsub}) {{")
     w("        const int m = lane;")
-    w("        double P0 = 0.0, P1 = 0.0, P2 = 0.0, P3 = 0.0;")
+    # P: the subset's momentum; C: its complement's (all momenta outgoing)
+    w("        double P0 = 0.0, P1 = 0.0, P2 = 0.0, P3 = 0.0, C0 = 0.0, C1 = 0.0, C2 = 0.0, C3 = 0.0;")
     for g in range(n):
         if g == 0:
             pv = ["-eb", "0.0", "0.0", "-eb"]
@@ -199,6 +202,7 @@ def emit_coop_fill(n, tl, co):
         else:
             pv = [f"mom[{8 + 4 * (g - 2) + mu}]" for mu in range(4)]
         w(f"        if (m & {1 << g}) {{ P0 += {pv[0]}; P1 += {pv[1]}; P2 += {pv[2]}; P3 += {pv[3]}; }}")
+        w(f"        else {{ C0 += {pv[0]}; C1 += {pv[1]}; C2 += {pv[2]}; C3 += {pv[3]}; }}")
     p_off = ", ".join(str(tl.P.get(m, -1)) for m in range(1, 1 << n))
     w(f"        const short p_off[{nsub}] = {{{p_off}}};")
     w("        if (p_off[m - 1] >= 0) {")
@@ -223,8 +227,12 @@ def emit_coop_fill(n, tl, co):
     w("        }")
     kv_offsets = ", ".join(str(tl.Kv.get(m, -1)) for m in range(1, 1 << n))
     w(f"        const short kv_off[{nsub}] = {{{kv_offsets}}};")
+    # the antitop-line momentum -k_tbar - P[m] is formed as k_t + P[complement]:
+    # the same sum as the top-line propagator of that internal line, so that
+    # both sides of a near on-shell line see the same rounding of the event's
+    # momenta (their conservation holds to rounding only)
     w("        if (kv_off[m - 1] >= 0) {")
-    w("            const double K0 = -mom[4] - P0, K1 = -mom[5] - P1, K2 = -mom[6] - P2, K3 = -mom[7] - P3;")
+    w("            const double K0 = mom[0] + C0, K1 = mom[1] + C1, K2 = mom[2] + C2, K3 = mom[3] + C3;")
     w("            const double re = K0 * K0 - K1 * K1 - K2 * K2 - K3 * K3 - m2;")
     w("            const double inv = 1.0 / (re * re + mw * mw);")
     w("            T* k = tab + kv_off[m - 1];")
@@ -394,7 +402,7 @@ def emit_table_fill(n, lay):
     w("    const double m2 = mt * mt;")
     w(f"    if (lane >= 1 && lane <= {nsub}) {{")
     w("        const int m = lane;")
-    w("        double P0 = 0.0, P1 = 0.0, P2 = 0.0, P3 = 0.0;")
+    w("        double P0 = 0.0, P1 = 0.0, P2 = 0.0, P3 = 0.0, C0 = 0.0, C1 = 0.0, C2 = 0.0, C3 = 0.0;")
     for g in range(n):
         if g == 0:
             pv = ["-eb", "0.0", "0.0", "-eb"]
@@ -403,6 +411,7 @@ def emit_table_fill(n, lay):
         else:
             pv = [f"mom[{8 + 4 * (g - 2) + mu}]" for mu in range(4)]
         w(f"        if (m & {1 << g}) {{ P0 += {pv[0]}; P1 += {pv[1]}; P2 += {pv[2]}; P3 += {pv[3]}; }}")
+        w(f"        else {{ C0 += {pv[0]}; C1 += {pv[1]}; C2 += {pv[2]}; C3 += {pv[3]}; }}")
     w("        const int off_p = 4 * (m - 1);")
     w("        tab[off_p + 0] = P0; tab[off_p + 1] = P1; tab[off_p + 2] = P2; tab[off_p + 3] = P3;")
     # -1/P^2 for |m| >= 2
@@ -423,8 +432,9 @@ def emit_table_fill(n, lay):
     w("        }")
     kv_offsets = ", ".join(str(lay.Kv.get(m, -1)) for m in range(1, 1 << n))
     w(f"        const int kv_off[{nsub}] = {{{kv_offsets}}};")
+    # -k_tbar - P[m] formed as k_t + P[complement] (see the cooperative fill)
     w("        if (kv_off[m - 1] >= 0) {")
-    w("            const double K0 = -mom[4] - P0, K1 = -mom[5] - P1, K2 = -mom[6] - P2, K3 = -mom[7] - P3;")
+    w("            const double K0 = mom[0] + C0, K1 = mom[1] + C1, K2 = mom[2] + C2, K3 = mom[3] + C3;")
     w("            const double re = K0 * K0 - K1 * K1 - K2 * K2 - K3 * K3 - m2;")
     w("            const double inv = 1.0 / (re * re + mw * mw);")
     w("            double* k = tab + kv_off[m - 1];")

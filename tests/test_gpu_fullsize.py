@@ -80,7 +80,8 @@ def test_ttxgg_fp64_1e7_sampled_events_and_properties(api, oracle_lib, pdf_table
 def test_ttxgg_fp32_1e8_sampled_events_and_integral(api, oracle_lib, pdf_table):
     """The FP32-amplitude form at 1e8 events: sampled events against the FP64
     oracle at FP32 tolerance, and the integral against the FP64 GPU path on the
-    same 1e8 events and grid (target <= 1e-6)."""
+    same 1e8 events and grid (target <= 1e-6); the FP64 run's own sampled
+    events against the oracle at the FP64 bar."""
     import torch
     proc = api.Process("gg_ttxgg", **_cuts())
     N = 100_000_000
@@ -100,8 +101,15 @@ def test_ttxgg_fp32_1e8_sampled_events_and_integral(api, oracle_lib, pdf_table):
     I32 = float(w32.sum().item())
     del w32
     torch.cuda.empty_cache()
-    w64 = api.integrate(proc, SQRT_S, pdf_table, N, 1, 0, grid_in=grid, keep_weights=True).weights
+    r64 = api.integrate(proc, SQRT_S, pdf_table, N, 1, 0, grid_in=grid, keep_weights=True)
+    w64 = r64.weights
     I64 = float(w64.sum().item())
+    assert I64 / N == pytest.approx(r64.iter_sigma[0], rel=1e-12)
+    # the FP64 form at 1e8 events: sampled events against the oracle at the FP64 bar
+    rel64, used64, _, ids64 = _spot_check(api, oracle_lib, pdf_table, w64, grid, 0, N, 10_000, 23, 1e-12)
+    print(f"  1e8 FP64: {used64} of 10000 sampled events up to id {ids64.max()}, max rel {rel64.max():.2e}")
+    assert used64 > 7000
+    assert rel64.max() < 1e-12
     del w64
     torch.cuda.empty_cache()
     print(f"  integral FP32 vs FP64 over 1e8 events: rel {abs(I32 / I64 - 1):.2e}")
