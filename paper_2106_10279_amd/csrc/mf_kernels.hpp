@@ -469,8 +469,12 @@ __device__ __forceinline__ int event_kinematics(const EventParams& P, uint64_t e
     return flags;
 }
 
+// g g -> t tbar is bound by latency more than by issue: three resident waves
+// per SIMD (at most 168 registers, a few loop invariants spilled) run it
+// faster than two without spills.  The heavier processes keep their registers.
 template <int NG, typename T, int COL = 0>
-__global__ void __launch_bounds__(kBlock) event_kernel(EventParams P)
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(NG == 2 ? 3 : 1)))
+event_kernel(EventParams P)
 {
     constexpr int NF = NG;
     constexpr int D = 2 + 3 * NF - 4;
