@@ -10,4 +10,5 @@ from .oracle import (  # noqa: F401
     me2_sum_fullcolour, event_weight, event_weight_y, integrate, combine,
     neumaier_sum, ttx_dweight_dmt_analytic, n_dims, all_helicities,
     unweight_uniform, unweight, lab_event, event_weights, colour_lc, me2_sum_lc,
+    colour_count, colour_config, colour_factors, me2_sum_colour_config,
 )

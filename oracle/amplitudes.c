@@ -506,6 +506,83 @@ double mfo_me2_sum_lc(int n_g, const double *p, double m, double width)
     return mfo_colour_lc(n_g) * total;
 }
 
+int64_t mfo_colour_count(int n_g)
+{
+    int64_t n = 9;
+    for (int g = 0; g < n_g; ++g)
+        n *= 8;
+    return n;
+}
+
+int64_t mfo_colour_config(int n_g, uint64_t seed, uint32_t iter, uint64_t event)
+{
+    uint32_t ctr[4] = { (uint32_t)event, (uint32_t)(event >> 32), iter, 0x80000001u };
+    uint32_t key[2] = { (uint32_t)seed, (uint32_t)(seed >> 32) };
+    uint32_t r[4];
+    mfo_philox4x32_10(ctr, key, r);
+    uint64_t k = ((((uint64_t)r[0]) << 32) | (uint64_t)r[1]) >> 11;
+    return (int64_t)(((k >> 16) * (uint64_t)mfo_colour_count(n_g)) >> 37);
+}
+
+static cplx gm_T[8][3][3];
+static pthread_once_t gm_once = PTHREAD_ONCE_INIT;
+
+static void gm_init(void)
+{
+    gell_mann_T(gm_T);
+}
+
+void mfo_colour_factors(int n_g, int64_t cfg, double *c)
+{
+    pthread_once(&gm_once, gm_init);
+    cplx (*T)[3][3] = gm_T;
+    int jj = (int)(cfg % 3);
+    int ii = (int)((cfg / 3) % 3);
+    int a[MFO_MAX_G];
+    int64_t rest = cfg / 9;
+    for (int g = 0; g < n_g; ++g) {
+        a[g] = (int)(rest % 8);
+        rest /= 8;
+    }
+    int nperm = mfo_n_orderings(n_g);
+    int perm[120 * MFO_MAX_G];
+    mfo_orderings(n_g, perm);
+    for (int s = 0; s < nperm; ++s) {
+        /* row i of the product T^{a_sigma1} ... T^{a_sigman}, then entry j */
+        cplx row[3] = { 0, 0, 0 };
+        row[ii] = 1;
+        for (int k = 0; k < n_g; ++k) {
+            cplx (*M)[3] = T[a[perm[s * n_g + k]]];
+            cplx nr[3];
+            for (int q = 0; q < 3; ++q)
+                nr[q] = row[0] * M[0][q] + row[1] * M[1][q] + row[2] * M[2][q];
+            memcpy(row, nr, sizeof(nr));
+        }
+        c[2 * s] = creal(row[jj]);
+        c[2 * s + 1] = cimag(row[jj]);
+    }
+}
+
+double mfo_me2_sum_colour_config(int n_g, const double *p, double m, double width, int64_t cfg)
+{
+    int nperm = mfo_n_orderings(n_g);
+    double c[2 * 120];
+    mfo_colour_factors(n_g, cfg, c);
+    int nh = 1 << (n_g + 2);
+    double total = 0.0;
+    for (int h = 0; h < nh; ++h) {
+        int hel[MFO_MAX_G + 2];
+        hel_from_index(n_g, h, hel);
+        cplx A[120];
+        partial_amplitudes_core(n_g, p, m, width, hel, -1, A);
+        cplx M = 0;
+        for (int s = 0; s < nperm; ++s)
+            M += (c[2 * s] + I * c[2 * s + 1]) * A[s];
+        total += creal(M) * creal(M) + cimag(M) * cimag(M);
+    }
+    return (double)mfo_colour_count(n_g) * total;
+}
+
 double mfo_me2_sum(int n_g, const double *p, double m, double width)
 {
     int nh = 1 << (n_g + 2);

@@ -139,8 +139,13 @@ static double weight_from_x(const mfo_process *proc, double sqrt_s,
         memcpy(p + 4 * (2 + i), ev->k[i], sizeof(double) * 4);
 
     double gs2 = 4.0 * PI * proc->alpha_s;
-    double sum = proc->colour == 1 ? mfo_me2_sum_lc(n_g, p, m, proc->w_top)
-                                   : mfo_me2_sum(n_g, p, m, proc->w_top);
+    double sum;
+    if (proc->colour == 2)
+        sum = ev->colour_cfg >= 0 ? mfo_me2_sum_colour_config(n_g, p, m, proc->w_top, ev->colour_cfg) : NAN;
+    else if (proc->colour == 1)
+        sum = mfo_me2_sum_lc(n_g, p, m, proc->w_top);
+    else
+        sum = mfo_me2_sum(n_g, p, m, proc->w_top);
     /* average over 2 x 2 initial helicities and 8 x 8 initial colours,
      * symmetry factor 1/(n_g - 2)! for identical final-state gluons */
     ev->me2 = pow(gs2, n_g) * sum / (4.0 * 64.0 * factorial(n_g - 2));
@@ -162,9 +167,11 @@ double mfo_event_weight(const mfo_process *proc, double sqrt_s,
         mfo_bin_from_k53(k53[d], n_bins, &ev->bin[d], &delta[d]);
     }
     double jac = mfo_vegas_map(D, n_bins, grid, ev->bin, delta, ev->x);
+    ev->colour_cfg = proc->colour == 2 ? mfo_colour_config(proc->n_g, seed, (uint32_t)iter, event) : -1;
     return weight_from_x(proc, sqrt_s, pdf, jac, ev);
 }
 
+/* Caller uniforms carry no event counter: with colour = 2 the weight is NaN. */
 double mfo_event_weight_y(const mfo_process *proc, double sqrt_s,
                           const mfo_pdf_grid *pdf, int n_bins, const double *grid,
                           const double *y, mfo_event *ev)
@@ -181,6 +188,7 @@ double mfo_event_weight_y(const mfo_process *proc, double sqrt_s,
         delta[d] = t - (double)b;
     }
     double jac = mfo_vegas_map(D, n_bins, grid, ev->bin, delta, ev->x);
+    ev->colour_cfg = -1;
     return weight_from_x(proc, sqrt_s, pdf, jac, ev);
 }
 

@@ -44,7 +44,8 @@ typedef struct {
     double ptmin_g;            /* gluon pT cut (GeV); <= 0 disables            */
     double etamax_g;           /* gluon |eta| cut; <= 0 disables               */
     double drmin_gg;           /* Delta R between final gluons; <= 0 disables  */
-    int    colour;             /* 0: full colour sum; 1: leading colour        */
+    int    colour;             /* 0: full colour sum; 1: leading colour;
+                                  2: colour Monte Carlo (one sampled assignment) */
 } mfo_process;
 
 typedef struct {
@@ -70,6 +71,7 @@ typedef struct {
     int    newton_fail;
     int    near_edge;          /* a cut variable lies within 1e-9 of its cut   */
     int    ill_conditioned;    /* |d ln(x g) / d ln x| > 1e3 at x1 or x2      */
+    int64_t colour_cfg;        /* colour = 2: the event's colour assignment    */
 } mfo_event;
 
 typedef struct {
@@ -127,6 +129,22 @@ double mfo_me2_sum_hel(int n_g, const double *p, double m, double width,
  * mfo_me2_sum_lc the helicity sum of c_LC sum_sigma |A(sigma)|^2, g_s = 1. */
 double mfo_colour_lc(int n_g);
 double mfo_me2_sum_lc(int n_g, const double *p, double m, double width);
+/* Monte Carlo over colours (also named in Sec. 3.3): each event carries one
+ * colour assignment -- adjoint indices a_1 .. a_n of the gluons (labels as
+ * in the amplitudes), colour i of the top and anticolour j of the antitop --
+ * drawn uniformly from the N_cfg = 9 * 8^n_g assignments.  The word pair
+ * (r0, r1) of Philox block 0x80000001 of the event's counter gives
+ * k = ((r0 << 32) | r1) >> 11 and cfg = ((k >> 16) * N_cfg) >> 37, decoded
+ * as j = cfg mod 3, i = (cfg / 3) mod 3, a_g = (cfg / 9 / 8^g) mod 8.  The
+ * colour-dressed amplitude is M = sum_sigma (T^{a_sigma1} .. T^{a_sigman})_{ij}
+ * A(sigma), and N_cfg |M|^2 summed over helicities is an unbiased estimate of
+ * the colour sum: its sum over all assignments is A^dagger C A.            */
+int64_t mfo_colour_config(int n_g, uint64_t seed, uint32_t iter, uint64_t event);
+int64_t mfo_colour_count(int n_g);
+/* c: [n_g!][2] (re, im) colour factors of the orderings for assignment cfg. */
+void mfo_colour_factors(int n_g, int64_t cfg, double *c);
+/* N_cfg * sum_h |M(cfg)|^2, g_s = 1.                                        */
+double mfo_me2_sum_colour_config(int n_g, const double *p, double m, double width, int64_t cfg);
 
 /* ---- per-event weight and integration ---------------------------------- */
 int mfo_n_dims(int n_g);

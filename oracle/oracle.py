@@ -35,7 +35,8 @@ class _Event(C.Structure):
                 ("shat", C.c_double), ("ps_weight", C.c_double), ("f1", C.c_double),
                 ("f2", C.c_double), ("me2", C.c_double), ("w", C.c_double),
                 ("k", C.c_double * 16), ("pass_threshold", C.c_int), ("pass_cuts", C.c_int),
-                ("newton_fail", C.c_int), ("near_edge", C.c_int), ("ill_conditioned", C.c_int)]
+                ("newton_fail", C.c_int), ("near_edge", C.c_int), ("ill_conditioned", C.c_int),
+                ("colour_cfg", C.c_int64)]
 
 
 class _Result(C.Structure):
@@ -93,6 +94,13 @@ def lib():
         L.mfo_colour_lc.restype = C.c_double
         L.mfo_me2_sum_lc.argtypes = [C.c_int, _dp, C.c_double, C.c_double]
         L.mfo_me2_sum_lc.restype = C.c_double
+        L.mfo_colour_count.argtypes = [C.c_int]
+        L.mfo_colour_count.restype = C.c_int64
+        L.mfo_colour_config.argtypes = [C.c_int, C.c_uint64, C.c_uint32, C.c_uint64]
+        L.mfo_colour_config.restype = C.c_int64
+        L.mfo_colour_factors.argtypes = [C.c_int, C.c_int64, _dp]
+        L.mfo_me2_sum_colour_config.argtypes = [C.c_int, _dp, C.c_double, C.c_double, C.c_int64]
+        L.mfo_me2_sum_colour_config.restype = C.c_double
         L.mfo_me2_sum_fullcolour.argtypes = [C.c_int, _dp, C.c_double, C.c_double, C.c_int, _ip]
         L.mfo_me2_sum_fullcolour.restype = C.c_double
         L.mfo_n_dims.argtypes = [C.c_int]
@@ -148,13 +156,14 @@ class Process:
     ptmin_g: float = 0.0
     etamax_g: float = 0.0
     drmin_gg: float = 0.0
-    colour: str = "full"        # "full" or "leading" (leading-colour approximation)
+    colour: str = "full"        # "full", "leading" (leading colour) or "sampled" (colour Monte Carlo)
 
     def c(self):
-        if self.colour not in ("full", "leading"):
-            raise ValueError(f"colour must be 'full' or 'leading', not {self.colour!r}")
+        modes = {"full": 0, "leading": 1, "sampled": 2}
+        if self.colour not in modes:
+            raise ValueError(f"colour must be one of {sorted(modes)}, not {self.colour!r}")
         return _Process(self.n_g, self.m_top, self.w_top, self.alpha_s, self.mu_f,
-                        self.ptmin_g, self.etamax_g, self.drmin_gg, int(self.colour == "leading"))
+                        self.ptmin_g, self.etamax_g, self.drmin_gg, modes[self.colour])
 
 
 class _PdfHandle:
@@ -296,6 +305,30 @@ def me2_sum_lc(n_g, p, m, width):
     """Helicity sum of c_LC sum_sigma |A(sigma)|^2 (leading colour), g_s = 1."""
     p = _f64(p)
     return lib().mfo_me2_sum_lc(n_g, _d(p), m, width)
+
+
+def colour_count(n_g):
+    """Number of colour assignments 9 * 8^n_g sampled by the colour Monte Carlo."""
+    return lib().mfo_colour_count(n_g)
+
+
+def colour_config(n_g, seed, it, event):
+    """The colour assignment of an event (Philox block 0x80000001)."""
+    return lib().mfo_colour_config(n_g, seed, it, event)
+
+
+def colour_factors(n_g, cfg):
+    """(T^{a_sigma1} ... T^{a_sigman})_{ij} for every ordering, assignment cfg."""
+    n = lib().mfo_n_orderings(n_g)
+    out = np.zeros(2 * n)
+    lib().mfo_colour_factors(n_g, cfg, _d(out))
+    return out[0::2] + 1j * out[1::2]
+
+
+def me2_sum_colour_config(n_g, p, m, width, cfg):
+    """N_cfg times the helicity sum of |M|^2 for colour assignment cfg, g_s = 1."""
+    p = _f64(p)
+    return lib().mfo_me2_sum_colour_config(n_g, _d(p), m, width, cfg)
 
 
 def all_helicities(n_g):
