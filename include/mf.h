@@ -53,7 +53,18 @@ typedef enum { MF_FP64 = 0, MF_FP32_KAHAN = 1 } mf_precision;
  * is replaced by c_LC = (N^2 - 1) N^(n_g - 1) / 2^n_g (N = 3: 6, 9, 13.5)
  * times the identity, the leading power of N of its diagonal; it changes the
  * integrand (by O(1/N^2)), not only its variance. */
-typedef enum { MF_COLOUR_FULL = 0, MF_COLOUR_LEADING = 1 } mf_colour;
+/* MF_COLOUR_SAMPLED is the Monte Carlo over colours that Sec. 3.3 names as
+ * well: every event carries one colour assignment (gluon adjoint indices,
+ * top colour, antitop anticolour), drawn uniformly from the N_cfg = 9 8^n_g
+ * assignments with Philox block 0x80000001 of its counter (the integrand
+ * uses blocks 0 .. ceil(D/2) - 1, unweighting block 0x80000000): with k the
+ * 53-bit integer of the block's first word pair, cfg = ((k >> 16) N_cfg) >> 37,
+ * j = cfg mod 3, i = (cfg / 3) mod 3, gluon g's index (cfg / 9 / 8^g) mod 8.
+ * The event's |M|^2 is N_cfg |sum_sigma (T^{a_sigma1} .. T^{a_sigman})_{ij}
+ * A(sigma)|^2 summed over helicities: an unbiased estimate of the colour sum
+ * with a larger variance.  mf_integrate only, for MF_GG_TTXG and MF_GG_TTXGG;
+ * other calls return MF_EUNSUPPORTED. */
+typedef enum { MF_COLOUR_FULL = 0, MF_COLOUR_LEADING = 1, MF_COLOUR_SAMPLED = 2 } mf_colour;
 
 typedef struct {
     mf_process_id id;
@@ -87,8 +98,8 @@ typedef struct {
     int profile;             /* 1: time every kernel with HIP events (0)        */
     uint64_t max_batch;      /* n_g >= 3: events per batch of the per-event device
                                 buffers (about 170 B per event), 0 = 2^27 (0)   */
-    mf_colour colour;        /* MF_COLOUR_FULL or MF_COLOUR_LEADING (FULL); the
-                                gradient entry points take MF_COLOUR_FULL only */
+    mf_colour colour;        /* MF_COLOUR_FULL, MF_COLOUR_LEADING or MF_COLOUR_SAMPLED
+                                (FULL); the gradient entry points take FULL only */
 } mf_options;
 
 typedef struct {

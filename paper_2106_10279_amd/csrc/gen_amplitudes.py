@@ -85,6 +85,28 @@ def lc_numerator(n, den):
     return int(v)
 
 
+def colour_count(n):
+    """Colour assignments sampled by the Monte Carlo over colours: gluon
+    adjoint indices (8 each), top colour and antitop anticolour (3 each)."""
+    return 9 * 8 ** n
+
+
+def gell_mann_half():
+    """T^a = lambda^a / 2, a = 1 .. 8, as (re, im) 3 x 3 tables."""
+    r3 = math.sqrt(3.0)
+    lam = [[[0j] * 3 for _ in range(3)] for _ in range(8)]
+    lam[0][0][1] = lam[0][1][0] = 1
+    lam[1][0][1], lam[1][1][0] = -1j, 1j
+    lam[2][0][0], lam[2][1][1] = 1, -1
+    lam[3][0][2] = lam[3][2][0] = 1
+    lam[4][0][2], lam[4][2][0] = -1j, 1j
+    lam[5][1][2] = lam[5][2][1] = 1
+    lam[6][1][2], lam[6][2][1] = -1j, 1j
+    lam[7][0][0] = lam[7][1][1] = 1 / r3
+    lam[7][2][2] = -2 / r3
+    return [[[complex(v) / 2 for v in row] for row in m] for m in lam]
+
+
 # ----------------------------------------------------------------------------
 # code emission helpers
 # ----------------------------------------------------------------------------
@@ -1024,7 +1046,7 @@ def emit_coop(n, lay, co, K, den, perms):
         a(f"        me += Ai[{sidx}] * ti;")
         full_flops += 2
         a("    }")
-    a("    } else {")
+    a("    } else if constexpr (COL == 1) {")
     a("        T s2 = Ar[0] * Ar[0];")
     a("        s2 += Ai[0] * Ai[0];")
     lc_flops = 3
@@ -1034,22 +1056,40 @@ def emit_coop(n, lay, co, K, den, perms):
         lc_flops += 4
     a(f"        me = (T){lc_numerator(n, den)} * s2;")
     lc_flops += 1
+    # Monte Carlo over colours (COL = 2): the event's colour factors cf
+    # (re, im per ordering) dress the amplitudes, M = sum_s c_s A_s; N_cfg |M|^2
+    # over the common denominator keeps the final division of the full sum
+    a("    } else {")
+    a("        T mr = 0, mi = 0;")
+    mc_flops = 0
+    for sidx in range(nperm_):
+        op = "+=" if sig[sidx] > 0 else "-="
+        a(f"        {{ const T cr = cf[{2 * sidx}], ci = cf[{2 * sidx + 1}];")
+        a(f"          mr {op} cr * Ar[{sidx}] - ci * Ai[{sidx}]; mi {op} cr * Ai[{sidx}] + ci * Ar[{sidx}]; }}")
+        mc_flops += 8
+    a(f"        me = (T){colour_count(n) * den} * (mr * mr + mi * mi);")
+    mc_flops += 4
     a("    }")
     A_seq[acc_decl] = A[acc_decl]
     A_seq.extend(A[tail_start:])
     amp = ("\n".join(A), "\n".join(A_seq))
-    return "\n".join(tables), stages, amp, flops_stage, (hel_flops + full_flops, hel_flops + lc_flops)
+    return "\n".join(tables), stages, amp, flops_stage, (hel_flops + full_flops, hel_flops + lc_flops,
+                                                          hel_flops + mc_flops)
 
 
 def generate_coop(n):
     perms, K, den = colour_matrix(n)
     tl = CoopTable(n)
     co = CoopLayout(n)
-    tables, stages, amp, fst, (fhel, fhel_lc) = emit_coop(n, tl, co, K, den, perms)
+    tables, stages, amp, fst, (fhel, fhel_lc, fhel_mc) = emit_coop(n, tl, co, K, den, perms)
     fill = emit_coop_fill(n, tl, co)
     global _COOP_COUNT
-    _COOP_COUNT = {"stages": fst, "per_helicity": fhel, "per_helicity_lc": fhel_lc, "object_store": co.size,
-                   "table": tl.size, "momentum_only": tl.mom_flops()}
+    _COOP_COUNT = {"stages": fst, "per_helicity": fhel, "per_helicity_lc": fhel_lc, "per_helicity_mc": fhel_mc,
+                   "object_store": co.size, "table": tl.size, "momentum_only": tl.mom_flops()}
+    gm = gell_mann_half()
+    gm_re = ", ".join(repr(v.real) for m in gm for row in m for v in row)
+    gm_im = ", ".join(repr(v.imag) for m in gm for row in m for v in row)
+    perm_tab = ", ".join(str(g) for sg in perms for g in sg)
     return f"""
 // ---- cooperative evaluation (helicity-recycled objects in LDS) ----
 // Table: {tl.size} T per event; object store: {co.size} T per event.  Table
@@ -1084,16 +1124,19 @@ __device__ __forceinline__ void coop_stages_ng{n}(const T* __restrict__ tab, T* 
 // Colour-summed |M|^2 (g_s = 1) of helicity configuration `hel` from the
 // object store: meet-in-the-middle at the vertex that carries the second
 // gluon of each colour ordering, A = sum Xbar gamma.j(block) Y.  COL = 0:
-// full colour matrix; COL = 1: leading colour, {lc_numerator(n, den)}/{den} times the identity.
+// full colour matrix; COL = 1: leading colour, {lc_numerator(n, den)}/{den} times the identity;
+// COL = 2: one sampled colour assignment with factors cf (Monte Carlo over colours).
 template <typename T, int COL>
-__device__ __forceinline__ double coop_me2_ng{n}_ahead(const T* __restrict__ tab, const T* __restrict__ obj, int hel)
+__device__ __forceinline__ double coop_me2_ng{n}_ahead(const T* __restrict__ tab, const T* __restrict__ obj,
+                                                      const T* __restrict__ cf, int hel)
 {{
 {amp[0]}
     return (double)me / COLOUR_DEN_NG{n};
 }}
 
 template <typename T, int COL>
-__device__ __forceinline__ double coop_me2_ng{n}_inplace(const T* __restrict__ tab, const T* __restrict__ obj, int hel)
+__device__ __forceinline__ double coop_me2_ng{n}_inplace(const T* __restrict__ tab, const T* __restrict__ obj,
+                                                        const T* __restrict__ cf, int hel)
 {{
 {amp[1]}
     return (double)me / COLOUR_DEN_NG{n};
@@ -1102,12 +1145,64 @@ __device__ __forceinline__ double coop_me2_ng{n}_inplace(const T* __restrict__ t
 // The spinor reads go one group ahead where the registers allow it without
 // spilling or losing occupancy: FP64 with four final-state partons.
 template <typename T, int COL>
-__device__ __forceinline__ double coop_me2_ng{n}(const T* __restrict__ tab, const T* __restrict__ obj, int hel)
+__device__ __forceinline__ double coop_me2_ng{n}(const T* __restrict__ tab, const T* __restrict__ obj,
+                                                const T* __restrict__ cf, int hel)
 {{
     if constexpr (sizeof(T) == 8 && {n} == 4)
-        return coop_me2_ng{n}_ahead<T, COL>(tab, obj, hel);
+        return coop_me2_ng{n}_ahead<T, COL>(tab, obj, cf, hel);
     else
-        return coop_me2_ng{n}_inplace<T, COL>(tab, obj, hel);
+        return coop_me2_ng{n}_inplace<T, COL>(tab, obj, cf, hel);
+}}
+
+// Monte Carlo over colours: the colour assignment of event `event` -- Philox
+// block 0x80000001 of its counter, cfg = ((k >> 16) N_cfg) >> 37 with the
+// 53-bit integer k of the first word pair, N_cfg = {colour_count(n)} -- and, on lanes
+// 0 .. {len(perms) - 1}, the factor (T^(a_s1) .. T^(a_sn))_(i j) of ordering s into
+// cf[2 s], cf[2 s + 1].  Decoding: j = cfg mod 3, i = (cfg / 3) mod 3, gluon g's
+// adjoint index (cfg / 9 / 8^g) mod 8.
+static constexpr int64_t COLOUR_CFG_NG{n} = {colour_count(n)};
+static constexpr double GM_RE_NG{n}[72] = {{{gm_re}}};
+static constexpr double GM_IM_NG{n}[72] = {{{gm_im}}};
+static constexpr signed char PERM_NG{n}[{len(perms) * n}] = {{{perm_tab}}};
+template <typename T>
+__device__ __forceinline__ void colour_factors_ng{n}(uint64_t event, uint64_t seed, uint32_t iter,
+                                                    T* __restrict__ cf, int lane)
+{{
+    if (lane >= {len(perms)})
+        return;
+    uint32_t r[4];
+    philox4x32_10((uint32_t)event, (uint32_t)(event >> 32), iter, 0x80000001u, (uint32_t)seed,
+                  (uint32_t)(seed >> 32), r);
+    const uint64_t k = ((((uint64_t)r[0]) << 32) | (uint64_t)r[1]) >> 11;
+    const uint64_t cfg = ((k >> 16) * (uint64_t)COLOUR_CFG_NG{n}) >> 37;
+    const int cj = (int)(cfg % 3), ci = (int)((cfg / 3) % 3);
+    const uint64_t adj = cfg / 9;
+    double rr[3], ri[3];
+    for (int q = 0; q < 3; ++q) {{
+        rr[q] = q == ci ? 1.0 : 0.0;
+        ri[q] = 0.0;
+    }}
+    for (int step = 0; step < {n}; ++step) {{
+        const int g = PERM_NG{n}[lane * {n} + step];
+        const int a = (int)((adj >> (3 * g)) & 7u);
+        const double* tr = GM_RE_NG{n} + 9 * a;
+        const double* ti = GM_IM_NG{n} + 9 * a;
+        double nr[3], ni[3];
+        for (int q = 0; q < 3; ++q) {{
+            nr[q] = rr[0] * tr[q] - ri[0] * ti[q] + rr[1] * tr[3 + q] - ri[1] * ti[3 + q]
+                  + rr[2] * tr[6 + q] - ri[2] * ti[6 + q];
+            ni[q] = rr[0] * ti[q] + ri[0] * tr[q] + rr[1] * ti[3 + q] + ri[1] * tr[3 + q]
+                  + rr[2] * ti[6 + q] + ri[2] * tr[6 + q];
+        }}
+        for (int q = 0; q < 3; ++q) {{
+            rr[q] = nr[q];
+            ri[q] = ni[q];
+        }}
+    }}
+    const double cr = cj == 0 ? rr[0] : (cj == 1 ? rr[1] : rr[2]);
+    const double cim = cj == 0 ? ri[0] : (cj == 1 ? ri[1] : ri[2]);
+    cf[2 * lane] = (T)cr;
+    cf[2 * lane + 1] = (T)cim;
 }}
 """
 
@@ -1122,21 +1217,27 @@ def flop_count(n, colour="full"):
     evaluations (n = 2) or the shared object stages and the per-helicity
     meet-in-the-middle contractions (n >= 3).  colour = "leading" counts the
     leading-colour sum in place of the full colour matrix."""
-    assert colour in ("full", "leading")
+    assert colour in ("full", "leading", "sampled")
     generate(n)
     c = dict(_LAST_COUNT)
     lc = colour == "leading"
     if n >= 3:
         c["algorithm"] = "helicity-recycled objects"
         c["stages"] = _COOP_COUNT["stages"]
-        c["per_helicity"] = _COOP_COUNT["per_helicity_lc" if lc else "per_helicity"]
+        c["per_helicity"] = _COOP_COUNT[{"full": "per_helicity", "leading": "per_helicity_lc",
+                                         "sampled": "per_helicity_mc"}[colour]]
         c["object_store"] = _COOP_COUNT["object_store"]
         c["per_event"] = c["momentum_only"] + c["stages"] + c["n_hel"] * c["per_helicity"]
+        if colour == "sampled":
+            # the event's colour factors: n steps of a complex row times a 3 x 3 matrix per ordering
+            c["colour_factors"] = 36 * n * c["n_orderings"]
+            c["per_event"] += c["colour_factors"]
     else:
         c["algorithm"] = "independent helicities"
         c["stages"] = 0
         if lc:
             c["per_helicity"] = c["per_helicity_lc"]
+        assert colour != "sampled", "the Monte Carlo over colours runs for n >= 3 only"
         c["per_event"] = c["momentum_only"] + c["n_hel"] * c["per_helicity"]
     return c
 

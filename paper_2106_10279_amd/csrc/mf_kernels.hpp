@@ -331,9 +331,11 @@ struct Layout {
 // Colour-summed |M|^2 of helicity `h` for the event whose table is `tab`:
 // lanes of the event (h = 0 .. 2^(NG+2) - 1) build the object store first
 // (n_g >= 3).  `any_live` must be uniform over the wave.  COL = 0: full
-// colour matrix; COL = 1: leading-colour approximation (Sec. 3.3 names it).
+// colour matrix; COL = 1: leading-colour approximation; COL = 2: one sampled
+// colour assignment whose factors are cf (n_g >= 3; Sec. 3.3 names both).
 template <int NG, typename T, int COL = 0>
-__device__ __forceinline__ double event_me2(const TabT<NG, T>* tab, T* obj, int h, double mt, bool live, bool any_live)
+__device__ __forceinline__ double event_me2(const TabT<NG, T>* tab, T* obj, int h, double mt, bool live, bool any_live,
+                                            const T* cf = nullptr)
 {
     using L = Layout<NG>;
     if constexpr (L::kCoop) {
@@ -346,10 +348,11 @@ __device__ __forceinline__ double event_me2(const TabT<NG, T>* tab, T* obj, int 
         if (!live)
             return 0.0;
         if constexpr (NG == 3)
-            return coop_me2_ng3<T, COL>(tab, obj, h);
+            return coop_me2_ng3<T, COL>(tab, obj, cf, h);
         else
-            return coop_me2_ng4<T, COL>(tab, obj, h);
+            return coop_me2_ng4<T, COL>(tab, obj, cf, h);
     } else {
+        static_assert(COL != 2, "the Monte Carlo over colours runs for n_g >= 3 only");
         return live ? colour_summed_me2_ng2<T, COL>(tab, h, mt) : 0.0;
     }
 }
@@ -690,12 +693,16 @@ __global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(size
     __shared__ __align__(16) TabT<NG, T> s_tab[L::kEventsPerPass][L::kTable];
     __shared__ __align__(16) T s_obj[L::kEventsPerPass][L::kObj];
     __shared__ double s_mom[L::kEventsPerPass][L::kMom];
+    // colour factors of the sampled assignment (COL = 2), re and im per ordering
+    constexpr int kCf = COL == 2 ? 2 * (NG == 3 ? 6 : 24) : 2;
+    __shared__ __align__(16) T s_cf[L::kEventsPerPass][kCf];
     const int lane = threadIdx.x;
     const int h0 = lane % L::kHel;
     const int sub = lane / L::kHel;
     TabT<NG, T>* tab = s_tab[sub];
     T* obj = s_obj[sub];
     double* mom = s_mom[sub];
+    T* cf = s_cf[sub];
     const uint64_t n_groups = (S.count + L::kEventsPerPass - 1) / L::kEventsPerPass;
     // one lane claims a chunk with a vector atomic; the wave reads its value
     auto claim = [&]() -> uint64_t {
@@ -734,10 +741,17 @@ __global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(size
             if (h0 < L::kMom)
                 mom[h0] = mc;
             wave_sync();
-            if (live)
+            if (live) {
                 fill_table<NG, T>(mom, mom[L::kMom - 1], S.P.m_top, S.P.mw, tab, obj, h);
+                if constexpr (COL == 2) {
+                    if constexpr (NG == 3)
+                        colour_factors_ng3<T>(S.first + e, S.P.seed, S.P.iter, cf, h);
+                    else
+                        colour_factors_ng4<T>(S.first + e, S.P.seed, S.P.iter, cf, h);
+                }
+            }
             wave_sync();
-            double v = event_me2<NG, T, COL>(tab, obj, h, S.P.m_top, live, any_live);
+            double v = event_me2<NG, T, COL>(tab, obj, h, S.P.m_top, live, any_live, cf);
             v = group_sum(v, L::kHel);
             if (h == 0 && live)
                 S.me[e] = v;
