@@ -686,8 +686,108 @@ __global__ void __launch_bounds__(kBlock) kin_kernel(StageParams S)
 // momentum component).  Groups without a passing event are skipped whole.
 constexpr int kAmpChunk = 16;
 
-template <int NG, typename T, int COL = 0>
-__global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2))) amp_kernel(StageParams S)
+// t tbar g: the table fill (divisions, square roots, lane groups on different
+// paths) costs about as much per pass whether it serves one event or more,
+// and next to the short 32-helicity amplitudes of this process it is a large
+// share of the work.  A wave therefore fills the tables of four events at
+// once (16 lanes each), then builds the objects and evaluates the helicities
+// of two pairs of them in turn (32 helicity lanes per event).  The level-1
+// currents that the fill writes go to an extension of each event's table and
+// are copied into the pair's object store before its stages.  The chunks of
+// the work counter stay in units of pairs (kAmpChunk pairs = kAmpChunk / 2
+// quads), and the results do not depend on the grouping.
+template <typename T, int COL>
+__device__ __forceinline__ void amp_quads_ng3(const StageParams& S)
+{
+    using L = Layout<3>;
+    constexpr int kQ = 4;                    // events per fill pass
+    constexpr int kL1 = 4 * 2 * 3;           // level-1 currents of an event, in T
+    static_assert(kQ * L::kMom <= kWave && kQ * 16 == kWave && 2 * L::kHel == kWave, "quad layout");
+    static_assert(L::kTable % 4 == 0, "16-byte aligned table rows");
+    __shared__ __align__(16) T s_tab[kQ][L::kTable + kL1];
+    __shared__ __align__(16) T s_obj[2][L::kObj];
+    __shared__ double s_mom[kQ][L::kMom];
+    constexpr int kCf = COL == 2 ? 2 * 6 : 2;
+    __shared__ __align__(16) T s_cf[2][kCf];
+    const int lane = threadIdx.x;
+    const int h0 = lane % L::kHel, sub = lane / L::kHel;      // helicity phase: 2 events x 32 lanes
+    const int fq = lane / 16, fl0 = lane % 16;                // fill: 4 events x 16 lanes
+    const int mq = lane / L::kMom, mk = lane % L::kMom;       // momenta: 4 events x 13 values
+    const uint64_t n_quads = (S.count + kQ - 1) / kQ;
+    auto claim = [&]() -> uint64_t {
+        unsigned long long c = 0;
+        if (lane == 0)
+            c = atomicAdd(S.next_group, (unsigned long long)kAmpChunk);
+        return (uint64_t)__shfl(c, 0) / 2;   // pairs -> quads
+    };
+    auto load = [&](uint64_t qd, double& pref, double& mc) {
+        const uint64_t ef = qd * kQ + fq, em = qd * kQ + mq;
+        pref = 0.0;
+        mc = 0.0;
+        if (qd < n_quads) {
+            if (ef < S.count)
+                pref = S.pref[ef];
+            if (mq < kQ && em < S.count)
+                mc = S.mom[em * L::kMom + mk];
+        }
+    };
+    uint64_t cur = claim();
+    uint64_t nxt = claim();
+    double pref_next, mc_next;
+    load(cur, pref_next, mc_next);
+    int j = 0;
+    while (cur < n_quads) {
+        const uint64_t qd = cur + j;
+        const double pref = pref_next, mc = mc_next;
+        const bool last_in_chunk = j + 1 == kAmpChunk / 2 || qd + 1 >= n_quads;
+        load(last_in_chunk ? nxt : qd + 1, pref_next, mc_next);
+        int h = h0, fl = fl0;
+        asm volatile("" : "+v"(h), "+v"(fl));
+        const bool live_f = qd * kQ + fq < S.count && pref != 0.0;
+        if (__any(live_f)) {
+            if (mq < kQ)
+                s_mom[mq][mk] = mc;
+            wave_sync();
+            if (live_f)
+                fill_table_coop_ng3<T>(s_mom[fq], s_mom[fq][L::kMom - 1], S.P.m_top, S.P.mw, s_tab[fq],
+                                       s_tab[fq] + L::kTable, fl);
+            wave_sync();
+            for (int pr = 0; pr < 2; ++pr) {
+                const int k = 2 * pr + sub;
+                const uint64_t e = qd * kQ + k;
+                const double pe = __shfl(pref, 16 * k);
+                const bool live = e < S.count && pe != 0.0;
+                const bool any_live = __any(live);
+                if (!any_live)
+                    continue;
+                const T* tab = s_tab[k];
+                T* obj = s_obj[sub];
+                if (live && h < kL1)
+                    obj[h] = tab[L::kTable + h];
+                if constexpr (COL == 2) {
+                    if (live)
+                        colour_factors_ng3<T>(S.first + e, S.P.seed, S.P.iter, s_cf[sub], h);
+                }
+                wave_sync();
+                double v = event_me2<3, T, COL>(tab, obj, h, S.P.m_top, live, any_live, s_cf[sub]);
+                v = group_sum(v, L::kHel);
+                if (h == 0 && live)
+                    S.me[e] = v;
+                wave_sync();
+            }
+        }
+        if (last_in_chunk) {
+            cur = nxt;
+            nxt = claim();
+            j = 0;
+        } else {
+            ++j;
+        }
+    }
+}
+
+template <int NG, typename T, int COL>
+__device__ __forceinline__ void amp_groups(const StageParams& S)
 {
     using L = Layout<NG>;
     __shared__ __align__(16) TabT<NG, T> s_tab[L::kEventsPerPass][L::kTable];
@@ -765,6 +865,16 @@ __global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(size
             ++j;
         }
     }
+}
+
+// The amplitude kernel: quads of events for t tbar g, single events for t tbar g g.
+template <int NG, typename T, int COL = 0>
+__global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 || NG == 3 ? 4 : 2))) amp_kernel(StageParams S)
+{
+    if constexpr (NG == 3)
+        amp_quads_ng3<T, COL>(S);
+    else
+        amp_groups<NG, T, COL>(S);
 }
 
 // Phase 3 over a batch: weights, compensated sums, w_max, counts and the
