@@ -32,8 +32,10 @@ PEAK_FP64_TFLOPS = 78.6      # MI355X vector FP64 (256 CUs x 2.4 GHz x 128 flop/
 PEAK_FP32_TFLOPS = 157.3     # MI355X vector FP32 (packed)
 
 # Per-event flops outside |M|^2 (Philox is integer work): VEGAS map 5 D,
-# kinematics, phase space with massive rescaling, cuts, two PDF evaluations,
-# weight and accumulation.  Counted from the kernel source, see the design doc.
+# kinematics, phase space with massive rescaling (about 40 per particle, plus
+# 10 per particle per Newton step), cuts (about 50), two PDF evaluations
+# (about 170 each), weight and accumulation (about 25); estimated from the
+# kernel source.
 OTHER_FLOPS = {2: 420, 3: 720, 4: 1030}
 
 WORKLOADS = {

@@ -70,7 +70,7 @@ class MFError(RuntimeError):
 
 def load():
     if not os.path.exists(LIB_PATH):
-        raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_2106_10279_amd/build.py "
                           "(hipcc, gfx950); there is no CPU fallback")
     L = C.CDLL(LIB_PATH)
     L.mf_default_options.argtypes = [C.POINTER(mf_options)]
