@@ -583,6 +583,127 @@ double mfo_me2_sum_colour_config(int n_g, const double *p, double m, double widt
     return (double)mfo_colour_count(n_g) * total;
 }
 
+/* Colour flows: gluon g carries a colour a_g and an anticolour b_g, state
+ * G_ab = (e_ab - delta_ab 1/N) / sqrt 2 with (e_ab)_{rs} = delta_ra delta_sb.
+ * Summed over the 9 pairs, G_ab (x) conj(G_ab) equals sum_a T^a (x) conj(T^a),
+ * so flows replace adjoint indices without changing the colour sum.  The
+ * flows are enumerated by code = j + 3 i + 9 sum_g 9^g (3 a_g + b_g); a flow
+ * whose factors vanish for every ordering contributes nothing and is dropped,
+ * the rest are numbered in increasing code.                                */
+static int64_t *flow_codes[MFO_MAX_G + 1];
+static int64_t flow_n[MFO_MAX_G + 1];
+static pthread_once_t flow_once = PTHREAD_ONCE_INIT;
+
+static void flow_matrix(int a, int b, double G[3][3])
+{
+    for (int r = 0; r < 3; ++r)
+        for (int s = 0; s < 3; ++s)
+            G[r][s] = ((r == a && s == b ? 1.0 : 0.0) - (a == b && r == s ? 1.0 / 3.0 : 0.0)) / sqrt(2.0);
+}
+
+/* c[sigma] = (G_{sigma1} ... G_{sigman})_{ij} for the flow with this code. */
+static void flow_factors_of_code(int n_g, int64_t code, const int *perm, int nperm, double *c)
+{
+    int jj = (int)(code % 3), ii = (int)((code / 3) % 3);
+    double G[MFO_MAX_G][3][3];
+    int64_t rest = code / 9;
+    for (int g = 0; g < n_g; ++g) {
+        int pr = (int)(rest % 9);
+        rest /= 9;
+        flow_matrix(pr / 3, pr % 3, G[g]);
+    }
+    for (int s = 0; s < nperm; ++s) {
+        double P[3][3] = { { 1, 0, 0 }, { 0, 1, 0 }, { 0, 0, 1 } };
+        for (int k = 0; k < n_g; ++k) {
+            double (*Gk)[3] = G[perm[s * n_g + k]];
+            double Q[3][3];
+            for (int r = 0; r < 3; ++r)
+                for (int q = 0; q < 3; ++q)
+                    Q[r][q] = P[r][0] * Gk[0][q] + P[r][1] * Gk[1][q] + P[r][2] * Gk[2][q];
+            memcpy(P, Q, sizeof(Q));
+        }
+        c[s] = P[ii][jj];
+    }
+}
+
+static void flow_init(void)
+{
+    for (int n_g = 2; n_g <= MFO_MAX_G; ++n_g) {
+        int64_t total = 9;
+        for (int g = 0; g < n_g; ++g)
+            total *= 9;
+        int nperm = mfo_n_orderings(n_g);
+        int perm[120 * MFO_MAX_G];
+        mfo_orderings(n_g, perm);
+        flow_codes[n_g] = malloc(sizeof(int64_t) * (size_t)total);
+        int64_t k = 0;
+        for (int64_t code = 0; code < total; ++code) {
+            double c[120];
+            flow_factors_of_code(n_g, code, perm, nperm, c);
+            int any = 0;
+            for (int s = 0; s < nperm; ++s)
+                any |= c[s] != 0.0;
+            if (any)
+                flow_codes[n_g][k++] = code;
+        }
+        flow_n[n_g] = k;
+    }
+}
+
+int64_t mfo_flow_count(int n_g)
+{
+    if (n_g < 2 || n_g > MFO_MAX_G)
+        return -1;
+    pthread_once(&flow_once, flow_init);
+    return flow_n[n_g];
+}
+
+int64_t mfo_flow_code(int n_g, int64_t idx)
+{
+    int64_t n = mfo_flow_count(n_g);
+    if (n < 0 || idx < 0 || idx >= n)
+        return -1;
+    return flow_codes[n_g][idx];
+}
+
+int64_t mfo_flow_config(int n_g, uint64_t seed, uint32_t iter, uint64_t event)
+{
+    uint32_t ctr[4] = { (uint32_t)event, (uint32_t)(event >> 32), iter, 0x80000001u };
+    uint32_t key[2] = { (uint32_t)seed, (uint32_t)(seed >> 32) };
+    uint32_t r[4];
+    mfo_philox4x32_10(ctr, key, r);
+    uint64_t k = ((((uint64_t)r[0]) << 32) | (uint64_t)r[1]) >> 11;
+    return (int64_t)(((k >> 16) * (uint64_t)mfo_flow_count(n_g)) >> 37);
+}
+
+void mfo_flow_factors(int n_g, int64_t idx, double *c)
+{
+    int nperm = mfo_n_orderings(n_g);
+    int perm[120 * MFO_MAX_G];
+    mfo_orderings(n_g, perm);
+    flow_factors_of_code(n_g, mfo_flow_code(n_g, idx), perm, nperm, c);
+}
+
+double mfo_me2_sum_colour_flow(int n_g, const double *p, double m, double width, int64_t idx)
+{
+    int nperm = mfo_n_orderings(n_g);
+    double c[120];
+    mfo_flow_factors(n_g, idx, c);
+    int nh = 1 << (n_g + 2);
+    double total = 0.0;
+    for (int h = 0; h < nh; ++h) {
+        int hel[MFO_MAX_G + 2];
+        hel_from_index(n_g, h, hel);
+        cplx A[120];
+        partial_amplitudes_core(n_g, p, m, width, hel, -1, A);
+        cplx M = 0;
+        for (int s = 0; s < nperm; ++s)
+            M += c[s] * A[s];
+        total += creal(M) * creal(M) + cimag(M) * cimag(M);
+    }
+    return (double)mfo_flow_count(n_g) * total;
+}
+
 double mfo_me2_sum(int n_g, const double *p, double m, double width)
 {
     int nh = 1 << (n_g + 2);

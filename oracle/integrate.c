@@ -140,7 +140,9 @@ static double weight_from_x(const mfo_process *proc, double sqrt_s,
 
     double gs2 = 4.0 * PI * proc->alpha_s;
     double sum;
-    if (proc->colour == 2)
+    if (proc->colour == 3)
+        sum = ev->colour_cfg >= 0 ? mfo_me2_sum_colour_flow(n_g, p, m, proc->w_top, ev->colour_cfg) : NAN;
+    else if (proc->colour == 2)
         sum = ev->colour_cfg >= 0 ? mfo_me2_sum_colour_config(n_g, p, m, proc->w_top, ev->colour_cfg) : NAN;
     else if (proc->colour == 1)
         sum = mfo_me2_sum_lc(n_g, p, m, proc->w_top);
@@ -167,7 +169,8 @@ double mfo_event_weight(const mfo_process *proc, double sqrt_s,
         mfo_bin_from_k53(k53[d], n_bins, &ev->bin[d], &delta[d]);
     }
     double jac = mfo_vegas_map(D, n_bins, grid, ev->bin, delta, ev->x);
-    ev->colour_cfg = proc->colour == 2 ? mfo_colour_config(proc->n_g, seed, (uint32_t)iter, event) : -1;
+    ev->colour_cfg = proc->colour == 2 ? mfo_colour_config(proc->n_g, seed, (uint32_t)iter, event)
+                   : proc->colour == 3 ? mfo_flow_config(proc->n_g, seed, (uint32_t)iter, event) : -1;
     return weight_from_x(proc, sqrt_s, pdf, jac, ev);
 }
 

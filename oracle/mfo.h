@@ -45,7 +45,8 @@ typedef struct {
     double etamax_g;           /* gluon |eta| cut; <= 0 disables               */
     double drmin_gg;           /* Delta R between final gluons; <= 0 disables  */
     int    colour;             /* 0: full colour sum; 1: leading colour;
-                                  2: colour Monte Carlo (one sampled assignment) */
+                                  2: colour Monte Carlo (one sampled assignment);
+                                  3: Monte Carlo over colour flows          */
 } mfo_process;
 
 typedef struct {
@@ -71,7 +72,7 @@ typedef struct {
     int    newton_fail;
     int    near_edge;          /* a cut variable lies within 1e-9 of its cut   */
     int    ill_conditioned;    /* |d ln(x g) / d ln x| > 1e3 at x1 or x2      */
-    int64_t colour_cfg;        /* colour = 2: the event's colour assignment    */
+    int64_t colour_cfg;        /* colour = 2, 3: the event's assignment, flow   */
 } mfo_event;
 
 typedef struct {
@@ -145,6 +146,26 @@ int64_t mfo_colour_count(int n_g);
 void mfo_colour_factors(int n_g, int64_t cfg, double *c);
 /* N_cfg * sum_h |M(cfg)|^2, g_s = 1.                                        */
 double mfo_me2_sum_colour_config(int n_g, const double *p, double m, double width, int64_t cfg);
+/* Monte Carlo over colour flows (colour = 3): gluon g carries a colour a_g
+ * and an anticolour b_g ('t Hooft double line; Maltoni, Paul, Stelzer and
+ * Willenbrock, Phys. Rev. D67 (2003) 014026), state matrix
+ * G_ab = (e_ab - delta_ab 1/N) / sqrt 2, whose 9 pairs resolve
+ * sum_a T^a (x) conj(T^a).  Flows are coded as
+ * code = j + 3 i + 9 sum_g 9^g (3 a_g + b_g); those whose factors vanish
+ * for every ordering are dropped and the remaining N_flow are numbered in
+ * increasing code.  An event draws its flow index from Philox block
+ * 0x80000001 as the adjoint sampling does, with N_flow in place of N_cfg;
+ * M = sum_sigma (G_{sigma1} .. G_{sigman})_{ij} A(sigma), and N_flow |M|^2
+ * summed over helicities estimates the colour sum without bias.  n_g = 2..4;
+ * mfo_flow_count returns -1 otherwise, mfo_flow_code -1 for an index out
+ * of range.                                                                */
+int64_t mfo_flow_count(int n_g);
+int64_t mfo_flow_code(int n_g, int64_t idx);
+int64_t mfo_flow_config(int n_g, uint64_t seed, uint32_t iter, uint64_t event);
+/* c: [n_g!] real colour factors of the orderings for flow index idx.       */
+void mfo_flow_factors(int n_g, int64_t idx, double *c);
+/* N_flow * sum_h |M(flow idx)|^2, g_s = 1.                                  */
+double mfo_me2_sum_colour_flow(int n_g, const double *p, double m, double width, int64_t idx);
 
 /* ---- per-event weight and integration ---------------------------------- */
 int mfo_n_dims(int n_g);

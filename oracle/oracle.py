@@ -101,6 +101,15 @@ def lib():
         L.mfo_colour_factors.argtypes = [C.c_int, C.c_int64, _dp]
         L.mfo_me2_sum_colour_config.argtypes = [C.c_int, _dp, C.c_double, C.c_double, C.c_int64]
         L.mfo_me2_sum_colour_config.restype = C.c_double
+        L.mfo_flow_count.argtypes = [C.c_int]
+        L.mfo_flow_count.restype = C.c_int64
+        L.mfo_flow_code.argtypes = [C.c_int, C.c_int64]
+        L.mfo_flow_code.restype = C.c_int64
+        L.mfo_flow_config.argtypes = [C.c_int, C.c_uint64, C.c_uint32, C.c_uint64]
+        L.mfo_flow_config.restype = C.c_int64
+        L.mfo_flow_factors.argtypes = [C.c_int, C.c_int64, _dp]
+        L.mfo_me2_sum_colour_flow.argtypes = [C.c_int, _dp, C.c_double, C.c_double, C.c_int64]
+        L.mfo_me2_sum_colour_flow.restype = C.c_double
         L.mfo_me2_sum_fullcolour.argtypes = [C.c_int, _dp, C.c_double, C.c_double, C.c_int, _ip]
         L.mfo_me2_sum_fullcolour.restype = C.c_double
         L.mfo_n_dims.argtypes = [C.c_int]
@@ -156,10 +165,11 @@ class Process:
     ptmin_g: float = 0.0
     etamax_g: float = 0.0
     drmin_gg: float = 0.0
-    colour: str = "full"        # "full", "leading" (leading colour) or "sampled" (colour Monte Carlo)
+    colour: str = "full"        # "full", "leading" (leading colour), "sampled" (colour Monte Carlo
+                                # over adjoint indices) or "flow" (Monte Carlo over colour flows)
 
     def c(self):
-        modes = {"full": 0, "leading": 1, "sampled": 2}
+        modes = {"full": 0, "leading": 1, "sampled": 2, "flow": 3}
         if self.colour not in modes:
             raise ValueError(f"colour must be one of {sorted(modes)}, not {self.colour!r}")
         return _Process(self.n_g, self.m_top, self.w_top, self.alpha_s, self.mu_f,
@@ -329,6 +339,34 @@ def me2_sum_colour_config(n_g, p, m, width, cfg):
     """N_cfg times the helicity sum of |M|^2 for colour assignment cfg, g_s = 1."""
     p = _f64(p)
     return lib().mfo_me2_sum_colour_config(n_g, _d(p), m, width, cfg)
+
+
+def flow_count(n_g):
+    """Number of colour flows with a non-vanishing factor for some ordering."""
+    return lib().mfo_flow_count(n_g)
+
+
+def flow_code(n_g, idx):
+    """code = j + 3 i + 9 sum_g 9^g (3 a_g + b_g) of flow idx (-1 out of range)."""
+    return lib().mfo_flow_code(n_g, idx)
+
+
+def flow_config(n_g, seed, it, event):
+    """The colour-flow index of an event (Philox block 0x80000001)."""
+    return lib().mfo_flow_config(n_g, seed, it, event)
+
+
+def flow_factors(n_g, idx):
+    """(G_{sigma1} ... G_{sigman})_{ij} for every ordering, flow idx (real)."""
+    out = np.zeros(lib().mfo_n_orderings(n_g))
+    lib().mfo_flow_factors(n_g, idx, _d(out))
+    return out
+
+
+def me2_sum_colour_flow(n_g, p, m, width, idx):
+    """N_flow times the helicity sum of |M|^2 for colour flow idx, g_s = 1."""
+    p = _f64(p)
+    return lib().mfo_me2_sum_colour_flow(n_g, _d(p), m, width, idx)
 
 
 def all_helicities(n_g):

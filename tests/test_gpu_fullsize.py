@@ -164,3 +164,56 @@ def test_ttxgg_1e7_unweighting_sampled_events_and_properties(api, oracle_lib, pd
           f"records max |dp|/E_beam {worst:.1e}; {int(clear.sum())} rejected events confirmed")
     assert (~border).sum() > 0.9 * len(sel) and clear.sum() > 2500
     assert worst < 1e-12
+
+
+def test_ttxg_1e7x10_five_seeds(api, oracle_lib, pdf_table):
+    """g g -> t tbar g at its full size (1e7 events x 10 iterations, seeds
+    0 .. 4): the five combined estimates agree within their errors, and 1e4
+    sampled events of the last iteration of seed 4 match the oracle on the grid
+    that iteration ran on."""
+    cuts = dict(ptmin_g=20.0, etamax_g=2.5)
+    proc = api.Process("gg_ttxg", **cuts)
+    N = 10_000_000
+    res = [api.integrate(proc, SQRT_S, pdf_table, N, 10, seed, keep_weights=(seed == 4)) for seed in range(5)]
+    s = np.array([r.sigma for r in res])
+    e = np.array([r.sigma_err for r in res])
+    mean = float(np.sum(s / e**2) / np.sum(1 / e**2))
+    chi2 = float(np.sum((s - mean) ** 2 / e**2))
+    print(f"\n  ttg 1e7 x 10: sigma per seed {np.round(s, 3)} +- {np.round(e, 3)} pb; chi2 {chi2:.2f} / 4; "
+          f"chi2/dof per run {[round(r.chi2_dof, 2) for r in res]}")
+    assert chi2 < 20.0
+    r = res[4]
+    rng = np.random.default_rng(71)
+    ids = np.sort(rng.choice(N, size=10_000, replace=False))
+    op = oracle_lib.Process(n_g=3, **cuts)
+    w_o, flags = oracle_lib.event_weights(op, SQRT_S, pdf_table, r.grid_last, 4, 9, ids)
+    wg = r.weights[ids].cpu().numpy()
+    skip = (flags & (8 | 16)) != 0
+    zero = (w_o == 0.0) & ~skip
+    assert np.all(wg[zero] == 0.0)
+    use = ~skip & ~zero
+    rel = np.abs(wg[use] / w_o[use] - 1.0)
+    print(f"  seed 4, iteration 9: {int(use.sum())} of 10000 sampled events, max rel {rel.max():.2e}")
+    assert use.sum() > 6000
+    assert rel.max() < 1e-12
+
+
+def test_ttx_gradient_1e7x10_against_quadrature(api, pdf_table):
+    """The differentiation workload at its full size (g g -> t tbar, 1e7 events
+    x 10 iterations, m_t = 170, 173, 176 GeV), at zero width: sigma and
+    d sigma / d m_t against the 2-D quadrature of the closed form with the
+    analytic synthetic gluon (the grid interpolant differs from it by a few
+    1e-4), and d sigma / d alpha_s = 2 sigma / alpha_s."""
+    from test_oracle_integrate import sigma_quadrature
+    N = 10_000_000
+    for m in (170.0, 173.0, 176.0):
+        proc = api.Process("gg_ttx", m_top=m, w_top=0.0)
+        rg, g = api.integrate_grad(proc, SQRT_S, pdf_table, N, 10, 0)
+        q = sigma_quadrature(m)
+        dq = (sigma_quadrature(m + 0.1) - sigma_quadrature(m - 0.1)) / 0.2
+        spread = np.std(g.iter_dmt[1:], ddof=1) / np.sqrt(len(g.iter_dmt) - 1)
+        print(f"\n  m_t = {m}: sigma {rg.sigma:.4f} +- {rg.sigma_err:.4f} (quadrature {q:.4f}); "
+              f"d sigma/d m_t {g.dsigma_dmt:.4f} (spread {spread:.4f}; quadrature {dq:.4f}) pb/GeV")
+        assert abs(rg.sigma - q) < 5 * rg.sigma_err + 5e-4 * q
+        assert abs(g.dsigma_dmt - dq) < 5 * spread + 2e-3 * abs(dq)
+        assert g.dsigma_dalphas == pytest.approx(2.0 * rg.sigma / 0.118, rel=1e-12)

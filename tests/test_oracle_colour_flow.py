@@ -1,0 +1,148 @@
+"""Pins for the oracle's Monte Carlo over colour flows (colour = "flow").
+
+Sec. 3.3 names a Monte Carlo over colours as a remedy for high-multiplicity
+matrix elements.  Besides adjoint indices, the colour of a gluon can be
+sampled as a colour-anticolour pair (a, b) with state matrix
+G_ab = (e_ab - delta_ab / N) / sqrt 2 (the 't Hooft double line with the
+U(1) part projected out), whose nine pairs resolve
+sum_a T^a (x) conj(T^a) exactly.  Flows whose factors vanish for every
+ordering carry no weight and are dropped; drawing uniformly among the rest
+gives an unbiased estimate of the colour sum with a smaller variance than
+adjoint sampling, because each surviving flow selects few orderings.
+"""
+import itertools
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from test_oracle_me import M, random_momenta
+
+
+def all_flow_factors(n_g):
+    return np.array([O.flow_factors(n_g, k) for k in range(O.flow_count(n_g))])
+
+
+def walk_factor(order, pairs, i, j):
+    """(G_{order1} ... G_{ordern})_{ij} by following the colour line: an
+    off-diagonal pair (a, b) moves colour a to b (factor 1/sqrt 2), a
+    diagonal pair (a, a) keeps the colour with factor ([r == a] - 1/3)/sqrt 2.
+    A second algorithm, independent of the oracle's matrix products."""
+    r, v = i, 1.0
+    for g in order:
+        a, b = pairs[g]
+        if a != b:
+            if r != a:
+                return 0.0
+            r = b
+            v /= math.sqrt(2.0)
+        else:
+            v *= ((1.0 if r == a else 0.0) - 1.0 / 3.0) / math.sqrt(2.0)
+    return v if r == j else 0.0
+
+
+@pytest.mark.parametrize("n_g", [2, 3, 4])
+def test_kept_flows_are_exactly_those_with_a_nonzero_factor(n_g):
+    """Enumerate every code by the colour-line walk: the oracle's list is the
+    set of codes with some non-vanishing factor, in increasing order, and its
+    factors agree with the walk."""
+    orders = [tuple(s) for s in O.orderings(n_g)]
+    kept = []
+    for code in range(9 * 9 ** n_g):
+        j, i, rest = code % 3, (code // 3) % 3, code // 9
+        pairs = [divmod((rest // 9 ** g) % 9, 3) for g in range(n_g)]
+        f = [walk_factor(s, pairs, i, j) for s in orders]
+        if any(x != 0.0 for x in f):
+            kept.append((code, f))
+    assert O.flow_count(n_g) == len(kept)
+    assert [O.flow_code(n_g, k) for k in range(len(kept))] == [c for c, _ in kept]
+    assert O.flow_code(n_g, len(kept)) == -1 and O.flow_code(n_g, -1) == -1
+    for k in range(0, len(kept), max(1, len(kept) // 50)):
+        assert np.allclose(O.flow_factors(n_g, k), kept[k][1], rtol=1e-14, atol=0)
+
+
+def test_flow_counts_and_factors_by_hand():
+    assert [O.flow_count(n) for n in (2, 3, 4)] == [87, 585, 4311]
+    assert O.flow_count(1) == -1 and O.flow_count(5) == -1
+    # code 0: every pair (0, 0), i = j = 0: (2/3)^n / 2^(n/2) for each ordering
+    for n in (2, 3, 4):
+        assert np.allclose(O.flow_factors(n, 0), (2 / 3) ** n / 2 ** (n / 2), rtol=1e-15, atol=0)
+    # i = 0, gluon 0 = (0 -> 1), gluon 1 = (1 -> 2), j = 2: only the ordering (0, 1) connects
+    code = 2 + 3 * 0 + 9 * ((3 * 0 + 1) + 9 * (3 * 1 + 2))
+    k = [O.flow_code(2, q) for q in range(O.flow_count(2))].index(code)
+    assert [tuple(s) for s in O.orderings(2)] == [(0, 1), (1, 0)]
+    assert np.allclose(O.flow_factors(2, k), [0.5, 0.0], rtol=1e-15, atol=0)
+
+
+@pytest.mark.parametrize("n_g", [2, 3, 4])
+def test_flow_factors_rebuild_the_colour_matrix(n_g):
+    """sum over kept flows of c_s c_t = C_st (the dropped flows add zero)."""
+    F = all_flow_factors(n_g)
+    assert np.allclose(F.T @ F, O.colour_matrix(n_g), rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("n_g", [2, 3, 4])
+def test_flow_estimator_unbiased_and_tighter_than_adjoint_sampling(n_g):
+    """At a random point: the sum over flows of |M|^2 is the colour sum, the
+    oracle's per-flow function agrees with the same products, and the exact
+    variance per event of the flow estimate is below that of adjoint sampling."""
+    rng = np.random.default_rng(800 + n_g)
+    p = random_momenta(n_g, 1300.0, rng)
+    A = np.array([O.partial_amplitudes(n_g, p, M, 1.5, h) for h in O.all_helicities(n_g)])
+    exact = O.me2_sum(n_g, p, M, 1.5)
+    F = all_flow_factors(n_g)
+    per_flow = np.sum(np.abs(F @ A.T) ** 2, axis=1)
+    assert per_flow.sum() == pytest.approx(exact, rel=1e-12)
+    n = len(F)
+    for k in (0, 7, n // 2, n - 1):
+        assert O.me2_sum_colour_flow(n_g, p, M, 1.5, k) == pytest.approx(n * per_flow[k], rel=1e-12, abs=1e-300)
+    relvar_flow = n * np.sum(per_flow ** 2) / exact ** 2 - 1
+    Fa = np.array([O.colour_factors(n_g, c) for c in range(O.colour_count(n_g))])
+    per_adj = np.sum(np.abs(Fa @ A.T) ** 2, axis=1)
+    relvar_adj = len(Fa) * np.sum(per_adj ** 2) / exact ** 2 - 1
+    print(f"\n  n_g = {n_g}: relative variance per event, flows {relvar_flow:.3g}, adjoint indices {relvar_adj:.3g}")
+    assert relvar_flow < relvar_adj
+
+
+def test_flow_draw_is_philox_block_0x80000001(torch_philox):
+    cases = [(0, 0, 0), (0, 9, 4), (3, 123456789, 0), (2**40 + 1, 2**33 + 5, 7)]
+    triples = [(seed, e, it | (0x80000001 << 32)) for seed, e, it in cases]
+    for n_g in (3, 4):
+        for (seed, e, it), r in zip(cases, torch_philox(triples)):
+            k = ((r[0] << 32) | r[1]) >> 11
+            assert O.flow_config(n_g, seed, it, e) == ((k >> 16) * O.flow_count(n_g)) >> 37
+
+
+def test_flow_draws_uniform():
+    n_g, n = 3, 30000
+    N = O.flow_count(n_g)
+    idx = np.array([O.flow_config(n_g, 1, 2, e) for e in range(n)])
+    assert idx.min() >= 0 and idx.max() < N
+    counts = np.bincount(idx, minlength=N)
+    chi2 = float(np.sum((counts - n / N) ** 2 / (n / N)))
+    assert abs(chi2 - (N - 1)) < 6 * math.sqrt(2 * (N - 1))
+
+
+def test_flow_event_weight_uses_the_events_flow(pdf_table):
+    grid = np.tile(np.arange(51) / 50, (10, 1))
+    full = O.Process(n_g=4, ptmin_g=20.0, drmin_gg=0.4)
+    flow = O.Process(n_g=4, ptmin_g=20.0, drmin_gg=0.4, colour="flow")
+    checked = 0
+    for e in range(30):
+        wf, ev = O.event_weight(full, 13000.0, pdf_table, grid, 0, 0, e)
+        ws, evs = O.event_weight(flow, 13000.0, pdf_table, grid, 0, 0, e)
+        if wf == 0.0:
+            assert ws == 0.0
+            continue
+        k = np.asarray(ev.k)
+        e_b = math.sqrt(ev.shat) / 2
+        p = np.array([k[0], k[1], [-e_b, 0, 0, -e_b], [-e_b, 0, 0, e_b], k[2], k[3]])
+        idx = O.flow_config(4, 0, 0, e)
+        ratio = O.me2_sum_colour_flow(4, p, M, 1.5, idx) / O.me2_sum(4, p, M, 1.5)
+        assert ws == pytest.approx(wf * ratio, rel=1e-12, abs=1e-300)
+        checked += 1
+    assert checked > 15
+    y = np.full(10, 0.37)
+    w, _ = O.event_weight_y(flow, 13000.0, pdf_table, grid, y)
+    assert math.isnan(w)
