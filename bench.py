@@ -356,31 +356,36 @@ def main():
         }
         log(f"[bench] leading colour done: {vlc:.4g} events/s, sigma / sigma_full = "
             f"{rlc.sigma / r64.sigma:.4f}")
-    if not args.no_colour_mc and wl["n_g"] >= 3:
-        log(f"[bench] Monte Carlo over colours, fp64: {args.warmup} warm-up + {args.steps} timed "
-            f"iterations x {n_events} events")
+    legs = (("sampled", "colour_mc", "one colour assignment (adjoint indices) per event"),
+            ("flow", "colour_flow", "one colour flow per event, drawn among the flows with a "
+                                    "non-vanishing factor"))
+    for mode, key, what in legs if not args.no_colour_mc and wl["n_g"] >= 3 else ():
+        log(f"[bench] Monte Carlo over colours ({mode}), fp64: {args.warmup} warm-up + {args.steps} "
+            f"timed iterations x {n_events} events")
         rmc, wallmc, _ = timed_run(api, torch, proc, pdf, n_events, args.steps, args.warmup, "fp64",
-                                   args.seed, colour="sampled")
+                                   args.seed, colour=mode)
         vmc = args.steps * n_events / wallmc
-        f_mc = me_flops(wl["n_g"], "sampled")
+        f_mc = me_flops(wl["n_g"], mode)
         # the price of the sampling: per-event weight variance against the full colour
         # sum, on the same events and the same (final) grid of the fp64 line
         ws = api.integrate(proc, 13000.0, pdf, n_events, 1, args.seed, grid_in=r64.grid,
-                           start_iter=args.warmup + args.steps, colour="sampled").weights
+                           start_iter=args.warmup + args.steps, colour=mode).weights
         wf = api.integrate(proc, 13000.0, pdf, n_events, 1, args.seed, grid_in=r64.grid,
                            start_iter=args.warmup + args.steps).weights
         var_ratio = float(ws.var().item()) / float(wf.var().item())
         del ws, wf
-        out["colour_mc"] = {
+        out[key] = {
             "value": round(vmc, 2), "unit": "events/s", "events_per_step": n_events,
             "steps": args.steps, "ms_per_step": round(wallmc / args.steps * 1e3, 3),
             "roofline": roofline(wl["n_g"], f_mc, f_other, n_events, rmc, PEAK_FP64_TFLOPS),
             "sigma": rmc.sigma, "sigma_err": rmc.sigma_err,
             "weight_variance_vs_full_colour": round(var_ratio, 3),
-            "note": "one colour assignment per event (Philox block 0x80000001), unbiased; the "
-                    "variance ratio is the factor on events needed for the full-colour error",
+            "full_colour_equivalent_events_per_s": round(vmc / var_ratio, 2),
+            "note": what + " (Philox block 0x80000001), unbiased; the variance ratio is the factor "
+                    "on events needed for the full-colour error",
         }
-        log(f"[bench] colour Monte Carlo done: {vmc:.4g} events/s, weight variance x{var_ratio:.1f}")
+        log(f"[bench] colour Monte Carlo ({mode}) done: {vmc:.4g} events/s, weight variance "
+            f"x{var_ratio:.2f}")
     if not args.no_adjoint:
         log(f"[bench] adjoint: gg_ttx forward + gradient, {args.adjoint_events} events x 3 iterations")
         out["adjoint"] = adjoint_run(api, torch, pdf, args.adjoint_events, 3, args.seed)

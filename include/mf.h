@@ -64,7 +64,20 @@ typedef enum { MF_FP64 = 0, MF_FP32_KAHAN = 1 } mf_precision;
  * A(sigma)|^2 summed over helicities: an unbiased estimate of the colour sum
  * with a larger variance.  mf_integrate only, for MF_GG_TTXG and MF_GG_TTXGG;
  * other calls return MF_EUNSUPPORTED. */
-typedef enum { MF_COLOUR_FULL = 0, MF_COLOUR_LEADING = 1, MF_COLOUR_SAMPLED = 2 } mf_colour;
+/* MF_COLOUR_FLOW samples colour flows instead: gluon g carries a colour a_g
+ * and an anticolour b_g with state (e_ab - delta_ab / 3) / sqrt 2, whose 9
+ * pairs resolve sum_a T^a (x) conj(T^a) ('t Hooft double line with the U(1)
+ * part removed; Maltoni, Paul, Stelzer and Willenbrock, Phys. Rev. D67 (2003)
+ * 014026).  Flows are ordered by code = j + 3 i + 9 sum_g 9^g (3 a_g + b_g);
+ * those whose factor vanishes for every ordering are dropped, leaving
+ * N_flow = 585 (MF_GG_TTXG) and 4311 (MF_GG_TTXGG), and the event's flow is
+ * the idx-th of them, idx = ((k >> 16) N_flow) >> 37 from the same Philox
+ * block.  |M|^2 is N_flow |sum_sigma (G_{sigma1} .. G_{sigman})_{ij} A(sigma)|^2
+ * summed over helicities: unbiased, with a per-event variance several times
+ * smaller than that of MF_COLOUR_SAMPLED.  Same entry points as SAMPLED. */
+typedef enum {
+    MF_COLOUR_FULL = 0, MF_COLOUR_LEADING = 1, MF_COLOUR_SAMPLED = 2, MF_COLOUR_FLOW = 3
+} mf_colour;
 
 typedef struct {
     mf_process_id id;
@@ -98,8 +111,8 @@ typedef struct {
     int profile;             /* 1: time every kernel with HIP events (0)        */
     uint64_t max_batch;      /* n_g >= 3: events per batch of the per-event device
                                 buffers (about 170 B per event), 0 = 2^27 (0)   */
-    mf_colour colour;        /* MF_COLOUR_FULL, MF_COLOUR_LEADING or MF_COLOUR_SAMPLED
-                                (FULL); the gradient entry points take FULL only */
+    mf_colour colour;        /* MF_COLOUR_FULL, _LEADING, _SAMPLED or _FLOW (FULL);
+                                the gradient entry points take FULL only       */
 } mf_options;
 
 typedef struct {

@@ -563,24 +563,59 @@ void mfo_colour_factors(int n_g, int64_t cfg, double *c)
     }
 }
 
-double mfo_me2_sum_colour_config(int n_g, const double *p, double m, double width, int64_t cfg)
+/* sum_h |sum_sigma c_sigma A_sigma,h|^2 for factors c (re, im per ordering)
+ * and, in *kappa, sum_h |M_h| sum_sigma |c_sigma A_sigma,h| / sum_h |M_h|^2:
+ * the factor by which the sum magnifies relative errors of the amplitudes
+ * (0 if the sum vanishes). */
+static double dressed_sum(int n_g, const double *p, double m, double width, const double *c, double *kappa)
 {
     int nperm = mfo_n_orderings(n_g);
-    double c[2 * 120];
-    mfo_colour_factors(n_g, cfg, c);
     int nh = 1 << (n_g + 2);
-    double total = 0.0;
+    double total = 0.0, bound = 0.0;
     for (int h = 0; h < nh; ++h) {
         int hel[MFO_MAX_G + 2];
         hel_from_index(n_g, h, hel);
         cplx A[120];
         partial_amplitudes_core(n_g, p, m, width, hel, -1, A);
         cplx M = 0;
-        for (int s = 0; s < nperm; ++s)
-            M += (c[2 * s] + I * c[2 * s + 1]) * A[s];
+        double mag = 0.0;
+        for (int s = 0; s < nperm; ++s) {
+            cplx t = (c[2 * s] + I * c[2 * s + 1]) * A[s];
+            M += t;
+            mag += cabs(t);
+        }
         total += creal(M) * creal(M) + cimag(M) * cimag(M);
+        bound += cabs(M) * mag;
     }
-    return (double)mfo_colour_count(n_g) * total;
+    if (kappa)
+        *kappa = total > 0.0 ? bound / total : 0.0;
+    return total;
+}
+
+double mfo_me2_sum_sampled(int n_g, const double *p, double m, double width, int mode, int64_t cfg,
+                           double *kappa)
+{
+    double c[2 * 120];
+    int64_t count;
+    if (mode == 2) {
+        mfo_colour_factors(n_g, cfg, c);
+        count = mfo_colour_count(n_g);
+    } else {
+        int nperm = mfo_n_orderings(n_g);
+        double r[120];
+        mfo_flow_factors(n_g, cfg, r);
+        for (int s = 0; s < nperm; ++s) {
+            c[2 * s] = r[s];
+            c[2 * s + 1] = 0.0;
+        }
+        count = mfo_flow_count(n_g);
+    }
+    return (double)count * dressed_sum(n_g, p, m, width, c, kappa);
+}
+
+double mfo_me2_sum_colour_config(int n_g, const double *p, double m, double width, int64_t cfg)
+{
+    return mfo_me2_sum_sampled(n_g, p, m, width, 2, cfg, NULL);
 }
 
 /* Colour flows: gluon g carries a colour a_g and an anticolour b_g, state
@@ -686,22 +721,7 @@ void mfo_flow_factors(int n_g, int64_t idx, double *c)
 
 double mfo_me2_sum_colour_flow(int n_g, const double *p, double m, double width, int64_t idx)
 {
-    int nperm = mfo_n_orderings(n_g);
-    double c[120];
-    mfo_flow_factors(n_g, idx, c);
-    int nh = 1 << (n_g + 2);
-    double total = 0.0;
-    for (int h = 0; h < nh; ++h) {
-        int hel[MFO_MAX_G + 2];
-        hel_from_index(n_g, h, hel);
-        cplx A[120];
-        partial_amplitudes_core(n_g, p, m, width, hel, -1, A);
-        cplx M = 0;
-        for (int s = 0; s < nperm; ++s)
-            M += c[s] * A[s];
-        total += creal(M) * creal(M) + cimag(M) * cimag(M);
-    }
-    return (double)mfo_flow_count(n_g) * total;
+    return mfo_me2_sum_sampled(n_g, p, m, width, 3, idx, NULL);
 }
 
 double mfo_me2_sum(int n_g, const double *p, double m, double width)

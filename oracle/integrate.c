@@ -95,6 +95,7 @@ static double weight_from_x(const mfo_process *proc, double sqrt_s,
     ev->newton_fail = 0;
     ev->near_edge = 0;
     ev->ill_conditioned = 0;
+    ev->colour_kappa = 0.0;
     ev->ps_weight = ev->f1 = ev->f2 = ev->me2 = 0.0;
     ev->w = 0.0;
     memset(ev->k, 0, sizeof(ev->k));
@@ -140,10 +141,10 @@ static double weight_from_x(const mfo_process *proc, double sqrt_s,
 
     double gs2 = 4.0 * PI * proc->alpha_s;
     double sum;
-    if (proc->colour == 3)
-        sum = ev->colour_cfg >= 0 ? mfo_me2_sum_colour_flow(n_g, p, m, proc->w_top, ev->colour_cfg) : NAN;
-    else if (proc->colour == 2)
-        sum = ev->colour_cfg >= 0 ? mfo_me2_sum_colour_config(n_g, p, m, proc->w_top, ev->colour_cfg) : NAN;
+    if (proc->colour == 2 || proc->colour == 3)
+        sum = ev->colour_cfg >= 0 ? mfo_me2_sum_sampled(n_g, p, m, proc->w_top, proc->colour, ev->colour_cfg,
+                                                        &ev->colour_kappa)
+                                  : NAN;
     else if (proc->colour == 1)
         sum = mfo_me2_sum_lc(n_g, p, m, proc->w_top);
     else
@@ -356,7 +357,7 @@ static void *run_list(void *arg)
         lw->w[i] = mfo_event_weight(lw->proc, lw->sqrt_s, lw->pdf, lw->n_bins, lw->grid, lw->seed,
                                     lw->iter, lw->ids[i], &ev);
         lw->flags[i] = ev.pass_threshold | ev.newton_fail << 1 | ev.pass_cuts << 2 | ev.near_edge << 3
-                       | ev.ill_conditioned << 4;
+                       | ev.ill_conditioned << 4 | (ev.colour_kappa > 50.0) << 5;
     }
     return NULL;
 }

@@ -73,6 +73,7 @@ typedef struct {
     int    near_edge;          /* a cut variable lies within 1e-9 of its cut   */
     int    ill_conditioned;    /* |d ln(x g) / d ln x| > 1e3 at x1 or x2      */
     int64_t colour_cfg;        /* colour = 2, 3: the event's assignment, flow   */
+    double colour_kappa;       /* colour = 2, 3: condition number of the sum   */
 } mfo_event;
 
 typedef struct {
@@ -167,6 +168,14 @@ void mfo_flow_factors(int n_g, int64_t idx, double *c);
 /* N_flow * sum_h |M(flow idx)|^2, g_s = 1.                                  */
 double mfo_me2_sum_colour_flow(int n_g, const double *p, double m, double width, int64_t idx);
 
+/* Either sampled sum (mode 2: adjoint assignment cfg; mode 3: flow index
+ * cfg) and, if kappa is not NULL, its condition number
+ * kappa = sum_h |M_h| sum_sigma |c_sigma A_sigma,h| / sum_h |M_h|^2 (>= 1;
+ * 0 if the sum vanishes): cancellations between orderings magnify relative
+ * rounding errors of the partial amplitudes by up to 2 kappa.              */
+double mfo_me2_sum_sampled(int n_g, const double *p, double m, double width, int mode, int64_t cfg,
+                           double *kappa);
+
 /* ---- per-event weight and integration ---------------------------------- */
 int mfo_n_dims(int n_g);
 double mfo_event_weight(const mfo_process *proc, double sqrt_s,
@@ -192,7 +201,8 @@ int mfo_lab_event(const mfo_process *proc, double sqrt_s, int n_bins, const doub
 
 /* Weights w[i] of events ids[i] of iteration iter on n_threads threads;
  * flags[i]: bit 0 above threshold, bit 1 Newton failed, bit 2 passed the
- * cuts, bit 3 near a cut edge, bit 4 ill-conditioned PDF value.           */
+ * cuts, bit 3 near a cut edge, bit 4 ill-conditioned PDF value, bit 5
+ * sampled colour sum with condition number colour_kappa > 50.             */
 int mfo_event_weights(const mfo_process *proc, double sqrt_s, const mfo_pdf_grid *pdf, int n_bins,
                       const double *grid, uint64_t seed, int iter, uint64_t n, const uint64_t *ids,
                       int n_threads, double *w, int *flags);

@@ -36,7 +36,7 @@ class _Event(C.Structure):
                 ("f2", C.c_double), ("me2", C.c_double), ("w", C.c_double),
                 ("k", C.c_double * 16), ("pass_threshold", C.c_int), ("pass_cuts", C.c_int),
                 ("newton_fail", C.c_int), ("near_edge", C.c_int), ("ill_conditioned", C.c_int),
-                ("colour_cfg", C.c_int64)]
+                ("colour_cfg", C.c_int64), ("colour_kappa", C.c_double)]
 
 
 class _Result(C.Structure):
@@ -110,6 +110,9 @@ def lib():
         L.mfo_flow_factors.argtypes = [C.c_int, C.c_int64, _dp]
         L.mfo_me2_sum_colour_flow.argtypes = [C.c_int, _dp, C.c_double, C.c_double, C.c_int64]
         L.mfo_me2_sum_colour_flow.restype = C.c_double
+        L.mfo_me2_sum_sampled.argtypes = [C.c_int, _dp, C.c_double, C.c_double, C.c_int, C.c_int64,
+                                          C.POINTER(C.c_double)]
+        L.mfo_me2_sum_sampled.restype = C.c_double
         L.mfo_me2_sum_fullcolour.argtypes = [C.c_int, _dp, C.c_double, C.c_double, C.c_int, _ip]
         L.mfo_me2_sum_fullcolour.restype = C.c_double
         L.mfo_n_dims.argtypes = [C.c_int]
@@ -205,6 +208,7 @@ class EventInfo:
     newton_fail: bool
     near_edge: bool
     ill_conditioned: bool
+    colour_kappa: float = 0.0
 
 
 def _event_info(ev, D):
@@ -212,7 +216,7 @@ def _event_info(ev, D):
                      ev.shat, ev.ps_weight, ev.f1, ev.f2, ev.me2, ev.w,
                      np.array(ev.k[:]).reshape(4, 4), bool(ev.pass_threshold),
                      bool(ev.pass_cuts), bool(ev.newton_fail), bool(ev.near_edge),
-                     bool(ev.ill_conditioned))
+                     bool(ev.ill_conditioned), ev.colour_kappa)
 
 
 def n_dims(n_g: int) -> int:
@@ -363,6 +367,15 @@ def flow_factors(n_g, idx):
     return out
 
 
+def me2_sum_sampled(n_g, p, m, width, mode, cfg):
+    """(sampled colour sum, condition number) for mode 2 (adjoint assignment
+    cfg) or 3 (flow index cfg), g_s = 1."""
+    p = _f64(p)
+    k = C.c_double()
+    v = lib().mfo_me2_sum_sampled(n_g, _d(p), m, width, mode, cfg, C.byref(k))
+    return v, k.value
+
+
 def me2_sum_colour_flow(n_g, p, m, width, idx):
     """N_flow times the helicity sum of |M|^2 for colour flow idx, g_s = 1."""
     p = _f64(p)
@@ -499,7 +512,8 @@ def lab_event(proc: Process, sqrt_s, grid, seed, it, event):
 def event_weights(proc: Process, sqrt_s, table, grid, seed, it, ids, n_threads=None):
     """Weights of the events `ids` of iteration `it`, threaded; returns (w, flags)
     with flags bit 0 above threshold, 1 Newton failed, 2 passed the cuts,
-    3 near a cut edge, 4 ill-conditioned PDF value."""
+    3 near a cut edge, 4 ill-conditioned PDF value, 5 sampled colour sum
+    with condition number above 50 (EventInfo.colour_kappa gives it)."""
     h = _PdfHandle(table)
     grid = _f64(grid)
     ids = np.ascontiguousarray(ids, dtype=np.uint64)

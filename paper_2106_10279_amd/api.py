@@ -26,8 +26,8 @@ PROCESS_IDS = {"gg_ttx": _lib.MF_GG_TTX, "gg_ttxg": _lib.MF_GG_TTXG, "gg_ttxgg":
                2: _lib.MF_GG_TTX, 3: _lib.MF_GG_TTXG, 4: _lib.MF_GG_TTXGG}
 PRECISIONS = {"fp64": MF_FP64, "fp32_kahan": MF_FP32_KAHAN}
 # colour sum: the full colour matrix, the leading-colour approximation, or a
-# Monte Carlo over colour assignments (mf_integrate, n_g >= 3)
-COLOURS = {"full": 0, "leading": 1, "sampled": 2}
+# Monte Carlo over colour assignments or colour flows (mf_integrate, n_g >= 3)
+COLOURS = {"full": 0, "leading": 1, "sampled": 2, "flow": 3}
 
 _dp = C.POINTER(C.c_double)
 

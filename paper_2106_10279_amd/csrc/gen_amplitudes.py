@@ -32,6 +32,7 @@ from __future__ import annotations
 
 import argparse
 import itertools
+import functools
 import math
 import os
 from fractions import Fraction
@@ -105,6 +106,46 @@ def gell_mann_half():
     lam[7][0][0] = lam[7][1][1] = 1 / r3
     lam[7][2][2] = -2 / r3
     return [[[complex(v) / 2 for v in row] for row in m] for m in lam]
+
+
+@functools.lru_cache(maxsize=None)
+def _flow_table(n, perms):
+    return flow_table_uncached(n, perms)
+
+
+def flow_table(n, perms):
+    return _flow_table(n, tuple(tuple(sg) for sg in perms))
+
+
+def flow_table_uncached(n, perms):
+    """Colour flows with a non-vanishing factor for some ordering, in
+    increasing code = j + 3 i + 9 sum_g 9^g (3 a_g + b_g), packed as
+    j | i << 2 | a_g << (4 + 4 g) | b_g << (6 + 4 g).  Gluon g carries colour
+    a_g and anticolour b_g, state (e_ab - delta_ab / 3) / sqrt 2; each row of
+    such a matrix has at most one non-zero entry, so a factor is a walk along
+    the colour line from i: an off-diagonal pair (a, b) needs the current colour
+    a and moves it to b, a diagonal pair keeps it.  The walk ends on j or the
+    factor vanishes."""
+    def nonzero(order, pairs, i, j):
+        r = i
+        for g in order:
+            a, b = pairs[g]
+            if a != b:
+                if r != a:
+                    return False
+                r = b
+        return r == j
+
+    out = []
+    for code in range(9 * 9 ** n):
+        j, i, rest = code % 3, (code // 3) % 3, code // 9
+        pairs = [divmod((rest // 9 ** g) % 9, 3) for g in range(n)]
+        if any(nonzero(sg, pairs, i, j) for sg in perms):
+            word = j | (i << 2)
+            for g, (a, b) in enumerate(pairs):
+                word |= (a << (4 + 4 * g)) | (b << (6 + 4 * g))
+            out.append(word)
+    return out
 
 
 # ----------------------------------------------------------------------------
@@ -1059,7 +1100,7 @@ def emit_coop(n, lay, co, K, den, perms):
     # Monte Carlo over colours (COL = 2): the event's colour factors cf
     # (re, im per ordering) dress the amplitudes, M = sum_s c_s A_s; N_cfg |M|^2
     # over the common denominator keeps the final division of the full sum
-    a("    } else {")
+    a("    } else if constexpr (COL == 2) {")
     a("        T mr = 0, mi = 0;")
     mc_flops = 0
     for sidx in range(nperm_):
@@ -1069,27 +1110,40 @@ def emit_coop(n, lay, co, K, den, perms):
         mc_flops += 8
     a(f"        me = (T){colour_count(n) * den} * (mr * mr + mi * mi);")
     mc_flops += 4
+    # Monte Carlo over colour flows (COL = 3): real factors cf[s], N_flow |M|^2
+    a("    } else {")
+    a("        T mr = 0, mi = 0;")
+    flow_flops = 0
+    for sidx in range(nperm_):
+        op = "+=" if sig[sidx] > 0 else "-="
+        a(f"        mr {op} cf[{sidx}] * Ar[{sidx}]; mi {op} cf[{sidx}] * Ai[{sidx}];")
+        flow_flops += 4
+    a(f"        me = (T){len(flow_table(n, perms)) * den} * (mr * mr + mi * mi);")
+    flow_flops += 4
     a("    }")
     A_seq[acc_decl] = A[acc_decl]
     A_seq.extend(A[tail_start:])
     amp = ("\n".join(A), "\n".join(A_seq))
     return "\n".join(tables), stages, amp, flops_stage, (hel_flops + full_flops, hel_flops + lc_flops,
-                                                          hel_flops + mc_flops)
+                                                          hel_flops + mc_flops, hel_flops + flow_flops)
 
 
 def generate_coop(n):
     perms, K, den = colour_matrix(n)
     tl = CoopTable(n)
     co = CoopLayout(n)
-    tables, stages, amp, fst, (fhel, fhel_lc, fhel_mc) = emit_coop(n, tl, co, K, den, perms)
+    tables, stages, amp, fst, (fhel, fhel_lc, fhel_mc, fhel_flow) = emit_coop(n, tl, co, K, den, perms)
     fill = emit_coop_fill(n, tl, co)
     global _COOP_COUNT
     _COOP_COUNT = {"stages": fst, "per_helicity": fhel, "per_helicity_lc": fhel_lc, "per_helicity_mc": fhel_mc,
+                   "per_helicity_flow": fhel_flow,
                    "object_store": co.size, "table": tl.size, "momentum_only": tl.mom_flops()}
     gm = gell_mann_half()
     gm_re = ", ".join(repr(v.real) for m in gm for row in m for v in row)
     gm_im = ", ".join(repr(v.imag) for m in gm for row in m for v in row)
     perm_tab = ", ".join(str(g) for sg in perms for g in sg)
+    flows = flow_table(n, perms)
+    flow_tab = ", ".join(f"{w}u" for w in flows)
     return f"""
 // ---- cooperative evaluation (helicity-recycled objects in LDS) ----
 // Table: {tl.size} T per event; object store: {co.size} T per event.  Table
@@ -1204,6 +1258,44 @@ __device__ __forceinline__ void colour_factors_ng{n}(uint64_t event, uint64_t se
     cf[2 * lane] = (T)cr;
     cf[2 * lane + 1] = (T)cim;
 }}
+
+// Monte Carlo over colour flows: the event's flow index from the same Philox
+// block and formula with N_flow = {len(flows)} in place of N_cfg, the flow
+// word from the table (j | i << 2 | a_g << (4 + 4 g) | b_g << (6 + 4 g): gluon g
+// has colour a_g and anticolour b_g, state (e_ab - delta_ab / 3) / sqrt 2), and
+// on lanes 0 .. {len(perms) - 1} the real factor of ordering s into cf[s]: the
+// colour line from i through the gluons of the ordering, where an off-diagonal
+// pair needs the current colour a and moves it to b, a diagonal pair keeps it
+// with factor 2/3 (same colour) or -1/3, and the line must end on j.
+static constexpr int64_t FLOW_COUNT_NG{n} = {len(flows)};
+static constexpr uint32_t FLOW_NG{n}[{len(flows)}] = {{{flow_tab}}};
+template <typename T>
+__device__ __forceinline__ void flow_factors_ng{n}(uint64_t event, uint64_t seed, uint32_t iter,
+                                                  T* __restrict__ cf, int lane)
+{{
+    if (lane >= {len(perms)})
+        return;
+    uint32_t r[4];
+    philox4x32_10((uint32_t)event, (uint32_t)(event >> 32), iter, 0x80000001u, (uint32_t)seed,
+                  (uint32_t)(seed >> 32), r);
+    const uint64_t k = ((((uint64_t)r[0]) << 32) | (uint64_t)r[1]) >> 11;
+    const uint64_t idx = ((k >> 16) * (uint64_t)FLOW_COUNT_NG{n}) >> 37;
+    const uint32_t f = FLOW_NG{n}[idx];
+    uint32_t col = (f >> 2) & 3u;
+    bool alive = true;
+    double v = {repr(2.0 ** (-n / 2))};
+    for (int step = 0; step < {n}; ++step) {{
+        const int g = PERM_NG{n}[lane * {n} + step];
+        const uint32_t a = (f >> (4 + 4 * g)) & 3u, b = (f >> (6 + 4 * g)) & 3u;
+        if (a != b) {{
+            alive = alive && col == a;
+            col = b;
+        }} else {{
+            v *= col == a ? {repr(2.0 / 3.0)} : {repr(-1.0 / 3.0)};
+        }}
+    }}
+    cf[lane] = (T)(alive && col == (f & 3u) ? v : 0.0);
+}}
 """
 
 
@@ -1217,7 +1309,7 @@ def flop_count(n, colour="full"):
     evaluations (n = 2) or the shared object stages and the per-helicity
     meet-in-the-middle contractions (n >= 3).  colour = "leading" counts the
     leading-colour sum in place of the full colour matrix."""
-    assert colour in ("full", "leading", "sampled")
+    assert colour in ("full", "leading", "sampled", "flow")
     generate(n)
     c = dict(_LAST_COUNT)
     lc = colour == "leading"
@@ -1225,19 +1317,23 @@ def flop_count(n, colour="full"):
         c["algorithm"] = "helicity-recycled objects"
         c["stages"] = _COOP_COUNT["stages"]
         c["per_helicity"] = _COOP_COUNT[{"full": "per_helicity", "leading": "per_helicity_lc",
-                                         "sampled": "per_helicity_mc"}[colour]]
+                                         "sampled": "per_helicity_mc", "flow": "per_helicity_flow"}[colour]]
         c["object_store"] = _COOP_COUNT["object_store"]
         c["per_event"] = c["momentum_only"] + c["stages"] + c["n_hel"] * c["per_helicity"]
         if colour == "sampled":
             # the event's colour factors: n steps of a complex row times a 3 x 3 matrix per ordering
             c["colour_factors"] = 36 * n * c["n_orderings"]
             c["per_event"] += c["colour_factors"]
+        elif colour == "flow":
+            # the event's flow factors: at most n multiplications per ordering
+            c["colour_factors"] = n * c["n_orderings"]
+            c["per_event"] += c["colour_factors"]
     else:
         c["algorithm"] = "independent helicities"
         c["stages"] = 0
         if lc:
             c["per_helicity"] = c["per_helicity_lc"]
-        assert colour != "sampled", "the Monte Carlo over colours runs for n >= 3 only"
+        assert colour not in ("sampled", "flow"), "the Monte Carlo over colours runs for n >= 3 only"
         c["per_event"] = c["momentum_only"] + c["n_hel"] * c["per_helicity"]
     return c
 

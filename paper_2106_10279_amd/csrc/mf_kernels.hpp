@@ -332,7 +332,9 @@ struct Layout {
 // lanes of the event (h = 0 .. 2^(NG+2) - 1) build the object store first
 // (n_g >= 3).  `any_live` must be uniform over the wave.  COL = 0: full
 // colour matrix; COL = 1: leading-colour approximation; COL = 2: one sampled
-// colour assignment whose factors are cf (n_g >= 3; Sec. 3.3 names both).
+// colour assignment whose complex factors are cf; COL = 3: one sampled colour
+// flow whose real factors are cf (n_g >= 3; Sec. 3.3 names leading colour and
+// colour sampling).
 template <int NG, typename T, int COL = 0>
 __device__ __forceinline__ double event_me2(const TabT<NG, T>* tab, T* obj, int h, double mt, bool live, bool any_live,
                                             const T* cf = nullptr)
@@ -352,7 +354,7 @@ __device__ __forceinline__ double event_me2(const TabT<NG, T>* tab, T* obj, int 
         else
             return coop_me2_ng4<T, COL>(tab, obj, cf, h);
     } else {
-        static_assert(COL != 2, "the Monte Carlo over colours runs for n_g >= 3 only");
+        static_assert(COL < 2, "the Monte Carlo over colours runs for n_g >= 3 only");
         return live ? colour_summed_me2_ng2<T, COL>(tab, h, mt) : 0.0;
     }
 }
@@ -707,7 +709,7 @@ __device__ __forceinline__ void amp_quads_ng3(const StageParams& S)
     __shared__ __align__(16) T s_tab[kQ][L::kTable + kL1];
     __shared__ __align__(16) T s_obj[2][L::kObj];
     __shared__ double s_mom[kQ][L::kMom];
-    constexpr int kCf = COL == 2 ? 2 * 6 : 2;
+    constexpr int kCf = COL >= 2 ? 2 * 6 : 2;
     __shared__ __align__(16) T s_cf[2][kCf];
     const int lane = threadIdx.x;
     const int h0 = lane % L::kHel, sub = lane / L::kHel;      // helicity phase: 2 events x 32 lanes
@@ -767,6 +769,9 @@ __device__ __forceinline__ void amp_quads_ng3(const StageParams& S)
                 if constexpr (COL == 2) {
                     if (live)
                         colour_factors_ng3<T>(S.first + e, S.P.seed, S.P.iter, s_cf[sub], h);
+                } else if constexpr (COL == 3) {
+                    if (live)
+                        flow_factors_ng3<T>(S.first + e, S.P.seed, S.P.iter, s_cf[sub], h);
                 }
                 wave_sync();
                 double v = event_me2<3, T, COL>(tab, obj, h, S.P.m_top, live, any_live, s_cf[sub]);
@@ -793,8 +798,9 @@ __device__ __forceinline__ void amp_groups(const StageParams& S)
     __shared__ __align__(16) TabT<NG, T> s_tab[L::kEventsPerPass][L::kTable];
     __shared__ __align__(16) T s_obj[L::kEventsPerPass][L::kObj];
     __shared__ double s_mom[L::kEventsPerPass][L::kMom];
-    // colour factors of the sampled assignment (COL = 2), re and im per ordering
-    constexpr int kCf = COL == 2 ? 2 * (NG == 3 ? 6 : 24) : 2;
+    // colour factors of the sampled assignment (COL = 2: re and im per
+    // ordering) or flow (COL = 3: one real value per ordering)
+    constexpr int kCf = COL >= 2 ? 2 * (NG == 3 ? 6 : 24) : 2;
     __shared__ __align__(16) T s_cf[L::kEventsPerPass][kCf];
     const int lane = threadIdx.x;
     const int h0 = lane % L::kHel;
@@ -848,6 +854,11 @@ __device__ __forceinline__ void amp_groups(const StageParams& S)
                         colour_factors_ng3<T>(S.first + e, S.P.seed, S.P.iter, cf, h);
                     else
                         colour_factors_ng4<T>(S.first + e, S.P.seed, S.P.iter, cf, h);
+                } else if constexpr (COL == 3) {
+                    if constexpr (NG == 3)
+                        flow_factors_ng3<T>(S.first + e, S.P.seed, S.P.iter, cf, h);
+                    else
+                        flow_factors_ng4<T>(S.first + e, S.P.seed, S.P.iter, cf, h);
                 }
             }
             wave_sync();

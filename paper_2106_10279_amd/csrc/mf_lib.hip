@@ -174,7 +174,8 @@ mf_status validate_options(const mf_options* opt, int D)
         return fail(MF_EINVAL, "alpha must be finite and > 0");
     if (opt->precision != MF_FP64 && opt->precision != MF_FP32_KAHAN)
         return fail(MF_EINVAL, "unknown precision");
-    if (opt->colour != MF_COLOUR_FULL && opt->colour != MF_COLOUR_LEADING && opt->colour != MF_COLOUR_SAMPLED)
+    if (opt->colour != MF_COLOUR_FULL && opt->colour != MF_COLOUR_LEADING && opt->colour != MF_COLOUR_SAMPLED &&
+        opt->colour != MF_COLOUR_FLOW)
         return fail(MF_EINVAL, "unknown colour mode");
     if (opt->max_batch > kStageBatch)
         return fail(MF_EINVAL, "max_batch must be at most 2^27");
@@ -266,7 +267,7 @@ mf_status launch_event_prec(mf_precision prec, const mf::EventParams& P, int blo
 mf_status dispatch_event(int ng, mf_precision prec, mf_colour col, const mf::EventParams& P, int blocks,
                          hipStream_t s)
 {
-    if (col == MF_COLOUR_SAMPLED)
+    if (col == MF_COLOUR_SAMPLED || col == MF_COLOUR_FLOW)
         return fail(MF_EUNSUPPORTED, "the Monte Carlo over colours runs in mf_integrate for g g -> t tbar g (g) only");
     const bool lc = col == MF_COLOUR_LEADING;
     switch (ng) {
@@ -329,11 +330,15 @@ mf_status dispatch_stages(int ng, mf_precision prec, mf_colour col, const mf::St
     if (ng == 3) {
         if (col == MF_COLOUR_SAMPLED)
             return launch_stages_prec<3, 2>(prec, S, kin_blocks, n_cu, s, a, b);
+        if (col == MF_COLOUR_FLOW)
+            return launch_stages_prec<3, 3>(prec, S, kin_blocks, n_cu, s, a, b);
         return col == MF_COLOUR_LEADING ? launch_stages_prec<3, 1>(prec, S, kin_blocks, n_cu, s, a, b)
                                         : launch_stages_prec<3, 0>(prec, S, kin_blocks, n_cu, s, a, b);
     }
     if (col == MF_COLOUR_SAMPLED)
         return launch_stages_prec<4, 2>(prec, S, kin_blocks, n_cu, s, a, b);
+    if (col == MF_COLOUR_FLOW)
+        return launch_stages_prec<4, 3>(prec, S, kin_blocks, n_cu, s, a, b);
     return col == MF_COLOUR_LEADING ? launch_stages_prec<4, 1>(prec, S, kin_blocks, n_cu, s, a, b)
                                     : launch_stages_prec<4, 0>(prec, S, kin_blocks, n_cu, s, a, b);
 }
@@ -471,7 +476,7 @@ mf_status integrate_impl(const mf_process* proc, double sqrt_s, const mf_pdf_gri
         return fail(MF_EINVAL, "n_iter must be in [1, 256]");
     if ((uint64_t)opt->start_iter + (uint64_t)n_iter > 0xFFFFFFFFull)
         return fail(MF_EINVAL, "iteration index exceeds the 32-bit Philox counter word");
-    if (opt->colour == MF_COLOUR_SAMPLED && ng == 2)
+    if ((opt->colour == MF_COLOUR_SAMPLED || opt->colour == MF_COLOUR_FLOW) && ng == 2)
         return fail(MF_EUNSUPPORTED, "the Monte Carlo over colours runs for g g -> t tbar g (g) only");
     if (grad) {
         if (ng != 2)
@@ -803,7 +808,7 @@ mf_status mf_evaluate(const mf_process* proc, double sqrt_s, const mf_pdf_grid* 
 {
     if (!w_out)
         return fail(MF_EINVAL, "w_out is NULL");
-    if (opt && opt->colour == MF_COLOUR_SAMPLED)
+    if (opt && (opt->colour == MF_COLOUR_SAMPLED || opt->colour == MF_COLOUR_FLOW))
         return fail(MF_EUNSUPPORTED, "the Monte Carlo over colours runs in mf_integrate only");
     std::unique_lock<std::mutex> lock;
     Setup S;

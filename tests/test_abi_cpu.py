@@ -164,21 +164,23 @@ def test_colour_mode_default_and_validation_without_device(L, pdf_table):
     assert o.colour == 0                      # MF_COLOUR_FULL
     with pytest.raises(L.MFError) as e:
         api.integrate(api.Process("gg_ttxgg"), 13000.0, pdf_table, 1000, 1, 0, keep_weights=False,
-                      stream=0, colour=3)
+                      stream=0, colour=4)
     assert e.value.status == L.MF_EINVAL
     assert b"colour" in L.lib.mf_last_error()
-    # the Monte Carlo over colours: mf_integrate for n_g >= 3 only, rejected before any device call
-    with pytest.raises(L.MFError) as e:
-        api.integrate(api.Process("gg_ttx"), 13000.0, pdf_table, 1000, 1, 0, keep_weights=False,
-                      stream=0, colour="sampled")
-    assert e.value.status == L.MF_EUNSUPPORTED
-    o.colour = 2
-    proc = api.Process("gg_ttxgg").c()
-    pdf = api._Pdf(pdf_table)
-    st = L.lib.mf_evaluate(C.byref(proc), 13000.0, C.byref(pdf.c), None, None, None, 10, 0, 0, C.byref(o),
-                           C.c_void_p(16), None, None, None)
-    assert st == L.MF_EUNSUPPORTED
-    assert b"colours" in L.lib.mf_last_error()
+    # the Monte Carlo over colours (adjoint indices or flows): mf_integrate for
+    # n_g >= 3 only, rejected before any device call
+    for mode, code in (("sampled", 2), ("flow", 3)):
+        with pytest.raises(L.MFError) as e:
+            api.integrate(api.Process("gg_ttx"), 13000.0, pdf_table, 1000, 1, 0, keep_weights=False,
+                          stream=0, colour=mode)
+        assert e.value.status == L.MF_EUNSUPPORTED
+        o.colour = code
+        proc = api.Process("gg_ttxgg").c()
+        pdf = api._Pdf(pdf_table)
+        st = L.lib.mf_evaluate(C.byref(proc), 13000.0, C.byref(pdf.c), None, None, None, 10, 0, 0, C.byref(o),
+                               C.c_void_p(16), None, None, None)
+        assert st == L.MF_EUNSUPPORTED
+        assert b"colours" in L.lib.mf_last_error()
 
 
 def test_gradient_rejects_leading_colour_without_device(L, pdf_table):

@@ -103,8 +103,20 @@ def test_sampled_colour_ttxgg_1e7_sampled_events_and_unbiasedness(api, oracle_li
     zero = (w_o == 0.0) & ~skip
     assert np.all(wg[zero] == 0.0)
     use = ~skip & ~zero
-    rel = np.abs(wg[use] / w_o[use] - 1.0)
-    say(f"  {int(use.sum())} of 2000 sampled events nonzero and usable, max rel {rel.max():.2e}")
+    # bit 5: the sampled sum cancels between orderings (condition number kappa
+    # above 50), which magnifies the rounding of the partial amplitudes; those
+    # events are held to 1e-12 kappa / 50
+    cond = (flags & 32) != 0
+    rel = np.abs(wg[use & ~cond] / w_o[use & ~cond] - 1.0)
+    worst = 0.0
+    for i in np.nonzero(use & cond)[0]:
+        wo, ev = O.event_weight(oproc(4), SQRT_S, pdf_table, grid, 0, 1, int(ids[i]))
+        assert wo == w_o[i]
+        r = abs(wg[i] / wo - 1.0)
+        worst = max(worst, r / ev.colour_kappa)
+        assert r < 1e-12 * ev.colour_kappa / 50
+    say(f"  {int(use.sum())} of 2000 sampled events nonzero and usable, max rel {rel.max():.2e} "
+        f"({int((use & cond).sum())} with kappa > 50: max rel / kappa {worst:.2e})")
     # most assignments give a vanishing colour factor for every ordering: about a
     # quarter of the passing events carry a nonzero weight
     assert use.sum() > 300

@@ -146,3 +146,28 @@ def test_flow_event_weight_uses_the_events_flow(pdf_table):
     y = np.full(10, 0.37)
     w, _ = O.event_weight_y(flow, 13000.0, pdf_table, grid, y)
     assert math.isnan(w)
+
+
+def test_condition_number_of_the_sampled_sums():
+    """kappa = sum_h |M_h| sum_s |c_s A_s,h| / sum_h |M_h|^2 against its
+    definition; kappa = 1 exactly when a single ordering contributes, and
+    kappa >= 1 always (triangle inequality)."""
+    rng = np.random.default_rng(900)
+    p = random_momenta(4, 1400.0, rng)
+    A = np.array([O.partial_amplitudes(4, p, M, 1.5, h) for h in O.all_helicities(4)])
+    for k in range(0, O.flow_count(4), 97):
+        c = O.flow_factors(4, k)
+        v, kappa = O.me2_sum_sampled(4, p, M, 1.5, 3, k)
+        Mh = A @ c
+        S = np.sum(np.abs(Mh) ** 2)
+        assert v == pytest.approx(O.flow_count(4) * S, rel=1e-12)
+        assert kappa == pytest.approx(np.sum(np.abs(Mh) * (np.abs(A) @ np.abs(c))) / S, rel=1e-12)
+        assert kappa >= 1.0 - 1e-14
+    # a single contributing ordering: i = 0, gluon 0 = (0 -> 1), gluon 1 = (1 -> 2), j = 2
+    code = 2 + 9 * ((3 * 0 + 1) + 9 * (3 * 1 + 2))
+    k = [O.flow_code(2, q) for q in range(O.flow_count(2))].index(code)
+    p2 = random_momenta(2, 900.0, rng)
+    assert O.me2_sum_sampled(2, p2, M, 1.5, 3, k)[1] == pytest.approx(1.0, rel=1e-14)
+    v, kappa = O.me2_sum_sampled(4, p, M, 1.5, 2, 12345)
+    assert v == pytest.approx(O.me2_sum_colour_config(4, p, M, 1.5, 12345), rel=1e-15, abs=1e-300)
+    assert kappa == 0.0 or kappa >= 1.0 - 1e-14
