@@ -69,12 +69,15 @@ typedef enum { MF_FP64 = 0, MF_FP32_KAHAN = 1 } mf_precision;
  * pairs resolve sum_a T^a (x) conj(T^a) ('t Hooft double line with the U(1)
  * part removed; Maltoni, Paul, Stelzer and Willenbrock, Phys. Rev. D67 (2003)
  * 014026).  Flows are ordered by code = j + 3 i + 9 sum_g 9^g (3 a_g + b_g);
- * those whose factor vanishes for every ordering are dropped, leaving
- * N_flow = 585 (MF_GG_TTXG) and 4311 (MF_GG_TTXGG), and the event's flow is
- * the idx-th of them, idx = ((k >> 16) N_flow) >> 37 from the same Philox
- * block.  |M|^2 is N_flow |sum_sigma (G_{sigma1} .. G_{sigman})_{ij} A(sigma)|^2
- * summed over helicities: unbiased, with a per-event variance several times
- * smaller than that of MF_COLOUR_SAMPLED.  Same entry points as SAMPLED. */
+ * those whose factor vanishes for every ordering are dropped, leaving 585
+ * (MF_GG_TTXG) and 4311 (MF_GG_TTXGG).  Flow f has the integer weight
+ * W_f = 18^n sum_sigma c_sigma(f)^2, T = sum_f W_f (248832 and 23887872), and
+ * the event draws flow f with probability W_f / T: u = floor(k T / 2^53) with
+ * k from the same Philox block, f the flow with C_f <= u < C_(f+1) for the
+ * cumulative weights C in flow order.  |M|^2 is
+ * (T / W_f) |sum_sigma (G_{sigma1} .. G_{sigman})_{ij} A(sigma)|^2 summed over
+ * helicities: unbiased, with a per-event variance several times smaller than
+ * that of MF_COLOUR_SAMPLED.  Same entry points as SAMPLED. */
 typedef enum {
     MF_COLOUR_FULL = 0, MF_COLOUR_LEADING = 1, MF_COLOUR_SAMPLED = 2, MF_COLOUR_FLOW = 3
 } mf_colour;

@@ -11,5 +11,5 @@ from .oracle import (  # noqa: F401
     neumaier_sum, ttx_dweight_dmt_analytic, n_dims, all_helicities,
     unweight_uniform, unweight, lab_event, event_weights, colour_lc, me2_sum_lc,
     colour_count, colour_config, colour_factors, me2_sum_colour_config,
-    flow_count, flow_code, flow_config, flow_factors, me2_sum_colour_flow, me2_sum_sampled,
+    flow_count, flow_code, flow_weight, flow_total, flow_config, flow_factors, me2_sum_colour_flow, me2_sum_sampled,
 )

@@ -608,7 +608,7 @@ double mfo_me2_sum_sampled(int n_g, const double *p, double m, double width, int
             c[2 * s] = r[s];
             c[2 * s + 1] = 0.0;
         }
-        count = mfo_flow_count(n_g);
+        return (double)mfo_flow_total(n_g) / (double)mfo_flow_weight(n_g, cfg) * dressed_sum(n_g, p, m, width, c, kappa);
     }
     return (double)count * dressed_sum(n_g, p, m, width, c, kappa);
 }
@@ -624,8 +624,10 @@ double mfo_me2_sum_colour_config(int n_g, const double *p, double m, double widt
  * so flows replace adjoint indices without changing the colour sum.  The
  * flows are enumerated by code = j + 3 i + 9 sum_g 9^g (3 a_g + b_g); a flow
  * whose factors vanish for every ordering contributes nothing and is dropped,
- * the rest are numbered in increasing code.                                */
+ * the rest are numbered in increasing code and drawn with probability
+ * proportional to W_f = 18^n sum_sigma c_sigma^2, an integer.               */
 static int64_t *flow_codes[MFO_MAX_G + 1];
+static int64_t *flow_cum[MFO_MAX_G + 1];      /* [n + 1] cumulative weights          */
 static int64_t flow_n[MFO_MAX_G + 1];
 static pthread_once_t flow_once = PTHREAD_ONCE_INIT;
 
@@ -671,15 +673,21 @@ static void flow_init(void)
         int perm[120 * MFO_MAX_G];
         mfo_orderings(n_g, perm);
         flow_codes[n_g] = malloc(sizeof(int64_t) * (size_t)total);
+        flow_cum[n_g] = malloc(sizeof(int64_t) * (size_t)(total + 1));
+        double scale = pow(18.0, n_g);         /* 2^n 9^n: c_sigma^2 times it is an integer */
         int64_t k = 0;
+        flow_cum[n_g][0] = 0;
         for (int64_t code = 0; code < total; ++code) {
             double c[120];
             flow_factors_of_code(n_g, code, perm, nperm, c);
-            int any = 0;
+            double w = 0.0;
             for (int s = 0; s < nperm; ++s)
-                any |= c[s] != 0.0;
-            if (any)
-                flow_codes[n_g][k++] = code;
+                w += c[s] * c[s] * scale;
+            if (w > 0.5) {
+                flow_codes[n_g][k] = code;
+                flow_cum[n_g][k + 1] = flow_cum[n_g][k] + llround(w);
+                ++k;
+            }
         }
         flow_n[n_g] = k;
     }
@@ -701,6 +709,20 @@ int64_t mfo_flow_code(int n_g, int64_t idx)
     return flow_codes[n_g][idx];
 }
 
+int64_t mfo_flow_weight(int n_g, int64_t idx)
+{
+    int64_t n = mfo_flow_count(n_g);
+    if (n < 0 || idx < 0 || idx >= n)
+        return -1;
+    return flow_cum[n_g][idx + 1] - flow_cum[n_g][idx];
+}
+
+int64_t mfo_flow_total(int n_g)
+{
+    int64_t n = mfo_flow_count(n_g);
+    return n < 0 ? -1 : flow_cum[n_g][n];
+}
+
 int64_t mfo_flow_config(int n_g, uint64_t seed, uint32_t iter, uint64_t event)
 {
     uint32_t ctr[4] = { (uint32_t)event, (uint32_t)(event >> 32), iter, 0x80000001u };
@@ -708,7 +730,17 @@ int64_t mfo_flow_config(int n_g, uint64_t seed, uint32_t iter, uint64_t event)
     uint32_t r[4];
     mfo_philox4x32_10(ctr, key, r);
     uint64_t k = ((((uint64_t)r[0]) << 32) | (uint64_t)r[1]) >> 11;
-    return (int64_t)(((k >> 16) * (uint64_t)mfo_flow_count(n_g)) >> 37);
+    uint64_t u = (uint64_t)(((unsigned __int128)k * (uint64_t)mfo_flow_total(n_g)) >> 53);
+    /* the flow whose weight interval [C_idx, C_idx+1) holds u */
+    int64_t lo = 0, hi = mfo_flow_count(n_g);
+    while (hi - lo > 1) {
+        int64_t mid = (lo + hi) / 2;
+        if ((uint64_t)flow_cum[n_g][mid] <= u)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
 }
 
 void mfo_flow_factors(int n_g, int64_t idx, double *c)

@@ -154,18 +154,25 @@ double mfo_me2_sum_colour_config(int n_g, const double *p, double m, double widt
  * sum_a T^a (x) conj(T^a).  Flows are coded as
  * code = j + 3 i + 9 sum_g 9^g (3 a_g + b_g); those whose factors vanish
  * for every ordering are dropped and the remaining N_flow are numbered in
- * increasing code.  An event draws its flow index from Philox block
- * 0x80000001 as the adjoint sampling does, with N_flow in place of N_cfg;
- * M = sum_sigma (G_{sigma1} .. G_{sigman})_{ij} A(sigma), and N_flow |M|^2
- * summed over helicities estimates the colour sum without bias.  n_g = 2..4;
- * mfo_flow_count returns -1 otherwise, mfo_flow_code -1 for an index out
- * of range.                                                                */
+ * increasing code.  Flow f has the integer weight
+ * W_f = 2^n 9^n sum_sigma c_sigma(f)^2 (every factor is (1/sqrt 2)^n times a
+ * product of 1, 2/3 and -1/3), total T = sum_f W_f, cumulative
+ * C_f = sum_{f' < f} W_f'.  An event draws its flow with probability W_f / T:
+ * with k the 53-bit integer of the first word pair of Philox block
+ * 0x80000001, u = floor(k T / 2^53) and the flow is the f with
+ * C_f <= u < C_{f+1}.  M = sum_sigma (G_{sigma1} .. G_{sigman})_{ij} A(sigma),
+ * and (T / W_f) |M|^2 summed over helicities estimates the colour sum
+ * without bias.  n_g = 2..4; mfo_flow_count and mfo_flow_total return -1
+ * otherwise, mfo_flow_code and mfo_flow_weight -1 for an index out of
+ * range.                                                                   */
 int64_t mfo_flow_count(int n_g);
 int64_t mfo_flow_code(int n_g, int64_t idx);
+int64_t mfo_flow_weight(int n_g, int64_t idx);
+int64_t mfo_flow_total(int n_g);
 int64_t mfo_flow_config(int n_g, uint64_t seed, uint32_t iter, uint64_t event);
 /* c: [n_g!] real colour factors of the orderings for flow index idx.       */
 void mfo_flow_factors(int n_g, int64_t idx, double *c);
-/* N_flow * sum_h |M(flow idx)|^2, g_s = 1.                                  */
+/* (T / W_idx) * sum_h |M(flow idx)|^2, g_s = 1.                             */
 double mfo_me2_sum_colour_flow(int n_g, const double *p, double m, double width, int64_t idx);
 
 /* Either sampled sum (mode 2: adjoint assignment cfg; mode 3: flow index

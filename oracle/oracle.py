@@ -105,6 +105,10 @@ def lib():
         L.mfo_flow_count.restype = C.c_int64
         L.mfo_flow_code.argtypes = [C.c_int, C.c_int64]
         L.mfo_flow_code.restype = C.c_int64
+        L.mfo_flow_weight.argtypes = [C.c_int, C.c_int64]
+        L.mfo_flow_weight.restype = C.c_int64
+        L.mfo_flow_total.argtypes = [C.c_int]
+        L.mfo_flow_total.restype = C.c_int64
         L.mfo_flow_config.argtypes = [C.c_int, C.c_uint64, C.c_uint32, C.c_uint64]
         L.mfo_flow_config.restype = C.c_int64
         L.mfo_flow_factors.argtypes = [C.c_int, C.c_int64, _dp]
@@ -355,6 +359,16 @@ def flow_code(n_g, idx):
     return lib().mfo_flow_code(n_g, idx)
 
 
+def flow_weight(n_g, idx):
+    """Integer sampling weight W = 2^n 9^n sum_sigma c_sigma^2 of flow idx."""
+    return lib().mfo_flow_weight(n_g, idx)
+
+
+def flow_total(n_g):
+    """T = sum of the flow weights."""
+    return lib().mfo_flow_total(n_g)
+
+
 def flow_config(n_g, seed, it, event):
     """The colour-flow index of an event (Philox block 0x80000001)."""
     return lib().mfo_flow_config(n_g, seed, it, event)
@@ -377,7 +391,7 @@ def me2_sum_sampled(n_g, p, m, width, mode, cfg):
 
 
 def me2_sum_colour_flow(n_g, p, m, width, idx):
-    """N_flow times the helicity sum of |M|^2 for colour flow idx, g_s = 1."""
+    """T / W_idx times the helicity sum of |M|^2 for colour flow idx, g_s = 1."""
     p = _f64(p)
     return lib().mfo_me2_sum_colour_flow(n_g, _d(p), m, width, idx)
 

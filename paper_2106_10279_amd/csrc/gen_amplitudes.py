@@ -120,31 +120,38 @@ def flow_table(n, perms):
 def flow_table_uncached(n, perms):
     """Colour flows with a non-vanishing factor for some ordering, in
     increasing code = j + 3 i + 9 sum_g 9^g (3 a_g + b_g), packed as
-    j | i << 2 | a_g << (4 + 4 g) | b_g << (6 + 4 g).  Gluon g carries colour
+    j | i << 2 | a_g << (4 + 4 g) | b_g << (6 + 4 g), each with its integer
+    sampling weight 18^n sum_s c_s^2 = sum_s prod_g (3 f_g)^2 over the
+    orderings s whose line reaches j, f_g the gluon's factor without the
+    1/sqrt 2 (1 off the diagonal, 2/3 or -1/3 on it).  Gluon g carries colour
     a_g and anticolour b_g, state (e_ab - delta_ab / 3) / sqrt 2; each row of
     such a matrix has at most one non-zero entry, so a factor is a walk along
     the colour line from i: an off-diagonal pair (a, b) needs the current colour
     a and moves it to b, a diagonal pair keeps it.  The walk ends on j or the
     factor vanishes."""
-    def nonzero(order, pairs, i, j):
-        r = i
+    def weight(order, pairs, i, j):
+        r, w = i, 1
         for g in order:
             a, b = pairs[g]
             if a != b:
                 if r != a:
-                    return False
+                    return 0
                 r = b
-        return r == j
+                w *= 9
+            else:
+                w *= 4 if r == a else 1
+        return w if r == j else 0
 
     out = []
     for code in range(9 * 9 ** n):
         j, i, rest = code % 3, (code // 3) % 3, code // 9
         pairs = [divmod((rest // 9 ** g) % 9, 3) for g in range(n)]
-        if any(nonzero(sg, pairs, i, j) for sg in perms):
+        wsum = sum(weight(sg, pairs, i, j) for sg in perms)
+        if wsum:
             word = j | (i << 2)
             for g, (a, b) in enumerate(pairs):
                 word |= (a << (4 + 4 * g)) | (b << (6 + 4 * g))
-            out.append(word)
+            out.append((word, wsum))
     return out
 
 
@@ -1110,7 +1117,8 @@ def emit_coop(n, lay, co, K, den, perms):
         mc_flops += 8
     a(f"        me = (T){colour_count(n) * den} * (mr * mr + mi * mi);")
     mc_flops += 4
-    # Monte Carlo over colour flows (COL = 3): real factors cf[s], N_flow |M|^2
+    # Monte Carlo over colour flows (COL = 3): real factors cf[s] and the
+    # event's scale T / W_f in cf[n!]: (T / W_f) |M|^2
     a("    } else {")
     a("        T mr = 0, mi = 0;")
     flow_flops = 0
@@ -1118,8 +1126,8 @@ def emit_coop(n, lay, co, K, den, perms):
         op = "+=" if sig[sidx] > 0 else "-="
         a(f"        mr {op} cf[{sidx}] * Ar[{sidx}]; mi {op} cf[{sidx}] * Ai[{sidx}];")
         flow_flops += 4
-    a(f"        me = (T){len(flow_table(n, perms)) * den} * (mr * mr + mi * mi);")
-    flow_flops += 4
+    a(f"        me = (T){den} * cf[{nperm_}] * (mr * mr + mi * mi);")
+    flow_flops += 5
     a("    }")
     A_seq[acc_decl] = A[acc_decl]
     A_seq.extend(A[tail_start:])
@@ -1143,7 +1151,11 @@ def generate_coop(n):
     gm_im = ", ".join(repr(v.imag) for m in gm for row in m for v in row)
     perm_tab = ", ".join(str(g) for sg in perms for g in sg)
     flows = flow_table(n, perms)
-    flow_tab = ", ".join(f"{w}u" for w in flows)
+    flow_tab = ", ".join(f"{w}u" for w, _ in flows)
+    cum = [0]
+    for _, wt in flows:
+        cum.append(cum[-1] + wt)
+    flow_cum = ", ".join(f"{c}ull" for c in cum)
     return f"""
 // ---- cooperative evaluation (helicity-recycled objects in LDS) ----
 // Table: {tl.size} T per event; object store: {co.size} T per event.  Table
@@ -1259,16 +1271,20 @@ __device__ __forceinline__ void colour_factors_ng{n}(uint64_t event, uint64_t se
     cf[2 * lane + 1] = (T)cim;
 }}
 
-// Monte Carlo over colour flows: the event's flow index from the same Philox
-// block and formula with N_flow = {len(flows)} in place of N_cfg, the flow
-// word from the table (j | i << 2 | a_g << (4 + 4 g) | b_g << (6 + 4 g): gluon g
-// has colour a_g and anticolour b_g, state (e_ab - delta_ab / 3) / sqrt 2), and
-// on lanes 0 .. {len(perms) - 1} the real factor of ordering s into cf[s]: the
-// colour line from i through the gluons of the ordering, where an off-diagonal
-// pair needs the current colour a and moves it to b, a diagonal pair keeps it
-// with factor 2/3 (same colour) or -1/3, and the line must end on j.
+// Monte Carlo over colour flows: {len(flows)} flows with integer weights
+// W_f = 18^n sum_s c_s^2, cumulative sums C_f, total T = {cum[-1]}.  The event's
+// flow is the f with C_f <= u < C_(f+1), u = floor(k T / 2^53), k the 53-bit
+// integer of the first word pair of Philox block 0x80000001; its word
+// (j | i << 2 | a_g << (4 + 4 g) | b_g << (6 + 4 g): gluon g has colour a_g and
+// anticolour b_g, state (e_ab - delta_ab / 3) / sqrt 2) gives, on lanes
+// 0 .. {len(perms) - 1}, the real factor of ordering s into cf[s]: the colour
+// line from i through the gluons of the ordering, where an off-diagonal pair
+// needs the current colour a and moves it to b, a diagonal pair keeps it with
+// factor 2/3 (same colour) or -1/3, and the line must end on j.  Lane 0 also
+// stores the scale T / W_f into cf[{len(perms)}].
 static constexpr int64_t FLOW_COUNT_NG{n} = {len(flows)};
 static constexpr uint32_t FLOW_NG{n}[{len(flows)}] = {{{flow_tab}}};
+static constexpr uint64_t FLOW_CUM_NG{n}[{len(flows) + 1}] = {{{flow_cum}}};
 template <typename T>
 __device__ __forceinline__ void flow_factors_ng{n}(uint64_t event, uint64_t seed, uint32_t iter,
                                                   T* __restrict__ cf, int lane)
@@ -1279,8 +1295,19 @@ __device__ __forceinline__ void flow_factors_ng{n}(uint64_t event, uint64_t seed
     philox4x32_10((uint32_t)event, (uint32_t)(event >> 32), iter, 0x80000001u, (uint32_t)seed,
                   (uint32_t)(seed >> 32), r);
     const uint64_t k = ((((uint64_t)r[0]) << 32) | (uint64_t)r[1]) >> 11;
-    const uint64_t idx = ((k >> 16) * (uint64_t)FLOW_COUNT_NG{n}) >> 37;
-    const uint32_t f = FLOW_NG{n}[idx];
+    const uint64_t u = __umul64hi(k << 11, FLOW_CUM_NG{n}[FLOW_COUNT_NG{n}]);
+    int64_t lo = 0, hi = FLOW_COUNT_NG{n};
+    while (hi - lo > 1) {{
+        const int64_t mid = (lo + hi) >> 1;
+        if (FLOW_CUM_NG{n}[mid] <= u)
+            lo = mid;
+        else
+            hi = mid;
+    }}
+    const uint32_t f = FLOW_NG{n}[lo];
+    if (lane == 0)
+        cf[{len(perms)}] = (T)((double)FLOW_CUM_NG{n}[FLOW_COUNT_NG{n}]
+                               / (double)(FLOW_CUM_NG{n}[lo + 1] - FLOW_CUM_NG{n}[lo]));
     uint32_t col = (f >> 2) & 3u;
     bool alive = true;
     double v = {repr(2.0 ** (-n / 2))};

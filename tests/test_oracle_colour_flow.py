@@ -8,7 +8,9 @@ U(1) part projected out), whose nine pairs resolve
 sum_a T^a (x) conj(T^a) exactly.  Flows whose factors vanish for every
 ordering carry no weight and are dropped; drawing uniformly among the rest
 gives an unbiased estimate of the colour sum with a smaller variance than
-adjoint sampling, because each surviving flow selects few orderings.
+adjoint sampling, because each surviving flow selects few orderings; drawing
+flow f with probability proportional to its integer weight
+W_f = 18^n sum_sigma c_sigma(f)^2 and scaling by T / W_f lowers it further.
 """
 import itertools
 import math
@@ -60,11 +62,20 @@ def test_kept_flows_are_exactly_those_with_a_nonzero_factor(n_g):
     assert O.flow_code(n_g, len(kept)) == -1 and O.flow_code(n_g, -1) == -1
     for k in range(0, len(kept), max(1, len(kept) // 50)):
         assert np.allclose(O.flow_factors(n_g, k), kept[k][1], rtol=1e-14, atol=0)
+        assert O.flow_weight(n_g, k) == round(18 ** n_g * sum(x * x for x in kept[k][1]))
+    assert O.flow_weight(n_g, len(kept)) == -1
 
 
 def test_flow_counts_and_factors_by_hand():
     assert [O.flow_count(n) for n in (2, 3, 4)] == [87, 585, 4311]
-    assert O.flow_count(1) == -1 and O.flow_count(5) == -1
+    assert O.flow_count(1) == -1 and O.flow_count(5) == -1 and O.flow_total(5) == -1
+    for n in (2, 3, 4):
+        # T = 18^n sum_f sum_s c_s^2 = 18^n tr C (the colour matrix is pinned on its own)
+        assert O.flow_total(n) == round(18 ** n * np.trace(O.colour_matrix(n)))
+        assert O.flow_total(n) == sum(O.flow_weight(n, k) for k in range(O.flow_count(n)))
+        # code 0: every ordering's factor is (2/3)^n / 2^(n/2): weight n! 4^n
+        assert O.flow_weight(n, 0) == math.factorial(n) * 4 ** n
+    assert [O.flow_total(n) for n in (2, 3, 4)] == [3456, 248832, 23887872]
     # code 0: every pair (0, 0), i = j = 0: (2/3)^n / 2^(n/2) for each ordering
     for n in (2, 3, 4):
         assert np.allclose(O.flow_factors(n, 0), (2 / 3) ** n / 2 ** (n / 2), rtol=1e-15, atol=0)
@@ -73,6 +84,7 @@ def test_flow_counts_and_factors_by_hand():
     k = [O.flow_code(2, q) for q in range(O.flow_count(2))].index(code)
     assert [tuple(s) for s in O.orderings(2)] == [(0, 1), (1, 0)]
     assert np.allclose(O.flow_factors(2, k), [0.5, 0.0], rtol=1e-15, atol=0)
+    assert O.flow_weight(2, k) == 81
 
 
 @pytest.mark.parametrize("n_g", [2, 3, 4])
@@ -85,8 +97,9 @@ def test_flow_factors_rebuild_the_colour_matrix(n_g):
 @pytest.mark.parametrize("n_g", [2, 3, 4])
 def test_flow_estimator_unbiased_and_tighter_than_adjoint_sampling(n_g):
     """At a random point: the sum over flows of |M|^2 is the colour sum, the
-    oracle's per-flow function agrees with the same products, and the exact
-    variance per event of the flow estimate is below that of adjoint sampling."""
+    oracle's per-flow function is T / W_f times the same products, and the
+    exact variance per event of the weighted flow draw (probability W_f / T)
+    is below that of the uniform flow draw and of adjoint sampling."""
     rng = np.random.default_rng(800 + n_g)
     p = random_momenta(n_g, 1300.0, rng)
     A = np.array([O.partial_amplitudes(n_g, p, M, 1.5, h) for h in O.all_helicities(n_g)])
@@ -95,14 +108,19 @@ def test_flow_estimator_unbiased_and_tighter_than_adjoint_sampling(n_g):
     per_flow = np.sum(np.abs(F @ A.T) ** 2, axis=1)
     assert per_flow.sum() == pytest.approx(exact, rel=1e-12)
     n = len(F)
+    T = O.flow_total(n_g)
+    W = np.array([O.flow_weight(n_g, k) for k in range(n)], dtype=float)
     for k in (0, 7, n // 2, n - 1):
-        assert O.me2_sum_colour_flow(n_g, p, M, 1.5, k) == pytest.approx(n * per_flow[k], rel=1e-12, abs=1e-300)
-    relvar_flow = n * np.sum(per_flow ** 2) / exact ** 2 - 1
+        ref = T / W[k] * per_flow[k]
+        assert O.me2_sum_colour_flow(n_g, p, M, 1.5, k) == pytest.approx(ref, rel=1e-12, abs=1e-300)
+    relvar_uniform = n * np.sum(per_flow ** 2) / exact ** 2 - 1
+    relvar_flow = np.sum(per_flow ** 2 * T / W) / exact ** 2 - 1
     Fa = np.array([O.colour_factors(n_g, c) for c in range(O.colour_count(n_g))])
     per_adj = np.sum(np.abs(Fa @ A.T) ** 2, axis=1)
     relvar_adj = len(Fa) * np.sum(per_adj ** 2) / exact ** 2 - 1
-    print(f"\n  n_g = {n_g}: relative variance per event, flows {relvar_flow:.3g}, adjoint indices {relvar_adj:.3g}")
-    assert relvar_flow < relvar_adj
+    print(f"\n  n_g = {n_g}: relative variance per event, weighted flows {relvar_flow:.3g}, uniform flows "
+          f"{relvar_uniform:.3g}, adjoint indices {relvar_adj:.3g}")
+    assert relvar_flow < relvar_uniform < relvar_adj
 
 
 def test_flow_draw_is_philox_block_0x80000001(torch_philox):
@@ -111,16 +129,19 @@ def test_flow_draw_is_philox_block_0x80000001(torch_philox):
     for n_g in (3, 4):
         for (seed, e, it), r in zip(cases, torch_philox(triples)):
             k = ((r[0] << 32) | r[1]) >> 11
-            assert O.flow_config(n_g, seed, it, e) == ((k >> 16) * O.flow_count(n_g)) >> 37
+            u = (k * O.flow_total(n_g)) >> 53
+            cum = np.cumsum([0] + [O.flow_weight(n_g, f) for f in range(O.flow_count(n_g))])
+            assert O.flow_config(n_g, seed, it, e) == int(np.searchsorted(cum, u, side="right")) - 1
 
 
-def test_flow_draws_uniform():
-    n_g, n = 3, 30000
+def test_flow_draw_frequencies_follow_the_weights():
+    n_g, n = 3, 60000
     N = O.flow_count(n_g)
     idx = np.array([O.flow_config(n_g, 1, 2, e) for e in range(n)])
     assert idx.min() >= 0 and idx.max() < N
     counts = np.bincount(idx, minlength=N)
-    chi2 = float(np.sum((counts - n / N) ** 2 / (n / N)))
+    expect = n * np.array([O.flow_weight(n_g, f) for f in range(N)]) / O.flow_total(n_g)
+    chi2 = float(np.sum((counts - expect) ** 2 / expect))
     assert abs(chi2 - (N - 1)) < 6 * math.sqrt(2 * (N - 1))
 
 
@@ -160,7 +181,7 @@ def test_condition_number_of_the_sampled_sums():
         v, kappa = O.me2_sum_sampled(4, p, M, 1.5, 3, k)
         Mh = A @ c
         S = np.sum(np.abs(Mh) ** 2)
-        assert v == pytest.approx(O.flow_count(4) * S, rel=1e-12)
+        assert v == pytest.approx(O.flow_total(4) / O.flow_weight(4, k) * S, rel=1e-12)
         assert kappa == pytest.approx(np.sum(np.abs(Mh) * (np.abs(A) @ np.abs(c))) / S, rel=1e-12)
         assert kappa >= 1.0 - 1e-14
     # a single contributing ordering: i = 0, gluon 0 = (0 -> 1), gluon 1 = (1 -> 2), j = 2
