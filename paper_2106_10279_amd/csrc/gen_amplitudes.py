@@ -31,8 +31,9 @@ precision from double momenta and cast to the arithmetic type T afterwards.
 from __future__ import annotations
 
 import argparse
-import itertools
+import bisect
 import functools
+import itertools
 import math
 import os
 from fractions import Fraction
@@ -1156,6 +1157,16 @@ def generate_coop(n):
     for _, wt in flows:
         cum.append(cum[-1] + wt)
     flow_cum = ", ".join(f"{c}ull" for c in cum)
+    # guide table: for slice j of [0, T), the flow holding ceil(j T / G); the
+    # flow holding u lies at or after GUIDE[u G / T] (Chen and Asau's method)
+    n_guide = 1 << (len(flows) - 1).bit_length()
+    guide = [bisect.bisect_right(cum, -(-j * cum[-1] // n_guide)) - 1 for j in range(n_guide)]
+    for u in list(range(0, cum[-1], max(1, cum[-1] // 5000))) + [cum[-1] - 1] + cum[1:-1]:
+        f = guide[u * n_guide // cum[-1]]
+        while cum[f + 1] <= u:
+            f += 1
+        assert f == bisect.bisect_right(cum, u) - 1
+    flow_guide = ", ".join(str(g) for g in guide)
     return f"""
 // ---- cooperative evaluation (helicity-recycled objects in LDS) ----
 // Table: {tl.size} T per event; object store: {co.size} T per event.  Table
@@ -1281,10 +1292,13 @@ __device__ __forceinline__ void colour_factors_ng{n}(uint64_t event, uint64_t se
 // line from i through the gluons of the ordering, where an off-diagonal pair
 // needs the current colour a and moves it to b, a diagonal pair keeps it with
 // factor 2/3 (same colour) or -1/3, and the line must end on j.  Lane 0 also
-// stores the scale T / W_f into cf[{len(perms)}].
+// stores the scale T / W_f into cf[{len(perms)}].  The search for f starts at
+// FLOW_GUIDE_NG{n}[u G / T], G = {n_guide}, the flow holding ceil(j T / G) for
+// slice j, and steps forward while C_(f+1) <= u; it ends because C_N = T > u.
 static constexpr int64_t FLOW_COUNT_NG{n} = {len(flows)};
 static constexpr uint32_t FLOW_NG{n}[{len(flows)}] = {{{flow_tab}}};
 static constexpr uint64_t FLOW_CUM_NG{n}[{len(flows) + 1}] = {{{flow_cum}}};
+static constexpr uint16_t FLOW_GUIDE_NG{n}[{n_guide}] = {{{flow_guide}}};
 template <typename T>
 __device__ __forceinline__ void flow_factors_ng{n}(uint64_t event, uint64_t seed, uint32_t iter,
                                                   T* __restrict__ cf, int lane)
@@ -1295,15 +1309,11 @@ __device__ __forceinline__ void flow_factors_ng{n}(uint64_t event, uint64_t seed
     philox4x32_10((uint32_t)event, (uint32_t)(event >> 32), iter, 0x80000001u, (uint32_t)seed,
                   (uint32_t)(seed >> 32), r);
     const uint64_t k = ((((uint64_t)r[0]) << 32) | (uint64_t)r[1]) >> 11;
-    const uint64_t u = __umul64hi(k << 11, FLOW_CUM_NG{n}[FLOW_COUNT_NG{n}]);
-    int64_t lo = 0, hi = FLOW_COUNT_NG{n};
-    while (hi - lo > 1) {{
-        const int64_t mid = (lo + hi) >> 1;
-        if (FLOW_CUM_NG{n}[mid] <= u)
-            lo = mid;
-        else
-            hi = mid;
-    }}
+    constexpr uint64_t kTotal = FLOW_CUM_NG{n}[FLOW_COUNT_NG{n}];
+    const uint64_t u = __umul64hi(k << 11, kTotal);
+    int lo = FLOW_GUIDE_NG{n}[u * {n_guide}ull / kTotal];
+    while (FLOW_CUM_NG{n}[lo + 1] <= u)
+        ++lo;
     const uint32_t f = FLOW_NG{n}[lo];
     if (lane == 0)
         cf[{len(perms)}] = (T)((double)FLOW_CUM_NG{n}[FLOW_COUNT_NG{n}]

@@ -1,6 +1,7 @@
 """GPU parity of the Monte Carlo over colour flows (colour = "flow": one
 colour flow per event, drawn from the flows with a non-vanishing factor with
-Philox block 0x80000001) against the oracle, its unbiasedness against the
+probability proportional to its colour weight, from Philox block 0x80000001)
+against the oracle, its unbiasedness against the
 full colour sum on the same events, and its variance against the sampling
 of adjoint indices."""
 import math
