@@ -597,6 +597,11 @@ double mfo_me2_sum_sampled(int n_g, const double *p, double m, double width, int
 {
     double c[2 * 120];
     int64_t count;
+    if (kappa)
+        *kappa = NAN;
+    if ((mode != 2 && mode != 3) || n_g < 2 || n_g > MFO_MAX_G || cfg < 0 ||
+        cfg >= (mode == 2 ? mfo_colour_count(n_g) : mfo_flow_count(n_g)))
+        return NAN;
     if (mode == 2) {
         mfo_colour_factors(n_g, cfg, c);
         count = mfo_colour_count(n_g);
@@ -730,6 +735,8 @@ int64_t mfo_flow_config(int n_g, uint64_t seed, uint32_t iter, uint64_t event)
     uint32_t r[4];
     mfo_philox4x32_10(ctr, key, r);
     uint64_t k = ((((uint64_t)r[0]) << 32) | (uint64_t)r[1]) >> 11;
+    if (mfo_flow_count(n_g) < 0)
+        return -1;
     uint64_t u = (uint64_t)(((unsigned __int128)k * (uint64_t)mfo_flow_total(n_g)) >> 53);
     /* the flow whose weight interval [C_idx, C_idx+1) holds u */
     int64_t lo = 0, hi = mfo_flow_count(n_g);
@@ -745,10 +752,15 @@ int64_t mfo_flow_config(int n_g, uint64_t seed, uint32_t iter, uint64_t event)
 
 void mfo_flow_factors(int n_g, int64_t idx, double *c)
 {
+    int64_t code = mfo_flow_code(n_g, idx);
+    if (code < 0) {
+        c[0] = NAN;                            /* n_g or idx out of range */
+        return;
+    }
     int nperm = mfo_n_orderings(n_g);
     int perm[120 * MFO_MAX_G];
     mfo_orderings(n_g, perm);
-    flow_factors_of_code(n_g, mfo_flow_code(n_g, idx), perm, nperm, c);
+    flow_factors_of_code(n_g, code, perm, nperm, c);
 }
 
 double mfo_me2_sum_colour_flow(int n_g, const double *p, double m, double width, int64_t idx)

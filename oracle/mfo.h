@@ -179,7 +179,10 @@ double mfo_me2_sum_colour_flow(int n_g, const double *p, double m, double width,
  * cfg) and, if kappa is not NULL, its condition number
  * kappa = sum_h |M_h| sum_sigma |c_sigma A_sigma,h| / sum_h |M_h|^2 (>= 1;
  * 0 if the sum vanishes): cancellations between orderings magnify relative
- * rounding errors of the partial amplitudes by up to 2 kappa.              */
+ * rounding errors of the partial amplitudes by up to 2 kappa.  NaN (and
+ * kappa NaN) for a mode other than 2 and 3, n_g outside 2..4 or cfg out of
+ * range; mfo_flow_config returns -1 and mfo_flow_factors sets c[0] = NaN for
+ * an n_g or index out of range.                                            */
 double mfo_me2_sum_sampled(int n_g, const double *p, double m, double width, int mode, int64_t cfg,
                            double *kappa);
 

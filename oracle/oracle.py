@@ -46,10 +46,15 @@ class _Result(C.Structure):
 
 
 def build(force: bool = False) -> str:
-    """Compile libmfo.so with the oracle's Makefile (plain gcc)."""
-    if force or not os.path.exists(_LIB_PATH) or _stale():
-        subprocess.run(["make", "-C", _HERE, "-B" if force else "-s", "libmfo.so"],
-                       check=True, capture_output=True)
+    """Compile libmfo.so with the oracle's Makefile (plain gcc).  An exclusive
+    lock on a file beside it keeps concurrent test processes from building
+    (and loading a half-written library) at the same time."""
+    import fcntl
+    with open(os.path.join(_HERE, ".build.lock"), "w") as lk:
+        fcntl.flock(lk, fcntl.LOCK_EX)
+        if force or not os.path.exists(_LIB_PATH) or _stale():
+            subprocess.run(["make", "-C", _HERE, "-B" if force else "-s", "libmfo.so"],
+                           check=True, capture_output=True)
     return _LIB_PATH
 
 

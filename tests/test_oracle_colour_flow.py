@@ -192,3 +192,13 @@ def test_condition_number_of_the_sampled_sums():
     v, kappa = O.me2_sum_sampled(4, p, M, 1.5, 2, 12345)
     assert v == pytest.approx(O.me2_sum_colour_config(4, p, M, 1.5, 12345), rel=1e-15, abs=1e-300)
     assert kappa == 0.0 or kappa >= 1.0 - 1e-14
+
+
+def test_out_of_range_arguments_are_rejected():
+    p = random_momenta(3, 1000.0, np.random.default_rng(4))
+    assert O.flow_config(5, 0, 0, 1) == -1
+    assert math.isnan(O.flow_factors(3, O.flow_count(3))[0])
+    assert math.isnan(O.flow_factors(3, -1)[0])
+    for mode, cfg in ((4, 0), (3, O.flow_count(3)), (2, O.colour_count(3)), (3, -1)):
+        v, kappa = O.me2_sum_sampled(3, p, M, 1.5, mode, cfg)
+        assert math.isnan(v) and math.isnan(kappa)
