@@ -5,7 +5,7 @@ benchmark import this package.  The product library never does.
 """
 from .oracle import (  # noqa: F401
     Process, EventInfo, build, lib, philox4x32_10, event_k53, bin_from_k53,
-    vegas_map, vegas_refine, massless_volume, phase_space, pdf_xf,
+    vegas_map, vegas_refine, massless_volume, phase_space, cuts, pdf_xf,
     colour_matrix, orderings, partial_amplitudes, me2_sum, me2_sum_hel,
     me2_sum_fullcolour, event_weight, event_weight_y, integrate, combine,
     neumaier_sum, ttx_dweight_dmt_analytic, n_dims, all_helicities,

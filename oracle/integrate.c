@@ -196,13 +196,18 @@ double mfo_event_weight_y(const mfo_process *proc, double sqrt_s,
     return weight_from_x(proc, sqrt_s, pdf, jac, ev);
 }
 
-/* Inverse-variance weighted mean of the iteration estimates. */
+/* Inverse-variance weighted mean of the iteration estimates: iterations
+ * with V_j > 0 enter with weight 1/V_j; sigma_I = (sum 1/V_j)^(-1/2);
+ * chi^2/dof = sum (I_j - I)^2 / V_j / (n_used - 1).  Any n_iter. */
 void mfo_combine(int n_iter, const double *I, const double *V,
                  double *sigma, double *err, double *chi2_dof)
 {
-    double num[256], den[256];
+    int cap = n_iter > 0 ? n_iter : 1;
+    double *num = malloc(sizeof(double) * (size_t)cap);
+    double *den = malloc(sizeof(double) * (size_t)cap);
+    double *chi = malloc(sizeof(double) * (size_t)cap);
     int n = 0;
-    for (int j = 0; j < n_iter && n < 256; ++j) {
+    for (int j = 0; j < n_iter; ++j) {
         if (V[j] > 0.0) {
             num[n] = I[j] / V[j];
             den[n] = 1.0 / V[j];
@@ -213,19 +218,20 @@ void mfo_combine(int n_iter, const double *I, const double *V,
         *sigma = n_iter > 0 ? I[n_iter - 1] : 0.0;
         *err = 0.0;
         *chi2_dof = 0.0;
-        return;
+    } else {
+        double snum = mfo_neumaier_sum(n, num), sden = mfo_neumaier_sum(n, den);
+        double mean = snum / sden;
+        *sigma = mean;
+        *err = 1.0 / sqrt(sden);
+        int k = 0;
+        for (int j = 0; j < n_iter; ++j)
+            if (V[j] > 0.0)
+                chi[k++] = (I[j] - mean) * (I[j] - mean) / V[j];
+        *chi2_dof = n > 1 ? mfo_neumaier_sum(k, chi) / (double)(n - 1) : 0.0;
     }
-    double snum = mfo_neumaier_sum(n, num), sden = mfo_neumaier_sum(n, den);
-    double mean = snum / sden;
-    *sigma = mean;
-    *err = 1.0 / sqrt(sden);
-    double chi[256];
-    int k = 0;
-    for (int j = 0; j < n_iter && k < 256; ++j)
-        if (V[j] > 0.0) {
-            chi[k++] = (I[j] - mean) * (I[j] - mean) / V[j];
-        }
-    *chi2_dof = n > 1 ? mfo_neumaier_sum(k, chi) / (double)(n - 1) : 0.0;
+    free(num);
+    free(den);
+    free(chi);
 }
 
 typedef struct {
@@ -268,7 +274,7 @@ int mfo_integrate(const mfo_process *proc, double sqrt_s, const mfo_pdf_grid *pd
                   double *grid, double *iter_sigma, double *iter_var,
                   double *hist_last, double *weights_last, mfo_result *res)
 {
-    if (n_events < 2 || n_iter < 1 || n_bins < 2 || n_bins > 1024 || n_threads < 1)
+    if (n_events < 2 || n_iter < 1 || n_iter > 256 || n_bins < 2 || n_bins > 1024 || n_threads < 1)
         return -1;
     int D = mfo_n_dims(proc->n_g);
     double *I = calloc((size_t)n_iter, sizeof(double));

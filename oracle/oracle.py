@@ -285,6 +285,16 @@ def phase_space(n_f, masses, sqrt_shat, r, max_newton=50):
     return k, w.value, st
 
 
+def cuts(proc: Process, k, y_boost):
+    """Fiducial cuts on the final-state gluons of momenta k [n_f][4] (partonic CM
+    frame, slots t, tbar, gluons); returns (passed, near_edge)."""
+    k = _f64(k)
+    near = C.c_int()
+    pc = proc.c()
+    ok = lib().mfo_cuts(C.byref(pc), k.shape[0], _d(k), y_boost, C.byref(near))
+    return bool(ok), bool(near.value)
+
+
 def pdf_xf(table, x, q2):
     h = _PdfHandle(table)
     return lib().mfo_pdf_xf(C.byref(h.c), x, q2)
