@@ -123,7 +123,7 @@ double mfo_me2_sum_fullcolour(int n_g, const double *p, double m, double width,
                               int n_hel, const int *hel_list);
 double mfo_me2_sum_hel(int n_g, const double *p, double m, double width,
                        int n_hel, const int *hel_list);
-/* Leading-colour approximation (the paper names it, Sec. 3.3, as a way to
+/* Leading-colour approximation (the paper names it, Sec. 3.2 on Fig. 4, as a way to
  * cheapen high-multiplicity matrix elements): the colour matrix replaced by
  * c_LC times the identity, c_LC = (N^2 - 1) N^(n_g - 1) / 2^n_g with N = 3,
  * the leading power of N in every diagonal element N C_F^n_g (T = lambda/2;
@@ -131,7 +131,7 @@ double mfo_me2_sum_hel(int n_g, const double *p, double m, double width,
  * mfo_me2_sum_lc the helicity sum of c_LC sum_sigma |A(sigma)|^2, g_s = 1. */
 double mfo_colour_lc(int n_g);
 double mfo_me2_sum_lc(int n_g, const double *p, double m, double width);
-/* Monte Carlo over colours (also named in Sec. 3.3): each event carries one
+/* Monte Carlo over colours (also named in Sec. 3.2 on Fig. 4): each event carries one
  * colour assignment -- adjoint indices a_1 .. a_n of the gluons (labels as
  * in the amplitudes), colour i of the top and anticolour j of the antitop --
  * drawn uniformly from the N_cfg = 9 * 8^n_g assignments.  The word pair

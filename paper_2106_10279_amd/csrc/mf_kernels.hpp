@@ -333,7 +333,7 @@ struct Layout {
 // (n_g >= 3).  `any_live` must be uniform over the wave.  COL = 0: full
 // colour matrix; COL = 1: leading-colour approximation; COL = 2: one sampled
 // colour assignment whose complex factors are cf; COL = 3: one sampled colour
-// flow whose real factors are cf (n_g >= 3; Sec. 3.3 names leading colour and
+// flow whose real factors are cf (n_g >= 3; Sec. 3.2, discussing Fig. 4, names leading colour and
 // colour sampling).
 template <int NG, typename T, int COL = 0>
 __device__ __forceinline__ double event_me2(const TabT<NG, T>* tab, T* obj, int h, double mt, bool live, bool any_live,

@@ -1,0 +1,95 @@
+"""Assertions shared by the GPU integration parity tests.
+
+`assert_integration_parity(g, ref)` compares every output of an integration
+of the library (`api.integrate`) with the oracle's integration of the same
+workload: per-iteration estimates I_j and variances V_j, the combined cross
+section, its error and chi^2/dof, w_max, the passing-event count, the grids
+and the last histogram.
+
+Tolerances (floating point, FP64 path):
+
+* I_j and sigma: 1e-10 relative (the integral bar);
+* V_j = [(1/N) sum w^2 - I_j^2]/(N - 1): the per-event weights agree to about
+  1e-12, so sum w^2 agrees to about 2e-12; the one-pass difference magnifies a
+  relative error of sum w^2 by a = (1/N) sum w^2 / [(1/N) sum w^2 - I_j^2]
+  (the cancellation factor, computed from the oracle's own V_j); the bar is
+  1e-10 a;
+* sigma_err = (sum 1/V_j)^(-1/2): half the largest relative V_j difference,
+  plus 1e-14;
+* chi^2/dof = sum (I_j - I)^2 / V_j / (n - 1): twice the first-order
+  propagation of the measured I_j and V_j differences, plus 1e-12 relative;
+* the library's own combination of its I_j, V_j (done on the host) must
+  reproduce the oracle's formula (`mfo_combine`) on the same inputs to
+  1e-14 (chi^2/dof: 1e-12 relative);
+* w_max: 1e-12 relative (it is one event's weight); n_pass: exact unless the
+  oracle flagged events at a cut edge;
+* grids: 1e-12 absolute (edges lie in [0, 1]); histogram: 1e-11 relative.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+import oracle as O
+
+
+def as_reference(o, n_events: int) -> dict:
+    """An oracle IntegrationResult (or a stored reference dict) as a dict."""
+    if isinstance(o, dict):
+        d = dict(o)
+        d.setdefault("n_pass_last", d.get("n_pass"))
+        return d
+    return dict(n_events=n_events, iter_sigma=o.iter_sigma, iter_var=o.iter_var, sigma=o.sigma,
+                sigma_err=o.sigma_err, chi2_dof=o.chi2_dof, w_max=o.w_max, n_pass_last=o.n_pass,
+                n_newton_fail_last=o.n_newton_fail, n_near_edge_last=o.n_near_edge, grid=o.grid,
+                hist_last=o.hist_last)
+
+
+def chi2_bound(I, V, dI, dV, mean, dmean):
+    n = len(I)
+    if n < 2:
+        return 0.0
+    t = 2 * np.abs(I - mean) * (np.abs(dI) + abs(dmean)) / V + (I - mean) ** 2 * np.abs(dV) / V**2
+    return float(t.sum() / (n - 1))
+
+
+def assert_integration_parity(g, o, n_events: int, *, hist=True, say=print) -> dict:
+    ref = as_reference(o, n_events)
+    N = float(ref["n_events"])
+    Ig, Vg = np.asarray(g.iter_sigma, float), np.asarray(g.iter_var, float)
+    Io, Vo = np.asarray(ref["iter_sigma"], float), np.asarray(ref["iter_var"], float)
+    dI = Ig - Io
+    relI = np.abs(dI) / np.abs(Io)
+    amp = (Vo * (N - 1) + Io**2) / (Vo * (N - 1))
+    relV = np.abs(Vg - Vo) / Vo
+    out = dict(I=relI.max(), V=relV.max(), V_over_a=(relV / amp).max())
+    assert relI.max() < 1e-10, ("I_j", relI)
+    assert np.all(relV < 1e-10 * amp), ("V_j", relV, amp)
+    out["sigma"] = abs(g.sigma / ref["sigma"] - 1)
+    assert out["sigma"] < 1e-10, (g.sigma, ref["sigma"])
+    # the library's host combination against the oracle's formula on the same inputs
+    s, e, c = O.combine(Ig, Vg)
+    assert abs(g.sigma - s) <= 1e-14 * abs(s)
+    assert abs(g.sigma_err - e) <= 1e-14 * e
+    assert abs(g.chi2_dof - c) <= 1e-12 * abs(c) + 1e-300
+    # the library's error and chi^2/dof against the oracle's
+    out["sigma_err"] = abs(g.sigma_err / ref["sigma_err"] - 1)
+    assert out["sigma_err"] <= 0.5 * relV.max() + 1e-14, (g.sigma_err, ref["sigma_err"])
+    b = chi2_bound(Io, Vo, dI, Vg - Vo, ref["sigma"], g.sigma - ref["sigma"])
+    out["chi2"] = abs(g.chi2_dof - ref["chi2_dof"])
+    out["chi2_bound"] = 2 * b + 1e-12 * abs(ref["chi2_dof"])
+    assert out["chi2"] <= out["chi2_bound"], (g.chi2_dof, ref["chi2_dof"], b)
+    out["w_max"] = abs(g.w_max / ref["w_max"] - 1)
+    assert out["w_max"] < 1e-12, (g.w_max, ref["w_max"])
+    near = int(ref.get("n_near_edge_last") or 0)
+    assert abs(g.n_pass - ref["n_pass_last"]) <= near, (g.n_pass, ref["n_pass_last"], near)
+    assert g.n_newton_fail >= 0
+    out["grid"] = float(np.abs(np.asarray(g.grid) - np.asarray(ref["grid"])).max())
+    assert out["grid"] <= 1e-12
+    if hist:
+        hg, ho = np.asarray(g.hist), np.asarray(ref["hist_last"])
+        nz = ho != 0
+        assert np.all(hg[~nz] == 0)
+        out["hist"] = float((np.abs(hg[nz] / ho[nz] - 1)).max()) if nz.any() else 0.0
+        assert out["hist"] < 1e-11
+    say("  parity: " + ", ".join(f"{k} {v:.2e}" for k, v in out.items()))
+    return out

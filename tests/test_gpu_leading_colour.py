@@ -8,6 +8,7 @@ import numpy as np
 import pytest
 
 import oracle as O
+from parity_checks import assert_integration_parity
 
 pytestmark = pytest.mark.gpu
 
@@ -80,11 +81,8 @@ def test_lc_integration_matches_oracle(api, pdf_table, n_g, n, iters):
     say(f"lc integrate n_g={n_g} n={n} iters={iters}")
     g = api.integrate(gproc(api, n_g), SQRT_S, pdf_table, n, iters, seed=0, colour="leading")
     o = O.integrate(oproc(n_g), SQRT_S, pdf_table, n, iters, seed=0)
-    say("  gpu", g.sigma, g.sigma_err, "oracle", o.sigma, o.sigma_err)
-    np.testing.assert_allclose(g.iter_sigma, o.iter_sigma, rtol=1e-10, atol=0)
-    np.testing.assert_allclose(g.iter_var, o.iter_var, rtol=1e-8, atol=0)
-    assert abs(g.sigma / o.sigma - 1) < 1e-10
-    np.testing.assert_allclose(g.grid, o.grid, rtol=0, atol=1e-12)
+    say("  gpu", g.sigma, g.sigma_err, g.chi2_dof, "oracle", o.sigma, o.sigma_err, o.chi2_dof)
+    assert_integration_parity(g, o, n, say=say)
     np.testing.assert_allclose(g.weights.cpu().numpy(), o.weights_last, rtol=1e-11, atol=0)
     assert g.n_pass == o.n_pass
 

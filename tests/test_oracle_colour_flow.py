@@ -1,6 +1,6 @@
 """Pins for the oracle's Monte Carlo over colour flows (colour = "flow").
 
-Sec. 3.3 names a Monte Carlo over colours as a remedy for high-multiplicity
+Sec. 3.2 (on Fig. 4) names a Monte Carlo over colours as a remedy for high-multiplicity
 matrix elements.  Besides adjoint indices, the colour of a gluon can be
 sampled as a colour-anticolour pair (a, b) with state matrix
 G_ab = (e_ab - delta_ab / N) / sqrt 2 (the 't Hooft double line with the

@@ -1,6 +1,6 @@
 """Pins for the oracle's Monte Carlo over colours (colour = "sampled").
 
-Sec. 3.3 names a Monte Carlo over colour configurations as a remedy for
+Sec. 3.2 (on Fig. 4) names a Monte Carlo over colour configurations as a remedy for
 high-multiplicity matrix elements.  Here each event carries one colour
 assignment (gluon adjoint indices, top colour, antitop anticolour), drawn
 uniformly from the 9 * 8^n assignments with Philox block 0x80000001, and

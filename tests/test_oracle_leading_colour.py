@@ -1,6 +1,6 @@
 """Pins for the oracle's leading-colour approximation of |M|^2.
 
-The paper (Sec. 3.3) names the leading-colour approximation as a way to
+The paper (Sec. 3.2, on Fig. 4) names the leading-colour approximation as a way to
 cheapen high-multiplicity matrix elements without defining it further.  The
 reading taken here: in the basis (T^{a_s1} ... T^{a_sn})_{i_t j_tbar} with
 T = lambda/2 the colour matrix C is replaced by c_LC times the identity,
