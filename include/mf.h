@@ -48,12 +48,12 @@ typedef enum { MF_GG_TTX = 0, MF_GG_TTXG = 1, MF_GG_TTXGG = 2 } mf_process_id;
 typedef enum { MF_FP64 = 0, MF_FP32_KAHAN = 1 } mf_precision;
 
 /* Colour sum of |M|^2.  MF_COLOUR_LEADING is the leading-colour
- * approximation that Sec. 3.3 names for high multiplicities: in the colour
+ * approximation that Sec. 3.2 names for high multiplicities (on Fig. 4): in the colour
  * basis (T^{a_s1} ... T^{a_sn})_{i_t j_tbar}, T = lambda/2, the colour matrix
  * is replaced by c_LC = (N^2 - 1) N^(n_g - 1) / 2^n_g (N = 3: 6, 9, 13.5)
  * times the identity, the leading power of N of its diagonal; it changes the
  * integrand (by O(1/N^2)), not only its variance. */
-/* MF_COLOUR_SAMPLED is the Monte Carlo over colours that Sec. 3.3 names as
+/* MF_COLOUR_SAMPLED is the Monte Carlo over colours that Sec. 3.2 names as
  * well: every event carries one colour assignment (gluon adjoint indices,
  * top colour, antitop anticolour), drawn uniformly from the N_cfg = 9 8^n_g
  * assignments with Philox block 0x80000001 of its counter (the integrand

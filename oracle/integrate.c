@@ -96,6 +96,7 @@ static double weight_from_x(const mfo_process *proc, double sqrt_s,
     ev->near_edge = 0;
     ev->ill_conditioned = 0;
     ev->colour_kappa = 0.0;
+    ev->newton_kappa = 0.0;
     ev->ps_weight = ev->f1 = ev->f2 = ev->me2 = 0.0;
     ev->w = 0.0;
     memset(ev->k, 0, sizeof(ev->k));
@@ -113,6 +114,20 @@ static double weight_from_x(const mfo_process *proc, double sqrt_s,
         return 0.0;
     }
     ev->ps_weight = W;
+    /* Condition number of the rescaling root xi (Sec. 2.4 massive step):
+     * F(xi) = sum_i sqrt(m_i^2 + xi^2 E_i^2) - sqrt(s_hat) is known only to
+     * its rounding (the residual floor of the Newton stop), so xi is fixed
+     * only to that over xi F'(xi) = sum_i |k_i|^2 / k_i^0, relative to
+     * sqrt(s_hat).  Close to threshold this becomes large (1 / beta^2 for
+     * t tbar). */
+    {
+        double den = 0.0;
+        for (int i = 0; i < n_f; ++i) {
+            double a2 = ev->k[i][1] * ev->k[i][1] + ev->k[i][2] * ev->k[i][2] + ev->k[i][3] * ev->k[i][3];
+            den += a2 / ev->k[i][0];
+        }
+        ev->newton_kappa = sqrt_shat / den;
+    }
 
     double y_boost = 0.5 * log(ev->x1 / ev->x2);
     int near_edge = 0;
@@ -353,6 +368,7 @@ typedef struct {
     const uint64_t *ids;
     double *w;
     int *flags;
+    double *kappa;
 } list_worker;
 
 static void *run_list(void *arg)
@@ -363,14 +379,17 @@ static void *run_list(void *arg)
         lw->w[i] = mfo_event_weight(lw->proc, lw->sqrt_s, lw->pdf, lw->n_bins, lw->grid, lw->seed,
                                     lw->iter, lw->ids[i], &ev);
         lw->flags[i] = ev.pass_threshold | ev.newton_fail << 1 | ev.pass_cuts << 2 | ev.near_edge << 3
-                       | ev.ill_conditioned << 4 | (ev.colour_kappa > 50.0) << 5;
+                       | ev.ill_conditioned << 4 | (ev.colour_kappa > 50.0) << 5
+                       | (ev.newton_kappa > 1e3) << 6;
+        if (lw->kappa)
+            lw->kappa[i] = ev.newton_kappa;
     }
     return NULL;
 }
 
 int mfo_event_weights(const mfo_process *proc, double sqrt_s, const mfo_pdf_grid *pdf, int n_bins,
                       const double *grid, uint64_t seed, int iter, uint64_t n, const uint64_t *ids,
-                      int n_threads, double *w, int *flags)
+                      int n_threads, double *w, int *flags, double *newton_kappa)
 {
     if (n_threads < 1)
         return -1;
@@ -390,6 +409,7 @@ int mfo_event_weights(const mfo_process *proc, double sqrt_s, const mfo_pdf_grid
         x->ids = ids;
         x->w = w;
         x->flags = flags;
+        x->kappa = newton_kappa;
         pthread_create(&th[t], NULL, run_list, x);
     }
     for (int t = 0; t < n_threads; ++t)

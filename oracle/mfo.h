@@ -74,6 +74,10 @@ typedef struct {
     int    ill_conditioned;    /* |d ln(x g) / d ln x| > 1e3 at x1 or x2      */
     int64_t colour_cfg;        /* colour = 2, 3: the event's assignment, flow   */
     double colour_kappa;       /* colour = 2, 3: condition number of the sum   */
+    double newton_kappa;       /* condition number of the mass-rescaling root:
+                                  sqrt(s_hat) / (xi F'(xi)) = sqrt(s_hat) /
+                                  sum_i |k_i|^2 / E_i (1 for massless momenta,
+                                  1 / beta^2 for t tbar); 0 below threshold */
 } mfo_event;
 
 typedef struct {
@@ -212,10 +216,12 @@ int mfo_lab_event(const mfo_process *proc, double sqrt_s, int n_bins, const doub
 /* Weights w[i] of events ids[i] of iteration iter on n_threads threads;
  * flags[i]: bit 0 above threshold, bit 1 Newton failed, bit 2 passed the
  * cuts, bit 3 near a cut edge, bit 4 ill-conditioned PDF value, bit 5
- * sampled colour sum with condition number colour_kappa > 50.             */
+ * sampled colour sum with condition number colour_kappa > 50, bit 6
+ * mass-rescaling root with condition number newton_kappa > 1e3 (written to
+ * newton_kappa[i] unless it is NULL).                                      */
 int mfo_event_weights(const mfo_process *proc, double sqrt_s, const mfo_pdf_grid *pdf, int n_bins,
                       const double *grid, uint64_t seed, int iter, uint64_t n, const uint64_t *ids,
-                      int n_threads, double *w, int *flags);
+                      int n_threads, double *w, int *flags, double *newton_kappa);
 
 int mfo_integrate(const mfo_process *proc, double sqrt_s, const mfo_pdf_grid *pdf,
                   uint64_t n_events, int n_iter, uint64_t seed, int start_iter,

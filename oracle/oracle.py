@@ -36,7 +36,8 @@ class _Event(C.Structure):
                 ("f2", C.c_double), ("me2", C.c_double), ("w", C.c_double),
                 ("k", C.c_double * 16), ("pass_threshold", C.c_int), ("pass_cuts", C.c_int),
                 ("newton_fail", C.c_int), ("near_edge", C.c_int), ("ill_conditioned", C.c_int),
-                ("colour_cfg", C.c_int64), ("colour_kappa", C.c_double)]
+                ("colour_cfg", C.c_int64), ("colour_kappa", C.c_double),
+                ("newton_kappa", C.c_double)]
 
 
 class _Result(C.Structure):
@@ -153,7 +154,8 @@ def lib():
                                     C.c_int, C.c_uint64, _dp]
         L.mfo_lab_event.restype = C.c_int
         L.mfo_event_weights.argtypes = [C.POINTER(_Process), C.c_double, C.POINTER(_Pdf), C.c_int, _dp,
-                                        C.c_uint64, C.c_int, C.c_uint64, _u64p, C.c_int, _dp, _ip]
+                                        C.c_uint64, C.c_int, C.c_uint64, _u64p, C.c_int, _dp, _ip,
+                                        _dp]
         L.mfo_event_weights.restype = C.c_int
         _lib = L
     return _lib
@@ -218,6 +220,7 @@ class EventInfo:
     near_edge: bool
     ill_conditioned: bool
     colour_kappa: float = 0.0
+    newton_kappa: float = 0.0
 
 
 def _event_info(ev, D):
@@ -225,7 +228,7 @@ def _event_info(ev, D):
                      ev.shat, ev.ps_weight, ev.f1, ev.f2, ev.me2, ev.w,
                      np.array(ev.k[:]).reshape(4, 4), bool(ev.pass_threshold),
                      bool(ev.pass_cuts), bool(ev.newton_fail), bool(ev.near_edge),
-                     bool(ev.ill_conditioned), ev.colour_kappa)
+                     bool(ev.ill_conditioned), ev.colour_kappa, ev.newton_kappa)
 
 
 def n_dims(n_g: int) -> int:
@@ -538,11 +541,14 @@ def lab_event(proc: Process, sqrt_s, grid, seed, it, event):
     return p, st
 
 
-def event_weights(proc: Process, sqrt_s, table, grid, seed, it, ids, n_threads=None):
+def event_weights(proc: Process, sqrt_s, table, grid, seed, it, ids, n_threads=None,
+                  return_kappa=False):
     """Weights of the events `ids` of iteration `it`, threaded; returns (w, flags)
     with flags bit 0 above threshold, 1 Newton failed, 2 passed the cuts,
     3 near a cut edge, 4 ill-conditioned PDF value, 5 sampled colour sum
-    with condition number above 50 (EventInfo.colour_kappa gives it)."""
+    with condition number above 50 (EventInfo.colour_kappa gives it), 6
+    mass-rescaling root with condition number above 1e3.  With
+    return_kappa=True also returns that condition number per event."""
     h = _PdfHandle(table)
     grid = _f64(grid)
     ids = np.ascontiguousarray(ids, dtype=np.uint64)
@@ -551,7 +557,8 @@ def event_weights(proc: Process, sqrt_s, table, grid, seed, it, ids, n_threads=N
     w = np.zeros(len(ids))
     flags = np.zeros(len(ids), dtype=np.int32)
     pc = proc.c()
+    kappa = np.zeros(len(ids))
     lib().mfo_event_weights(C.byref(pc), sqrt_s, C.byref(h.c), grid.shape[1] - 1, _d(grid), seed, it,
                             len(ids), ids.ctypes.data_as(_u64p), n_threads, _d(w),
-                            flags.ctypes.data_as(_ip))
-    return w, flags
+                            flags.ctypes.data_as(_ip), _d(kappa))
+    return (w, flags, kappa) if return_kappa else (w, flags)

@@ -32,6 +32,16 @@ import numpy as np
 import oracle as O
 
 
+def newton_bar(kappa, n_f):
+    """Per-event bar for an event whose mass-rescaling root is ill-conditioned
+    (oracle flag bit 6, kappa_N = sqrt(s_hat) / (xi F'(xi)) > 1e3, close to
+    threshold).  The Newton stop accepts any xi whose residual is below
+    2 n_f 2^-52 sqrt(s_hat), which fixes xi only to 4 n_f 2^-53 kappa_N
+    relative; the two sides may stop anywhere inside that (factor 2), and the
+    weight depends on xi at most like xi^(2 n_f) (factor 2 n_f)."""
+    return 1e-12 + 16 * n_f * n_f * 2.0**-53 * np.asarray(kappa)
+
+
 def as_reference(o, n_events: int) -> dict:
     """An oracle IntegrationResult (or a stored reference dict) as a dict."""
     if isinstance(o, dict):

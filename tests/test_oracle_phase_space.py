@@ -97,3 +97,44 @@ def test_three_body_massive_volume_matches_dalitz_quadrature():
 def test_newton_failure_is_reported():
     k, w, st = O.phase_space(3, [M, M, 0.0], 600.0, np.full(5, 0.3), max_newton=0)
     assert st == 1 and w == 0.0
+
+
+def test_newton_condition_number_closed_forms(pdf_table):
+    """kappa_N = sqrt(s_hat) / (xi F'(xi)) of the mass-rescaling root.  For
+    t tbar it is 1 / beta^2 = s_hat / (s_hat - 4 m^2) (both momenta have
+    |k| = beta sqrt(s_hat) / 2 and E = sqrt(s_hat) / 2); for (nearly)
+    massless tops the rescaling is the identity and kappa_N -> 1 for any
+    number of particles, so a dropped or doubled term of the sum shows."""
+    grid4 = np.tile(np.arange(51) / 50, (4, 1))
+    seen = 0
+    for e in range(400):
+        _, ev = O.event_weight(O.Process(n_g=2), 13000.0, pdf_table, grid4, 11, 0, e)
+        if not ev.pass_threshold or ev.newton_fail:
+            assert ev.newton_kappa == 0.0 or ev.pass_threshold
+            continue
+        beta2 = 1.0 - 4.0 * 173.0**2 / ev.shat
+        assert ev.newton_kappa == pytest.approx(1.0 / beta2, rel=1e-9 / beta2)
+        seen += 1
+    assert seen > 100
+    for n_g in (2, 3, 4):
+        D = 3 * n_g - 2
+        grid = np.tile(np.arange(51) / 50, (D, 1))
+        p = O.Process(n_g=n_g, m_top=1e-3)
+        for e in range(50):
+            _, ev = O.event_weight(p, 13000.0, pdf_table, grid, 5, 0, e)
+            if ev.pass_threshold and not ev.newton_fail:
+                # m^2 / E^2 corrections only
+                assert abs(ev.newton_kappa - 1.0) < 1e-6, (n_g, e, ev.newton_kappa)
+
+
+def test_newton_condition_number_flag(pdf_table):
+    """Bit 6 of the event flags marks kappa_N > 1e3, and event_weights
+    returns the same kappa_N as the single-event call."""
+    grid4 = np.tile(np.arange(51) / 50, (4, 1))
+    ids = np.arange(3000)
+    w, fl, kap = O.event_weights(O.Process(n_g=2), 13000.0, pdf_table, grid4, 0, 0, ids,
+                                 return_kappa=True)
+    for e in (0, 7, 1234):
+        _, ev = O.event_weight(O.Process(n_g=2), 13000.0, pdf_table, grid4, 0, 0, e)
+        assert kap[e] == ev.newton_kappa
+    assert np.array_equal((fl & 64) != 0, kap > 1e3)
