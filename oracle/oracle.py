@@ -9,7 +9,9 @@ from dataclasses import dataclass
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_HERE, "libmfo.so")
+# MFO_LIB names another build of the same sources (the reference writer's
+# contracted build, libmfo_fma.so); it is loaded as it is, without building.
+_LIB_PATH = os.environ.get("MFO_LIB") or os.path.join(_HERE, "libmfo.so")
 _lib = None
 
 _dp = C.POINTER(C.c_double)
@@ -51,6 +53,8 @@ def build(force: bool = False) -> str:
     lock on a file beside it keeps concurrent test processes from building
     (and loading a half-written library) at the same time."""
     import fcntl
+    if os.environ.get("MFO_LIB"):
+        return _LIB_PATH
     with open(os.path.join(_HERE, ".build.lock"), "w") as lk:
         fcntl.flock(lk, fcntl.LOCK_EX)
         if force or not os.path.exists(_LIB_PATH) or _stale():

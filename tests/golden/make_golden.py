@@ -19,7 +19,19 @@ all iterations), so that every iteration's counts and the grid of the last
 iteration are known.  The oracle runs on 8 threads; the
 thread count changes the grids only at the rounding level.
 
-Run from the repository root:  python tests/golden/make_golden.py [name ...]
+Rounding drift (``--drift``, added to an existing file): the same
+integration with the oracle's sources built with fused multiply-add
+contraction (``oracle/Makefile`` target libmfo_fma.so), a second correct FP64
+implementation that differs only in rounding.  Bins do not move with the
+grid, but every weight depends on its bins' widths through J_V, and the next
+grid is refined from those weights, so after several iterations rounding
+differences in the grid grow well above 1e-12.  Stored under "drift": the
+largest relative differences of I_j, V_j, sigma, w_max and the last
+histogram, and the largest absolute difference of the final grid, between
+the two builds; and "w_max_event", the index of the last iteration's largest
+weight (plain build).
+
+Run from the repository root:  python tests/golden/make_golden.py [--drift] [name ...]
 """
 from __future__ import annotations
 
@@ -86,7 +98,54 @@ def run(name: str) -> dict:
     return out
 
 
+def contracted_run(name: str) -> dict:
+    """The integration of `run` on the contracted build, in a child process
+    (the build is chosen when the oracle's library is loaded)."""
+    import subprocess
+    subprocess.run(["make", "-C", os.path.join(ROOT, "oracle"), "-s", "libmfo_fma.so"], check=True)
+    env = dict(os.environ, MFO_LIB=os.path.join(ROOT, "oracle", "libmfo_fma.so"))
+    code = ("import json, sys; sys.path.insert(0, %r); import make_golden as M; "
+            "r = M.run(%r); print(json.dumps(r))" % (HERE, name))
+    out = subprocess.run([sys.executable, "-c", code], env=env, check=True, capture_output=True, text=True)
+    return json.loads(out.stdout.strip().splitlines()[-1])
+
+
+def drift(name: str) -> None:
+    path = os.path.join(HERE, name + ".json")
+    with open(path) as f:
+        ref = json.load(f)
+    alt = contracted_run(name)
+
+    def rel(a, b):
+        a, b = np.asarray(a, float), np.asarray(b, float)
+        nz = b != 0
+        return float(np.max(np.abs(a[nz] / b[nz] - 1))) if nz.any() else 0.0
+
+    ref["drift"] = dict(
+        build="oracle sources with -mfma -ffp-contract=fast", seconds=alt["seconds"],
+        I=rel(alt["iter_sigma"], ref["iter_sigma"]), V=rel(alt["iter_var"], ref["iter_var"]),
+        sigma=rel(alt["sigma"], ref["sigma"]), w_max=rel(alt["w_max"], ref["w_max"]),
+        hist=rel(alt["hist_last"], ref["hist_last"]),
+        grid=float(np.max(np.abs(np.asarray(alt["grid"]) - np.asarray(ref["grid"])))))
+    # the last iteration's largest weight: which event it is
+    c = CASES[name]
+    proc = O.Process(n_g=c["n_g"], **c["cuts"])
+    pdf = W.synthetic_pdf()
+    w, _ = O.event_weights(proc, W.SQRT_S, pdf, np.asarray(ref["grid_last"]), ref["seed"], ref["n_iter"] - 1,
+                           np.arange(ref["n_events"], dtype=np.uint64), n_threads=THREADS)
+    e = int(np.argmax(w))
+    assert w[e] == ref["w_max"]
+    ref["w_max_event"] = e
+    with open(path, "w") as f:
+        json.dump(ref, f)
+    print(f"{name}: drift {ref['drift']}, w_max event {e}", flush=True)
+
+
 def main(names):
+    if names and names[0] == "--drift":
+        for name in names[1:] or CASES:
+            drift(name)
+        return
     for name in names or CASES:
         out = run(name)
         path = os.path.join(HERE, name + ".json")
