@@ -260,6 +260,7 @@ def emit_coop_fill(n, tl, co):
     L = []
     w = L.append
     nsub = (1 << n) - 1
+    w("    constexpr int CW = 16 / (int)sizeof(T);")
     w("    const double m2 = mt * mt;")
     w(f"    if (lane >= 1 && lane <= {nsub}) {{")
     w("        const int m = lane;")
@@ -324,17 +325,17 @@ def emit_coop_fill(n, tl, co):
     w("    }")
     # incoming gluons along the beams: (0, 1, 0, 0) and (0, 0, 1, 0)
     w("    if (lane == 0) {")
-    w(f"        T* o = obj + {co.gj};")
-    w("        for (int i = 0; i < 16; ++i) o[i] = (T)0;")
-    w("        o[1] = (T)1; o[6] = (T)1; o[9] = (T)1; o[14] = (T)1;")
+    w(f"        st4s<NS>(obj + {co.gj}, (T)0, (T)1, (T)0, (T)0);")
+    w(f"        st4s<NS>(obj + {co.gj} + CW, (T)0, (T)0, (T)1, (T)0);")
+    w(f"        st4s<NS>(obj + {co.gj} + 2 * CW, (T)0, (T)1, (T)0, (T)0);")
+    w(f"        st4s<NS>(obj + {co.gj} + 3 * CW, (T)0, (T)0, (T)1, (T)0);")
     w("    }")
     w(f"    if (lane >= {nsub + 5} && lane < {nsub + 5 + 2 * (n - 2)}) {{")
     w(f"        const int t = lane - {nsub + 5};")
     w("        const int g = 2 + t / 2, h = t & 1;")
     w("        double e[4];")
     w("        linear_pol<double>(mom + 8 + 4 * (g - 2), h, e);")
-    w(f"        T* o = obj + {co.gj} + 4 * (2 * g + h);")
-    w("        for (int mu = 0; mu < 4; ++mu) o[mu] = (T)e[mu];")
+    w(f"        st4s<NS>(obj + {co.gj} + CW * (2 * g + h), (T)e[0], (T)e[1], (T)e[2], (T)e[3]);")
     w("    }")
     return "\n".join(L)
 
@@ -677,7 +678,10 @@ class CoopLayout:
        gluon currents j(s; hm) for every canonical ordered sequence s of
        length 1 .. n and helicity pattern hm of its gluons (sorted labels),
        4 T each; Ubar(a; s_t, h_a) and V(d; s_tbar, h_d), V(cd; s_tbar, h_c,
-       h_d), 8 T each (complex 4-spinors, re/im interleaved)."""
+       h_d), 8 T each (complex 4-spinors, re/im interleaved).  Each of the
+       four regions (currents, Ubar, V, two-gluon V) is stored chunk-major in
+       16-byte chunks (ld4s / ldspins): object i of a region starts CW i
+       values after the region's start, CW = 16 / sizeof(T)."""
 
     def __init__(self, n):
         self.n = n
@@ -697,6 +701,9 @@ class CoopLayout:
         self.pairs = sorted(itertools.permutations(range(n), 2)) if n >= 4 else []
         self.v2 = self.v1 + 8 * 4 * n
         self.size = self.v2 + 8 * 8 * len(self.pairs)
+        # objects per region: the chunk stride of the chunk-major layout
+        self.n_u1 = 4 * n
+        self.n_v2 = 8 * len(self.pairs)
 
     def obj(self, seq):
         c, sg = canon(seq)
@@ -792,6 +799,7 @@ def emit_coop(n, lay, co, K, den, perms):
     tables.append(f"static constexpr short KV1_{n}[{n}] = {{{kv_off}}};")
 
     # ---- stages ----
+    w("    constexpr int CW = 16 / (int)sizeof(T);")
     w("    const double mtd = mt;")
     w("    // level 1 (the polarisation vectors j(g; h) = eps_g(h)) is written by the table fill")
     for L in range(2, n + 1):
@@ -806,11 +814,11 @@ def emit_coop(n, lay, co, K, den, perms):
         w(f"        for (int k = 0; k < {npair}; ++k) {{")
         w(f"            const unsigned long long sp = GJ{n}_L{L}_PAIRX[it * {npair} + k];")
         w("            const unsigned lo = (unsigned)sp, hi = (unsigned)(sp >> 32);")
-        w(f"            const T* q1 = al16(obj + {co.gj} + 4 * (int)(lo & 511u));")
-        w(f"            const T* q2 = al16(obj + {co.gj} + 4 * (int)((lo >> 9) & 511u));")
+        w(f"            const T* q1 = al16(obj + {co.gj} + CW * (int)(lo & 511u));")
+        w(f"            const T* q2 = al16(obj + {co.gj} + CW * (int)((lo >> 9) & 511u));")
         w("            const T g = (lo >> 18) & 1u ? (T)-1 : (T)1;")
         w("            T j1[4], j2[4];")
-        w("            ld4(q1, j1); ld4(q2, j2);")
+        w(f"            ld4s<COOP_NGJ_NG{n}>(q1, j1); ld4s<COOP_NGJ_NG{n}>(q2, j2);")
         w("            const T* p1 = tab + (hi & 0xffffu); const T* p2 = tab + (hi >> 16);")
         w("            const T P1[4] = {(T)p1[0], (T)p1[1], (T)p1[2], (T)p1[3]};")
         w("            const T P2[4] = {(T)p2[0], (T)p2[1], (T)p2[2], (T)p2[3]};")
@@ -824,12 +832,13 @@ def emit_coop(n, lay, co, K, den, perms):
             w("#pragma unroll")
             w(f"        for (int k = 0; k < {ntrip}; ++k) {{")
             w(f"            const unsigned tp = GJ{n}_L{L}_TRIPX[it * {ntrip} + k];")
-            w(f"            const T* q1 = al16(obj + {co.gj} + 4 * (int)(tp & 511u));")
-            w(f"            const T* q2 = al16(obj + {co.gj} + 4 * (int)((tp >> 9) & 511u));")
-            w(f"            const T* q3 = al16(obj + {co.gj} + 4 * (int)((tp >> 18) & 511u));")
+            w(f"            const T* q1 = al16(obj + {co.gj} + CW * (int)(tp & 511u));")
+            w(f"            const T* q2 = al16(obj + {co.gj} + CW * (int)((tp >> 9) & 511u));")
+            w(f"            const T* q3 = al16(obj + {co.gj} + CW * (int)((tp >> 18) & 511u));")
             w("            const T g = (tp >> 27) & 1u ? (T)-1 : (T)1;")
             w("            T j1[4], j2[4], j3[4];")
-            w("            ld4(q1, j1); ld4(q2, j2); ld4(q3, j3);")
+            w(f"            ld4s<COOP_NGJ_NG{n}>(q1, j1); ld4s<COOP_NGJ_NG{n}>(q2, j2); "
+              f"ld4s<COOP_NGJ_NG{n}>(q3, j3);")
             w("            const T d23 = j2[0] * j3[0] - j2[1] * j3[1] - j2[2] * j3[2] - j2[3] * j3[3];")
             w("            const T d13 = j1[0] * j3[0] - j1[1] * j3[1] - j1[2] * j3[2] - j1[3] * j3[3];")
             w("            const T d12 = j1[0] * j2[0] - j1[1] * j2[1] - j1[2] * j2[2] - j1[3] * j2[3];")
@@ -837,8 +846,8 @@ def emit_coop(n, lay, co, K, den, perms):
                 w(f"            a{mu} += g * (j1[{mu}] * d23 - (T)2 * j2[{mu}] * d13 + j3[{mu}] * d12);")
             w("        }")
         w(f"        const T f = (T)tab[GJ{n}_L{L}_NINV[si]];")
-        w(f"        T* o = al16(obj + {co.gj} + 4 * (GJ{n}_L{L}_BASE[si] + hm));")
-        w("        st4(o, a0 * f, a1 * f, a2 * f, a3 * f);")
+        w(f"        T* o = al16(obj + {co.gj} + CW * (GJ{n}_L{L}_BASE[si] + hm));")
+        w(f"        st4s<COOP_NGJ_NG{n}>(o, a0 * f, a1 * f, a2 * f, a3 * f);")
         w("    }")
         w(f"//@@END L{L}")
     # top line from the top side: Ubar(a; s_t, h_a)
@@ -848,7 +857,7 @@ def emit_coop(n, lay, co, K, den, perms):
     w(f"        const int side = it >= {4 * n}, r = it - side * {4 * n};")
     w("        const int g = r >> 2, sp = (r >> 1) & 1, h = r & 1;")
     w(f"        T e[4];")
-    w(f"        ld4(al16(obj + {co.gj} + 4 * (2 * g + h)), e);")
+    w(f"        ld4s<COOP_NGJ_NG{n}>(al16(obj + {co.gj} + CW * (2 * g + h)), e);")
     w(f"        const T* q = tab + (side ? {lay.v} : {lay.ub}) + 8 * sp;")
     w("        cplx<T> x[4];")
     w("        for (int i = 0; i < 4; ++i) x[i] = cplx<T>((T)q[2 * i], (T)q[2 * i + 1]);")
@@ -864,7 +873,7 @@ def emit_coop(n, lay, co, K, den, perms):
     w("            slashcol_acc(e, x, W);")
     w("            colprop(W, Kc, (T)mtd, (T)k[4], (T)k[5], out);")
     w("        }")
-    w(f"        stspin(al16(obj + (side ? {co.v1} : {co.u1}) + 8 * r), out);")
+    w(f"        stspins<COOP_NU1_NG{n}>(al16(obj + (side ? {co.v1} : {co.u1}) + CW * r), out);")
     w("    }")
     w("//@@END U1V1")
     if pairs:
@@ -874,15 +883,15 @@ def emit_coop(n, lay, co, K, den, perms):
         w("        const int pi = it >> 3, sb = (it >> 2) & 1, hc = (it >> 1) & 1, hd = it & 1;")
         w(f"        const int c = V2_{n}_CD[2 * pi], d = V2_{n}_CD[2 * pi + 1];")
         w("        T ec[4];")
-        w(f"        ld4(al16(obj + {co.gj} + 4 * (2 * c + hc)), ec);")
+        w(f"        ld4s<COOP_NGJ_NG{n}>(al16(obj + {co.gj} + CW * (2 * c + hc)), ec);")
         w("        cplx<T> y[4];")
-        w(f"        ldspin(al16(obj + {co.v1} + 8 * (4 * d + 2 * sb + hd)), y);")
+        w(f"        ldspins<COOP_NU1_NG{n}>(al16(obj + {co.v1} + CW * (4 * d + 2 * sb + hd)), y);")
         w("        cplx<T> W[4] = {cplx<T>(0, 0), cplx<T>(0, 0), cplx<T>(0, 0), cplx<T>(0, 0)};")
         w("        slashcol_acc(ec, y, W);")
         w(f"        const int hm = V2_{n}_CLOW[pi] ? (hc | (hd << 1)) : (hd | (hc << 1));")
         w(f"        const T gs = (T)V2_{n}_JS[pi];")
         w("        T jcd[4];")
-        w(f"        ld4(al16(obj + {co.gj} + 4 * (V2_{n}_JB[pi] + hm)), jcd);")
+        w(f"        ld4s<COOP_NGJ_NG{n}>(al16(obj + {co.gj} + CW * (V2_{n}_JB[pi] + hm)), jcd);")
         w("        for (int i = 0; i < 4; ++i) jcd[i] *= gs;")
         w(f"        const T* qv = tab + {lay.v} + 8 * sb;")
         w("        cplx<T> x[4];")
@@ -892,7 +901,7 @@ def emit_coop(n, lay, co, K, den, perms):
         w("        const T Kc[4] = {(T)k[0], (T)k[1], (T)k[2], (T)k[3]};")
         w("        cplx<T> out[4];")
         w("        colprop(W, Kc, (T)mtd, (T)k[4], (T)k[5], out);")
-        w(f"        stspin(al16(obj + {co.v2} + 8 * it), out);")
+        w(f"        stspins<COOP_NV2_NG{n}>(al16(obj + {co.v2} + CW * it), out);")
         w("    }")
         w("//@@END V2")
     # Order of the stages: level 2 and the single-gluon spinor chains depend
@@ -932,6 +941,7 @@ def emit_coop(n, lay, co, K, den, perms):
     # an opaque copy of the helicity index: offsets derived from it are then
     # recomputed per event instead of being hoisted out of the event loop
     a('    asm volatile("" : "+v"(hel));')
+    a("    constexpr int CW = 16 / (int)sizeof(T);")
     a("    const int sT = hel & 1, sB = (hel >> 1) & 1, hg = hel >> 2;")
     hel_flops = 0
     lex = {sq: i for i, sq in enumerate(perms)}
@@ -949,14 +959,15 @@ def emit_coop(n, lay, co, K, den, perms):
 
     def gj_ptr(block, ob):
         b, sg, cs = co.obj(block)
-        return f"al16({ob} + {co.gj} + 4 * ({b} + ({hexpr(cs)})))", sg
+        return f"al16({ob} + {co.gj} + CW * ({b} + ({hexpr(cs)})))", sg
 
     def row_load(X, nm, ob):
         if not X:
             tb = ob.replace("ob", "tb")
             return nm, [f"    cplx<T> {nm}[4];", f"    ldspin(al16({tb} + {lay.ub} + 8 * sT), {nm});"]
         return nm, [f"    cplx<T> {nm}[4];",
-                    f"    ldspin(al16({ob} + {co.u1} + 8 * (4 * {X[0]} + 2 * sT + ((hg >> {X[0]}) & 1))), {nm});"]
+                    f"    ldspins<COOP_NU1_NG{n}>(al16({ob} + {co.u1} + CW * (4 * {X[0]} + 2 * sT + "
+                    f"((hg >> {X[0]}) & 1))), {nm});"]
 
     def col_load(Y, nm, ob):
         if not Y:
@@ -964,12 +975,14 @@ def emit_coop(n, lay, co, K, den, perms):
             return nm, [f"    cplx<T> {nm}[4];", f"    ldspin(al16({tb} + {lay.v} + 8 * sB), {nm});"]
         if len(Y) == 1:
             d = Y[0]
-            idx = f"{co.v1} + 8 * (4 * {d} + 2 * sB + ((hg >> {d}) & 1))"
+            idx = f"{co.v1} + CW * (4 * {d} + 2 * sB + ((hg >> {d}) & 1))"
+            ns = f"COOP_NU1_NG{n}"
         else:
             c, d = Y
             pi = co.pairs.index((c, d))
-            idx = f"{co.v2} + 8 * ({8 * pi} + 4 * sB + 2 * ((hg >> {c}) & 1) + ((hg >> {d}) & 1))"
-        return nm, [f"    cplx<T> {nm}[4];", f"    ldspin(al16({ob} + {idx}), {nm});"]
+            idx = f"{co.v2} + CW * ({8 * pi} + 4 * sB + 2 * ((hg >> {c}) & 1) + ((hg >> {d}) & 1))"
+            ns = f"COOP_NV2_NG{n}"
+        return nm, [f"    cplx<T> {nm}[4];", f"    ldspins<{ns}>(al16({ob} + {idx}), {nm});"]
 
     # group the terms by bilinear: key (X, Y) -> list of (beta, ordering)
     groups = {}
@@ -1011,7 +1024,7 @@ def emit_coop(n, lay, co, K, den, perms):
         for ci, (cs, uses) in enumerate(byc.items()):
             ptr, _ = gj_ptr(cs, "oc")
             jn = f"j{ci}"
-            Cc += [f"        T {jn}[4];", f"        ld4({ptr}, {jn});"]
+            Cc += [f"        T {jn}[4];", f"        ld4s<COOP_NGJ_NG{n}>({ptr}, {jn});"]
             if len(uses) == 1:
                 # one ordering meets this current: multiply-add into its accumulator
                 sgn, sg = uses[0]
@@ -1174,6 +1187,11 @@ def generate_coop(n):
 // helicity lane: {fhel} ({fhel_lc} in leading colour).
 static constexpr int COOP_TABLE_NG{n} = {tl.size};
 static constexpr int COOP_OBJ_NG{n} = {co.size};
+// objects per region of the chunk-major object store: currents, Ubar and V
+// chains, two-gluon V chains
+static constexpr int COOP_NGJ_NG{n} = {co.n_gj};
+static constexpr int COOP_NU1_NG{n} = {co.n_u1};
+static constexpr int COOP_NV2_NG{n} = {co.n_v2};
 static constexpr int COOP_FLOPS_STAGES_NG{n} = {fst};
 static constexpr int COOP_FLOPS_HEL_NG{n} = {fhel};
 {tables}
@@ -1182,7 +1200,9 @@ static constexpr int COOP_FLOPS_HEL_NG{n} = {fhel};
 // gluon currents in the object store, written by the lanes of one event;
 // the caller synchronises the wave afterwards.  mom: t[4], tbar[4], final
 // gluons[4 each]; eb: beam energy sqrt(s_hat)/2; mt: top mass; mw: m_t Gamma_t.
-template <typename T>
+// NS: objects of the current region `obj` points into (the object store's,
+// or a smaller staging area that holds only the level-1 currents).
+template <typename T, int NS = COOP_NGJ_NG{n}>
 __device__ __forceinline__ void fill_table_coop_ng{n}(const double* __restrict__ mom, double eb, double mt, double mw,
                                                      T* __restrict__ tab, T* __restrict__ obj, int lane)
 {{

@@ -219,6 +219,72 @@ __device__ __forceinline__ void stspin(T* p, const cplx<T>* s)
     st4(p + 4, s[2].x, s[2].y, s[3].x, s[3].y);
 }
 
+// The object store keeps each region chunk-major: of a region of N objects
+// (4-vectors of 4 values, spinors of 8), 16-byte chunk c of object i lies at
+// chunk c N + i of the region.  Lanes that read or write different objects of
+// a region then touch consecutive 16-byte words, and up to 16 distinct
+// objects per quarter wave fall in distinct LDS banks (a 32-byte FP64 4-vector
+// per object would put objects 256 bytes apart in the same banks).  p points
+// at chunk 0 of the object; the other chunks follow at a stride of N chunks,
+// which the immediate offset of the access carries.
+template <int N>
+__device__ __forceinline__ void ld4s(const double* p, double* o)
+{
+    const mf_d2 a = reinterpret_cast<const mf_d2*>(p)[0], b = reinterpret_cast<const mf_d2*>(p + 2 * N)[0];
+    o[0] = a.x; o[1] = a.y; o[2] = b.x; o[3] = b.y;
+}
+template <int N>
+__device__ __forceinline__ void ld4s(const float* p, float* o)
+{
+    ld4(p, o);
+}
+template <int N>
+__device__ __forceinline__ void st4s(double* p, double a0, double a1, double a2, double a3)
+{
+    mf_d2 a, b;
+    a.x = a0; a.y = a1; b.x = a2; b.y = a3;
+    reinterpret_cast<mf_d2*>(p)[0] = a;
+    reinterpret_cast<mf_d2*>(p + 2 * N)[0] = b;
+}
+template <int N>
+__device__ __forceinline__ void st4s(float* p, float a0, float a1, float a2, float a3)
+{
+    st4(p, a0, a1, a2, a3);
+}
+template <int N>
+__device__ __forceinline__ void ldspins(const double* p, cplx<double>* s)
+{
+    for (int c = 0; c < 4; ++c) {
+        const mf_d2 a = reinterpret_cast<const mf_d2*>(p + 2 * N * c)[0];
+        s[c] = cplx<double>(a.x, a.y);
+    }
+}
+template <int N>
+__device__ __forceinline__ void ldspins(const float* p, cplx<float>* s)
+{
+    const mf_f4 a = *reinterpret_cast<const mf_f4*>(p), b = *reinterpret_cast<const mf_f4*>(p + 4 * N);
+    s[0] = cplx<float>(a.x, a.y); s[1] = cplx<float>(a.z, a.w);
+    s[2] = cplx<float>(b.x, b.y); s[3] = cplx<float>(b.z, b.w);
+}
+template <int N>
+__device__ __forceinline__ void stspins(double* p, const cplx<double>* s)
+{
+    for (int c = 0; c < 4; ++c) {
+        mf_d2 a;
+        a.x = s[c].x; a.y = s[c].y;
+        reinterpret_cast<mf_d2*>(p + 2 * N * c)[0] = a;
+    }
+}
+template <int N>
+__device__ __forceinline__ void stspins(float* p, const cplx<float>* s)
+{
+    mf_f4 a, b;
+    a.x = s[0].x; a.y = s[0].y; a.z = s[1].x; a.w = s[1].y;
+    b.x = s[2].x; b.y = s[2].y; b.z = s[3].x; b.w = s[3].y;
+    *reinterpret_cast<mf_f4*>(p) = a;
+    *reinterpret_cast<mf_f4*>(p + 4 * N) = b;
+}
+
 // (ar, ai) = c^mu j_mu for complex c and a real 4-vector j held in registers.
 template <typename T>
 __device__ __forceinline__ void cdot_set(const T* j, const cplx<T>* c, T& ar, T& ai)

@@ -750,9 +750,11 @@ __device__ __forceinline__ void amp_quads_ng3(const StageParams& S)
             if (mq < kQ)
                 s_mom[mq][mk] = mc;
             wave_sync();
+            // the fill stages each event's level-1 currents (6 objects,
+            // chunk-major over those 6) in the extension of its table
             if (live_f)
-                fill_table_coop_ng3<T>(s_mom[fq], s_mom[fq][L::kMom - 1], S.P.m_top, S.P.mw, s_tab[fq],
-                                       s_tab[fq] + L::kTable, fl);
+                fill_table_coop_ng3<T, 6>(s_mom[fq], s_mom[fq][L::kMom - 1], S.P.m_top, S.P.mw, s_tab[fq],
+                                          s_tab[fq] + L::kTable, fl);
             wave_sync();
             for (int pr = 0; pr < 2; ++pr) {
                 const int k = 2 * pr + sub;
@@ -764,8 +766,12 @@ __device__ __forceinline__ void amp_quads_ng3(const StageParams& S)
                     continue;
                 const T* tab = s_tab[k];
                 T* obj = s_obj[sub];
-                if (live && h < kL1)
-                    obj[h] = tab[L::kTable + h];
+                if (live && h < kL1) {
+                    // value h of the staging area: chunk h / (6 CW), place h mod (6 CW);
+                    // in the store the chunks of the current region are COOP_NGJ_NG3 apart
+                    constexpr int CW = 16 / (int)sizeof(T);
+                    obj[(h / (6 * CW)) * CW * COOP_NGJ_NG3 + h % (6 * CW)] = tab[L::kTable + h];
+                }
                 if constexpr (COL == 2) {
                     if (live)
                         colour_factors_ng3<T>(S.first + e, S.P.seed, S.P.iter, s_cf[sub], h);
