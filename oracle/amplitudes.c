@@ -259,6 +259,25 @@ static void polarisation(const double *p, int hel, cplx *eps)
         eps[mu] = (sgn * e1[mu] - I * e2[mu]) / sqrt(2.0);
 }
 
+/* Real linear polarisations of the same frame: hel 0 -> e1, 1 -> e2.  The
+ * helicity vectors above are (-/+ e1 - i e2)/sqrt(2) of these, so both pairs
+ * span the same transverse plane and the polarisation sum is the same. */
+static void polarisation_linear(const double *p, int hel, cplx *eps)
+{
+    double pt = sqrt(p[1] * p[1] + p[2] * p[2]);
+    double th = atan2(pt, p[3]);
+    double ph = pt > 0.0 ? atan2(p[2], p[1]) : 0.0;
+    double e1[4] = { 0.0, cos(th) * cos(ph), cos(th) * sin(ph), -sin(th) };
+    double e2[4] = { 0.0, -sin(ph), cos(ph), 0.0 };
+    for (int mu = 0; mu < 4; ++mu)
+        eps[mu] = hel == 0 ? e1[mu] : e2[mu];
+}
+
+/* Gluon polarisation basis of the partial amplitudes on this thread: 0 the
+ * helicity vectors, 1 the linear ones (the Monte Carlo over helicities
+ * samples configurations of the linear basis). */
+static __thread int pol_linear;
+
 /* ------------------------------------------------------------------------ */
 /* Colour-ordered Berends-Giele recursion                                    */
 /* ------------------------------------------------------------------------ */
@@ -408,6 +427,8 @@ static void partial_amplitudes_core(int n, const double *p, double m, double wid
         if (g == ward_gluon) {
             for (int mu = 0; mu < 4; ++mu)
                 st->eps[g][mu] = p[4 * (2 + g) + mu];
+        } else if (pol_linear) {
+            polarisation_linear(p + 4 * (2 + g), hel[2 + g], st->eps[g]);
         } else {
             polarisation(p + 4 * (2 + g), hel[2 + g], st->eps[g]);
         }
@@ -616,6 +637,89 @@ double mfo_me2_sum_sampled(int n_g, const double *p, double m, double width, int
         return (double)mfo_flow_total(n_g) / (double)mfo_flow_weight(n_g, cfg) * dressed_sum(n_g, p, m, width, c, kappa);
     }
     return (double)count * dressed_sum(n_g, p, m, width, c, kappa);
+}
+
+/* ---- Monte Carlo over helicities -------------------------------------- */
+
+int mfo_hel_count(int n_g)
+{
+    return 1 << (n_g + 2);
+}
+
+/* Configuration h of event `event`: Philox block 0x80000002 of its counter,
+ * k the 53-bit integer of the first word pair, h = (k N_h) >> 53, uniform over
+ * the N_h = 2^(n_g + 2) configurations (bit 0 top spin, bit 1 antitop spin,
+ * bit 2 + g polarisation of gluon g). */
+int mfo_hel_config(int n_g, uint64_t seed, uint32_t iter, uint64_t event)
+{
+    uint32_t ctr[4] = { (uint32_t)event, (uint32_t)(event >> 32), iter, 0x80000002u };
+    uint32_t key[2] = { (uint32_t)seed, (uint32_t)(seed >> 32) };
+    uint32_t r[4];
+    mfo_philox4x32_10(ctr, key, r);
+    uint64_t k = ((((uint64_t)r[0]) << 32) | (uint64_t)r[1]) >> 11;
+    return (int)((k * (uint64_t)mfo_hel_count(n_g)) >> 53);
+}
+
+/* Colour sum of |M|^2 for the one configuration h of the linear basis, with
+ * the colour treatment of mode (0 full, 1 leading colour, 2 assignment cfg,
+ * 3 flow cfg; for 2 and 3 including their N_cfg or T / W_f scale).  *kappa
+ * (may be NULL): for modes 2 and 3 the condition number of the dressed sum,
+ * as in mfo_me2_sum_sampled. */
+double mfo_me2_hel(int n_g, const double *p, double m, double width, int mode, int64_t cfg, int h,
+                   double *kappa)
+{
+    if (kappa)
+        *kappa = 0.0;
+    if (n_g < 2 || n_g > MFO_MAX_G || h < 0 || h >= mfo_hel_count(n_g) || mode < 0 || mode > 3)
+        return NAN;
+    if ((mode == 2 && (cfg < 0 || cfg >= mfo_colour_count(n_g))) ||
+        (mode == 3 && (cfg < 0 || cfg >= mfo_flow_count(n_g))))
+        return NAN;
+    int nperm = mfo_n_orderings(n_g);
+    int hel[MFO_MAX_G + 2];
+    hel_from_index(n_g, h, hel);
+    cplx A[120];
+    pol_linear = 1;
+    partial_amplitudes_core(n_g, p, m, width, hel, -1, A);
+    pol_linear = 0;
+    if (mode == 0) {
+        const double *C = colour_matrix_cached(n_g);
+        double s = 0.0;
+        for (int a = 0; a < nperm; ++a)
+            for (int b = 0; b < nperm; ++b)
+                s += creal(conj(A[a]) * C[a * nperm + b] * A[b]);
+        return s;
+    }
+    if (mode == 1) {
+        double s = 0.0;
+        for (int a = 0; a < nperm; ++a)
+            s += creal(A[a]) * creal(A[a]) + cimag(A[a]) * cimag(A[a]);
+        return mfo_colour_lc(n_g) * s;
+    }
+    double c[2 * 120], scale;
+    if (mode == 2) {
+        mfo_colour_factors(n_g, cfg, c);
+        scale = (double)mfo_colour_count(n_g);
+    } else {
+        double r[120];
+        mfo_flow_factors(n_g, cfg, r);
+        for (int s = 0; s < nperm; ++s) {
+            c[2 * s] = r[s];
+            c[2 * s + 1] = 0.0;
+        }
+        scale = (double)mfo_flow_total(n_g) / (double)mfo_flow_weight(n_g, cfg);
+    }
+    cplx M = 0;
+    double mag = 0.0;
+    for (int s = 0; s < nperm; ++s) {
+        cplx t = (c[2 * s] + I * c[2 * s + 1]) * A[s];
+        M += t;
+        mag += cabs(t);
+    }
+    double v = creal(M) * creal(M) + cimag(M) * cimag(M);
+    if (kappa)
+        *kappa = v > 0.0 ? cabs(M) * mag / v : 0.0;
+    return scale * v;
 }
 
 double mfo_me2_sum_colour_config(int n_g, const double *p, double m, double width, int64_t cfg)

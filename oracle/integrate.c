@@ -156,7 +156,13 @@ static double weight_from_x(const mfo_process *proc, double sqrt_s,
 
     double gs2 = 4.0 * PI * proc->alpha_s;
     double sum;
-    if (proc->colour == 2 || proc->colour == 3)
+    if (proc->helicity == 1) {
+        int cfg_ok = (proc->colour != 2 && proc->colour != 3) || ev->colour_cfg >= 0;
+        sum = ev->hel_cfg >= 0 && cfg_ok
+                  ? (double)mfo_hel_count(n_g) * mfo_me2_hel(n_g, p, m, proc->w_top, proc->colour,
+                                                             ev->colour_cfg, ev->hel_cfg, &ev->colour_kappa)
+                  : NAN;
+    } else if (proc->colour == 2 || proc->colour == 3)
         sum = ev->colour_cfg >= 0 ? mfo_me2_sum_sampled(n_g, p, m, proc->w_top, proc->colour, ev->colour_cfg,
                                                         &ev->colour_kappa)
                                   : NAN;
@@ -187,6 +193,7 @@ double mfo_event_weight(const mfo_process *proc, double sqrt_s,
     double jac = mfo_vegas_map(D, n_bins, grid, ev->bin, delta, ev->x);
     ev->colour_cfg = proc->colour == 2 ? mfo_colour_config(proc->n_g, seed, (uint32_t)iter, event)
                    : proc->colour == 3 ? mfo_flow_config(proc->n_g, seed, (uint32_t)iter, event) : -1;
+    ev->hel_cfg = proc->helicity == 1 ? mfo_hel_config(proc->n_g, seed, (uint32_t)iter, event) : -1;
     return weight_from_x(proc, sqrt_s, pdf, jac, ev);
 }
 
@@ -208,6 +215,7 @@ double mfo_event_weight_y(const mfo_process *proc, double sqrt_s,
     }
     double jac = mfo_vegas_map(D, n_bins, grid, ev->bin, delta, ev->x);
     ev->colour_cfg = -1;
+    ev->hel_cfg = -1;
     return weight_from_x(proc, sqrt_s, pdf, jac, ev);
 }
 

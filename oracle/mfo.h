@@ -47,6 +47,9 @@ typedef struct {
     int    colour;             /* 0: full colour sum; 1: leading colour;
                                   2: colour Monte Carlo (one sampled assignment);
                                   3: Monte Carlo over colour flows          */
+    int    helicity;           /* 0: sum over helicity configurations;
+                                  1: Monte Carlo over them (one sampled
+                                  configuration of the linear basis)         */
 } mfo_process;
 
 typedef struct {
@@ -74,6 +77,7 @@ typedef struct {
     int    ill_conditioned;    /* |d ln(x g) / d ln x| > 1e3 at x1 or x2      */
     int64_t colour_cfg;        /* colour = 2, 3: the event's assignment, flow   */
     double colour_kappa;       /* colour = 2, 3: condition number of the sum   */
+    int    hel_cfg;            /* helicity = 1: the event's configuration      */
     double newton_kappa;       /* condition number of the mass-rescaling root:
                                   sqrt(s_hat) / (xi F'(xi)) = sqrt(s_hat) /
                                   sum_i |k_i|^2 / E_i (1 for massless momenta,
@@ -178,6 +182,21 @@ int64_t mfo_flow_config(int n_g, uint64_t seed, uint32_t iter, uint64_t event);
 void mfo_flow_factors(int n_g, int64_t idx, double *c);
 /* (T / W_idx) * sum_h |M(flow idx)|^2, g_s = 1.                             */
 double mfo_me2_sum_colour_flow(int n_g, const double *p, double m, double width, int64_t idx);
+/* Monte Carlo over helicities (Sec. 3.2 on Fig. 4 names it with the one over
+ * colours): each event carries one configuration h of the gluon
+ * polarisations and top spins, uniform over N_h = 2^(n_g + 2), from Philox
+ * block 0x80000002 of its counter (k the 53-bit integer of the first word
+ * pair, h = (k N_h) >> 53).  Configurations are those of the kernels: top and
+ * antitop spin along z in their rest frames (bits 0, 1), and for gluon g
+ * (bit 2 + g) the real linear polarisation e1 = (0, cos th cos ph,
+ * cos th sin ph, -sin th) or e2 = (0, -sin ph, cos ph, 0) of its momentum's
+ * angles.  N_h |M_h|^2 estimates the helicity sum without bias.            */
+int mfo_hel_count(int n_g);
+int mfo_hel_config(int n_g, uint64_t seed, uint32_t iter, uint64_t event);
+/* Colour sum (mode 0 full, 1 leading colour, 2 assignment cfg, 3 flow cfg)
+ * of |M|^2 with g_s = 1 for the single configuration h of the linear basis. */
+double mfo_me2_hel(int n_g, const double *p, double m, double width, int mode, int64_t cfg, int h,
+                   double *kappa);
 
 /* Either sampled sum (mode 2: adjoint assignment cfg; mode 3: flow index
  * cfg) and, if kappa is not NULL, its condition number

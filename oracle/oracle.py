@@ -23,7 +23,8 @@ _u64p = C.POINTER(C.c_uint64)
 class _Process(C.Structure):
     _fields_ = [("n_g", C.c_int), ("m_top", C.c_double), ("w_top", C.c_double),
                 ("alpha_s", C.c_double), ("mu_f", C.c_double), ("ptmin_g", C.c_double),
-                ("etamax_g", C.c_double), ("drmin_gg", C.c_double), ("colour", C.c_int)]
+                ("etamax_g", C.c_double), ("drmin_gg", C.c_double), ("colour", C.c_int),
+                ("helicity", C.c_int)]
 
 
 class _Pdf(C.Structure):
@@ -38,7 +39,7 @@ class _Event(C.Structure):
                 ("f2", C.c_double), ("me2", C.c_double), ("w", C.c_double),
                 ("k", C.c_double * 16), ("pass_threshold", C.c_int), ("pass_cuts", C.c_int),
                 ("newton_fail", C.c_int), ("near_edge", C.c_int), ("ill_conditioned", C.c_int),
-                ("colour_cfg", C.c_int64), ("colour_kappa", C.c_double),
+                ("colour_cfg", C.c_int64), ("colour_kappa", C.c_double), ("hel_cfg", C.c_int),
                 ("newton_kappa", C.c_double)]
 
 
@@ -157,6 +158,12 @@ def lib():
         L.mfo_lab_event.argtypes = [C.POINTER(_Process), C.c_double, C.c_int, _dp, C.c_uint64,
                                     C.c_int, C.c_uint64, _dp]
         L.mfo_lab_event.restype = C.c_int
+        L.mfo_hel_count.argtypes = [C.c_int]
+        L.mfo_hel_count.restype = C.c_int
+        L.mfo_hel_config.argtypes = [C.c_int, C.c_uint64, C.c_uint32, C.c_uint64]
+        L.mfo_hel_config.restype = C.c_int
+        L.mfo_me2_hel.argtypes = [C.c_int, _dp, C.c_double, C.c_double, C.c_int, C.c_int64, C.c_int, _dp]
+        L.mfo_me2_hel.restype = C.c_double
         L.mfo_event_weights.argtypes = [C.POINTER(_Process), C.c_double, C.POINTER(_Pdf), C.c_int, _dp,
                                         C.c_uint64, C.c_int, C.c_uint64, _u64p, C.c_int, _dp, _ip,
                                         _dp]
@@ -185,13 +192,18 @@ class Process:
     drmin_gg: float = 0.0
     colour: str = "full"        # "full", "leading" (leading colour), "sampled" (colour Monte Carlo
                                 # over adjoint indices) or "flow" (Monte Carlo over colour flows)
+    helicity: str = "sum"       # "sum" or "sampled" (Monte Carlo over helicity configurations)
 
     def c(self):
         modes = {"full": 0, "leading": 1, "sampled": 2, "flow": 3}
         if self.colour not in modes:
             raise ValueError(f"colour must be one of {sorted(modes)}, not {self.colour!r}")
+        hmodes = {"sum": 0, "sampled": 1}
+        if self.helicity not in hmodes:
+            raise ValueError(f"helicity must be one of {sorted(hmodes)}, not {self.helicity!r}")
         return _Process(self.n_g, self.m_top, self.w_top, self.alpha_s, self.mu_f,
-                        self.ptmin_g, self.etamax_g, self.drmin_gg, modes[self.colour])
+                        self.ptmin_g, self.etamax_g, self.drmin_gg, modes[self.colour],
+                        hmodes[self.helicity])
 
 
 class _PdfHandle:
@@ -566,3 +578,24 @@ def event_weights(proc: Process, sqrt_s, table, grid, seed, it, ids, n_threads=N
                             len(ids), ids.ctypes.data_as(_u64p), n_threads, _d(w),
                             flags.ctypes.data_as(_ip), _d(kappa))
     return (w, flags, kappa) if return_kappa else (w, flags)
+
+
+def hel_count(n_g: int) -> int:
+    return lib().mfo_hel_count(n_g)
+
+
+def hel_config(n_g: int, seed: int, it: int, event: int) -> int:
+    """Helicity configuration of event e (Monte Carlo over helicities): Philox
+    block 0x80000002, h = (k N_h) >> 53."""
+    return lib().mfo_hel_config(n_g, seed, it, event)
+
+
+def me2_hel(n_g: int, p, m=173.0, width=1.5, colour="full", cfg=-1, h=0, return_kappa=False):
+    """Colour sum of |M|^2 (g_s = 1) for the single configuration h of the linear
+    polarisation basis; colour "full", "leading", "sampled" (assignment cfg) or
+    "flow" (flow cfg)."""
+    p = _f64(p)
+    modes = {"full": 0, "leading": 1, "sampled": 2, "flow": 3}
+    k = C.c_double()
+    v = lib().mfo_me2_hel(n_g, _d(p), m, width, modes[colour], cfg, h, C.byref(k))
+    return (v, k.value) if return_kappa else v
