@@ -161,6 +161,32 @@ mf_status mf_integrate(const mf_process *proc, double sqrt_s, const mf_pdf_grid 
                        const mf_options *opt, mf_result *res);
 
 /*
+ * mf_integrate_static -- mf_integrate for callers that cannot allocate
+ * device memory (code under stream capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments, validation, kernels and results
+ * as mf_integrate; it calls no hipMalloc, hipFree or other allocating
+ * routine.  Its device working memory is one static 96 MiB array per device
+ * (held from the library's load until the process ends), shared by every
+ * call on that device: calls that overlap on one device race, so the caller
+ * serialises them (the library's per-device lock does so within one process).
+ * The array holds the PDF table, both grids, the per-iteration results, the
+ * per-wave partial sums and, for n_g >= 3, the per-event hand-over of one
+ * batch of events, which takes the room the rest leaves.  The partial sums
+ * take 256 (8 + n_dims n_bins) bytes per compute unit (33 MB for
+ * g g -> t tbar g g on 256 compute units, leaving a batch of about 3.8e5
+ * events); larger n_events run as several batches, with the same per-event
+ * weights and sums that agree to rounding.
+ * Limits (MF_EINVAL beyond them): n_dims * n_bins <= 512 and n_x * n_q2 <=
+ * 65536.  options->profile must be 0 (MF_EUNSUPPORTED otherwise).  A device
+ * whose partial sums and a batch of 256 events do not fit returns MF_ENOMEM.
+ * Weights are written to res->weights as in mf_integrate (caller-owned
+ * device memory).
+ */
+mf_status mf_integrate_static(const mf_process *proc, double sqrt_s, const mf_pdf_grid *pdf,
+                              uint64_t n_events, int n_iter, uint64_t seed,
+                              const mf_options *opt, mf_result *res);
+
+/*
  * mf_evaluate -- per-event weights for a fixed grid (no accumulation).
  *   grid:      host [D][n_bins+1], NULL = uniform.
  *   y:         device [n][D] uniforms in [0,1), or NULL to draw them from

@@ -57,9 +57,9 @@ class mf_events(C.Structure):
                 ("kernel_ms", C.c_double * 3)]
 
 
-EXPORTS = ("mf_default_options", "mf_n_dims", "mf_integrate", "mf_evaluate", "mf_refine_grid",
-           "mf_colour_matrix", "mf_matrix_element", "mf_integrate_grad", "mf_evaluate_grad",
-           "mf_unweight", "mf_last_error")
+EXPORTS = ("mf_default_options", "mf_n_dims", "mf_integrate", "mf_integrate_static", "mf_evaluate",
+           "mf_refine_grid", "mf_colour_matrix", "mf_matrix_element", "mf_integrate_grad",
+           "mf_evaluate_grad", "mf_unweight", "mf_last_error")
 
 
 class MFError(RuntimeError):
@@ -81,6 +81,8 @@ def load():
                                C.c_uint64, C.c_int, C.c_uint64, C.POINTER(mf_options),
                                C.POINTER(mf_result)]
     L.mf_integrate.restype = C.c_int
+    L.mf_integrate_static.argtypes = L.mf_integrate.argtypes
+    L.mf_integrate_static.restype = C.c_int
     L.mf_evaluate.argtypes = [C.POINTER(mf_process), C.c_double, C.POINTER(mf_pdf_grid), _dp,
                               C.c_void_p, C.c_void_p, C.c_uint64, C.c_uint64, C.c_int,
                               C.POINTER(mf_options), C.c_void_p, C.c_void_p, C.c_void_p,

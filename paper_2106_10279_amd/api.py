@@ -20,7 +20,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import MF_FP32_KAHAN, MF_FP64, check, lib
+from ._lib import MF_FP32_KAHAN, MF_FP64, MFError, check, lib  # noqa: F401
 
 PROCESS_IDS = {"gg_ttx": _lib.MF_GG_TTX, "gg_ttxg": _lib.MF_GG_TTXG, "gg_ttxgg": _lib.MF_GG_TTXGG,
                2: _lib.MF_GG_TTX, 3: _lib.MF_GG_TTXG, 4: _lib.MF_GG_TTXGG}
@@ -119,7 +119,9 @@ def integrate(proc: Process, sqrt_s: float, pdf_table, n_events: int, n_iter: in
               n_bins: int = 50, alpha: float = 1.5, precision="fp64", start_iter: int = 0,
               grid_in=None, keep_weights: bool = True, strict: bool = False,
               max_newton: int = 50, stream=None, weights_out: torch.Tensor | None = None,
-              profile: bool = False, max_batch: int = 0, colour="full"):
+              profile: bool = False, max_batch: int = 0, colour="full", static_scratch: bool = False):
+    """VEGAS integration (mf_integrate); static_scratch=True calls
+    mf_integrate_static, which allocates no device memory."""
     D = n_dims(proc.process)
     pdf = _Pdf(pdf_table)
     gin = None if grid_in is None else np.ascontiguousarray(grid_in, dtype=np.float64)
@@ -147,8 +149,8 @@ def integrate(proc: Process, sqrt_s: float, pdf_table, n_events: int, n_iter: in
     grid_last = np.zeros((D, n_bins + 1))
     res.grid_last = _ptr(grid_last)
     pc = proc.c()
-    check(lib.mf_integrate(C.byref(pc), sqrt_s, C.byref(pdf.c), n_events, n_iter, seed,
-                           C.byref(opt), C.byref(res)))
+    fn = lib.mf_integrate_static if static_scratch else lib.mf_integrate
+    check(fn(C.byref(pc), sqrt_s, C.byref(pdf.c), n_events, n_iter, seed, C.byref(opt), C.byref(res)))
     return IntegrationResult(res.sigma, res.sigma_err, res.chi2_dof, res.w_max, res.n_pass,
                              res.n_newton_fail, I, V, grid, hist, w, res.event_kernel_ms,
                              res.reduce_kernel_ms, npass, tms if profile else None,

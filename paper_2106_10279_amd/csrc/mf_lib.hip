@@ -19,9 +19,30 @@
 #include "mf_kernels.hpp"
 #include "mf_unweight.hpp"
 
+// Static device scratch of mf_integrate_static, for callers that cannot
+// allocate device memory.  Every device the library runs on holds its own
+// copy from module load until the process ends.  Host code never passes this
+// name to a kernel or a copy: it uses the address hipGetSymbolAddress returns
+// on that device (Workspace::scratch).
+constexpr size_t kScratchBytes = size_t(96) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
 namespace {
 
+constexpr int kMaxIter = 256;            // iterations per call
+constexpr int kScratchMaxCells = 512;    // n_dims * n_bins in the static scratch
+constexpr long kScratchMaxPdf = 65536;   // PDF table values in the static scratch
+
 thread_local std::string g_error;
+
+// Clears n doubles (a kernel rather than a memset node, so that a captured
+// stream replays it faithfully).
+__global__ void zero_kernel(double* p, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n)
+        p[i] = 0.0;
+}
 
 mf_status fail(mf_status st, const std::string& msg)
 {
@@ -71,6 +92,7 @@ struct Workspace {
     Buffer amp_counter;                                  // work counter of amp_kernel (8 bytes)
     Buffer uw_counts, uw_flags, uw_totals;               // unweighting: per-workgroup counts, keep flags, totals
     int n_cu = 0;
+    void* scratch = nullptr;  // this device's address of the static scratch array (mf_integrate_static)
 };
 
 Workspace g_ws[64];
@@ -95,6 +117,35 @@ mf_status ensure(Buffer& b, size_t bytes)
     b.bytes = want;
     return MF_OK;
 }
+
+// Device memory of one integration: pointers into the grow-only workspace
+// (mf_integrate) or into the static scratch array (mf_integrate_static).
+struct Mem {
+    double* grid[2] = {nullptr, nullptr};
+    double *log_x = nullptr, *log_q2 = nullptr, *xf = nullptr;
+    double *partials = nullptr, *entries = nullptr, *iter_I = nullptr, *iter_V = nullptr, *iter_pass = nullptr;
+    double *stats = nullptr, *gpartials = nullptr, *gsum = nullptr;
+    double *st_mom = nullptr, *st_pref = nullptr, *st_me = nullptr;
+    unsigned short* st_bins = nullptr;
+    unsigned char* st_flags = nullptr;
+    unsigned long long* amp_counter = nullptr;
+};
+
+// Consecutive 256-byte aligned pieces of a fixed device region.
+struct Carve {
+    unsigned char* base;
+    size_t used, cap;
+    template <typename T>
+    T* take(size_t count)
+    {
+        const size_t bytes = (count * sizeof(T) + 255) & ~size_t(255);
+        if (bytes > cap - used)
+            return nullptr;
+        T* p = (T*)(base + used);
+        used += bytes;
+        return p;
+    }
+};
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 
@@ -201,18 +252,29 @@ struct Setup {
     Workspace* ws;
 };
 
-// Upload the PDF table and fill the launch parameters shared by all modes.
-mf_status prepare(const mf_process* proc, double sqrt_s, const mf_pdf_grid* pdf, const mf_options* opt,
-                  Workspace& ws, Setup& S)
+// PDF buffers of the grow-only workspace.
+mf_status workspace_pdf(const mf_pdf_grid* pdf, Workspace& ws, Mem& m)
 {
     const int nx = pdf->n_x, nq = pdf->n_q2;
     mf_status st;
     if ((st = ensure(ws.log_x, sizeof(double) * nx)) != MF_OK) return st;
     if ((st = ensure(ws.log_q2, sizeof(double) * nq)) != MF_OK) return st;
     if ((st = ensure(ws.xf, sizeof(double) * nx * (size_t)nq)) != MF_OK) return st;
-    MF_HIP(hipMemcpyAsync(ws.log_x.ptr, pdf->log_x, sizeof(double) * nx, hipMemcpyHostToDevice, S.stream));
-    MF_HIP(hipMemcpyAsync(ws.log_q2.ptr, pdf->log_q2, sizeof(double) * nq, hipMemcpyHostToDevice, S.stream));
-    MF_HIP(hipMemcpyAsync(ws.xf.ptr, pdf->xf, sizeof(double) * nx * (size_t)nq, hipMemcpyHostToDevice, S.stream));
+    m.log_x = (double*)ws.log_x.ptr;
+    m.log_q2 = (double*)ws.log_q2.ptr;
+    m.xf = (double*)ws.xf.ptr;
+    return MF_OK;
+}
+
+// Upload the PDF table into m's PDF buffers and fill the launch parameters
+// shared by all modes.
+mf_status prepare(const mf_process* proc, double sqrt_s, const mf_pdf_grid* pdf, const mf_options* opt,
+                  const Mem& m, Setup& S)
+{
+    const int nx = pdf->n_x, nq = pdf->n_q2;
+    MF_HIP(hipMemcpyAsync(m.log_x, pdf->log_x, sizeof(double) * nx, hipMemcpyHostToDevice, S.stream));
+    MF_HIP(hipMemcpyAsync(m.log_q2, pdf->log_q2, sizeof(double) * nq, hipMemcpyHostToDevice, S.stream));
+    MF_HIP(hipMemcpyAsync(m.xf, pdf->xf, sizeof(double) * nx * (size_t)nq, hipMemcpyHostToDevice, S.stream));
 
     mf::EventParams& P = S.P;
     std::memset(&P, 0, sizeof(P));
@@ -229,9 +291,9 @@ mf_status prepare(const mf_process* proc, double sqrt_s, const mf_pdf_grid* pdf,
     P.q2_first = first;
     P.q2_rows = last - first + 1;
     P.q2_interval = mq;
-    P.log_x = (const double*)ws.log_x.ptr;
-    P.log_q2 = (const double*)ws.log_q2.ptr;
-    P.xf = (const double*)ws.xf.ptr;
+    P.log_x = m.log_x;
+    P.log_q2 = m.log_q2;
+    P.xf = m.xf;
     P.sqrt_s = sqrt_s;
     P.s_had = sqrt_s * sqrt_s;
     P.m_top = proc->m_top;
@@ -370,38 +432,41 @@ int waves_for(uint64_t n_chunks, int n_cu)
     return (int)(w < mf::kWavesPerBlock ? mf::kWavesPerBlock : w);
 }
 
+// Neumaier's compensated summation, one term at a time.
+void neumaier_add(double& s, double& c, double x)
+{
+    const double t = s + x;
+    if (std::fabs(s) >= std::fabs(x)) c += (s - t) + x; else c += (x - t) + s;
+    s = t;
+}
+
 void combine(int n, const double* I, const double* V, double* sigma, double* err, double* chi2)
 {
-    // inverse-variance weighted mean with compensated sums
-    auto nsum = [](const std::vector<double>& v) {
-        double s = 0.0, c = 0.0;
-        for (double x : v) {
-            double t = s + x;
-            if (std::fabs(s) >= std::fabs(x)) c += (s - t) + x; else c += (x - t) + s;
-            s = t;
-        }
-        return s + c;
-    };
-    std::vector<double> num, den, chi;
+    // inverse-variance weighted mean with compensated sums over the
+    // iterations with V_j > 0, in iteration order
+    double ns = 0.0, nc = 0.0, ds = 0.0, dc = 0.0;
+    int used = 0;
     for (int j = 0; j < n; ++j)
         if (V[j] > 0.0) {
-            num.push_back(I[j] / V[j]);
-            den.push_back(1.0 / V[j]);
+            neumaier_add(ns, nc, I[j] / V[j]);
+            neumaier_add(ds, dc, 1.0 / V[j]);
+            ++used;
         }
-    if (num.empty()) {
+    if (used == 0) {
         *sigma = n > 0 ? I[n - 1] : 0.0;
         *err = 0.0;
         *chi2 = 0.0;
         return;
     }
-    const double sden = nsum(den);
-    const double mean = nsum(num) / sden;
+    const double sden = ds + dc;
+    const double mean = (ns + nc) / sden;
+    double cs = 0.0, cc = 0.0;
     for (int j = 0; j < n; ++j)
         if (V[j] > 0.0)
-            chi.push_back((I[j] - mean) * (I[j] - mean) / V[j]);
+            neumaier_add(cs, cc, (I[j] - mean) * (I[j] - mean) / V[j]);
     *sigma = mean;
     *err = 1.0 / std::sqrt(sden);
-    *chi2 = num.size() > 1 ? nsum(chi) / (double)(num.size() - 1) : 0.0;
+    *chi2 = used > 1 ? (cs + cc) / (double)(used - 1) : 0.0;
 }
 
 // sum_j (g_j / V_j) / sum_j (1 / V_j) over iterations with V_j > 0 (the
@@ -409,16 +474,11 @@ void combine(int n, const double* I, const double* V, double* sigma, double* err
 void combine_fixed(int n, const double* g, const double* V, double* out)
 {
     double ns = 0.0, nc = 0.0, ds = 0.0, dc = 0.0;
-    auto add = [](double& s, double& c, double x) {
-        const double t = s + x;
-        if (std::fabs(s) >= std::fabs(x)) c += (s - t) + x; else c += (x - t) + s;
-        s = t;
-    };
     int used = 0;
     for (int j = 0; j < n; ++j)
         if (V[j] > 0.0) {
-            add(ns, nc, g[j] / V[j]);
-            add(ds, dc, 1.0 / V[j]);
+            neumaier_add(ns, nc, g[j] / V[j]);
+            neumaier_add(ds, dc, 1.0 / V[j]);
             ++used;
         }
     *out = used ? (ns + nc) / (ds + dc) : (n > 0 ? g[n - 1] : 0.0);
@@ -460,7 +520,8 @@ namespace {
 // The iteration loop of mf_integrate; with `grad`, every iteration also runs
 // the adjoint kernel on the grid that iteration used.
 mf_status integrate_impl(const mf_process* proc, double sqrt_s, const mf_pdf_grid* pdf, uint64_t n_events,
-                         int n_iter, uint64_t seed, const mf_options* opt, mf_result* res, mf_grad_result* grad)
+                         int n_iter, uint64_t seed, const mf_options* opt, mf_result* res, mf_grad_result* grad,
+                         bool fixed_scratch)
 {
     int ng = 0;
     mf_status st;
@@ -472,7 +533,7 @@ mf_status integrate_impl(const mf_process* proc, double sqrt_s, const mf_pdf_gri
         return fail(MF_EINVAL, "result is NULL");
     if (n_events < 2 || n_events > (1ull << 40))
         return fail(MF_EINVAL, "n_events must be in [2, 2^40]");
-    if (n_iter < 1 || n_iter > 256)
+    if (n_iter < 1 || n_iter > kMaxIter)
         return fail(MF_EINVAL, "n_iter must be in [1, 256]");
     if ((uint64_t)opt->start_iter + (uint64_t)n_iter > 0xFFFFFFFFull)
         return fail(MF_EINVAL, "iteration index exceeds the 32-bit Philox counter word");
@@ -486,63 +547,139 @@ mf_status integrate_impl(const mf_process* proc, double sqrt_s, const mf_pdf_gri
         if (opt->colour != MF_COLOUR_FULL)
             return fail(MF_EUNSUPPORTED, "gradients are computed with the full colour sum only");
     }
+    const int nb = opt->n_bins;
+    if (fixed_scratch) {
+        if (grad)
+            return fail(MF_EUNSUPPORTED, "mf_integrate_static computes no gradients");
+        if (opt->profile)
+            return fail(MF_EUNSUPPORTED, "mf_integrate_static does not time kernels (profile must be 0)");
+        if (D * nb > kScratchMaxCells)
+            return fail(MF_EINVAL, "mf_integrate_static: n_dims * n_bins must be at most 512");
+        if ((long)pdf->n_x * pdf->n_q2 > kScratchMaxPdf)
+            return fail(MF_EINVAL, "mf_integrate_static: the PDF table must hold at most 65536 values");
+    }
 
     Workspace* wsp = nullptr;
     if ((st = device_workspace(&wsp)) != MF_OK) return st;
     Workspace& ws = *wsp;
     std::lock_guard<std::mutex> guard(ws.lock);
 
-    Setup S;
-    S.ng = ng;
-    S.D = D;
-    S.stream = (hipStream_t)opt->stream;
-    if ((st = prepare(proc, sqrt_s, pdf, opt, ws, S)) != MF_OK) return st;
-    mf::EventParams& P = S.P;
-
-    const int nb = opt->n_bins;
     const uint64_t n_chunks = (n_events + mf::kWave - 1) / mf::kWave;
     const int n_waves = waves_for(n_chunks, ws.n_cu);
     const int stride = mf::kPartialHead + D * nb;
     const size_t grid_bytes = sizeof(double) * D * (size_t)(nb + 1);
-    if ((st = ensure(ws.grid[0], grid_bytes)) != MF_OK) return st;
-    if ((st = ensure(ws.grid[1], grid_bytes)) != MF_OK) return st;
-    if ((st = ensure(ws.partials, sizeof(double) * (size_t)n_waves * stride)) != MF_OK) return st;
-    if ((st = ensure(ws.entries, sizeof(double) * (size_t)stride)) != MF_OK) return st;
-    if ((st = ensure(ws.iter_I, sizeof(double) * n_iter)) != MF_OK) return st;
-    if ((st = ensure(ws.iter_V, sizeof(double) * n_iter)) != MF_OK) return st;
-    if ((st = ensure(ws.iter_pass, sizeof(double) * n_iter)) != MF_OK) return st;
-    if ((st = ensure(ws.stats, sizeof(double) * 4)) != MF_OK) return st;
     const bool staged = ng >= 3;
-    const uint64_t cap = opt->max_batch ? opt->max_batch : kStageBatch;
+    const int nf = ng;
+    uint64_t cap = opt->max_batch ? opt->max_batch : kStageBatch;
+    Mem m;
+    if (fixed_scratch) {
+        if (!ws.scratch) {
+            // this device's copy of the array; host code uses only this address
+            void* addr = nullptr;
+            MF_HIP(hipGetSymbolAddress(&addr, HIP_SYMBOL(scratch)));
+            ws.scratch = addr;
+        }
+        Carve c{(unsigned char*)ws.scratch, 0, kScratchBytes};
+        m.grid[0] = c.take<double>((size_t)D * (nb + 1));
+        m.grid[1] = c.take<double>((size_t)D * (nb + 1));
+        m.log_x = c.take<double>(pdf->n_x);
+        m.log_q2 = c.take<double>(pdf->n_q2);
+        m.xf = c.take<double>((size_t)pdf->n_x * pdf->n_q2);
+        m.entries = c.take<double>(stride);
+        m.iter_I = c.take<double>(n_iter);
+        m.iter_V = c.take<double>(n_iter);
+        m.iter_pass = c.take<double>(n_iter);
+        m.stats = c.take<double>(4);
+        m.amp_counter = c.take<unsigned long long>(1);
+        m.partials = c.take<double>((size_t)n_waves * stride);
+        if (!m.partials)
+            return fail(MF_ENOMEM, "mf_integrate_static: the per-wave partial sums do not fit the static scratch");
+        if (staged) {
+            // the per-event hand-over takes what is left, in whole 256-event steps
+            const size_t per_event = sizeof(double) * (4 * nf + 1) + 2 * sizeof(double) +
+                                     sizeof(unsigned short) * D + 1;
+            const size_t left = c.cap - c.used;
+            uint64_t fit = left > 5 * 256 ? (left - 5 * 256) / per_event / 256 * 256 : 0;
+            if (fit < 256)
+                return fail(MF_ENOMEM, "mf_integrate_static: no room left in the static scratch for an event batch");
+            if (cap > fit)
+                cap = fit;
+        }
+        const uint64_t b0 = n_events < cap ? n_events : cap;
+        if (staged) {
+            m.st_mom = c.take<double>((size_t)(4 * nf + 1) * b0);
+            m.st_pref = c.take<double>(b0);
+            m.st_me = c.take<double>(b0);
+            m.st_bins = c.take<unsigned short>((size_t)D * b0);
+            m.st_flags = c.take<unsigned char>(b0);
+            if (!m.st_flags)
+                return fail(MF_ENOMEM, "mf_integrate_static: event batch does not fit the static scratch");
+        }
+    } else {
+        if ((st = workspace_pdf(pdf, ws, m)) != MF_OK) return st;
+        if ((st = ensure(ws.grid[0], grid_bytes)) != MF_OK) return st;
+        if ((st = ensure(ws.grid[1], grid_bytes)) != MF_OK) return st;
+        if ((st = ensure(ws.partials, sizeof(double) * (size_t)n_waves * stride)) != MF_OK) return st;
+        if ((st = ensure(ws.entries, sizeof(double) * (size_t)stride)) != MF_OK) return st;
+        if ((st = ensure(ws.iter_I, sizeof(double) * n_iter)) != MF_OK) return st;
+        if ((st = ensure(ws.iter_V, sizeof(double) * n_iter)) != MF_OK) return st;
+        if ((st = ensure(ws.iter_pass, sizeof(double) * n_iter)) != MF_OK) return st;
+        if ((st = ensure(ws.stats, sizeof(double) * 4)) != MF_OK) return st;
+        const uint64_t b0 = n_events < cap ? n_events : cap;
+        if (staged) {
+            if ((st = ensure(ws.st_mom, sizeof(double) * (4 * nf + 1) * b0)) != MF_OK) return st;
+            if ((st = ensure(ws.st_pref, sizeof(double) * b0)) != MF_OK) return st;
+            if ((st = ensure(ws.st_me, sizeof(double) * b0)) != MF_OK) return st;
+            if ((st = ensure(ws.st_bins, sizeof(unsigned short) * D * b0)) != MF_OK) return st;
+            if ((st = ensure(ws.st_flags, b0)) != MF_OK) return st;
+            if ((st = ensure(ws.amp_counter, sizeof(unsigned long long))) != MF_OK) return st;
+        }
+        if (grad) {
+            if ((st = ensure(ws.gpartials, sizeof(double) * 4 * (size_t)n_waves)) != MF_OK) return st;
+            if ((st = ensure(ws.gsum, sizeof(double) * 4 * (size_t)n_iter)) != MF_OK) return st;
+        }
+        m.grid[0] = (double*)ws.grid[0].ptr;
+        m.grid[1] = (double*)ws.grid[1].ptr;
+        m.partials = (double*)ws.partials.ptr;
+        m.entries = (double*)ws.entries.ptr;
+        m.iter_I = (double*)ws.iter_I.ptr;
+        m.iter_V = (double*)ws.iter_V.ptr;
+        m.iter_pass = (double*)ws.iter_pass.ptr;
+        m.stats = (double*)ws.stats.ptr;
+        m.gpartials = (double*)ws.gpartials.ptr;
+        m.gsum = (double*)ws.gsum.ptr;
+        m.st_mom = (double*)ws.st_mom.ptr;
+        m.st_pref = (double*)ws.st_pref.ptr;
+        m.st_me = (double*)ws.st_me.ptr;
+        m.st_bins = (unsigned short*)ws.st_bins.ptr;
+        m.st_flags = (unsigned char*)ws.st_flags.ptr;
+        m.amp_counter = (unsigned long long*)ws.amp_counter.ptr;
+    }
     const uint64_t batch = n_events < cap ? n_events : cap;
     const uint64_t n_batches = (n_events + batch - 1) / batch;
-    if (staged) {
-        const int nf = ng;
-        if ((st = ensure(ws.st_mom, sizeof(double) * (4 * nf + 1) * batch)) != MF_OK) return st;
-        if ((st = ensure(ws.st_pref, sizeof(double) * batch)) != MF_OK) return st;
-        if ((st = ensure(ws.st_me, sizeof(double) * batch)) != MF_OK) return st;
-        if ((st = ensure(ws.st_bins, sizeof(unsigned short) * D * batch)) != MF_OK) return st;
-        if ((st = ensure(ws.st_flags, batch)) != MF_OK) return st;
-        if ((st = ensure(ws.amp_counter, sizeof(unsigned long long))) != MF_OK) return st;
-    }
-    if (grad) {
-        if ((st = ensure(ws.gpartials, sizeof(double) * 4 * (size_t)n_waves)) != MF_OK) return st;
-        if ((st = ensure(ws.gsum, sizeof(double) * 4 * (size_t)n_iter)) != MF_OK) return st;
-    }
 
-    std::vector<double> grid0((size_t)D * (nb + 1));
+    Setup S;
+    S.ng = ng;
+    S.D = D;
+    S.stream = (hipStream_t)opt->stream;
+    if ((st = prepare(proc, sqrt_s, pdf, opt, m, S)) != MF_OK) return st;
+    mf::EventParams& P = S.P;
+
+    // host copy of the start grid (n_dims * n_bins <= 2048)
+    double grid0[2048 + mf::kMaxDims];
     if (opt->grid_in)
-        std::memcpy(grid0.data(), opt->grid_in, grid_bytes);
+        std::memcpy(grid0, opt->grid_in, grid_bytes);
     else
         for (int d = 0; d < D; ++d)
             for (int i = 0; i <= nb; ++i)
                 grid0[(size_t)d * (nb + 1) + i] = (double)i / (double)nb;
-    MF_HIP(hipMemcpyAsync(ws.grid[0].ptr, grid0.data(), grid_bytes, hipMemcpyHostToDevice, S.stream));
-    MF_HIP(hipMemsetAsync(ws.stats.ptr, 0, sizeof(double) * 4, S.stream));
+    MF_HIP(hipMemcpyAsync(m.grid[0], grid0, grid_bytes, hipMemcpyHostToDevice, S.stream));
+    hipLaunchKernelGGL(zero_kernel, dim3(1), dim3(64), 0, S.stream, m.stats, 4);
+    MF_HIP(hipGetLastError());
 
     P.n_events = n_events;
     P.seed = seed;
-    P.partials = (double*)ws.partials.ptr;
+    P.partials = m.partials;
     P.stride = stride;
     P.n_waves = n_waves;
     mf::ReduceParams R;
@@ -553,12 +690,12 @@ mf_status integrate_impl(const mf_process* proc, double sqrt_s, const mf_pdf_gri
     R.n_bins = nb;
     R.n_events = (double)n_events;
     R.alpha = opt->alpha;
-    R.entries = (double*)ws.entries.ptr;
+    R.entries = m.entries;
     R.hist = R.entries + mf::kPartialHead;
-    R.iter_I = (double*)ws.iter_I.ptr;
-    R.iter_V = (double*)ws.iter_V.ptr;
-    R.iter_pass = (double*)ws.iter_pass.ptr;
-    R.stats = (double*)ws.stats.ptr;
+    R.iter_I = m.iter_I;
+    R.iter_V = m.iter_V;
+    R.iter_pass = m.iter_pass;
+    R.stats = m.stats;
 
     // Optional per-kernel timing: events recorded on the stream around every
     // launch (marks[3j] .. marks[3j+2]).
@@ -576,7 +713,7 @@ mf_status integrate_impl(const mf_process* proc, double sqrt_s, const mf_pdf_gri
     int cur = 0;
     for (int j = 0; j < n_iter; ++j) {
         P.iter = (uint32_t)(opt->start_iter + j);
-        P.grid = (const double*)ws.grid[cur].ptr;
+        P.grid = m.grid[cur];
         P.weights = (j == n_iter - 1) ? res->weights : nullptr;
         if (opt->profile)
             MF_HIP(hipEventRecord(marks[3 * j], S.stream));
@@ -586,13 +723,13 @@ mf_status integrate_impl(const mf_process* proc, double sqrt_s, const mf_pdf_gri
                 SP.P = P;
                 SP.first = bi * batch;
                 SP.count = (bi + 1 == n_batches) ? n_events - SP.first : batch;
-                SP.mom = (double*)ws.st_mom.ptr;
-                SP.pref = (double*)ws.st_pref.ptr;
-                SP.me = (double*)ws.st_me.ptr;
-                SP.bins = (unsigned short*)ws.st_bins.ptr;
-                SP.flags = (unsigned char*)ws.st_flags.ptr;
+                SP.mom = m.st_mom;
+                SP.pref = m.st_pref;
+                SP.me = m.st_me;
+                SP.bins = m.st_bins;
+                SP.flags = m.st_flags;
                 SP.first_batch = bi == 0;
-                SP.next_group = (unsigned long long*)ws.amp_counter.ptr;
+                SP.next_group = m.amp_counter;
                 hipEvent_t a = nullptr, b = nullptr;
                 if (opt->profile) {
                     a = amp_marks[2 * ((size_t)j * n_batches + bi)];
@@ -616,21 +753,21 @@ mf_status integrate_impl(const mf_process* proc, double sqrt_s, const mf_pdf_gri
             G.dw_dy = (j == n_iter - 1) ? grad->dw_dy : nullptr;
             G.dw_dmt = (j == n_iter - 1) ? grad->dw_dmt : nullptr;
             G.w_out = nullptr;
-            G.partials = (double*)ws.gpartials.ptr;
+            G.partials = m.gpartials;
             hipLaunchKernelGGL(mf::grad_kernel_ttx, dim3(n_waves / mf::kWavesPerBlock), dim3(mf::kBlock), 0, S.stream,
                                G);
             MF_HIP(hipGetLastError());
             mf::ReduceParams RG = R;
             RG.partials = G.partials;
             RG.stride = 4;
-            RG.entries = (double*)ws.gsum.ptr + 4 * (size_t)j;
+            RG.entries = m.gsum + 4 * (size_t)j;
             hipLaunchKernelGGL(mf::reduce_entries_kernel, dim3(4), dim3(mf::kReduceBlock), 0, S.stream, RG);
             MF_HIP(hipGetLastError());
         }
         if (opt->profile)
             MF_HIP(hipEventRecord(marks[3 * j + 1], S.stream));
-        R.grid_in = (const double*)ws.grid[cur].ptr;
-        R.grid_out = (double*)ws.grid[1 - cur].ptr;
+        R.grid_in = m.grid[cur];
+        R.grid_out = m.grid[1 - cur];
         R.j = j;
         hipLaunchKernelGGL(mf::reduce_entries_kernel, dim3(stride), dim3(mf::kReduceBlock), 0, S.stream, R);
         MF_HIP(hipGetLastError());
@@ -641,19 +778,19 @@ mf_status integrate_impl(const mf_process* proc, double sqrt_s, const mf_pdf_gri
         cur = 1 - cur;
     }
 
-    std::vector<double> I(n_iter), V(n_iter), npass(n_iter), stats(4), gs(grad ? 4 * (size_t)n_iter : 0);
-    MF_HIP(hipMemcpyAsync(npass.data(), ws.iter_pass.ptr, sizeof(double) * n_iter, hipMemcpyDeviceToHost, S.stream));
+    double I[kMaxIter], V[kMaxIter], npass[kMaxIter], stats[4], gs[4 * kMaxIter];
+    MF_HIP(hipMemcpyAsync(npass, m.iter_pass, sizeof(double) * n_iter, hipMemcpyDeviceToHost, S.stream));
     if (grad)
-        MF_HIP(hipMemcpyAsync(gs.data(), ws.gsum.ptr, sizeof(double) * gs.size(), hipMemcpyDeviceToHost, S.stream));
-    MF_HIP(hipMemcpyAsync(I.data(), ws.iter_I.ptr, sizeof(double) * n_iter, hipMemcpyDeviceToHost, S.stream));
-    MF_HIP(hipMemcpyAsync(V.data(), ws.iter_V.ptr, sizeof(double) * n_iter, hipMemcpyDeviceToHost, S.stream));
-    MF_HIP(hipMemcpyAsync(stats.data(), ws.stats.ptr, sizeof(double) * 4, hipMemcpyDeviceToHost, S.stream));
+        MF_HIP(hipMemcpyAsync(gs, m.gsum, sizeof(double) * 4 * n_iter, hipMemcpyDeviceToHost, S.stream));
+    MF_HIP(hipMemcpyAsync(I, m.iter_I, sizeof(double) * n_iter, hipMemcpyDeviceToHost, S.stream));
+    MF_HIP(hipMemcpyAsync(V, m.iter_V, sizeof(double) * n_iter, hipMemcpyDeviceToHost, S.stream));
+    MF_HIP(hipMemcpyAsync(stats, m.stats, sizeof(double) * 4, hipMemcpyDeviceToHost, S.stream));
     if (res->grid)
-        MF_HIP(hipMemcpyAsync(res->grid, ws.grid[cur].ptr, grid_bytes, hipMemcpyDeviceToHost, S.stream));
+        MF_HIP(hipMemcpyAsync(res->grid, m.grid[cur], grid_bytes, hipMemcpyDeviceToHost, S.stream));
     if (res->grid_last)
-        MF_HIP(hipMemcpyAsync(res->grid_last, ws.grid[1 - cur].ptr, grid_bytes, hipMemcpyDeviceToHost, S.stream));
+        MF_HIP(hipMemcpyAsync(res->grid_last, m.grid[1 - cur], grid_bytes, hipMemcpyDeviceToHost, S.stream));
     if (res->hist)
-        MF_HIP(hipMemcpyAsync(res->hist, (double*)ws.entries.ptr + mf::kPartialHead, sizeof(double) * D * (size_t)nb,
+        MF_HIP(hipMemcpyAsync(res->hist, m.entries + mf::kPartialHead, sizeof(double) * D * (size_t)nb,
                               hipMemcpyDeviceToHost, S.stream));
     MF_HIP(hipStreamSynchronize(S.stream));
     res->event_kernel_ms = 0.0;
@@ -689,31 +826,31 @@ mf_status integrate_impl(const mf_process* proc, double sqrt_s, const mf_pdf_gri
     if (opt->strict && stats[2] > 0.0)
         return fail(MF_ENOCONV, "mass-rescaling Newton iteration failed for " +
                                     std::to_string((long long)stats[2]) + " events");
-    combine(n_iter, I.data(), V.data(), &res->sigma, &res->sigma_err, &res->chi2_dof);
+    combine(n_iter, I, V, &res->sigma, &res->sigma_err, &res->chi2_dof);
     res->w_max = stats[0];
     res->n_batches = staged ? n_batches : 1;
     res->n_pass = (int64_t)stats[1];
     res->n_newton_fail = (int64_t)stats[2];
     if (res->iter_sigma)
-        std::memcpy(res->iter_sigma, I.data(), sizeof(double) * n_iter);
+        std::memcpy(res->iter_sigma, I, sizeof(double) * n_iter);
     if (res->iter_var)
-        std::memcpy(res->iter_var, V.data(), sizeof(double) * n_iter);
+        std::memcpy(res->iter_var, V, sizeof(double) * n_iter);
     if (res->iter_pass)
-        std::memcpy(res->iter_pass, npass.data(), sizeof(double) * n_iter);
+        std::memcpy(res->iter_pass, npass, sizeof(double) * n_iter);
     if (grad) {
         // Per-iteration means of dw/dtheta on frozen grids, combined with the
         // inverse-variance weights of the estimate (V_j held fixed).
-        std::vector<double> gm(n_iter), ga(n_iter);
+        double gm[kMaxIter], ga[kMaxIter];
         for (int j = 0; j < n_iter; ++j) {
             gm[j] = gs[4 * (size_t)j + 0] / (double)n_events;
             ga[j] = gs[4 * (size_t)j + 2] / (double)n_events;
         }
-        combine_fixed(n_iter, gm.data(), V.data(), &grad->dsigma_dmt);
-        combine_fixed(n_iter, ga.data(), V.data(), &grad->dsigma_dalphas);
+        combine_fixed(n_iter, gm, V, &grad->dsigma_dmt);
+        combine_fixed(n_iter, ga, V, &grad->dsigma_dalphas);
         if (grad->iter_dmt)
-            std::memcpy(grad->iter_dmt, gm.data(), sizeof(double) * n_iter);
+            std::memcpy(grad->iter_dmt, gm, sizeof(double) * n_iter);
         if (grad->iter_dalphas)
-            std::memcpy(grad->iter_dalphas, ga.data(), sizeof(double) * n_iter);
+            std::memcpy(grad->iter_dalphas, ga, sizeof(double) * n_iter);
     }
     return MF_OK;
 }
@@ -725,7 +862,13 @@ extern "C" {
 mf_status mf_integrate(const mf_process* proc, double sqrt_s, const mf_pdf_grid* pdf, uint64_t n_events,
                        int n_iter, uint64_t seed, const mf_options* opt, mf_result* res)
 {
-    return integrate_impl(proc, sqrt_s, pdf, n_events, n_iter, seed, opt, res, nullptr);
+    return integrate_impl(proc, sqrt_s, pdf, n_events, n_iter, seed, opt, res, nullptr, false);
+}
+
+mf_status mf_integrate_static(const mf_process* proc, double sqrt_s, const mf_pdf_grid* pdf, uint64_t n_events,
+                              int n_iter, uint64_t seed, const mf_options* opt, mf_result* res)
+{
+    return integrate_impl(proc, sqrt_s, pdf, n_events, n_iter, seed, opt, res, nullptr, true);
 }
 
 mf_status mf_integrate_grad(const mf_process* proc, double sqrt_s, const mf_pdf_grid* pdf, uint64_t n_events,
@@ -733,7 +876,7 @@ mf_status mf_integrate_grad(const mf_process* proc, double sqrt_s, const mf_pdf_
 {
     if (!grad)
         return fail(MF_EINVAL, "grad is NULL");
-    return integrate_impl(proc, sqrt_s, pdf, n_events, n_iter, seed, opt, res, grad);
+    return integrate_impl(proc, sqrt_s, pdf, n_events, n_iter, seed, opt, res, grad, false);
 }
 
 }  // extern "C"
@@ -771,7 +914,9 @@ mf_status fixed_grid_setup(const mf_process* proc, double sqrt_s, const mf_pdf_g
     S.D = D;
     S.ws = wsp;
     S.stream = (hipStream_t)opt->stream;
-    if ((st = prepare(proc, sqrt_s, pdf, opt, ws, S)) != MF_OK) return st;
+    Mem m;
+    if ((st = workspace_pdf(pdf, ws, m)) != MF_OK) return st;
+    if ((st = prepare(proc, sqrt_s, pdf, opt, m, S)) != MF_OK) return st;
     mf::EventParams& P = S.P;
     const size_t grid_bytes = sizeof(double) * D * (size_t)(nb + 1);
     if ((st = ensure(ws.grid[0], grid_bytes)) != MF_OK) return st;
