@@ -57,17 +57,24 @@ def me_flops(n_g, colour="full"):
     return mod.flop_count(n_g, colour)["per_event"]
 
 
-def timed_run(api, torch, proc, pdf, n_events, steps, warmup, precision, seed, colour="full"):
+def timed_run(api, torch, proc, pdf, n_events, steps, warmup, precision, seed, colour="full", grid_in=None,
+              keep_weights=True, helicity="sum"):
+    """One warm-up call of `warmup` iterations, then one timed call of `steps`
+    iterations (continuing the Philox iteration counter).  The last timed
+    iteration stores its per-event weights into a buffer allocated before the
+    timed region, as integrate returns them."""
     if warmup > 0:
         api.integrate(proc, 13000.0, pdf, n_events, warmup, seed, precision=precision,
-                      keep_weights=False, colour=colour)
+                      keep_weights=False, colour=colour, grid_in=grid_in, helicity=helicity)
+    w = torch.empty(n_events, dtype=torch.float64, device="cuda") if keep_weights else None
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
     e0.record(stream)
     r = api.integrate(proc, 13000.0, pdf, n_events, steps, seed, precision=precision,
-                      keep_weights=False, profile=True, start_iter=warmup, colour=colour)
+                      keep_weights=keep_weights, weights_out=w, profile=True, start_iter=warmup,
+                      colour=colour, grid_in=grid_in, helicity=helicity)
     e1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -153,20 +160,43 @@ def precision_error(api, torch, proc, pdf, grid, n, seed):
     return out
 
 
+# Algorithmic flops per passing event of the adjoint kernel (grad_kernel_ttx),
+# counted from its source like the forward code (+, -, x = 1, FMA = 2): per
+# helicity configuration the forward amplitudes (624) and their reverse sweep
+# (s-channel terms 480, top-exchange terms 748, amplitude adjoints 16), for 16
+# configurations; the momentum-only quantities and their reverse (about 650);
+# phase space, PDFs and weight forward and backward through the Newton root
+# (about 1000).
+ADJOINT_FLOPS = 16 * (624 + 480 + 748 + 16) + 650 + 1000
+
+
 def adjoint_run(api, torch, pdf, n_events, n_iter, seed):
     """g g -> t tbar forward integration plus the adjoint (d sigma / d m_t,
-    d sigma / d alpha_s); events/s counts forward + adjoint per event."""
+    d sigma / d alpha_s); events/s counts forward + adjoint per event.  The
+    roofline is that of the adjoint kernel from the library's HIP-event timing
+    of each of its launches."""
     proc = api.Process("gg_ttx")
     api.integrate_grad(proc, 13000.0, pdf, n_events, 1, seed)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    r, g = api.integrate_grad(proc, 13000.0, pdf, n_events, n_iter, seed)
+    r, g = api.integrate_grad(proc, 13000.0, pdf, n_events, n_iter, seed, profile=True)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    t_grad = float(np.sum(g.iter_grad_ms)) / 1e3
+    n_pass = float(np.sum(r.iter_pass))
+    achieved = n_pass * ADJOINT_FLOPS / t_grad / 1e12
     return {"workload": f"gg_ttx LO + adjoint, {n_events} events x {n_iter} iterations, FP64",
             "value": round(n_events * n_iter / dt, 2), "unit": "events/s (forward + adjoint)",
             "sigma_pb": r.sigma, "sigma_err_pb": r.sigma_err, "dsigma_dmt_pb_per_gev": g.dsigma_dmt,
-            "dsigma_dalphas_pb": g.dsigma_dalphas}
+            "dsigma_dalphas_pb": g.dsigma_dalphas,
+            "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS,
+                         "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": None,
+                         "kernel": "grad_kernel_ttx", "launches": n_iter,
+                         "avg_launch_ms": round(t_grad * 1e3 / n_iter, 3),
+                         "flops_per_passing_event": ADJOINT_FLOPS,
+                         "pass_fraction": round(n_pass / (n_iter * n_events), 4),
+                         "forward_event_kernel_ms": round((float(np.sum(r.iter_event_ms)) - t_grad * 1e3)
+                                                          / n_iter, 3)}}
 
 
 PEAK_HBM_GBS = 8000.0        # MI355X HBM3E
@@ -219,17 +249,59 @@ def unweight_run(api, torch, proc, pdf, grid, n_events, seed, n_f, reps=5):
                          "avg_launch_ms": round(tc * 1e3, 4), "bytes_per_launch": alg}}
 
 
-def cpu_baseline(wl, pdf, budget_s):
-    """The oracle on a bounded sample of the same workload: one iteration on a
-    uniform grid, sized by two calibration runs to about budget_s seconds."""
+def host_cpu():
+    """CPU model and physical core count of this host (from /proc/cpuinfo)."""
+    model, cores = None, set()
+    phys = core = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                k, _, v = line.partition(":")
+                k, v = k.strip(), v.strip()
+                if k == "model name" and model is None:
+                    model = v
+                elif k == "physical id":
+                    phys = v
+                elif k == "core id":
+                    core = v
+                elif not k and phys is not None:
+                    cores.add((phys, core))
+                    phys = core = None
+        if phys is not None:
+            cores.add((phys, core))
+    except OSError:
+        pass
+    return model, (len(cores) or None)
+
+
+def usable_cpus():
+    """Host CPUs this process may run on: its affinity mask, capped by a
+    cgroup CPU quota when one is set."""
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    try:
+        with open("/sys/fs/cgroup/cpu.max") as fh:
+            quota, period = fh.read().split()[:2]
+        if quota != "max":
+            n = min(n, max(1, math.ceil(int(quota) / int(period))))
+    except (OSError, ValueError):
+        pass
+    return max(1, n)
+
+
+def cpu_baseline(wl, pdf, budget_s, grid=None, start_iter=0):
+    """The oracle on a bounded sample of the same workload: one iteration on
+    `grid` (the GPU run's adapted grid, so that the pass fraction matches the
+    timed GPU iterations), on every host CPU the process may use, sized by
+    calibration runs to about budget_s seconds."""
     import oracle as O
-    threads = max(1, min(os.cpu_count() or 1, 16))
+    threads = usable_cpus()
     proc = O.Process(n_g=wl["n_g"], **wl["cuts"])
     n = 8 * threads
     rate = None
     for _ in range(2):
         t0 = time.perf_counter()
-        O.integrate(proc, 13000.0, pdf, n, 1, 0, n_threads=threads, keep_weights=False)
+        O.integrate(proc, 13000.0, pdf, n, 1, 0, n_threads=threads, keep_weights=False, grid=grid,
+                    start_iter=start_iter)
         dt = time.perf_counter() - t0
         rate = n / max(dt, 1e-3)
         if dt > 0.3 * budget_s:
@@ -237,11 +309,51 @@ def cpu_baseline(wl, pdf, budget_s):
         n = max(n, int(0.1 * budget_s * rate))
     n = max(n, int(budget_s * rate))
     t0 = time.perf_counter()
-    O.integrate(proc, 13000.0, pdf, n, 1, 0, n_threads=threads, keep_weights=False)
+    o = O.integrate(proc, 13000.0, pdf, n, 1, 0, n_threads=threads, keep_weights=False, grid=grid,
+                    start_iter=start_iter)
     dt = time.perf_counter() - t0
+    model, phys = host_cpu()
     return {"value": round(n / dt, 2), "unit": "events/s", "cores": threads, "kind": "oracle",
-            "sample": f"1 iteration x {n} events of {wl['process']} (same cuts, uniform grid), "
-                      f"{dt:.1f} s on {threads} host threads"}
+            "per_thread": round(n / dt / threads, 2), "host_logical_cpus": os.cpu_count(),
+            "host_physical_cores": phys, "cpu_model": model,
+            "pass_fraction": round(o.n_pass / n, 4),
+            "sample": f"1 iteration x {n} events of {wl['process']} (same cuts, "
+                      f"{'the GPU run' + chr(39) + 's adapted grid' if grid is not None else 'uniform grid'}), "
+                      f"{dt:.1f} s on {threads} threads, one per CPU this process may use (host: "
+                      f"{os.cpu_count()} logical CPUs, {phys} physical cores, {model})"}
+
+
+def config_leg(api, torch, name, n_events, n_iter, seeds, events_note=""):
+    """A workload of the parity plan timed like the headline: per seed one
+    warm-up iteration, then n_iter timed iterations; events/s over all seeds,
+    with the roofline of its dominant kernel."""
+    import workloads as W
+    wl = WORKLOADS[name]
+    pdf = W.synthetic_pdf()
+    proc = api.Process(wl["process"], **wl["cuts"])
+    f_me, f_other = me_flops(wl["n_g"]), OTHER_FLOPS[wl["n_g"]]
+    total, walls, sig, roof = 0, 0.0, [], []
+    for seed in seeds:
+        r, wall, _ = timed_run(api, torch, proc, pdf, n_events, n_iter, 1, "fp64", seed)
+        total += n_events * n_iter
+        walls += wall
+        sig.append((r.sigma, r.sigma_err, r.chi2_dof))
+        roof.append(roofline(wl["n_g"], f_me, f_other, n_events, r, PEAK_FP64_TFLOPS))
+        del r
+    torch.cuda.empty_cache()
+    best = roof[-1]
+    if len(roof) > 1:
+        # durations and flops summed over the seeds
+        t = sum(x["avg_launch_ms"] * x["launches"] for x in roof)
+        fl = sum(x["achieved"] * x["avg_launch_ms"] * x["launches"] for x in roof)
+        best = dict(roof[-1], achieved=round(fl / t, 3), frac=round(fl / t / PEAK_FP64_TFLOPS, 4),
+                    launches=sum(x["launches"] for x in roof), avg_launch_ms=round(t / sum(x["launches"] for x in roof), 3),
+                    pass_fraction=round(float(np.mean([x["pass_fraction"] for x in roof])), 4))
+    return {"workload": f"{wl['process']} at 13 TeV, {n_events} events x {n_iter} iterations, seeds "
+                        f"{list(seeds)}, FP64{events_note}",
+            "value": round(total / walls, 2), "unit": "events/s", "ms_per_step": round(walls / (n_iter * len(seeds)) * 1e3, 3),
+            "roofline": best, "sigma_pb": [s[0] for s in sig], "sigma_err_pb": [s[1] for s in sig],
+            "chi2_dof": [s[2] for s in sig]}
 
 
 def main():
@@ -263,6 +375,9 @@ def main():
     ap.add_argument("--no-leading-colour", action="store_true")
     ap.add_argument("--no-colour-mc", action="store_true")
     ap.add_argument("--adjoint-events", type=int, default=10_000_000)
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the legs of the other workloads (g g -> t tbar at 1e5 x 5 and 1e8 x 5, "
+                         "g g -> t tbar g at 1e7 x 10 for seeds 0-4)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device-to-device copy of this many bytes (3 times), "
                          "the reference kernel for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE")
@@ -324,7 +439,7 @@ def main():
         log(f"[bench] fp32 amplitudes with fp64 compensated accumulation: {args.warmup} warm-up + "
             f"{args.fp32_steps} timed iterations x {n32} events")
         r32, wall32, _ = timed_run(api, torch, proc, pdf, n32, args.fp32_steps, args.warmup,
-                                   "fp32_kahan", args.seed)
+                                   "fp32_kahan", args.seed, grid_in=r64.grid)
         v32 = args.fp32_steps * n32 / wall32
         log(f"[bench] fp32 done: {v32:.4g} events/s; error vs fp64 on {n32} events")
         err = precision_error(api, torch, proc, pdf, r64.grid, n32, args.seed + 1)
@@ -335,7 +450,8 @@ def main():
                                  f"{args.workload}_fp32_{n32}"),
             "sigma": r32.sigma, "sigma_err": r32.sigma_err,
             "error_vs_fp64": err,
-            "note": "packed FP32 disabled at compile time: FP32 issues at the FP64 vector rate",
+            "note": "on the FP64 leg's adapted grid (same pass fraction); packed FP32 instructions "
+                    "disabled at compile time, so the peak is the packed rate the code does not use",
         }
         log(f"[bench] fp32 integral rel err {err['integral_rel']:.2e}, event max {err['event_rel_max']:.2e}")
     if not args.no_leading_colour:
@@ -386,13 +502,46 @@ def main():
         }
         log(f"[bench] colour Monte Carlo ({mode}) done: {vmc:.4g} events/s, weight variance "
             f"x{var_ratio:.2f}")
+    if not args.no_colour_mc:
+        log(f"[bench] Monte Carlo over helicities, fp64: {args.warmup} warm-up + {args.steps} timed "
+            f"iterations x {n_events} events")
+        rh, wallh, _ = timed_run(api, torch, proc, pdf, n_events, args.steps, args.warmup, "fp64",
+                                 args.seed, helicity="sampled")
+        vh = args.steps * n_events / wallh
+        ws = api.integrate(proc, 13000.0, pdf, n_events, 1, args.seed, grid_in=r64.grid,
+                           start_iter=args.warmup + args.steps, helicity="sampled").weights
+        wf = api.integrate(proc, 13000.0, pdf, n_events, 1, args.seed, grid_in=r64.grid,
+                           start_iter=args.warmup + args.steps).weights
+        var_ratio = float(ws.var().item()) / float(wf.var().item())
+        del ws, wf
+        out["helicity_mc"] = {
+            "value": round(vh, 2), "unit": "events/s", "events_per_step": n_events,
+            "steps": args.steps, "ms_per_step": round(wallh / args.steps * 1e3, 3),
+            "roofline": roofline(wl["n_g"], f_me, f_other, n_events, rh, PEAK_FP64_TFLOPS),
+            "sigma": rh.sigma, "sigma_err": rh.sigma_err,
+            "weight_variance_vs_helicity_sum": round(var_ratio, 3),
+            "helicity_sum_equivalent_events_per_s": round(vh / var_ratio, 2),
+            "note": "one helicity configuration per event (Philox block 0x80000002), N_h |M_h|^2, "
+                    "unbiased; every configuration is still evaluated by the cooperative kernel (one "
+                    "lane each) and the drawn one kept, so the roofline counts the full per-event work",
+        }
+        log(f"[bench] helicity Monte Carlo done: {vh:.4g} events/s, weight variance x{var_ratio:.2f}")
+    if not args.no_configs and args.workload == "ttxgg":
+        log("[bench] g g -> t tbar, 1e5 x 5 and 1e8 x 5; g g -> t tbar g, 1e7 x 10, seeds 0-4")
+        out["ttx_1e5x5"] = config_leg(api, torch, "ttx", 100_000, 5, [0])
+        out["ttx_1e8x5"] = config_leg(api, torch, "ttx", 100_000_000, 5, [0],
+                                      " (the scaled run: 1e5 events do not fill 256 compute units)")
+        out["ttxg_1e7x10"] = config_leg(api, torch, "ttxg", 10_000_000, 10, [0, 1, 2, 3, 4])
+        log(f"[bench] configs done: ttx {out['ttx_1e8x5']['value']:.4g}, ttxg {out['ttxg_1e7x10']['value']:.4g} "
+            "events/s")
     if not args.no_adjoint:
         log(f"[bench] adjoint: gg_ttx forward + gradient, {args.adjoint_events} events x 3 iterations")
         out["adjoint"] = adjoint_run(api, torch, pdf, args.adjoint_events, 3, args.seed)
         log(f"[bench] adjoint done: {out['adjoint']['value']:.4g} events/s")
     if not args.no_cpu_baseline:
         log(f"[bench] CPU oracle baseline (~{args.cpu_seconds:.0f} s)")
-        out["cpu_baseline"] = cpu_baseline(wl, pdf, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(wl, pdf, args.cpu_seconds, grid=r64.grid,
+                                           start_iter=args.warmup + args.steps)
         log(f"[bench] cpu done: {out['cpu_baseline']['value']} events/s")
     print(json.dumps(out), flush=True)
 

@@ -82,6 +82,19 @@ typedef enum {
     MF_COLOUR_FULL = 0, MF_COLOUR_LEADING = 1, MF_COLOUR_SAMPLED = 2, MF_COLOUR_FLOW = 3
 } mf_colour;
 
+/* Helicity treatment of |M|^2.  MF_HELICITY_SAMPLED is the Monte Carlo over
+ * helicity configurations that Sec. 3.2 names (on Fig. 4) with the one over
+ * colours: every event carries one configuration h of the N_h = 2^(n_g + 2)
+ * (bit 0 top spin, bit 1 antitop spin along z in their rest frames; bit 2 + g
+ * gluon g's real linear polarisation, e1 = (0, cos th cos ph, cos th sin ph,
+ * -sin th) for 0 and e2 = (0, -sin ph, cos ph, 0) for 1, th and ph the angles
+ * of its momentum), uniform, from Philox block 0x80000002 of its counter:
+ * k the 53-bit integer of the first word pair, h = (k N_h) >> 53.  |M|^2 is
+ * N_h times the colour sum (of any mf_colour mode) for that configuration: an
+ * unbiased estimate of the helicity sum.  Needs the events' Philox counters:
+ * mf_integrate, or mf_evaluate with y = NULL (MF_EINVAL otherwise). */
+typedef enum { MF_HELICITY_SUM = 0, MF_HELICITY_SAMPLED = 1 } mf_helicity;
+
 typedef struct {
     mf_process_id id;
     double m_top;            /* GeV, > 0                                       */
@@ -116,6 +129,8 @@ typedef struct {
                                 buffers (about 170 B per event), 0 = 2^27 (0)   */
     mf_colour colour;        /* MF_COLOUR_FULL, _LEADING, _SAMPLED or _FLOW (FULL);
                                 the gradient entry points take FULL only       */
+    mf_helicity helicity;    /* MF_HELICITY_SUM or _SAMPLED (SUM); the gradient
+                                entry points take SUM only                     */
 } mf_options;
 
 typedef struct {
@@ -249,6 +264,8 @@ typedef struct {
     double *iter_dalphas;    /* host [n_iter] per-iteration mean dw/dalpha_s, may be NULL */
     double *dw_dy;           /* device [n_events][D] last iteration dw/dy, may be NULL    */
     double *dw_dmt;          /* device [n_events] last iteration dw/dm_t, may be NULL     */
+    double *iter_grad_ms;    /* host [n_iter] options->profile = 1: duration of the adjoint
+                                kernel per iteration in ms (HIP events on the stream), may be NULL */
 } mf_grad_result;
 
 /*

@@ -34,7 +34,7 @@ class mf_options(C.Structure):
     _fields_ = [("n_bins", C.c_int), ("alpha", C.c_double), ("start_iter", C.c_int),
                 ("precision", C.c_int), ("strict", C.c_int), ("max_newton", C.c_int),
                 ("grid_in", _dp), ("stream", C.c_void_p), ("profile", C.c_int),
-                ("max_batch", C.c_uint64), ("colour", C.c_int)]
+                ("max_batch", C.c_uint64), ("colour", C.c_int), ("helicity", C.c_int)]
 
 
 class mf_result(C.Structure):
@@ -48,7 +48,7 @@ class mf_result(C.Structure):
 
 class mf_grad_result(C.Structure):
     _fields_ = [("dsigma_dmt", C.c_double), ("dsigma_dalphas", C.c_double), ("iter_dmt", _dp),
-                ("iter_dalphas", _dp), ("dw_dy", _dp), ("dw_dmt", _dp)]
+                ("iter_dalphas", _dp), ("dw_dy", _dp), ("dw_dmt", _dp), ("iter_grad_ms", _dp)]
 
 
 class mf_events(C.Structure):

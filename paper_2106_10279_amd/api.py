@@ -28,6 +28,7 @@ PRECISIONS = {"fp64": MF_FP64, "fp32_kahan": MF_FP32_KAHAN}
 # colour sum: the full colour matrix, the leading-colour approximation, or a
 # Monte Carlo over colour assignments or colour flows (mf_integrate, n_g >= 3)
 COLOURS = {"full": 0, "leading": 1, "sampled": 2, "flow": 3}
+HELICITIES = {"sum": 0, "sampled": 1}
 
 _dp = C.POINTER(C.c_double)
 
@@ -76,7 +77,7 @@ def n_dims(process) -> int:
 
 
 def _options(n_bins, alpha, start_iter, precision, strict, max_newton, grid_in, stream, profile=False,
-             max_batch=0, colour="full"):
+             max_batch=0, colour="full", helicity="sum"):
     o = _lib.mf_options()
     lib.mf_default_options(C.byref(o))
     o.n_bins = n_bins
@@ -90,6 +91,7 @@ def _options(n_bins, alpha, start_iter, precision, strict, max_newton, grid_in, 
     o.profile = int(profile)
     o.max_batch = int(max_batch)
     o.colour = COLOURS.get(colour, colour)
+    o.helicity = HELICITIES.get(helicity, helicity)
     return o
 
 
@@ -119,14 +121,15 @@ def integrate(proc: Process, sqrt_s: float, pdf_table, n_events: int, n_iter: in
               n_bins: int = 50, alpha: float = 1.5, precision="fp64", start_iter: int = 0,
               grid_in=None, keep_weights: bool = True, strict: bool = False,
               max_newton: int = 50, stream=None, weights_out: torch.Tensor | None = None,
-              profile: bool = False, max_batch: int = 0, colour="full", static_scratch: bool = False):
+              profile: bool = False, max_batch: int = 0, colour="full", static_scratch: bool = False,
+              helicity="sum"):
     """VEGAS integration (mf_integrate); static_scratch=True calls
     mf_integrate_static, which allocates no device memory."""
     D = n_dims(proc.process)
     pdf = _Pdf(pdf_table)
     gin = None if grid_in is None else np.ascontiguousarray(grid_in, dtype=np.float64)
     opt = _options(n_bins, alpha, start_iter, precision, strict, max_newton, gin, stream, profile,
-                   max_batch, colour)
+                   max_batch, colour, helicity)
     I = np.zeros(n_iter)
     V = np.zeros(n_iter)
     grid = np.zeros((D, n_bins + 1))
@@ -162,13 +165,14 @@ def evaluate_weights(proc: Process, sqrt_s: float, pdf_table, n: int, seed: int 
                      event_ids: torch.Tensor | None = None, n_bins: int = 50,
                      precision="fp64", max_newton: int = 50, return_k53: bool = False,
                      return_bins: bool = False, return_record: bool = False, stream=None,
-                     colour="full"):
+                     colour="full", helicity="sum"):
     """Per-event weights (pb) for a fixed grid; optionally the Philox integers,
     the bin indices and the per-stage record (see mf_evaluate in include/mf.h)."""
     D = n_dims(proc.process)
     pdf = _Pdf(pdf_table)
     g = None if grid is None else np.ascontiguousarray(grid, dtype=np.float64)
-    opt = _options(n_bins, 1.5, 0, precision, False, max_newton, None, stream, colour=colour)
+    opt = _options(n_bins, 1.5, 0, precision, False, max_newton, None, stream, colour=colour,
+                   helicity=helicity)
     w = torch.empty(n, dtype=torch.float64, device="cuda")
     k53 = torch.empty((n, D), dtype=torch.int64, device="cuda") if return_k53 else None
     bins = torch.empty((n, D), dtype=torch.int32, device="cuda") if return_bins else None
@@ -235,18 +239,19 @@ class GradResult:
     iter_dalphas: np.ndarray
     dw_dy: torch.Tensor | None
     dw_dmt: torch.Tensor | None
+    iter_grad_ms: np.ndarray | None = None
 
 
 def integrate_grad(proc: Process, sqrt_s: float, pdf_table, n_events: int, n_iter: int, seed: int,
                    n_bins: int = 50, alpha: float = 1.5, start_iter: int = 0, grid_in=None,
                    keep_weights: bool = False, keep_event_grads: bool = False, max_newton: int = 50,
-                   stream=None):
+                   stream=None, profile: bool = False):
     """mf_integrate_grad: the integration of `integrate` (same grids and
     estimates) plus the gradient; g g -> t tbar, FP64 only."""
     D = n_dims(proc.process)
     pdf = _Pdf(pdf_table)
     gin = None if grid_in is None else np.ascontiguousarray(grid_in, dtype=np.float64)
-    opt = _options(n_bins, alpha, start_iter, "fp64", False, max_newton, gin, stream)
+    opt = _options(n_bins, alpha, start_iter, "fp64", False, max_newton, gin, stream, profile)
     I = np.zeros(n_iter)
     V = np.zeros(n_iter)
     grid = np.zeros((D, n_bins + 1))
@@ -267,12 +272,19 @@ def integrate_grad(proc: Process, sqrt_s: float, pdf_table, n_events: int, n_ite
     g.iter_dalphas = _ptr(ga)
     g.dw_dy = C.cast(C.c_void_p(dy.data_ptr()), _dp) if dy is not None else None
     g.dw_dmt = C.cast(C.c_void_p(dm.data_ptr()), _dp) if dm is not None else None
+    gms = np.zeros(n_iter)
+    g.iter_grad_ms = _ptr(gms)
+    tms = np.zeros(n_iter)
+    res.iter_event_ms = _ptr(tms)
+    npass = np.zeros(n_iter)
+    res.iter_pass = _ptr(npass)
     pc = proc.c()
     check(lib.mf_integrate_grad(C.byref(pc), sqrt_s, C.byref(pdf.c), n_events, n_iter, seed,
                                 C.byref(opt), C.byref(res), C.byref(g)))
     r = IntegrationResult(res.sigma, res.sigma_err, res.chi2_dof, res.w_max, res.n_pass,
-                          res.n_newton_fail, I, V, grid, hist, w)
-    return r, GradResult(g.dsigma_dmt, g.dsigma_dalphas, gm, ga, dy, dm)
+                          res.n_newton_fail, I, V, grid, hist, w, res.event_kernel_ms, res.reduce_kernel_ms,
+                          npass, tms if profile else None)
+    return r, GradResult(g.dsigma_dmt, g.dsigma_dalphas, gm, ga, dy, dm, gms if profile else None)
 
 
 def evaluate_weights_grad(proc: Process, sqrt_s: float, pdf_table, n: int, seed: int = 0, it: int = 0,

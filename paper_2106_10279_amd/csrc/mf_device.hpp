@@ -416,6 +416,20 @@ __device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t
     r[0] = c0; r[1] = c1; r[2] = c2; r[3] = c3;
 }
 
+// Monte Carlo over helicities: the configuration of event `event` (bit 0 top
+// spin, bit 1 antitop spin, bit 2 + g gluon g's linear polarisation), uniform
+// over n_hel: Philox block 0x80000002 of its counter, k the 53-bit integer of
+// the first word pair, h = (k n_hel) >> 53 (Sec. 3.2 on Fig. 4 names the
+// sampling of helicity configurations).
+__device__ __forceinline__ int hel_config(uint64_t event, uint64_t seed, uint32_t iter, int n_hel)
+{
+    uint32_t r[4];
+    philox4x32_10((uint32_t)event, (uint32_t)(event >> 32), iter, 0x80000002u, (uint32_t)seed,
+                  (uint32_t)(seed >> 32), r);
+    const uint64_t k = ((((uint64_t)r[0]) << 32) | (uint64_t)r[1]) >> 11;
+    return (int)((k * (uint64_t)n_hel) >> 53);
+}
+
 // ---------------------------------------------------------------------------
 // Compensated accumulation.
 // ---------------------------------------------------------------------------

@@ -59,7 +59,19 @@ struct EventParams {
     double* record;                  // [n][8 + 4 NF] per-stage record or null
     int stride;
     int n_waves;
+    int hel_mc;                      // 1: Monte Carlo over helicity configurations
 };
+
+// Monte Carlo over helicities: lane `h` of an event holds the colour sum of
+// |M_h|^2 for configuration h; with sampling only the event's drawn
+// configuration counts, scaled by the number of configurations, so that the
+// group sum over the event's lanes is N_h |M_h*|^2 (an unbiased estimate of
+// the helicity sum).
+template <int NHEL>
+__device__ __forceinline__ double hel_sampled(double v, int h, uint64_t event, uint64_t seed, uint32_t iter)
+{
+    return h == hel_config(event, seed, iter, NHEL) ? (double)NHEL * v : 0.0;
+}
 
 // ---------------------------------------------------------------------------
 // VEGAS map.  The bin index and the position in the bin come from the exact
@@ -556,6 +568,10 @@ event_kernel(EventParams P)
                     fill_table<NG, T>(m_e, m_e[L::kMom - 1], P.m_top, P.mw, tab, obj, h);
                 wave_sync();
                 double v = event_me2<NG, T, COL>(tab, obj, h, P.m_top, live, any_live);
+                if (P.hel_mc && live) {
+                    const uint64_t ev_e = chunk * kWave + e;
+                    v = hel_sampled<L::kHel>(v, h, P.event_ids ? P.event_ids[ev_e] : ev_e, P.seed, P.iter);
+                }
                 v = group_sum(v, L::kHel);
                 if (h == 0)
                     s_me[wv][e] = v;
@@ -781,6 +797,8 @@ __device__ __forceinline__ void amp_quads_ng3(const StageParams& S)
                 }
                 wave_sync();
                 double v = event_me2<3, T, COL>(tab, obj, h, S.P.m_top, live, any_live, s_cf[sub]);
+                if (S.P.hel_mc && live)
+                    v = hel_sampled<L::kHel>(v, h, S.first + e, S.P.seed, S.P.iter);
                 v = group_sum(v, L::kHel);
                 if (h == 0 && live)
                     S.me[e] = v;
@@ -869,6 +887,8 @@ __device__ __forceinline__ void amp_groups(const StageParams& S)
             }
             wave_sync();
             double v = event_me2<NG, T, COL>(tab, obj, h, S.P.m_top, live, any_live, cf);
+            if (S.P.hel_mc && live)
+                v = hel_sampled<L::kHel>(v, h, S.first + e, S.P.seed, S.P.iter);
             v = group_sum(v, L::kHel);
             if (h == 0 && live)
                 S.me[e] = v;

@@ -228,6 +228,8 @@ mf_status validate_options(const mf_options* opt, int D)
     if (opt->colour != MF_COLOUR_FULL && opt->colour != MF_COLOUR_LEADING && opt->colour != MF_COLOUR_SAMPLED &&
         opt->colour != MF_COLOUR_FLOW)
         return fail(MF_EINVAL, "unknown colour mode");
+    if (opt->helicity != MF_HELICITY_SUM && opt->helicity != MF_HELICITY_SAMPLED)
+        return fail(MF_EINVAL, "unknown helicity mode");
     if (opt->max_batch > kStageBatch)
         return fail(MF_EINVAL, "max_batch must be at most 2^27");
     if (opt->max_newton < 0 || opt->max_newton > 1000)
@@ -306,6 +308,7 @@ mf_status prepare(const mf_process* proc, double sqrt_s, const mf_pdf_grid* pdf,
     P.me_norm = std::pow(gs2, n) / (4.0 * 64.0 * factorial(n - 2)) * mf::kGeV2ToPb;
     P.ps_const = std::pow(2.0 * mf::kPi, 4 - 3 * n) * std::pow(mf::kPi / 2.0, n - 1) /
                  (factorial(n - 1) * factorial(n - 2));
+    P.hel_mc = opt->helicity == MF_HELICITY_SAMPLED;
     return MF_OK;
 }
 
@@ -503,6 +506,7 @@ void mf_default_options(mf_options* opt)
     opt->profile = 0;
     opt->max_batch = 0;
     opt->colour = MF_COLOUR_FULL;
+    opt->helicity = MF_HELICITY_SUM;
 }
 
 int mf_n_dims(int process_id)
@@ -546,6 +550,8 @@ mf_status integrate_impl(const mf_process* proc, double sqrt_s, const mf_pdf_gri
             return fail(MF_EUNSUPPORTED, "gradients are computed in FP64 only");
         if (opt->colour != MF_COLOUR_FULL)
             return fail(MF_EUNSUPPORTED, "gradients are computed with the full colour sum only");
+        if (opt->helicity != MF_HELICITY_SUM)
+            return fail(MF_EUNSUPPORTED, "gradients are computed with the full helicity sum only");
     }
     const int nb = opt->n_bins;
     if (fixed_scratch) {
@@ -699,11 +705,16 @@ mf_status integrate_impl(const mf_process* proc, double sqrt_s, const mf_pdf_gri
 
     // Optional per-kernel timing: events recorded on the stream around every
     // launch (marks[3j] .. marks[3j+2]).
-    std::vector<hipEvent_t> marks, amp_marks;
+    std::vector<hipEvent_t> marks, amp_marks, grad_marks;
     if (opt->profile) {
         marks.resize(3 * (size_t)n_iter);
         for (auto& ev : marks)
             MF_HIP(hipEventCreate(&ev));
+        if (grad) {
+            grad_marks.resize(2 * (size_t)n_iter);
+            for (auto& ev : grad_marks)
+                MF_HIP(hipEventCreate(&ev));
+        }
         if (staged) {
             amp_marks.resize(2 * (size_t)n_iter * n_batches);
             for (auto& ev : amp_marks)
@@ -754,9 +765,13 @@ mf_status integrate_impl(const mf_process* proc, double sqrt_s, const mf_pdf_gri
             G.dw_dmt = (j == n_iter - 1) ? grad->dw_dmt : nullptr;
             G.w_out = nullptr;
             G.partials = m.gpartials;
+            if (opt->profile)
+                MF_HIP(hipEventRecord(grad_marks[2 * j], S.stream));
             hipLaunchKernelGGL(mf::grad_kernel_ttx, dim3(n_waves / mf::kWavesPerBlock), dim3(mf::kBlock), 0, S.stream,
                                G);
             MF_HIP(hipGetLastError());
+            if (opt->profile)
+                MF_HIP(hipEventRecord(grad_marks[2 * j + 1], S.stream));
             mf::ReduceParams RG = R;
             RG.partials = G.partials;
             RG.stride = 4;
@@ -817,9 +832,17 @@ mf_status integrate_impl(const mf_process* proc, double sqrt_s, const mf_pdf_gri
             if (res->iter_amp_ms)
                 res->iter_amp_ms[j] = amp;
         }
+        if (grad && grad->iter_grad_ms)
+            for (int j = 0; j < n_iter; ++j) {
+                float c = 0.f;
+                MF_HIP(hipEventElapsedTime(&c, grad_marks[2 * j], grad_marks[2 * j + 1]));
+                grad->iter_grad_ms[j] = c;
+            }
         for (auto& ev : marks)
             (void)hipEventDestroy(ev);
         for (auto& ev : amp_marks)
+            (void)hipEventDestroy(ev);
+        for (auto& ev : grad_marks)
             (void)hipEventDestroy(ev);
     }
 
@@ -955,6 +978,8 @@ mf_status mf_evaluate(const mf_process* proc, double sqrt_s, const mf_pdf_grid* 
         return fail(MF_EINVAL, "w_out is NULL");
     if (opt && (opt->colour == MF_COLOUR_SAMPLED || opt->colour == MF_COLOUR_FLOW))
         return fail(MF_EUNSUPPORTED, "the Monte Carlo over colours runs in mf_integrate only");
+    if (opt && opt->helicity == MF_HELICITY_SAMPLED && y)
+        return fail(MF_EINVAL, "the Monte Carlo over helicities needs the events' Philox counters (y must be NULL)");
     std::unique_lock<std::mutex> lock;
     Setup S;
     mf_status st;
@@ -983,6 +1008,8 @@ mf_status mf_evaluate_grad(const mf_process* proc, double sqrt_s, const mf_pdf_g
         return fail(MF_EUNSUPPORTED, "gradients are computed in FP64 only");
     if (opt && opt->colour != MF_COLOUR_FULL)
         return fail(MF_EUNSUPPORTED, "gradients are computed with the full colour sum only");
+    if (opt && opt->helicity != MF_HELICITY_SUM)
+        return fail(MF_EUNSUPPORTED, "gradients are computed with the full helicity sum only");
     std::unique_lock<std::mutex> lock;
     Setup S;
     mf_status st;
