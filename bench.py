@@ -114,28 +114,22 @@ def measured_traffic(key):
 
 def roofline(n_g, me_flops_event, other_flops_event, n_events, r, peak, traffic_key=None):
     """Roofline of the dominant kernel over the timed iterations, from its
-    HIP-event durations recorded on the library's stream.  For n_g >= 3 that
-    is amp_kernel (helicity amplitudes and colour sum of the events that pass
-    threshold and cuts); for n_g = 2 the fused event kernel (amplitudes of the
-    passing events plus phase space, PDF and accumulation of all events)."""
-    launches = len(r.iter_event_ms) * (r.n_batches if n_g >= 3 else 1)
+    HIP-event durations recorded on the library's stream: amp_kernel, the
+    helicity amplitudes and colour sum of the events that pass threshold and
+    cuts (mf_integrate runs phase space, amplitudes and accumulation as three
+    kernels for every process)."""
+    launches = len(r.iter_event_ms) * r.n_batches
     n_pass = float(np.sum(r.iter_pass))
-    if n_g >= 3:
-        t_s = float(np.sum(r.iter_amp_ms)) / 1e3
-        flops = n_pass * me_flops_event
-        kernel = "amp_kernel"
-    else:
-        t_s = float(np.sum(r.iter_event_ms)) / 1e3
-        flops = n_pass * me_flops_event + len(r.iter_event_ms) * n_events * other_flops_event
-        kernel = "event_kernel"
+    t_s = float(np.sum(r.iter_amp_ms)) / 1e3
+    flops = n_pass * me_flops_event
     achieved = flops / t_s / 1e12
     t_all = float(np.sum(r.iter_event_ms)) / 1e3
     all_flops = n_pass * me_flops_event + len(r.iter_event_ms) * n_events * other_flops_event
     return {"bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
             "frac": round(achieved / peak, 4),
             "traffic": measured_traffic(traffic_key) if traffic_key else None,
-            "kernel": kernel, "launches": launches, "avg_launch_ms": round(t_s * 1e3 / launches, 3),
-            "flops_per_passing_event": me_flops_event if n_g >= 3 else me_flops_event + other_flops_event,
+            "kernel": "amp_kernel", "launches": launches, "avg_launch_ms": round(t_s * 1e3 / launches, 3),
+            "flops_per_passing_event": me_flops_event,
             "pass_fraction": round(n_pass / (len(r.iter_event_ms) * n_events), 4),
             "per_event_kernels": {"ms_per_iteration": round(t_all * 1e3 / len(r.iter_event_ms), 3),
                                   "achieved_tflops": round(all_flops / t_all / 1e12, 3)}}

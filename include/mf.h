@@ -125,7 +125,7 @@ typedef struct {
     const double *grid_in;   /* host [D][n_bins+1] start grid, NULL = uniform   */
     void *stream;            /* hipStream_t or NULL                             */
     int profile;             /* 1: time every kernel with HIP events (0)        */
-    uint64_t max_batch;      /* n_g >= 3: events per batch of the per-event device
+    uint64_t max_batch;      /* mf_integrate: events per batch of the per-event device
                                 buffers (about 170 B per event), 0 = 2^27 (0)   */
     mf_colour colour;        /* MF_COLOUR_FULL, _LEADING, _SAMPLED or _FLOW (FULL);
                                 the gradient entry points take FULL only       */
@@ -148,8 +148,8 @@ typedef struct {
     double *iter_pass;       /* host [n_iter] events passing threshold and cuts per iteration, may be NULL */
     double *iter_event_ms;   /* host [n_iter] profile = 1: time of the per-event kernels per iteration, ms, may be NULL */
     double *iter_amp_ms;     /* host [n_iter] profile = 1: of which the helicity-amplitude code, ms, may be NULL
-                                (n_g >= 3 run it as a kernel of its own; for n_g = 2 it equals iter_event_ms) */
-    uint64_t n_batches;      /* event batches per iteration (n_g >= 3: up to 2^27 events each), else 1 */
+                                (mf_integrate runs it as a kernel of its own between phase space and accumulation) */
+    uint64_t n_batches;      /* event batches per iteration (up to 2^27 events each, or max_batch) */
     double *grid_last;       /* host [D][n_bins+1] the grid the last iteration ran on (the one
                                 its weights belong to), may be NULL */
 } mf_result;
@@ -185,7 +185,7 @@ mf_status mf_integrate(const mf_process *proc, double sqrt_s, const mf_pdf_grid 
  * call on that device: calls that overlap on one device race, so the caller
  * serialises them (the library's per-device lock does so within one process).
  * The array holds the PDF table, both grids, the per-iteration results, the
- * per-wave partial sums and, for n_g >= 3, the per-event hand-over of one
+ * per-wave partial sums and the per-event hand-over of one
  * batch of events, which takes the room the rest leaves.  The partial sums
  * take 256 (8 + n_dims n_bins) bytes per compute unit (33 MB for
  * g g -> t tbar g g on 256 compute units, leaving a batch of about 3.8e5

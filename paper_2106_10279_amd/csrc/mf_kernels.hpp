@@ -906,7 +906,7 @@ __device__ __forceinline__ void amp_groups(const StageParams& S)
 
 // The amplitude kernel: quads of events for t tbar g, single events for t tbar g g.
 template <int NG, typename T, int COL = 0>
-__global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 || NG == 3 ? 4 : 2))) amp_kernel(StageParams S)
+__global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 || NG <= 3 ? 4 : 2))) amp_kernel(StageParams S)
 {
     if constexpr (NG == 3)
         amp_quads_ng3<T, COL>(S);

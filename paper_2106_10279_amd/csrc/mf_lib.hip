@@ -392,6 +392,9 @@ mf_status launch_stages_prec(mf_precision prec, const mf::StageParams& S, int ki
 mf_status dispatch_stages(int ng, mf_precision prec, mf_colour col, const mf::StageParams& S, int kin_blocks,
                           int n_cu, hipStream_t s, hipEvent_t a, hipEvent_t b)
 {
+    if (ng == 2)
+        return col == MF_COLOUR_LEADING ? launch_stages_prec<2, 1>(prec, S, kin_blocks, n_cu, s, a, b)
+                                        : launch_stages_prec<2, 0>(prec, S, kin_blocks, n_cu, s, a, b);
     if (ng == 3) {
         if (col == MF_COLOUR_SAMPLED)
             return launch_stages_prec<3, 2>(prec, S, kin_blocks, n_cu, s, a, b);
@@ -574,7 +577,9 @@ mf_status integrate_impl(const mf_process* proc, double sqrt_s, const mf_pdf_gri
     const int n_waves = waves_for(n_chunks, ws.n_cu);
     const int stride = mf::kPartialHead + D * nb;
     const size_t grid_bytes = sizeof(double) * D * (size_t)(nb + 1);
-    const bool staged = ng >= 3;
+    // every process runs as three kernels per batch: phase space, amplitudes,
+    // accumulation (mf_evaluate keeps the fused kernel)
+    const bool staged = true;
     const int nf = ng;
     uint64_t cap = opt->max_batch ? opt->max_batch : kStageBatch;
     Mem m;

@@ -217,15 +217,18 @@ def test_newton_failure_counted_and_strict(api, pdf_table):
     assert e.value.status == _lib.MF_ENOCONV
 
 
-@pytest.mark.parametrize("n_g", [3, 4])
+@pytest.mark.parametrize("n_g", [2, 3, 4])
 def test_three_kernel_integration_weights_equal_the_fused_kernel(api, pdf_table, n_g):
-    """For t tbar g and t tbar g g the integration runs phase space, amplitudes
-    and accumulation as three kernels; its per-event weights are bit for bit
-    those of the fused event kernel (mf_evaluate) on the same events and grid,
-    also when the iteration is split into many batches."""
+    """The integration runs phase space, amplitudes and accumulation as three
+    kernels; its per-event weights are bit for bit those of the fused event
+    kernel (mf_evaluate) on the same events and grid, also when the iteration
+    is split into many batches."""
     import torch
-    proc = api.Process({3: "gg_ttxg", 4: "gg_ttxgg"}[n_g], ptmin_g=20.0,
-                       etamax_g=2.5 if n_g == 3 else 0.0, drmin_gg=0.4 if n_g == 4 else 0.0)
+    if n_g == 2:
+        proc = api.Process("gg_ttx")
+    else:
+        proc = api.Process({3: "gg_ttxg", 4: "gg_ttxgg"}[n_g], ptmin_g=20.0,
+                           etamax_g=2.5 if n_g == 3 else 0.0, drmin_gg=0.4 if n_g == 4 else 0.0)
     N = 5000
     g1 = api.integrate(proc, SQRT_S, pdf_table, N, 1, 0, keep_weights=False).grid
     r = api.integrate(proc, SQRT_S, pdf_table, N, 2, 0, keep_weights=True)
