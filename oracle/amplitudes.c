@@ -94,12 +94,87 @@ void mfo_orderings(int n_g, int *perm)
     }
 }
 
+/* Lexicographic index of a permutation of 0..n-1. */
+static int perm_index(int n, const int *p)
+{
+    int idx = 0;
+    for (int i = 0; i < n; ++i) {
+        int smaller = 0;
+        for (int j = i + 1; j < n; ++j)
+            if (p[j] < p[i]) ++smaller;
+        idx = idx * (n - i) + smaller;
+    }
+    return idx;
+}
+
+/* The same matrix from its first row: the sum over all adjoint indices is
+ * unchanged by relabelling the gluons, so C_{sigma tau} = C_{id, sigma^-1 tau}
+ * with (sigma^-1 tau)_k = sigma^-1(tau_k); the first row is summed by brute
+ * force over the 8^n assignments. */
+void mfo_colour_matrix_relabel(int n_g, double *C)
+{
+    cplx T[8][3][3];
+    gell_mann_T(T);
+    int nperm = mfo_n_orderings(n_g);
+    int *perm = malloc(sizeof(int) * nperm * n_g);
+    mfo_orderings(n_g, perm);
+    double *row = calloc((size_t)nperm, sizeof(double));
+    int total = 1;
+    for (int i = 0; i < n_g; ++i)
+        total *= 8;
+    int a[MFO_MAX_G];
+    for (int code = 0; code < total; ++code) {
+        int c = code;
+        for (int i = 0; i < n_g; ++i) {
+            a[i] = c % 8;
+            c /= 8;
+        }
+        cplx P0[3][3], P[3][3];
+        memcpy(P0, T[a[0]], sizeof(cplx) * 9);
+        for (int l = 1; l < n_g; ++l)
+            mat3_mul(P0, T[a[l]], P0);
+        for (int t = 0; t < nperm; ++t) {
+            const int *tg = perm + t * n_g;
+            memcpy(P, T[a[tg[0]]], sizeof(cplx) * 9);
+            for (int l = 1; l < n_g; ++l)
+                mat3_mul(P, T[a[tg[l]]], P);
+            cplx tr = 0;
+            for (int i = 0; i < 3; ++i)
+                for (int j = 0; j < 3; ++j)
+                    tr += conj(P0[i][j]) * P[i][j];
+            row[t] += creal(tr);
+        }
+    }
+    double den = pow(6.0, n_g);
+    for (int s = 0; s < nperm; ++s) {
+        const int *sg = perm + s * n_g;
+        int inv[MFO_MAX_G], q[MFO_MAX_G];
+        for (int k = 0; k < n_g; ++k)
+            inv[sg[k]] = k;
+        for (int t = 0; t < nperm; ++t) {
+            const int *tg = perm + t * n_g;
+            for (int k = 0; k < n_g; ++k)
+                q[k] = inv[tg[k]];
+            C[s * nperm + t] = nearbyint(row[perm_index(n_g, q)] * den) / den;
+        }
+    }
+    free(row);
+    free(perm);
+}
+
 /* C_{sigma sigma'} = sum over all adjoint indices and i, j of
  * conj((T^sigma)_{ij}) (T^sigma')_{ij}, by brute force over the 8^n
  * assignments of Gell-Mann generators.  The exact value is a rational
- * number with denominator dividing 6^n; the sum is rounded to it once. */
+ * number with denominator dividing 6^n; the sum is rounded to it once.
+ * For five gluons (120 orderings) the matrix is built from its first row
+ * (mfo_colour_matrix_relabel), which the tests check against this full
+ * sum for two to four gluons. */
 void mfo_colour_matrix(int n_g, double *C)
 {
+    if (n_g >= 5) {
+        mfo_colour_matrix_relabel(n_g, C);
+        return;
+    }
     cplx T[8][3][3];
     gell_mann_T(T);
     int nperm = mfo_n_orderings(n_g);
@@ -282,7 +357,7 @@ static __thread int pol_linear;
 /* Colour-ordered Berends-Giele recursion                                    */
 /* ------------------------------------------------------------------------ */
 
-#define MAXCODE 625    /* codes of ordered gluon sequences, base n+1 <= 5 */
+#define MAXCODE 7776   /* codes of ordered gluon sequences, base n+1 <= 6 */
 
 typedef struct {
     int n;
@@ -467,7 +542,7 @@ void mfo_partial_amplitudes(int n_g, const double *p, double m, double width,
 }
 
 static pthread_mutex_t colour_lock = PTHREAD_MUTEX_INITIALIZER;
-static double colour_cache[MFO_MAX_G + 1][24 * 24];
+static double colour_cache[MFO_MAX_G + 1][120 * 120];
 static int colour_ready[MFO_MAX_G + 1];
 
 static const double *colour_matrix_cached(int n_g)
@@ -774,7 +849,8 @@ static void flow_factors_of_code(int n_g, int64_t code, const int *perm, int npe
 
 static void flow_init(void)
 {
-    for (int n_g = 2; n_g <= MFO_MAX_G; ++n_g) {
+    /* flows are tabulated for up to four gluons (9^(n+1) codes each) */
+    for (int n_g = 2; n_g <= 4; ++n_g) {
         int64_t total = 9;
         for (int g = 0; g < n_g; ++g)
             total *= 9;
@@ -804,7 +880,7 @@ static void flow_init(void)
 
 int64_t mfo_flow_count(int n_g)
 {
-    if (n_g < 2 || n_g > MFO_MAX_G)
+    if (n_g < 2 || n_g > 4)
         return -1;
     pthread_once(&flow_once, flow_init);
     return flow_n[n_g];
@@ -875,7 +951,7 @@ double mfo_me2_sum_colour_flow(int n_g, const double *p, double m, double width,
 double mfo_me2_sum(int n_g, const double *p, double m, double width)
 {
     int nh = 1 << (n_g + 2);
-    int hel[64 * (MFO_MAX_G + 2)];
+    int hel[(4 << MFO_MAX_G) * (MFO_MAX_G + 2)];
     for (int h = 0; h < nh; ++h)
         hel_from_index(n_g, h, hel + h * (n_g + 2));
     return mfo_me2_sum_hel(n_g, p, m, width, nh, hel);
@@ -1026,11 +1102,10 @@ static void colour_contract(const fc_state *st, int S, cplx K[3][3][4])
             }
 }
 
-double mfo_me2_sum_fullcolour(int n_g, const double *p, double m, double width,
-                              int n_hel, const int *hel_list)
+/* Colour constants of the Feynman-rule evaluation: generators, f^abc and
+ * sum_e f^abe f^cde. */
+static void fc_init(fc_state *st, int n_g, const double *p, double m, double width)
 {
-    init_gamma();
-    fc_state *st = malloc(sizeof(fc_state));
     st->n = n_g;
     st->p = p;
     st->m = m;
@@ -1060,7 +1135,81 @@ double mfo_me2_sum_fullcolour(int n_g, const double *p, double m, double width,
                         s += st->f[a][b][e] * st->f[c][d][e];
                     st->ff[a][b][c][d] = s;
                 }
+}
+
+/* M_ij for the external colours st->col and polarisations st->eps: the
+ * colour-dressed amplitude with top colour i and antitop anticolour j. */
+static void fc_Mij(fc_state *st, const double *p, double m, double width, const cplx *ubar, const cplx *v,
+                   cplx Mij[3][3])
+{
+    int n_g = st->n;
     int full = (1 << n_g) - 1;
+    memset(st->Jdone, 0, sizeof(st->Jdone));
+    /* colour-dressed fermion currents U[S][top colour][line colour][4] */
+    cplx U[1 << MFO_MAX_G][3][3][4];
+    memset(U, 0, sizeof(U));
+    for (int it = 0; it < 3; ++it)
+        memcpy(U[0][it][it], ubar, sizeof(cplx) * 4);
+    /* subsets in increasing order: every proper subset of S precedes S */
+    for (int S = 1; S < full; ++S) {
+        double P[4];
+        subset_momentum(st, S, P);
+        for (int mu = 0; mu < 4; ++mu)
+            P[mu] += p[mu];
+        cplx acc[3][3][4];
+        memset(acc, 0, sizeof(acc));
+        for (int S2 = S; S2 > 0; S2 = (S2 - 1) & S) {
+            int S1 = S & ~S2;
+            fc_current(st, S2);
+            cplx K[3][3][4];
+            colour_contract(st, S2, K);
+            for (int cp = 0; cp < 3; ++cp)
+                for (int cc = 0; cc < 3; ++cc) {
+                    if (is_zero4(K[cp][cc])) continue;
+                    cplx Sl[4][4];
+                    slash(K[cp][cc], Sl);
+                    for (int it = 0; it < 3; ++it) {
+                        cplx t[4];
+                        row_times(U[S1][it][cp], Sl, t);
+                        for (int i = 0; i < 4; ++i)
+                            acc[it][cc][i] += I * t[i];
+                    }
+                }
+        }
+        bg_state tmp;          /* only m, width used by the propagator */
+        tmp.m = m;
+        tmp.width = width;
+        for (int it = 0; it < 3; ++it)
+            for (int cc = 0; cc < 3; ++cc)
+                fermion_propagate(&tmp, P, acc[it][cc], U[S][it][cc]);
+    }
+    /* close the line on v(k_tbar) with antitop colour j */
+    memset(Mij, 0, sizeof(cplx) * 9);
+    for (int S2 = full; S2 > 0; S2 = (S2 - 1) & full) {
+        int S1 = full & ~S2;
+        fc_current(st, S2);
+        cplx K[3][3][4];
+        colour_contract(st, S2, K);
+        for (int cp = 0; cp < 3; ++cp)
+            for (int jj = 0; jj < 3; ++jj) {
+                if (is_zero4(K[cp][jj])) continue;
+                cplx Sl[4][4];
+                slash(K[cp][jj], Sl);
+                for (int it = 0; it < 3; ++it) {
+                    cplx t[4];
+                    row_times(U[S1][it][cp], Sl, t);
+                    Mij[it][jj] += I * row_dot_col(t, v);
+                }
+            }
+    }
+}
+
+double mfo_me2_sum_fullcolour(int n_g, const double *p, double m, double width,
+                              int n_hel, const int *hel_list)
+{
+    init_gamma();
+    fc_state *st = malloc(sizeof(fc_state));
+    fc_init(st, n_g, p, m, width);
     int total_col = 1;
     for (int i = 0; i < n_g; ++i)
         total_col *= 8;
@@ -1078,65 +1227,8 @@ double mfo_me2_sum_fullcolour(int n_g, const double *p, double m, double width,
                 st->col[g] = c % 8;
                 c /= 8;
             }
-            memset(st->Jdone, 0, sizeof(st->Jdone));
-            /* colour-dressed fermion currents U[S][top colour][line colour][4] */
-            cplx U[1 << MFO_MAX_G][3][3][4];
-            memset(U, 0, sizeof(U));
-            for (int it = 0; it < 3; ++it)
-                memcpy(U[0][it][it], ubar, sizeof(cplx) * 4);
-            /* subsets in increasing order: every proper subset of S precedes S */
-            for (int S = 1; S < full; ++S) {
-                double P[4];
-                subset_momentum(st, S, P);
-                for (int mu = 0; mu < 4; ++mu)
-                    P[mu] += p[mu];
-                cplx acc[3][3][4];
-                memset(acc, 0, sizeof(acc));
-                for (int S2 = S; S2 > 0; S2 = (S2 - 1) & S) {
-                    int S1 = S & ~S2;
-                    fc_current(st, S2);
-                    cplx K[3][3][4];
-                    colour_contract(st, S2, K);
-                    for (int cp = 0; cp < 3; ++cp)
-                        for (int cc = 0; cc < 3; ++cc) {
-                            if (is_zero4(K[cp][cc])) continue;
-                            cplx Sl[4][4];
-                            slash(K[cp][cc], Sl);
-                            for (int it = 0; it < 3; ++it) {
-                                cplx t[4];
-                                row_times(U[S1][it][cp], Sl, t);
-                                for (int i = 0; i < 4; ++i)
-                                    acc[it][cc][i] += I * t[i];
-                            }
-                        }
-                }
-                bg_state tmp;          /* only m, width used by the propagator */
-                tmp.m = m;
-                tmp.width = width;
-                for (int it = 0; it < 3; ++it)
-                    for (int cc = 0; cc < 3; ++cc)
-                        fermion_propagate(&tmp, P, acc[it][cc], U[S][it][cc]);
-            }
-            /* close the line on v(k_tbar) with antitop colour j */
             cplx Mij[3][3];
-            memset(Mij, 0, sizeof(Mij));
-            for (int S2 = full; S2 > 0; S2 = (S2 - 1) & full) {
-                int S1 = full & ~S2;
-                fc_current(st, S2);
-                cplx K[3][3][4];
-                colour_contract(st, S2, K);
-                for (int cp = 0; cp < 3; ++cp)
-                    for (int jj = 0; jj < 3; ++jj) {
-                        if (is_zero4(K[cp][jj])) continue;
-                        cplx Sl[4][4];
-                        slash(K[cp][jj], Sl);
-                        for (int it = 0; it < 3; ++it) {
-                            cplx t[4];
-                            row_times(U[S1][it][cp], Sl, t);
-                            Mij[it][jj] += I * row_dot_col(t, v);
-                        }
-                    }
-            }
+            fc_Mij(st, p, m, width, ubar, v, Mij);
             for (int it = 0; it < 3; ++it)
                 for (int jj = 0; jj < 3; ++jj)
                     total += creal(Mij[it][jj] * conj(Mij[it][jj]));
@@ -1144,4 +1236,30 @@ double mfo_me2_sum_fullcolour(int n_g, const double *p, double m, double width,
     }
     free(st);
     return total;
+}
+
+/* The colour-dressed amplitude M_ij (Feynman rules with explicit SU(3)
+ * indices, helicity polarisations) for gluon adjoint indices cols[0 .. n-1],
+ * top colour i, antitop anticolour j: out[2 (3 i + j)] re, [+1] im. */
+void mfo_dressed_amplitude(int n_g, const double *p, double m, double width, const int *hel, const int *cols,
+                           double *out)
+{
+    init_gamma();
+    fc_state *st = malloc(sizeof(fc_state));
+    fc_init(st, n_g, p, m, width);
+    for (int g = 0; g < n_g; ++g) {
+        polarisation(p + 4 * (2 + g), hel[2 + g], st->eps[g]);
+        st->col[g] = cols[g];
+    }
+    cplx ubar[4], v[4];
+    spinor_ubar(p, m, hel[0], ubar);
+    spinor_v(p + 4, m, hel[1], v);
+    cplx Mij[3][3];
+    fc_Mij(st, p, m, width, ubar, v, Mij);
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            out[2 * (3 * i + j)] = creal(Mij[i][j]);
+            out[2 * (3 * i + j) + 1] = cimag(Mij[i][j]);
+        }
+    free(st);
 }

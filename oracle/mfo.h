@@ -32,9 +32,9 @@
 extern "C" {
 #endif
 
-#define MFO_MAX_G   4          /* gluons in the process (2, 3 or 4)          */
-#define MFO_MAX_F   4          /* final-state particles                      */
-#define MFO_MAX_DIM 10         /* integration dimensions 2 + 3 n_f - 4       */
+#define MFO_MAX_G   5          /* gluons in the process (2 .. 5)             */
+#define MFO_MAX_F   5          /* final-state particles                      */
+#define MFO_MAX_DIM 13         /* integration dimensions 2 + 3 n_f - 4       */
 
 typedef struct {
     int    n_g;                /* total gluons: 2 (tt), 3 (ttg), 4 (ttgg)     */
@@ -116,6 +116,15 @@ double mfo_pdf_xf(const mfo_pdf_grid *g, double x, double q2);
 int  mfo_n_orderings(int n_g);
 void mfo_orderings(int n_g, int *perm);           /* [n_g!][n_g], 0-based     */
 void mfo_colour_matrix(int n_g, double *C);       /* [n_g!][n_g!]            */
+/* The same matrix from its brute-force first row and the relabelling
+ * symmetry C_{sigma tau} = C_{id, sigma^-1 tau} (used for five gluons). */
+void mfo_colour_matrix_relabel(int n_g, double *C);
+/* Colour-dressed amplitude M_ij from Feynman rules with explicit SU(3)
+ * indices for one assignment of gluon adjoint indices cols[n_g] (0 .. 7) and
+ * helicity configuration hel: out[2 (3 i + j)] = Re M_ij, [+1] = Im, i the
+ * top colour, j the antitop anticolour. */
+void mfo_dressed_amplitude(int n_g, const double *p, double m, double width, const int *hel,
+                           const int *cols, double *out);
 /* Colour-ordered partial amplitudes for one helicity configuration.
  * p: [n_g+2][4] all-outgoing momenta; hel: [n_g+2] (0/1 for each slot);
  * ward_gluon >= 0 replaces that gluon's polarisation by its momentum.

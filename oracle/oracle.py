@@ -33,11 +33,11 @@ class _Pdf(C.Structure):
 
 
 class _Event(C.Structure):
-    _fields_ = [("y", C.c_double * 10), ("bin", C.c_int * 10), ("x", C.c_double * 10),
+    _fields_ = [("y", C.c_double * 13), ("bin", C.c_int * 13), ("x", C.c_double * 13),
                 ("jac", C.c_double), ("x1", C.c_double), ("x2", C.c_double),
                 ("shat", C.c_double), ("ps_weight", C.c_double), ("f1", C.c_double),
                 ("f2", C.c_double), ("me2", C.c_double), ("w", C.c_double),
-                ("k", C.c_double * 16), ("pass_threshold", C.c_int), ("pass_cuts", C.c_int),
+                ("k", C.c_double * 20), ("pass_threshold", C.c_int), ("pass_cuts", C.c_int),
                 ("newton_fail", C.c_int), ("near_edge", C.c_int), ("ill_conditioned", C.c_int),
                 ("colour_cfg", C.c_int64), ("colour_kappa", C.c_double), ("hel_cfg", C.c_int),
                 ("newton_kappa", C.c_double)]
@@ -95,6 +95,7 @@ def lib():
         L.mfo_n_orderings.restype = C.c_int
         L.mfo_orderings.argtypes = [C.c_int, _ip]
         L.mfo_colour_matrix.argtypes = [C.c_int, _dp]
+        L.mfo_colour_matrix_relabel.argtypes = [C.c_int, _dp]
         L.mfo_partial_amplitudes.argtypes = [C.c_int, _dp, C.c_double, C.c_double, _ip,
                                              C.c_int, _dp]
         L.mfo_me2_sum.argtypes = [C.c_int, _dp, C.c_double, C.c_double]
@@ -130,6 +131,7 @@ def lib():
         L.mfo_me2_sum_sampled.restype = C.c_double
         L.mfo_me2_sum_fullcolour.argtypes = [C.c_int, _dp, C.c_double, C.c_double, C.c_int, _ip]
         L.mfo_me2_sum_fullcolour.restype = C.c_double
+        L.mfo_dressed_amplitude.argtypes = [C.c_int, _dp, C.c_double, C.c_double, _ip, _ip, _dp]
         L.mfo_n_dims.argtypes = [C.c_int]
         L.mfo_n_dims.restype = C.c_int
         L.mfo_event_weight.argtypes = [C.POINTER(_Process), C.c_double, C.POINTER(_Pdf),
@@ -242,7 +244,7 @@ class EventInfo:
 def _event_info(ev, D):
     return EventInfo(np.array(ev.y[:D]), np.array(ev.bin[:D]), np.array(ev.x[:D]), ev.jac,
                      ev.shat, ev.ps_weight, ev.f1, ev.f2, ev.me2, ev.w,
-                     np.array(ev.k[:]).reshape(4, 4), bool(ev.pass_threshold),
+                     np.array(ev.k[:]).reshape(5, 4)[:(D + 2) // 3], bool(ev.pass_threshold),
                      bool(ev.pass_cuts), bool(ev.newton_fail), bool(ev.near_edge),
                      bool(ev.ill_conditioned), ev.colour_kappa, ev.newton_kappa)
 
@@ -439,6 +441,26 @@ def me2_sum_hel(n_g, p, m, width, hels):
     p = _f64(p)
     h = np.ascontiguousarray(hels, dtype=np.int32)
     return lib().mfo_me2_sum_hel(n_g, _d(p), m, width, len(h), h.ctypes.data_as(_ip))
+
+
+def colour_matrix_relabel(n_g):
+    """The colour matrix from its first row (brute force over the 8^n_g
+    assignments) and the relabelling symmetry of the sum over adjoint indices."""
+    n = lib().mfo_n_orderings(n_g)
+    out = np.zeros((n, n))
+    lib().mfo_colour_matrix_relabel(n_g, _d(out))
+    return out
+
+
+def dressed_amplitude(n_g, p, m, width, hel, cols):
+    """[3][3] colour-dressed amplitude M_ij (Feynman rules, explicit SU(3)
+    indices) for gluon adjoint indices cols and helicity configuration hel."""
+    p = _f64(p)
+    h = np.ascontiguousarray(hel, dtype=np.int32)
+    c = np.ascontiguousarray(cols, dtype=np.int32)
+    out = np.zeros(18)
+    lib().mfo_dressed_amplitude(n_g, _d(p), m, width, h.ctypes.data_as(_ip), c.ctypes.data_as(_ip), _d(out))
+    return (out[0::2] + 1j * out[1::2]).reshape(3, 3)
 
 
 def me2_sum_fullcolour(n_g, p, m, width, hels):

@@ -41,8 +41,19 @@ static double solve_mass_ratio(int power, double r)
 {
     if (power == 1)                  /* 2u - u^2 = r */
         return 1.0 - sqrt(1.0 - r);
-    /* power == 2: 3u^2 - 2u^3 = r; u = 1/2 - sin(asin(1 - 2r)/3) */
-    return 0.5 - sin(asin(1.0 - 2.0 * r) / 3.0);
+    if (power == 2)                  /* 3u^2 - 2u^3 = r; u = 1/2 - sin(asin(1 - 2r)/3) */
+        return 0.5 - sin(asin(1.0 - 2.0 * r) / 3.0);
+    /* power 3: 4u^3 - 3u^4 = r, increasing on [0, 1]: bisection until the
+     * bracket cannot shrink (the root to the last bit) */
+    double lo = 0.0, hi = 1.0;
+    for (int it = 0; it < 200; ++it) {
+        double mid = 0.5 * (lo + hi);
+        if (mid <= lo || mid >= hi)
+            break;
+        double f = 4.0 * mid * mid * mid - 3.0 * mid * mid * mid * mid - r;
+        if (f < 0.0) lo = mid; else hi = mid;
+    }
+    return 0.5 * (lo + hi);
 }
 
 /* Boost v, given in the rest frame of Q (mass M), to the frame where Q has

@@ -158,12 +158,17 @@ def random_event(rng, n_f, wrap):
         phi0 = rng.uniform(-math.pi, math.pi)
         etas = [eta0, eta0 + rng.uniform(-0.6, 0.6)]
         phis = [phi0, phi0 + rng.uniform(-0.6, 0.6)]
+    if n_f == 5:      # a third gluon close to one of the first two
+        j = rng.integers(0, 2)
+        etas.append(etas[j] + rng.uniform(-0.6, 0.6))
+        phis.append(phis[j] + rng.uniform(-0.6, 0.6))
     return np.array(tops + [gluon(p, e, f) for p, e, f in zip(pts, etas, phis)])
 
 
 @pytest.mark.parametrize("n_f,cuts", [
     (3, (20.0, 2.5, 0.0)), (3, (20.0, 0.0, 0.0)), (3, (0.0, 2.5, 0.0)),
     (4, (20.0, 0.0, 0.4)), (4, (0.0, 0.0, 0.4)), (4, (20.0, 2.5, 0.4)), (4, (0.0, 2.5, 0.0)),
+    (5, (20.0, 0.0, 0.4)), (5, (20.0, 2.5, 0.4)),
 ])
 def test_cuts_against_independent_evaluation(n_f, cuts):
     ptmin, etamax, drmin = cuts
@@ -171,7 +176,7 @@ def test_cuts_against_independent_evaluation(n_f, cuts):
     rng = np.random.default_rng(1000 * n_f + int(10 * sum(cuts)))
     n_pass = n_fail = n_wrap_fail = compared = 0
     for t in range(4000):
-        wrap = n_f == 4 and t % 2 == 1
+        wrap = n_f >= 4 and t % 2 == 1
         k = random_event(rng, n_f, wrap)
         yb = rng.uniform(-1.5, 1.5)
         ok, near = O.cuts(proc, k, yb)
@@ -187,7 +192,7 @@ def test_cuts_against_independent_evaluation(n_f, cuts):
     assert compared > 3900
     # both sides of the cuts are exercised
     assert n_pass > 200 and n_fail > 200, (n_pass, n_fail)
-    if n_f == 4 and drmin > 0:
+    if n_f >= 4 and drmin > 0:
         assert n_wrap_fail > 100
 
 

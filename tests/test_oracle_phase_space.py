@@ -23,7 +23,7 @@ def test_massless_volume_closed_form():
     assert abs(O.massless_volume(4, 2.0) / (1.32966e-7 * 4) - 1) < 1e-5
 
 
-@pytest.mark.parametrize("n_f", [2, 3, 4])
+@pytest.mark.parametrize("n_f", [2, 3, 4, 5])
 def test_momentum_conservation_and_mass_shell(n_f):
     rng = np.random.default_rng(n_f)
     masses = [M, M] + [0.0] * (n_f - 2)
@@ -49,7 +49,7 @@ def test_two_body_massive_weight_is_beta_over_8pi():
         assert abs(math.sqrt(k[0][1] ** 2 + k[0][2] ** 2 + k[0][3] ** 2) - beta * rs / 2) < 1e-12 * rs
 
 
-@pytest.mark.parametrize("n_f", [3, 4])
+@pytest.mark.parametrize("n_f", [3, 4, 5])
 def test_massless_generator_is_flat(n_f):
     """Flat massless phase space: <s_ij> = 2 s/(n(n-1)) for every pair; for n = 3
     the Dalitz plot is uniform so <s_ij^2> = s^2 / 6."""
@@ -69,6 +69,25 @@ def test_massless_generator_is_flat(n_f):
             assert abs(v.mean() - expect) < 5 * v.std() / math.sqrt(N)
             if n_f == 3:
                 assert abs((v**2).mean() - 1 / 6) < 5 * (v**2).std() / math.sqrt(N)
+
+
+@pytest.mark.parametrize("n_f", [3, 4, 5])
+def test_massless_single_particle_energy_spectrum(n_f):
+    """In flat massless n-body phase space the remaining n - 1 particles have
+    invariant mass squared s (1 - x), x = 2E/sqrt(s), and their phase space
+    grows like that to the power n - 3, so x of every particle follows
+    x (1 - x)^(n - 3): Beta(2, n - 2).  Each particle is generated at a
+    different step of the sequential construction (the mass-ratio equations
+    of degree 1 .. n - 2), so each slot tests one of them."""
+    from scipy import stats
+    rng = np.random.default_rng(40 + n_f)
+    N = 6000
+    x = np.zeros((N, n_f))
+    for e in range(N):
+        k, w, st = O.phase_space(n_f, [0.0] * n_f, 1.0, rng.random(3 * n_f - 4))
+        x[e] = 2 * k[:, 0]
+    for i in range(n_f):
+        assert stats.kstest(x[:, i], stats.beta(2, n_f - 2).cdf).pvalue > 1e-4, i
 
 
 def test_three_body_massive_volume_matches_dalitz_quadrature():
