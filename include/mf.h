@@ -40,8 +40,14 @@ typedef enum {
     MF_EUNSUPPORTED = -5     /* valid request the library does not implement       */
 } mf_status;
 
-/* Processes: g g -> t tbar + (n_g - 2) gluons. */
-typedef enum { MF_GG_TTX = 0, MF_GG_TTXG = 1, MF_GG_TTXGG = 2 } mf_process_id;
+/* Processes: g g -> t tbar + (n_g - 2) gluons.  MF_GG_TTXGGG (five gluons,
+ * the gluon channel of the paper's largest process, Sec. 3.2 and Fig. 4)
+ * runs with the full colour and helicity sums only (MF_COLOUR_FULL,
+ * MF_HELICITY_SUM), not in mf_integrate_static, and with at most 2^15
+ * events per batch: each event's 120 x 128 complex partial amplitudes
+ * (240 KB in FP64, 120 KB in FP32) pass through device memory between the
+ * amplitude kernel and the matrix-core colour sum. */
+typedef enum { MF_GG_TTX = 0, MF_GG_TTXG = 1, MF_GG_TTXGG = 2, MF_GG_TTXGGG = 3 } mf_process_id;
 
 /* Arithmetic of the helicity amplitudes and colour sum.  Everything else
  * (VEGAS, phase space, PDF, accumulation, refinement) is FP64 in both. */

@@ -23,7 +23,8 @@ from . import _lib
 from ._lib import MF_FP32_KAHAN, MF_FP64, MFError, check, lib  # noqa: F401
 
 PROCESS_IDS = {"gg_ttx": _lib.MF_GG_TTX, "gg_ttxg": _lib.MF_GG_TTXG, "gg_ttxgg": _lib.MF_GG_TTXGG,
-               2: _lib.MF_GG_TTX, 3: _lib.MF_GG_TTXG, 4: _lib.MF_GG_TTXGG}
+               "gg_ttxggg": _lib.MF_GG_TTXGGG,
+               2: _lib.MF_GG_TTX, 3: _lib.MF_GG_TTXG, 4: _lib.MF_GG_TTXGG, 5: _lib.MF_GG_TTXGGG}
 PRECISIONS = {"fp64": MF_FP64, "fp32_kahan": MF_FP32_KAHAN}
 # colour sum: the full colour matrix, the leading-colour approximation, or a
 # Monte Carlo over colour assignments or colour flows (mf_integrate, n_g >= 3)
@@ -176,7 +177,7 @@ def evaluate_weights(proc: Process, sqrt_s: float, pdf_table, n: int, seed: int 
     w = torch.empty(n, dtype=torch.float64, device="cuda")
     k53 = torch.empty((n, D), dtype=torch.int64, device="cuda") if return_k53 else None
     bins = torch.empty((n, D), dtype=torch.int32, device="cuda") if return_bins else None
-    n_f = {4: 2, 7: 3, 10: 4}[D]
+    n_f = {4: 2, 7: 3, 10: 4, 13: 5}[D]
     rec = torch.empty((n, 8 + 4 * n_f), dtype=torch.float64, device="cuda") if return_record else None
     if y is not None:
         assert y.dtype == torch.float64 and y.is_cuda and y.is_contiguous() and y.shape == (n, D)
@@ -225,7 +226,7 @@ def refine_grid(hist: torch.Tensor, grid: torch.Tensor, alpha: float = 1.5, stre
 
 def colour_matrix(process) -> np.ndarray:
     pid = PROCESS_IDS[process]
-    n = {0: 2, 1: 6, 2: 24}[pid]
+    n = {0: 2, 1: 6, 2: 24, 3: 120}[pid]
     C_ = np.zeros((n, n))
     check(lib.mf_colour_matrix(pid, _ptr(C_)))
     return C_
@@ -377,7 +378,7 @@ def unweight(proc: Process, sqrt_s: float, weights: torch.Tensor, w_max: float, 
     assert weights.is_cuda and weights.dtype == torch.float64 and weights.is_contiguous()
     n = weights.numel()
     n_f = n_dims(proc.process)
-    n_f = {4: 2, 7: 3, 10: 4}[n_f]
+    n_f = {4: 2, 7: 3, 10: 4, 13: 5}[n_f]
     g = None if grid is None else np.ascontiguousarray(grid, dtype=np.float64)
     opt = _options(n_bins, 1.5, 0, "fp64", False, max_newton, None, stream, profile)
     pc = proc.c()

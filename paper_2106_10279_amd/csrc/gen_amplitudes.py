@@ -1360,6 +1360,21 @@ _LAST_COUNT = None
 _COOP_COUNT = None
 
 
+def _helpers():
+    import types
+    return types.SimpleNamespace(_contract=_contract, CoopTable=CoopTable, emit_coop_fill=emit_coop_fill)
+
+
+def _ttggg():
+    """The five-gluon generator (gen_ttggg.py next to this file)."""
+    import importlib.util
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "gen_ttggg.py")
+    spec = importlib.util.spec_from_file_location("gen_ttggg", path)
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
 def flop_count(n, colour="full"):
     """Algorithmic flops per event of the |M|^2 code the kernels run for n
     gluons: the momentum table, plus either 2^(n+2) independent helicity
@@ -1367,6 +1382,18 @@ def flop_count(n, colour="full"):
     meet-in-the-middle contractions (n >= 3).  colour = "leading" counts the
     leading-colour sum in place of the full colour matrix."""
     assert colour in ("full", "leading", "sampled", "flow")
+    if n == 5:
+        _, c5 = _ttggg().generate_ng5(_helpers())
+        nh = 1 << (n + 2)
+        c = {"algorithm": "helicity-recycled objects, amplitudes to memory, colour sum on the matrix cores",
+             "n_hel": nh, "n_orderings": 120, "momentum_only": c5["momentum_only"], "stages": c5["stages"],
+             "per_lane": c5["per_lane"], "lanes": 5 * nh, "colour_per_helicity": c5["colour_per_helicity"],
+             "object_store": c5["object_store"], "table_doubles": c5["table"]}
+        assert colour == "full", "t tbar g g g runs with the full colour sum"
+        c["amplitudes"] = c["momentum_only"] + c["stages"] + c["lanes"] * c["per_lane"]
+        c["colour"] = nh * c["colour_per_helicity"]
+        c["per_event"] = c["amplitudes"] + c["colour"]
+        return c
     generate(n)
     c = dict(_LAST_COUNT)
     lc = colour == "leading"
@@ -1400,9 +1427,9 @@ def main():
     ap.add_argument("--out", required=True)
     args = ap.parse_args()
     os.makedirs(args.out, exist_ok=True)
-    for n in (2, 3, 4):
+    for n in (2, 3, 4, 5):
         path = os.path.join(args.out, f"amp_ng{n}.inc")
-        text = generate(n)
+        text = generate(n) if n <= 4 else _ttggg().generate_ng5(_helpers())[0]
         old = open(path).read() if os.path.exists(path) else None
         if old != text:
             with open(path, "w") as f:

@@ -285,6 +285,32 @@ __device__ __forceinline__ void stspins(float* p, const cplx<float>* s)
     *reinterpret_cast<mf_f4*>(p + 4 * N) = b;
 }
 
+// Helicity pattern of the sub-sequence at positions start .. start+len-1 of a
+// gluon sequence whose pattern is hm (bit k: the gluon at position k), in
+// the order of the sub-sequence's stored orientation (rev: stored reversed).
+__device__ __forceinline__ unsigned sub_pattern(unsigned hm, int start, int len, unsigned rev)
+{
+    const unsigned x = (hm >> start) & ((1u << len) - 1u);
+    return rev ? (__brev(x) >> (32 - len)) : x;
+}
+
+// One complex amplitude (re, im) to device memory as a single store.
+__device__ __forceinline__ void stj(double* p, double re, double im)
+{
+    mf_d2 v;
+    v.x = re;
+    v.y = im;
+    *reinterpret_cast<mf_d2*>(p) = v;
+}
+typedef float mf_f2 __attribute__((ext_vector_type(2), __may_alias__));
+__device__ __forceinline__ void stj(float* p, float re, float im)
+{
+    mf_f2 v;
+    v.x = re;
+    v.y = im;
+    *reinterpret_cast<mf_f2*>(p) = v;
+}
+
 // (ar, ai) = c^mu j_mu for complex c and a real 4-vector j held in registers.
 template <typename T>
 __device__ __forceinline__ void cdot_set(const T* j, const cplx<T>* c, T& ar, T& ai)

@@ -23,11 +23,12 @@ namespace mf {
 #include "_gen/amp_ng2.inc"
 #include "_gen/amp_ng3.inc"
 #include "_gen/amp_ng4.inc"
+#include "_gen/amp_ng5.inc"
 
 constexpr int kWave = 64;
 constexpr int kWavesPerBlock = 4;
 constexpr int kBlock = kWave * kWavesPerBlock;
-constexpr int kMaxDims = 10;
+constexpr int kMaxDims = 13;
 constexpr int kPartialHead = 8;         // sw.s, sw.c, sw2.s, sw2.c, w_max, n_pass, n_fail, spare
 constexpr int kMaxPdfX = 256;
 constexpr double kGeV2ToPb = 0.3893793721e9;
@@ -110,6 +111,37 @@ __device__ __forceinline__ void boost_from_rest(const double* Q, double M, const
     out[3] = v[3] + c * Q[3];
 }
 
+// The mass-ratio equation of degree 3, 4u^3 - 3u^4 = r (increasing on
+// [0, 1]): Newton steps kept inside a bisection bracket, until a step falls
+// below the spacing of doubles at the iterate.
+__device__ __forceinline__ double mass_ratio3(double r)
+{
+#pragma clang fp contract(off)
+    if (!(r > 0.0))
+        return 0.0;
+    if (!(r < 1.0))
+        return 1.0;
+    double lo = 0.0, hi = 1.0, u = 0.5;
+    for (int it = 0; it < 200; ++it) {
+        const double u2 = u * u;
+        const double f = 4.0 * u2 * u - 3.0 * u2 * u2 - r;
+        if (f == 0.0)
+            return u;
+        if (f < 0.0)
+            lo = u;
+        else
+            hi = u;
+        const double fp = 12.0 * u2 * (1.0 - u);
+        double un = u - f / fp;
+        if (!(un > lo && un < hi))
+            un = 0.5 * (lo + hi);
+        if (fabs(un - u) <= 0x1p-52 * un)
+            return un;
+        u = un;
+    }
+    return u;
+}
+
 template <int NF>
 __device__ bool phase_space(const double* __restrict__ r, double rs, double m, int max_newton, double ps_const,
                             double (&k)[NF][4], double& W)
@@ -122,7 +154,8 @@ __device__ bool phase_space(const double* __restrict__ r, double rs, double m, i
     for (int i = 2; i <= NF - 1; ++i) {
         const int power = NF - i;
         const double ri = r[i - 2];
-        const double u = (power == 1) ? 1.0 - sqrt(1.0 - ri) : 0.5 - sin(asin(1.0 - 2.0 * ri) / 3.0);
+        const double u = (power == 1) ? 1.0 - sqrt(1.0 - ri)
+                         : (power == 2 ? 0.5 - sin(asin(1.0 - 2.0 * ri) / 3.0) : mass_ratio3(ri));
         M[i] = sqrt(u) * M[i - 1];
     }
     M[NF] = 0.0;
@@ -331,11 +364,12 @@ template <int NG>
 struct Layout {
     static constexpr int kMom = 8 + 4 * (NG - 2) + 1;
     static constexpr int kHel = 1 << (NG + 2);
-    static constexpr int kEventsPerPass = kWave / kHel;   // 4, 2, 1
-    static constexpr int kTable = NG == 2 ? TABLE_NG2 : (NG == 3 ? COOP_TABLE_NG3 : COOP_TABLE_NG4);
+    static constexpr int kEventsPerPass = kHel <= kWave ? kWave / kHel : 1;   // 4, 2, 1 (t tbar g g g: a workgroup)
+    static constexpr int kTable = NG == 2 ? TABLE_NG2
+                                  : (NG == 3 ? COOP_TABLE_NG3 : (NG == 4 ? COOP_TABLE_NG4 : COOP_TABLE_NG5));
     // helicity-recycled object store per event (units of the amplitude type)
     static constexpr bool kCoop = NG >= 3;
-    static constexpr int kObj = NG == 2 ? 1 : (NG == 3 ? COOP_OBJ_NG3 : COOP_OBJ_NG4);
+    static constexpr int kObj = NG == 2 ? 1 : (NG == 3 ? COOP_OBJ_NG3 : (NG == 4 ? COOP_OBJ_NG4 : COOP_OBJ_NG5));
     // objects sit at multiples of 4 elements: 16-byte aligned in every event's store
     static_assert(!kCoop || kObj % 4 == 0, "object store rows must keep 16-byte alignment");
 };
@@ -659,6 +693,7 @@ struct StageParams {
     unsigned char* flags;    // [count] event_kinematics flags
     int first_batch;         // acc: 1 = start the per-wave partials from zero
     unsigned long long* next_group;  // amp: work counter, cleared by kin_kernel
+    void* amps;              // t tbar g g g: [count][120][128][re, im] partial amplitudes (type T)
 };
 
 template <int NF>
@@ -1008,6 +1043,196 @@ __global__ void __launch_bounds__(kBlock) acc_kernel(StageParams S)
     }
     for (int i = lane; i < D * nb; i += kWave)
         out[(kPartialHead + i) * nw] = hist[i];
+}
+
+// ---------------------------------------------------------------------------
+// g g -> t tbar g g g (Sec. 3.2, Fig. 4: the paper's largest process).  The
+// object store of one event (15560 values: 124 KB in FP64, 62 KB in FP32)
+// takes most of a compute unit's LDS, so one workgroup of ten waves serves
+// one event at a time: all 640 lanes build the objects, then lane
+// (c, h) = (tid / 128, tid % 128) evaluates the 24 orderings that start with
+// gluon c for helicity configuration h and stores them to the event's
+// amplitude block in device memory.  The colour sum over 120 x 120 orderings
+// is a dense contraction and runs on the matrix cores in colour_kernel_ng5.
+// Events are claimed one at a time from a device counter (cleared by
+// kin_kernel); rejected events (prefactor 0) are skipped.
+// ---------------------------------------------------------------------------
+constexpr int kBlockNg5 = 640;
+constexpr int kAmpRowNg5 = 2 * 128;                        // T per row: 128 helicities x (re, im)
+constexpr size_t kAmpEventNg5 = (size_t)NPERM_NG5 * kAmpRowNg5;  // T per event
+
+template <typename T>
+__global__ void __launch_bounds__(kBlockNg5) amp_kernel_ng5(StageParams S)
+{
+    using L = Layout<5>;
+    __shared__ __align__(16) T s_tab[COOP_TABLE_NG5];
+    __shared__ __align__(16) T s_obj[COOP_OBJ_NG5];
+    __shared__ double s_mom[L::kMom];
+    __shared__ unsigned long long s_ev;
+    const int tid = threadIdx.x;
+    // the chunk is uniform over each wave (two waves per chunk)
+    const int c = __builtin_amdgcn_readfirstlane(tid >> 7);
+    const int h = tid & 127;
+    T* J = static_cast<T*>(S.amps);
+    for (;;) {
+        if (tid == 0)
+            s_ev = atomicAdd(S.next_group, 1ull);
+        __syncthreads();
+        const uint64_t e = s_ev;
+        __syncthreads();
+        if (e >= S.count)
+            break;
+        if (S.pref[e] == 0.0)
+            continue;
+        if (tid < L::kMom)
+            s_mom[tid] = S.mom[e * L::kMom + tid];
+        __syncthreads();
+        if (tid < kWave)
+            fill_table_coop_ng5<T>(s_mom, s_mom[L::kMom - 1], S.P.m_top, S.P.mw, s_tab, s_obj, tid);
+        __syncthreads();
+        coop_stages_ng5<T>(s_tab, s_obj, S.P.m_top, tid, kBlockNg5);
+        coop_amp_ng5<T>(s_tab, s_obj, h, c, J + e * kAmpEventNg5);
+        __syncthreads();
+    }
+}
+
+typedef double mf_d4v __attribute__((ext_vector_type(4)));
+typedef float mf_f4v __attribute__((ext_vector_type(4)));
+template <typename T>
+struct MfmaAcc;
+template <>
+struct MfmaAcc<double> {
+    using type = mf_d4v;
+};
+template <>
+struct MfmaAcc<float> {
+    using type = mf_f4v;
+};
+
+// D += A B for one 16 x 16 x 4 matrix-core step (wave64): lane l supplies
+// A[l % 16][l / 16] and B[l / 16][l % 16]; in component r it holds
+// D[l / 16 + 4 r][l % 16] (FP64 step) or D[4 (l / 16) + r][l % 16] (FP32 step).
+__device__ __forceinline__ mf_d4v mfma_16x16x4(double a, double b, mf_d4v d)
+{
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, d, 0, 0, 0);
+}
+__device__ __forceinline__ mf_f4v mfma_16x16x4(float a, float b, mf_f4v d)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, d, 0, 0, 0);
+}
+
+// Colour sum of t tbar g g g on the matrix cores.  Per event the stored
+// amplitudes form X[120 rows][256 columns] (column = 2 h + re/im), and
+// sum_h A_h^dagger C A_h = sum over columns of x^T K' x / den with K' the
+// integer colour matrix in the stored row order and signs.  Rows are cut in
+// tiles of 16 (the last padded with zeros); with K' symmetric only the block
+// lower triangle is needed, the blocks below the diagonal doubled (36 tile
+// pairs, CFRAG_NG5).  For column block cb (16 columns) a wave forms
+// D_a = sum_(b <= a) K'_ab X_b with four 16 x 16 x 4 steps per tile pair and
+// contracts D_a with X_a.  Step s of tile b contracts, in lane group
+// k = l / 16, the tile row that the lane holds in component s of D (row
+// k + 4 s for the FP64 step, 4 k + s for the FP32 step), so one set of 32
+// loaded values per lane serves both the products and the final
+// contraction.  The fragments of K' sit in LDS; one wave per event.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) colour_kernel_ng5(StageParams S)
+{
+    constexpr int kFrag = 36 * 4 * kWave;
+    __shared__ T s_frag[kFrag];
+    const int tid = threadIdx.x;
+    for (int i = tid; i < kFrag; i += kBlock)
+        s_frag[i] = (T)(sizeof(T) == 8 ? CFRAG64_NG5[i] : CFRAG32_NG5[i]);
+    __syncthreads();
+    const int lane = tid % kWave, q = lane >> 4, col0 = lane & 15;
+    const T* J = static_cast<const T*>(S.amps);
+    const uint64_t stride = (uint64_t)gridDim.x * kWavesPerBlock;
+    for (uint64_t e = (uint64_t)blockIdx.x * kWavesPerBlock + tid / kWave; e < S.count; e += stride) {
+        if (S.pref[e] == 0.0)
+            continue;
+        const T* X = J + e * kAmpEventNg5;
+        double acc = 0.0;
+        for (int cb = 0; cb < kAmpRowNg5 / 16; ++cb) {
+            const int col = 16 * cb + col0;
+            T x[8][4];
+#pragma unroll
+            for (int b = 0; b < 8; ++b)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = 16 * b + (sizeof(T) == 8 ? q + 4 * r : 4 * q + r);
+                    x[b][r] = row < NPERM_NG5 ? X[(size_t)row * kAmpRowNg5 + col] : (T)0;
+                }
+            // tile pairs in order (a, b <= a); the four fragments of the next
+            // pair are read from LDS while the current pair's steps run
+            constexpr int PA[36] = {0, 1, 1, 2, 2, 2, 3, 3, 3, 3, 4, 4, 4, 4, 4, 5, 5, 5,
+                                    5, 5, 5, 6, 6, 6, 6, 6, 6, 6, 7, 7, 7, 7, 7, 7, 7, 7};
+            constexpr int PB[36] = {0, 0, 1, 0, 1, 2, 0, 1, 2, 3, 0, 1, 2, 3, 4, 0, 1, 2,
+                                    3, 4, 5, 0, 1, 2, 3, 4, 5, 6, 0, 1, 2, 3, 4, 5, 6, 7};
+            const T* fr = s_frag + lane;
+            T f[4] = {fr[0], fr[kWave], fr[2 * kWave], fr[3 * kWave]};
+            typename MfmaAcc<T>::type d = {0, 0, 0, 0};
+#pragma unroll
+            for (int p = 0; p < 36; ++p) {
+                const int a = PA[p], b = PB[p];
+                T g[4] = {0, 0, 0, 0};
+                if (p + 1 < 36) {
+                    const T* fn = fr + (p + 1) * 4 * kWave;
+                    g[0] = fn[0];
+                    g[1] = fn[kWave];
+                    g[2] = fn[2 * kWave];
+                    g[3] = fn[3 * kWave];
+                }
+                if (b == 0)
+                    d = {0, 0, 0, 0};
+#pragma unroll
+                for (int s = 0; s < 4; ++s)
+                    d = mfma_16x16x4(f[s], x[b][s], d);
+                if (b == a)
+                    acc += (double)x[a][0] * (double)d[0] + (double)x[a][1] * (double)d[1] +
+                           (double)x[a][2] * (double)d[2] + (double)x[a][3] * (double)d[3];
+#pragma unroll
+                for (int s = 0; s < 4; ++s)
+                    f[s] = g[s];
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+        for (int off = kWave >> 1; off > 0; off >>= 1)
+            acc += __shfl_xor(acc, off);
+        if (lane == 0)
+            S.me[e] = acc / COLOUR_DEN_NG5;
+    }
+}
+
+// mf_matrix_element for t tbar g g g: the caller's momenta [n][20] and beam
+// energies into the amplitude kernel's per-event layout [n][21], prefactor 1
+// (every event evaluated); thread 0 clears the amplitude kernel's counter.
+__global__ void __launch_bounds__(kBlock) me_prep_kernel_ng5(const double* __restrict__ mom,
+                                                             const double* __restrict__ eb, uint64_t n,
+                                                             StageParams S)
+{
+    const uint64_t e = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (e == 0)
+        *S.next_group = 0ull;
+    if (e >= n)
+        return;
+    constexpr int K = Layout<5>::kMom;
+    for (int i = 0; i < K - 1; ++i)
+        S.mom[e * K + i] = mom[e * (K - 1) + i];
+    S.mom[e * K + K - 1] = eb[e];
+    S.pref[e] = 1.0;
+}
+
+// mf_evaluate for the staged processes: weight (and the record's |M|^2 entry)
+// of every event of the batch.
+__global__ void __launch_bounds__(kBlock) weight_kernel(StageParams S, int nf)
+{
+    const uint64_t e = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (e >= S.count)
+        return;
+    const double pref = S.pref[e];
+    const double me = pref != 0.0 ? S.me[e] : 0.0;
+    S.P.weights[S.first + e] = pref != 0.0 ? pref * (me * S.P.me_norm) : 0.0;
+    if (S.P.record)
+        S.P.record[(S.first + e) * (8 + 4 * (uint64_t)nf) + 6] = me;
 }
 
 // ---------------------------------------------------------------------------

@@ -63,6 +63,7 @@ int n_gluons(int id)
     case MF_GG_TTX: return 2;
     case MF_GG_TTXG: return 3;
     case MF_GG_TTXGG: return 4;
+    case MF_GG_TTXGGG: return 5;
     default: return -1;
     }
 }
@@ -84,12 +85,16 @@ struct Buffer {
 // Events per batch of the three-kernel form (per-event buffers of about
 // 170 B for t tbar g g: 23 GB at the cap, sized for a 288 GB device).
 constexpr uint64_t kStageBatch = 1ull << 27;
+// t tbar g g g: the partial amplitudes of a batch pass through device memory
+// (120 x 128 complex values per event: 8 GB per batch in FP64).
+constexpr uint64_t kStageBatchNg5 = 1ull << 15;
 
 struct Workspace {
     std::mutex lock;
     Buffer grid[2], log_x, log_q2, xf, partials, entries, iter_I, iter_V, iter_pass, stats, gpartials, gsum;
     Buffer st_mom, st_pref, st_me, st_bins, st_flags;   // per-event hand-over of the three-kernel form
     Buffer amp_counter;                                  // work counter of amp_kernel (8 bytes)
+    Buffer st_amp;                                       // t tbar g g g: partial amplitudes of a batch
     Buffer uw_counts, uw_flags, uw_totals;               // unweighting: per-workgroup counts, keep flags, totals
     int n_cu = 0;
     void* scratch = nullptr;  // this device's address of the static scratch array (mf_integrate_static)
@@ -129,6 +134,7 @@ struct Mem {
     unsigned short* st_bins = nullptr;
     unsigned char* st_flags = nullptr;
     unsigned long long* amp_counter = nullptr;
+    void* st_amp = nullptr;
 };
 
 // Consecutive 256-byte aligned pieces of a fixed device region.
@@ -389,9 +395,55 @@ mf_status launch_stages_prec(mf_precision prec, const mf::StageParams& S, int ki
                                  : launch_stages<NG, double, COL>(S, kin_blocks, n_cu, s, a, b);
 }
 
+// t tbar g g g: phase space, amplitudes (one ten-wave workgroup per event,
+// as many as fit at once), colour sum on the matrix cores, accumulation.
+template <typename T>
+mf_status launch_stages_ng5(const mf::StageParams& S, int kin_blocks, int n_cu, hipStream_t stream,
+                            hipEvent_t amp_begin, hipEvent_t amp_end, bool accumulate)
+{
+    constexpr int D = 2 + 3 * 5 - 4;
+    int per_cu = 0, col_per_cu = 0;
+    MF_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, mf::amp_kernel_ng5<T>, mf::kBlockNg5, 0));
+    MF_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&col_per_cu, mf::colour_kernel_ng5<T>, mf::kBlock, 0));
+    if (per_cu < 1)
+        return fail(MF_EDEVICE, "the t tbar g g g amplitude kernel does not fit a compute unit");
+    if (col_per_cu < 1)
+        col_per_cu = 1;
+    const uint64_t amp_cap = (uint64_t)n_cu * per_cu;
+    const int amp_grid = (int)(S.count < amp_cap ? S.count : amp_cap);
+    const uint64_t col_need = (S.count + mf::kWavesPerBlock - 1) / mf::kWavesPerBlock;
+    const uint64_t col_cap = (uint64_t)n_cu * col_per_cu;
+    const int col_grid = (int)(col_need < col_cap ? col_need : col_cap);
+    hipLaunchKernelGGL((mf::kin_kernel<5>), dim3(kin_blocks), dim3(mf::kBlock), 0, stream, S);
+    MF_HIP(hipGetLastError());
+    if (amp_begin)
+        MF_HIP(hipEventRecord(amp_begin, stream));
+    hipLaunchKernelGGL((mf::amp_kernel_ng5<T>), dim3(amp_grid), dim3(mf::kBlockNg5), 0, stream, S);
+    MF_HIP(hipGetLastError());
+    if (amp_end)
+        MF_HIP(hipEventRecord(amp_end, stream));
+    hipLaunchKernelGGL((mf::colour_kernel_ng5<T>), dim3(col_grid), dim3(mf::kBlock), 0, stream, S);
+    MF_HIP(hipGetLastError());
+    if (accumulate) {
+        const size_t dyn = sizeof(double) * mf::kWavesPerBlock * D * S.P.n_bins;
+        hipLaunchKernelGGL((mf::acc_kernel<5>), dim3(kin_blocks), dim3(mf::kBlock), dyn, stream, S);
+    } else {
+        const unsigned wb = (unsigned)((S.count + mf::kBlock - 1) / mf::kBlock);
+        hipLaunchKernelGGL(mf::weight_kernel, dim3(wb), dim3(mf::kBlock), 0, stream, S, 5);
+    }
+    MF_HIP(hipGetLastError());
+    return MF_OK;
+}
+
 mf_status dispatch_stages(int ng, mf_precision prec, mf_colour col, const mf::StageParams& S, int kin_blocks,
                           int n_cu, hipStream_t s, hipEvent_t a, hipEvent_t b)
 {
+    if (ng == 5) {
+        if (col != MF_COLOUR_FULL)
+            return fail(MF_EUNSUPPORTED, "g g -> t tbar g g g runs with the full colour sum only");
+        return prec == MF_FP32_KAHAN ? launch_stages_ng5<float>(S, kin_blocks, n_cu, s, a, b, true)
+                                     : launch_stages_ng5<double>(S, kin_blocks, n_cu, s, a, b, true);
+    }
     if (ng == 2)
         return col == MF_COLOUR_LEADING ? launch_stages_prec<2, 1>(prec, S, kin_blocks, n_cu, s, a, b)
                                         : launch_stages_prec<2, 0>(prec, S, kin_blocks, n_cu, s, a, b);
@@ -546,6 +598,14 @@ mf_status integrate_impl(const mf_process* proc, double sqrt_s, const mf_pdf_gri
         return fail(MF_EINVAL, "iteration index exceeds the 32-bit Philox counter word");
     if ((opt->colour == MF_COLOUR_SAMPLED || opt->colour == MF_COLOUR_FLOW) && ng == 2)
         return fail(MF_EUNSUPPORTED, "the Monte Carlo over colours runs for g g -> t tbar g (g) only");
+    if (ng == 5) {
+        if (opt->colour != MF_COLOUR_FULL)
+            return fail(MF_EUNSUPPORTED, "g g -> t tbar g g g runs with the full colour sum only");
+        if (opt->helicity != MF_HELICITY_SUM)
+            return fail(MF_EUNSUPPORTED, "g g -> t tbar g g g runs with the full helicity sum only");
+        if (fixed_scratch)
+            return fail(MF_EUNSUPPORTED, "mf_integrate_static does not run g g -> t tbar g g g");
+    }
     if (grad) {
         if (ng != 2)
             return fail(MF_EUNSUPPORTED, "gradients are implemented for g g -> t tbar only");
@@ -582,6 +642,10 @@ mf_status integrate_impl(const mf_process* proc, double sqrt_s, const mf_pdf_gri
     const bool staged = true;
     const int nf = ng;
     uint64_t cap = opt->max_batch ? opt->max_batch : kStageBatch;
+    if (ng == 5 && cap > kStageBatchNg5)
+        cap = kStageBatchNg5;
+    const size_t amp_bytes = ng == 5 ? (opt->precision == MF_FP32_KAHAN ? sizeof(float) : sizeof(double)) *
+                                           mf::kAmpEventNg5 : 0;
     Mem m;
     if (fixed_scratch) {
         if (!ws.scratch) {
@@ -644,6 +708,7 @@ mf_status integrate_impl(const mf_process* proc, double sqrt_s, const mf_pdf_gri
             if ((st = ensure(ws.st_bins, sizeof(unsigned short) * D * b0)) != MF_OK) return st;
             if ((st = ensure(ws.st_flags, b0)) != MF_OK) return st;
             if ((st = ensure(ws.amp_counter, sizeof(unsigned long long))) != MF_OK) return st;
+            if (amp_bytes && (st = ensure(ws.st_amp, amp_bytes * b0)) != MF_OK) return st;
         }
         if (grad) {
             if ((st = ensure(ws.gpartials, sizeof(double) * 4 * (size_t)n_waves)) != MF_OK) return st;
@@ -665,6 +730,7 @@ mf_status integrate_impl(const mf_process* proc, double sqrt_s, const mf_pdf_gri
         m.st_bins = (unsigned short*)ws.st_bins.ptr;
         m.st_flags = (unsigned char*)ws.st_flags.ptr;
         m.amp_counter = (unsigned long long*)ws.amp_counter.ptr;
+        m.st_amp = amp_bytes ? ws.st_amp.ptr : nullptr;
     }
     const uint64_t batch = n_events < cap ? n_events : cap;
     const uint64_t n_batches = (n_events + batch - 1) / batch;
@@ -746,6 +812,7 @@ mf_status integrate_impl(const mf_process* proc, double sqrt_s, const mf_pdf_gri
                 SP.flags = m.st_flags;
                 SP.first_batch = bi == 0;
                 SP.next_group = m.amp_counter;
+                SP.amps = m.st_amp;
                 hipEvent_t a = nullptr, b = nullptr;
                 if (opt->profile) {
                     a = amp_marks[2 * ((size_t)j * n_batches + bi)];
@@ -970,6 +1037,59 @@ mf_status fixed_grid_setup(const mf_process* proc, double sqrt_s, const mf_pdf_g
     return MF_OK;
 }
 
+// Per-event buffers of a t tbar g g g batch in the grow-only workspace.
+mf_status stage_buffers_ng5(Workspace& ws, uint64_t b0, mf_precision prec, mf::StageParams& SP)
+{
+    constexpr int D = 2 + 3 * 5 - 4;
+    constexpr int K = mf::Layout<5>::kMom;
+    const size_t amp_bytes = (prec == MF_FP32_KAHAN ? sizeof(float) : sizeof(double)) * mf::kAmpEventNg5;
+    mf_status st;
+    if ((st = ensure(ws.st_mom, sizeof(double) * K * b0)) != MF_OK) return st;
+    if ((st = ensure(ws.st_pref, sizeof(double) * b0)) != MF_OK) return st;
+    if ((st = ensure(ws.st_me, sizeof(double) * b0)) != MF_OK) return st;
+    if ((st = ensure(ws.st_bins, sizeof(unsigned short) * D * b0)) != MF_OK) return st;
+    if ((st = ensure(ws.st_flags, b0)) != MF_OK) return st;
+    if ((st = ensure(ws.amp_counter, sizeof(unsigned long long))) != MF_OK) return st;
+    if ((st = ensure(ws.st_amp, amp_bytes * b0)) != MF_OK) return st;
+    SP.mom = (double*)ws.st_mom.ptr;
+    SP.pref = (double*)ws.st_pref.ptr;
+    SP.me = (double*)ws.st_me.ptr;
+    SP.bins = (unsigned short*)ws.st_bins.ptr;
+    SP.flags = (unsigned char*)ws.st_flags.ptr;
+    SP.next_group = (unsigned long long*)ws.amp_counter.ptr;
+    SP.amps = ws.st_amp.ptr;
+    SP.first_batch = 1;
+    return MF_OK;
+}
+
+// mf_evaluate for t tbar g g g: the staged kernels in batches, weights
+// (and records) written by weight_kernel.
+mf_status evaluate_ng5(Setup& S, const mf_options* opt, uint64_t n)
+{
+    if (opt->colour != MF_COLOUR_FULL)
+        return fail(MF_EUNSUPPORTED, "g g -> t tbar g g g runs with the full colour sum only");
+    if (opt->helicity != MF_HELICITY_SUM)
+        return fail(MF_EUNSUPPORTED, "g g -> t tbar g g g runs with the full helicity sum only");
+    const uint64_t cap = opt->max_batch && opt->max_batch < kStageBatchNg5 ? opt->max_batch : kStageBatchNg5;
+    const uint64_t batch = n < cap ? n : cap;
+    mf::StageParams SP;
+    SP.P = S.P;
+    mf_status st;
+    if ((st = stage_buffers_ng5(*S.ws, batch, opt->precision, SP)) != MF_OK) return st;
+    for (uint64_t first = 0; first < n; first += batch) {
+        SP.first = first;
+        SP.count = n - first < batch ? n - first : batch;
+        SP.P.n_waves = waves_for((SP.count + mf::kWave - 1) / mf::kWave, S.ws->n_cu);
+        const int kin_blocks = SP.P.n_waves / mf::kWavesPerBlock;
+        st = opt->precision == MF_FP32_KAHAN
+                 ? launch_stages_ng5<float>(SP, kin_blocks, S.ws->n_cu, S.stream, nullptr, nullptr, false)
+                 : launch_stages_ng5<double>(SP, kin_blocks, S.ws->n_cu, S.stream, nullptr, nullptr, false);
+        if (st != MF_OK)
+            return st;
+    }
+    return MF_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -995,6 +1115,12 @@ mf_status mf_evaluate(const mf_process* proc, double sqrt_s, const mf_pdf_grid* 
     P.k53_out = k53_out;
     P.bins_out = bins_out;
     P.record = record_out;
+    if (S.ng == 5) {
+        if ((st = evaluate_ng5(S, opt, n)) != MF_OK)
+            return st;
+        MF_HIP(hipStreamSynchronize(S.stream));
+        return MF_OK;
+    }
     if ((st = dispatch_event(S.ng, opt->precision, opt->colour, P, P.n_waves / mf::kWavesPerBlock, S.stream)) != MF_OK)
         return st;
     MF_HIP(hipStreamSynchronize(S.stream));
@@ -1192,7 +1318,8 @@ mf_status mf_unweight(const mf_process* proc, double sqrt_s, const double* grid,
         switch (ng) {
         case 2: hipLaunchKernelGGL(mf::unweight_record_kernel<2>, grid, dim3(mf::kBlock), 0, stream, U, tot); break;
         case 3: hipLaunchKernelGGL(mf::unweight_record_kernel<3>, grid, dim3(mf::kBlock), 0, stream, U, tot); break;
-        default: hipLaunchKernelGGL(mf::unweight_record_kernel<4>, grid, dim3(mf::kBlock), 0, stream, U, tot); break;
+        case 4: hipLaunchKernelGGL(mf::unweight_record_kernel<4>, grid, dim3(mf::kBlock), 0, stream, U, tot); break;
+        default: hipLaunchKernelGGL(mf::unweight_record_kernel<5>, grid, dim3(mf::kBlock), 0, stream, U, tot); break;
         }
         MF_HIP(hipGetLastError());
     }
@@ -1225,6 +1352,11 @@ mf_status mf_colour_matrix(int process_id, double* C)
         return fail(MF_EINVAL, "unknown process id");
     if (!C)
         return fail(MF_EINVAL, "C is NULL");
+    if (n == 5) {
+        for (int i = 0; i < 120 * 120; ++i)
+            C[i] = (double)mf::COLOUR_NUM_NG5[i] / mf::COLOUR_DEN_NG5;
+        return MF_OK;
+    }
     const int* num = n == 2 ? mf::COLOUR_NUM_NG2 : (n == 3 ? mf::COLOUR_NUM_NG3 : mf::COLOUR_NUM_NG4);
     const double den = n == 2 ? mf::COLOUR_DEN_NG2 : (n == 3 ? mf::COLOUR_DEN_NG3 : mf::COLOUR_DEN_NG4);
     const int np = n == 2 ? 2 : (n == 3 ? 6 : 24);
@@ -1232,6 +1364,69 @@ mf_status mf_colour_matrix(int process_id, double* C)
         C[i] = (double)num[i] / den;
     return MF_OK;
 }
+
+}  // extern "C"
+
+namespace {
+
+// mf_matrix_element for t tbar g g g: the amplitude and colour kernels of
+// the staged path in batches, on the caller's momenta.
+mf_status matrix_element_ng5(mf_precision precision, const double* mom, const double* eb, uint64_t n, double m_top,
+                             double w_top, double* out, hipStream_t s)
+{
+    Workspace* wsp = nullptr;
+    mf_status st;
+    if ((st = device_workspace(&wsp)) != MF_OK) return st;
+    Workspace& ws = *wsp;
+    std::lock_guard<std::mutex> guard(ws.lock);
+    const uint64_t batch = n < kStageBatchNg5 ? n : kStageBatchNg5;
+    mf::StageParams SP;
+    std::memset(&SP.P, 0, sizeof(SP.P));
+    SP.P.m_top = m_top;
+    SP.P.mw = m_top * w_top;
+    if ((st = stage_buffers_ng5(ws, batch, precision, SP)) != MF_OK) return st;
+    constexpr int K = mf::Layout<5>::kMom;
+    for (uint64_t first = 0; first < n; first += batch) {
+        SP.first = first;
+        SP.count = n - first < batch ? n - first : batch;
+        SP.me = out + first;
+        const unsigned pb = (unsigned)((SP.count + mf::kBlock - 1) / mf::kBlock);
+        hipLaunchKernelGGL(mf::me_prep_kernel_ng5, dim3(pb), dim3(mf::kBlock), 0, s, mom + first * (K - 1),
+                           eb + first, SP.count, SP);
+        MF_HIP(hipGetLastError());
+        int per_cu = 0, col_per_cu = 0;
+        const bool f32 = precision == MF_FP32_KAHAN;
+        MF_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per_cu, f32 ? (const void*)mf::amp_kernel_ng5<float> : (const void*)mf::amp_kernel_ng5<double>,
+            mf::kBlockNg5, 0));
+        MF_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &col_per_cu, f32 ? (const void*)mf::colour_kernel_ng5<float> : (const void*)mf::colour_kernel_ng5<double>,
+            mf::kBlock, 0));
+        if (per_cu < 1)
+            return fail(MF_EDEVICE, "the t tbar g g g amplitude kernel does not fit a compute unit");
+        const uint64_t acap = (uint64_t)ws.n_cu * per_cu;
+        const int agrid = (int)(SP.count < acap ? SP.count : acap);
+        const uint64_t cneed = (SP.count + mf::kWavesPerBlock - 1) / mf::kWavesPerBlock;
+        const uint64_t ccap = (uint64_t)ws.n_cu * (col_per_cu < 1 ? 1 : col_per_cu);
+        const int cgrid = (int)(cneed < ccap ? cneed : ccap);
+        if (f32) {
+            hipLaunchKernelGGL((mf::amp_kernel_ng5<float>), dim3(agrid), dim3(mf::kBlockNg5), 0, s, SP);
+            MF_HIP(hipGetLastError());
+            hipLaunchKernelGGL((mf::colour_kernel_ng5<float>), dim3(cgrid), dim3(mf::kBlock), 0, s, SP);
+        } else {
+            hipLaunchKernelGGL((mf::amp_kernel_ng5<double>), dim3(agrid), dim3(mf::kBlockNg5), 0, s, SP);
+            MF_HIP(hipGetLastError());
+            hipLaunchKernelGGL((mf::colour_kernel_ng5<double>), dim3(cgrid), dim3(mf::kBlock), 0, s, SP);
+        }
+        MF_HIP(hipGetLastError());
+    }
+    MF_HIP(hipStreamSynchronize(s));
+    return MF_OK;
+}
+
+}  // namespace
+
+extern "C" {
 
 mf_status mf_matrix_element(int process_id, mf_precision precision, const double* mom, const double* eb,
                             uint64_t n, double m_top, double w_top, double* out, void* stream)
@@ -1248,6 +1443,8 @@ mf_status mf_matrix_element(int process_id, mf_precision precision, const double
     if (!finite_pos(m_top) || !std::isfinite(w_top) || w_top < 0.0)
         return fail(MF_EINVAL, "m_top must be > 0 and w_top >= 0");
     hipStream_t s = (hipStream_t)stream;
+    if (ng == 5)
+        return matrix_element_ng5(precision, mom, eb, n, m_top, w_top, out, s);
     const int epp = mf::kWave >> (ng + 2);              // events per wave
     const uint64_t per_block = (uint64_t)epp * mf::kWavesPerBlock;
     const uint64_t blocks = (n + per_block - 1) / per_block;
