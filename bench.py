@@ -36,12 +36,13 @@ PEAK_FP32_TFLOPS = 157.3     # MI355X vector FP32 (packed)
 # 10 per particle per Newton step), cuts (about 50), two PDF evaluations
 # (about 170 each), weight and accumulation (about 25); estimated from the
 # kernel source.
-OTHER_FLOPS = {2: 420, 3: 720, 4: 1030}
+OTHER_FLOPS = {2: 420, 3: 720, 4: 1030, 5: 1340}
 
 WORKLOADS = {
     "ttx": dict(process="gg_ttx", n_g=2, cuts={}, events=1_000_000),
     "ttxg": dict(process="gg_ttxg", n_g=3, cuts=dict(ptmin_g=20.0, etamax_g=2.5), events=10_000_000),
     "ttxgg": dict(process="gg_ttxgg", n_g=4, cuts=dict(ptmin_g=20.0, drmin_gg=0.4), events=10_000_000),
+    "ttxggg": dict(process="gg_ttxggg", n_g=5, cuts=dict(ptmin_g=20.0, drmin_gg=0.4), events=1_000_000),
 }
 
 
@@ -350,12 +351,64 @@ def config_leg(api, torch, name, n_events, n_iter, seeds, events_note=""):
             "chi2_dof": [s[2] for s in sig]}
 
 
+def flop_record(n_g):
+    path = os.path.join(ROOT, "paper_2106_10279_amd", "csrc", "gen_amplitudes.py")
+    spec = importlib.util.spec_from_file_location("gen_amplitudes", path)
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod.flop_count(n_g)
+
+
+def ttxggg_leg(api, torch, n_events, n_iter, precision):
+    """g g -> t tbar g g g (five gluons): one warm-up iteration, then n_iter
+    timed ones.  Two rooflines from the library's HIP-event timing of every
+    launch: the amplitude kernel (object stages and partial amplitudes of the
+    passing events, VALU) and the matrix-core colour sum (algorithmic flops of
+    the symmetric quadratic form, 29040 per helicity configuration)."""
+    import workloads as W
+    wl = WORKLOADS["ttxggg"]
+    pdf = W.synthetic_pdf()
+    proc = api.Process(wl["process"], **wl["cuts"])
+    c = flop_record(5)
+    r, wall, _ = timed_run(api, torch, proc, pdf, n_events, n_iter, 1, precision, 0)
+    n_pass = float(np.sum(r.iter_pass))
+    launches = len(r.iter_event_ms) * r.n_batches
+    t_amp = float(np.sum(r.iter_amp_ms)) / 1e3
+    t_col = float(np.sum(r.iter_colour_ms)) / 1e3
+    t_all = float(np.sum(r.iter_event_ms)) / 1e3
+    f32 = precision != "fp64"
+    vpeak = PEAK_FP32_TFLOPS if f32 else PEAK_FP64_TFLOPS
+    mpeak = 157.3 if f32 else 78.6        # dense matrix-core FP32 / FP64
+    amp_fl = n_pass * c["amplitudes"]
+    col_fl = n_pass * c["colour"]
+    out = {"workload": f"gg_ttxggg at 13 TeV (pT > 20 GeV, Delta R > 0.4 on the gluons), {n_events} events x "
+                       f"{n_iter} iterations, amplitudes {precision}",
+           "value": round(n_events * n_iter / wall, 2), "unit": "events/s",
+           "ms_per_step": round(wall / n_iter * 1e3, 3), "sigma_pb": r.sigma, "sigma_err_pb": r.sigma_err,
+           "pass_fraction": round(n_pass / (n_iter * n_events), 4), "batches_per_iteration": r.n_batches,
+           "flops_per_passing_event": {"amplitudes": c["amplitudes"], "colour": c["colour"]},
+           "roofline": {"bound": "alu", "achieved": round(amp_fl / t_amp / 1e12, 3), "peak": vpeak,
+                        "unit": "TFLOP/s", "frac": round(amp_fl / t_amp / 1e12 / vpeak, 4), "traffic": None,
+                        "kernel": "amp_kernel_ng5", "launches": launches,
+                        "avg_launch_ms": round(t_amp * 1e3 / launches, 3)},
+           "colour_roofline": {"bound": "mfma", "achieved": round(col_fl / t_col / 1e12, 3), "peak": mpeak,
+                               "unit": "TFLOP/s", "frac": round(col_fl / t_col / 1e12 / mpeak, 4),
+                               "traffic": None, "kernel": "colour_kernel_ng5", "launches": launches,
+                               "avg_launch_ms": round(t_col * 1e3 / launches, 3)},
+           "per_event_kernels_ms_per_iteration": round(t_all * 1e3 / n_iter, 3)}
+    del r
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="ttxgg", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="ttxgg", choices=sorted(k for k in WORKLOADS if k != "ttxggg"))
+    ap.add_argument("--no-ttxggg", action="store_true", help="skip the g g -> t tbar g g g legs")
+    ap.add_argument("--ttxggg-events", type=int, default=1_000_000)
     ap.add_argument("--events", type=int, default=None)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-fp32", action="store_true")
@@ -528,6 +581,11 @@ def main():
         out["ttxg_1e7x10"] = config_leg(api, torch, "ttxg", 10_000_000, 10, [0, 1, 2, 3, 4])
         log(f"[bench] configs done: ttx {out['ttx_1e8x5']['value']:.4g}, ttxg {out['ttxg_1e7x10']['value']:.4g} "
             "events/s")
+    if not args.no_ttxggg and args.workload == "ttxgg":
+        for prec in ("fp64", "fp32_kahan"):
+            log(f"[bench] g g -> t tbar g g g, {args.ttxggg_events} events x 3 iterations, {prec}")
+            out[f"ttxggg_{prec}"] = ttxggg_leg(api, torch, args.ttxggg_events, 3, prec)
+            log(f"[bench] ttxggg {prec} done: {out[f'ttxggg_{prec}']['value']:.4g} events/s")
     if not args.no_adjoint:
         log(f"[bench] adjoint: gg_ttx forward + gradient, {args.adjoint_events} events x 3 iterations")
         out["adjoint"] = adjoint_run(api, torch, pdf, args.adjoint_events, 3, args.seed)

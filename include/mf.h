@@ -158,12 +158,15 @@ typedef struct {
     uint64_t n_batches;      /* event batches per iteration (up to 2^27 events each, or max_batch) */
     double *grid_last;       /* host [D][n_bins+1] the grid the last iteration ran on (the one
                                 its weights belong to), may be NULL */
+    double *iter_colour_ms;  /* host [n_iter] profile = 1, MF_GG_TTXGGG: of the per-event kernels,
+                                the matrix-core colour sum (a kernel of its own after the
+                                amplitudes), ms, may be NULL */
 } mf_result;
 
 /* Fills *opt with the defaults shown above. */
 void mf_default_options(mf_options *opt);
 
-/* Number of integration dimensions D = 2 + 3 n_f - 4 (4, 7, 10), or -1. */
+/* Number of integration dimensions D = 2 + 3 n_f - 4 (4, 7, 10, 13), or -1. */
 int mf_n_dims(int process_id);
 
 /*

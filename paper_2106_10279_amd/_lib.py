@@ -43,7 +43,8 @@ class mf_result(C.Structure):
                 ("hist", _dp), ("weights", _dp), ("n_pass", C.c_int64),
                 ("n_newton_fail", C.c_int64), ("event_kernel_ms", C.c_double),
                 ("reduce_kernel_ms", C.c_double), ("iter_pass", _dp), ("iter_event_ms", _dp),
-                ("iter_amp_ms", _dp), ("n_batches", C.c_uint64), ("grid_last", _dp)]
+                ("iter_amp_ms", _dp), ("n_batches", C.c_uint64), ("grid_last", _dp),
+                ("iter_colour_ms", _dp)]
 
 
 class mf_grad_result(C.Structure):

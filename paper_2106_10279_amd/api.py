@@ -116,6 +116,7 @@ class IntegrationResult:
     iter_amp_ms: np.ndarray | None = None
     n_batches: int = 1
     grid_last: np.ndarray | None = None
+    iter_colour_ms: np.ndarray | None = None
 
 
 def integrate(proc: Process, sqrt_s: float, pdf_table, n_events: int, n_iter: int, seed: int,
@@ -147,9 +148,11 @@ def integrate(proc: Process, sqrt_s: float, pdf_table, n_events: int, n_iter: in
     npass = np.zeros(n_iter)
     tms = np.zeros(n_iter)
     ams = np.zeros(n_iter)
+    cms = np.zeros(n_iter)
     res.iter_pass = _ptr(npass)
     res.iter_event_ms = _ptr(tms)
     res.iter_amp_ms = _ptr(ams)
+    res.iter_colour_ms = _ptr(cms)
     grid_last = np.zeros((D, n_bins + 1))
     res.grid_last = _ptr(grid_last)
     pc = proc.c()
@@ -158,7 +161,8 @@ def integrate(proc: Process, sqrt_s: float, pdf_table, n_events: int, n_iter: in
     return IntegrationResult(res.sigma, res.sigma_err, res.chi2_dof, res.w_max, res.n_pass,
                              res.n_newton_fail, I, V, grid, hist, w, res.event_kernel_ms,
                              res.reduce_kernel_ms, npass, tms if profile else None,
-                             ams if profile else None, res.n_batches, grid_last)
+                             ams if profile else None, res.n_batches, grid_last,
+                             cms if profile else None)
 
 
 def evaluate_weights(proc: Process, sqrt_s: float, pdf_table, n: int, seed: int = 0, it: int = 0,

@@ -399,7 +399,8 @@ mf_status launch_stages_prec(mf_precision prec, const mf::StageParams& S, int ki
 // as many as fit at once), colour sum on the matrix cores, accumulation.
 template <typename T>
 mf_status launch_stages_ng5(const mf::StageParams& S, int kin_blocks, int n_cu, hipStream_t stream,
-                            hipEvent_t amp_begin, hipEvent_t amp_end, bool accumulate)
+                            hipEvent_t amp_begin, hipEvent_t amp_end, bool accumulate, hipEvent_t col_begin = nullptr,
+                            hipEvent_t col_end = nullptr)
 {
     constexpr int D = 2 + 3 * 5 - 4;
     int per_cu = 0, col_per_cu = 0;
@@ -422,8 +423,12 @@ mf_status launch_stages_ng5(const mf::StageParams& S, int kin_blocks, int n_cu, 
     MF_HIP(hipGetLastError());
     if (amp_end)
         MF_HIP(hipEventRecord(amp_end, stream));
+    if (col_begin)
+        MF_HIP(hipEventRecord(col_begin, stream));
     hipLaunchKernelGGL((mf::colour_kernel_ng5<T>), dim3(col_grid), dim3(mf::kBlock), 0, stream, S);
     MF_HIP(hipGetLastError());
+    if (col_end)
+        MF_HIP(hipEventRecord(col_end, stream));
     if (accumulate) {
         const size_t dyn = sizeof(double) * mf::kWavesPerBlock * D * S.P.n_bins;
         hipLaunchKernelGGL((mf::acc_kernel<5>), dim3(kin_blocks), dim3(mf::kBlock), dyn, stream, S);
@@ -436,13 +441,14 @@ mf_status launch_stages_ng5(const mf::StageParams& S, int kin_blocks, int n_cu, 
 }
 
 mf_status dispatch_stages(int ng, mf_precision prec, mf_colour col, const mf::StageParams& S, int kin_blocks,
-                          int n_cu, hipStream_t s, hipEvent_t a, hipEvent_t b)
+                          int n_cu, hipStream_t s, hipEvent_t a, hipEvent_t b, hipEvent_t c = nullptr,
+                          hipEvent_t d = nullptr)
 {
     if (ng == 5) {
         if (col != MF_COLOUR_FULL)
             return fail(MF_EUNSUPPORTED, "g g -> t tbar g g g runs with the full colour sum only");
-        return prec == MF_FP32_KAHAN ? launch_stages_ng5<float>(S, kin_blocks, n_cu, s, a, b, true)
-                                     : launch_stages_ng5<double>(S, kin_blocks, n_cu, s, a, b, true);
+        return prec == MF_FP32_KAHAN ? launch_stages_ng5<float>(S, kin_blocks, n_cu, s, a, b, true, c, d)
+                                     : launch_stages_ng5<double>(S, kin_blocks, n_cu, s, a, b, true, c, d);
     }
     if (ng == 2)
         return col == MF_COLOUR_LEADING ? launch_stages_prec<2, 1>(prec, S, kin_blocks, n_cu, s, a, b)
@@ -777,6 +783,8 @@ mf_status integrate_impl(const mf_process* proc, double sqrt_s, const mf_pdf_gri
     // Optional per-kernel timing: events recorded on the stream around every
     // launch (marks[3j] .. marks[3j+2]).
     std::vector<hipEvent_t> marks, amp_marks, grad_marks;
+    // per batch: amplitude kernel begin / end, and for t tbar g g g the colour kernel's
+    const size_t kMarks = ng == 5 ? 4 : 2;
     if (opt->profile) {
         marks.resize(3 * (size_t)n_iter);
         for (auto& ev : marks)
@@ -787,7 +795,7 @@ mf_status integrate_impl(const mf_process* proc, double sqrt_s, const mf_pdf_gri
                 MF_HIP(hipEventCreate(&ev));
         }
         if (staged) {
-            amp_marks.resize(2 * (size_t)n_iter * n_batches);
+            amp_marks.resize(kMarks * (size_t)n_iter * n_batches);
             for (auto& ev : amp_marks)
                 MF_HIP(hipEventCreate(&ev));
         }
@@ -813,13 +821,18 @@ mf_status integrate_impl(const mf_process* proc, double sqrt_s, const mf_pdf_gri
                 SP.first_batch = bi == 0;
                 SP.next_group = m.amp_counter;
                 SP.amps = m.st_amp;
-                hipEvent_t a = nullptr, b = nullptr;
+                hipEvent_t a = nullptr, b = nullptr, c = nullptr, d = nullptr;
                 if (opt->profile) {
-                    a = amp_marks[2 * ((size_t)j * n_batches + bi)];
-                    b = amp_marks[2 * ((size_t)j * n_batches + bi) + 1];
+                    const size_t at = kMarks * ((size_t)j * n_batches + bi);
+                    a = amp_marks[at];
+                    b = amp_marks[at + 1];
+                    if (kMarks == 4) {
+                        c = amp_marks[at + 2];
+                        d = amp_marks[at + 3];
+                    }
                 }
                 if ((st = dispatch_stages(ng, opt->precision, opt->colour, SP, n_waves / mf::kWavesPerBlock,
-                                          ws.n_cu, S.stream, a, b)) != MF_OK)
+                                          ws.n_cu, S.stream, a, b, c, d)) != MF_OK)
                     return st;
             }
         } else if ((st = dispatch_event(ng, opt->precision, opt->colour, P, n_waves / mf::kWavesPerBlock,
@@ -891,18 +904,24 @@ mf_status integrate_impl(const mf_process* proc, double sqrt_s, const mf_pdf_gri
             res->reduce_kernel_ms += b;
             if (res->iter_event_ms)
                 res->iter_event_ms[j] = a;
-            double amp = a;
+            double amp = a, colour = 0.0;
             if (staged) {
                 amp = 0.0;
                 for (uint64_t bi = 0; bi < n_batches; ++bi) {
+                    const size_t at = kMarks * ((size_t)j * n_batches + bi);
                     float c = 0.f;
-                    MF_HIP(hipEventElapsedTime(&c, amp_marks[2 * ((size_t)j * n_batches + bi)],
-                                               amp_marks[2 * ((size_t)j * n_batches + bi) + 1]));
+                    MF_HIP(hipEventElapsedTime(&c, amp_marks[at], amp_marks[at + 1]));
                     amp += c;
+                    if (kMarks == 4) {
+                        MF_HIP(hipEventElapsedTime(&c, amp_marks[at + 2], amp_marks[at + 3]));
+                        colour += c;
+                    }
                 }
             }
             if (res->iter_amp_ms)
                 res->iter_amp_ms[j] = amp;
+            if (res->iter_colour_ms)
+                res->iter_colour_ms[j] = colour;
         }
         if (grad && grad->iter_grad_ms)
             for (int j = 0; j < n_iter; ++j) {
