@@ -409,6 +409,9 @@ def main():
     ap.add_argument("--workload", default="ttxgg", choices=sorted(k for k in WORKLOADS if k != "ttxggg"))
     ap.add_argument("--no-ttxggg", action="store_true", help="skip the g g -> t tbar g g g legs")
     ap.add_argument("--ttxggg-events", type=int, default=1_000_000)
+    ap.add_argument("--ttxggg-only", action="store_true",
+                    help="only the g g -> t tbar g g g legs (for profiling them alone)")
+    ap.add_argument("--ttxggg-steps", type=int, default=3)
     ap.add_argument("--events", type=int, default=None)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-fp32", action="store_true")
@@ -447,6 +450,14 @@ def main():
         return
     import workloads as W
     from paper_2106_10279_amd import api
+
+    if args.ttxggg_only:
+        legs = {}
+        for prec in ("fp64",) + (() if args.no_fp32 else ("fp32_kahan",)):
+            log(f"[bench] g g -> t tbar g g g, {args.ttxggg_events} events x {args.ttxggg_steps} iterations, {prec}")
+            legs[f"ttxggg_{prec}"] = ttxggg_leg(api, torch, args.ttxggg_events, args.ttxggg_steps, prec)
+        print(json.dumps(legs), flush=True)
+        return
 
     wl = WORKLOADS[args.workload]
     n_events = args.events or wl["events"]
@@ -583,8 +594,8 @@ def main():
             "events/s")
     if not args.no_ttxggg and args.workload == "ttxgg":
         for prec in ("fp64", "fp32_kahan"):
-            log(f"[bench] g g -> t tbar g g g, {args.ttxggg_events} events x 3 iterations, {prec}")
-            out[f"ttxggg_{prec}"] = ttxggg_leg(api, torch, args.ttxggg_events, 3, prec)
+            log(f"[bench] g g -> t tbar g g g, {args.ttxggg_events} events x {args.ttxggg_steps} iterations, {prec}")
+            out[f"ttxggg_{prec}"] = ttxggg_leg(api, torch, args.ttxggg_events, args.ttxggg_steps, prec)
             log(f"[bench] ttxggg {prec} done: {out[f'ttxggg_{prec}']['value']:.4g} events/s")
     if not args.no_adjoint:
         log(f"[bench] adjoint: gg_ttx forward + gradient, {args.adjoint_events} events x 3 iterations")

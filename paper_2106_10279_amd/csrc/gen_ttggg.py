@@ -187,10 +187,22 @@ def emit_stages(st, tl):
     w("    constexpr int NG = COOP_NGJ_NG5;")
     w("    const T mtt = (T)mt;")
 
+    nloops = [0]
+
     def loop(count, offset):
-        # items spread over the lanes from `offset` on, so that independent
-        # stages of one group run side by side
-        w(f"    for (int it = (lane + nl - {offset % 640}) % nl; it < {count}; it += nl) {{")
+        # Waves take blocks of 64 items from a workgroup counter in LDS
+        # (ctr[k], zero at the start of the event): a wave on a compute unit
+        # SIMD shared by fewer waves runs faster and takes more blocks, so the
+        # workgroup reaches the next barrier together.
+        k = nloops[0]
+        nloops[0] += 1
+        w("    for (;;) {")
+        w("        unsigned blk = 0;")
+        w(f"        if ((lane & 63) == 0) blk = atomicAdd(&ctr[{k}], 64u);")
+        w("        blk = __builtin_amdgcn_readfirstlane(__shfl(blk, 0));")
+        w(f"        if (blk >= {count}u) break;")
+        w("        const int it = (int)blk + (lane & 63);")
+        w(f"        if (it >= {count}) continue;")
 
     def level(L, offset):
         nonlocal flops
@@ -223,7 +235,7 @@ def emit_stages(st, tl):
             w(f"            a{mu} += g * (j1[{mu}] * c1 - j2[{mu}] * c2 + c12 * (P2[{mu}] - P1[{mu}]));")
         w("        }")
         if ntrip:
-            w("#pragma unroll 2")
+            w("#pragma unroll 1")
             w(f"        for (int t = 0; t < {ntrip}; ++t) {{")
             w(f"            const unsigned long long tp = GJ5_L{L}_TRIP[si * {ntrip} + t];")
             w("            const unsigned lo = (unsigned)tp, hi = (unsigned)(tp >> 32);")
@@ -340,6 +352,7 @@ def emit_stages(st, tl):
     w("    __syncthreads();")
     level(5, 0)
     w("    __syncthreads();")
+    assert nloops[0] <= 8
     return "\n".join(L_), flops
 
 
@@ -362,8 +375,8 @@ def emit_amplitudes(st, K, den, perms):
         a(f"    const int m{x} = {x} + c >= 5 ? {x} + c - 5 : {x} + c;")
     flops = 0
 
-    def hbit(g):
-        return f"((hq >> {g}) & 1)"
+    def hbit(g, hv="hq"):
+        return f"(({hv} >> {g}) & 1)"
 
     def cur_ptr(cs):
         L = len(cs)
@@ -388,18 +401,18 @@ def emit_amplitudes(st, K, den, perms):
 
     def y_load(Y):
         if not Y:
-            return ["        cplx<T> yc[4];",
-                    f"        {{ const T* q = tab + {st_tab.v} + 8 * sB; "
+            return ["    cplx<T> yc[4];",
+                    f"    {{ const T* q = tab + {st_tab.v} + 8 * sB; "
                     "for (int i = 0; i < 4; ++i) yc[i] = cplx<T>(q[2 * i], q[2 * i + 1]); }"]
         if len(Y) == 1:
             g = Y[0]
-            return ["        cplx<T> yc[4];",
-                    f"        ldspins<COOP_NU1_NG5>(al16(obj + {st.v1} + CW * (4 * m{g} + 2 * sB + {hbit(g)})), yc);"]
+            return ["    cplx<T> yc[4];",
+                    f"    ldspins<COOP_NU1_NG5>(al16(obj + {st.v1} + CW * (4 * m{g} + 2 * sB + {hbit(g, 'hy')})), yc);"]
         gc, gd = Y
         orb = (((gd - gc) % N) - 1) * N
-        return ["        cplx<T> yc[4];",
-                f"        ldspins<COOP_NV2_NG5>(al16(obj + {st.v2} + CW * (8 * ({orb} + m{gc}) + 4 * sB + "
-                f"2 * {hbit(gc)} + {hbit(gd)})), yc);"]
+        return ["    cplx<T> yc[4];",
+                f"    ldspins<COOP_NV2_NG5>(al16(obj + {st.v2} + CW * (8 * ({orb} + m{gc}) + 4 * sB + "
+                f"2 * {hbit(gc, 'hy')} + {hbit(gd, 'hy')})), yc);"]
 
     # Two passes over the chunk, split by the last gluon of the ordering: the
     # blocks that end before the last gluon (Y = V(d) or V(cd)) differ between
@@ -409,9 +422,9 @@ def emit_amplitudes(st, K, den, perms):
     passes = [[k for k, sg in enumerate(chunk0) if sg[-1] in rest[:2]],
               [k for k, sg in enumerate(chunk0) if sg[-1] in rest[2:]]]
     sig = {}
-    for ks in passes:
+    for pi, ks in enumerate(passes):
         loc = {k: i for i, k in enumerate(ks)}
-        a("    {")
+        a(f"    if (pass == {pi}) {{")
         a(f"    T Ar[{len(ks)}], Ai[{len(ks)}];")
         groups = {}
         for k in ks:
@@ -424,14 +437,26 @@ def emit_amplitudes(st, K, den, perms):
         for gi, key in enumerate(keys):
             for (_, k) in groups[key]:
                 last[k] = gi
+        # Each group forms its addresses from an opaque copy of the helicity
+        # bits (hp0 / hp1 alternately), defined at the start of the group
+        # before it: the addresses and LDS reads of a group can move up into
+        # the arithmetic of the one before, not further (each further group
+        # ahead would hold its operands in registers).
+        a("    int hp0 = hg, hp1 = hg;")
+        a('    asm volatile("" : "+v"(hp0));')
         for gi, (X, Y) in enumerate(keys):
+            cur, nxt = f"hp{gi % 2}", f"hp{(gi + 1) % 2}"
+            if gi == 0 or keys[gi - 1][1] != Y:
+                # a run of groups with the same antitop-side spinor Y: read
+                # once for the run
+                a("    {")
+                a(f"    const int hy = {cur};")
+                A.extend(y_load(Y))
             a("    {")
-            # an opaque copy of the helicity bits per group: the group's
-            # addresses are formed here, not hoisted and held from the start
-            a("        int hq = hg;")
-            a('        asm volatile("" : "+v"(hq));')
+            a(f"        const int hq = {cur};")
+            a(f"        {nxt} = hg;")
+            a(f'        asm volatile("" : "+v"({nxt}));')
             A.extend(x_load(X))
-            A.extend(y_load(Y))
             a("        cplx<T> d[4];")
             a("        bilinear(xr, yc, d);")
             flops += 64
@@ -481,6 +506,8 @@ def emit_amplitudes(st, K, den, perms):
             # orderings complete after this group go to memory at once
             for k in sorted(k for k, g in last.items() if g == gi):
                 a(f"    stj(J + (size_t)(c * {CHUNK} + {k}) * {2 * NHEL} + 2 * hel, Ar[{loc[k]}], Ai[{loc[k]}]);")
+            if gi + 1 == len(keys) or keys[gi + 1][1] != Y:
+                a("    }")
         a("    }")
     assert len(sig) == CHUNK
     # row R = c * 24 + k holds sig[k] A(shift(chunk0[k], c))
@@ -568,6 +595,11 @@ static constexpr short CFRAG64_NG5[{len(frag64)}] = {{{frag64_s}}};
 static constexpr short CFRAG32_NG5[{len(frag32)}] = {{{frag32_s}}};
 {tables}
 
+// Items of the amplitude phase per event: chunk (first gluon) x pass (last
+// gluon in {1, 2} or {3, 4} after relabelling) x half of the helicity
+// configurations, one wave each.
+static constexpr int AMP_ITEMS_NG5 = 20;
+
 // Per-event table and level-1 currents, written by lanes 0 .. 63.
 template <typename T, int NS = COOP_NGJ_NG5>
 __device__ __forceinline__ void fill_table_coop_ng5(const double* __restrict__ mom, double eb, double mt, double mw,
@@ -576,21 +608,23 @@ __device__ __forceinline__ void fill_table_coop_ng5(const double* __restrict__ m
 {fill}
 }}
 
-// The event's object store from its table; every lane 0 .. nl-1 of the
-// workgroup calls it (it contains workgroup barriers, the last at its end).
+// The event's object store from its table; every lane of the workgroup
+// calls it (it contains workgroup barriers, the last at its end).  ctr: eight
+// work counters in LDS, zero on entry.
 template <typename T>
 __device__ __forceinline__ void coop_stages_ng5(const T* __restrict__ tab, T* __restrict__ obj, double mt,
-                                               int lane, int nl)
+                                               int lane, unsigned* ctr)
 {{
 {stages}
 }}
 
-// The 24 partial amplitudes of chunk c (orderings whose first gluon is c)
-// for helicity configuration hel, into rows 24 c .. 24 c + 23 of the event's
-// amplitude block J ([row][hel][re, im]).
+// The 12 partial amplitudes of pass `pass` of chunk c (orderings whose
+// first gluon is c) for helicity configuration hel, into their rows of the
+// event's amplitude block J ([row][hel][re, im], rows 24 c .. 24 c + 23).
+// c and pass are uniform over the wave.
 template <typename T>
 __device__ __forceinline__ void coop_amp_ng5(const T* __restrict__ tab, const T* __restrict__ obj, int hel, int c,
-                                            T* __restrict__ J)
+                                            int pass, T* __restrict__ J)
 {{
 {amp}
 }}

@@ -1049,10 +1049,13 @@ __global__ void __launch_bounds__(kBlock) acc_kernel(StageParams S)
 // g g -> t tbar g g g (Sec. 3.2, Fig. 4: the paper's largest process).  The
 // object store of one event (15560 values: 124 KB in FP64, 62 KB in FP32)
 // takes most of a compute unit's LDS, so one workgroup of ten waves serves
-// one event at a time: all 640 lanes build the objects, then lane
-// (c, h) = (tid / 128, tid % 128) evaluates the 24 orderings that start with
-// gluon c for helicity configuration h and stores them to the event's
-// amplitude block in device memory.  The colour sum over 120 x 120 orderings
+// one event at a time: all 640 lanes build the objects, then the waves take
+// the event's 20 amplitude items -- (first gluon c, pass, half of the 128
+// helicity configurations), 12 orderings for 64 configurations each -- and
+// store the partial amplitudes to the event's block in device memory.  Work
+// is handed out per wave from LDS counters: ten waves share four SIMDs
+// unevenly, and a static split would leave the workgroup waiting at every
+// barrier for the waves of the busiest SIMD.  The colour sum over 120 x 120 orderings
 // is a dense contraction and runs on the matrix cores in colour_kernel_ng5.
 // Events are claimed one at a time from a device counter (cleared by
 // kin_kernel); rejected events (prefactor 0) are skipped.
@@ -1069,29 +1072,44 @@ __global__ void __launch_bounds__(kBlockNg5) amp_kernel_ng5(StageParams S)
     __shared__ __align__(16) T s_obj[COOP_OBJ_NG5];
     __shared__ double s_mom[L::kMom];
     __shared__ unsigned long long s_ev;
+    __shared__ unsigned s_ctr[9];          // work counters: eight for the stages, one for the amplitude items
     const int tid = threadIdx.x;
-    // the chunk is uniform over each wave (two waves per chunk)
-    const int c = __builtin_amdgcn_readfirstlane(tid >> 7);
-    const int h = tid & 127;
     T* J = static_cast<T*>(S.amps);
-    for (;;) {
+    if (tid == 0)
+        s_ev = atomicAdd(S.next_group, 1ull);
+    __syncthreads();
+    uint64_t e = s_ev;
+    __syncthreads();
+    while (e < S.count) {
+        // the next event is claimed now; its index is read after this one
         if (tid == 0)
             s_ev = atomicAdd(S.next_group, 1ull);
+        if (S.pref[e] != 0.0) {
+            if (tid < L::kMom)
+                s_mom[tid] = S.mom[e * L::kMom + tid];
+            if (tid < 9)
+                s_ctr[tid] = 0u;
+            __syncthreads();
+            if (tid < kWave)
+                fill_table_coop_ng5<T>(s_mom, s_mom[L::kMom - 1], S.P.m_top, S.P.mw, s_tab, s_obj, tid);
+            __syncthreads();
+            coop_stages_ng5<T>(s_tab, s_obj, S.P.m_top, tid, s_ctr);
+            // amplitude items (chunk, pass, helicity half), one wave each, taken
+            // from a counter so that waves on less crowded SIMDs take more
+            for (;;) {
+                unsigned item = 0;
+                if ((tid & 63) == 0)
+                    item = atomicAdd(&s_ctr[8], 1u);
+                item = __builtin_amdgcn_readfirstlane(__shfl(item, 0));
+                if (item >= (unsigned)AMP_ITEMS_NG5)
+                    break;
+                const int c = (int)(item % 5u), rest = (int)(item / 5u);
+                coop_amp_ng5<T>(s_tab, s_obj, 64 * (rest & 1) + (tid & 63), c, rest >> 1, J + e * kAmpEventNg5);
+            }
+        }
         __syncthreads();
-        const uint64_t e = s_ev;
-        __syncthreads();
-        if (e >= S.count)
-            break;
-        if (S.pref[e] == 0.0)
-            continue;
-        if (tid < L::kMom)
-            s_mom[tid] = S.mom[e * L::kMom + tid];
-        __syncthreads();
-        if (tid < kWave)
-            fill_table_coop_ng5<T>(s_mom, s_mom[L::kMom - 1], S.P.m_top, S.P.mw, s_tab, s_obj, tid);
-        __syncthreads();
-        coop_stages_ng5<T>(s_tab, s_obj, S.P.m_top, tid, kBlockNg5);
-        coop_amp_ng5<T>(s_tab, s_obj, h, c, J + e * kAmpEventNg5);
+        e = s_ev;
+        // every lane has read the index before lane 0 claims the next one
         __syncthreads();
     }
 }
