@@ -5,9 +5,9 @@ _gen/amp_ng5.inc.
 Same physics and representation as the smaller processes (Sec. 2.3: external
 wavefunctions, vertices and propagators; colour-ordered Berends-Giele
 recursion; chiral spinors, real linear gluon polarisations), organised for a
-workgroup of ten waves per event:
+workgroup of eight waves per event:
 
-  * Object store in LDS, built once per event by all 640 lanes: gluon
+  * Object store in LDS, built once per event by all the workgroup's lanes: gluon
     currents j(s; h) of every ordered gluon sequence s up to reflection,
     j(reverse s) = (-1)^(|s|+1) j(s), for every helicity pattern of its
     gluons; top-line spinors Ubar(a), Ubar(ab) and antitop-line spinors
@@ -16,8 +16,9 @@ workgroup of ten waves per event:
     ordering: A(sigma) = sum over blocks beta = sigma[i:j] with i <= 2 < j of
     Xbar(sigma[:i]) gamma.j(beta) Y(sigma[j:]), Xbar in {ubar, Ubar(a),
     Ubar(ab)}, Y in {v, V(d), V(cd)}.
-  * One lane per (first gluon c, helicity configuration): the 24 orderings
-    that start with gluon c.  The five chunks share one code path: the cyclic
+  * One lane per (first gluon c, helicity configuration) and pass: the
+    orderings that start with gluon c, in passes by their last gluon.  The
+    five chunks share one code path: the cyclic
     relabelling g -> (g + c) mod 5 maps the orderings that start with gluon 0
     onto those that start with c.  Reflections of gluon sequences are
     resolved by a rule that commutes with that relabelling (the orientation
@@ -36,6 +37,10 @@ N = 5
 NPERM = 120
 CHUNK = 24
 NHEL = 1 << (N + 2)
+# passes over each chunk's orderings (split by the last gluon): fewer live
+# accumulators and finer work items, against the antitop-side spinor products
+# that every pass forms again
+NPASS = 2
 
 
 def shift(seq, c):
@@ -127,12 +132,16 @@ def colour_matrix_ng5(G):
 
 
 def emit_tables(st, tl):
+    """Split tables of the current levels, concatenated into one array that
+    the kernel stages in LDS (STAGE_TAB_NG5, offsets STAGE_*_NG5), and the
+    table offsets of -1/P^2 per sequence (STAGE_NINV_NG5)."""
     out = []
+    tab, ninv, offs = [], [], {}
     for L in range(2, N + 1):
         seqs = st.levels[L]
         px, tx, ni = [], [], []
         for cs in seqs:
-            ni.append(str(tl.ninv[mask(cs)]))
+            ni.append(tl.ninv[mask(cs)])
             for k in range(1, L):
                 parts = (cs[:k], cs[k:])
                 (c1, s1, r1), (c2, s2, r2) = (canon5(p) for p in parts)
@@ -149,12 +158,19 @@ def emit_tables(st, tl):
                     neg = (cc[0][1] * cc[1][1] * cc[2][1]) < 0
                     lo = bs[0] | cc[0][2] << 12 | bs[1] << 13 | cc[1][2] << 25 | neg << 26
                     tx.append(lo | (bs[2] | cc[2][2] << 12) << 32)
-        out.append(f"static constexpr unsigned long long GJ5_L{L}_PAIR[{len(px)}] = "
-                   f"{{{', '.join(f'{v}ull' for v in px)}}};")
-        if tx:
-            out.append(f"static constexpr unsigned long long GJ5_L{L}_TRIP[{len(tx)}] = "
-                       f"{{{', '.join(f'{v}ull' for v in tx)}}};")
-        out.append(f"static constexpr short GJ5_L{L}_NINV[{len(ni)}] = {{{', '.join(ni)}}};")
+        offs[f"L{L}_PAIR"] = len(tab)
+        tab += px
+        offs[f"L{L}_TRIP"] = len(tab)
+        tab += tx
+        offs[f"L{L}_NINV"] = len(ninv)
+        ninv += ni
+    for k, v in offs.items():
+        out.append(f"static constexpr int STAGE_{k}_NG5 = {v};")
+    out.append(f"static constexpr int STAGE_TAB_SIZE_NG5 = {len(tab)};")
+    out.append(f"static constexpr unsigned long long STAGE_TAB_NG5[{len(tab)}] = "
+               f"{{{', '.join(f'{v}ull' for v in tab)}}};")
+    out.append(f"static constexpr int STAGE_NINV_SIZE_NG5 = {len(ninv)};")
+    out.append(f"static constexpr short STAGE_NINV_NG5[{len(ninv)}] = {{{', '.join(str(v) for v in ninv)}}};")
     # ordered pairs in object order: labels, the current j(ab) (base, sign,
     # orientation) and the momentum-table entries of the propagators
     cd, jb, js, jr, kv, ku = [], [], [], [], [], []
@@ -214,9 +230,9 @@ def emit_stages(st, tl):
         w(f"        const int si = it >> {L};")
         w(f"        const unsigned hm = (unsigned)it & {(1 << L) - 1}u;")
         w("        T a0 = 0, a1 = 0, a2 = 0, a3 = 0;")
-        w("#pragma unroll 2")
+        w("#pragma unroll")
         w(f"        for (int k = 1; k < {L}; ++k) {{")
-        w(f"            const unsigned long long sp = GJ5_L{L}_PAIR[si * {npair} + k - 1];")
+        w(f"            const unsigned long long sp = stab[STAGE_L{L}_PAIR_NG5 + si * {npair} + k - 1];")
         w("            const unsigned lo = (unsigned)sp, hi = (unsigned)(sp >> 32);")
         w("            const unsigned h1 = sub_pattern(hm, 0, k, (lo >> 12) & 1u);")
         w(f"            const unsigned h2 = sub_pattern(hm, k, {L} - k, (lo >> 25) & 1u);")
@@ -235,9 +251,9 @@ def emit_stages(st, tl):
             w(f"            a{mu} += g * (j1[{mu}] * c1 - j2[{mu}] * c2 + c12 * (P2[{mu}] - P1[{mu}]));")
         w("        }")
         if ntrip:
-            w("#pragma unroll 1")
+            w("#pragma unroll")
             w(f"        for (int t = 0; t < {ntrip}; ++t) {{")
-            w(f"            const unsigned long long tp = GJ5_L{L}_TRIP[si * {ntrip} + t];")
+            w(f"            const unsigned long long tp = stab[STAGE_L{L}_TRIP_NG5 + si * {ntrip} + t];")
             w("            const unsigned lo = (unsigned)tp, hi = (unsigned)(tp >> 32);")
             # split points of triple t (a < b), in the order of the table
             spl = [(a, b) for a in range(1, L) for b in range(a + 1, L)]
@@ -259,7 +275,7 @@ def emit_stages(st, tl):
             for mu in range(4):
                 w(f"            a{mu} += g * (j1[{mu}] * d23 - (T)2 * j2[{mu}] * d13 + j3[{mu}] * d12);")
             w("        }")
-        w(f"        const T f = tab[GJ5_L{L}_NINV[si]];")
+        w(f"        const T f = tab[sninv[STAGE_L{L}_NINV_NG5 + si]];")
         w(f"        st4s<NG>(al16(obj + CW * ({st.ob[L]} + it)), a0 * f, a1 * f, a2 * f, a3 * f);")
         w("    }")
 
@@ -414,13 +430,13 @@ def emit_amplitudes(st, K, den, perms):
                 f"    ldspins<COOP_NV2_NG5>(al16(obj + {st.v2} + CW * (8 * ({orb} + m{gc}) + 4 * sB + "
                 f"2 * {hbit(gc, 'hy')} + {hbit(gd, 'hy')})), yc);"]
 
-    # Two passes over the chunk, split by the last gluon of the ordering: the
+    # Passes over the chunk, split by the last gluon of the ordering: the
     # blocks that end before the last gluon (Y = V(d) or V(cd)) differ between
-    # the passes, only the few with Y = v are formed twice; half the
-    # accumulators are live at a time.
+    # the passes, only the few with Y = v are formed in each pass; a fraction
+    # of the accumulators is live at a time.
     rest = [g for g in range(1, N)]
-    passes = [[k for k, sg in enumerate(chunk0) if sg[-1] in rest[:2]],
-              [k for k, sg in enumerate(chunk0) if sg[-1] in rest[2:]]]
+    per = len(rest) // NPASS
+    passes = [[k for k, sg in enumerate(chunk0) if sg[-1] in rest[q * per:(q + 1) * per]] for q in range(NPASS)]
     sig = {}
     for pi, ks in enumerate(passes):
         loc = {k: i for i, k in enumerate(ks)}
@@ -595,10 +611,11 @@ static constexpr short CFRAG64_NG5[{len(frag64)}] = {{{frag64_s}}};
 static constexpr short CFRAG32_NG5[{len(frag32)}] = {{{frag32_s}}};
 {tables}
 
-// Items of the amplitude phase per event: chunk (first gluon) x pass (last
-// gluon in {1, 2} or {3, 4} after relabelling) x half of the helicity
-// configurations, one wave each.
-static constexpr int AMP_ITEMS_NG5 = 20;
+// Items of the amplitude phase per event: chunk (first gluon) x pass (a
+// subset of the last gluon's labels after relabelling) x half of the
+// helicity configurations, one wave each; item = c + 5 (half + 2 pass).
+static constexpr int AMP_PASSES_NG5 = {NPASS};
+static constexpr int AMP_ITEMS_NG5 = {5 * 2 * NPASS};
 
 // Per-event table and level-1 currents, written by lanes 0 .. 63.
 template <typename T, int NS = COOP_NGJ_NG5>
@@ -610,15 +627,18 @@ __device__ __forceinline__ void fill_table_coop_ng5(const double* __restrict__ m
 
 // The event's object store from its table; every lane of the workgroup
 // calls it (it contains workgroup barriers, the last at its end).  ctr: eight
-// work counters in LDS, zero on entry.
+// work counters in LDS, zero on entry; stab, sninv: copies of STAGE_TAB_NG5
+// and STAGE_NINV_NG5 in LDS.
 template <typename T>
 __device__ __forceinline__ void coop_stages_ng5(const T* __restrict__ tab, T* __restrict__ obj, double mt,
-                                               int lane, unsigned* ctr)
+                                               int lane, unsigned* ctr,
+                                               const unsigned long long* __restrict__ stab,
+                                               const short* __restrict__ sninv)
 {{
 {stages}
 }}
 
-// The 12 partial amplitudes of pass `pass` of chunk c (orderings whose
+// The partial amplitudes of pass `pass` of chunk c (orderings whose
 // first gluon is c) for helicity configuration hel, into their rows of the
 // event's amplitude block J ([row][hel][re, im], rows 24 c .. 24 c + 23).
 // c and pass are uniform over the wave.

@@ -1048,19 +1048,20 @@ __global__ void __launch_bounds__(kBlock) acc_kernel(StageParams S)
 // ---------------------------------------------------------------------------
 // g g -> t tbar g g g (Sec. 3.2, Fig. 4: the paper's largest process).  The
 // object store of one event (15560 values: 124 KB in FP64, 62 KB in FP32)
-// takes most of a compute unit's LDS, so one workgroup of ten waves serves
-// one event at a time: all 640 lanes build the objects, then the waves take
-// the event's 20 amplitude items -- (first gluon c, pass, half of the 128
+// takes most of a compute unit's LDS, so one workgroup of eight waves (two
+// per SIMD) serves one event at a time -- in FP32 two workgroups share a
+// compute unit.  All 512 lanes build the objects, then the waves take the
+// event's 20 amplitude items -- (first gluon c, pass, half of the 128
 // helicity configurations), 12 orderings for 64 configurations each -- and
 // store the partial amplitudes to the event's block in device memory.  Work
-// is handed out per wave from LDS counters: ten waves share four SIMDs
-// unevenly, and a static split would leave the workgroup waiting at every
-// barrier for the waves of the busiest SIMD.  The colour sum over 120 x 120 orderings
+// is handed out per wave from LDS counters, so that waves that run faster
+// (a SIMD shared with fewer waves) take more of it and the workgroup meets
+// at its barriers together.  The colour sum over 120 x 120 orderings
 // is a dense contraction and runs on the matrix cores in colour_kernel_ng5.
 // Events are claimed one at a time from a device counter (cleared by
 // kin_kernel); rejected events (prefactor 0) are skipped.
 // ---------------------------------------------------------------------------
-constexpr int kBlockNg5 = 640;
+constexpr int kBlockNg5 = 512;
 constexpr int kAmpRowNg5 = 2 * 128;                        // T per row: 128 helicities x (re, im)
 constexpr size_t kAmpEventNg5 = (size_t)NPERM_NG5 * kAmpRowNg5;  // T per event
 
@@ -1073,8 +1074,14 @@ __global__ void __launch_bounds__(kBlockNg5) amp_kernel_ng5(StageParams S)
     __shared__ double s_mom[L::kMom];
     __shared__ unsigned long long s_ev;
     __shared__ unsigned s_ctr[9];          // work counters: eight for the stages, one for the amplitude items
+    __shared__ unsigned long long s_stab[STAGE_TAB_SIZE_NG5];   // split tables of the current levels
+    __shared__ short s_ninv[STAGE_NINV_SIZE_NG5];
     const int tid = threadIdx.x;
     T* J = static_cast<T*>(S.amps);
+    for (int i = tid; i < STAGE_TAB_SIZE_NG5; i += kBlockNg5)
+        s_stab[i] = STAGE_TAB_NG5[i];
+    for (int i = tid; i < STAGE_NINV_SIZE_NG5; i += kBlockNg5)
+        s_ninv[i] = STAGE_NINV_NG5[i];
     if (tid == 0)
         s_ev = atomicAdd(S.next_group, 1ull);
     __syncthreads();
@@ -1093,7 +1100,7 @@ __global__ void __launch_bounds__(kBlockNg5) amp_kernel_ng5(StageParams S)
             if (tid < kWave)
                 fill_table_coop_ng5<T>(s_mom, s_mom[L::kMom - 1], S.P.m_top, S.P.mw, s_tab, s_obj, tid);
             __syncthreads();
-            coop_stages_ng5<T>(s_tab, s_obj, S.P.m_top, tid, s_ctr);
+            coop_stages_ng5<T>(s_tab, s_obj, S.P.m_top, tid, s_ctr, s_stab, s_ninv);
             // amplitude items (chunk, pass, helicity half), one wave each, taken
             // from a counter so that waves on less crowded SIMDs take more
             for (;;) {
@@ -1169,16 +1176,23 @@ __global__ void __launch_bounds__(kBlock) colour_kernel_ng5(StageParams S)
             continue;
         const T* X = J + e * kAmpEventNg5;
         double acc = 0.0;
-        for (int cb = 0; cb < kAmpRowNg5 / 16; ++cb) {
+        // the lane's 32 values of column block cb (rows of the tiles it holds)
+        auto load = [&](int cb, T (&v)[8][4]) {
             const int col = 16 * cb + col0;
-            T x[8][4];
 #pragma unroll
             for (int b = 0; b < 8; ++b)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int row = 16 * b + (sizeof(T) == 8 ? q + 4 * r : 4 * q + r);
-                    x[b][r] = row < NPERM_NG5 ? X[(size_t)row * kAmpRowNg5 + col] : (T)0;
+                    v[b][r] = row < NPERM_NG5 ? X[(size_t)row * kAmpRowNg5 + col] : (T)0;
                 }
+        };
+        T x[8][4], xn[8][4];
+        load(0, x);
+        for (int cb = 0; cb < kAmpRowNg5 / 16; ++cb) {
+            // the next column block is read while this one is contracted
+            if (cb + 1 < kAmpRowNg5 / 16)
+                load(cb + 1, xn);
             // tile pairs in order (a, b <= a); the four fragments of the next
             // pair are read from LDS while the current pair's steps run
             constexpr int PA[36] = {0, 1, 1, 2, 2, 2, 3, 3, 3, 3, 4, 4, 4, 4, 4, 5, 5, 5,
@@ -1212,6 +1226,11 @@ __global__ void __launch_bounds__(kBlock) colour_kernel_ng5(StageParams S)
                     f[s] = g[s];
                 __builtin_amdgcn_sched_barrier(0);
             }
+#pragma unroll
+            for (int b = 0; b < 8; ++b)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    x[b][r] = xn[b][r];
         }
         for (int off = kWave >> 1; off > 0; off >>= 1)
             acc += __shfl_xor(acc, off);
