@@ -319,6 +319,28 @@ static void spinor_v(const double *p, double m, int s, cplx *v)
     v[3] = n * eta[1];
 }
 
+/* u(p, s) for an incoming fermion (the column spinor whose Dirac adjoint is
+ * spinor_ubar), and vbar(p, s) = v^dagger gamma^0 for an incoming antifermion. */
+static void spinor_u(const double *p, double m, int s, cplx *u)
+{
+    cplx ub[4];
+    spinor_ubar(p, m, s, ub);
+    u[0] = conj(ub[0]);
+    u[1] = conj(ub[1]);
+    u[2] = -conj(ub[2]);
+    u[3] = -conj(ub[3]);
+}
+
+static void spinor_vbar(const double *p, double m, int s, cplx *vb)
+{
+    cplx v[4];
+    spinor_v(p, m, s, v);
+    vb[0] = conj(v[0]);
+    vb[1] = conj(v[1]);
+    vb[2] = -conj(v[2]);
+    vb[3] = -conj(v[3]);
+}
+
 /* Helicity polarisation vectors transverse to the 3-momentum of p:
  * eps_pm = (-/+ e1 - i e2)/sqrt(2) with e1 = (0, cos th cos ph, cos th sin ph, -sin th),
  * e2 = (0, -sin ph, cos ph, 0).  hel 0 -> +, 1 -> -. */
@@ -955,6 +977,45 @@ double mfo_me2_sum(int n_g, const double *p, double m, double width)
     for (int h = 0; h < nh; ++h)
         hel_from_index(n_g, h, hel + h * (n_g + 2));
     return mfo_me2_sum_hel(n_g, p, m, width, nh, hel);
+}
+
+/* ------------------------------------------------------------------------ */
+/* q qbar -> t tbar                                                          */
+/* ------------------------------------------------------------------------ */
+/* One s-channel gluon (Peskin-Schroeder rules as below, g = 1):
+ *   M = T^a_{i_qbar i_q} T^a_{i_t i_tbar} [vbar(pb) gamma^mu u(pa)]
+ *       [ubar(k1) gamma_mu v(k2)] / s      (overall phase dropped);
+ * the colour sum of |T^a_{ji} T^a_{kl}|^2 over all indices is
+ * Tr(T^a T^b) Tr(T^a T^b) = delta^ab delta^ab / 4 = 2.  Massless quarks. */
+double mfo_me2_qqbar_ttx(const double *p, double m)
+{
+    init_gamma();
+    double pa[4], pb[4];
+    for (int mu = 0; mu < 4; ++mu) {
+        pa[mu] = -p[8 + mu];
+        pb[mu] = -p[12 + mu];
+    }
+    double P[4] = { pa[0] + pb[0], pa[1] + pb[1], pa[2] + pb[2], pa[3] + pb[3] };
+    double s = P[0] * P[0] - P[1] * P[1] - P[2] * P[2] - P[3] * P[3];
+    double total = 0.0;
+    for (int h = 0; h < 16; ++h) {
+        cplx u[4], vb[4], ub[4], v[4];
+        spinor_u(pa, 0.0, h & 1, u);
+        spinor_vbar(pb, 0.0, (h >> 1) & 1, vb);
+        spinor_ubar(p, m, (h >> 2) & 1, ub);
+        spinor_v(p + 4, m, (h >> 3) & 1, v);
+        cplx J[4], K[4];
+        for (int mu = 0; mu < 4; ++mu) {
+            cplx t[4];
+            row_times(vb, G[mu], t);
+            J[mu] = row_dot_col(t, u);
+            row_times(ub, G[mu], t);
+            K[mu] = row_dot_col(t, v);
+        }
+        cplx amp = (J[0] * K[0] - J[1] * K[1] - J[2] * K[2] - J[3] * K[3]) / s;
+        total += creal(amp * conj(amp));
+    }
+    return 2.0 * total;
 }
 
 /* ------------------------------------------------------------------------ */

@@ -68,15 +68,29 @@ static double factorial(int n)
  * ill-conditioned: |d ln(x g)/d ln x| above 1e3 means that a one-ulp change
  * of ln x moves the result by more than ~1e-13.  Estimated by a central
  * difference of the interpolant itself with relative step 1e-7 in x. */
-static int pdf_ill_conditioned(const mfo_pdf_grid *pdf, double x, double q2)
+static double pdf_value(const mfo_pdf_grid *pdf, int table, double x, double q2)
+{
+    return table < 0 ? mfo_pdf_xf(pdf, x, q2) : mfo_pdf_xq(pdf, table, x, q2);
+}
+
+static int table_ill_conditioned(const mfo_pdf_grid *pdf, int table, double x, double q2)
 {
     double h = 1e-7;
-    double up = mfo_pdf_xf(pdf, x * (1.0 + h), q2);
-    double dn = mfo_pdf_xf(pdf, x * (1.0 - h), q2);
+    double up = pdf_value(pdf, table, x * (1.0 + h), q2);
+    double dn = pdf_value(pdf, table, x * (1.0 - h), q2);
     if (up == 0.0 || dn == 0.0 || (up > 0.0) != (dn > 0.0))
         return 1;
     double kappa = fabs(log(fabs(up)) - log(fabs(dn))) / (2.0 * h);
     return kappa > 1e3;
+}
+
+/* The gluon table (table -1) and, for p p, the four quark tables. */
+static int pdf_ill_conditioned(const mfo_pdf_grid *pdf, double x, double q2, int quarks)
+{
+    for (int t = -1; t < (quarks ? 4 : 0); ++t)
+        if (table_ill_conditioned(pdf, t, x, q2))
+            return 1;
+    return 0;
 }
 
 /* Everything after the VEGAS map: x = mapped variables, jac = J_V. */
@@ -98,6 +112,7 @@ static double weight_from_x(const mfo_process *proc, double sqrt_s,
     ev->colour_kappa = 0.0;
     ev->newton_kappa = 0.0;
     ev->ps_weight = ev->f1 = ev->f2 = ev->me2 = 0.0;
+    ev->me2_q[0] = ev->me2_q[1] = ev->lum_q[0] = ev->lum_q[1] = 0.0;
     ev->w = 0.0;
     memset(ev->k, 0, sizeof(ev->k));
 
@@ -140,7 +155,8 @@ static double weight_from_x(const mfo_process *proc, double sqrt_s,
     double q2 = proc->mu_f * proc->mu_f;
     ev->f1 = mfo_pdf_xf(pdf, ev->x1, q2) / ev->x1;
     ev->f2 = mfo_pdf_xf(pdf, ev->x2, q2) / ev->x2;
-    ev->ill_conditioned = pdf_ill_conditioned(pdf, ev->x1, q2) || pdf_ill_conditioned(pdf, ev->x2, q2);
+    const int pp = proc->initial == 1;
+    ev->ill_conditioned = pdf_ill_conditioned(pdf, ev->x1, q2, pp) || pdf_ill_conditioned(pdf, ev->x2, q2, pp);
 
     /* All-outgoing momenta for the amplitude: t, tbar, -p_a, -p_b, gluons. */
     double p[(MFO_MAX_G + 2) * 4];
@@ -173,8 +189,28 @@ static double weight_from_x(const mfo_process *proc, double sqrt_s,
     /* average over 2 x 2 initial helicities and 8 x 8 initial colours,
      * symmetry factor 1/(n_g - 2)! for identical final-state gluons */
     ev->me2 = pow(gs2, n_g) * sum / (4.0 * 64.0 * factorial(n_g - 2));
+    ev->me2_q[0] = ev->me2_q[1] = 0.0;
+    ev->lum_q[0] = ev->lum_q[1] = 0.0;
+    if (pp) {
+        /* q qbar channels: the quark from beam 1 (u ubar, d dbar) or from beam 2
+         * (ubar u, dbar d); average over 2 x 2 helicities and 3 x 3 colours */
+        double pr[16];
+        memcpy(pr, p, sizeof(double) * 8);
+        memcpy(pr + 8, pb, sizeof(pb));
+        memcpy(pr + 12, pa, sizeof(pa));
+        ev->me2_q[0] = gs2 * gs2 * mfo_me2_qqbar_ttx(p, m) / 36.0;
+        ev->me2_q[1] = gs2 * gs2 * mfo_me2_qqbar_ttx(pr, m) / 36.0;
+        double x1 = ev->x1, x2 = ev->x2;
+        double u1 = mfo_pdf_xq(pdf, 0, x1, q2) / x1, ub1 = mfo_pdf_xq(pdf, 1, x1, q2) / x1;
+        double d1 = mfo_pdf_xq(pdf, 2, x1, q2) / x1, db1 = mfo_pdf_xq(pdf, 3, x1, q2) / x1;
+        double u2 = mfo_pdf_xq(pdf, 0, x2, q2) / x2, ub2 = mfo_pdf_xq(pdf, 1, x2, q2) / x2;
+        double d2 = mfo_pdf_xq(pdf, 2, x2, q2) / x2, db2 = mfo_pdf_xq(pdf, 3, x2, q2) / x2;
+        ev->lum_q[0] = u1 * ub2 + d1 * db2;
+        ev->lum_q[1] = ub1 * u2 + db1 * d2;
+    }
 
-    ev->w = jac * W * ev->f1 * ev->f2 * ev->me2 / (2.0 * ev->shat) * GEV2_TO_PB;
+    ev->w = jac * W * (ev->f1 * ev->f2 * ev->me2 + ev->lum_q[0] * ev->me2_q[0] + ev->lum_q[1] * ev->me2_q[1]) /
+            (2.0 * ev->shat) * GEV2_TO_PB;
     return ev->w;
 }
 

@@ -50,6 +50,9 @@ typedef struct {
     int    helicity;           /* 0: sum over helicity configurations;
                                   1: Monte Carlo over them (one sampled
                                   configuration of the linear basis)         */
+    int    initial;            /* 0: g g initial state; 1: p p, the g g channel
+                                  plus q qbar from the quark tables (u, ubar,
+                                  d, dbar; n_g = 2 only)                     */
 } mfo_process;
 
 typedef struct {
@@ -57,6 +60,8 @@ typedef struct {
     const double *log_x;       /* [n_x]  ascending ln x knots                  */
     const double *log_q2;      /* [n_q2] ascending ln Q^2 knots                */
     const double *xf;          /* [n_q2][n_x] row-major values of x g(x, Q^2)  */
+    const double *xq;          /* [4][n_q2][n_x] x q(x, Q^2) for u, ubar, d,
+                                  dbar, or NULL (gluons only)                 */
 } mfo_pdf_grid;
 
 typedef struct {
@@ -78,6 +83,10 @@ typedef struct {
     int64_t colour_cfg;        /* colour = 2, 3: the event's assignment, flow   */
     double colour_kappa;       /* colour = 2, 3: condition number of the sum   */
     int    hel_cfg;            /* helicity = 1: the event's configuration      */
+    double me2_q[2];           /* p p: averaged q qbar |M|^2 (with g_s powers),
+                                  quark from beam 1 / from beam 2             */
+    double lum_q[2];           /* p p: sum over u, d of q(x1) qbar(x2) and of
+                                  qbar(x1) q(x2) number densities            */
     double newton_kappa;       /* condition number of the mass-rescaling root:
                                   sqrt(s_hat) / (xi F'(xi)) = sqrt(s_hat) /
                                   sum_i |k_i|^2 / E_i (1 for massless momenta,
@@ -111,6 +120,8 @@ int mfo_cuts(const mfo_process *proc, int n_f, const double *k, double y_boost,
 
 /* ---- PDF ---------------------------------------------------------------- */
 double mfo_pdf_xf(const mfo_pdf_grid *g, double x, double q2);
+/* x q(x, Q^2) of quark table `flavour` (0 u, 1 ubar, 2 d, 3 dbar). */
+double mfo_pdf_xq(const mfo_pdf_grid *g, int flavour, double x, double q2);
 
 /* ---- colour and matrix element ----------------------------------------- */
 int  mfo_n_orderings(int n_g);
@@ -119,6 +130,9 @@ void mfo_colour_matrix(int n_g, double *C);       /* [n_g!][n_g!]            */
 /* The same matrix from its brute-force first row and the relabelling
  * symmetry C_{sigma tau} = C_{id, sigma^-1 tau} (used for five gluons). */
 void mfo_colour_matrix_relabel(int n_g, double *C);
+/* q(pa) qbar(pb) -> t tbar: |M|^2 summed over helicities and colours, g = 1.
+ * p: [4][4] all outgoing: t, tbar, -pa, -pb. */
+double mfo_me2_qqbar_ttx(const double *p, double m);
 /* Colour-dressed amplitude M_ij from Feynman rules with explicit SU(3)
  * indices for one assignment of gluon adjoint indices cols[n_g] (0 .. 7) and
  * helicity configuration hel: out[2 (3 i + j)] = Re M_ij, [+1] = Im, i the

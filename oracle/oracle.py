@@ -24,12 +24,12 @@ class _Process(C.Structure):
     _fields_ = [("n_g", C.c_int), ("m_top", C.c_double), ("w_top", C.c_double),
                 ("alpha_s", C.c_double), ("mu_f", C.c_double), ("ptmin_g", C.c_double),
                 ("etamax_g", C.c_double), ("drmin_gg", C.c_double), ("colour", C.c_int),
-                ("helicity", C.c_int)]
+                ("helicity", C.c_int), ("initial", C.c_int)]
 
 
 class _Pdf(C.Structure):
     _fields_ = [("n_x", C.c_int), ("n_q2", C.c_int), ("log_x", _dp), ("log_q2", _dp),
-                ("xf", _dp)]
+                ("xf", _dp), ("xq", _dp)]
 
 
 class _Event(C.Structure):
@@ -40,7 +40,7 @@ class _Event(C.Structure):
                 ("k", C.c_double * 20), ("pass_threshold", C.c_int), ("pass_cuts", C.c_int),
                 ("newton_fail", C.c_int), ("near_edge", C.c_int), ("ill_conditioned", C.c_int),
                 ("colour_cfg", C.c_int64), ("colour_kappa", C.c_double), ("hel_cfg", C.c_int),
-                ("newton_kappa", C.c_double)]
+                ("me2_q", C.c_double * 2), ("lum_q", C.c_double * 2), ("newton_kappa", C.c_double)]
 
 
 class _Result(C.Structure):
@@ -90,6 +90,10 @@ def lib():
         L.mfo_cuts.argtypes = [C.POINTER(_Process), C.c_int, _dp, C.c_double, _ip]
         L.mfo_cuts.restype = C.c_int
         L.mfo_pdf_xf.argtypes = [C.POINTER(_Pdf), C.c_double, C.c_double]
+        L.mfo_pdf_xq.argtypes = [C.POINTER(_Pdf), C.c_int, C.c_double, C.c_double]
+        L.mfo_pdf_xq.restype = C.c_double
+        L.mfo_me2_qqbar_ttx.argtypes = [_dp, C.c_double]
+        L.mfo_me2_qqbar_ttx.restype = C.c_double
         L.mfo_pdf_xf.restype = C.c_double
         L.mfo_n_orderings.argtypes = [C.c_int]
         L.mfo_n_orderings.restype = C.c_int
@@ -195,6 +199,7 @@ class Process:
     colour: str = "full"        # "full", "leading" (leading colour), "sampled" (colour Monte Carlo
                                 # over adjoint indices) or "flow" (Monte Carlo over colour flows)
     helicity: str = "sum"       # "sum" or "sampled" (Monte Carlo over helicity configurations)
+    initial: str = "gg"         # "gg" or "pp" (g g plus the q qbar channels from the quark tables)
 
     def c(self):
         modes = {"full": 0, "leading": 1, "sampled": 2, "flow": 3}
@@ -203,9 +208,12 @@ class Process:
         hmodes = {"sum": 0, "sampled": 1}
         if self.helicity not in hmodes:
             raise ValueError(f"helicity must be one of {sorted(hmodes)}, not {self.helicity!r}")
+        imodes = {"gg": 0, "pp": 1}
+        if self.initial not in imodes:
+            raise ValueError(f"initial must be one of {sorted(imodes)}, not {self.initial!r}")
         return _Process(self.n_g, self.m_top, self.w_top, self.alpha_s, self.mu_f,
                         self.ptmin_g, self.etamax_g, self.drmin_gg, modes[self.colour],
-                        hmodes[self.helicity])
+                        hmodes[self.helicity], imodes[self.initial])
 
 
 class _PdfHandle:
@@ -215,8 +223,10 @@ class _PdfHandle:
         self.log_x = _f64(table.log_x)
         self.log_q2 = _f64(table.log_q2)
         self.xf = _f64(table.xf)
+        xq = getattr(table, "xq", None)
+        self.xq = None if xq is None else _f64(xq)
         self.c = _Pdf(len(self.log_x), len(self.log_q2), _d(self.log_x), _d(self.log_q2),
-                      _d(self.xf))
+                      _d(self.xf), _d(self.xq) if self.xq is not None else None)
 
 
 @dataclass
@@ -239,6 +249,8 @@ class EventInfo:
     ill_conditioned: bool
     colour_kappa: float = 0.0
     newton_kappa: float = 0.0
+    me2_q: tuple = (0.0, 0.0)
+    lum_q: tuple = (0.0, 0.0)
 
 
 def _event_info(ev, D):
@@ -246,7 +258,8 @@ def _event_info(ev, D):
                      ev.shat, ev.ps_weight, ev.f1, ev.f2, ev.me2, ev.w,
                      np.array(ev.k[:]).reshape(5, 4)[:(D + 2) // 3], bool(ev.pass_threshold),
                      bool(ev.pass_cuts), bool(ev.newton_fail), bool(ev.near_edge),
-                     bool(ev.ill_conditioned), ev.colour_kappa, ev.newton_kappa)
+                     bool(ev.ill_conditioned), ev.colour_kappa, ev.newton_kappa,
+                     (ev.me2_q[0], ev.me2_q[1]), (ev.lum_q[0], ev.lum_q[1]))
 
 
 def n_dims(n_g: int) -> int:
@@ -319,6 +332,18 @@ def cuts(proc: Process, k, y_boost):
 def pdf_xf(table, x, q2):
     h = _PdfHandle(table)
     return lib().mfo_pdf_xf(C.byref(h.c), x, q2)
+
+
+def pdf_xq(table, flavour, x, q2):
+    """x q(x, Q^2) of quark table `flavour` (0 u, 1 ubar, 2 d, 3 dbar)."""
+    h = _PdfHandle(table)
+    return lib().mfo_pdf_xq(C.byref(h.c), flavour, x, q2)
+
+
+def me2_qqbar_ttx(p, m):
+    """q qbar -> t tbar |M|^2 summed over helicities and colours (g = 1);
+    p: [4][4] all outgoing: t, tbar, -p_q, -p_qbar."""
+    return lib().mfo_me2_qqbar_ttx(_d(_f64(p)), m)
 
 
 def colour_matrix(n_g):

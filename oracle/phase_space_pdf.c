@@ -258,7 +258,7 @@ static double hermite(const double *t, const double *f, int i, int first, int la
     return h00 * f[i] + h10 * h * s0 + h01 * f[i + 1] + h11 * h * s1;
 }
 
-double mfo_pdf_xf(const mfo_pdf_grid *g, double x, double q2)
+static double pdf_table_value(const mfo_pdf_grid *g, const double *table, double x, double q2)
 {
     double lx = log(x), lq = log(q2);
     int kx = find_interval(g->log_x, g->n_x, lx);
@@ -269,8 +269,20 @@ double mfo_pdf_xf(const mfo_pdf_grid *g, double x, double q2)
     int last = mq + 2 > g->n_q2 - 1 ? g->n_q2 - 1 : mq + 2;
     double rowval[64];
     for (int r = first; r <= last; ++r) {
-        const double *row = g->xf + (size_t)r * g->n_x;
+        const double *row = table + (size_t)r * g->n_x;
         rowval[r - first] = hermite(g->log_x, row, kx, 0, g->n_x - 1, lx);
     }
     return hermite(g->log_q2 + first, rowval, mq - first, 0, last - first, lq);
+}
+
+double mfo_pdf_xf(const mfo_pdf_grid *g, double x, double q2)
+{
+    return pdf_table_value(g, g->xf, x, q2);
+}
+
+double mfo_pdf_xq(const mfo_pdf_grid *g, int flavour, double x, double q2)
+{
+    if (!g->xq || flavour < 0 || flavour > 3)
+        return NAN;
+    return pdf_table_value(g, g->xq + (size_t)flavour * g->n_q2 * g->n_x, x, q2);
 }

@@ -22,7 +22,7 @@ MU_F = 173.0              # GeV, factorisation scale, held fixed
 N_BINS = 50               # VEGAS bins per dimension
 ALPHA_DAMP = 1.5          # VEGAS damping exponent
 
-PROCESS_NG = {"gg_ttx": 2, "gg_ttxg": 3, "gg_ttxgg": 4}
+PROCESS_NG = {"gg_ttx": 2, "gg_ttxg": 3, "gg_ttxgg": 4, "gg_ttxggg": 5, "pp_ttx": 2}
 
 
 @dataclass(frozen=True)
@@ -30,17 +30,31 @@ class PdfTable:
     log_x: np.ndarray      # [n_x] ascending ln x
     log_q2: np.ndarray     # [n_q2] ascending ln Q^2
     xf: np.ndarray         # [n_q2, n_x] x g(x, Q^2), C-contiguous float64
+    xq: np.ndarray | None = None   # [4, n_q2, n_x] x q(x, Q^2) for u, ubar, d, dbar, or None
 
 
-def synthetic_pdf(n_x: int = 100, n_q2: int = 50, A: float = 1.0) -> PdfTable:
+def synthetic_pdf(n_x: int = 100, n_q2: int = 50, A: float = 1.0, quarks: bool = False) -> PdfTable:
     """x g(x, Q^2) = A x^-0.2 (1 - x)^5 (1 + 0.1 ln Q^2) on log-spaced knots:
-    x in [1e-7, 1] (100 knots, the last one x = 1), Q^2 in [10, 1e8] GeV^2."""
+    x in [1e-7, 1] (100 knots, the last one x = 1), Q^2 in [10, 1e8] GeV^2.
+
+    With quarks=True also proton-like quark tables for the q qbar channels,
+    valence plus sea, the same Q^2 factor:
+      x ubar = 0.09 x^-0.2 (1 - x)^7,   x u = 1.6 x^0.55 (1 - x)^3.2 + x ubar,
+      x dbar = 0.11 x^-0.2 (1 - x)^7,   x d = 0.85 x^0.55 (1 - x)^4 + x dbar."""
     x = 10.0 ** (-7.0 + 7.0 * np.arange(n_x) / (n_x - 1))
     q2 = 10.0 ** (1.0 + 7.0 * np.arange(n_q2) / (n_q2 - 1))
+    fq = 1.0 + 0.1 * np.log(q2)
     xg = A * x ** -0.2 * (1.0 - x) ** 5
-    table = np.outer(1.0 + 0.1 * np.log(q2), xg)
+    table = np.outer(fq, xg)
+    xq = None
+    if quarks:
+        ubar = 0.09 * x ** -0.2 * (1.0 - x) ** 7
+        dbar = 0.11 * x ** -0.2 * (1.0 - x) ** 7
+        u = 1.6 * x ** 0.55 * (1.0 - x) ** 3.2 + ubar
+        d = 0.85 * x ** 0.55 * (1.0 - x) ** 4 + dbar
+        xq = np.ascontiguousarray(np.stack([np.outer(fq, f) for f in (u, ubar, d, dbar)]), dtype=np.float64)
     return PdfTable(np.ascontiguousarray(np.log(x)), np.ascontiguousarray(np.log(q2)),
-                    np.ascontiguousarray(table, dtype=np.float64))
+                    np.ascontiguousarray(table, dtype=np.float64), xq)
 
 
 @dataclass(frozen=True)
