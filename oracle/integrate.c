@@ -209,8 +209,9 @@ static double weight_from_x(const mfo_process *proc, double sqrt_s,
         ev->lum_q[1] = ub1 * u2 + db1 * d2;
     }
 
-    ev->w = jac * W * (ev->f1 * ev->f2 * ev->me2 + ev->lum_q[0] * ev->me2_q[0] + ev->lum_q[1] * ev->me2_q[1]) /
-            (2.0 * ev->shat) * GEV2_TO_PB;
+    ev->w = jac * W * ev->f1 * ev->f2 * ev->me2 / (2.0 * ev->shat) * GEV2_TO_PB;
+    if (pp)
+        ev->w += jac * W * (ev->lum_q[0] * ev->me2_q[0] + ev->lum_q[1] * ev->me2_q[1]) / (2.0 * ev->shat) * GEV2_TO_PB;
     return ev->w;
 }
 
