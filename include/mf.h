@@ -47,7 +47,12 @@ typedef enum {
  * events per batch: each event's 120 x 128 complex partial amplitudes
  * (240 KB in FP64, 120 KB in FP32) pass through device memory between the
  * amplitude kernel and the matrix-core colour sum. */
-typedef enum { MF_GG_TTX = 0, MF_GG_TTXG = 1, MF_GG_TTXGG = 2, MF_GG_TTXGGG = 3 } mf_process_id;
+/* MF_PP_TTX is p p -> t tbar as in Sec. 3 and Table 1: the g g channel plus
+ * the q qbar channels u ubar, ubar u, d dbar, dbar d (one s-channel gluon
+ * each), weighted by the quark tables of mf_pdf_grid (xq, required); full
+ * colour and helicity sums, FP64 or FP32 amplitudes for the g g channel
+ * (the q qbar channel is FP64), no gradients, not in mf_integrate_static. */
+typedef enum { MF_GG_TTX = 0, MF_GG_TTXG = 1, MF_GG_TTXGG = 2, MF_GG_TTXGGG = 3, MF_PP_TTX = 4 } mf_process_id;
 
 /* Arithmetic of the helicity amplitudes and colour sum.  Everything else
  * (VEGAS, phase space, PDF, accumulation, refinement) is FP64 in both. */
@@ -119,6 +124,8 @@ typedef struct {
     const double *log_x;     /* host [n_x]                                     */
     const double *log_q2;    /* host [n_q2]                                    */
     const double *xf;        /* host [n_q2][n_x], row-major                    */
+    const double *xq;        /* host [4][n_q2][n_x] x q(x, Q^2) for u, ubar, d, dbar
+                                (MF_PP_TTX), NULL for the g g processes       */
 } mf_pdf_grid;
 
 typedef struct {
@@ -248,7 +255,8 @@ mf_status mf_refine_grid(int n_dims, int n_bins, double alpha, const double *his
  * gluons in lexicographic order, generators T = lambda/2. */
 mf_status mf_colour_matrix(int process_id, double *C);
 
-/* Colour- and helicity-summed |M|^2 with g_s = 1 for explicit momenta:
+/* Colour- and helicity-summed |M|^2 with g_s = 1 for explicit momenta
+ * (MF_PP_TTX: its q qbar channel, the quark along +z, FP64):
  *   mom: device [n][4 (t) + 4 (tbar) + 4 (n_g-2) (final gluons)] in the
  *        partonic CM frame with the beams along +z/-z; eb: device [n] beam
  *        energies sqrt(s_hat)/2.  out: device [n]. */

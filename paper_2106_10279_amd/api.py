@@ -23,7 +23,7 @@ from . import _lib
 from ._lib import MF_FP32_KAHAN, MF_FP64, MFError, check, lib  # noqa: F401
 
 PROCESS_IDS = {"gg_ttx": _lib.MF_GG_TTX, "gg_ttxg": _lib.MF_GG_TTXG, "gg_ttxgg": _lib.MF_GG_TTXGG,
-               "gg_ttxggg": _lib.MF_GG_TTXGGG,
+               "gg_ttxggg": _lib.MF_GG_TTXGGG, "pp_ttx": _lib.MF_PP_TTX,
                2: _lib.MF_GG_TTX, 3: _lib.MF_GG_TTXG, 4: _lib.MF_GG_TTXGG, 5: _lib.MF_GG_TTXGGG}
 PRECISIONS = {"fp64": MF_FP64, "fp32_kahan": MF_FP32_KAHAN}
 # colour sum: the full colour matrix, the leading-colour approximation, or a
@@ -69,8 +69,11 @@ class _Pdf:
         self.log_x = np.ascontiguousarray(table.log_x, dtype=np.float64)
         self.log_q2 = np.ascontiguousarray(table.log_q2, dtype=np.float64)
         self.xf = np.ascontiguousarray(table.xf, dtype=np.float64)
+        xq = getattr(table, "xq", None)
+        self.xq = None if xq is None else np.ascontiguousarray(xq, dtype=np.float64)
         self.c = _lib.mf_pdf_grid(len(self.log_x), len(self.log_q2), _ptr(self.log_x),
-                                  _ptr(self.log_q2), _ptr(self.xf))
+                                  _ptr(self.log_q2), _ptr(self.xf),
+                                  _ptr(self.xq) if self.xq is not None else None)
 
 
 def n_dims(process) -> int:
@@ -230,7 +233,7 @@ def refine_grid(hist: torch.Tensor, grid: torch.Tensor, alpha: float = 1.5, stre
 
 def colour_matrix(process) -> np.ndarray:
     pid = PROCESS_IDS[process]
-    n = {0: 2, 1: 6, 2: 24, 3: 120}[pid]
+    n = {0: 2, 1: 6, 2: 24, 3: 120, 4: 2}[pid]
     C_ = np.zeros((n, n))
     check(lib.mf_colour_matrix(pid, _ptr(C_)))
     return C_

@@ -61,6 +61,10 @@ struct EventParams {
     int stride;
     int n_waves;
     int hel_mc;                      // 1: Monte Carlo over helicity configurations
+    // p p initial state (g g -> t tbar plus the q qbar channels)
+    int pp;                          // 1: add the q qbar channels
+    const double* xq;                // [4][n_q2][n_x] x q for u, ubar, d, dbar (device)
+    double me_norm_q;                // g^4 / (4 9) x (hbar c)^2 in pb
 };
 
 // Monte Carlo over helicities: lane `h` of an event holds the colour sum of
@@ -469,7 +473,8 @@ __device__ __forceinline__ double draw_point(const EventParams& P, uint64_t ev, 
 template <int NF>
 __device__ __forceinline__ int event_kinematics(const EventParams& P, uint64_t ev, const double* s_rows,
                                                 const double* s_lx, const double* s_lq, unsigned short* bins,
-                                                size_t bin_stride, double* mom, double& pref)
+                                                size_t bin_stride, double* mom, double& pref,
+                                                const double* s_qrows = nullptr, double* pref_q = nullptr)
 {
     constexpr int D = 2 + 3 * NF - 4;
     pref = 0.0;
@@ -492,6 +497,19 @@ __device__ __forceinline__ int event_kinematics(const EventParams& P, uint64_t e
                 f1 = pdf_xg(P, s_rows, s_lx, s_lq, x1) / x1;
                 f2 = pdf_xg(P, s_rows, s_lx, s_lq, x2) / x2;
                 pref = jac * W * f1 * f2 / (2.0 * shat);
+                if (s_qrows) {
+                    // q qbar luminosities: the quark from beam 1 (u ubar, d dbar)
+                    // and from beam 2 (ubar u, dbar d), number densities
+                    const int rs = P.q2_rows * P.n_x;
+                    double q1[4], q2[4];
+#pragma unroll
+                    for (int f = 0; f < 4; ++f) {
+                        q1[f] = pdf_xg(P, s_qrows + f * rs, s_lx, s_lq, x1) / x1;
+                        q2[f] = pdf_xg(P, s_qrows + f * rs, s_lx, s_lq, x2) / x2;
+                    }
+                    pref_q[0] = jac * W * (q1[0] * q2[1] + q1[2] * q2[3]) / (2.0 * shat);
+                    pref_q[1] = jac * W * (q1[1] * q2[0] + q1[3] * q2[2]) / (2.0 * shat);
+                }
 #pragma unroll
                 for (int i = 0; i < NF; ++i)
 #pragma unroll
@@ -694,14 +712,17 @@ struct StageParams {
     int first_batch;         // acc: 1 = start the per-wave partials from zero
     unsigned long long* next_group;  // amp: work counter, cleared by kin_kernel
     void* amps;              // t tbar g g g: [count][120][128][re, im] partial amplitudes (type T)
+    double* pref_q;          // p p: [2][count] J_V W L_q / (2 s_hat), quark from beam 1 / beam 2
+    double* me_q;            // p p: [2][count] q qbar |M|^2 summed over helicities and colours
 };
 
-template <int NF>
+template <int NF, bool PP = false>
 __global__ void __launch_bounds__(kBlock) kin_kernel(StageParams S)
 {
     const EventParams& P = S.P;
     __shared__ double s_lx[kMaxPdfX];
     __shared__ double s_rows[4 * kMaxPdfX];
+    __shared__ double s_qrows[PP ? 4 * 4 * kMaxPdfX : 1];   // p p: the quark tables' Q^2 rows
     __shared__ double s_lq[4];
     const int tid = threadIdx.x;
     const int lane = tid % kWave;
@@ -714,17 +735,28 @@ __global__ void __launch_bounds__(kBlock) kin_kernel(StageParams S)
         s_rows[i] = P.xf[(size_t)P.q2_first * P.n_x + i];
     if (tid < P.q2_rows)
         s_lq[tid] = P.log_q2[P.q2_first + tid];
+    if constexpr (PP) {
+        const int rs = P.q2_rows * P.n_x;
+        for (int i = tid; i < 4 * rs; i += kBlock) {
+            const int f = i / rs, r = i % rs;
+            s_qrows[i] = P.xq[((size_t)f * P.n_q2 + P.q2_first) * P.n_x + r];
+        }
+    }
     __syncthreads();
     const uint64_t n_chunks = (S.count + kWave - 1) / kWave;
     for (uint64_t chunk = wave_id; chunk < n_chunks; chunk += P.n_waves) {
         const uint64_t e = chunk * kWave + lane;
         if (e >= S.count)
             continue;
-        double pref;
+        double pref, pq[2] = {0.0, 0.0};
         const int flags = event_kinematics<NF>(P, S.first + e, s_rows, s_lx, s_lq, S.bins + e, S.count,
-                                               S.mom + e * (4 * NF + 1), pref);
+                                               S.mom + e * (4 * NF + 1), pref, PP ? s_qrows : nullptr, pq);
         S.pref[e] = pref;
         S.flags[e] = (unsigned char)flags;
+        if constexpr (PP) {
+            S.pref_q[e] = pq[0];
+            S.pref_q[S.count + e] = pq[1];
+        }
     }
 }
 
@@ -850,6 +882,43 @@ __device__ __forceinline__ void amp_quads_ng3(const StageParams& S)
     }
 }
 
+// q qbar -> t tbar for the p p processes (Sec. 3, Table 1): one s-channel
+// gluon, |M_h|^2 = 2 |[vbar(pb) gamma^mu u(pa)] [ubar(k1) gamma_mu v(k2)]|^2 / s^2
+// for helicity configuration h (bit 0: quark, 1: antiquark, 2: top, 3:
+// antitop), summed over colours (the factor 2), g = 1; fwd: the quark along
+// +z (beam 1), rev: along -z.  u = gamma^0 ubar^dagger and
+// vbar = v^dagger gamma^0 in the chiral basis (gamma^0 swaps the halves).
+__device__ __forceinline__ void qqbar_me2_config(const double* __restrict__ mom, double eb, double mt, int h,
+                                                 double& fwd, double& rev)
+{
+    cplx<double> ub[4], v[4], K[4];
+    spinor_ubar<double>(mom, mt, (h >> 2) & 1, ub);
+    spinor_v<double>(mom + 4, mt, (h >> 3) & 1, v);
+    bilinear(ub, v, K);
+    const double pz[4] = {eb, 0.0, 0.0, eb}, mz[4] = {eb, 0.0, 0.0, -eb};
+    const double s = 4.0 * eb * eb;
+    double out[2];
+#pragma unroll
+    for (int o = 0; o < 2; ++o) {
+        cplx<double> a[4], b[4], u[4], vb[4], J[4];
+        spinor_ubar<double>(o ? mz : pz, 0.0, h & 1, a);
+        spinor_v<double>(o ? pz : mz, 0.0, (h >> 1) & 1, b);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            u[i] = cplx<double>(a[(i + 2) & 3].x, -a[(i + 2) & 3].y);
+            vb[i] = cplx<double>(b[(i + 2) & 3].x, -b[(i + 2) & 3].y);
+        }
+        bilinear(vb, u, J);
+        const double mr = J[0].x * K[0].x - J[0].y * K[0].y - J[1].x * K[1].x + J[1].y * K[1].y -
+                          J[2].x * K[2].x + J[2].y * K[2].y - J[3].x * K[3].x + J[3].y * K[3].y;
+        const double mi = J[0].x * K[0].y + J[0].y * K[0].x - J[1].x * K[1].y - J[1].y * K[1].x -
+                          J[2].x * K[2].y - J[2].y * K[2].x - J[3].x * K[3].y - J[3].y * K[3].x;
+        out[o] = 2.0 * (mr * mr + mi * mi) / (s * s);
+    }
+    fwd = out[0];
+    rev = out[1];
+}
+
 template <int NG, typename T, int COL>
 __device__ __forceinline__ void amp_groups(const StageParams& S)
 {
@@ -927,6 +996,21 @@ __device__ __forceinline__ void amp_groups(const StageParams& S)
             v = group_sum(v, L::kHel);
             if (h == 0 && live)
                 S.me[e] = v;
+            if constexpr (NG == 2) {
+                // p p: the q qbar channels of the same event, one helicity
+                // configuration per lane (16 of them, like g g)
+                if (S.P.pp) {
+                    double qf = 0.0, qr = 0.0;
+                    if (live)
+                        qqbar_me2_config(mom, mom[L::kMom - 1], S.P.m_top, h, qf, qr);
+                    qf = group_sum(qf, L::kHel);
+                    qr = group_sum(qr, L::kHel);
+                    if (h == 0 && live) {
+                        S.me_q[e] = qf;
+                        S.me_q[S.count + e] = qr;
+                    }
+                }
+            }
             wave_sync();
         }
         if (last_in_chunk) {
@@ -993,8 +1077,11 @@ __global__ void __launch_bounds__(kBlock) acc_kernel(StageParams S)
         if (active) {
             const double pref = S.pref[e];
             const int flags = S.flags[e];
-            if (pref != 0.0)
+            if (pref != 0.0) {
                 w = pref * (S.me[e] * P.me_norm);
+                if (P.pp)
+                    w += S.pref_q[e] * (S.me_q[e] * P.me_norm_q) + S.pref_q[S.count + e] * (S.me_q[S.count + e] * P.me_norm_q);
+            }
             if (P.weights)
                 P.weights[S.first + e] = w;
             nm_add(sw, w);
@@ -1258,6 +1345,22 @@ __global__ void __launch_bounds__(kBlock) me_prep_kernel_ng5(const double* __res
     S.pref[e] = 1.0;
 }
 
+// mf_matrix_element for the q qbar channel of p p -> t tbar: quark along +z.
+__global__ void __launch_bounds__(kBlock) qqbar_me_kernel(const double* __restrict__ mom, const double* __restrict__ eb,
+                                                          uint64_t n, double mt, double* __restrict__ out)
+{
+    const uint64_t e = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (e >= n)
+        return;
+    double sum = 0.0;
+    for (int h = 0; h < 16; ++h) {
+        double f, r;
+        qqbar_me2_config(mom + 8 * e, eb[e], mt, h, f, r);
+        sum += f;
+    }
+    out[e] = sum;
+}
+
 // mf_evaluate for the staged processes: weight (and the record's |M|^2 entry)
 // of every event of the batch.
 __global__ void __launch_bounds__(kBlock) weight_kernel(StageParams S, int nf)
@@ -1267,7 +1370,10 @@ __global__ void __launch_bounds__(kBlock) weight_kernel(StageParams S, int nf)
         return;
     const double pref = S.pref[e];
     const double me = pref != 0.0 ? S.me[e] : 0.0;
-    S.P.weights[S.first + e] = pref != 0.0 ? pref * (me * S.P.me_norm) : 0.0;
+    double w = pref != 0.0 ? pref * (me * S.P.me_norm) : 0.0;
+    if (S.P.pp && pref != 0.0)
+        w += S.pref_q[e] * (S.me_q[e] * S.P.me_norm_q) + S.pref_q[S.count + e] * (S.me_q[S.count + e] * S.P.me_norm_q);
+    S.P.weights[S.first + e] = w;
     if (S.P.record)
         S.P.record[(S.first + e) * (8 + 4 * (uint64_t)nf) + 6] = me;
 }

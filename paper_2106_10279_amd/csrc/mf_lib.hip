@@ -64,6 +64,7 @@ int n_gluons(int id)
     case MF_GG_TTXG: return 3;
     case MF_GG_TTXGG: return 4;
     case MF_GG_TTXGGG: return 5;
+    case MF_PP_TTX: return 2;
     default: return -1;
     }
 }
@@ -95,6 +96,7 @@ struct Workspace {
     Buffer st_mom, st_pref, st_me, st_bins, st_flags;   // per-event hand-over of the three-kernel form
     Buffer amp_counter;                                  // work counter of amp_kernel (8 bytes)
     Buffer st_amp;                                       // t tbar g g g: partial amplitudes of a batch
+    Buffer xq, st_prefq, st_meq;                         // p p: quark tables; per-event q qbar prefactors, |M|^2
     Buffer uw_counts, uw_flags, uw_totals;               // unweighting: per-workgroup counts, keep flags, totals
     int n_cu = 0;
     void* scratch = nullptr;  // this device's address of the static scratch array (mf_integrate_static)
@@ -135,6 +137,7 @@ struct Mem {
     unsigned char* st_flags = nullptr;
     unsigned long long* amp_counter = nullptr;
     void* st_amp = nullptr;
+    double *xq = nullptr, *st_prefq = nullptr, *st_meq = nullptr;
 };
 
 // Consecutive 256-byte aligned pieces of a fixed device region.
@@ -219,6 +222,19 @@ mf_status validate_pdf(const mf_pdf_grid* pdf, double mu_f)
     return MF_OK;
 }
 
+// p p processes: the quark tables must be there and finite.
+mf_status validate_quarks(const mf_process* proc, const mf_pdf_grid* pdf)
+{
+    if (proc->id != MF_PP_TTX)
+        return MF_OK;
+    if (!pdf->xq)
+        return fail(MF_EINVAL, "p p processes need the quark tables (pdf->xq)");
+    for (long i = 0; i < 4L * pdf->n_x * pdf->n_q2; ++i)
+        if (!std::isfinite(pdf->xq[i]))
+            return fail(MF_EINVAL, "quark PDF values must be finite");
+    return MF_OK;
+}
+
 mf_status validate_options(const mf_options* opt, int D)
 {
     if (!opt)
@@ -271,6 +287,10 @@ mf_status workspace_pdf(const mf_pdf_grid* pdf, Workspace& ws, Mem& m)
     m.log_x = (double*)ws.log_x.ptr;
     m.log_q2 = (double*)ws.log_q2.ptr;
     m.xf = (double*)ws.xf.ptr;
+    if (pdf->xq) {
+        if ((st = ensure(ws.xq, sizeof(double) * 4 * nx * (size_t)nq)) != MF_OK) return st;
+        m.xq = (double*)ws.xq.ptr;
+    }
     return MF_OK;
 }
 
@@ -283,6 +303,12 @@ mf_status prepare(const mf_process* proc, double sqrt_s, const mf_pdf_grid* pdf,
     MF_HIP(hipMemcpyAsync(m.log_x, pdf->log_x, sizeof(double) * nx, hipMemcpyHostToDevice, S.stream));
     MF_HIP(hipMemcpyAsync(m.log_q2, pdf->log_q2, sizeof(double) * nq, hipMemcpyHostToDevice, S.stream));
     MF_HIP(hipMemcpyAsync(m.xf, pdf->xf, sizeof(double) * nx * (size_t)nq, hipMemcpyHostToDevice, S.stream));
+    const bool pp = proc->id == MF_PP_TTX;
+    if (pp) {
+        if (!m.xq)
+            return fail(MF_EUNSUPPORTED, "no device room for the quark tables");
+        MF_HIP(hipMemcpyAsync(m.xq, pdf->xq, sizeof(double) * 4 * nx * (size_t)nq, hipMemcpyHostToDevice, S.stream));
+    }
 
     mf::EventParams& P = S.P;
     std::memset(&P, 0, sizeof(P));
@@ -315,6 +341,9 @@ mf_status prepare(const mf_process* proc, double sqrt_s, const mf_pdf_grid* pdf,
     P.ps_const = std::pow(2.0 * mf::kPi, 4 - 3 * n) * std::pow(mf::kPi / 2.0, n - 1) /
                  (factorial(n - 1) * factorial(n - 2));
     P.hel_mc = opt->helicity == MF_HELICITY_SAMPLED;
+    P.pp = pp ? 1 : 0;
+    P.xq = pp ? m.xq : nullptr;
+    P.me_norm_q = gs2 * gs2 / 36.0 * mf::kGeV2ToPb;
     return MF_OK;
 }
 
@@ -365,7 +394,7 @@ mf_status amp_grid_for(uint64_t n_groups, int n_cu, int* grid)
 
 template <int NG, typename T, int COL>
 mf_status launch_stages(const mf::StageParams& S, int kin_blocks, int n_cu, hipStream_t stream,
-                        hipEvent_t amp_begin, hipEvent_t amp_end)
+                        hipEvent_t amp_begin, hipEvent_t amp_end, bool accumulate = true)
 {
     constexpr int D = 2 + 3 * NG - 4;
     int amp_grid = 1;
@@ -373,7 +402,14 @@ mf_status launch_stages(const mf::StageParams& S, int kin_blocks, int n_cu, hipS
                                        n_cu, &amp_grid);
     if (st != MF_OK)
         return st;
-    hipLaunchKernelGGL((mf::kin_kernel<NG>), dim3(kin_blocks), dim3(mf::kBlock), 0, stream, S);
+    if constexpr (NG == 2) {
+        if (S.P.pp)
+            hipLaunchKernelGGL((mf::kin_kernel<NG, true>), dim3(kin_blocks), dim3(mf::kBlock), 0, stream, S);
+        else
+            hipLaunchKernelGGL((mf::kin_kernel<NG>), dim3(kin_blocks), dim3(mf::kBlock), 0, stream, S);
+    } else {
+        hipLaunchKernelGGL((mf::kin_kernel<NG>), dim3(kin_blocks), dim3(mf::kBlock), 0, stream, S);
+    }
     MF_HIP(hipGetLastError());
     if (amp_begin)
         MF_HIP(hipEventRecord(amp_begin, stream));
@@ -381,8 +417,13 @@ mf_status launch_stages(const mf::StageParams& S, int kin_blocks, int n_cu, hipS
     MF_HIP(hipGetLastError());
     if (amp_end)
         MF_HIP(hipEventRecord(amp_end, stream));
-    const size_t dyn = sizeof(double) * mf::kWavesPerBlock * D * S.P.n_bins;
-    hipLaunchKernelGGL((mf::acc_kernel<NG>), dim3(kin_blocks), dim3(mf::kBlock), dyn, stream, S);
+    if (accumulate) {
+        const size_t dyn = sizeof(double) * mf::kWavesPerBlock * D * S.P.n_bins;
+        hipLaunchKernelGGL((mf::acc_kernel<NG>), dim3(kin_blocks), dim3(mf::kBlock), dyn, stream, S);
+    } else {
+        const unsigned wb = (unsigned)((S.count + mf::kBlock - 1) / mf::kBlock);
+        hipLaunchKernelGGL(mf::weight_kernel, dim3(wb), dim3(mf::kBlock), 0, stream, S, NG);
+    }
     MF_HIP(hipGetLastError());
     return MF_OK;
 }
@@ -592,6 +633,7 @@ mf_status integrate_impl(const mf_process* proc, double sqrt_s, const mf_pdf_gri
     mf_status st;
     if ((st = validate_process(proc, sqrt_s, &ng)) != MF_OK) return st;
     if ((st = validate_pdf(pdf, proc->mu_f)) != MF_OK) return st;
+    if ((st = validate_quarks(proc, pdf)) != MF_OK) return st;
     const int D = 2 + 3 * ng - 4;
     if ((st = validate_options(opt, D)) != MF_OK) return st;
     if (!res)
@@ -611,6 +653,15 @@ mf_status integrate_impl(const mf_process* proc, double sqrt_s, const mf_pdf_gri
             return fail(MF_EUNSUPPORTED, "g g -> t tbar g g g runs with the full helicity sum only");
         if (fixed_scratch)
             return fail(MF_EUNSUPPORTED, "mf_integrate_static does not run g g -> t tbar g g g");
+    }
+    const bool pp = proc->id == MF_PP_TTX;
+    if (pp) {
+        if (opt->colour != MF_COLOUR_FULL || opt->helicity != MF_HELICITY_SUM)
+            return fail(MF_EUNSUPPORTED, "p p -> t tbar runs with the full colour and helicity sums only");
+        if (fixed_scratch)
+            return fail(MF_EUNSUPPORTED, "mf_integrate_static does not run p p processes");
+        if (grad)
+            return fail(MF_EUNSUPPORTED, "gradients are implemented for g g -> t tbar only");
     }
     if (grad) {
         if (ng != 2)
@@ -715,6 +766,10 @@ mf_status integrate_impl(const mf_process* proc, double sqrt_s, const mf_pdf_gri
             if ((st = ensure(ws.st_flags, b0)) != MF_OK) return st;
             if ((st = ensure(ws.amp_counter, sizeof(unsigned long long))) != MF_OK) return st;
             if (amp_bytes && (st = ensure(ws.st_amp, amp_bytes * b0)) != MF_OK) return st;
+            if (pp) {
+                if ((st = ensure(ws.st_prefq, sizeof(double) * 2 * b0)) != MF_OK) return st;
+                if ((st = ensure(ws.st_meq, sizeof(double) * 2 * b0)) != MF_OK) return st;
+            }
         }
         if (grad) {
             if ((st = ensure(ws.gpartials, sizeof(double) * 4 * (size_t)n_waves)) != MF_OK) return st;
@@ -737,6 +792,8 @@ mf_status integrate_impl(const mf_process* proc, double sqrt_s, const mf_pdf_gri
         m.st_flags = (unsigned char*)ws.st_flags.ptr;
         m.amp_counter = (unsigned long long*)ws.amp_counter.ptr;
         m.st_amp = amp_bytes ? ws.st_amp.ptr : nullptr;
+        m.st_prefq = pp ? (double*)ws.st_prefq.ptr : nullptr;
+        m.st_meq = pp ? (double*)ws.st_meq.ptr : nullptr;
     }
     const uint64_t batch = n_events < cap ? n_events : cap;
     const uint64_t n_batches = (n_events + batch - 1) / batch;
@@ -821,6 +878,8 @@ mf_status integrate_impl(const mf_process* proc, double sqrt_s, const mf_pdf_gri
                 SP.first_batch = bi == 0;
                 SP.next_group = m.amp_counter;
                 SP.amps = m.st_amp;
+                SP.pref_q = m.st_prefq;
+                SP.me_q = m.st_meq;
                 hipEvent_t a = nullptr, b = nullptr, c = nullptr, d = nullptr;
                 if (opt->profile) {
                     const size_t at = kMarks * ((size_t)j * n_batches + bi);
@@ -1007,6 +1066,7 @@ mf_status fixed_grid_setup(const mf_process* proc, double sqrt_s, const mf_pdf_g
     mf_status st;
     if ((st = validate_process(proc, sqrt_s, &ng)) != MF_OK) return st;
     if ((st = validate_pdf(pdf, proc->mu_f)) != MF_OK) return st;
+    if ((st = validate_quarks(proc, pdf)) != MF_OK) return st;
     const int D = 2 + 3 * ng - 4;
     if ((st = validate_options(opt, D)) != MF_OK) return st;
     if (n < 1 || n > (1ull << 40))
@@ -1081,28 +1141,58 @@ mf_status stage_buffers_ng5(Workspace& ws, uint64_t b0, mf_precision prec, mf::S
     return MF_OK;
 }
 
-// mf_evaluate for t tbar g g g: the staged kernels in batches, weights
-// (and records) written by weight_kernel.
-mf_status evaluate_ng5(Setup& S, const mf_options* opt, uint64_t n)
+// mf_evaluate for the processes that only the staged kernels run (t tbar g g g,
+// p p -> t tbar): batches of phase space, amplitudes and weight_kernel,
+// which writes the weights (and the records' |M|^2).
+mf_status evaluate_staged(Setup& S, const mf_options* opt, uint64_t n)
 {
     if (opt->colour != MF_COLOUR_FULL)
-        return fail(MF_EUNSUPPORTED, "g g -> t tbar g g g runs with the full colour sum only");
+        return fail(MF_EUNSUPPORTED, "this process runs with the full colour sum only");
     if (opt->helicity != MF_HELICITY_SUM)
-        return fail(MF_EUNSUPPORTED, "g g -> t tbar g g g runs with the full helicity sum only");
-    const uint64_t cap = opt->max_batch && opt->max_batch < kStageBatchNg5 ? opt->max_batch : kStageBatchNg5;
+        return fail(MF_EUNSUPPORTED, "this process runs with the full helicity sum only");
+    const uint64_t big = S.ng == 5 ? kStageBatchNg5 : kStageBatch;
+    const uint64_t cap = opt->max_batch && opt->max_batch < big ? opt->max_batch : big;
     const uint64_t batch = n < cap ? n : cap;
     mf::StageParams SP;
     SP.P = S.P;
     mf_status st;
-    if ((st = stage_buffers_ng5(*S.ws, batch, opt->precision, SP)) != MF_OK) return st;
+    if (S.ng == 5) {
+        if ((st = stage_buffers_ng5(*S.ws, batch, opt->precision, SP)) != MF_OK) return st;
+    } else {
+        Workspace& ws = *S.ws;
+        constexpr int K = mf::Layout<2>::kMom;
+        if ((st = ensure(ws.st_mom, sizeof(double) * K * batch)) != MF_OK) return st;
+        if ((st = ensure(ws.st_pref, sizeof(double) * batch)) != MF_OK) return st;
+        if ((st = ensure(ws.st_me, sizeof(double) * batch)) != MF_OK) return st;
+        if ((st = ensure(ws.st_bins, sizeof(unsigned short) * 4 * batch)) != MF_OK) return st;
+        if ((st = ensure(ws.st_flags, batch)) != MF_OK) return st;
+        if ((st = ensure(ws.amp_counter, sizeof(unsigned long long))) != MF_OK) return st;
+        if ((st = ensure(ws.st_prefq, sizeof(double) * 2 * batch)) != MF_OK) return st;
+        if ((st = ensure(ws.st_meq, sizeof(double) * 2 * batch)) != MF_OK) return st;
+        SP.mom = (double*)ws.st_mom.ptr;
+        SP.pref = (double*)ws.st_pref.ptr;
+        SP.me = (double*)ws.st_me.ptr;
+        SP.bins = (unsigned short*)ws.st_bins.ptr;
+        SP.flags = (unsigned char*)ws.st_flags.ptr;
+        SP.next_group = (unsigned long long*)ws.amp_counter.ptr;
+        SP.amps = nullptr;
+        SP.pref_q = (double*)ws.st_prefq.ptr;
+        SP.me_q = (double*)ws.st_meq.ptr;
+        SP.first_batch = 1;
+    }
     for (uint64_t first = 0; first < n; first += batch) {
         SP.first = first;
         SP.count = n - first < batch ? n - first : batch;
         SP.P.n_waves = waves_for((SP.count + mf::kWave - 1) / mf::kWave, S.ws->n_cu);
         const int kin_blocks = SP.P.n_waves / mf::kWavesPerBlock;
-        st = opt->precision == MF_FP32_KAHAN
-                 ? launch_stages_ng5<float>(SP, kin_blocks, S.ws->n_cu, S.stream, nullptr, nullptr, false)
-                 : launch_stages_ng5<double>(SP, kin_blocks, S.ws->n_cu, S.stream, nullptr, nullptr, false);
+        if (S.ng == 5)
+            st = opt->precision == MF_FP32_KAHAN
+                     ? launch_stages_ng5<float>(SP, kin_blocks, S.ws->n_cu, S.stream, nullptr, nullptr, false)
+                     : launch_stages_ng5<double>(SP, kin_blocks, S.ws->n_cu, S.stream, nullptr, nullptr, false);
+        else
+            st = opt->precision == MF_FP32_KAHAN
+                     ? launch_stages<2, float, 0>(SP, kin_blocks, S.ws->n_cu, S.stream, nullptr, nullptr, false)
+                     : launch_stages<2, double, 0>(SP, kin_blocks, S.ws->n_cu, S.stream, nullptr, nullptr, false);
         if (st != MF_OK)
             return st;
     }
@@ -1134,8 +1224,8 @@ mf_status mf_evaluate(const mf_process* proc, double sqrt_s, const mf_pdf_grid* 
     P.k53_out = k53_out;
     P.bins_out = bins_out;
     P.record = record_out;
-    if (S.ng == 5) {
-        if ((st = evaluate_ng5(S, opt, n)) != MF_OK)
+    if (S.ng == 5 || proc->id == MF_PP_TTX) {
+        if ((st = evaluate_staged(S, opt, n)) != MF_OK)
             return st;
         MF_HIP(hipStreamSynchronize(S.stream));
         return MF_OK;
@@ -1464,6 +1554,16 @@ mf_status mf_matrix_element(int process_id, mf_precision precision, const double
     hipStream_t s = (hipStream_t)stream;
     if (ng == 5)
         return matrix_element_ng5(precision, mom, eb, n, m_top, w_top, out, s);
+    if (process_id == MF_PP_TTX) {
+        // the q qbar channel (quark along +z), FP64
+        const uint64_t qb = (n + mf::kBlock - 1) / mf::kBlock;
+        if (qb > 0x7FFFFFFFull)
+            return fail(MF_EINVAL, "too many events for one launch");
+        hipLaunchKernelGGL(mf::qqbar_me_kernel, dim3((unsigned)qb), dim3(mf::kBlock), 0, s, mom, eb, n, m_top, out);
+        MF_HIP(hipGetLastError());
+        MF_HIP(hipStreamSynchronize(s));
+        return MF_OK;
+    }
     const int epp = mf::kWave >> (ng + 2);              // events per wave
     const uint64_t per_block = (uint64_t)epp * mf::kWavesPerBlock;
     const uint64_t blocks = (n + per_block - 1) / per_block;
