@@ -334,6 +334,24 @@ __device__ __forceinline__ double pdf_xg(const EventParams& P, const double* row
     return hermite(lq_knots, rv, P.q2_interval - P.q2_first, P.q2_rows - 1, P.log_muf2);
 }
 
+// The four quark tables (u, ubar, d, dbar; rows of table f at f * q2_rows * n_x)
+// at one x: one logarithm and one interval search for all of them, each
+// value as pdf_xg computes it, divided by x.
+__device__ __forceinline__ void pdf_xq4(const EventParams& P, const double* rows, const double* lx_knots,
+                                        const double* lq_knots, double x, double* q)
+{
+    const double lx = log(x);
+    const int k = find_interval(lx_knots, P.n_x, lx);
+    const int rs = P.q2_rows * P.n_x;
+#pragma unroll 1
+    for (int f = 0; f < 4; ++f) {
+        double rv[4];
+        for (int r = 0; r < P.q2_rows; ++r)
+            rv[r] = hermite(lx_knots, rows + f * rs + r * P.n_x, k, P.n_x - 1, lx);
+        q[f] = hermite(lq_knots, rv, P.q2_interval - P.q2_first, P.q2_rows - 1, P.log_muf2) / x;
+    }
+}
+
 // Reduce v over groups of `width` consecutive lanes; lane 0 of each group
 // receives the sum in a fixed association order.
 __device__ __forceinline__ double group_sum(double v, int width)
@@ -498,17 +516,15 @@ __device__ __forceinline__ int event_kinematics(const EventParams& P, uint64_t e
                 f2 = pdf_xg(P, s_rows, s_lx, s_lq, x2) / x2;
                 pref = jac * W * f1 * f2 / (2.0 * shat);
                 if (s_qrows) {
-                    // q qbar luminosities: the quark from beam 1 (u ubar, d dbar)
-                    // and from beam 2 (ubar u, dbar d), number densities
-                    const int rs = P.q2_rows * P.n_x;
+                    // q qbar luminosity, number densities: the quark from beam 1
+                    // (u ubar, d dbar) plus the quark from beam 2 (ubar u, dbar d);
+                    // the summed q qbar |M|^2 is the same for both orientations
+                    // (symmetric under t <-> u at tree level)
                     double q1[4], q2[4];
-#pragma unroll
-                    for (int f = 0; f < 4; ++f) {
-                        q1[f] = pdf_xg(P, s_qrows + f * rs, s_lx, s_lq, x1) / x1;
-                        q2[f] = pdf_xg(P, s_qrows + f * rs, s_lx, s_lq, x2) / x2;
-                    }
-                    pref_q[0] = jac * W * (q1[0] * q2[1] + q1[2] * q2[3]) / (2.0 * shat);
-                    pref_q[1] = jac * W * (q1[1] * q2[0] + q1[3] * q2[2]) / (2.0 * shat);
+                    pdf_xq4(P, s_qrows, s_lx, s_lq, x1, q1);
+                    pdf_xq4(P, s_qrows, s_lx, s_lq, x2, q2);
+                    const double lq = (q1[0] * q2[1] + q1[2] * q2[3]) + (q1[1] * q2[0] + q1[3] * q2[2]);
+                    *pref_q = jac * W * lq / (2.0 * shat);
                 }
 #pragma unroll
                 for (int i = 0; i < NF; ++i)
@@ -712,8 +728,8 @@ struct StageParams {
     int first_batch;         // acc: 1 = start the per-wave partials from zero
     unsigned long long* next_group;  // amp: work counter, cleared by kin_kernel
     void* amps;              // t tbar g g g: [count][120][128][re, im] partial amplitudes (type T)
-    double* pref_q;          // p p: [2][count] J_V W L_q / (2 s_hat), quark from beam 1 / beam 2
-    double* me_q;            // p p: [2][count] q qbar |M|^2 summed over helicities and colours
+    double* pref_q;          // p p: [count] J_V W L_qqbar / (2 s_hat), both beam orientations
+    double* me_q;            // p p: [count] q qbar |M|^2 summed over helicities and colours
 };
 
 template <int NF, bool PP = false>
@@ -748,15 +764,13 @@ __global__ void __launch_bounds__(kBlock) kin_kernel(StageParams S)
         const uint64_t e = chunk * kWave + lane;
         if (e >= S.count)
             continue;
-        double pref, pq[2] = {0.0, 0.0};
+        double pref, pq = 0.0;
         const int flags = event_kinematics<NF>(P, S.first + e, s_rows, s_lx, s_lq, S.bins + e, S.count,
-                                               S.mom + e * (4 * NF + 1), pref, PP ? s_qrows : nullptr, pq);
+                                               S.mom + e * (4 * NF + 1), pref, PP ? s_qrows : nullptr, &pq);
         S.pref[e] = pref;
         S.flags[e] = (unsigned char)flags;
-        if constexpr (PP) {
-            S.pref_q[e] = pq[0];
-            S.pref_q[S.count + e] = pq[1];
-        }
+        if constexpr (PP)
+            S.pref_q[e] = pq;
     }
 }
 
@@ -883,43 +897,30 @@ __device__ __forceinline__ void amp_quads_ng3(const StageParams& S)
 }
 
 // q qbar -> t tbar for the p p processes (Sec. 3, Table 1): one s-channel
-// gluon, |M_h|^2 = 2 |[vbar(pb) gamma^mu u(pa)] [ubar(k1) gamma_mu v(k2)]|^2 / s^2
-// for helicity configuration h (bit 0: quark, 1: antiquark, 2: top, 3:
-// antitop), summed over colours (the factor 2), g = 1; fwd: the quark along
-// +z (beam 1), rev: along -z.  u = gamma^0 ubar^dagger and
-// vbar = v^dagger gamma^0 in the chiral basis (gamma^0 swaps the halves).
-__device__ __forceinline__ void qqbar_me2_config(const double* __restrict__ mom, double eb, double mt, int h,
-                                                 double& fwd, double& rev)
+// gluon, |M_h|^2 = 2 |J . K|^2 / s^2 for helicity configuration h, summed over
+// colours (the factor 2), g = 1, with K^mu = ubar(k1) gamma^mu v(k2) the top
+// current and J^mu = vbar(pb) gamma^mu u(pa) the beam current.  Massless beams
+// along +-z in the partonic frame conserve helicity: J vanishes for two of
+// the four beam configurations and is sqrt(s) (0, 1, +-i, 0) up to a phase for
+// the other two, for either orientation of the beams (so the summed |M|^2 is
+// the same for the quark along +z and along -z).  h: bits 0-1 beam
+// configuration (bit 1 set: the vanishing ones), bit 2 top and bit 3 antitop
+// spin.
+__device__ __forceinline__ double qqbar_me2_config(const double* __restrict__ mom, double eb, double mt, int h)
 {
+    if (h & 2)
+        return 0.0;
     cplx<double> ub[4], v[4], K[4];
     spinor_ubar<double>(mom, mt, (h >> 2) & 1, ub);
     spinor_v<double>(mom + 4, mt, (h >> 3) & 1, v);
     bilinear(ub, v, K);
-    const double pz[4] = {eb, 0.0, 0.0, eb}, mz[4] = {eb, 0.0, 0.0, -eb};
-    const double s = 4.0 * eb * eb;
-    double out[2];
-#pragma unroll
-    for (int o = 0; o < 2; ++o) {
-        cplx<double> a[4], b[4], u[4], vb[4], J[4];
-        spinor_ubar<double>(o ? mz : pz, 0.0, h & 1, a);
-        spinor_v<double>(o ? pz : mz, 0.0, (h >> 1) & 1, b);
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            u[i] = cplx<double>(a[(i + 2) & 3].x, -a[(i + 2) & 3].y);
-            vb[i] = cplx<double>(b[(i + 2) & 3].x, -b[(i + 2) & 3].y);
-        }
-        bilinear(vb, u, J);
-        const double mr = J[0].x * K[0].x - J[0].y * K[0].y - J[1].x * K[1].x + J[1].y * K[1].y -
-                          J[2].x * K[2].x + J[2].y * K[2].y - J[3].x * K[3].x + J[3].y * K[3].y;
-        const double mi = J[0].x * K[0].y + J[0].y * K[0].x - J[1].x * K[1].y - J[1].y * K[1].x -
-                          J[2].x * K[2].y - J[2].y * K[2].x - J[3].x * K[3].y - J[3].y * K[3].x;
-        out[o] = 2.0 * (mr * mr + mi * mi) / (s * s);
-    }
-    fwd = out[0];
-    rev = out[1];
+    // J . K = -sqrt(s) (K^1 +- i K^2) up to a phase
+    const double sg = (h & 1) ? -1.0 : 1.0;
+    const double re = K[1].x - sg * K[2].y, im = K[1].y + sg * K[2].x;
+    return 2.0 * (re * re + im * im) / (4.0 * eb * eb);
 }
 
-template <int NG, typename T, int COL>
+template <int NG, typename T, int COL, bool PP = false>
 __device__ __forceinline__ void amp_groups(const StageParams& S)
 {
     using L = Layout<NG>;
@@ -996,20 +997,13 @@ __device__ __forceinline__ void amp_groups(const StageParams& S)
             v = group_sum(v, L::kHel);
             if (h == 0 && live)
                 S.me[e] = v;
-            if constexpr (NG == 2) {
-                // p p: the q qbar channels of the same event, one helicity
+            if constexpr (PP) {
+                // p p: the q qbar channel of the same event, one helicity
                 // configuration per lane (16 of them, like g g)
-                if (S.P.pp) {
-                    double qf = 0.0, qr = 0.0;
-                    if (live)
-                        qqbar_me2_config(mom, mom[L::kMom - 1], S.P.m_top, h, qf, qr);
-                    qf = group_sum(qf, L::kHel);
-                    qr = group_sum(qr, L::kHel);
-                    if (h == 0 && live) {
-                        S.me_q[e] = qf;
-                        S.me_q[S.count + e] = qr;
-                    }
-                }
+                double q = live ? qqbar_me2_config(mom, mom[L::kMom - 1], S.P.m_top, h) : 0.0;
+                q = group_sum(q, L::kHel);
+                if (h == 0 && live)
+                    S.me_q[e] = q;
             }
             wave_sync();
         }
@@ -1024,13 +1018,15 @@ __device__ __forceinline__ void amp_groups(const StageParams& S)
 }
 
 // The amplitude kernel: quads of events for t tbar g, single events for t tbar g g.
-template <int NG, typename T, int COL = 0>
+// PP (n_g = 2 only): p p, the q qbar channel evaluated alongside g g.
+template <int NG, typename T, int COL = 0, bool PP = false>
 __global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 || NG <= 3 ? 4 : 2))) amp_kernel(StageParams S)
 {
+    static_assert(!PP || NG == 2, "the q qbar channel runs with n_g = 2");
     if constexpr (NG == 3)
         amp_quads_ng3<T, COL>(S);
     else
-        amp_groups<NG, T, COL>(S);
+        amp_groups<NG, T, COL, PP>(S);
 }
 
 // Phase 3 over a batch: weights, compensated sums, w_max, counts and the
@@ -1080,7 +1076,7 @@ __global__ void __launch_bounds__(kBlock) acc_kernel(StageParams S)
             if (pref != 0.0) {
                 w = pref * (S.me[e] * P.me_norm);
                 if (P.pp)
-                    w += S.pref_q[e] * (S.me_q[e] * P.me_norm_q) + S.pref_q[S.count + e] * (S.me_q[S.count + e] * P.me_norm_q);
+                    w += S.pref_q[e] * (S.me_q[e] * P.me_norm_q);
             }
             if (P.weights)
                 P.weights[S.first + e] = w;
@@ -1353,11 +1349,8 @@ __global__ void __launch_bounds__(kBlock) qqbar_me_kernel(const double* __restri
     if (e >= n)
         return;
     double sum = 0.0;
-    for (int h = 0; h < 16; ++h) {
-        double f, r;
-        qqbar_me2_config(mom + 8 * e, eb[e], mt, h, f, r);
-        sum += f;
-    }
+    for (int h = 0; h < 16; ++h)
+        sum += qqbar_me2_config(mom + 8 * e, eb[e], mt, h);
     out[e] = sum;
 }
 
@@ -1372,7 +1365,7 @@ __global__ void __launch_bounds__(kBlock) weight_kernel(StageParams S, int nf)
     const double me = pref != 0.0 ? S.me[e] : 0.0;
     double w = pref != 0.0 ? pref * (me * S.P.me_norm) : 0.0;
     if (S.P.pp && pref != 0.0)
-        w += S.pref_q[e] * (S.me_q[e] * S.P.me_norm_q) + S.pref_q[S.count + e] * (S.me_q[S.count + e] * S.P.me_norm_q);
+        w += S.pref_q[e] * (S.me_q[e] * S.P.me_norm_q);
     S.P.weights[S.first + e] = w;
     if (S.P.record)
         S.P.record[(S.first + e) * (8 + 4 * (uint64_t)nf) + 6] = me;

@@ -380,11 +380,11 @@ mf_status dispatch_event(int ng, mf_precision prec, mf_colour col, const mf::Eve
 // Amplitude-kernel workgroups (one wave each) for the persistent loop: as
 // many as can be resident at once, so that every workgroup runs from start to
 // end alongside all the others (the groups of events are assigned statically).
-template <int NG, typename T, int COL>
+template <int NG, typename T, int COL, bool PP = false>
 mf_status amp_grid_for(uint64_t n_groups, int n_cu, int* grid)
 {
     int per_cu = 0;
-    MF_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, mf::amp_kernel<NG, T, COL>, mf::kWave, 0));
+    MF_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, mf::amp_kernel<NG, T, COL, PP>, mf::kWave, 0));
     if (per_cu < 1)
         per_cu = 1;
     const uint64_t cap = (uint64_t)n_cu * per_cu;
@@ -397,9 +397,12 @@ mf_status launch_stages(const mf::StageParams& S, int kin_blocks, int n_cu, hipS
                         hipEvent_t amp_begin, hipEvent_t amp_end, bool accumulate = true)
 {
     constexpr int D = 2 + 3 * NG - 4;
+    constexpr bool kCanPP = NG == 2 && COL == 0;
+    const bool pp = kCanPP && S.P.pp;
+    const uint64_t n_groups = (S.count + mf::Layout<NG>::kEventsPerPass - 1) / mf::Layout<NG>::kEventsPerPass;
     int amp_grid = 1;
-    mf_status st = amp_grid_for<NG, T, COL>((S.count + mf::Layout<NG>::kEventsPerPass - 1) / mf::Layout<NG>::kEventsPerPass,
-                                       n_cu, &amp_grid);
+    mf_status st = pp ? amp_grid_for<NG, T, COL, kCanPP>(n_groups, n_cu, &amp_grid)
+                      : amp_grid_for<NG, T, COL>(n_groups, n_cu, &amp_grid);
     if (st != MF_OK)
         return st;
     if constexpr (NG == 2) {
@@ -413,7 +416,10 @@ mf_status launch_stages(const mf::StageParams& S, int kin_blocks, int n_cu, hipS
     MF_HIP(hipGetLastError());
     if (amp_begin)
         MF_HIP(hipEventRecord(amp_begin, stream));
-    hipLaunchKernelGGL((mf::amp_kernel<NG, T, COL>), dim3(amp_grid), dim3(mf::kWave), 0, stream, S);
+    if (pp)
+        hipLaunchKernelGGL((mf::amp_kernel<NG, T, COL, kCanPP>), dim3(amp_grid), dim3(mf::kWave), 0, stream, S);
+    else
+        hipLaunchKernelGGL((mf::amp_kernel<NG, T, COL>), dim3(amp_grid), dim3(mf::kWave), 0, stream, S);
     MF_HIP(hipGetLastError());
     if (amp_end)
         MF_HIP(hipEventRecord(amp_end, stream));
@@ -767,8 +773,8 @@ mf_status integrate_impl(const mf_process* proc, double sqrt_s, const mf_pdf_gri
             if ((st = ensure(ws.amp_counter, sizeof(unsigned long long))) != MF_OK) return st;
             if (amp_bytes && (st = ensure(ws.st_amp, amp_bytes * b0)) != MF_OK) return st;
             if (pp) {
-                if ((st = ensure(ws.st_prefq, sizeof(double) * 2 * b0)) != MF_OK) return st;
-                if ((st = ensure(ws.st_meq, sizeof(double) * 2 * b0)) != MF_OK) return st;
+                if ((st = ensure(ws.st_prefq, sizeof(double) * b0)) != MF_OK) return st;
+                if ((st = ensure(ws.st_meq, sizeof(double) * b0)) != MF_OK) return st;
             }
         }
         if (grad) {
@@ -1167,8 +1173,8 @@ mf_status evaluate_staged(Setup& S, const mf_options* opt, uint64_t n)
         if ((st = ensure(ws.st_bins, sizeof(unsigned short) * 4 * batch)) != MF_OK) return st;
         if ((st = ensure(ws.st_flags, batch)) != MF_OK) return st;
         if ((st = ensure(ws.amp_counter, sizeof(unsigned long long))) != MF_OK) return st;
-        if ((st = ensure(ws.st_prefq, sizeof(double) * 2 * batch)) != MF_OK) return st;
-        if ((st = ensure(ws.st_meq, sizeof(double) * 2 * batch)) != MF_OK) return st;
+        if ((st = ensure(ws.st_prefq, sizeof(double) * batch)) != MF_OK) return st;
+        if ((st = ensure(ws.st_meq, sizeof(double) * batch)) != MF_OK) return st;
         SP.mom = (double*)ws.st_mom.ptr;
         SP.pref = (double*)ws.st_pref.ptr;
         SP.me = (double*)ws.st_me.ptr;
