@@ -13,4 +13,5 @@ from .oracle import (  # noqa: F401
     colour_count, colour_config, colour_factors, me2_sum_colour_config,
     flow_count, flow_code, flow_weight, flow_total, flow_config, flow_factors, me2_sum_colour_flow, me2_sum_sampled,
     hel_count, hel_config, me2_hel, colour_matrix_relabel, dressed_amplitude, pdf_xq, me2_qqbar_ttx,
+    qqbar_ttxg_diagrams, qqbar_ttxg_colour, me2_qqbar_ttxg,
 )

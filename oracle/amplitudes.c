@@ -1324,3 +1324,225 @@ void mfo_dressed_amplitude(int n_g, const double *p, double m, double width, con
         }
     free(st);
 }
+
+/* ------------------------------------------------------------------------ */
+/* q qbar -> t tbar g (the q qbar channel of p p -> t tbar g, Sec. 3)        */
+/* ------------------------------------------------------------------------ */
+/* Feynman rules as listed above the colour-dressed engine (g = 1).  Legs:
+ * quark q(pa) with colour i, antiquark qbar(pb) with anticolour j, top t(k1)
+ * colour k, antitop tbar(k2) anticolour l, gluon g(k3) adjoint a; s = (pa +
+ * pb)^2, s12 = (k1 + k2)^2.  The five diagrams:
+ *   D1  g emitted by the quark:     vbar(pb) g^nu S(pa - k3) eps u(pa) . ubar(k1) g_nu v(k2) / s12
+ *                                   colour (T^b T^a)_ji (T^b)_kl
+ *   D2  g emitted by the antiquark: vbar(pb) eps S(k3 - pb) g^nu u(pa) . ubar g_nu v / s12
+ *                                   colour (T^a T^b)_ji (T^b)_kl
+ *   D3  g emitted by the top:       ubar(k1) eps S(k1 + k3) g^nu v(k2) . vbar g_nu u / s
+ *                                   colour (T^b)_ji (T^a T^b)_kl
+ *   D4  g emitted by the antitop:   ubar(k1) g^nu S(-k2 - k3) eps v(k2) . vbar g_nu u / s
+ *                                   colour (T^b)_ji (T^b T^a)_kl
+ *   D5  three-gluon vertex: J = vbar g u (gluon b, momentum P = pa + pb into
+ *       the vertex), K = ubar g v (gluon c, momentum -Q = -(k1 + k2) into the
+ *       vertex), the external gluon (a, momentum -k3 into the vertex):
+ *       [J.K (P + Q).eps + K.eps J.(k3 - Q) - J.eps K.(k3 + P)] / (s s12)
+ *                                   colour f^{bca} (T^b)_ji (T^c)_kl
+ * with S(p) = (p-slash + m) / (p^2 - m^2 + i m Gamma) (m = 0 on the quark
+ * line).  Counting the factors i of the rules, D1 .. D4 carry -i and D5
+ * carries +1, so M = -i [A1 C1 + A2 C2 + A3 C3 + A4 C4 + i A5 C5]; the
+ * common factor -i is dropped.                                              */
+
+static void qq_vec_current(const cplx *row, const cplx *col, cplx *J)
+{
+    for (int mu = 0; mu < 4; ++mu) {
+        cplx t[4];
+        row_times(row, G[mu], t);
+        J[mu] = row_dot_col(t, col);
+    }
+}
+
+static void qq_mat_col(cplx M[4][4], const cplx *col, cplx *out)
+{
+    cplx t[4];
+    for (int i = 0; i < 4; ++i) {
+        cplx s = 0;
+        for (int j = 0; j < 4; ++j)
+            s += M[i][j] * col[j];
+        t[i] = s;
+    }
+    memcpy(out, t, sizeof(t));
+}
+
+/* (p-slash + m) / (p^2 - m^2 + i m Gamma) as a matrix */
+static void qq_propagator(const double *p, double m, double width, cplx S[4][4])
+{
+    cplx pc[4] = { p[0], p[1], p[2], p[3] };
+    slash(pc, S);
+    cplx den = rdot(p, p) - m * m + I * m * width;
+    for (int i = 0; i < 4; ++i) {
+        S[i][i] += m;
+        for (int j = 0; j < 4; ++j)
+            S[i][j] /= den;
+    }
+}
+
+static cplx qq_cdot(const cplx *a, const double *b)
+{
+    return a[0] * b[0] - a[1] * b[1] - a[2] * b[2] - a[3] * b[3];
+}
+
+void mfo_qqbar_ttxg_diagrams(const double *p, double m, double width, const int *hel, int ward, double *amp)
+{
+    init_gamma();
+    double pa[4], pb[4], k1[4], k2[4], k3[4];
+    for (int mu = 0; mu < 4; ++mu) {
+        k1[mu] = p[mu];
+        k2[mu] = p[4 + mu];
+        pa[mu] = -p[8 + mu];
+        pb[mu] = -p[12 + mu];
+        k3[mu] = p[16 + mu];
+    }
+    cplx u[4], vb[4], ub[4], v[4], eps[4];
+    spinor_u(pa, 0.0, hel[0], u);
+    spinor_vbar(pb, 0.0, hel[1], vb);
+    spinor_ubar(k1, m, hel[2], ub);
+    spinor_v(k2, m, hel[3], v);
+    if (ward) {
+        for (int mu = 0; mu < 4; ++mu)
+            eps[mu] = k3[mu];
+    } else {
+        polarisation(k3, hel[4], eps);
+    }
+    double P[4], Q[4];
+    for (int mu = 0; mu < 4; ++mu) {
+        P[mu] = pa[mu] + pb[mu];
+        Q[mu] = k1[mu] + k2[mu];
+    }
+    double s = rdot(P, P), s12 = rdot(Q, Q);
+    cplx E[4][4], S[4][4], t[4], w[4];
+    slash(eps, E);
+    cplx J[4], K[4], X[4];
+    qq_vec_current(vb, u, J);
+    qq_vec_current(ub, v, K);
+    cplx A[5];
+    /* D1 */
+    double q1[4];
+    for (int mu = 0; mu < 4; ++mu)
+        q1[mu] = pa[mu] - k3[mu];
+    qq_propagator(q1, 0.0, 0.0, S);
+    qq_mat_col(E, u, t);
+    qq_mat_col(S, t, w);
+    qq_vec_current(vb, w, X);
+    A[0] = mdot(X, K) / s12;
+    /* D2 */
+    double q2[4];
+    for (int mu = 0; mu < 4; ++mu)
+        q2[mu] = k3[mu] - pb[mu];
+    qq_propagator(q2, 0.0, 0.0, S);
+    row_times(vb, E, t);
+    row_times(t, S, w);
+    qq_vec_current(w, u, X);
+    A[1] = mdot(X, K) / s12;
+    /* D3 */
+    double q3[4];
+    for (int mu = 0; mu < 4; ++mu)
+        q3[mu] = k1[mu] + k3[mu];
+    qq_propagator(q3, m, width, S);
+    row_times(ub, E, t);
+    row_times(t, S, w);
+    qq_vec_current(w, v, X);
+    A[2] = mdot(X, J) / s;
+    /* D4 */
+    double q4[4];
+    for (int mu = 0; mu < 4; ++mu)
+        q4[mu] = -k2[mu] - k3[mu];
+    qq_propagator(q4, m, width, S);
+    qq_mat_col(E, v, t);
+    qq_mat_col(S, t, w);
+    qq_vec_current(ub, w, X);
+    A[3] = mdot(X, J) / s;
+    /* D5 */
+    double PQ[4], kQ[4], kP[4];
+    for (int mu = 0; mu < 4; ++mu) {
+        PQ[mu] = P[mu] + Q[mu];
+        kQ[mu] = k3[mu] - Q[mu];
+        kP[mu] = k3[mu] + P[mu];
+    }
+    cplx v5 = mdot(J, K) * qq_cdot(eps, PQ) + mdot(K, eps) * qq_cdot(J, kQ) - mdot(J, eps) * qq_cdot(K, kP);
+    A[4] = I * v5 / (s * s12);
+    for (int d = 0; d < 5; ++d) {
+        amp[2 * d] = creal(A[d]);
+        amp[2 * d + 1] = cimag(A[d]);
+    }
+}
+
+static cplx qq_T[8][3][3];
+static double qq_f[8][8][8];
+static pthread_once_t qq_once = PTHREAD_ONCE_INIT;
+
+static void qq_colour_init(void)
+{
+    gell_mann_T(qq_T);
+    /* f^{abc} = -2 i Tr([T^a, T^b] T^c) */
+    for (int a = 0; a < 8; ++a)
+        for (int b = 0; b < 8; ++b)
+            for (int c = 0; c < 8; ++c) {
+                cplx tr = 0;
+                for (int i = 0; i < 3; ++i)
+                    for (int j = 0; j < 3; ++j)
+                        for (int k = 0; k < 3; ++k)
+                            tr += (qq_T[a][i][j] * qq_T[b][j][k] - qq_T[b][i][j] * qq_T[a][j][k]) * qq_T[c][k][i];
+                qq_f[a][b][c] = creal(-2.0 * I * tr);
+            }
+}
+
+void mfo_qqbar_ttxg_colour(const int *cols, double *c)
+{
+    pthread_once(&qq_once, qq_colour_init);
+    const int i = cols[0], j = cols[1], k = cols[2], l = cols[3], a = cols[4];
+    cplx C[5] = { 0, 0, 0, 0, 0 };
+    for (int b = 0; b < 8; ++b) {
+        cplx ba_ji = 0, ab_ji = 0, ab_kl = 0, ba_kl = 0;
+        for (int x = 0; x < 3; ++x) {
+            ba_ji += qq_T[b][j][x] * qq_T[a][x][i];
+            ab_ji += qq_T[a][j][x] * qq_T[b][x][i];
+            ab_kl += qq_T[a][k][x] * qq_T[b][x][l];
+            ba_kl += qq_T[b][k][x] * qq_T[a][x][l];
+        }
+        C[0] += ba_ji * qq_T[b][k][l];
+        C[1] += ab_ji * qq_T[b][k][l];
+        C[2] += qq_T[b][j][i] * ab_kl;
+        C[3] += qq_T[b][j][i] * ba_kl;
+        for (int cc = 0; cc < 8; ++cc)
+            C[4] += qq_f[b][cc][a] * qq_T[b][j][i] * qq_T[cc][k][l];
+    }
+    for (int d = 0; d < 5; ++d) {
+        c[2 * d] = creal(C[d]);
+        c[2 * d + 1] = cimag(C[d]);
+    }
+}
+
+/* Sum over the 32 helicity configurations and the 3^4 x 8 colour
+ * assignments of |sum_d C_d A_d|^2 (g = 1, no averaging).                  */
+double mfo_me2_qqbar_ttxg(const double *p, double m, double width)
+{
+    double C[648][10];
+    for (int ci = 0; ci < 648; ++ci) {
+        int cols[5] = { ci % 3, (ci / 3) % 3, (ci / 9) % 3, (ci / 27) % 3, ci / 81 };
+        mfo_qqbar_ttxg_colour(cols, C[ci]);
+    }
+    double total = 0.0;
+    for (int h = 0; h < 32; ++h) {
+        int hel[5] = { h & 1, (h >> 1) & 1, (h >> 2) & 1, (h >> 3) & 1, (h >> 4) & 1 };
+        double A[10];
+        mfo_qqbar_ttxg_diagrams(p, m, width, hel, 0, A);
+        for (int ci = 0; ci < 648; ++ci) {
+            const double *c = C[ci];
+            double re = 0.0, im = 0.0;
+            for (int d = 0; d < 5; ++d) {
+                re += c[2 * d] * A[2 * d] - c[2 * d + 1] * A[2 * d + 1];
+                im += c[2 * d] * A[2 * d + 1] + c[2 * d + 1] * A[2 * d];
+            }
+            total += re * re + im * im;
+        }
+    }
+    return total;
+}

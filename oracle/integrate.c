@@ -193,13 +193,21 @@ static double weight_from_x(const mfo_process *proc, double sqrt_s,
     ev->lum_q[0] = ev->lum_q[1] = 0.0;
     if (pp) {
         /* q qbar channels: the quark from beam 1 (u ubar, d dbar) or from beam 2
-         * (ubar u, dbar d); average over 2 x 2 helicities and 3 x 3 colours */
-        double pr[16];
-        memcpy(pr, p, sizeof(double) * 8);
+         * (ubar u, dbar d); average over 2 x 2 helicities and 3 x 3 colours;
+         * t tbar (n_g = 2) or t tbar g (n_g = 3) */
+        double pr[(MFO_MAX_G + 2) * 4];
+        memcpy(pr, p, sizeof(double) * 4 * (n_g + 2));
         memcpy(pr + 8, pb, sizeof(pb));
         memcpy(pr + 12, pa, sizeof(pa));
-        ev->me2_q[0] = gs2 * gs2 * mfo_me2_qqbar_ttx(p, m) / 36.0;
-        ev->me2_q[1] = gs2 * gs2 * mfo_me2_qqbar_ttx(pr, m) / 36.0;
+        if (n_g == 2) {
+            ev->me2_q[0] = gs2 * gs2 * mfo_me2_qqbar_ttx(p, m) / 36.0;
+            ev->me2_q[1] = gs2 * gs2 * mfo_me2_qqbar_ttx(pr, m) / 36.0;
+        } else if (n_g == 3) {
+            ev->me2_q[0] = gs2 * gs2 * gs2 * mfo_me2_qqbar_ttxg(p, m, proc->w_top) / 36.0;
+            ev->me2_q[1] = gs2 * gs2 * gs2 * mfo_me2_qqbar_ttxg(pr, m, proc->w_top) / 36.0;
+        } else {
+            ev->me2_q[0] = ev->me2_q[1] = NAN;   /* q qbar channels with more gluons: not in the oracle */
+        }
         double x1 = ev->x1, x2 = ev->x2;
         double u1 = mfo_pdf_xq(pdf, 0, x1, q2) / x1, ub1 = mfo_pdf_xq(pdf, 1, x1, q2) / x1;
         double d1 = mfo_pdf_xq(pdf, 2, x1, q2) / x1, db1 = mfo_pdf_xq(pdf, 3, x1, q2) / x1;

@@ -133,6 +133,17 @@ void mfo_colour_matrix_relabel(int n_g, double *C);
 /* q(pa) qbar(pb) -> t tbar: |M|^2 summed over helicities and colours, g = 1.
  * p: [4][4] all outgoing: t, tbar, -pa, -pb. */
 double mfo_me2_qqbar_ttx(const double *p, double m);
+/* q(pa) qbar(pb) -> t tbar g from its five Feynman diagrams (amplitudes.c):
+ * the colour-stripped diagram amplitudes of helicity configuration hel[5]
+ * (quark, antiquark, top, antitop spin; gluon helicity), amp[2 d] = Re,
+ * [2 d + 1] = Im; ward != 0 replaces the gluon polarisation by its momentum.
+ * p: [5][4] all outgoing: t, tbar, -pa, -pb, g. */
+void mfo_qqbar_ttxg_diagrams(const double *p, double m, double width, const int *hel, int ward, double *amp);
+/* The diagrams' colour factors for cols[5] = (quark colour, antiquark
+ * anticolour, top colour, antitop anticolour, gluon adjoint index). */
+void mfo_qqbar_ttxg_colour(const int *cols, double *c);
+/* Sum over helicities and colour assignments of |sum_d C_d A_d|^2, g = 1. */
+double mfo_me2_qqbar_ttxg(const double *p, double m, double width);
 /* Colour-dressed amplitude M_ij from Feynman rules with explicit SU(3)
  * indices for one assignment of gluon adjoint indices cols[n_g] (0 .. 7) and
  * helicity configuration hel: out[2 (3 i + j)] = Re M_ij, [+1] = Im, i the

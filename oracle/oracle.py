@@ -94,6 +94,12 @@ def lib():
         L.mfo_pdf_xq.restype = C.c_double
         L.mfo_me2_qqbar_ttx.argtypes = [_dp, C.c_double]
         L.mfo_me2_qqbar_ttx.restype = C.c_double
+        L.mfo_qqbar_ttxg_diagrams.argtypes = [_dp, C.c_double, C.c_double, _ip, C.c_int, _dp]
+        L.mfo_qqbar_ttxg_diagrams.restype = None
+        L.mfo_qqbar_ttxg_colour.argtypes = [_ip, _dp]
+        L.mfo_qqbar_ttxg_colour.restype = None
+        L.mfo_me2_qqbar_ttxg.argtypes = [_dp, C.c_double, C.c_double]
+        L.mfo_me2_qqbar_ttxg.restype = C.c_double
         L.mfo_pdf_xf.restype = C.c_double
         L.mfo_n_orderings.argtypes = [C.c_int]
         L.mfo_n_orderings.restype = C.c_int
@@ -211,6 +217,8 @@ class Process:
         imodes = {"gg": 0, "pp": 1}
         if self.initial not in imodes:
             raise ValueError(f"initial must be one of {sorted(imodes)}, not {self.initial!r}")
+        if self.initial == "pp" and self.n_g not in (2, 3):
+            raise ValueError("the q qbar channels are in the oracle for p p -> t tbar and t tbar g only")
         return _Process(self.n_g, self.m_top, self.w_top, self.alpha_s, self.mu_f,
                         self.ptmin_g, self.etamax_g, self.drmin_gg, modes[self.colour],
                         hmodes[self.helicity], imodes[self.initial])
@@ -344,6 +352,30 @@ def me2_qqbar_ttx(p, m):
     """q qbar -> t tbar |M|^2 summed over helicities and colours (g = 1);
     p: [4][4] all outgoing: t, tbar, -p_q, -p_qbar."""
     return lib().mfo_me2_qqbar_ttx(_d(_f64(p)), m)
+
+
+def qqbar_ttxg_diagrams(p, m, width, hel, ward=False):
+    """The five colour-stripped diagram amplitudes of q qbar -> t tbar g
+    (complex [5]); p: [5][4] all outgoing: t, tbar, -p_q, -p_qbar, g;
+    hel: (quark, antiquark, top, antitop spin, gluon helicity)."""
+    out = np.zeros(10)
+    h = np.ascontiguousarray(hel, dtype=np.int32)
+    lib().mfo_qqbar_ttxg_diagrams(_d(_f64(p)), m, width, h.ctypes.data_as(_ip), int(bool(ward)), _d(out))
+    return out[0::2] + 1j * out[1::2]
+
+
+def qqbar_ttxg_colour(cols):
+    """Colour factors (complex [5]) of the diagrams for cols = (i_q, j_qbar,
+    k_t, l_tbar, a_g)."""
+    out = np.zeros(10)
+    c = np.ascontiguousarray(cols, dtype=np.int32)
+    lib().mfo_qqbar_ttxg_colour(c.ctypes.data_as(_ip), _d(out))
+    return out[0::2] + 1j * out[1::2]
+
+
+def me2_qqbar_ttxg(p, m, width):
+    """q qbar -> t tbar g |M|^2 summed over helicities and colours (g = 1)."""
+    return lib().mfo_me2_qqbar_ttxg(_d(_f64(p)), m, width)
 
 
 def colour_matrix(n_g):
