@@ -17,6 +17,7 @@
 #include <type_traits>
 
 #include "mf_device.hpp"
+#include "mf_qqbar_ttxg.hpp"
 
 namespace mf {
 
@@ -515,16 +516,23 @@ __device__ __forceinline__ int event_kinematics(const EventParams& P, uint64_t e
                 f1 = pdf_xg(P, s_rows, s_lx, s_lq, x1) / x1;
                 f2 = pdf_xg(P, s_rows, s_lx, s_lq, x2) / x2;
                 pref = jac * W * f1 * f2 / (2.0 * shat);
-                if (s_qrows) {
-                    // q qbar luminosity, number densities: the quark from beam 1
-                    // (u ubar, d dbar) plus the quark from beam 2 (ubar u, dbar d);
+                if (s_qrows && pref != 0.0) {
+                    // q qbar luminosities, number densities: the quark from beam 1
+                    // (u ubar, d dbar) and from beam 2 (ubar u, dbar d).  For t tbar
                     // the summed q qbar |M|^2 is the same for both orientations
-                    // (symmetric under t <-> u at tree level)
+                    // (symmetric under t <-> u at tree level) and one prefactor
+                    // carries both; for t tbar g they differ.
                     double q1[4], q2[4];
                     pdf_xq4(P, s_qrows, s_lx, s_lq, x1, q1);
                     pdf_xq4(P, s_qrows, s_lx, s_lq, x2, q2);
-                    const double lq = (q1[0] * q2[1] + q1[2] * q2[3]) + (q1[1] * q2[0] + q1[3] * q2[2]);
-                    *pref_q = jac * W * lq / (2.0 * shat);
+                    const double lf = q1[0] * q2[1] + q1[2] * q2[3];
+                    const double lr = q1[1] * q2[0] + q1[3] * q2[2];
+                    if constexpr (NF == 2) {
+                        pref_q[0] = jac * W * (lf + lr) / (2.0 * shat);
+                    } else {
+                        pref_q[0] = jac * W * lf / (2.0 * shat);
+                        pref_q[1] = jac * W * lr / (2.0 * shat);
+                    }
                 }
 #pragma unroll
                 for (int i = 0; i < NF; ++i)
@@ -728,8 +736,9 @@ struct StageParams {
     int first_batch;         // acc: 1 = start the per-wave partials from zero
     unsigned long long* next_group;  // amp: work counter, cleared by kin_kernel
     void* amps;              // t tbar g g g: [count][120][128][re, im] partial amplitudes (type T)
-    double* pref_q;          // p p: [count] J_V W L_qqbar / (2 s_hat), both beam orientations
-    double* me_q;            // p p: [count] q qbar |M|^2 summed over helicities and colours
+    double* pref_q;          // p p: J_V W L_qqbar / (2 s_hat); t tbar: [count], both beam orientations,
+                             // t tbar g: [2][count], the quark from beam 1 / beam 2
+    double* me_q;            // p p: q qbar |M|^2 summed over helicities and colours; [count] / [2][count]
 };
 
 template <int NF, bool PP = false>
@@ -764,13 +773,16 @@ __global__ void __launch_bounds__(kBlock) kin_kernel(StageParams S)
         const uint64_t e = chunk * kWave + lane;
         if (e >= S.count)
             continue;
-        double pref, pq = 0.0;
+        double pref, pq[2] = {0.0, 0.0};
         const int flags = event_kinematics<NF>(P, S.first + e, s_rows, s_lx, s_lq, S.bins + e, S.count,
-                                               S.mom + e * (4 * NF + 1), pref, PP ? s_qrows : nullptr, &pq);
+                                               S.mom + e * (4 * NF + 1), pref, PP ? s_qrows : nullptr, pq);
         S.pref[e] = pref;
         S.flags[e] = (unsigned char)flags;
-        if constexpr (PP)
-            S.pref_q[e] = pq;
+        if constexpr (PP) {
+            S.pref_q[e] = pq[0];
+            if constexpr (NF == 3)
+                S.pref_q[S.count + e] = pq[1];
+        }
     }
 }
 
@@ -1075,8 +1087,11 @@ __global__ void __launch_bounds__(kBlock) acc_kernel(StageParams S)
             const int flags = S.flags[e];
             if (pref != 0.0) {
                 w = pref * (S.me[e] * P.me_norm);
-                if (P.pp)
+                if (P.pp) {
                     w += S.pref_q[e] * (S.me_q[e] * P.me_norm_q);
+                    if constexpr (NF == 3)
+                        w += S.pref_q[S.count + e] * (S.me_q[S.count + e] * P.me_norm_q);
+                }
             }
             if (P.weights)
                 P.weights[S.first + e] = w;
@@ -1354,6 +1369,40 @@ __global__ void __launch_bounds__(kBlock) qqbar_me_kernel(const double* __restri
     out[e] = sum;
 }
 
+// p p -> t tbar g: the q qbar amplitudes of the batch's passing events, 32
+// lanes per event (the 16 non-vanishing configurations of each beam
+// orientation), summed to me_q[e] (quark along +z) and me_q[count + e].
+__global__ void __launch_bounds__(kBlock) qqbar_ttxg_kernel(StageParams S)
+{
+    const uint64_t e = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) >> 5;
+    const int c = threadIdx.x & 31;
+    const bool live = e < S.count && S.pref[e] != 0.0;
+    double v = 0.0;
+    if (live) {
+        const double* mom = S.mom + e * 13;
+        v = qqbar_ttxg_config(mom, mom[12], S.P.m_top, S.P.mw, c & 15, c >> 4);
+    }
+    v = group_sum(v, 16);
+    if (live && (c & 15) == 0)
+        S.me_q[(uint64_t)(c >> 4) * S.count + e] = v;
+}
+
+// q qbar -> t tbar g |M|^2 (g = 1) for explicit momenta [n][12] (t, tbar, g),
+// the quark along +z; 16 lanes per event.
+__global__ void __launch_bounds__(kBlock) qqbar_ttxg_me_kernel(const double* __restrict__ mom,
+                                                               const double* __restrict__ eb, uint64_t n,
+                                                               double mt, double mw, double* __restrict__ out)
+{
+    const uint64_t e = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) >> 4;
+    const int c = threadIdx.x & 15;
+    double v = 0.0;
+    if (e < n)
+        v = qqbar_ttxg_config(mom + 12 * e, eb[e], mt, mw, c, 0);
+    v = group_sum(v, 16);
+    if (e < n && c == 0)
+        out[e] = v;
+}
+
 // mf_evaluate for the staged processes: weight (and the record's |M|^2 entry)
 // of every event of the batch.
 __global__ void __launch_bounds__(kBlock) weight_kernel(StageParams S, int nf)
@@ -1364,8 +1413,11 @@ __global__ void __launch_bounds__(kBlock) weight_kernel(StageParams S, int nf)
     const double pref = S.pref[e];
     const double me = pref != 0.0 ? S.me[e] : 0.0;
     double w = pref != 0.0 ? pref * (me * S.P.me_norm) : 0.0;
-    if (S.P.pp && pref != 0.0)
+    if (S.P.pp && pref != 0.0) {
         w += S.pref_q[e] * (S.me_q[e] * S.P.me_norm_q);
+        if (nf == 3)
+            w += S.pref_q[S.count + e] * (S.me_q[S.count + e] * S.P.me_norm_q);
+    }
     S.P.weights[S.first + e] = w;
     if (S.P.record)
         S.P.record[(S.first + e) * (8 + 4 * (uint64_t)nf) + 6] = me;

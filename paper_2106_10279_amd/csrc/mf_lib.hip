@@ -65,8 +65,15 @@ int n_gluons(int id)
     case MF_GG_TTXGG: return 4;
     case MF_GG_TTXGGG: return 5;
     case MF_PP_TTX: return 2;
+    case MF_PP_TTXG: return 3;
     default: return -1;
     }
+}
+
+// p p processes: the g g channel plus the q qbar channels from the quark tables.
+bool is_pp(int id)
+{
+    return id == MF_PP_TTX || id == MF_PP_TTXG;
 }
 
 double factorial(int n)
@@ -225,7 +232,7 @@ mf_status validate_pdf(const mf_pdf_grid* pdf, double mu_f)
 // p p processes: the quark tables must be there and finite.
 mf_status validate_quarks(const mf_process* proc, const mf_pdf_grid* pdf)
 {
-    if (proc->id != MF_PP_TTX)
+    if (!is_pp(proc->id))
         return MF_OK;
     if (!pdf->xq)
         return fail(MF_EINVAL, "p p processes need the quark tables (pdf->xq)");
@@ -303,7 +310,7 @@ mf_status prepare(const mf_process* proc, double sqrt_s, const mf_pdf_grid* pdf,
     MF_HIP(hipMemcpyAsync(m.log_x, pdf->log_x, sizeof(double) * nx, hipMemcpyHostToDevice, S.stream));
     MF_HIP(hipMemcpyAsync(m.log_q2, pdf->log_q2, sizeof(double) * nq, hipMemcpyHostToDevice, S.stream));
     MF_HIP(hipMemcpyAsync(m.xf, pdf->xf, sizeof(double) * nx * (size_t)nq, hipMemcpyHostToDevice, S.stream));
-    const bool pp = proc->id == MF_PP_TTX;
+    const bool pp = is_pp(proc->id);
     if (pp) {
         if (!m.xq)
             return fail(MF_EUNSUPPORTED, "no device room for the quark tables");
@@ -343,7 +350,8 @@ mf_status prepare(const mf_process* proc, double sqrt_s, const mf_pdf_grid* pdf,
     P.hel_mc = opt->helicity == MF_HELICITY_SAMPLED;
     P.pp = pp ? 1 : 0;
     P.xq = pp ? m.xq : nullptr;
-    P.me_norm_q = gs2 * gs2 / 36.0 * mf::kGeV2ToPb;
+    // q qbar: average over 2 x 2 helicities and 3 x 3 colours, g_s^(2 n_g)
+    P.me_norm_q = std::pow(gs2, n) / 36.0 * mf::kGeV2ToPb;
     return MF_OK;
 }
 
@@ -405,7 +413,7 @@ mf_status launch_stages(const mf::StageParams& S, int kin_blocks, int n_cu, hipS
                       : amp_grid_for<NG, T, COL>(n_groups, n_cu, &amp_grid);
     if (st != MF_OK)
         return st;
-    if constexpr (NG == 2) {
+    if constexpr (NG == 2 || NG == 3) {
         if (S.P.pp)
             hipLaunchKernelGGL((mf::kin_kernel<NG, true>), dim3(kin_blocks), dim3(mf::kBlock), 0, stream, S);
         else
@@ -421,6 +429,14 @@ mf_status launch_stages(const mf::StageParams& S, int kin_blocks, int n_cu, hipS
     else
         hipLaunchKernelGGL((mf::amp_kernel<NG, T, COL>), dim3(amp_grid), dim3(mf::kWave), 0, stream, S);
     MF_HIP(hipGetLastError());
+    if (NG == 3 && S.P.pp) {
+        // the q qbar channel of t tbar g (FP64): 32 lanes per event
+        const uint64_t qb = (S.count * 32 + mf::kBlock - 1) / mf::kBlock;
+        if (qb > 0x7FFFFFFFull)
+            return fail(MF_EINVAL, "too many events for one launch");
+        hipLaunchKernelGGL(mf::qqbar_ttxg_kernel, dim3((unsigned)qb), dim3(mf::kBlock), 0, stream, S);
+        MF_HIP(hipGetLastError());
+    }
     if (amp_end)
         MF_HIP(hipEventRecord(amp_end, stream));
     if (accumulate) {
@@ -660,10 +676,10 @@ mf_status integrate_impl(const mf_process* proc, double sqrt_s, const mf_pdf_gri
         if (fixed_scratch)
             return fail(MF_EUNSUPPORTED, "mf_integrate_static does not run g g -> t tbar g g g");
     }
-    const bool pp = proc->id == MF_PP_TTX;
+    const bool pp = is_pp(proc->id);
     if (pp) {
         if (opt->colour != MF_COLOUR_FULL || opt->helicity != MF_HELICITY_SUM)
-            return fail(MF_EUNSUPPORTED, "p p -> t tbar runs with the full colour and helicity sums only");
+            return fail(MF_EUNSUPPORTED, "p p processes run with the full colour and helicity sums only");
         if (fixed_scratch)
             return fail(MF_EUNSUPPORTED, "mf_integrate_static does not run p p processes");
         if (grad)
@@ -773,8 +789,9 @@ mf_status integrate_impl(const mf_process* proc, double sqrt_s, const mf_pdf_gri
             if ((st = ensure(ws.amp_counter, sizeof(unsigned long long))) != MF_OK) return st;
             if (amp_bytes && (st = ensure(ws.st_amp, amp_bytes * b0)) != MF_OK) return st;
             if (pp) {
-                if ((st = ensure(ws.st_prefq, sizeof(double) * b0)) != MF_OK) return st;
-                if ((st = ensure(ws.st_meq, sizeof(double) * b0)) != MF_OK) return st;
+                const size_t orient = ng == 3 ? 2 : 1;   // t tbar g: both beam orientations
+                if ((st = ensure(ws.st_prefq, sizeof(double) * orient * b0)) != MF_OK) return st;
+                if ((st = ensure(ws.st_meq, sizeof(double) * orient * b0)) != MF_OK) return st;
             }
         }
         if (grad) {
@@ -1166,15 +1183,16 @@ mf_status evaluate_staged(Setup& S, const mf_options* opt, uint64_t n)
         if ((st = stage_buffers_ng5(*S.ws, batch, opt->precision, SP)) != MF_OK) return st;
     } else {
         Workspace& ws = *S.ws;
-        constexpr int K = mf::Layout<2>::kMom;
+        const int K = 4 * S.ng + 1;           // momenta and beam energy
         if ((st = ensure(ws.st_mom, sizeof(double) * K * batch)) != MF_OK) return st;
         if ((st = ensure(ws.st_pref, sizeof(double) * batch)) != MF_OK) return st;
         if ((st = ensure(ws.st_me, sizeof(double) * batch)) != MF_OK) return st;
-        if ((st = ensure(ws.st_bins, sizeof(unsigned short) * 4 * batch)) != MF_OK) return st;
+        if ((st = ensure(ws.st_bins, sizeof(unsigned short) * S.D * batch)) != MF_OK) return st;
         if ((st = ensure(ws.st_flags, batch)) != MF_OK) return st;
         if ((st = ensure(ws.amp_counter, sizeof(unsigned long long))) != MF_OK) return st;
-        if ((st = ensure(ws.st_prefq, sizeof(double) * batch)) != MF_OK) return st;
-        if ((st = ensure(ws.st_meq, sizeof(double) * batch)) != MF_OK) return st;
+        const size_t orient = S.ng == 3 ? 2 : 1;
+        if ((st = ensure(ws.st_prefq, sizeof(double) * orient * batch)) != MF_OK) return st;
+        if ((st = ensure(ws.st_meq, sizeof(double) * orient * batch)) != MF_OK) return st;
         SP.mom = (double*)ws.st_mom.ptr;
         SP.pref = (double*)ws.st_pref.ptr;
         SP.me = (double*)ws.st_me.ptr;
@@ -1195,6 +1213,10 @@ mf_status evaluate_staged(Setup& S, const mf_options* opt, uint64_t n)
             st = opt->precision == MF_FP32_KAHAN
                      ? launch_stages_ng5<float>(SP, kin_blocks, S.ws->n_cu, S.stream, nullptr, nullptr, false)
                      : launch_stages_ng5<double>(SP, kin_blocks, S.ws->n_cu, S.stream, nullptr, nullptr, false);
+        else if (S.ng == 3)
+            st = opt->precision == MF_FP32_KAHAN
+                     ? launch_stages<3, float, 0>(SP, kin_blocks, S.ws->n_cu, S.stream, nullptr, nullptr, false)
+                     : launch_stages<3, double, 0>(SP, kin_blocks, S.ws->n_cu, S.stream, nullptr, nullptr, false);
         else
             st = opt->precision == MF_FP32_KAHAN
                      ? launch_stages<2, float, 0>(SP, kin_blocks, S.ws->n_cu, S.stream, nullptr, nullptr, false)
@@ -1230,7 +1252,7 @@ mf_status mf_evaluate(const mf_process* proc, double sqrt_s, const mf_pdf_grid* 
     P.k53_out = k53_out;
     P.bins_out = bins_out;
     P.record = record_out;
-    if (S.ng == 5 || proc->id == MF_PP_TTX) {
+    if (S.ng == 5 || is_pp(proc->id)) {
         if ((st = evaluate_staged(S, opt, n)) != MF_OK)
             return st;
         MF_HIP(hipStreamSynchronize(S.stream));
@@ -1560,6 +1582,17 @@ mf_status mf_matrix_element(int process_id, mf_precision precision, const double
     hipStream_t s = (hipStream_t)stream;
     if (ng == 5)
         return matrix_element_ng5(precision, mom, eb, n, m_top, w_top, out, s);
+    if (process_id == MF_PP_TTXG) {
+        // the q qbar channel (quark along +z), FP64
+        const uint64_t qb = (n * 16 + mf::kBlock - 1) / mf::kBlock;
+        if (n > (1ull << 36) || qb > 0x7FFFFFFFull)
+            return fail(MF_EINVAL, "too many events for one launch");
+        hipLaunchKernelGGL(mf::qqbar_ttxg_me_kernel, dim3((unsigned)qb), dim3(mf::kBlock), 0, s, mom, eb, n, m_top,
+                           m_top * w_top, out);
+        MF_HIP(hipGetLastError());
+        MF_HIP(hipStreamSynchronize(s));
+        return MF_OK;
+    }
     if (process_id == MF_PP_TTX) {
         // the q qbar channel (quark along +z), FP64
         const uint64_t qb = (n + mf::kBlock - 1) / mf::kBlock;

@@ -1,7 +1,7 @@
-"""GPU parity of p p -> t tbar (the g g channel plus the q qbar channels u
-ubar, ubar u, d dbar, dbar d; Sec. 3, Table 1) against the oracle: the
-q qbar |M|^2 for explicit momenta, per-event weights, a short integration,
-and the requests this process refuses."""
+"""GPU parity of p p -> t tbar and p p -> t tbar g (the g g channel plus the
+q qbar channels u ubar, ubar u, d dbar, dbar d; Sec. 3, Table 1) against the
+oracle: the q qbar |M|^2 for explicit momenta, per-event weights, a short
+integration, and the requests these processes refuse."""
 import sys
 
 import numpy as np
@@ -15,6 +15,11 @@ pytestmark = pytest.mark.gpu
 
 SQRT_S = 13000.0
 M = 173.0
+# process, gluons, cuts, events for the weight and integration checks
+CASES = {
+    "pp_ttx": (2, {}, 20_000, 20_000),
+    "pp_ttxg": (3, dict(ptmin_g=20.0, etamax_g=2.5), 6_000, 3_000),
+}
 
 
 @pytest.fixture(scope="module")
@@ -36,73 +41,88 @@ def say(*a):
     sys.stdout.flush()
 
 
-def test_qqbar_matrix_element(api):
+@pytest.mark.parametrize("process", sorted(CASES))
+def test_qqbar_matrix_element(api, process):
     import torch
+    n_g = CASES[process][0]
     rng = np.random.default_rng(31)
     moms, ebs, refs = [], [], []
-    for _ in range(300):
+    for _ in range(300 if n_g == 2 else 150):
         rs = 2 * M + 1.0 + rng.exponential(600.0)
-        k, w, st = O.phase_space(2, [M, M], rs, rng.random(2))
+        masses = [M, M] + [0.0] * (n_g - 2)
+        k, w, st = O.phase_space(n_g, masses, rs, rng.random(3 * n_g - 4))
         E = rs / 2
-        p = np.array([k[0], k[1], [-E, 0, 0, -E], [-E, 0, 0, E]])
-        refs.append(O.me2_qqbar_ttx(p, M))
+        p = np.array([k[0], k[1], [-E, 0, 0, -E], [-E, 0, 0, E], *k[2:]])
+        refs.append(O.me2_qqbar_ttx(p, M) if n_g == 2 else O.me2_qqbar_ttxg(p, M, 1.5))
         moms.append(k.reshape(-1))
         ebs.append(E)
     mom = torch.tensor(np.array(moms), dtype=torch.float64, device="cuda").contiguous()
     eb = torch.tensor(np.array(ebs), dtype=torch.float64, device="cuda")
-    got = api.matrix_element("pp_ttx", mom, eb, M, 1.5).cpu().numpy()
+    say(f"\n  {process} q qbar |M|^2: {len(refs)} points")
+    got = api.matrix_element(process, mom, eb, M, 1.5).cpu().numpy()
     rel = np.abs(got / np.array(refs) - 1)
-    say(f"\n  q qbar -> t tbar |M|^2: max rel {rel.max():.2e}")
+    say(f"  max rel {rel.max():.2e}")
     assert rel.max() < 1e-12
 
 
+@pytest.mark.parametrize("process", sorted(CASES))
 @pytest.mark.parametrize("precision,bar", [("fp64", 1e-12), ("fp32_kahan", 2e-4)])
-def test_event_weights_match_oracle(api, pp_table, precision, bar):
+def test_event_weights_match_oracle(api, pp_table, process, precision, bar):
     """Per-event weights against the oracle.  The weight is the g g term plus
     the q qbar terms; where the interpolated tables go negative (x near 1)
     these have opposite signs, so the bar is relative to |g g| + |q qbar|
     of the oracle's own split."""
-    n = 20_000
+    n_g, cuts, n, _ = CASES[process]
+    D = 3 * n_g - 2
     rng = np.random.default_rng(8)
-    grid = np.sort(np.concatenate([np.zeros((4, 1)), rng.uniform(0, 1, (4, 49)), np.ones((4, 1))], axis=1), axis=1)
-    w = api.evaluate_weights(api.Process("pp_ttx"), SQRT_S, pp_table, n, seed=2, it=4, grid=grid,
+    grid = np.sort(np.concatenate([np.zeros((D, 1)), rng.uniform(0, 1, (D, 49)), np.ones((D, 1))], axis=1), axis=1)
+    say(f"\n  weights {process} {precision}: {n} events")
+    w = api.evaluate_weights(api.Process(process, **cuts), SQRT_S, pp_table, n, seed=2, it=4, grid=grid,
                              precision=precision).cpu().numpy()
-    w_o, flags, kap = O.event_weights(O.Process(n_g=2, initial="pp"), SQRT_S, pp_table, grid, 2, 4, np.arange(n),
-                                      return_kappa=True)
-    w_og, _ = O.event_weights(O.Process(n_g=2), SQRT_S, pp_table, grid, 2, 4, np.arange(n))
+    w_o, flags, kap = O.event_weights(O.Process(n_g=n_g, initial="pp", **cuts), SQRT_S, pp_table, grid, 2, 4,
+                                      np.arange(n), return_kappa=True)
+    w_og, _ = O.event_weights(O.Process(n_g=n_g, **cuts), SQRT_S, pp_table, grid, 2, 4, np.arange(n))
     skip = (flags & (8 | 16)) != 0
     zero = (w_o == 0.0) & ~skip
     assert np.all(w[zero] == 0.0)
     use = ~skip & ~zero
     scale = np.abs(w_og) + np.abs(w_o - w_og)
     rel = np.abs(w - w_o)[use] / scale[use]
-    limit = np.where((flags[use] & 64) != 0, np.maximum(bar, newton_bar(kap[use], 2)), bar)
-    say(f"\n  p p -> t tbar weights {precision}: {int(use.sum())} nonzero, max rel {rel.max():.2e}, "
+    limit = np.where((flags[use] & 64) != 0, np.maximum(bar, newton_bar(kap[use], n_g)), bar)
+    say(f"  {int(use.sum())} nonzero, max rel {rel.max():.2e}, "
         f"{int(np.sum(np.sign(w_og[use]) != np.sign(w_o[use] - w_og[use])))} with opposite-sign channels")
-    assert use.sum() > n // 2 and np.all(rel <= limit)
+    assert use.sum() > n // 3 and np.all(rel <= limit)
     # the q qbar channels separately: p p minus the g g process on the same events
-    wg = api.evaluate_weights(api.Process("gg_ttx"), SQRT_S, pp_table, n, seed=2, it=4, grid=grid,
+    gg = "gg_" + process[3:]
+    wg = api.evaluate_weights(api.Process(gg, **cuts), SQRT_S, pp_table, n, seed=2, it=4, grid=grid,
                               precision=precision).cpu().numpy()
     q, q_o = (w - wg)[use], (w_o - w_og)[use]
     assert np.all(np.abs(q - q_o) <= 2 * limit * scale[use])
     assert np.mean(np.abs(q_o) > 1e-3 * np.abs(w_og[use])) > 0.9
 
 
-def test_integration_matches_oracle(api, pp_table):
-    n, iters = 20_000, 3
-    g = api.integrate(api.Process("pp_ttx"), SQRT_S, pp_table, n, iters, seed=0)
-    o = O.integrate(O.Process(n_g=2, initial="pp"), SQRT_S, pp_table, n, iters, seed=0)
-    say(f"\n  integrate p p -> t tbar: gpu {g.sigma:.8g} +- {g.sigma_err:.3g}, oracle {o.sigma:.8g}")
+@pytest.mark.parametrize("process", sorted(CASES))
+def test_integration_matches_oracle(api, pp_table, process):
+    n_g, cuts, _, n = CASES[process]
+    iters = 3 if n_g == 2 else 2
+    say(f"\n  integrate {process} n={n} iters={iters}")
+    g = api.integrate(api.Process(process, **cuts), SQRT_S, pp_table, n, iters, seed=0)
+    o = O.integrate(O.Process(n_g=n_g, initial="pp", **cuts), SQRT_S, pp_table, n, iters, seed=0)
+    say(f"  gpu {g.sigma:.8g} +- {g.sigma_err:.3g}, oracle {o.sigma:.8g}")
     assert_integration_parity(g, o, n, say=say)
-    np.testing.assert_allclose(g.weights.cpu().numpy(), o.weights_last, rtol=1e-11, atol=0)
+    # absolute floor: events whose g g and q qbar terms cancel (tables negative near x = 1)
+    np.testing.assert_allclose(g.weights.cpu().numpy(), o.weights_last, rtol=1e-11,
+                               atol=1e-14 * np.abs(o.weights_last).max())
 
 
-def test_requests_refused(api, pp_table):
+@pytest.mark.parametrize("process", sorted(CASES))
+def test_requests_refused(api, pp_table, process):
     from paper_2106_10279_amd import _lib as L
+    cuts = CASES[process][1]
     with pytest.raises(L.MFError) as e:
-        api.integrate(api.Process("pp_ttx"), SQRT_S, W.synthetic_pdf(), 1000, 1, seed=0)
+        api.integrate(api.Process(process, **cuts), SQRT_S, W.synthetic_pdf(), 1000, 1, seed=0)
     assert e.value.status == L.MF_EINVAL
     for kw in (dict(colour="leading"), dict(helicity="sampled"), dict(static_scratch=True)):
         with pytest.raises(L.MFError) as e:
-            api.integrate(api.Process("pp_ttx"), SQRT_S, pp_table, 1000, 1, seed=0, **kw)
+            api.integrate(api.Process(process, **cuts), SQRT_S, pp_table, 1000, 1, seed=0, **kw)
         assert e.value.status == L.MF_EUNSUPPORTED, kw
