@@ -42,6 +42,14 @@ OTHER_FLOPS = {2: 420, 3: 720, 4: 1030, 5: 1340}
 # each), the top bilinear (64) and its contraction with the beam current and
 # |.|^2 / s (11); then the 16-lane sum.
 QQBAR_FLOPS = 8 * (2 * 14 + 64 + 11) + 15
+# p p -> t tbar g: 32 lanes per event (16 configurations per beam orientation),
+# each: four spinors (56), the gluon polarisation (11), the beam and top
+# currents (128), invariants (17), the quark- and antiquark-emission diagrams
+# (236 each: two slashes, a bilinear, a contraction, the propagator), the top-
+# and antitop-emission diagrams (264 each, with the mass term and the complex
+# Breit-Wigner denominator), the three-gluon diagram (126) and the 5 x 5
+# colour form (86); then two 16-lane sums.
+QQBAR_TTXG_FLOPS = 32 * (56 + 11 + 128 + 17 + 2 * 236 + 2 * 264 + 126 + 86) + 30
 
 WORKLOADS = {
     "ttx": dict(process="gg_ttx", n_g=2, cuts={}, events=1_000_000),
@@ -49,6 +57,7 @@ WORKLOADS = {
     "ttxgg": dict(process="gg_ttxgg", n_g=4, cuts=dict(ptmin_g=20.0, drmin_gg=0.4), events=10_000_000),
     "ttxggg": dict(process="gg_ttxggg", n_g=5, cuts=dict(ptmin_g=20.0, drmin_gg=0.4), events=1_000_000),
     "ppttx": dict(process="pp_ttx", n_g=2, cuts={}, events=10_000_000, quarks=True),
+    "ppttxg": dict(process="pp_ttxg", n_g=3, cuts=dict(ptmin_g=20.0, etamax_g=2.5), events=10_000_000, quarks=True),
 }
 
 
@@ -332,7 +341,8 @@ def config_leg(api, torch, name, n_events, n_iter, seeds, events_note=""):
     wl = WORKLOADS[name]
     pdf = W.synthetic_pdf(quarks=wl.get("quarks", False))
     proc = api.Process(wl["process"], **wl["cuts"])
-    f_me, f_other = me_flops(wl["n_g"]) + (QQBAR_FLOPS if wl.get("quarks") else 0), OTHER_FLOPS[wl["n_g"]]
+    qq = {2: QQBAR_FLOPS, 3: QQBAR_TTXG_FLOPS}[wl["n_g"]] if wl.get("quarks") else 0
+    f_me, f_other = me_flops(wl["n_g"]) + qq, OTHER_FLOPS[wl["n_g"]]
     total, walls, sig, roof = 0, 0.0, [], []
     for seed in seeds:
         r, wall, _ = timed_run(api, torch, proc, pdf, n_events, n_iter, 1, "fp64", seed)
@@ -412,14 +422,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="ttxgg", choices=sorted(k for k in WORKLOADS if k not in ("ttxggg", "ppttx")))
+    ap.add_argument("--workload", default="ttxgg", choices=sorted(k for k in WORKLOADS if k not in ("ttxggg", "ppttx", "ppttxg")))
     ap.add_argument("--no-ttxggg", action="store_true", help="skip the g g -> t tbar g g g legs")
     ap.add_argument("--ttxggg-events", type=int, default=1_000_000)
     ap.add_argument("--ttxggg-only", action="store_true",
                     help="only the g g -> t tbar g g g legs (for profiling them alone)")
     ap.add_argument("--ttxggg-steps", type=int, default=3)
     ap.add_argument("--pp-only", action="store_true",
-                    help="only the p p -> t tbar leg (for profiling it alone)")
+                    help="only the p p legs (for profiling them alone)")
     ap.add_argument("--events", type=int, default=None)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-fp32", action="store_true")
@@ -435,7 +445,8 @@ def main():
     ap.add_argument("--adjoint-events", type=int, default=10_000_000)
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the legs of the other workloads (g g -> t tbar at 1e5 x 5 and 1e8 x 5, "
-                         "g g -> t tbar g at 1e7 x 10 for seeds 0-4, p p -> t tbar at 1e8 x 5)")
+                         "g g -> t tbar g at 1e7 x 10 for seeds 0-4, p p -> t tbar at 1e8 x 5, "
+                         "p p -> t tbar g at 1e7 x 10)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device-to-device copy of this many bytes (3 times), "
                          "the reference kernel for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE")
@@ -460,8 +471,9 @@ def main():
     from paper_2106_10279_amd import api
 
     if args.pp_only:
-        log("[bench] p p -> t tbar, 1e8 x 5")
-        print(json.dumps({"pptx_1e8x5": config_leg(api, torch, "ppttx", 100_000_000, 5, [0])}), flush=True)
+        log("[bench] p p -> t tbar, 1e8 x 5; p p -> t tbar g, 1e7 x 10")
+        print(json.dumps({"pptx_1e8x5": config_leg(api, torch, "ppttx", 100_000_000, 5, [0]),
+                          "pptxg_1e7x10": config_leg(api, torch, "ppttxg", 10_000_000, 10, [0])}), flush=True)
         return
     if args.ttxggg_only:
         legs = {}
@@ -598,7 +610,7 @@ def main():
         log(f"[bench] helicity Monte Carlo done: {vh:.4g} events/s, weight variance x{var_ratio:.2f}")
     if not args.no_configs and args.workload == "ttxgg":
         log("[bench] g g -> t tbar, 1e5 x 5 and 1e8 x 5; g g -> t tbar g, 1e7 x 10, seeds 0-4; "
-            "p p -> t tbar, 1e8 x 5")
+            "p p -> t tbar, 1e8 x 5; p p -> t tbar g, 1e7 x 10")
         out["ttx_1e5x5"] = config_leg(api, torch, "ttx", 100_000, 5, [0])
         out["ttx_1e8x5"] = config_leg(api, torch, "ttx", 100_000_000, 5, [0],
                                       " (the scaled run: 1e5 events do not fill 256 compute units)")
@@ -606,8 +618,10 @@ def main():
         out["pptx_1e8x5"] = config_leg(api, torch, "ppttx", 100_000_000, 5, [0],
                                        " (g g and the q qbar channels u ubar, ubar u, d dbar, dbar d; synthetic "
                                        "quark tables)")
+        out["pptxg_1e7x10"] = config_leg(api, torch, "ppttxg", 10_000_000, 10, [0],
+                                         " (g g and the q qbar channels; synthetic quark tables)")
         log(f"[bench] configs done: ttx {out['ttx_1e8x5']['value']:.4g}, ttxg {out['ttxg_1e7x10']['value']:.4g}, "
-            f"pp ttx {out['pptx_1e8x5']['value']:.4g} events/s")
+            f"pp ttx {out['pptx_1e8x5']['value']:.4g}, pp ttxg {out['pptxg_1e7x10']['value']:.4g} events/s")
     if not args.no_ttxggg and args.workload == "ttxgg":
         for prec in ("fp64", "fp32_kahan"):
             log(f"[bench] g g -> t tbar g g g, {args.ttxggg_events} events x {args.ttxggg_steps} iterations, {prec}")
