@@ -42,14 +42,15 @@ OTHER_FLOPS = {2: 420, 3: 720, 4: 1030, 5: 1340}
 # each), the top bilinear (64) and its contraction with the beam current and
 # |.|^2 / s (11); then the 16-lane sum.
 QQBAR_FLOPS = 8 * (2 * 14 + 64 + 11) + 15
-# p p -> t tbar g: 32 lanes per event (16 configurations per beam orientation),
-# each: four spinors (56), the gluon polarisation (11), the beam and top
-# currents (128), invariants (17), the quark- and antiquark-emission diagrams
-# (236 each: two slashes, a bilinear, a contraction, the propagator), the top-
-# and antitop-emission diagrams (264 each, with the mass term and the complex
-# Breit-Wigner denominator), the three-gluon diagram (126) and the 5 x 5
-# colour form (86); then two 16-lane sums.
-QQBAR_TTXG_FLOPS = 32 * (56 + 11 + 128 + 17 + 2 * 236 + 2 * 264 + 126 + 86) + 30
+# p p -> t tbar g, helicity-recycled: per event 8 lanes each build the beam
+# chains X1, X2 of one beam combination (two massless spinors 28, the gluon
+# polarisation 13, s12 11, two chains of 205, scaling 16) and the top chains
+# Y3, Y4 of one top combination (two massive spinors 28, polarisation 13, two
+# chains of 232 with the mass term and the Breit-Wigner factor, scaling 48,
+# s 2), 4 + 4 of them the currents J and K (64 each); then 32 configurations
+# of 312 (four chain contractions, the three-gluon term, the 5 x 5 colour
+# form) after a per-lane setup of 47, and two 8-lane sums.
+QQBAR_TTXG_FLOPS = 8 * (478 + 555) + 8 * 64 + 8 * 47 + 32 * 312 + 14
 
 WORKLOADS = {
     "ttx": dict(process="gg_ttx", n_g=2, cuts={}, events=1_000_000),

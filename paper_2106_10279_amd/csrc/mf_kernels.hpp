@@ -1369,22 +1369,59 @@ __global__ void __launch_bounds__(kBlock) qqbar_me_kernel(const double* __restri
     out[e] = sum;
 }
 
-// p p -> t tbar g: the q qbar amplitudes of the batch's passing events, 32
-// lanes per event (the 16 non-vanishing configurations of each beam
-// orientation), summed to me_q[e] (quark along +z) and me_q[count + e].
-__global__ void __launch_bounds__(kBlock) qqbar_ttxg_kernel(StageParams S)
+// p p -> t tbar g: the q qbar amplitudes of the batch's passing events,
+// with helicity recycling.  Eight events per one-wave workgroup, eight lanes
+// per event.  Lane c first builds the beam chains X1, X2 of beam combination
+// c and the top chains Y3, Y4 of top combination c (and, for even c, the
+// currents J and K they belong with) into LDS; then it evaluates the four
+// configurations with top combination c (both orientations, both quark
+// spins).  The sums go to me_q[e] (quark along +z) and me_q[count + e].
+constexpr int kQqEvents = kWave / 8;
+__global__ void __launch_bounds__(kWave) qqbar_ttxg_kernel(StageParams S)
 {
-    const uint64_t e = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) >> 5;
-    const int c = threadIdx.x & 31;
+    // per event: X1[8], X2[8], Y3[8], Y4[8], J[4], K[4] (complex 4-vectors)
+    __shared__ __align__(16) cplx<double> s_ch[kQqEvents][40][4];
+    const int lane = threadIdx.x;
+    const int ev = lane >> 3, c = lane & 7;
+    const uint64_t e = (uint64_t)blockIdx.x * kQqEvents + ev;
     const bool live = e < S.count && S.pref[e] != 0.0;
-    double v = 0.0;
+    double mom[13];
+    if (live)
+        for (int i = 0; i < 13; ++i)
+            mom[i] = S.mom[e * 13 + i];
+    cplx<double>(*ch)[4] = s_ch[ev];
     if (live) {
-        const double* mom = S.mom + e * 13;
-        v = qqbar_ttxg_config(mom, mom[12], S.P.m_top, S.P.mw, c & 15, c >> 4);
+        const bool cur = (c & 1) == 0;
+        qq_beam_chains(mom, mom[12], c, cur, ch[c], ch[8 + c], ch[32 + (c >> 1)]);
+        qq_top_chains(mom, mom[12], S.P.m_top, S.P.mw, c, cur, ch[16 + c], ch[24 + c], ch[36 + (c >> 1)]);
     }
-    v = group_sum(v, 16);
-    if (live && (c & 15) == 0)
-        S.me_q[(uint64_t)(c >> 4) * S.count + e] = v;
+    __syncthreads();
+    double acc[2] = {0.0, 0.0};
+    if (live) {
+        const double eb = mom[12];
+        double ep[4], Q[4], kq[4], kp[4];
+        qq_linear_pol(mom + 8, c & 1, ep);
+        for (int mu = 0; mu < 4; ++mu) {
+            Q[mu] = mom[mu] + mom[4 + mu];
+            kq[mu] = mom[8 + mu] - Q[mu];
+            kp[mu] = mom[8 + mu];
+        }
+        kp[0] += 2.0 * eb;                        // k3 + P, P = (2 eb, 0, 0, 0)
+        const double pe = (2.0 * eb + Q[0]) * ep[0] - Q[1] * ep[1] - Q[2] * ep[2] - Q[3] * ep[3];
+        const double inv = 1.0 / (4.0 * eb * eb * qq_m2(Q));
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int b = (j << 1) | (c & 1);     // orientation j >> 1, quark spin j & 1
+            acc[j >> 1] += qq_config_from_chains(ch[b], ch[8 + b], ch[32 + (b >> 1)], ch[16 + c], ch[24 + c],
+                                                 ch[36 + (c >> 1)], ep, pe, kq, kp, inv);
+        }
+    }
+    const double f = group_sum(acc[0], 8);
+    const double r = group_sum(acc[1], 8);
+    if (live && c == 0) {
+        S.me_q[e] = f;
+        S.me_q[S.count + e] = r;
+    }
 }
 
 // q qbar -> t tbar g |M|^2 (g = 1) for explicit momenta [n][12] (t, tbar, g),

@@ -430,11 +430,11 @@ mf_status launch_stages(const mf::StageParams& S, int kin_blocks, int n_cu, hipS
         hipLaunchKernelGGL((mf::amp_kernel<NG, T, COL>), dim3(amp_grid), dim3(mf::kWave), 0, stream, S);
     MF_HIP(hipGetLastError());
     if (NG == 3 && S.P.pp) {
-        // the q qbar channel of t tbar g (FP64): 32 lanes per event
-        const uint64_t qb = (S.count * 32 + mf::kBlock - 1) / mf::kBlock;
+        // the q qbar channel of t tbar g (FP64): eight events per one-wave workgroup
+        const uint64_t qb = (S.count + mf::kQqEvents - 1) / mf::kQqEvents;
         if (qb > 0x7FFFFFFFull)
             return fail(MF_EINVAL, "too many events for one launch");
-        hipLaunchKernelGGL(mf::qqbar_ttxg_kernel, dim3((unsigned)qb), dim3(mf::kBlock), 0, stream, S);
+        hipLaunchKernelGGL(mf::qqbar_ttxg_kernel, dim3((unsigned)qb), dim3(mf::kWave), 0, stream, S);
         MF_HIP(hipGetLastError());
     }
     if (amp_end)

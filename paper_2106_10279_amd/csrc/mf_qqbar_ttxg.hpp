@@ -237,4 +237,144 @@ __host__ __device__ __forceinline__ double qqbar_ttxg_config(const double* __res
     return sum / 3.0;
 }
 
+// ---------------------------------------------------------------------------
+// Helicity recycling.  A1, A2 depend on the helicities only through the
+// quark-line chains X1 = vbar g^nu (pa - k3)-slash eps-slash u and
+// X2 = vbar eps-slash (k3 - pb)-slash g^nu u (beam orientation, quark spin,
+// gluon polarisation: 8 combinations) contracted with K (top and antitop
+// spins: 4); A3, A4 through the top-line chains Y3 = ubar eps-slash
+// S(k1 + k3) g^nu v and Y4 = ubar g^nu S(-k2 - k3) eps-slash v (top spins,
+// gluon polarisation: 8, the same for both orientations) contracted with J
+// (orientation, quark spin: 4).  The chains carry their denominators.
+// ---------------------------------------------------------------------------
+
+// Beam combination b = (orientation << 2) | (quark spin << 1) | gluon
+// polarisation: X1, X2 and, for the current J of (orientation, quark spin),
+// want_j; mom: t, tbar, g; eb = sqrt(s)/2.
+__host__ __device__ __forceinline__ void qq_beam_chains(const double* __restrict__ mom, double eb, int b,
+                                                        bool want_j, cplx<double>* X1, cplx<double>* X2,
+                                                        cplx<double>* J)
+{
+    const double* k1 = mom;
+    const double* k2 = mom + 4;
+    const double* k3 = mom + 8;
+    const int rev = b >> 2, sq = (b >> 1) & 1;
+    const double pz[4] = {eb, 0.0, 0.0, eb}, mz[4] = {eb, 0.0, 0.0, -eb};
+    const double* pa = rev ? mz : pz;
+    const double* pb = rev ? pz : mz;
+    cplx<double> a[4], bb[4], u[4], vb[4];
+    spinor_ubar<double>(pa, 0.0, sq, a);
+    spinor_v<double>(pb, 0.0, sq ^ 1, bb);
+    for (int i = 0; i < 4; ++i) {
+        u[i] = cplx<double>(a[(i + 2) & 3].x, -a[(i + 2) & 3].y);
+        vb[i] = cplx<double>(bb[(i + 2) & 3].x, -bb[(i + 2) & 3].y);
+    }
+    if (want_j)
+        bilinear(vb, u, J);
+    double ep[4];
+    qq_linear_pol(k3, b & 1, ep);
+    cplx<double> E[4], q[4], t[4], w[4];
+    qq_real(ep, E);
+    double Q[4];
+    for (int mu = 0; mu < 4; ++mu)
+        Q[mu] = k1[mu] + k2[mu];
+    const double s12 = qq_m2(Q);
+    double d[4];
+    for (int mu = 0; mu < 4; ++mu)
+        d[mu] = pa[mu] - k3[mu];
+    qq_slash_col(E, u, t);
+    qq_real(d, q);
+    qq_slash_col(q, t, w);
+    bilinear(vb, w, X1);
+    const double r1 = 1.0 / (qq_m2(d) * s12);
+    for (int mu = 0; mu < 4; ++mu)
+        d[mu] = k3[mu] - pb[mu];
+    qq_row_slash(vb, E, t);
+    qq_real(d, q);
+    qq_row_slash(t, q, w);
+    bilinear(w, u, X2);
+    const double r2 = 1.0 / (qq_m2(d) * s12);
+    for (int mu = 0; mu < 4; ++mu) {
+        X1[mu] = cplx<double>(X1[mu].x * r1, X1[mu].y * r1);
+        X2[mu] = cplx<double>(X2[mu].x * r2, X2[mu].y * r2);
+    }
+}
+
+// Top combination c = (top spin << 2) | (antitop spin << 1) | gluon
+// polarisation: Y3, Y4 (over s times the Breit-Wigner denominator) and, for
+// the current K of the two spins, want_k.
+__host__ __device__ __forceinline__ void qq_top_chains(const double* __restrict__ mom, double eb, double mt,
+                                                       double mw, int c, bool want_k, cplx<double>* Y3,
+                                                       cplx<double>* Y4, cplx<double>* K)
+{
+    const double* k1 = mom;
+    const double* k2 = mom + 4;
+    const double* k3 = mom + 8;
+    cplx<double> ub[4], v[4];
+    spinor_ubar<double>(k1, mt, (c >> 2) & 1, ub);
+    spinor_v<double>(k2, mt, (c >> 1) & 1, v);
+    if (want_k)
+        bilinear(ub, v, K);
+    double ep[4];
+    qq_linear_pol(k3, c & 1, ep);
+    cplx<double> E[4], q[4], t[4], w[4];
+    qq_real(ep, E);
+    const double s = 4.0 * eb * eb;
+    double d[4];
+    for (int mu = 0; mu < 4; ++mu)
+        d[mu] = k1[mu] + k3[mu];
+    qq_row_slash(ub, E, t);
+    qq_real(d, q);
+    qq_row_slash(t, q, w);
+    for (int i = 0; i < 4; ++i)
+        w[i] = cplx<double>(w[i].x + mt * t[i].x, w[i].y + mt * t[i].y);
+    bilinear(w, v, Y3);
+    cplx<double> r3 = qq_div(cplx<double>(1.0, 0.0), cplx<double>((qq_m2(d) - mt * mt) * s, mw * s));
+    for (int mu = 0; mu < 4; ++mu)
+        d[mu] = -k2[mu] - k3[mu];
+    qq_slash_col(E, v, t);
+    qq_real(d, q);
+    qq_slash_col(q, t, w);
+    for (int i = 0; i < 4; ++i)
+        w[i] = cplx<double>(w[i].x + mt * t[i].x, w[i].y + mt * t[i].y);
+    bilinear(ub, w, Y4);
+    cplx<double> r4 = qq_div(cplx<double>(1.0, 0.0), cplx<double>((qq_m2(d) - mt * mt) * s, mw * s));
+    for (int mu = 0; mu < 4; ++mu) {
+        Y3[mu] = cmul(Y3[mu], r3);
+        Y4[mu] = cmul(Y4[mu], r4);
+    }
+}
+
+// Colour-summed |M|^2 of one configuration from its chains: X1, X2, J of the
+// beam side, Y3, Y4, K of the top side, ep the gluon polarisation, pe =
+// (P + Q).eps, kq = k3 - Q, kp = k3 + P, inv = 1 / (s s12).
+__host__ __device__ __forceinline__ double qq_config_from_chains(const cplx<double>* X1, const cplx<double>* X2,
+                                                                 const cplx<double>* J, const cplx<double>* Y3,
+                                                                 const cplx<double>* Y4, const cplx<double>* K,
+                                                                 const double* ep, double pe, const double* kq,
+                                                                 const double* kp, double inv)
+{
+    cplx<double> B[5];
+    B[0] = qq_dot(X1, K);
+    B[1] = qq_dot(X2, K);
+    B[2] = qq_dot(Y3, J);
+    B[3] = qq_dot(Y4, J);
+    const cplx<double> jk = qq_dot(J, K), ke = qq_dotr(K, ep), je = qq_dotr(J, ep);
+    const cplx<double> jq = qq_dotr(J, kq), kpv = qq_dotr(K, kp);
+    const cplx<double> t1 = cmul(ke, jq), t2 = cmul(je, kpv);
+    B[4] = cplx<double>((jk.x * pe + t1.x - t2.x) * inv, (jk.y * pe + t1.y - t2.y) * inv);
+    constexpr double k3d[5][5] = {{8.0, -1.0, 7.0, -2.0, 9.0},
+                                  {-1.0, 8.0, -2.0, 7.0, -9.0},
+                                  {7.0, -2.0, 8.0, -1.0, 9.0},
+                                  {-2.0, 7.0, -1.0, 8.0, -9.0},
+                                  {9.0, -9.0, 9.0, -9.0, 18.0}};
+    double sum = 0.0;
+    for (int d = 0; d < 5; ++d) {
+        sum += k3d[d][d] * (B[d].x * B[d].x + B[d].y * B[d].y);
+        for (int e = d + 1; e < 5; ++e)
+            sum += 2.0 * k3d[d][e] * (B[d].x * B[e].x + B[d].y * B[e].y);
+    }
+    return sum / 3.0;
+}
+
 }  // namespace mf
