@@ -739,6 +739,12 @@ struct StageParams {
     double* pref_q;          // p p: J_V W L_qqbar / (2 s_hat); t tbar: [count], both beam orientations,
                              // t tbar g: [2][count], the quark from beam 1 / beam 2
     double* me_q;            // p p: q qbar |M|^2 summed over helicities and colours; [count] / [2][count]
+    // Optional list of the batch's events with a non-zero prefactor, in no
+    // particular order (kin_kernel appends, n_live cleared before it); the
+    // amplitude kernels of n_g <= 4 then take only these.  nullptr: all
+    // events in order.
+    unsigned* live = nullptr;
+    unsigned long long* n_live = nullptr;
 };
 
 template <int NF, bool PP = false>
@@ -769,19 +775,51 @@ __global__ void __launch_bounds__(kBlock) kin_kernel(StageParams S)
     }
     __syncthreads();
     const uint64_t n_chunks = (S.count + kWave - 1) / kWave;
-    for (uint64_t chunk = wave_id; chunk < n_chunks; chunk += P.n_waves) {
-        const uint64_t e = chunk * kWave + lane;
-        if (e >= S.count)
-            continue;
-        double pref, pq[2] = {0.0, 0.0};
-        const int flags = event_kinematics<NF>(P, S.first + e, s_rows, s_lx, s_lq, S.bins + e, S.count,
-                                               S.mom + e * (4 * NF + 1), pref, PP ? s_qrows : nullptr, pq);
-        S.pref[e] = pref;
-        S.flags[e] = (unsigned char)flags;
-        if constexpr (PP) {
-            S.pref_q[e] = pq[0];
-            if constexpr (NF == 3)
-                S.pref_q[S.count + e] = pq[1];
+    // a wave takes the chunks wave_id + k n_waves; kLiveBatch of them at a
+    // time, so that the live events of all of them are appended with one
+    // atomic (one counter for the whole batch)
+    constexpr int kLiveBatch = 8;
+    for (uint64_t c0 = wave_id; c0 < n_chunks; c0 += (uint64_t)kLiveBatch * P.n_waves) {
+        unsigned live = 0u;                       // bit t: the event of chunk t is live
+#pragma unroll 1
+        for (int t = 0; t < kLiveBatch; ++t) {
+            const uint64_t e = (c0 + (uint64_t)t * P.n_waves) * kWave + lane;
+            if (e < S.count) {
+                double pref, pq[2] = {0.0, 0.0};
+                const int flags = event_kinematics<NF>(P, S.first + e, s_rows, s_lx, s_lq, S.bins + e, S.count,
+                                                       S.mom + e * (4 * NF + 1), pref, PP ? s_qrows : nullptr, pq);
+                S.pref[e] = pref;
+                S.flags[e] = (unsigned char)flags;
+                if constexpr (PP) {
+                    S.pref_q[e] = pq[0];
+                    if constexpr (NF == 3)
+                        S.pref_q[S.count + e] = pq[1];
+                }
+                live |= (pref != 0.0 ? 1u : 0u) << t;
+            }
+        }
+        if (S.live) {
+            unsigned long long mask[kLiveBatch];
+            unsigned long long total = 0;
+#pragma unroll
+            for (int t = 0; t < kLiveBatch; ++t) {
+                mask[t] = __ballot((live >> t) & 1u);
+                total += (unsigned long long)__popcll(mask[t]);
+            }
+            if (total) {
+                unsigned long long base = 0;
+                if (lane == 0)
+                    base = atomicAdd(S.n_live, total);
+                base = __shfl(base, 0);
+                const unsigned long long below = (1ull << lane) - 1ull;
+#pragma unroll
+                for (int t = 0; t < kLiveBatch; ++t) {
+                    if ((live >> t) & 1u)
+                        S.live[base + __popcll(mask[t] & below)] =
+                            (unsigned)((c0 + (uint64_t)t * P.n_waves) * kWave + lane);
+                    base += (unsigned long long)__popcll(mask[t]);
+                }
+            }
         }
     }
 }
@@ -824,37 +862,46 @@ __device__ __forceinline__ void amp_quads_ng3(const StageParams& S)
     const int h0 = lane % L::kHel, sub = lane / L::kHel;      // helicity phase: 2 events x 32 lanes
     const int fq = lane / 16, fl0 = lane % 16;                // fill: 4 events x 16 lanes
     const int mq = lane / L::kMom, mk = lane % L::kMom;       // momenta: 4 events x 13 values
-    const uint64_t n_quads = (S.count + kQ - 1) / kQ;
+    // the events to evaluate: the live list, or all events in order
+    const uint64_t n_ev = S.live ? (uint64_t)*S.n_live : S.count;
+    const uint64_t n_quads = (n_ev + kQ - 1) / kQ;
     auto claim = [&]() -> uint64_t {
         unsigned long long c = 0;
         if (lane == 0)
             c = atomicAdd(S.next_group, (unsigned long long)kAmpChunk);
         return (uint64_t)__shfl(c, 0) / 2;   // pairs -> quads
     };
-    auto load = [&](uint64_t qd, double& pref, double& mc) {
-        const uint64_t ef = qd * kQ + fq, em = qd * kQ + mq;
+    auto event_of = [&](uint64_t i) -> uint64_t { return S.live ? (uint64_t)S.live[i] : i; };
+    // the fill lanes' event (S.count if none) and prefactor, the momenta lanes' value
+    auto load = [&](uint64_t qd, double& pref, double& mc, uint64_t& ef) {
+        const uint64_t i = qd * kQ + fq, im = qd * kQ + mq;
         pref = 0.0;
         mc = 0.0;
+        ef = S.count;
         if (qd < n_quads) {
-            if (ef < S.count)
+            if (i < n_ev) {
+                ef = event_of(i);
                 pref = S.pref[ef];
-            if (mq < kQ && em < S.count)
-                mc = S.mom[em * L::kMom + mk];
+            }
+            if (mq < kQ && im < n_ev)
+                mc = S.mom[event_of(im) * L::kMom + mk];
         }
     };
     uint64_t cur = claim();
     uint64_t nxt = claim();
     double pref_next, mc_next;
-    load(cur, pref_next, mc_next);
+    uint64_t ef_next;
+    load(cur, pref_next, mc_next, ef_next);
     int j = 0;
     while (cur < n_quads) {
         const uint64_t qd = cur + j;
         const double pref = pref_next, mc = mc_next;
+        const uint64_t ef = ef_next;
         const bool last_in_chunk = j + 1 == kAmpChunk / 2 || qd + 1 >= n_quads;
-        load(last_in_chunk ? nxt : qd + 1, pref_next, mc_next);
+        load(last_in_chunk ? nxt : qd + 1, pref_next, mc_next, ef_next);
         int h = h0, fl = fl0;
         asm volatile("" : "+v"(h), "+v"(fl));
-        const bool live_f = qd * kQ + fq < S.count && pref != 0.0;
+        const bool live_f = ef < S.count && pref != 0.0;
         if (__any(live_f)) {
             if (mq < kQ)
                 s_mom[mq][mk] = mc;
@@ -867,7 +914,7 @@ __device__ __forceinline__ void amp_quads_ng3(const StageParams& S)
             wave_sync();
             for (int pr = 0; pr < 2; ++pr) {
                 const int k = 2 * pr + sub;
-                const uint64_t e = qd * kQ + k;
+                const uint64_t e = __shfl(ef, 16 * k);
                 const double pe = __shfl(pref, 16 * k);
                 const bool live = e < S.count && pe != 0.0;
                 const bool any_live = __any(live);
@@ -950,7 +997,9 @@ __device__ __forceinline__ void amp_groups(const StageParams& S)
     T* obj = s_obj[sub];
     double* mom = s_mom[sub];
     T* cf = s_cf[sub];
-    const uint64_t n_groups = (S.count + L::kEventsPerPass - 1) / L::kEventsPerPass;
+    // the events to evaluate: the live list, or all events in order
+    const uint64_t n_ev = S.live ? (uint64_t)*S.n_live : S.count;
+    const uint64_t n_groups = (n_ev + L::kEventsPerPass - 1) / L::kEventsPerPass;
     // one lane claims a chunk with a vector atomic; the wave reads its value
     auto claim = [&]() -> uint64_t {
         unsigned long long c = 0;
@@ -958,30 +1007,34 @@ __device__ __forceinline__ void amp_groups(const StageParams& S)
             c = atomicAdd(S.next_group, (unsigned long long)kAmpChunk);
         return (uint64_t)__shfl(c, 0);
     };
-    auto load = [&](uint64_t g, double& pref, double& mc) {
-        const uint64_t e = g * L::kEventsPerPass + sub;
+    // slot `sub` of group g: its event (S.count if none), prefactor, momenta
+    auto load = [&](uint64_t g, double& pref, double& mc, uint64_t& ev) {
+        const uint64_t i = g * L::kEventsPerPass + sub;
         pref = 0.0;
         mc = 0.0;
-        if (g < n_groups && e < S.count) {
-            pref = S.pref[e];
+        ev = S.count;
+        if (g < n_groups && i < n_ev) {
+            ev = S.live ? (uint64_t)S.live[i] : i;
+            pref = S.pref[ev];
             if (h0 < L::kMom)
-                mc = S.mom[e * L::kMom + h0];
+                mc = S.mom[ev * L::kMom + h0];
         }
     };
     uint64_t cur = claim();
     uint64_t nxt = claim();
     double pref_next, mc_next;
-    load(cur, pref_next, mc_next);
+    uint64_t ev_next;
+    load(cur, pref_next, mc_next, ev_next);
     int j = 0;
     while (cur < n_groups) {
         const uint64_t g = cur + j;
         const double pref = pref_next, mc = mc_next;
+        const uint64_t e = ev_next;
         // the group after this one: in this chunk, or the first of the next
         const bool last_in_chunk = j + 1 == kAmpChunk || g + 1 >= n_groups;
-        load(last_in_chunk ? nxt : g + 1, pref_next, mc_next);
+        load(last_in_chunk ? nxt : g + 1, pref_next, mc_next, ev_next);
         int h = h0;
         asm volatile("" : "+v"(h));
-        const uint64_t e = g * L::kEventsPerPass + sub;
         const bool live = e < S.count && pref != 0.0;
         const bool any_live = __any(live);
         if (any_live) {
@@ -1383,7 +1436,9 @@ __global__ void __launch_bounds__(kWave) qqbar_ttxg_kernel(StageParams S)
     __shared__ __align__(16) cplx<double> s_ch[kQqEvents][40][4];
     const int lane = threadIdx.x;
     const int ev = lane >> 3, c = lane & 7;
-    const uint64_t e = (uint64_t)blockIdx.x * kQqEvents + ev;
+    const uint64_t i = (uint64_t)blockIdx.x * kQqEvents + ev;
+    const uint64_t n_ev = S.live ? (uint64_t)*S.n_live : S.count;
+    const uint64_t e = i < n_ev ? (S.live ? (uint64_t)S.live[i] : i) : S.count;
     const bool live = e < S.count && S.pref[e] != 0.0;
     double mom[13];
     if (live)

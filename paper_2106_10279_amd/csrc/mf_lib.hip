@@ -44,6 +44,12 @@ __global__ void zero_kernel(double* p, int n)
         p[i] = 0.0;
 }
 
+// Clears the live-event count of a batch before kin_kernel appends to it.
+__global__ void clear_count_kernel(unsigned long long* n)
+{
+    *n = 0ull;
+}
+
 mf_status fail(mf_status st, const std::string& msg)
 {
     g_error = msg;
@@ -102,6 +108,7 @@ struct Workspace {
     Buffer grid[2], log_x, log_q2, xf, partials, entries, iter_I, iter_V, iter_pass, stats, gpartials, gsum;
     Buffer st_mom, st_pref, st_me, st_bins, st_flags;   // per-event hand-over of the three-kernel form
     Buffer amp_counter;                                  // work counter of amp_kernel (8 bytes)
+    Buffer live_list, live_count;                        // live events of a batch (n_g <= 4) and their count
     Buffer st_amp;                                       // t tbar g g g: partial amplitudes of a batch
     Buffer xq, st_prefq, st_meq;                         // p p: quark tables; per-event q qbar prefactors, |M|^2
     Buffer uw_counts, uw_flags, uw_totals;               // unweighting: per-workgroup counts, keep flags, totals
@@ -143,6 +150,8 @@ struct Mem {
     unsigned short* st_bins = nullptr;
     unsigned char* st_flags = nullptr;
     unsigned long long* amp_counter = nullptr;
+    unsigned* live_list = nullptr;
+    unsigned long long* live_count = nullptr;
     void* st_amp = nullptr;
     double *xq = nullptr, *st_prefq = nullptr, *st_meq = nullptr;
 };
@@ -413,6 +422,10 @@ mf_status launch_stages(const mf::StageParams& S, int kin_blocks, int n_cu, hipS
                       : amp_grid_for<NG, T, COL>(n_groups, n_cu, &amp_grid);
     if (st != MF_OK)
         return st;
+    if (S.live) {
+        hipLaunchKernelGGL(clear_count_kernel, dim3(1), dim3(1), 0, stream, S.n_live);
+        MF_HIP(hipGetLastError());
+    }
     if constexpr (NG == 2 || NG == 3) {
         if (S.P.pp)
             hipLaunchKernelGGL((mf::kin_kernel<NG, true>), dim3(kin_blocks), dim3(mf::kBlock), 0, stream, S);
@@ -788,6 +801,10 @@ mf_status integrate_impl(const mf_process* proc, double sqrt_s, const mf_pdf_gri
             if ((st = ensure(ws.st_flags, b0)) != MF_OK) return st;
             if ((st = ensure(ws.amp_counter, sizeof(unsigned long long))) != MF_OK) return st;
             if (amp_bytes && (st = ensure(ws.st_amp, amp_bytes * b0)) != MF_OK) return st;
+            if (ng <= 4) {
+                if ((st = ensure(ws.live_list, sizeof(unsigned) * b0)) != MF_OK) return st;
+                if ((st = ensure(ws.live_count, sizeof(unsigned long long))) != MF_OK) return st;
+            }
             if (pp) {
                 const size_t orient = ng == 3 ? 2 : 1;   // t tbar g: both beam orientations
                 if ((st = ensure(ws.st_prefq, sizeof(double) * orient * b0)) != MF_OK) return st;
@@ -815,6 +832,8 @@ mf_status integrate_impl(const mf_process* proc, double sqrt_s, const mf_pdf_gri
         m.st_flags = (unsigned char*)ws.st_flags.ptr;
         m.amp_counter = (unsigned long long*)ws.amp_counter.ptr;
         m.st_amp = amp_bytes ? ws.st_amp.ptr : nullptr;
+        m.live_list = staged && ng <= 4 ? (unsigned*)ws.live_list.ptr : nullptr;
+        m.live_count = staged && ng <= 4 ? (unsigned long long*)ws.live_count.ptr : nullptr;
         m.st_prefq = pp ? (double*)ws.st_prefq.ptr : nullptr;
         m.st_meq = pp ? (double*)ws.st_meq.ptr : nullptr;
     }
@@ -903,6 +922,8 @@ mf_status integrate_impl(const mf_process* proc, double sqrt_s, const mf_pdf_gri
                 SP.amps = m.st_amp;
                 SP.pref_q = m.st_prefq;
                 SP.me_q = m.st_meq;
+                SP.live = m.live_list;
+                SP.n_live = m.live_count;
                 hipEvent_t a = nullptr, b = nullptr, c = nullptr, d = nullptr;
                 if (opt->profile) {
                     const size_t at = kMarks * ((size_t)j * n_batches + bi);
@@ -1202,6 +1223,10 @@ mf_status evaluate_staged(Setup& S, const mf_options* opt, uint64_t n)
         SP.amps = nullptr;
         SP.pref_q = (double*)ws.st_prefq.ptr;
         SP.me_q = (double*)ws.st_meq.ptr;
+        if ((st = ensure(ws.live_list, sizeof(unsigned) * batch)) != MF_OK) return st;
+        if ((st = ensure(ws.live_count, sizeof(unsigned long long))) != MF_OK) return st;
+        SP.live = (unsigned*)ws.live_list.ptr;
+        SP.n_live = (unsigned long long*)ws.live_count.ptr;
         SP.first_batch = 1;
     }
     for (uint64_t first = 0; first < n; first += batch) {
