@@ -983,23 +983,28 @@ template <int NG, typename T, int COL, bool PP = false>
 __device__ __forceinline__ void amp_groups(const StageParams& S)
 {
     using L = Layout<NG>;
-    __shared__ __align__(16) TabT<NG, T> s_tab[L::kEventsPerPass][L::kTable];
-    __shared__ __align__(16) T s_obj[L::kEventsPerPass][L::kObj];
-    __shared__ double s_mom[L::kEventsPerPass][L::kMom];
+    // lanes per event: t tbar evaluates two helicity configurations per lane
+    // (h and h + 8: the second gluon's polarisation), eight events per pass;
+    // the pair sum then the 8-lane tree is the 16-lane tree of one per lane
+    constexpr int kLanes = NG == 2 ? L::kHel / 2 : L::kHel;
+    constexpr int kPass = kLanes <= kWave ? kWave / kLanes : 1;
+    __shared__ __align__(16) TabT<NG, T> s_tab[kPass][L::kTable];
+    __shared__ __align__(16) T s_obj[kPass][L::kObj];
+    __shared__ double s_mom[kPass][L::kMom];
     // colour factors of the sampled assignment (COL = 2: re and im per
     // ordering) or flow (COL = 3: one real value per ordering)
     constexpr int kCf = COL >= 2 ? 2 * (NG == 3 ? 6 : 24) : 2;
-    __shared__ __align__(16) T s_cf[L::kEventsPerPass][kCf];
+    __shared__ __align__(16) T s_cf[kPass][kCf];
     const int lane = threadIdx.x;
-    const int h0 = lane % L::kHel;
-    const int sub = lane / L::kHel;
+    const int h0 = lane % kLanes;
+    const int sub = lane / kLanes;
     TabT<NG, T>* tab = s_tab[sub];
     T* obj = s_obj[sub];
     double* mom = s_mom[sub];
     T* cf = s_cf[sub];
     // the events to evaluate: the live list, or all events in order
     const uint64_t n_ev = S.live ? (uint64_t)*S.n_live : S.count;
-    const uint64_t n_groups = (n_ev + L::kEventsPerPass - 1) / L::kEventsPerPass;
+    const uint64_t n_groups = (n_ev + kPass - 1) / kPass;
     // one lane claims a chunk with a vector atomic; the wave reads its value
     auto claim = [&]() -> uint64_t {
         unsigned long long c = 0;
@@ -1008,31 +1013,35 @@ __device__ __forceinline__ void amp_groups(const StageParams& S)
         return (uint64_t)__shfl(c, 0);
     };
     // slot `sub` of group g: its event (S.count if none), prefactor, momenta
-    auto load = [&](uint64_t g, double& pref, double& mc, uint64_t& ev) {
-        const uint64_t i = g * L::kEventsPerPass + sub;
+    // (values h0 and h0 + kLanes of the kMom stored per event)
+    auto load = [&](uint64_t g, double& pref, double& mc, double& mc2, uint64_t& ev) {
+        const uint64_t i = g * kPass + sub;
         pref = 0.0;
         mc = 0.0;
+        mc2 = 0.0;
         ev = S.count;
         if (g < n_groups && i < n_ev) {
             ev = S.live ? (uint64_t)S.live[i] : i;
             pref = S.pref[ev];
             if (h0 < L::kMom)
                 mc = S.mom[ev * L::kMom + h0];
+            if (h0 + kLanes < L::kMom)
+                mc2 = S.mom[ev * L::kMom + h0 + kLanes];
         }
     };
     uint64_t cur = claim();
     uint64_t nxt = claim();
-    double pref_next, mc_next;
+    double pref_next, mc_next, mc2_next;
     uint64_t ev_next;
-    load(cur, pref_next, mc_next, ev_next);
+    load(cur, pref_next, mc_next, mc2_next, ev_next);
     int j = 0;
     while (cur < n_groups) {
         const uint64_t g = cur + j;
-        const double pref = pref_next, mc = mc_next;
+        const double pref = pref_next, mc = mc_next, mc2 = mc2_next;
         const uint64_t e = ev_next;
         // the group after this one: in this chunk, or the first of the next
         const bool last_in_chunk = j + 1 == kAmpChunk || g + 1 >= n_groups;
-        load(last_in_chunk ? nxt : g + 1, pref_next, mc_next, ev_next);
+        load(last_in_chunk ? nxt : g + 1, pref_next, mc_next, mc2_next, ev_next);
         int h = h0;
         asm volatile("" : "+v"(h));
         const bool live = e < S.count && pref != 0.0;
@@ -1040,6 +1049,8 @@ __device__ __forceinline__ void amp_groups(const StageParams& S)
         if (any_live) {
             if (h0 < L::kMom)
                 mom[h0] = mc;
+            if (h0 + kLanes < L::kMom)
+                mom[h0 + kLanes] = mc2;
             wave_sync();
             if (live) {
                 fill_table<NG, T>(mom, mom[L::kMom - 1], S.P.m_top, S.P.mw, tab, obj, h);
@@ -1059,14 +1070,25 @@ __device__ __forceinline__ void amp_groups(const StageParams& S)
             double v = event_me2<NG, T, COL>(tab, obj, h, S.P.m_top, live, any_live, cf);
             if (S.P.hel_mc && live)
                 v = hel_sampled<L::kHel>(v, h, S.first + e, S.P.seed, S.P.iter);
-            v = group_sum(v, L::kHel);
+            if constexpr (NG == 2) {
+                // one configuration after the other: interleaving the two
+                // chains only adds register pressure
+                __builtin_amdgcn_sched_barrier(0);
+                double v2 = event_me2<NG, T, COL>(tab, obj, h + kLanes, S.P.m_top, live, any_live, cf);
+                if (S.P.hel_mc && live)
+                    v2 = hel_sampled<L::kHel>(v2, h + kLanes, S.first + e, S.P.seed, S.P.iter);
+                v += v2;
+            }
+            v = group_sum(v, kLanes);
             if (h == 0 && live)
                 S.me[e] = v;
             if constexpr (PP) {
-                // p p: the q qbar channel of the same event, one helicity
-                // configuration per lane (16 of them, like g g)
-                double q = live ? qqbar_me2_config(mom, mom[L::kMom - 1], S.P.m_top, h) : 0.0;
-                q = group_sum(q, L::kHel);
+                // p p: the q qbar channel of the same event, configurations h
+                // and h + 8 of the lane (16 of them, like g g)
+                double q = live ? qqbar_me2_config(mom, mom[L::kMom - 1], S.P.m_top, h) +
+                                      qqbar_me2_config(mom, mom[L::kMom - 1], S.P.m_top, h + kLanes)
+                                : 0.0;
+                q = group_sum(q, kLanes);
                 if (h == 0 && live)
                     S.me_q[e] = q;
             }
@@ -1085,7 +1107,7 @@ __device__ __forceinline__ void amp_groups(const StageParams& S)
 // The amplitude kernel: quads of events for t tbar g, single events for t tbar g g.
 // PP (n_g = 2 only): p p, the q qbar channel evaluated alongside g g.
 template <int NG, typename T, int COL = 0, bool PP = false>
-__global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 || NG <= 3 ? 4 : 2))) amp_kernel(StageParams S)
+__global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 || NG == 3 ? 4 : (NG == 2 ? 3 : 2)))) amp_kernel(StageParams S)
 {
     static_assert(!PP || NG == 2, "the q qbar channel runs with n_g = 2");
     if constexpr (NG == 3)
