@@ -44,21 +44,15 @@ __device__ __forceinline__ double hermite_dv(const double* t, const double* f, i
             d11 * h * knot_slope(t, f, i + 1, last)) / h;
 }
 
-// x g(x) at mu_F and its derivative in ln x.  The interpolation in ln Q^2 is
-// linear in the row values, so the derivative interpolates the row
-// derivatives with the same weights.
-__device__ __forceinline__ void pdf_xg_dlnx(const EventParams& P, const double* rows, const double* lx_knots,
-                                            const double* lq_knots, double x, double& G, double& dG)
+// x g(x) at mu_F and its derivative in ln x, from the row staged at mu_F^2
+// (stage_pdf_row): the derivative of the same cubic.
+__device__ __forceinline__ void pdf_xg_dlnx(const EventParams& P, const double* row, const double* lx_knots,
+                                            double x, double& G, double& dG)
 {
     const double lx = log(x);
     const int k = find_interval(lx_knots, P.n_x, lx);
-    double rv[4], rd[4];
-    for (int r = 0; r < P.q2_rows; ++r) {
-        rv[r] = hermite(lx_knots, rows + r * P.n_x, k, P.n_x - 1, lx);
-        rd[r] = hermite_dv(lx_knots, rows + r * P.n_x, k, P.n_x - 1, lx);
-    }
-    G = hermite(lq_knots, rv, P.q2_interval - P.q2_first, P.q2_rows - 1, P.log_muf2);
-    dG = hermite(lq_knots, rd, P.q2_interval - P.q2_first, P.q2_rows - 1, P.log_muf2);
+    G = hermite(lx_knots, row, k, P.n_x - 1, lx);
+    dG = hermite_dv(lx_knots, row, k, P.n_x - 1, lx);
 }
 
 __global__ void __launch_bounds__(kBlock) grad_kernel_ttx(GradParams G)
@@ -66,18 +60,14 @@ __global__ void __launch_bounds__(kBlock) grad_kernel_ttx(GradParams G)
     constexpr int D = 4;
     const EventParams& P = G.P;
     __shared__ double s_lx[kMaxPdfX];
-    __shared__ double s_rows[4 * kMaxPdfX];
-    __shared__ double s_lq[4];
+    __shared__ double s_row[kMaxPdfX];
     const int tid = threadIdx.x;
     const int lane = tid % kWave;
     const int wave_id = blockIdx.x * kWavesPerBlock + tid / kWave;
     const int nb = P.n_bins;
     for (int i = tid; i < P.n_x; i += kBlock)
         s_lx[i] = P.log_x[i];
-    for (int i = tid; i < P.q2_rows * P.n_x; i += kBlock)
-        s_rows[i] = P.xf[(size_t)P.q2_first * P.n_x + i];
-    if (tid < P.q2_rows)
-        s_lq[tid] = P.log_q2[P.q2_first + tid];
+    stage_pdf_row(P, P.xf, s_row, tid, kBlock);
     __syncthreads();
 
     Neumaier sm{0.0, 0.0}, sa{0.0, 0.0};
@@ -126,8 +116,8 @@ __global__ void __launch_bounds__(kBlock) grad_kernel_ttx(GradParams G)
         if (shat > thr * thr && phase_space<2>(x + 2, sqrt(shat), m, P.max_newton, P.ps_const, k, W)) {
             const double rs = sqrt(shat);
             double G1, dG1, G2, dG2;
-            pdf_xg_dlnx(P, s_rows, s_lx, s_lq, x1, G1, dG1);
-            pdf_xg_dlnx(P, s_rows, s_lx, s_lq, x2, G2, dG2);
+            pdf_xg_dlnx(P, s_row, s_lx, x1, G1, dG1);
+            pdf_xg_dlnx(P, s_row, s_lx, x2, G2, dG2);
             const double f1 = G1 / x1, f2 = G2 / x2;
             const double pref = jac * W * f1 * f2 / (2.0 * shat);
             // ---- forward |M|^2 with its reverse sweep (seed d w / d|M|^2) ----

@@ -323,34 +323,43 @@ __device__ __forceinline__ int find_interval(const double* knots, int n, double 
     return lo;
 }
 
-// rows: LDS [q2_rows][n_x]; lx_knots: LDS [n_x]; q2 knots of the staged rows: LDS.
-__device__ __forceinline__ double pdf_xg(const EventParams& P, const double* rows, const double* lx_knots,
-                                         const double* lq_knots, double x)
+// The table's values at mu_F^2 on every x knot, staged once per workgroup:
+// the cubic Hermite interpolation in ln Q^2 over the four bracketing Q^2 rows
+// is done per knot, so an event interpolates in ln x only.  Both steps are
+// linear in the table values along their own axis (the knot slopes too), so
+// taking ln Q^2 first gives the same interpolant as taking ln x first.
+// xf: [n_q2][n_x] in device memory, row: [n_x] in LDS.
+__device__ __forceinline__ void stage_pdf_row(const EventParams& P, const double* __restrict__ xf, double* row,
+                                              int tid, int nthreads)
 {
-    const double lx = log(x);
-    const int k = find_interval(lx_knots, P.n_x, lx);
-    double rv[4];
+    double lq[4], rv[4];
     for (int r = 0; r < P.q2_rows; ++r)
-        rv[r] = hermite(lx_knots, rows + r * P.n_x, k, P.n_x - 1, lx);
-    return hermite(lq_knots, rv, P.q2_interval - P.q2_first, P.q2_rows - 1, P.log_muf2);
+        lq[r] = P.log_q2[P.q2_first + r];
+    for (int i = tid; i < P.n_x; i += nthreads) {
+        for (int r = 0; r < P.q2_rows; ++r)
+            rv[r] = xf[(size_t)(P.q2_first + r) * P.n_x + i];
+        row[i] = hermite(lq, rv, P.q2_interval - P.q2_first, P.q2_rows - 1, P.log_muf2);
+    }
 }
 
-// The four quark tables (u, ubar, d, dbar; rows of table f at f * q2_rows * n_x)
-// at one x: one logarithm and one interval search for all of them, each
-// value as pdf_xg computes it, divided by x.
-__device__ __forceinline__ void pdf_xq4(const EventParams& P, const double* rows, const double* lx_knots,
-                                        const double* lq_knots, double x, double* q)
+// x g(x, mu_F^2) from the staged row; lx_knots: LDS [n_x].
+__device__ __forceinline__ double pdf_xg(const EventParams& P, const double* row, const double* lx_knots, double x)
 {
     const double lx = log(x);
     const int k = find_interval(lx_knots, P.n_x, lx);
-    const int rs = P.q2_rows * P.n_x;
-#pragma unroll 1
-    for (int f = 0; f < 4; ++f) {
-        double rv[4];
-        for (int r = 0; r < P.q2_rows; ++r)
-            rv[r] = hermite(lx_knots, rows + f * rs + r * P.n_x, k, P.n_x - 1, lx);
-        q[f] = hermite(lq_knots, rv, P.q2_interval - P.q2_first, P.q2_rows - 1, P.log_muf2) / x;
-    }
+    return hermite(lx_knots, row, k, P.n_x - 1, lx);
+}
+
+// The four quark tables (u, ubar, d, dbar; staged rows at f * n_x) at one x:
+// one logarithm and one interval search for all of them, divided by x.
+__device__ __forceinline__ void pdf_xq4(const EventParams& P, const double* rows, const double* lx_knots, double x,
+                                        double* q)
+{
+    const double lx = log(x);
+    const int k = find_interval(lx_knots, P.n_x, lx);
+#pragma unroll
+    for (int f = 0; f < 4; ++f)
+        q[f] = hermite(lx_knots, rows + f * P.n_x, k, P.n_x - 1, lx) / x;
 }
 
 // Reduce v over groups of `width` consecutive lanes; lane 0 of each group
@@ -490,8 +499,8 @@ __device__ __forceinline__ double draw_point(const EventParams& P, uint64_t ev, 
 // mom is untouched.  bins[d * bin_stride] receives the bin of dimension d;
 // k53_out, bins_out and record of P are written if set.
 template <int NF>
-__device__ __forceinline__ int event_kinematics(const EventParams& P, uint64_t ev, const double* s_rows,
-                                                const double* s_lx, const double* s_lq, unsigned short* bins,
+__device__ __forceinline__ int event_kinematics(const EventParams& P, uint64_t ev, const double* s_row,
+                                                const double* s_lx, unsigned short* bins,
                                                 size_t bin_stride, double* mom, double& pref,
                                                 const double* s_qrows = nullptr, double* pref_q = nullptr)
 {
@@ -513,8 +522,8 @@ __device__ __forceinline__ int event_kinematics(const EventParams& P, uint64_t e
             const double y_boost = 0.5 * log(x1 / x2);
             if (pass_cuts<NF>(k, y_boost, P.ptmin, P.etamax, P.drmin)) {
                 flags |= 4;
-                f1 = pdf_xg(P, s_rows, s_lx, s_lq, x1) / x1;
-                f2 = pdf_xg(P, s_rows, s_lx, s_lq, x2) / x2;
+                f1 = pdf_xg(P, s_row, s_lx, x1) / x1;
+                f2 = pdf_xg(P, s_row, s_lx, x2) / x2;
                 pref = jac * W * f1 * f2 / (2.0 * shat);
                 if (s_qrows && pref != 0.0) {
                     // q qbar luminosities, number densities: the quark from beam 1
@@ -523,8 +532,8 @@ __device__ __forceinline__ int event_kinematics(const EventParams& P, uint64_t e
                     // (symmetric under t <-> u at tree level) and one prefactor
                     // carries both; for t tbar g they differ.
                     double q1[4], q2[4];
-                    pdf_xq4(P, s_qrows, s_lx, s_lq, x1, q1);
-                    pdf_xq4(P, s_qrows, s_lx, s_lq, x2, q2);
+                    pdf_xq4(P, s_qrows, s_lx, x1, q1);
+                    pdf_xq4(P, s_qrows, s_lx, x2, q2);
                     const double lf = q1[0] * q2[1] + q1[2] * q2[3];
                     const double lr = q1[1] * q2[0] + q1[3] * q2[2];
                     if constexpr (NF == 2) {
@@ -577,8 +586,7 @@ event_kernel(EventParams P)
     __shared__ double s_me[kWavesPerBlock][kWave];
     __shared__ unsigned short s_bin[kWavesPerBlock][D][kWave];
     __shared__ double s_lx[kMaxPdfX];
-    __shared__ double s_rows[4 * kMaxPdfX];
-    __shared__ double s_lq[4];
+    __shared__ double s_row[kMaxPdfX];
     __shared__ __align__(16) TabT<NG, T> s_tab[kWavesPerBlock][L::kEventsPerPass][L::kTable];
     __shared__ __align__(16) T s_obj[kWavesPerBlock][L::kEventsPerPass][L::kObj];
     extern __shared__ double s_hist[];     // [kWavesPerBlock][D][n_bins]
@@ -589,13 +597,10 @@ event_kernel(EventParams P)
     const int wave_id = blockIdx.x * kWavesPerBlock + wv;
     const int nb = P.n_bins;
 
-    // Stage ln x knots and the Q^2 stencil rows of the PDF table in LDS.
+    // Stage ln x knots and the PDF table at mu_F^2 in LDS.
     for (int i = tid; i < P.n_x; i += kBlock)
         s_lx[i] = P.log_x[i];
-    for (int i = tid; i < P.q2_rows * P.n_x; i += kBlock)
-        s_rows[i] = P.xf[(size_t)P.q2_first * P.n_x + i];
-    if (tid < P.q2_rows)
-        s_lq[tid] = P.log_q2[P.q2_first + tid];
+    stage_pdf_row(P, P.xf, s_row, tid, kBlock);
     double* hist = s_hist + (size_t)wv * D * nb;
     if (P.partials)
         for (int i = lane; i < D * nb; i += kWave)
@@ -614,7 +619,7 @@ event_kernel(EventParams P)
         double pref = 0.0;
         double* mom = s_mom[wv][lane];
         if (active) {
-            const int flags = event_kinematics<NF>(P, ev, s_rows, s_lx, s_lq, &s_bin[wv][0][lane], kWave, mom, pref);
+            const int flags = event_kinematics<NF>(P, ev, s_row, s_lx, &s_bin[wv][0][lane], kWave, mom, pref);
             if (flags & 4)
                 npass += 1.0;
             if (flags & 2)
@@ -752,9 +757,8 @@ __global__ void __launch_bounds__(kBlock) kin_kernel(StageParams S)
 {
     const EventParams& P = S.P;
     __shared__ double s_lx[kMaxPdfX];
-    __shared__ double s_rows[4 * kMaxPdfX];
-    __shared__ double s_qrows[PP ? 4 * 4 * kMaxPdfX : 1];   // p p: the quark tables' Q^2 rows
-    __shared__ double s_lq[4];
+    __shared__ double s_row[kMaxPdfX];
+    __shared__ double s_qrows[PP ? 4 * kMaxPdfX : 1];   // p p: the quark tables at mu_F^2
     const int tid = threadIdx.x;
     const int lane = tid % kWave;
     const int wave_id = blockIdx.x * kWavesPerBlock + tid / kWave;
@@ -762,16 +766,10 @@ __global__ void __launch_bounds__(kBlock) kin_kernel(StageParams S)
         *S.next_group = 0ull;
     for (int i = tid; i < P.n_x; i += kBlock)
         s_lx[i] = P.log_x[i];
-    for (int i = tid; i < P.q2_rows * P.n_x; i += kBlock)
-        s_rows[i] = P.xf[(size_t)P.q2_first * P.n_x + i];
-    if (tid < P.q2_rows)
-        s_lq[tid] = P.log_q2[P.q2_first + tid];
+    stage_pdf_row(P, P.xf, s_row, tid, kBlock);
     if constexpr (PP) {
-        const int rs = P.q2_rows * P.n_x;
-        for (int i = tid; i < 4 * rs; i += kBlock) {
-            const int f = i / rs, r = i % rs;
-            s_qrows[i] = P.xq[((size_t)f * P.n_q2 + P.q2_first) * P.n_x + r];
-        }
+        for (int f = 0; f < 4; ++f)
+            stage_pdf_row(P, P.xq + (size_t)f * P.n_q2 * P.n_x, s_qrows + f * P.n_x, tid, kBlock);
     }
     __syncthreads();
     const uint64_t n_chunks = (S.count + kWave - 1) / kWave;
@@ -786,7 +784,7 @@ __global__ void __launch_bounds__(kBlock) kin_kernel(StageParams S)
             const uint64_t e = (c0 + (uint64_t)t * P.n_waves) * kWave + lane;
             if (e < S.count) {
                 double pref, pq[2] = {0.0, 0.0};
-                const int flags = event_kinematics<NF>(P, S.first + e, s_rows, s_lx, s_lq, S.bins + e, S.count,
+                const int flags = event_kinematics<NF>(P, S.first + e, s_row, s_lx, S.bins + e, S.count,
                                                        S.mom + e * (4 * NF + 1), pref, PP ? s_qrows : nullptr, pq);
                 S.pref[e] = pref;
                 S.flags[e] = (unsigned char)flags;
