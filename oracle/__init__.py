@@ -14,4 +14,5 @@ from .oracle import (  # noqa: F401
     flow_count, flow_code, flow_weight, flow_total, flow_config, flow_factors, me2_sum_colour_flow, me2_sum_sampled,
     hel_count, hel_config, me2_hel, colour_matrix_relabel, dressed_amplitude, pdf_xq, me2_qqbar_ttx,
     qqbar_ttxg_diagrams, qqbar_ttxg_colour, me2_qqbar_ttxg,
+    qqbar_ttxgg_terms, qqbar_ttxgg_colour, qqbar_ttxgg_colour_matrix, me2_qqbar_ttxgg,
 )

@@ -1546,3 +1546,536 @@ double mfo_me2_qqbar_ttxg(const double *p, double m, double width)
     }
     return total;
 }
+
+/* ------------------------------------------------------------------------ */
+/* q qbar -> t tbar g g (the q qbar channel of p p -> t tbar g g, Sec. 3)    */
+/* ------------------------------------------------------------------------ */
+/* The 36 Feynman diagrams, written out by where the two gluons attach, with
+ * the rules above (g = 1).  The quark line vbar(pb) ... u(pa) and the top
+ * line ubar(k1) ... v(k2) are joined by one gluon, the spine.  Each line is
+ * a chain of vertices from its column end; an attachment emits momentum q
+ * (external gluon: k; spine, seen from the quark line: the momentum it
+ * carries to the top side; seen from the top line: minus that; the pair
+ * g1 g2 joined by a three-gluon vertex, "composite": K = k3 + k4).
+ *   1  both gluons on the quark line, 3! orders              (6)
+ *   2  both on the top line                                   (6)
+ *   3  one on each line, 2 x 2 orders, 2 assignments          (8)
+ *   4  one on the spine (three-gluon vertex), one on the quark line (4)
+ *   5  one on the spine, one on the top line                  (4)
+ *   6  both on the spine: two three-gluon vertices in either order (2),
+ *      or the four-gluon vertex (its three colour structures counted as
+ *      three terms)
+ *   7  the composite on the quark line (2), the top line (2), the spine (1)
+ * Counting the factors i of vertices and propagators, classes 1-3 carry i,
+ * classes 4, 5 and 7 (on a line) -1, class 6 and 7 (on the spine) -i; the
+ * common factor i is dropped, so the relative factors are 1, i and -1.
+ * Three-gluon vertex with the spine current J (colour c, momentum P into
+ * the vertex), a gluon (colour a, polarisation e, momentum k out of it) and
+ * the continuing spine (colour c', momentum P - k): colour f^{c a c'},
+ * current (J.e)(P + k) + e J.(P - 2k) + J e.(k - 2P).  The composite:
+ * colour f^{e a1 a2}, current [eps1 eps2.(K + k3) + eps1.eps2 (k4 - k3)
+ * - eps2 eps1.(K + k4)] / K^2.  Four-gluon vertex (spine in: colour c_q,
+ * gluons a1, a2, spine out: c_t, internal e): f^{c_q a1 e} f^{a2 c_t e}
+ * [Xq.eps2 eps1.Xt - Xq.Xt eps1.eps2] + f^{c_q a2 e} f^{a1 c_t e}
+ * [Xq.eps1 eps2.Xt - Xq.Xt eps1.eps2] + f^{c_q c_t e} f^{a1 a2 e}
+ * [Xq.eps1 eps2.Xt - Xq.eps2 eps1.Xt], times -i.                           */
+
+#define Q4_TERMS 38
+
+typedef struct {
+    double q[4];      /* outgoing momentum */
+    cplx e[4];        /* polarisation or off-shell current (unused if open) */
+    int open;         /* the line's free index (the spine) */
+} q4_att;
+
+/* colour slots: 0, 1 the gluons' adjoint indices a1, a2; 2 + x internal index x */
+typedef struct {
+    int nq, qs[3];    /* quark line, from the u end */
+    int nt, ts[3];    /* top line, from the v end */
+    int nf, f[3][3];  /* structure constants f^{xyz} */
+    int nint;
+} q4_colour;
+
+/* X^mu = row V_{n-1} S(P_{n-1}) ... S(P_1) V_0 col, V_t = e_t-slash except
+ * the open attachment, which carries gamma^mu; P_t = p0 - q_0 - ... - q_{t-1}. */
+static void q4_line(const cplx *row, const cplx *col, const double *p0, double m, double width, int n,
+                    const q4_att *att, cplx *X)
+{
+    int s = 0;
+    while (!att[s].open)
+        ++s;
+    double P[4];
+    memcpy(P, p0, sizeof(P));
+    cplx R[4], t[4], S[4][4], E[4][4];
+    memcpy(R, col, sizeof(R));
+    for (int a = 0; a < s; ++a) {
+        slash(att[a].e, E);
+        qq_mat_col(E, R, t);
+        for (int mu = 0; mu < 4; ++mu)
+            P[mu] -= att[a].q[mu];
+        qq_propagator(P, m, width, S);
+        qq_mat_col(S, t, R);
+    }
+    /* momentum after the open attachment, then the left part */
+    for (int mu = 0; mu < 4; ++mu)
+        P[mu] -= att[s].q[mu];
+    double Pt[3][4];
+    for (int a = s + 1; a < n; ++a) {
+        memcpy(Pt[a - s - 1], P, sizeof(P));   /* the segment between a - 1 and a */
+        for (int mu = 0; mu < 4; ++mu)
+            P[mu] -= att[a].q[mu];
+    }
+    cplx L[4];
+    memcpy(L, row, sizeof(L));
+    for (int a = n - 1; a > s; --a) {
+        slash(att[a].e, E);
+        row_times(L, E, t);
+        qq_propagator(Pt[a - s - 1], m, width, S);
+        row_times(t, S, L);
+    }
+    qq_vec_current(L, R, X);
+}
+
+static cplx q4_dot(const cplx *a, const cplx *b)
+{
+    return a[0] * b[0] - a[1] * b[1] - a[2] * b[2] - a[3] * b[3];
+}
+
+/* three-gluon vertex: J (momentum P in), e (momentum k out) -> continuing current */
+static void q4_v3(const cplx *J, const double *P, const cplx *e, const double *k, cplx *out)
+{
+    cplx Pk[4], P2k[4], k2P[4];
+    for (int mu = 0; mu < 4; ++mu) {
+        Pk[mu] = P[mu] + k[mu];
+        P2k[mu] = P[mu] - 2.0 * k[mu];
+        k2P[mu] = k[mu] - 2.0 * P[mu];
+    }
+    cplx je = q4_dot(J, e), jp = q4_dot(J, P2k), ek = q4_dot(e, k2P);
+    for (int mu = 0; mu < 4; ++mu)
+        out[mu] = je * Pk[mu] + e[mu] * jp + J[mu] * ek;
+}
+
+static void q4_set_colour(q4_colour *c, int nq, const int *qs, int nt, const int *ts, int nf, const int (*f)[3],
+                          int nint)
+{
+    memset(c, 0, sizeof(*c));
+    c->nq = nq;
+    for (int i = 0; i < nq; ++i)
+        c->qs[i] = qs[i];
+    c->nt = nt;
+    for (int i = 0; i < nt; ++i)
+        c->ts[i] = ts[i];
+    c->nf = nf;
+    for (int i = 0; i < nf; ++i)
+        for (int j = 0; j < 3; ++j)
+            c->f[i][j] = f[i][j];
+    c->nint = nint;
+}
+
+static double q4_m2(const double *p)
+{
+    return p[0] * p[0] - p[1] * p[1] - p[2] * p[2] - p[3] * p[3];
+}
+
+/* The 38 terms (Lorentz part with its relative factor, colour structure) of
+ * helicity configuration hel[6] = (quark, antiquark, top, antitop spin,
+ * gluon 1, gluon 2 helicity); ward = 1 or 2 replaces that gluon's
+ * polarisation by its momentum.  p: [6][4] all outgoing: t, tbar, -pa,
+ * -pb, g1, g2.  Returns the number of terms. */
+static int q4_terms(const double *p, double m, double width, const int *hel, int ward, cplx *A, q4_colour *C)
+{
+    init_gamma();
+    double k1[4], k2[4], pa[4], pb[4], kg[2][4];
+    for (int mu = 0; mu < 4; ++mu) {
+        k1[mu] = p[mu];
+        k2[mu] = p[4 + mu];
+        pa[mu] = -p[8 + mu];
+        pb[mu] = -p[12 + mu];
+        kg[0][mu] = p[16 + mu];
+        kg[1][mu] = p[20 + mu];
+    }
+    cplx u[4], vb[4], ub[4], v[4], eps[2][4];
+    spinor_u(pa, 0.0, hel[0], u);
+    spinor_vbar(pb, 0.0, hel[1], vb);
+    spinor_ubar(k1, m, hel[2], ub);
+    spinor_v(k2, m, hel[3], v);
+    for (int g = 0; g < 2; ++g) {
+        if (ward == g + 1)
+            for (int mu = 0; mu < 4; ++mu)
+                eps[g][mu] = kg[g][mu];
+        else
+            polarisation(kg[g], hel[4 + g], eps[g]);
+    }
+    double P0[4], Q[4], K[4], mk2[4];
+    for (int mu = 0; mu < 4; ++mu) {
+        P0[mu] = pa[mu] + pb[mu];
+        Q[mu] = k1[mu] + k2[mu];
+        K[mu] = kg[0][mu] + kg[1][mu];
+        mk2[mu] = -k2[mu];
+    }
+    /* the composite g1 g2 current (colour f^{e a1 a2}) */
+    cplx J12[4];
+    {
+        double Kk3[4], k43[4], Kk4[4];
+        for (int mu = 0; mu < 4; ++mu) {
+            Kk3[mu] = K[mu] + kg[0][mu];
+            k43[mu] = kg[1][mu] - kg[0][mu];
+            Kk4[mu] = K[mu] + kg[1][mu];
+        }
+        cplx a = q4_dot(eps[1], (cplx[4]){ Kk3[0], Kk3[1], Kk3[2], Kk3[3] });
+        cplx b = q4_dot(eps[0], eps[1]);
+        cplx c = q4_dot(eps[0], (cplx[4]){ Kk4[0], Kk4[1], Kk4[2], Kk4[3] });
+        double K2 = q4_m2(K);
+        for (int mu = 0; mu < 4; ++mu)
+            J12[mu] = (eps[0][mu] * a + b * k43[mu] - eps[1][mu] * c) / K2;
+    }
+    int n = 0;
+    q4_att qa[3], ta[3];
+    cplx Xq[4], Xt[4], J1[4], J2[4];
+    const cplx I1 = I;
+    static const int perm3[6][3] = { { 0, 1, 2 }, { 0, 2, 1 }, { 1, 0, 2 }, { 1, 2, 0 }, { 2, 0, 1 }, { 2, 1, 0 } };
+    /* attachment builders */
+#define Q4_GLUON(att, g) do { memcpy((att).q, kg[g], sizeof(double) * 4); memcpy((att).e, eps[g], sizeof(cplx) * 4); (att).open = 0; } while (0)
+#define Q4_COMP(att) do { memcpy((att).q, K, sizeof(double) * 4); memcpy((att).e, J12, sizeof(cplx) * 4); (att).open = 0; } while (0)
+#define Q4_SPINE(att, qq) do { for (int mu_ = 0; mu_ < 4; ++mu_) (att).q[mu_] = (qq)[mu_]; (att).open = 1; } while (0)
+    double mQ[4], mP0[4];
+    for (int mu = 0; mu < 4; ++mu) {
+        mQ[mu] = -Q[mu];
+        mP0[mu] = -P0[mu];
+    }
+    /* class 1: both gluons and the spine on the quark line */
+    Q4_SPINE(ta[0], mQ);
+    q4_line(ub, v, mk2, m, width, 1, ta, Xt);
+    for (int o = 0; o < 6; ++o) {
+        int slots[3];
+        for (int t = 0; t < 3; ++t) {
+            int x = perm3[o][t];
+            if (x < 2) {
+                Q4_GLUON(qa[t], x);
+                slots[t] = x;
+            } else {
+                Q4_SPINE(qa[t], Q);
+                slots[t] = 2;
+            }
+        }
+        q4_line(vb, u, pa, 0.0, 0.0, 3, qa, Xq);
+        A[n] = q4_dot(Xq, Xt) / q4_m2(Q);
+        int ts[1] = { 2 };
+        q4_set_colour(&C[n], 3, slots, 1, ts, 0, NULL, 1);
+        ++n;
+    }
+    /* class 2: both gluons and the spine on the top line */
+    Q4_SPINE(qa[0], P0);
+    q4_line(vb, u, pa, 0.0, 0.0, 1, qa, Xq);
+    for (int o = 0; o < 6; ++o) {
+        int slots[3];
+        for (int t = 0; t < 3; ++t) {
+            int x = perm3[o][t];
+            if (x < 2) {
+                Q4_GLUON(ta[t], x);
+                slots[t] = x;
+            } else {
+                Q4_SPINE(ta[t], mP0);
+                slots[t] = 2;
+            }
+        }
+        q4_line(ub, v, mk2, m, width, 3, ta, Xt);
+        A[n] = q4_dot(Xq, Xt) / q4_m2(P0);
+        int qs[1] = { 2 };
+        q4_set_colour(&C[n], 1, qs, 3, slots, 0, NULL, 1);
+        ++n;
+    }
+    /* class 3: gluon ga on the quark line, gb on the top line */
+    for (int ga = 0; ga < 2; ++ga) {
+        int gb = 1 - ga;
+        double Pq[4], mPq[4];
+        for (int mu = 0; mu < 4; ++mu) {
+            Pq[mu] = P0[mu] - kg[ga][mu];
+            mPq[mu] = -Pq[mu];
+        }
+        for (int oq = 0; oq < 2; ++oq) {
+            int qs[2];
+            Q4_GLUON(qa[oq], ga);
+            qs[oq] = ga;
+            Q4_SPINE(qa[1 - oq], Pq);
+            qs[1 - oq] = 2;
+            q4_line(vb, u, pa, 0.0, 0.0, 2, qa, Xq);
+            for (int ot = 0; ot < 2; ++ot) {
+                int ts[2];
+                Q4_GLUON(ta[ot], gb);
+                ts[ot] = gb;
+                Q4_SPINE(ta[1 - ot], mPq);
+                ts[1 - ot] = 2;
+                q4_line(ub, v, mk2, m, width, 2, ta, Xt);
+                A[n] = q4_dot(Xq, Xt) / q4_m2(Pq);
+                q4_set_colour(&C[n], 2, qs, 2, ts, 0, NULL, 1);
+                ++n;
+            }
+        }
+    }
+    /* class 4: ga on the spine, gb on the quark line */
+    Q4_SPINE(ta[0], mQ);
+    q4_line(ub, v, mk2, m, width, 1, ta, Xt);   /* the spine reaches the top line with Q */
+    for (int ga = 0; ga < 2; ++ga) {
+        int gb = 1 - ga;
+        double Pq[4];
+        for (int mu = 0; mu < 4; ++mu)
+            Pq[mu] = P0[mu] - kg[gb][mu];
+        for (int oq = 0; oq < 2; ++oq) {
+            int qs[2];
+            Q4_GLUON(qa[oq], gb);
+            qs[oq] = gb;
+            Q4_SPINE(qa[1 - oq], Pq);
+            qs[1 - oq] = 2;
+            q4_line(vb, u, pa, 0.0, 0.0, 2, qa, Xq);
+            q4_v3(Xq, Pq, eps[ga], kg[ga], J1);
+            A[n] = I1 * q4_dot(J1, Xt) / (q4_m2(Pq) * q4_m2(Q));
+            int ts[1] = { 3 };
+            int f[1][3] = { { 2, ga, 3 } };
+            q4_set_colour(&C[n], 2, qs, 1, ts, 1, (const int (*)[3])f, 2);
+            ++n;
+        }
+    }
+    /* class 5: ga on the spine, gb on the top line */
+    Q4_SPINE(qa[0], P0);
+    q4_line(vb, u, pa, 0.0, 0.0, 1, qa, Xq);
+    for (int ga = 0; ga < 2; ++ga) {
+        int gb = 1 - ga;
+        double Pt[4], mPt[4];
+        for (int mu = 0; mu < 4; ++mu) {
+            Pt[mu] = P0[mu] - kg[ga][mu];
+            mPt[mu] = -Pt[mu];
+        }
+        q4_v3(Xq, P0, eps[ga], kg[ga], J1);
+        for (int ot = 0; ot < 2; ++ot) {
+            int ts[2];
+            Q4_GLUON(ta[ot], gb);
+            ts[ot] = gb;
+            Q4_SPINE(ta[1 - ot], mPt);
+            ts[1 - ot] = 3;
+            q4_line(ub, v, mk2, m, width, 2, ta, Xt);
+            A[n] = I1 * q4_dot(J1, Xt) / (q4_m2(P0) * q4_m2(Pt));
+            int qs[1] = { 2 };
+            int f[1][3] = { { 2, ga, 3 } };
+            q4_set_colour(&C[n], 1, qs, 2, ts, 1, (const int (*)[3])f, 2);
+            ++n;
+        }
+    }
+    /* class 6: both gluons on the spine (Xq with P0, Xt with Q) */
+    Q4_SPINE(ta[0], mQ);
+    q4_line(ub, v, mk2, m, width, 1, ta, Xt);
+    for (int ga = 0; ga < 2; ++ga) {
+        int gb = 1 - ga;
+        double P1[4];
+        for (int mu = 0; mu < 4; ++mu)
+            P1[mu] = P0[mu] - kg[ga][mu];
+        q4_v3(Xq, P0, eps[ga], kg[ga], J1);
+        q4_v3(J1, P1, eps[gb], kg[gb], J2);
+        A[n] = -q4_dot(J2, Xt) / (q4_m2(P0) * q4_m2(P1) * q4_m2(Q));
+        int qs[1] = { 2 }, ts[1] = { 4 };
+        int f[2][3] = { { 2, ga, 3 }, { 3, gb, 4 } };
+        q4_set_colour(&C[n], 1, qs, 1, ts, 2, (const int (*)[3])f, 3);
+        ++n;
+    }
+    {
+        cplx q2 = q4_dot(Xq, eps[1]), q1 = q4_dot(Xq, eps[0]), qt = q4_dot(Xq, Xt);
+        cplx t1 = q4_dot(eps[0], Xt), t2 = q4_dot(eps[1], Xt), e12 = q4_dot(eps[0], eps[1]);
+        double den = q4_m2(P0) * q4_m2(Q);
+        int qs[1] = { 2 }, ts[1] = { 3 };
+        int f1[2][3] = { { 2, 0, 4 }, { 1, 3, 4 } };
+        A[n] = -(q2 * t1 - qt * e12) / den;
+        q4_set_colour(&C[n], 1, qs, 1, ts, 2, (const int (*)[3])f1, 3);
+        ++n;
+        int f2[2][3] = { { 2, 1, 4 }, { 0, 3, 4 } };
+        A[n] = -(q1 * t2 - qt * e12) / den;
+        q4_set_colour(&C[n], 1, qs, 1, ts, 2, (const int (*)[3])f2, 3);
+        ++n;
+        int f3[2][3] = { { 2, 3, 4 }, { 0, 1, 4 } };
+        A[n] = -(q1 * t2 - q2 * t1) / den;
+        q4_set_colour(&C[n], 1, qs, 1, ts, 2, (const int (*)[3])f3, 3);
+        ++n;
+    }
+    /* class 7: the composite (colour slot 3, f^{3 0 1}) */
+    {
+        /* on the quark line (spine slot 2, carrying Q to the top line) */
+        Q4_SPINE(ta[0], mQ);
+        q4_line(ub, v, mk2, m, width, 1, ta, Xt);
+        for (int oq = 0; oq < 2; ++oq) {
+            int qs[2];
+            Q4_COMP(qa[oq]);
+            qs[oq] = 3;
+            Q4_SPINE(qa[1 - oq], Q);
+            qs[1 - oq] = 2;
+            q4_line(vb, u, pa, 0.0, 0.0, 2, qa, Xq);
+            A[n] = I1 * q4_dot(Xq, Xt) / q4_m2(Q);
+            int ts[1] = { 2 };
+            int f[1][3] = { { 3, 0, 1 } };
+            q4_set_colour(&C[n], 2, qs, 1, ts, 1, (const int (*)[3])f, 2);
+            ++n;
+        }
+        /* on the top line */
+        Q4_SPINE(qa[0], P0);
+        q4_line(vb, u, pa, 0.0, 0.0, 1, qa, Xq);
+        for (int ot = 0; ot < 2; ++ot) {
+            int ts[2];
+            Q4_COMP(ta[ot]);
+            ts[ot] = 3;
+            Q4_SPINE(ta[1 - ot], mP0);
+            ts[1 - ot] = 2;
+            q4_line(ub, v, mk2, m, width, 2, ta, Xt);
+            A[n] = I1 * q4_dot(Xq, Xt) / q4_m2(P0);
+            int qs[1] = { 2 };
+            int f[1][3] = { { 3, 0, 1 } };
+            q4_set_colour(&C[n], 1, qs, 2, ts, 1, (const int (*)[3])f, 2);
+            ++n;
+        }
+        /* on the spine: spine in slot 2, composite 4, spine out 3 */
+        Q4_SPINE(ta[0], mQ);
+        q4_line(ub, v, mk2, m, width, 1, ta, Xt);
+        q4_v3(Xq, P0, J12, K, J1);
+        A[n] = -q4_dot(J1, Xt) / (q4_m2(P0) * q4_m2(Q));
+        int qs[1] = { 2 }, ts[1] = { 3 };
+        int f[2][3] = { { 2, 4, 3 }, { 4, 0, 1 } };
+        q4_set_colour(&C[n], 1, qs, 1, ts, 2, (const int (*)[3])f, 3);
+        ++n;
+    }
+#undef Q4_GLUON
+#undef Q4_COMP
+#undef Q4_SPINE
+    return n;
+}
+
+/* Value of a colour structure for the external colours ext[6] = (quark
+ * colour i, antiquark anticolour j, top colour k, antitop anticolour l,
+ * gluon adjoint indices a1, a2), the internal indices summed. */
+static cplx q4_colour_value(const q4_colour *c, const int *ext)
+{
+    pthread_once(&qq_once, qq_colour_init);
+    int slot[5];
+    slot[0] = ext[4];
+    slot[1] = ext[5];
+    int nint = c->nint, total = 1;
+    for (int x = 0; x < nint; ++x)
+        total *= 8;
+    cplx sum = 0;
+    for (int code = 0; code < total; ++code) {
+        int cc = code;
+        for (int x = 0; x < nint; ++x) {
+            slot[2 + x] = cc % 8;
+            cc /= 8;
+        }
+        double fv = 1.0;
+        for (int t = 0; t < c->nf; ++t)
+            fv *= qq_f[slot[c->f[t][0]]][slot[c->f[t][1]]][slot[c->f[t][2]]];
+        if (fv == 0.0)
+            continue;
+        /* quark line (T^{s_{n-1}} ... T^{s_0})_{j i}: a row vector from j */
+        cplx rq[3] = { 0, 0, 0 };
+        rq[ext[1]] = 1;
+        for (int t = c->nq - 1; t >= 0; --t) {
+            cplx nr[3] = { 0, 0, 0 };
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b)
+                    nr[b] += rq[a] * qq_T[slot[c->qs[t]]][a][b];
+            memcpy(rq, nr, sizeof(nr));
+        }
+        cplx rt[3] = { 0, 0, 0 };
+        rt[ext[2]] = 1;
+        for (int t = c->nt - 1; t >= 0; --t) {
+            cplx nr[3] = { 0, 0, 0 };
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b)
+                    nr[b] += rt[a] * qq_T[slot[c->ts[t]]][a][b];
+            memcpy(rt, nr, sizeof(nr));
+        }
+        sum += fv * rq[ext[0]] * rt[ext[3]];
+    }
+    return sum;
+}
+
+static double complex q4_K[Q4_TERMS][Q4_TERMS];
+static pthread_once_t q4_once = PTHREAD_ONCE_INIT;
+
+/* K_de = sum over the 3^4 8^2 colour assignments of C_d conj(C_e). */
+static void q4_K_init(void)
+{
+    static const double p[24] = { 0 };
+    int hel[6] = { 0, 0, 0, 0, 0, 0 };
+    cplx A[Q4_TERMS];
+    q4_colour C[Q4_TERMS];
+    (void)p;
+    double pp[24] = { 300, 0, 0, 100, 300, 0, 0, -100, -400, 0, 0, -400, -400, 0, 0, 400,
+                      100, 100, 0, 0, 100, -100, 0, 0 };
+    int n = q4_terms(pp, 173.0, 0.0, hel, 0, A, C);
+    static cplx val[5184][Q4_TERMS];
+    for (int ci = 0; ci < 5184; ++ci) {
+        int ext[6] = { ci % 3, (ci / 3) % 3, (ci / 9) % 3, (ci / 27) % 3, (ci / 81) % 8, ci / 648 };
+        for (int d = 0; d < n; ++d)
+            val[ci][d] = q4_colour_value(&C[d], ext);
+    }
+    for (int d = 0; d < n; ++d)
+        for (int e = 0; e < n; ++e) {
+            cplx s = 0;
+            for (int ci = 0; ci < 5184; ++ci)
+                s += val[ci][d] * conj(val[ci][e]);
+            q4_K[d][e] = s;
+        }
+}
+
+void mfo_qqbar_ttxgg_terms(const double *p, double m, double width, const int *hel, int ward, double *amp)
+{
+    cplx A[Q4_TERMS];
+    q4_colour C[Q4_TERMS];
+    q4_terms(p, m, width, hel, ward, A, C);
+    for (int d = 0; d < Q4_TERMS; ++d) {
+        amp[2 * d] = creal(A[d]);
+        amp[2 * d + 1] = cimag(A[d]);
+    }
+}
+
+void mfo_qqbar_ttxgg_colour(const int *cols, double *c)
+{
+    cplx A[Q4_TERMS];
+    q4_colour C[Q4_TERMS];
+    double pp[24] = { 300, 0, 0, 100, 300, 0, 0, -100, -400, 0, 0, -400, -400, 0, 0, 400,
+                      100, 100, 0, 0, 100, -100, 0, 0 };
+    int hel[6] = { 0, 0, 0, 0, 0, 0 };
+    q4_terms(pp, 173.0, 0.0, hel, 0, A, C);
+    for (int d = 0; d < Q4_TERMS; ++d) {
+        cplx v = q4_colour_value(&C[d], cols);
+        c[2 * d] = creal(v);
+        c[2 * d + 1] = cimag(v);
+    }
+}
+
+void mfo_qqbar_ttxgg_colour_matrix(double *K)
+{
+    pthread_once(&q4_once, q4_K_init);
+    for (int d = 0; d < Q4_TERMS; ++d)
+        for (int e = 0; e < Q4_TERMS; ++e) {
+            K[2 * (d * Q4_TERMS + e)] = creal(q4_K[d][e]);
+            K[2 * (d * Q4_TERMS + e) + 1] = cimag(q4_K[d][e]);
+        }
+}
+
+/* Sum over the 64 helicity configurations of A^dagger K A, g = 1. */
+double mfo_me2_qqbar_ttxgg(const double *p, double m, double width)
+{
+    pthread_once(&q4_once, q4_K_init);
+    double total = 0.0;
+    for (int h = 0; h < 64; ++h) {
+        int hel[6] = { h & 1, (h >> 1) & 1, (h >> 2) & 1, (h >> 3) & 1, (h >> 4) & 1, (h >> 5) & 1 };
+        cplx A[Q4_TERMS];
+        q4_colour C[Q4_TERMS];
+        int n = q4_terms(p, m, width, hel, 0, A, C);
+        double s = 0.0;
+        for (int d = 0; d < n; ++d) {
+            cplx row = 0;
+            for (int e = 0; e < n; ++e)
+                row += q4_K[d][e] * conj(A[e]);
+            s += creal(A[d] * row);
+        }
+        total += s;
+    }
+    return total;
+}

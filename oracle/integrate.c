@@ -194,7 +194,7 @@ static double weight_from_x(const mfo_process *proc, double sqrt_s,
     if (pp) {
         /* q qbar channels: the quark from beam 1 (u ubar, d dbar) or from beam 2
          * (ubar u, dbar d); average over 2 x 2 helicities and 3 x 3 colours;
-         * t tbar (n_g = 2) or t tbar g (n_g = 3) */
+         * t tbar (n_g = 2), t tbar g (n_g = 3) or t tbar g g (n_g = 4) */
         double pr[(MFO_MAX_G + 2) * 4];
         memcpy(pr, p, sizeof(double) * 4 * (n_g + 2));
         memcpy(pr + 8, pb, sizeof(pb));
@@ -205,6 +205,11 @@ static double weight_from_x(const mfo_process *proc, double sqrt_s,
         } else if (n_g == 3) {
             ev->me2_q[0] = gs2 * gs2 * gs2 * mfo_me2_qqbar_ttxg(p, m, proc->w_top) / 36.0;
             ev->me2_q[1] = gs2 * gs2 * gs2 * mfo_me2_qqbar_ttxg(pr, m, proc->w_top) / 36.0;
+        } else if (n_g == 4) {
+            /* and 1/2! for the two identical gluons */
+            const double g8 = gs2 * gs2 * gs2 * gs2;
+            ev->me2_q[0] = g8 * mfo_me2_qqbar_ttxgg(p, m, proc->w_top) / (36.0 * 2.0);
+            ev->me2_q[1] = g8 * mfo_me2_qqbar_ttxgg(pr, m, proc->w_top) / (36.0 * 2.0);
         } else {
             ev->me2_q[0] = ev->me2_q[1] = NAN;   /* q qbar channels with more gluons: not in the oracle */
         }

@@ -144,6 +144,20 @@ void mfo_qqbar_ttxg_diagrams(const double *p, double m, double width, const int 
 void mfo_qqbar_ttxg_colour(const int *cols, double *c);
 /* Sum over helicities and colour assignments of |sum_d C_d A_d|^2, g = 1. */
 double mfo_me2_qqbar_ttxg(const double *p, double m, double width);
+/* q(pa) qbar(pb) -> t tbar g g from its 36 Feynman diagrams (amplitudes.c),
+ * 38 terms (the four-gluon vertex in its three colour structures):
+ * the Lorentz parts of helicity configuration hel[6] (quark, antiquark, top,
+ * antitop spin; gluon 1, gluon 2 helicity), amp[2 d], [2 d + 1]; ward = 1 or
+ * 2 replaces that gluon's polarisation by its momentum.  p: [6][4] all
+ * outgoing: t, tbar, -pa, -pb, g1, g2. */
+void mfo_qqbar_ttxgg_terms(const double *p, double m, double width, const int *hel, int ward, double *amp);
+/* The terms' colour factors for cols[6] = (quark colour, antiquark
+ * anticolour, top colour, antitop anticolour, a1, a2). */
+void mfo_qqbar_ttxgg_colour(const int *cols, double *c);
+/* K_de = sum over colours of C_d conj(C_e), [38][38][re, im]. */
+void mfo_qqbar_ttxgg_colour_matrix(double *K);
+/* Sum over helicities and colours of |M|^2, g = 1. */
+double mfo_me2_qqbar_ttxgg(const double *p, double m, double width);
 /* Colour-dressed amplitude M_ij from Feynman rules with explicit SU(3)
  * indices for one assignment of gluon adjoint indices cols[n_g] (0 .. 7) and
  * helicity configuration hel: out[2 (3 i + j)] = Re M_ij, [+1] = Im, i the

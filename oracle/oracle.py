@@ -100,6 +100,14 @@ def lib():
         L.mfo_qqbar_ttxg_colour.restype = None
         L.mfo_me2_qqbar_ttxg.argtypes = [_dp, C.c_double, C.c_double]
         L.mfo_me2_qqbar_ttxg.restype = C.c_double
+        L.mfo_qqbar_ttxgg_terms.argtypes = [_dp, C.c_double, C.c_double, _ip, C.c_int, _dp]
+        L.mfo_qqbar_ttxgg_terms.restype = None
+        L.mfo_qqbar_ttxgg_colour.argtypes = [_ip, _dp]
+        L.mfo_qqbar_ttxgg_colour.restype = None
+        L.mfo_qqbar_ttxgg_colour_matrix.argtypes = [_dp]
+        L.mfo_qqbar_ttxgg_colour_matrix.restype = None
+        L.mfo_me2_qqbar_ttxgg.argtypes = [_dp, C.c_double, C.c_double]
+        L.mfo_me2_qqbar_ttxgg.restype = C.c_double
         L.mfo_pdf_xf.restype = C.c_double
         L.mfo_n_orderings.argtypes = [C.c_int]
         L.mfo_n_orderings.restype = C.c_int
@@ -217,8 +225,8 @@ class Process:
         imodes = {"gg": 0, "pp": 1}
         if self.initial not in imodes:
             raise ValueError(f"initial must be one of {sorted(imodes)}, not {self.initial!r}")
-        if self.initial == "pp" and self.n_g not in (2, 3):
-            raise ValueError("the q qbar channels are in the oracle for p p -> t tbar and t tbar g only")
+        if self.initial == "pp" and self.n_g not in (2, 3, 4):
+            raise ValueError("the q qbar channels are in the oracle for p p -> t tbar, t tbar g, t tbar g g only")
         return _Process(self.n_g, self.m_top, self.w_top, self.alpha_s, self.mu_f,
                         self.ptmin_g, self.etamax_g, self.drmin_gg, modes[self.colour],
                         hmodes[self.helicity], imodes[self.initial])
@@ -376,6 +384,36 @@ def qqbar_ttxg_colour(cols):
 def me2_qqbar_ttxg(p, m, width):
     """q qbar -> t tbar g |M|^2 summed over helicities and colours (g = 1)."""
     return lib().mfo_me2_qqbar_ttxg(_d(_f64(p)), m, width)
+
+
+def qqbar_ttxgg_terms(p, m, width, hel, ward=0):
+    """The 38 Lorentz terms (complex) of q qbar -> t tbar g g for helicities
+    hel = (quark, antiquark, top, antitop spin, gluon 1, gluon 2); ward = 1
+    or 2 replaces that gluon's polarisation by its momentum.  p: [6][4] all
+    outgoing: t, tbar, -p_q, -p_qbar, g1, g2."""
+    out = np.zeros(76)
+    h = np.ascontiguousarray(hel, dtype=np.int32)
+    lib().mfo_qqbar_ttxgg_terms(_d(_f64(p)), m, width, h.ctypes.data_as(_ip), int(ward), _d(out))
+    return out[0::2] + 1j * out[1::2]
+
+
+def qqbar_ttxgg_colour(cols):
+    """Colour factors (complex [38]) for cols = (i_q, j_qbar, k_t, l_tbar, a1, a2)."""
+    out = np.zeros(76)
+    c = np.ascontiguousarray(cols, dtype=np.int32)
+    lib().mfo_qqbar_ttxgg_colour(c.ctypes.data_as(_ip), _d(out))
+    return out[0::2] + 1j * out[1::2]
+
+
+def qqbar_ttxgg_colour_matrix():
+    out = np.zeros(38 * 38 * 2)
+    lib().mfo_qqbar_ttxgg_colour_matrix(_d(out))
+    return (out[0::2] + 1j * out[1::2]).reshape(38, 38)
+
+
+def me2_qqbar_ttxgg(p, m, width):
+    """q qbar -> t tbar g g |M|^2 summed over helicities and colours (g = 1)."""
+    return lib().mfo_me2_qqbar_ttxgg(_d(_f64(p)), m, width)
 
 
 def colour_matrix(n_g):

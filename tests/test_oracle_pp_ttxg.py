@@ -185,4 +185,4 @@ def test_pp_ttxg_event_weight_assembly():
         checked += 1
     assert checked > 15
     with pytest.raises(ValueError):
-        O.Process(n_g=4, initial="pp").c()
+        O.Process(n_g=5, initial="pp").c()
