@@ -47,15 +47,16 @@ typedef enum {
  * events per batch: each event's 120 x 128 complex partial amplitudes
  * (240 KB in FP64, 120 KB in FP32) pass through device memory between the
  * amplitude kernel and the matrix-core colour sum. */
-/* MF_PP_TTX and MF_PP_TTXG are p p -> t tbar and p p -> t tbar g as in
+/* MF_PP_TTX, MF_PP_TTXG and MF_PP_TTXGG are p p -> t tbar (g (g)) as in
  * Sec. 3 and Table 1: the g g channel plus the q qbar channels u ubar,
- * ubar u, d dbar, dbar d (1 and 5 diagrams per quark group; 7 and 36 with
- * g g), weighted by the quark tables of mf_pdf_grid (xq, required); full
+ * ubar u, d dbar, dbar d (1, 5 and 36 diagrams per quark group; 7, 36 and
+ * 267 with g g), weighted by the quark tables of mf_pdf_grid (xq, required); full
  * colour and helicity sums, FP64 or FP32 amplitudes for the g g channel
  * (the q qbar channel is FP64), no gradients, not in mf_integrate_static.
- * The cuts of mf_process apply to the final gluon as for MF_GG_TTXG. */
+ * The cuts of mf_process apply to the final gluons as for MF_GG_TTXG(G). */
 typedef enum {
-    MF_GG_TTX = 0, MF_GG_TTXG = 1, MF_GG_TTXGG = 2, MF_GG_TTXGGG = 3, MF_PP_TTX = 4, MF_PP_TTXG = 5
+    MF_GG_TTX = 0, MF_GG_TTXG = 1, MF_GG_TTXGG = 2, MF_GG_TTXGGG = 3, MF_PP_TTX = 4, MF_PP_TTXG = 5,
+    MF_PP_TTXGG = 6
 } mf_process_id;
 
 /* Arithmetic of the helicity amplitudes and colour sum.  Everything else
@@ -129,7 +130,7 @@ typedef struct {
     const double *log_q2;    /* host [n_q2]                                    */
     const double *xf;        /* host [n_q2][n_x], row-major                    */
     const double *xq;        /* host [4][n_q2][n_x] x q(x, Q^2) for u, ubar, d, dbar
-                                (MF_PP_TTX, MF_PP_TTXG), NULL for the g g
+                                (the MF_PP_ processes), NULL for the g g
                                 processes                                      */
 } mf_pdf_grid;
 
@@ -261,7 +262,7 @@ mf_status mf_refine_grid(int n_dims, int n_bins, double alpha, const double *his
 mf_status mf_colour_matrix(int process_id, double *C);
 
 /* Colour- and helicity-summed |M|^2 with g_s = 1 for explicit momenta
- * (MF_PP_TTX, MF_PP_TTXG: the q qbar channel, the quark along +z, FP64):
+ * (the MF_PP_ processes: the q qbar channel, the quark along +z, FP64):
  *   mom: device [n][4 (t) + 4 (tbar) + 4 (n_g-2) (final gluons)] in the
  *        partonic CM frame with the beams along +z/-z; eb: device [n] beam
  *        energies sqrt(s_hat)/2.  out: device [n]. */

@@ -13,7 +13,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "lib", "libmadflow_mi355x.so")
 
 MF_OK, MF_EINVAL, MF_ENOMEM, MF_EDEVICE, MF_ENOCONV, MF_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
-MF_GG_TTX, MF_GG_TTXG, MF_GG_TTXGG, MF_GG_TTXGGG, MF_PP_TTX, MF_PP_TTXG = 0, 1, 2, 3, 4, 5
+MF_GG_TTX, MF_GG_TTXG, MF_GG_TTXGG, MF_GG_TTXGGG, MF_PP_TTX, MF_PP_TTXG, MF_PP_TTXGG = 0, 1, 2, 3, 4, 5, 6
 MF_FP64, MF_FP32_KAHAN = 0, 1
 
 _dp = C.POINTER(C.c_double)

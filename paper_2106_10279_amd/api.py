@@ -24,6 +24,7 @@ from ._lib import MF_FP32_KAHAN, MF_FP64, MFError, check, lib  # noqa: F401
 
 PROCESS_IDS = {"gg_ttx": _lib.MF_GG_TTX, "gg_ttxg": _lib.MF_GG_TTXG, "gg_ttxgg": _lib.MF_GG_TTXGG,
                "gg_ttxggg": _lib.MF_GG_TTXGGG, "pp_ttx": _lib.MF_PP_TTX, "pp_ttxg": _lib.MF_PP_TTXG,
+               "pp_ttxgg": _lib.MF_PP_TTXGG,
                2: _lib.MF_GG_TTX, 3: _lib.MF_GG_TTXG, 4: _lib.MF_GG_TTXGG, 5: _lib.MF_GG_TTXGGG}
 PRECISIONS = {"fp64": MF_FP64, "fp32_kahan": MF_FP32_KAHAN}
 # colour sum: the full colour matrix, the leading-colour approximation, or a
@@ -233,7 +234,7 @@ def refine_grid(hist: torch.Tensor, grid: torch.Tensor, alpha: float = 1.5, stre
 
 def colour_matrix(process) -> np.ndarray:
     pid = PROCESS_IDS[process]
-    n = {0: 2, 1: 6, 2: 24, 3: 120, 4: 2, 5: 6}[pid]
+    n = {0: 2, 1: 6, 2: 24, 3: 120, 4: 2, 5: 6, 6: 24}[pid]
     C_ = np.zeros((n, n))
     check(lib.mf_colour_matrix(pid, _ptr(C_)))
     return C_

@@ -1362,7 +1362,18 @@ _COOP_COUNT = None
 
 def _helpers():
     import types
-    return types.SimpleNamespace(_contract=_contract, CoopTable=CoopTable, emit_coop_fill=emit_coop_fill)
+    return types.SimpleNamespace(_contract=_contract, CoopTable=CoopTable, emit_coop_fill=emit_coop_fill,
+                                 gell_mann_half=gell_mann_half)
+
+
+def _qqbar():
+    """The q qbar -> t tbar g g colour tables (gen_qqbar.py next to this file)."""
+    import importlib.util
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "gen_qqbar.py")
+    spec = importlib.util.spec_from_file_location("gen_qqbar", path)
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
 
 
 def _ttggg():
@@ -1427,9 +1438,12 @@ def main():
     ap.add_argument("--out", required=True)
     args = ap.parse_args()
     os.makedirs(args.out, exist_ok=True)
-    for n in (2, 3, 4, 5):
-        path = os.path.join(args.out, f"amp_ng{n}.inc")
-        text = generate(n) if n <= 4 else _ttggg().generate_ng5(_helpers())[0]
+    outputs = [(f"amp_ng{n}.inc", (lambda n=n: generate(n) if n <= 4 else _ttggg().generate_ng5(_helpers())[0]))
+               for n in (2, 3, 4, 5)]
+    outputs.append(("qqbar_ttxgg.inc", lambda: _qqbar().generate(_helpers())))
+    for name, make in outputs:
+        path = os.path.join(args.out, name)
+        text = make()
         old = open(path).read() if os.path.exists(path) else None
         if old != text:
             with open(path, "w") as f:

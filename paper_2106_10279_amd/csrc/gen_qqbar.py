@@ -1,0 +1,143 @@
+"""Colour tables of q qbar -> t tbar g g (the q qbar channel of p p -> t tbar
+g g, Sec. 3, Table 1: 36 Feynman diagrams per quark group), written by
+gen_amplitudes.py into _gen/qqbar_ttxgg.inc.
+
+The device code evaluates the Lorentz part A_d of 38 terms per helicity
+configuration (the 36 diagrams, the four-gluon vertex split into its three
+colour structures), in the order of TERMS below.  The colour sum
+sum_colours |sum_d C_d A_d|^2 = sum_de A_d K_de conj(A_e) with K_de =
+sum_colours C_d conj(C_e) is Hermitian and positive semi-definite of low
+rank; with K = sum_r lam_r v_r v_r^dagger it is sum_r |sum_d W_rd A_d|^2,
+W_rd = sqrt(lam_r) v_r[d], over the r with lam_r > 0.  K comes from an
+explicit sum over the 3^4 8^2 colour assignments of each term's colour
+factor: products of T = lambda/2 along the quark line (v-bar index j to u
+index i) and the top line (u-bar index k to v index l) and structure
+constants f^{abc} = -2i Tr([T^a, T^b] T^c), internal indices summed.
+
+Colour slots: 0, 1 the gluons' adjoint indices; 2 + x internal index x.
+A term: (quark-line slots from the u end, top-line slots from the v end,
+f factors (x, y, z) -> f^{xyz}, number of internal indices).
+"""
+import itertools
+
+import numpy as np
+
+
+def _terms():
+    t = []
+    orders = [(0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0)]
+    # 1: both gluons and the spine (internal 0) on the quark line
+    for o in orders:
+        t.append((tuple(o), (2,), (), 1))
+    # 2: both gluons and the spine on the top line
+    for o in orders:
+        t.append(((2,), tuple(o), (), 1))
+    # 3: gluon ga on the quark line, gb on the top line, 2 x 2 orders
+    for ga in (0, 1):
+        gb = 1 - ga
+        for oq in (0, 1):
+            qs = [0, 0]
+            qs[oq], qs[1 - oq] = ga, 2
+            for ot in (0, 1):
+                ts = [0, 0]
+                ts[ot], ts[1 - ot] = gb, 2
+                t.append((tuple(qs), tuple(ts), (), 1))
+    # 4: ga on the spine (f^{2 ga 3}), gb on the quark line
+    for ga in (0, 1):
+        gb = 1 - ga
+        for oq in (0, 1):
+            qs = [0, 0]
+            qs[oq], qs[1 - oq] = gb, 2
+            t.append((tuple(qs), (3,), ((2, ga, 3),), 2))
+    # 5: ga on the spine, gb on the top line
+    for ga in (0, 1):
+        gb = 1 - ga
+        for ot in (0, 1):
+            ts = [0, 0]
+            ts[ot], ts[1 - ot] = gb, 3
+            t.append(((2,), tuple(ts), ((2, ga, 3),), 2))
+    # 6: both on the spine, ga nearer the quark line
+    for ga in (0, 1):
+        gb = 1 - ga
+        t.append(((2,), (4,), ((2, ga, 3), (3, gb, 4)), 3))
+    # the four-gluon vertex: spine in 2, spine out 3, internal 4
+    t.append(((2,), (3,), ((2, 0, 4), (1, 3, 4)), 3))
+    t.append(((2,), (3,), ((2, 1, 4), (0, 3, 4)), 3))
+    t.append(((2,), (3,), ((2, 3, 4), (0, 1, 4)), 3))
+    # 7: the composite (slot 3, f^{3 0 1}) on the quark line, the top line, the spine
+    for oq in (0, 1):
+        qs = [0, 0]
+        qs[oq], qs[1 - oq] = 3, 2
+        t.append((tuple(qs), (2,), ((3, 0, 1),), 2))
+    for ot in (0, 1):
+        ts = [0, 0]
+        ts[ot], ts[1 - ot] = 3, 2
+        t.append(((2,), tuple(ts), ((3, 0, 1),), 2))
+    t.append(((2,), (3,), ((2, 4, 3), (4, 0, 1)), 3))
+    return t
+
+
+TERMS = _terms()
+
+
+def _generators(G):
+    T = np.array(G.gell_mann_half(), dtype=complex)          # [8][3][3]
+    f = np.zeros((8, 8, 8))
+    for a, b, c in itertools.product(range(8), repeat=3):
+        comm = T[a] @ T[b] - T[b] @ T[a]
+        f[a, b, c] = (-2j * np.trace(comm @ T[c])).real
+    return T, f
+
+
+def colour_values(G):
+    """C[assignment][term] for the assignments (i, j, k, l, a1, a2) in
+    lexicographic order (i slowest)."""
+    T, f = _generators(G)
+    n_ass = 3 ** 4 * 64
+    C = np.zeros((n_ass, len(TERMS)), dtype=complex)
+    for d, (qs, ts, fs, nint) in enumerate(TERMS):
+        # tensor over (a1, a2, internal...) of the f product, and the line matrices
+        for ints in itertools.product(range(8), repeat=nint):
+            for a1 in range(8):
+                for a2 in range(8):
+                    slot = [a1, a2, *ints]
+                    fv = 1.0
+                    for x, y, z in fs:
+                        fv *= f[slot[x], slot[y], slot[z]]
+                    if fv == 0.0:
+                        continue
+                    Mq = np.eye(3, dtype=complex)
+                    for s in qs:                     # from the u end: rightmost first
+                        Mq = T[slot[s]] @ Mq
+                    Mt = np.eye(3, dtype=complex)
+                    for s in ts:
+                        Mt = T[slot[s]] @ Mt
+                    # assignment index of (i, j, k, l, a1, a2)
+                    val = fv * np.einsum("ji,kl->ijkl", Mq, Mt).reshape(81)
+                    C[np.arange(81) * 64 + a1 * 8 + a2, d] += val
+    return C
+
+
+def projection(G):
+    """W [rank][38] complex with sum_r |sum_d W_rd A_d|^2 the colour sum."""
+    C = colour_values(G)
+    K = C.T @ C.conj()
+    # K = U diag(lam) U^dagger, so A^T K conj(A) = sum_r lam_r |sum_d U_dr A_d|^2
+    lam, U = np.linalg.eigh(K)
+    keep = lam > 1e-9 * lam.max()
+    W = np.sqrt(lam[keep])[:, None] * U[:, keep].T
+    return W, K
+
+
+def generate(G):
+    W, K = projection(G)
+    r = W.shape[0]
+    lines = ["// Generated by gen_qqbar.py: colour projection of q qbar -> t tbar g g.",
+             f"constexpr int QQ4_RANK = {r};",
+             f"constexpr int QQ4_TERMS = {len(TERMS)};",
+             "// W[r][d] = (re, im): the colour sum is sum_r |sum_d W[r][d] A_d|^2",
+             f"static constexpr double QQ4_W[{r}][{len(TERMS)}][2] = {{"]
+    for row in W:
+        lines.append("    {" + ", ".join(f"{{{z.real:.17g}, {z.imag:.17g}}}" for z in row) + "},")
+    lines.append("};")
+    return "\n".join(lines) + "\n"

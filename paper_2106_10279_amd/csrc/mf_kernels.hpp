@@ -18,6 +18,7 @@
 
 #include "mf_device.hpp"
 #include "mf_qqbar_ttxg.hpp"
+#include "mf_qqbar_ttxgg.hpp"
 
 namespace mf {
 
@@ -790,7 +791,7 @@ __global__ void __launch_bounds__(kBlock) kin_kernel(StageParams S)
                 S.flags[e] = (unsigned char)flags;
                 if constexpr (PP) {
                     S.pref_q[e] = pq[0];
-                    if constexpr (NF == 3)
+                    if constexpr (NF >= 3)
                         S.pref_q[S.count + e] = pq[1];
                 }
                 live |= (pref != 0.0 ? 1u : 0u) << t;
@@ -1162,7 +1163,7 @@ __global__ void __launch_bounds__(kBlock) acc_kernel(StageParams S)
                 w = pref * (S.me[e] * P.me_norm);
                 if (P.pp) {
                     w += S.pref_q[e] * (S.me_q[e] * P.me_norm_q);
-                    if constexpr (NF == 3)
+                    if constexpr (NF >= 3)
                         w += S.pref_q[S.count + e] * (S.me_q[S.count + e] * P.me_norm_q);
                 }
             }
@@ -1515,6 +1516,43 @@ __global__ void __launch_bounds__(kBlock) qqbar_ttxg_me_kernel(const double* __r
         out[e] = v;
 }
 
+// p p -> t tbar g g: the q qbar amplitudes of the batch's live events, one
+// wave per event: lane = orientation x 32 + configuration (the 32 with the
+// antiquark spin opposite the quark's); the sums go to me_q[e] (quark along
+// +z) and me_q[count + e].
+__global__ void __launch_bounds__(kBlock) qqbar_ttxgg_kernel(StageParams S)
+{
+    const int lane = threadIdx.x % kWave;
+    const uint64_t i = (uint64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+    const uint64_t n_ev = S.live ? (uint64_t)*S.n_live : S.count;
+    const uint64_t e = i < n_ev ? (S.live ? (uint64_t)S.live[i] : i) : S.count;
+    const bool live = e < S.count && S.pref[e] != 0.0;
+    double v = 0.0;
+    if (live) {
+        const double* mom = S.mom + e * 17;
+        v = qqbar_ttxgg_config(mom, mom[16], S.P.m_top, S.P.mw, lane & 31, lane >> 5);
+    }
+    v = group_sum(v, 32);
+    if (live && (lane & 31) == 0)
+        S.me_q[(uint64_t)(lane >> 5) * S.count + e] = v;
+}
+
+// q qbar -> t tbar g g |M|^2 (g = 1) for explicit momenta [n][16] (t, tbar,
+// g1, g2), the quark along +z; 32 lanes per event.
+__global__ void __launch_bounds__(kBlock) qqbar_ttxgg_me_kernel(const double* __restrict__ mom,
+                                                                const double* __restrict__ eb, uint64_t n,
+                                                                double mt, double mw, double* __restrict__ out)
+{
+    const uint64_t e = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) >> 5;
+    const int c = threadIdx.x & 31;
+    double v = 0.0;
+    if (e < n)
+        v = qqbar_ttxgg_config(mom + 16 * e, eb[e], mt, mw, c, 0);
+    v = group_sum(v, 32);
+    if (e < n && c == 0)
+        out[e] = v;
+}
+
 // mf_evaluate for the staged processes: weight (and the record's |M|^2 entry)
 // of every event of the batch.
 __global__ void __launch_bounds__(kBlock) weight_kernel(StageParams S, int nf)
@@ -1527,7 +1565,7 @@ __global__ void __launch_bounds__(kBlock) weight_kernel(StageParams S, int nf)
     double w = pref != 0.0 ? pref * (me * S.P.me_norm) : 0.0;
     if (S.P.pp && pref != 0.0) {
         w += S.pref_q[e] * (S.me_q[e] * S.P.me_norm_q);
-        if (nf == 3)
+        if (nf >= 3)
             w += S.pref_q[S.count + e] * (S.me_q[S.count + e] * S.P.me_norm_q);
     }
     S.P.weights[S.first + e] = w;

@@ -72,6 +72,7 @@ int n_gluons(int id)
     case MF_GG_TTXGGG: return 5;
     case MF_PP_TTX: return 2;
     case MF_PP_TTXG: return 3;
+    case MF_PP_TTXGG: return 4;
     default: return -1;
     }
 }
@@ -79,7 +80,7 @@ int n_gluons(int id)
 // p p processes: the g g channel plus the q qbar channels from the quark tables.
 bool is_pp(int id)
 {
-    return id == MF_PP_TTX || id == MF_PP_TTXG;
+    return id == MF_PP_TTX || id == MF_PP_TTXG || id == MF_PP_TTXGG;
 }
 
 double factorial(int n)
@@ -359,8 +360,9 @@ mf_status prepare(const mf_process* proc, double sqrt_s, const mf_pdf_grid* pdf,
     P.hel_mc = opt->helicity == MF_HELICITY_SAMPLED;
     P.pp = pp ? 1 : 0;
     P.xq = pp ? m.xq : nullptr;
-    // q qbar: average over 2 x 2 helicities and 3 x 3 colours, g_s^(2 n_g)
-    P.me_norm_q = std::pow(gs2, n) / 36.0 * mf::kGeV2ToPb;
+    // q qbar: average over 2 x 2 helicities and 3 x 3 colours, g_s^(2 n_g),
+    // 1/(n_g - 2)! for identical final-state gluons
+    P.me_norm_q = std::pow(gs2, n) / (36.0 * factorial(n - 2)) * mf::kGeV2ToPb;
     return MF_OK;
 }
 
@@ -426,7 +428,7 @@ mf_status launch_stages(const mf::StageParams& S, int kin_blocks, int n_cu, hipS
         hipLaunchKernelGGL(clear_count_kernel, dim3(1), dim3(1), 0, stream, S.n_live);
         MF_HIP(hipGetLastError());
     }
-    if constexpr (NG == 2 || NG == 3) {
+    if constexpr (NG == 2 || NG == 3 || NG == 4) {
         if (S.P.pp)
             hipLaunchKernelGGL((mf::kin_kernel<NG, true>), dim3(kin_blocks), dim3(mf::kBlock), 0, stream, S);
         else
@@ -448,6 +450,14 @@ mf_status launch_stages(const mf::StageParams& S, int kin_blocks, int n_cu, hipS
         if (qb > 0x7FFFFFFFull)
             return fail(MF_EINVAL, "too many events for one launch");
         hipLaunchKernelGGL(mf::qqbar_ttxg_kernel, dim3((unsigned)qb), dim3(mf::kWave), 0, stream, S);
+        MF_HIP(hipGetLastError());
+    }
+    if (NG == 4 && S.P.pp) {
+        // the q qbar channel of t tbar g g (FP64): one wave per event
+        const uint64_t qb = (S.count + mf::kWavesPerBlock - 1) / mf::kWavesPerBlock;
+        if (qb > 0x7FFFFFFFull)
+            return fail(MF_EINVAL, "too many events for one launch");
+        hipLaunchKernelGGL(mf::qqbar_ttxgg_kernel, dim3((unsigned)qb), dim3(mf::kBlock), 0, stream, S);
         MF_HIP(hipGetLastError());
     }
     if (amp_end)
@@ -806,7 +816,7 @@ mf_status integrate_impl(const mf_process* proc, double sqrt_s, const mf_pdf_gri
                 if ((st = ensure(ws.live_count, sizeof(unsigned long long))) != MF_OK) return st;
             }
             if (pp) {
-                const size_t orient = ng == 3 ? 2 : 1;   // t tbar g: both beam orientations
+                const size_t orient = ng >= 3 ? 2 : 1;   // t tbar g (g): both beam orientations
                 if ((st = ensure(ws.st_prefq, sizeof(double) * orient * b0)) != MF_OK) return st;
                 if ((st = ensure(ws.st_meq, sizeof(double) * orient * b0)) != MF_OK) return st;
             }
@@ -1211,7 +1221,7 @@ mf_status evaluate_staged(Setup& S, const mf_options* opt, uint64_t n)
         if ((st = ensure(ws.st_bins, sizeof(unsigned short) * S.D * batch)) != MF_OK) return st;
         if ((st = ensure(ws.st_flags, batch)) != MF_OK) return st;
         if ((st = ensure(ws.amp_counter, sizeof(unsigned long long))) != MF_OK) return st;
-        const size_t orient = S.ng == 3 ? 2 : 1;
+        const size_t orient = S.ng >= 3 ? 2 : 1;
         if ((st = ensure(ws.st_prefq, sizeof(double) * orient * batch)) != MF_OK) return st;
         if ((st = ensure(ws.st_meq, sizeof(double) * orient * batch)) != MF_OK) return st;
         SP.mom = (double*)ws.st_mom.ptr;
@@ -1242,6 +1252,10 @@ mf_status evaluate_staged(Setup& S, const mf_options* opt, uint64_t n)
             st = opt->precision == MF_FP32_KAHAN
                      ? launch_stages<3, float, 0>(SP, kin_blocks, S.ws->n_cu, S.stream, nullptr, nullptr, false)
                      : launch_stages<3, double, 0>(SP, kin_blocks, S.ws->n_cu, S.stream, nullptr, nullptr, false);
+        else if (S.ng == 4)
+            st = opt->precision == MF_FP32_KAHAN
+                     ? launch_stages<4, float, 0>(SP, kin_blocks, S.ws->n_cu, S.stream, nullptr, nullptr, false)
+                     : launch_stages<4, double, 0>(SP, kin_blocks, S.ws->n_cu, S.stream, nullptr, nullptr, false);
         else
             st = opt->precision == MF_FP32_KAHAN
                      ? launch_stages<2, float, 0>(SP, kin_blocks, S.ws->n_cu, S.stream, nullptr, nullptr, false)
@@ -1607,6 +1621,17 @@ mf_status mf_matrix_element(int process_id, mf_precision precision, const double
     hipStream_t s = (hipStream_t)stream;
     if (ng == 5)
         return matrix_element_ng5(precision, mom, eb, n, m_top, w_top, out, s);
+    if (process_id == MF_PP_TTXGG) {
+        // the q qbar channel (quark along +z), FP64
+        const uint64_t qb = (n * 32 + mf::kBlock - 1) / mf::kBlock;
+        if (n > (1ull << 36) || qb > 0x7FFFFFFFull)
+            return fail(MF_EINVAL, "too many events for one launch");
+        hipLaunchKernelGGL(mf::qqbar_ttxgg_me_kernel, dim3((unsigned)qb), dim3(mf::kBlock), 0, s, mom, eb, n, m_top,
+                           m_top * w_top, out);
+        MF_HIP(hipGetLastError());
+        MF_HIP(hipStreamSynchronize(s));
+        return MF_OK;
+    }
     if (process_id == MF_PP_TTXG) {
         // the q qbar channel (quark along +z), FP64
         const uint64_t qb = (n * 16 + mf::kBlock - 1) / mf::kBlock;

@@ -1,7 +1,7 @@
-"""GPU parity of p p -> t tbar and p p -> t tbar g (the g g channel plus the
-q qbar channels u ubar, ubar u, d dbar, dbar d; Sec. 3, Table 1) against the
-oracle: the q qbar |M|^2 for explicit momenta, per-event weights, a short
-integration, and the requests these processes refuse."""
+"""GPU parity of p p -> t tbar, t tbar g and t tbar g g (the g g channel
+plus the q qbar channels u ubar, ubar u, d dbar, dbar d; Sec. 3, Table 1)
+against the oracle: the q qbar |M|^2 for explicit momenta, per-event
+weights, a short integration, and the requests these processes refuse."""
 import sys
 
 import numpy as np
@@ -19,6 +19,7 @@ M = 173.0
 CASES = {
     "pp_ttx": (2, {}, 20_000, 20_000),
     "pp_ttxg": (3, dict(ptmin_g=20.0, etamax_g=2.5), 6_000, 3_000),
+    "pp_ttxgg": (4, dict(ptmin_g=20.0, drmin_gg=0.4), 1_500, 600),
 }
 
 
@@ -47,13 +48,14 @@ def test_qqbar_matrix_element(api, process):
     n_g = CASES[process][0]
     rng = np.random.default_rng(31)
     moms, ebs, refs = [], [], []
-    for _ in range(300 if n_g == 2 else 150):
+    for _ in range({2: 300, 3: 150, 4: 60}[n_g]):
         rs = 2 * M + 1.0 + rng.exponential(600.0)
         masses = [M, M] + [0.0] * (n_g - 2)
         k, w, st = O.phase_space(n_g, masses, rs, rng.random(3 * n_g - 4))
         E = rs / 2
         p = np.array([k[0], k[1], [-E, 0, 0, -E], [-E, 0, 0, E], *k[2:]])
-        refs.append(O.me2_qqbar_ttx(p, M) if n_g == 2 else O.me2_qqbar_ttxg(p, M, 1.5))
+        refs.append({2: lambda: O.me2_qqbar_ttx(p, M), 3: lambda: O.me2_qqbar_ttxg(p, M, 1.5),
+                     4: lambda: O.me2_qqbar_ttxgg(p, M, 1.5)}[n_g]())
         moms.append(k.reshape(-1))
         ebs.append(E)
     mom = torch.tensor(np.array(moms), dtype=torch.float64, device="cuda").contiguous()
