@@ -51,6 +51,14 @@ QQBAR_FLOPS = 8 * (2 * 14 + 64 + 11) + 15
 # of 312 (four chain contractions, the three-gluon term, the 5 x 5 colour
 # form) after a per-lane setup of 47, and two 8-lane sums.
 QQBAR_TTXG_FLOPS = 8 * (478 + 555) + 8 * 64 + 8 * 47 + 32 * 312 + 14
+# p p -> t tbar g g: 64 lanes per event (32 configurations per beam
+# orientation), each evaluating the 38 terms of the 36 diagrams on its own:
+# set-up and spinors (120), the composite current (158), the chains of the
+# two lines (bilinear 64, each further attachment 192 with its propagator)
+# and contractions per class (2992, 2992, 3398, 1792, 1524, 901, 1335), the
+# projection onto the 11 colour directions (3344) and its norm (43); then two
+# 32-lane sums.
+QQBAR_TTXGG_FLOPS = 64 * (120 + 158 + 2992 + 2992 + 3398 + 1792 + 1524 + 901 + 1335 + 3344 + 43) + 62
 
 WORKLOADS = {
     "ttx": dict(process="gg_ttx", n_g=2, cuts={}, events=1_000_000),
@@ -59,6 +67,7 @@ WORKLOADS = {
     "ttxggg": dict(process="gg_ttxggg", n_g=5, cuts=dict(ptmin_g=20.0, drmin_gg=0.4), events=1_000_000),
     "ppttx": dict(process="pp_ttx", n_g=2, cuts={}, events=10_000_000, quarks=True),
     "ppttxg": dict(process="pp_ttxg", n_g=3, cuts=dict(ptmin_g=20.0, etamax_g=2.5), events=10_000_000, quarks=True),
+    "ppttxgg": dict(process="pp_ttxgg", n_g=4, cuts=dict(ptmin_g=20.0, drmin_gg=0.4), events=1_000_000, quarks=True),
 }
 
 
@@ -342,7 +351,7 @@ def config_leg(api, torch, name, n_events, n_iter, seeds, events_note=""):
     wl = WORKLOADS[name]
     pdf = W.synthetic_pdf(quarks=wl.get("quarks", False))
     proc = api.Process(wl["process"], **wl["cuts"])
-    qq = {2: QQBAR_FLOPS, 3: QQBAR_TTXG_FLOPS}[wl["n_g"]] if wl.get("quarks") else 0
+    qq = {2: QQBAR_FLOPS, 3: QQBAR_TTXG_FLOPS, 4: QQBAR_TTXGG_FLOPS}[wl["n_g"]] if wl.get("quarks") else 0
     f_me, f_other = me_flops(wl["n_g"]) + qq, OTHER_FLOPS[wl["n_g"]]
     total, walls, sig, roof = 0, 0.0, [], []
     for seed in seeds:
@@ -423,7 +432,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="ttxgg", choices=sorted(k for k in WORKLOADS if k not in ("ttxggg", "ppttx", "ppttxg")))
+    ap.add_argument("--workload", default="ttxgg", choices=sorted(k for k in WORKLOADS if k not in ("ttxggg", "ppttx", "ppttxg", "ppttxgg")))
     ap.add_argument("--no-ttxggg", action="store_true", help="skip the g g -> t tbar g g g legs")
     ap.add_argument("--ttxggg-events", type=int, default=1_000_000)
     ap.add_argument("--ttxggg-only", action="store_true",
@@ -447,7 +456,7 @@ def main():
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the legs of the other workloads (g g -> t tbar at 1e5 x 5 and 1e8 x 5, "
                          "g g -> t tbar g at 1e7 x 10 for seeds 0-4, p p -> t tbar at 1e8 x 5, "
-                         "p p -> t tbar g at 1e7 x 10)")
+                         "p p -> t tbar g at 1e7 x 10, p p -> t tbar g g at 1e6 x 3)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device-to-device copy of this many bytes (3 times), "
                          "the reference kernel for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE")
@@ -472,9 +481,10 @@ def main():
     from paper_2106_10279_amd import api
 
     if args.pp_only:
-        log("[bench] p p -> t tbar, 1e8 x 5; p p -> t tbar g, 1e7 x 10")
+        log("[bench] p p -> t tbar, 1e8 x 5; p p -> t tbar g, 1e7 x 10; p p -> t tbar g g, 1e6 x 3")
         print(json.dumps({"pptx_1e8x5": config_leg(api, torch, "ppttx", 100_000_000, 5, [0]),
-                          "pptxg_1e7x10": config_leg(api, torch, "ppttxg", 10_000_000, 10, [0])}), flush=True)
+                          "pptxg_1e7x10": config_leg(api, torch, "ppttxg", 10_000_000, 10, [0]),
+                          "pptxgg_1e6x3": config_leg(api, torch, "ppttxgg", 1_000_000, 3, [0])}), flush=True)
         return
     if args.ttxggg_only:
         legs = {}
@@ -611,7 +621,7 @@ def main():
         log(f"[bench] helicity Monte Carlo done: {vh:.4g} events/s, weight variance x{var_ratio:.2f}")
     if not args.no_configs and args.workload == "ttxgg":
         log("[bench] g g -> t tbar, 1e5 x 5 and 1e8 x 5; g g -> t tbar g, 1e7 x 10, seeds 0-4; "
-            "p p -> t tbar, 1e8 x 5; p p -> t tbar g, 1e7 x 10")
+            "p p -> t tbar, 1e8 x 5; p p -> t tbar g, 1e7 x 10; p p -> t tbar g g, 1e6 x 3")
         out["ttx_1e5x5"] = config_leg(api, torch, "ttx", 100_000, 5, [0])
         out["ttx_1e8x5"] = config_leg(api, torch, "ttx", 100_000_000, 5, [0],
                                       " (the scaled run: 1e5 events do not fill 256 compute units)")
@@ -621,8 +631,11 @@ def main():
                                        "quark tables)")
         out["pptxg_1e7x10"] = config_leg(api, torch, "ppttxg", 10_000_000, 10, [0],
                                          " (g g and the q qbar channels; synthetic quark tables)")
+        out["pptxgg_1e6x3"] = config_leg(api, torch, "ppttxgg", 1_000_000, 3, [0],
+                                         " (g g and the q qbar channels; synthetic quark tables)")
         log(f"[bench] configs done: ttx {out['ttx_1e8x5']['value']:.4g}, ttxg {out['ttxg_1e7x10']['value']:.4g}, "
-            f"pp ttx {out['pptx_1e8x5']['value']:.4g}, pp ttxg {out['pptxg_1e7x10']['value']:.4g} events/s")
+            f"pp ttx {out['pptx_1e8x5']['value']:.4g}, pp ttxg {out['pptxg_1e7x10']['value']:.4g}, "
+            f"pp ttxgg {out['pptxgg_1e6x3']['value']:.4g} events/s")
     if not args.no_ttxggg and args.workload == "ttxgg":
         for prec in ("fp64", "fp32_kahan"):
             log(f"[bench] g g -> t tbar g g g, {args.ttxggg_events} events x {args.ttxggg_steps} iterations, {prec}")

@@ -60,38 +60,48 @@ __host__ __device__ __forceinline__ void q4_prop_row(const double* P, double m, 
         out[i] = cmul(cplx<double>(t[i].x + m * in[i].x, t[i].y + m * in[i].y), r);
 }
 
-// X^mu = row V_{n-1} S(P_{n-1}) ... S(P_1) V_0 col with V_a = e_a-slash,
-// except at the open slot s, which carries gamma^mu; P_a = p0 - q_0 - ... -
-// q_{a-1}.
+// X^mu = row V_{N-1} S(P_{N-1}) ... S(P_1) V_0 col with V_a = e_a-slash,
+// except at the open slot S, which carries gamma^mu; P_a = p0 - q_0 - ... -
+// q_{a-1}.  N and S are compile-time so that every array stays in registers.
+template <int N, int S>
 __host__ __device__ __forceinline__ void q4_chain(const cplx<double>* row, const cplx<double>* col, const double* p0,
-                                                  double m, double mw, int n, const Q4Att* att, int s,
-                                                  cplx<double>* X)
+                                                  double m, double mw, const Q4Att* att, cplx<double>* X)
 {
+    static_assert(N >= 1 && N <= 3 && S >= 0 && S < N, "chain shape");
     double P[4];
+#pragma unroll
     for (int mu = 0; mu < 4; ++mu)
         P[mu] = p0[mu];
     cplx<double> R[4], L[4], t[4];
+#pragma unroll
     for (int i = 0; i < 4; ++i)
         R[i] = col[i];
-    for (int a = 0; a < s; ++a) {
+#pragma unroll
+    for (int a = 0; a < S; ++a) {
         qq_slash_col(att[a].e, R, t);
+#pragma unroll
         for (int mu = 0; mu < 4; ++mu)
             P[mu] -= att[a].q[mu];
         q4_prop_col(P, m, mw, t, R);
     }
+#pragma unroll
     for (int mu = 0; mu < 4; ++mu)
-        P[mu] -= att[s].q[mu];
-    double Pt[3][4];
-    for (int a = s + 1; a < n; ++a)
+        P[mu] -= att[S].q[mu];
+    double Pt[N][4];
+#pragma unroll
+    for (int a = S + 1; a < N; ++a)
+#pragma unroll
         for (int mu = 0; mu < 4; ++mu) {
-            Pt[a - s - 1][mu] = P[mu];
+            Pt[a][mu] = P[mu];
             P[mu] -= att[a].q[mu];
         }
+#pragma unroll
     for (int i = 0; i < 4; ++i)
         L[i] = row[i];
-    for (int a = n - 1; a > s; --a) {
+#pragma unroll
+    for (int a = N - 1; a > S; --a) {
         qq_row_slash(L, att[a].e, t);
-        q4_prop_row(Pt[a - s - 1], m, mw, t, L);
+        q4_prop_row(Pt[a], m, mw, t, L);
     }
     bilinear(L, R, X);
 }
@@ -132,6 +142,7 @@ __host__ __device__ __forceinline__ void q4_set_open(Q4Att& a, const double* q)
 // Adds factor * A to the colour projections.
 __host__ __device__ __forceinline__ void q4_project(int d, cplx<double> A, cplx<double>* proj)
 {
+#pragma unroll
     for (int r = 0; r < QQ4_RANK; ++r) {
         const cplx<double> w(QQ4_W[r][d][0], QQ4_W[r][d][1]);
         const cplx<double> p = cmul(w, A);
@@ -169,6 +180,7 @@ __host__ __device__ __forceinline__ double qqbar_ttxgg_config(const double* __re
     spinor_ubar<double>(k1, mt, (c >> 3) & 1, ub);
     spinor_v<double>(k2, mt, (c >> 2) & 1, v);
     cplx<double> eps[2][4];
+#pragma unroll
     for (int g = 0; g < 2; ++g) {
         double e[4];
         qq_linear_pol(kg[g], (c >> g) & 1, e);
@@ -209,41 +221,51 @@ __host__ __device__ __forceinline__ double qqbar_ttxgg_config(const double* __re
     constexpr int perm3[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
     // terms 0-5: both gluons and the spine on the quark line; the top line is K
     q4_set_open(ta[0], mQ);
-    q4_chain(ub, v, mk2, mt, mw, 1, ta, 0, Xt);
+    q4_chain<1, 0>(ub, v, mk2, mt, mw, ta, Xt);
+#pragma unroll
     for (int o = 0; o < 6; ++o) {
-        int s = 0;
+#pragma unroll
         for (int t = 0; t < 3; ++t) {
             const int x = perm3[o][t];
             if (x < 2)
                 q4_set(qa[t], eps[x], kg[x]);
-            else {
+            else
                 q4_set_open(qa[t], Q);
-                s = t;
-            }
         }
-        q4_chain(vb, u, pa, 0.0, 0.0, 3, qa, s, Xq);
+        // the open slot: where 2 sits in perm3[o]
+        if (o == 4 || o == 5)
+            q4_chain<3, 0>(vb, u, pa, 0.0, 0.0, qa, Xq);
+        else if (o == 1 || o == 3)
+            q4_chain<3, 1>(vb, u, pa, 0.0, 0.0, qa, Xq);
+        else
+            q4_chain<3, 2>(vb, u, pa, 0.0, 0.0, qa, Xq);
         const cplx<double> A = qq_dot(Xq, Xt);
         q4_project(d++, cplx<double>(A.x / Q2, A.y / Q2), proj);
     }
     // terms 6-11: both on the top line; the quark line is J
     q4_set_open(qa[0], P0);
-    q4_chain(vb, u, pa, 0.0, 0.0, 1, qa, 0, Xq);
+    q4_chain<1, 0>(vb, u, pa, 0.0, 0.0, qa, Xq);
+#pragma unroll
     for (int o = 0; o < 6; ++o) {
-        int s = 0;
+#pragma unroll
         for (int t = 0; t < 3; ++t) {
             const int x = perm3[o][t];
             if (x < 2)
                 q4_set(ta[t], eps[x], kg[x]);
-            else {
+            else
                 q4_set_open(ta[t], mP0);
-                s = t;
-            }
         }
-        q4_chain(ub, v, mk2, mt, mw, 3, ta, s, Xt);
+        if (o == 4 || o == 5)
+            q4_chain<3, 0>(ub, v, mk2, mt, mw, ta, Xt);
+        else if (o == 1 || o == 3)
+            q4_chain<3, 1>(ub, v, mk2, mt, mw, ta, Xt);
+        else
+            q4_chain<3, 2>(ub, v, mk2, mt, mw, ta, Xt);
         const cplx<double> A = qq_dot(Xq, Xt);
         q4_project(d++, cplx<double>(A.x / P02, A.y / P02), proj);
     }
     // terms 12-19: ga on the quark line, gb on the top line
+#pragma unroll
     for (int ga = 0; ga < 2; ++ga) {
         const int gb = 1 - ga;
         double Pq[4], mPq[4];
@@ -252,14 +274,22 @@ __host__ __device__ __forceinline__ double qqbar_ttxgg_config(const double* __re
             mPq[mu] = -Pq[mu];
         }
         const double Pq2 = qq_m2(Pq);
+#pragma unroll
         for (int oq = 0; oq < 2; ++oq) {
             q4_set(qa[oq], eps[ga], kg[ga]);
             q4_set_open(qa[1 - oq], Pq);
-            q4_chain(vb, u, pa, 0.0, 0.0, 2, qa, 1 - oq, Xq);
+            if (oq == 0)
+                q4_chain<2, 1>(vb, u, pa, 0.0, 0.0, qa, Xq);
+            else
+                q4_chain<2, 0>(vb, u, pa, 0.0, 0.0, qa, Xq);
+#pragma unroll
             for (int ot = 0; ot < 2; ++ot) {
                 q4_set(ta[ot], eps[gb], kg[gb]);
                 q4_set_open(ta[1 - ot], mPq);
-                q4_chain(ub, v, mk2, mt, mw, 2, ta, 1 - ot, Xt);
+                if (ot == 0)
+                    q4_chain<2, 1>(ub, v, mk2, mt, mw, ta, Xt);
+                else
+                    q4_chain<2, 0>(ub, v, mk2, mt, mw, ta, Xt);
                 const cplx<double> A = qq_dot(Xq, Xt);
                 q4_project(d++, cplx<double>(A.x / Pq2, A.y / Pq2), proj);
             }
@@ -267,17 +297,22 @@ __host__ __device__ __forceinline__ double qqbar_ttxgg_config(const double* __re
     }
     // terms 20-23: ga on the spine, gb on the quark line; the top line is K
     q4_set_open(ta[0], mQ);
-    q4_chain(ub, v, mk2, mt, mw, 1, ta, 0, Xt);
+    q4_chain<1, 0>(ub, v, mk2, mt, mw, ta, Xt);
+#pragma unroll
     for (int ga = 0; ga < 2; ++ga) {
         const int gb = 1 - ga;
         double Pq[4];
         for (int mu = 0; mu < 4; ++mu)
             Pq[mu] = P0[mu] - kg[gb][mu];
         const double den = qq_m2(Pq) * Q2;
+#pragma unroll
         for (int oq = 0; oq < 2; ++oq) {
             q4_set(qa[oq], eps[gb], kg[gb]);
             q4_set_open(qa[1 - oq], Pq);
-            q4_chain(vb, u, pa, 0.0, 0.0, 2, qa, 1 - oq, Xq);
+            if (oq == 0)
+                q4_chain<2, 1>(vb, u, pa, 0.0, 0.0, qa, Xq);
+            else
+                q4_chain<2, 0>(vb, u, pa, 0.0, 0.0, qa, Xq);
             q4_v3(Xq, Pq, eps[ga], kg[ga], J1);
             const cplx<double> A = qq_dot(J1, Xt);
             q4_project(d++, q4_times(cplx<double>(A.x / den, A.y / den), 1), proj);
@@ -285,7 +320,8 @@ __host__ __device__ __forceinline__ double qqbar_ttxgg_config(const double* __re
     }
     // terms 24-27: ga on the spine, gb on the top line; the quark line is J
     q4_set_open(qa[0], P0);
-    q4_chain(vb, u, pa, 0.0, 0.0, 1, qa, 0, Xq);
+    q4_chain<1, 0>(vb, u, pa, 0.0, 0.0, qa, Xq);
+#pragma unroll
     for (int ga = 0; ga < 2; ++ga) {
         const int gb = 1 - ga;
         double Pt[4], mPt[4];
@@ -295,17 +331,22 @@ __host__ __device__ __forceinline__ double qqbar_ttxgg_config(const double* __re
         }
         const double den = P02 * qq_m2(Pt);
         q4_v3(Xq, P0, eps[ga], kg[ga], J1);
+#pragma unroll
         for (int ot = 0; ot < 2; ++ot) {
             q4_set(ta[ot], eps[gb], kg[gb]);
             q4_set_open(ta[1 - ot], mPt);
-            q4_chain(ub, v, mk2, mt, mw, 2, ta, 1 - ot, Xt);
+            if (ot == 0)
+                q4_chain<2, 1>(ub, v, mk2, mt, mw, ta, Xt);
+            else
+                q4_chain<2, 0>(ub, v, mk2, mt, mw, ta, Xt);
             const cplx<double> A = qq_dot(J1, Xt);
             q4_project(d++, q4_times(cplx<double>(A.x / den, A.y / den), 1), proj);
         }
     }
     // terms 28-32: both on the spine (Xq = J with P0, Xt = K with Q)
     q4_set_open(ta[0], mQ);
-    q4_chain(ub, v, mk2, mt, mw, 1, ta, 0, Xt);
+    q4_chain<1, 0>(ub, v, mk2, mt, mw, ta, Xt);
+#pragma unroll
     for (int ga = 0; ga < 2; ++ga) {
         const int gb = 1 - ga;
         double P1[4];
@@ -327,17 +368,25 @@ __host__ __device__ __forceinline__ double qqbar_ttxgg_config(const double* __re
         q4_project(d++, q4_times(cplx<double>((a3.x - a1.x) / den, (a3.y - a1.y) / den), 2), proj);
     }
     // terms 33-37: the composite
+#pragma unroll
     for (int oq = 0; oq < 2; ++oq) {        // on the quark line; the top line is K (Xt)
         q4_set(qa[oq], J12, K);
         q4_set_open(qa[1 - oq], Q);
-        q4_chain(vb, u, pa, 0.0, 0.0, 2, qa, 1 - oq, J1);
+        if (oq == 0)
+            q4_chain<2, 1>(vb, u, pa, 0.0, 0.0, qa, J1);
+        else
+            q4_chain<2, 0>(vb, u, pa, 0.0, 0.0, qa, J1);
         const cplx<double> A = qq_dot(J1, Xt);
         q4_project(d++, q4_times(cplx<double>(A.x / Q2, A.y / Q2), 1), proj);
     }
+#pragma unroll
     for (int ot = 0; ot < 2; ++ot) {        // on the top line; the quark line is J (Xq)
         q4_set(ta[ot], J12, K);
         q4_set_open(ta[1 - ot], mP0);
-        q4_chain(ub, v, mk2, mt, mw, 2, ta, 1 - ot, J1);
+        if (ot == 0)
+            q4_chain<2, 1>(ub, v, mk2, mt, mw, ta, J1);
+        else
+            q4_chain<2, 0>(ub, v, mk2, mt, mw, ta, J1);
         const cplx<double> A = qq_dot(Xq, J1);
         q4_project(d++, q4_times(cplx<double>(A.x / P02, A.y / P02), 1), proj);
     }
