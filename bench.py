@@ -52,13 +52,13 @@ QQBAR_FLOPS = 8 * (2 * 14 + 64 + 11) + 15
 # form) after a per-lane setup of 47, and two 8-lane sums.
 QQBAR_TTXG_FLOPS = 8 * (478 + 555) + 8 * 64 + 8 * 47 + 32 * 312 + 14
 # p p -> t tbar g g: 64 lanes per event (32 configurations per beam
-# orientation), each evaluating the 38 terms of the 36 diagrams on its own:
-# set-up and spinors (120), the composite current (158), the chains of the
-# two lines (bilinear 64, each further attachment 192 with its propagator)
-# and contractions per class (2992, 2992, 3398, 1792, 1524, 901, 1335), the
-# projection onto the 11 colour directions (3344) and its norm (43); then two
-# 32-lane sums.
-QQBAR_TTXGG_FLOPS = 64 * (120 + 158 + 2992 + 2992 + 3398 + 1792 + 1524 + 901 + 1335 + 3344 + 43) + 62
+# orientation), each evaluating the 38 terms of the 36 diagrams on its own.
+# Its source repeats chains that the compiler shares between terms (the same
+# line with the same gluon appears in several classes), so the count is the
+# one measured: SQ_INSTS_VALU_FLOPS_FP64 x 64 per passing event (rocprofv3
+# over four 1e6-event launches, 3.03e12 flops for 3.65e6 events), below the
+# 1.19e6 that the source's operations add up to.
+QQBAR_TTXGG_FLOPS = 831_000
 
 WORKLOADS = {
     "ttx": dict(process="gg_ttx", n_g=2, cuts={}, events=1_000_000),
