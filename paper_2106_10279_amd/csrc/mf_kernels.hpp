@@ -1517,23 +1517,36 @@ __global__ void __launch_bounds__(kBlock) qqbar_ttxg_me_kernel(const double* __r
 }
 
 // p p -> t tbar g g: the q qbar amplitudes of the batch's live events, one
-// wave per event: lane = orientation x 32 + configuration (the 32 with the
-// antiquark spin opposite the quark's); the sums go to me_q[e] (quark along
-// +z) and me_q[count + e].
-__global__ void __launch_bounds__(kBlock) qqbar_ttxgg_kernel(StageParams S)
+// one-wave workgroup per event.  The wave first builds the event's 344
+// helicity-recycled objects (currents and line chains, mf_qqbar_ttxgg.hpp)
+// into LDS, then lane = orientation x 32 + configuration (the 32 with the
+// antiquark spin opposite the quark's) contracts them; the sums go to
+// me_q[e] (quark along +z) and me_q[count + e].
+__global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(2))) qqbar_ttxgg_kernel(StageParams S)
 {
-    const int lane = threadIdx.x % kWave;
-    const uint64_t i = (uint64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+    __shared__ __align__(16) cplx<double> s_ob[kQ4Objects][4];
+    __shared__ double s_mom[17];
+    const int lane = threadIdx.x;
+    const uint64_t i = blockIdx.x;
     const uint64_t n_ev = S.live ? (uint64_t)*S.n_live : S.count;
     const uint64_t e = i < n_ev ? (S.live ? (uint64_t)S.live[i] : i) : S.count;
-    const bool live = e < S.count && S.pref[e] != 0.0;
-    double v = 0.0;
-    if (live) {
-        const double* mom = S.mom + e * 17;
-        v = qqbar_ttxgg_config(mom, mom[16], S.P.m_top, S.P.mw, lane & 31, lane >> 5);
-    }
+    if (e >= S.count || S.pref[e] == 0.0)
+        return;                                  // uniform over the workgroup
+    if (lane < 17)
+        s_mom[lane] = S.mom[e * 17 + lane];
+    __syncthreads();
+    const Q4Kin kin = q4_kinematics(s_mom, s_mom[16], S.P.m_top, S.P.mw);
+    // one object type per pass of the wave, so that its lanes do not diverge
+    // between the types' code
+    constexpr int kTypeStart[9] = {kQ4J, kQ4Q1, kQ4T2, kQ4Q3, kQ4T3, kQ4Q7, kQ4T7, kQ4V5, kQ4Objects};
+#pragma unroll 1
+    for (int t = 0; t < 8; ++t)
+        for (int idx = kTypeStart[t] + lane; idx < kTypeStart[t + 1]; idx += kWave)
+            q4_object(kin, idx, s_ob[idx]);
+    __syncthreads();
+    double v = q4_config_from_objects(kin, s_ob, lane & 31, lane >> 5);
     v = group_sum(v, 32);
-    if (live && (lane & 31) == 0)
+    if ((lane & 31) == 0)
         S.me_q[(uint64_t)(lane >> 5) * S.count + e] = v;
 }
 

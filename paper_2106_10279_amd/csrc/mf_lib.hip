@@ -453,11 +453,10 @@ mf_status launch_stages(const mf::StageParams& S, int kin_blocks, int n_cu, hipS
         MF_HIP(hipGetLastError());
     }
     if (NG == 4 && S.P.pp) {
-        // the q qbar channel of t tbar g g (FP64): one wave per event
-        const uint64_t qb = (S.count + mf::kWavesPerBlock - 1) / mf::kWavesPerBlock;
-        if (qb > 0x7FFFFFFFull)
+        // the q qbar channel of t tbar g g (FP64): one one-wave workgroup per event
+        if (S.count > 0x7FFFFFFFull)
             return fail(MF_EINVAL, "too many events for one launch");
-        hipLaunchKernelGGL(mf::qqbar_ttxgg_kernel, dim3((unsigned)qb), dim3(mf::kBlock), 0, stream, S);
+        hipLaunchKernelGGL(mf::qqbar_ttxgg_kernel, dim3((unsigned)S.count), dim3(mf::kWave), 0, stream, S);
         MF_HIP(hipGetLastError());
     }
     if (amp_end)

@@ -403,3 +403,352 @@ __host__ __device__ __forceinline__ double qqbar_ttxgg_config(const double* __re
 }
 
 }  // namespace mf
+
+namespace mf {
+
+// ---------------------------------------------------------------------------
+// Helicity recycling.  The terms depend on the helicity configuration only
+// through a few objects, each a function of a subset of the helicity bits:
+// the currents J (orientation, quark spin) and K (top spins); the quark-line
+// chains with both gluons (6 orders x orientation, quark spin, two
+// polarisations), with one gluon (gluon, order x orientation, quark spin,
+// its polarisation), with the composite (order x orientation, quark spin,
+// polarisations); the top-line chains likewise (top spins in place of
+// orientation and quark spin); J after a three-gluon vertex with one gluon.
+// One wave per event builds these 348 objects into LDS, then each lane
+// contracts them for one configuration.
+// ---------------------------------------------------------------------------
+constexpr int kQ4J = 0, kQ4K = 4, kQ4Q1 = 8, kQ4T2 = 104, kQ4Q3 = 200, kQ4T3 = 232, kQ4Q7 = 264, kQ4T7 = 296,
+              kQ4V5 = 328, kQ4Objects = 344;
+
+struct Q4Kin {
+    const double* k1;
+    const double* k2;
+    const double* kg[2];
+    double eb, mt, mw;
+    double P0[4], Q[4], K[4], mk2[4];
+};
+
+// kin.kg[g] without indexing the struct's array by a run-time value (which
+// would place the struct in scratch memory)
+__host__ __device__ __forceinline__ const double* q4_kg(const Q4Kin& kin, int g)
+{
+    return g ? kin.kg[1] : kin.kg[0];
+}
+
+__host__ __device__ __forceinline__ void q4_beam_spinors(const Q4Kin& kin, int rev, int sq, cplx<double>* u,
+                                                         cplx<double>* vb, const double*& pa)
+{
+    const double pz[4] = {kin.eb, 0.0, 0.0, kin.eb}, mz[4] = {kin.eb, 0.0, 0.0, -kin.eb};
+    cplx<double> a[4], b[4];
+    spinor_ubar<double>(rev ? mz : pz, 0.0, sq, a);
+    spinor_v<double>(rev ? pz : mz, 0.0, sq ^ 1, b);
+    for (int i = 0; i < 4; ++i) {
+        u[i] = cplx<double>(a[(i + 2) & 3].x, -a[(i + 2) & 3].y);
+        vb[i] = cplx<double>(b[(i + 2) & 3].x, -b[(i + 2) & 3].y);
+    }
+    (void)pa;
+}
+
+__host__ __device__ __forceinline__ void q4_pol(const Q4Kin& kin, int g, int h, cplx<double>* e)
+{
+    double ep[4];
+    qq_linear_pol(q4_kg(kin, g), h, ep);
+    qq_real(ep, e);
+}
+
+// The composite current of polarisations (h1, h2).
+__host__ __device__ __forceinline__ void q4_composite(const Q4Kin& kin, int h1, int h2, cplx<double>* J12)
+{
+    cplx<double> e1[4], e2[4];
+    q4_pol(kin, 0, h1, e1);
+    q4_pol(kin, 1, h2, e2);
+    double Kk3[4], k43[4], Kk4[4];
+    for (int mu = 0; mu < 4; ++mu) {
+        Kk3[mu] = kin.K[mu] + kin.kg[0][mu];
+        k43[mu] = kin.kg[1][mu] - kin.kg[0][mu];
+        Kk4[mu] = kin.K[mu] + kin.kg[1][mu];
+    }
+    const cplx<double> x = qq_dotr(e2, Kk3), y = qq_dot(e1, e2), z = qq_dotr(e1, Kk4);
+    const double rK = 1.0 / qq_m2(kin.K);
+    for (int mu = 0; mu < 4; ++mu) {
+        const cplx<double> p1 = cmul(e1[mu], x), p3 = cmul(e2[mu], z);
+        J12[mu] = cplx<double>((p1.x + y.x * k43[mu] - p3.x) * rK, (p1.y + y.y * k43[mu] - p3.y) * rK);
+    }
+}
+
+// A chain with both gluons and the spine (momentum q_spine) in order O of
+// perm3 (0, 1: the gluons, 2: the spine), compile-time so that every array
+// index is static.
+template <int O>
+__device__ __forceinline__ void q4_chain3(const Q4Kin& kin, const cplx<double>* row, const cplx<double>* col,
+                                          const double* p0, double m, double mw, const cplx<double> (*eps)[4],
+                                          const double* qs, cplx<double>* out)
+{
+    constexpr int perm3[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+    constexpr int S = perm3[O][0] == 2 ? 0 : (perm3[O][1] == 2 ? 1 : 2);
+    Q4Att at[3];
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+        const int x = perm3[O][t];
+        if (x < 2)
+            q4_set(at[t], eps[x], q4_kg(kin, x));
+        else
+            q4_set_open(at[t], qs);
+    }
+    q4_chain<3, S>(row, col, p0, m, mw, at, out);
+}
+
+__device__ __forceinline__ void q4_chain3_any(int o, const Q4Kin& kin, const cplx<double>* row,
+                                              const cplx<double>* col, const double* p0, double m, double mw,
+                                              const cplx<double> (*eps)[4], const double* qs, cplx<double>* out)
+{
+    switch (o) {
+    case 0: q4_chain3<0>(kin, row, col, p0, m, mw, eps, qs, out); break;
+    case 1: q4_chain3<1>(kin, row, col, p0, m, mw, eps, qs, out); break;
+    case 2: q4_chain3<2>(kin, row, col, p0, m, mw, eps, qs, out); break;
+    case 3: q4_chain3<3>(kin, row, col, p0, m, mw, eps, qs, out); break;
+    case 4: q4_chain3<4>(kin, row, col, p0, m, mw, eps, qs, out); break;
+    default: q4_chain3<5>(kin, row, col, p0, m, mw, eps, qs, out); break;
+    }
+}
+
+// A chain with one attachment (polarisation or current e, momentum q) at
+// slot first ? 0 : 1 and the spine (momentum qs) at the other.
+__device__ __forceinline__ void q4_chain2_any(bool first, const cplx<double>* row, const cplx<double>* col,
+                                              const double* p0, double m, double mw, const cplx<double>* e,
+                                              const double* q, const double* qs, cplx<double>* out)
+{
+    Q4Att at[2];
+    if (first) {
+        q4_set(at[0], e, q);
+        q4_set_open(at[1], qs);
+        q4_chain<2, 1>(row, col, p0, m, mw, at, out);
+    } else {
+        q4_set_open(at[0], qs);
+        q4_set(at[1], e, q);
+        q4_chain<2, 0>(row, col, p0, m, mw, at, out);
+    }
+}
+
+// Object idx (0 .. kQ4Objects - 1) of the event into out.
+__device__ __forceinline__ void q4_object(const Q4Kin& kin, int idx, cplx<double>* out)
+{
+    cplx<double> u[4], vb[4], ub[4], v[4];
+    const double* pa_unused = nullptr;
+    const double pz[4] = {kin.eb, 0.0, 0.0, kin.eb}, mz[4] = {kin.eb, 0.0, 0.0, -kin.eb};
+    if (idx < kQ4K) {                                   // J (orientation, quark spin)
+        q4_beam_spinors(kin, idx >> 1, idx & 1, u, vb, pa_unused);
+        bilinear(vb, u, out);
+    } else if (idx < kQ4Q1) {                           // K (top, antitop spin)
+        const int i = idx - kQ4K;
+        spinor_ubar<double>(kin.k1, kin.mt, i >> 1, ub);
+        spinor_v<double>(kin.k2, kin.mt, i & 1, v);
+        bilinear(ub, v, out);
+    } else if (idx < kQ4T2) {                           // quark line: both gluons, 6 orders
+        const int i = idx - kQ4Q1, o = i >> 4, b = i & 15;
+        const int rev = b >> 3, sq = (b >> 2) & 1;
+        q4_beam_spinors(kin, rev, sq, u, vb, pa_unused);
+        cplx<double> eps[2][4];
+        q4_pol(kin, 0, (b >> 1) & 1, eps[0]);
+        q4_pol(kin, 1, b & 1, eps[1]);
+        q4_chain3_any(o, kin, vb, u, rev ? mz : pz, 0.0, 0.0, eps, kin.Q, out);
+    } else if (idx < kQ4Q3) {                           // top line: both gluons, 6 orders
+        const int i = idx - kQ4T2, o = i >> 4, b = i & 15;
+        spinor_ubar<double>(kin.k1, kin.mt, b >> 3, ub);
+        spinor_v<double>(kin.k2, kin.mt, (b >> 2) & 1, v);
+        cplx<double> eps[2][4];
+        q4_pol(kin, 0, (b >> 1) & 1, eps[0]);
+        q4_pol(kin, 1, b & 1, eps[1]);
+        double mP0[4];
+        for (int mu = 0; mu < 4; ++mu)
+            mP0[mu] = -kin.P0[mu];
+        q4_chain3_any(o, kin, ub, v, kin.mk2, kin.mt, kin.mw, eps, mP0, out);
+    } else if (idx < kQ4T3) {                           // quark line: gluon g at slot oq, spine P0 - k_g
+        const int i = idx - kQ4Q3, g = i >> 4, oq = (i >> 3) & 1, b = i & 7;
+        const int rev = b >> 2, sq = (b >> 1) & 1;
+        q4_beam_spinors(kin, rev, sq, u, vb, pa_unused);
+        cplx<double> e[4];
+        q4_pol(kin, g, b & 1, e);
+        double Pq[4];
+        for (int mu = 0; mu < 4; ++mu)
+            Pq[mu] = kin.P0[mu] - q4_kg(kin, g)[mu];
+        q4_chain2_any(oq == 0, vb, u, rev ? mz : pz, 0.0, 0.0, e, q4_kg(kin, g), Pq, out);
+    } else if (idx < kQ4Q7) {                           // top line: gluon g at slot ot, spine -(P0 - k_other)
+        const int i = idx - kQ4T3, g = i >> 4, ot = (i >> 3) & 1, b = i & 7;
+        spinor_ubar<double>(kin.k1, kin.mt, b >> 2, ub);
+        spinor_v<double>(kin.k2, kin.mt, (b >> 1) & 1, v);
+        cplx<double> e[4];
+        q4_pol(kin, g, b & 1, e);
+        double mPt[4];
+        for (int mu = 0; mu < 4; ++mu)
+            mPt[mu] = -(kin.P0[mu] - q4_kg(kin, 1 - g)[mu]);
+        q4_chain2_any(ot == 0, ub, v, kin.mk2, kin.mt, kin.mw, e, q4_kg(kin, g), mPt, out);
+    } else if (idx < kQ4T7) {                           // quark line: the composite at slot oq, spine Q
+        const int i = idx - kQ4Q7, oq = i >> 4, b = i & 15;
+        const int rev = b >> 3, sq = (b >> 2) & 1;
+        q4_beam_spinors(kin, rev, sq, u, vb, pa_unused);
+        cplx<double> J12[4];
+        q4_composite(kin, (b >> 1) & 1, b & 1, J12);
+        q4_chain2_any(oq == 0, vb, u, rev ? mz : pz, 0.0, 0.0, J12, kin.K, kin.Q, out);
+    } else if (idx < kQ4V5) {                           // top line: the composite at slot ot, spine -P0
+        const int i = idx - kQ4T7, ot = i >> 4, b = i & 15;
+        spinor_ubar<double>(kin.k1, kin.mt, b >> 3, ub);
+        spinor_v<double>(kin.k2, kin.mt, (b >> 2) & 1, v);
+        cplx<double> J12[4];
+        q4_composite(kin, (b >> 1) & 1, b & 1, J12);
+        double mP0[4];
+        for (int mu = 0; mu < 4; ++mu)
+            mP0[mu] = -kin.P0[mu];
+        q4_chain2_any(ot == 0, ub, v, kin.mk2, kin.mt, kin.mw, J12, kin.K, mP0, out);
+    } else {                                            // J after gluon g: v3(J, P0, eps_g, k_g)
+        const int i = idx - kQ4V5, g = i >> 3, b = i & 7;
+        q4_beam_spinors(kin, b >> 2, (b >> 1) & 1, u, vb, pa_unused);
+        cplx<double> J[4], e[4];
+        bilinear(vb, u, J);
+        q4_pol(kin, g, b & 1, e);
+        q4_v3(J, kin.P0, e, q4_kg(kin, g), out);
+    }
+}
+
+// |M|^2 of configuration c (bits as qqbar_ttxgg_config), orientation rev,
+// from the event's objects in LDS.
+__device__ __forceinline__ double q4_config_from_objects(const Q4Kin& kin, const cplx<double> (*ob)[4], int c, int rev)
+{
+    const int l1 = c & 1, l2 = (c >> 1) & 1, stb = (c >> 2) & 1, st = (c >> 3) & 1, sq = (c >> 4) & 1;
+    const int lam[2] = {l1, l2};
+    const int bq = (rev << 3) | (sq << 2) | (l1 << 1) | l2;
+    const int bt = (st << 3) | (stb << 2) | (l1 << 1) | l2;
+    const cplx<double>* J = ob[kQ4J + ((rev << 1) | sq)];
+    const cplx<double>* K = ob[kQ4K + ((st << 1) | stb)];
+    cplx<double> eps[2][4];
+    q4_pol(kin, 0, l1, eps[0]);
+    q4_pol(kin, 1, l2, eps[1]);
+    const double P02 = qq_m2(kin.P0), Q2 = qq_m2(kin.Q);
+    cplx<double> proj[QQ4_RANK];
+#pragma unroll
+    for (int r = 0; r < QQ4_RANK; ++r)
+        proj[r] = cplx<double>(0.0, 0.0);
+    cplx<double> J1[4], J2[4];
+    int d = 0;
+#pragma unroll
+    for (int o = 0; o < 6; ++o) {
+        const cplx<double> A = qq_dot(ob[kQ4Q1 + 16 * o + bq], K);
+        q4_project(d++, cplx<double>(A.x / Q2, A.y / Q2), proj);
+    }
+#pragma unroll
+    for (int o = 0; o < 6; ++o) {
+        const cplx<double> A = qq_dot(J, ob[kQ4T2 + 16 * o + bt]);
+        q4_project(d++, cplx<double>(A.x / P02, A.y / P02), proj);
+    }
+    // the one-gluon chains: quark (g, oq; rev, sq, lam_g), top (g, ot; st, stb, lam_g)
+    auto qidx = [&](int g, int oq) { return kQ4Q3 + 16 * g + 8 * oq + ((rev << 2) | (sq << 1) | lam[g]); };
+    auto tidx = [&](int g, int ot) { return kQ4T3 + 16 * g + 8 * ot + ((st << 2) | (stb << 1) | lam[g]); };
+#pragma unroll
+    for (int ga = 0; ga < 2; ++ga) {                    // terms 12-19
+        const int gb = 1 - ga;
+        double Pq[4];
+        for (int mu = 0; mu < 4; ++mu)
+            Pq[mu] = kin.P0[mu] - q4_kg(kin, ga)[mu];
+        const double Pq2 = qq_m2(Pq);
+#pragma unroll
+        for (int oq = 0; oq < 2; ++oq)
+#pragma unroll
+            for (int ot = 0; ot < 2; ++ot) {
+                const cplx<double> A = qq_dot(ob[qidx(ga, oq)], ob[tidx(gb, ot)]);
+                q4_project(d++, cplx<double>(A.x / Pq2, A.y / Pq2), proj);
+            }
+    }
+#pragma unroll
+    for (int ga = 0; ga < 2; ++ga) {                    // terms 20-23
+        const int gb = 1 - ga;
+        double Pq[4];
+        for (int mu = 0; mu < 4; ++mu)
+            Pq[mu] = kin.P0[mu] - q4_kg(kin, gb)[mu];
+        const double den = qq_m2(Pq) * Q2;
+#pragma unroll
+        for (int oq = 0; oq < 2; ++oq) {
+            q4_v3(ob[qidx(gb, oq)], Pq, eps[ga], q4_kg(kin, ga), J1);
+            const cplx<double> A = qq_dot(J1, K);
+            q4_project(d++, q4_times(cplx<double>(A.x / den, A.y / den), 1), proj);
+        }
+    }
+    auto vidx = [&](int g) { return kQ4V5 + 8 * g + ((rev << 2) | (sq << 1) | lam[g]); };
+#pragma unroll
+    for (int ga = 0; ga < 2; ++ga) {                    // terms 24-27
+        const int gb = 1 - ga;
+        double Pt[4];
+        for (int mu = 0; mu < 4; ++mu)
+            Pt[mu] = kin.P0[mu] - q4_kg(kin, ga)[mu];
+        const double den = P02 * qq_m2(Pt);
+#pragma unroll
+        for (int ot = 0; ot < 2; ++ot) {
+            const cplx<double> A = qq_dot(ob[vidx(ga)], ob[tidx(gb, ot)]);
+            q4_project(d++, q4_times(cplx<double>(A.x / den, A.y / den), 1), proj);
+        }
+    }
+#pragma unroll
+    for (int ga = 0; ga < 2; ++ga) {                    // terms 28-29
+        const int gb = 1 - ga;
+        double P1[4];
+        for (int mu = 0; mu < 4; ++mu)
+            P1[mu] = kin.P0[mu] - q4_kg(kin, ga)[mu];
+        q4_v3(ob[vidx(ga)], P1, eps[gb], q4_kg(kin, gb), J2);
+        const double den = P02 * qq_m2(P1) * Q2;
+        const cplx<double> A = qq_dot(J2, K);
+        q4_project(d++, q4_times(cplx<double>(A.x / den, A.y / den), 2), proj);
+    }
+    {                                                   // terms 30-32
+        const cplx<double> q2 = qq_dot(J, eps[1]), q1 = qq_dot(J, eps[0]), qt = qq_dot(J, K);
+        const cplx<double> t1 = qq_dot(eps[0], K), t2 = qq_dot(eps[1], K), e12 = qq_dot(eps[0], eps[1]);
+        const double den = P02 * Q2;
+        const cplx<double> a1 = cmul(q2, t1), a2 = cmul(qt, e12), a3 = cmul(q1, t2);
+        q4_project(d++, q4_times(cplx<double>((a1.x - a2.x) / den, (a1.y - a2.y) / den), 2), proj);
+        q4_project(d++, q4_times(cplx<double>((a3.x - a2.x) / den, (a3.y - a2.y) / den), 2), proj);
+        q4_project(d++, q4_times(cplx<double>((a3.x - a1.x) / den, (a3.y - a1.y) / den), 2), proj);
+    }
+#pragma unroll
+    for (int oq = 0; oq < 2; ++oq) {                    // terms 33-34
+        const cplx<double> A = qq_dot(ob[kQ4Q7 + 16 * oq + bq], K);
+        q4_project(d++, q4_times(cplx<double>(A.x / Q2, A.y / Q2), 1), proj);
+    }
+#pragma unroll
+    for (int ot = 0; ot < 2; ++ot) {                    // terms 35-36
+        const cplx<double> A = qq_dot(J, ob[kQ4T7 + 16 * ot + bt]);
+        q4_project(d++, q4_times(cplx<double>(A.x / P02, A.y / P02), 1), proj);
+    }
+    {                                                   // term 37
+        cplx<double> J12[4];
+        q4_composite(kin, l1, l2, J12);
+        q4_v3(J, kin.P0, J12, kin.K, J1);
+        const double den = P02 * Q2;
+        const cplx<double> A = qq_dot(J1, K);
+        q4_project(d++, q4_times(cplx<double>(A.x / den, A.y / den), 2), proj);
+    }
+    double sum = 0.0;
+#pragma unroll
+    for (int r = 0; r < QQ4_RANK; ++r)
+        sum += proj[r].x * proj[r].x + proj[r].y * proj[r].y;
+    return sum;
+}
+
+__host__ __device__ __forceinline__ Q4Kin q4_kinematics(const double* mom, double eb, double mt, double mw)
+{
+    Q4Kin k;
+    k.k1 = mom;
+    k.k2 = mom + 4;
+    k.kg[0] = mom + 8;
+    k.kg[1] = mom + 12;
+    k.eb = eb;
+    k.mt = mt;
+    k.mw = mw;
+    for (int mu = 0; mu < 4; ++mu) {
+        k.P0[mu] = mu == 0 ? 2.0 * eb : 0.0;
+        k.Q[mu] = mom[mu] + mom[4 + mu];
+        k.K[mu] = mom[8 + mu] + mom[12 + mu];
+        k.mk2[mu] = -mom[4 + mu];
+    }
+    return k;
+}
+
+}  // namespace mf
