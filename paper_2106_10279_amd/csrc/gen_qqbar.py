@@ -2,13 +2,16 @@
 g g, Sec. 3, Table 1: 36 Feynman diagrams per quark group), written by
 gen_amplitudes.py into _gen/qqbar_ttxgg.inc.
 
-The device code evaluates the Lorentz part A_d of 38 terms per helicity
+The device code evaluates the Lorentz part a_d of 38 terms per helicity
 configuration (the 36 diagrams, the four-gluon vertex split into its three
-colour structures), in the order of TERMS below.  The colour sum
-sum_colours |sum_d C_d A_d|^2 = sum_de A_d K_de conj(A_e) with K_de =
-sum_colours C_d conj(C_e) is Hermitian and positive semi-definite of low
-rank; with K = sum_r lam_r v_r v_r^dagger it is sum_r |sum_d W_rd A_d|^2,
-W_rd = sqrt(lam_r) v_r[d], over the r with lam_r > 0.  K comes from an
+colour structures), in the order of TERMS below, without the factors of i
+that the Feynman rules give each class (PHASES below: 1, i or -1).  The
+colour sum sum_colours |sum_d C_d phi_d a_d|^2 = sum_de a_d K_de conj(a_e),
+K_de = phi_d conj(phi_e) sum_colours C_d conj(C_e), is Hermitian, positive
+semi-definite and of low rank; with the class phases inside, K is real, so
+K = sum_r lam_r v_r v_r^T with real v_r and the colour sum is
+sum_r |sum_d W_rd a_d|^2 with the real W_rd = sqrt(lam_r) v_r[d], over the r
+with lam_r > 0.  The colour factors come from an
 explicit sum over the 3^4 8^2 colour assignments of each term's colour
 factor: products of T = lambda/2 along the quark line (v-bar index j to u
 index i) and the top line (u-bar index k to v index l) and structure
@@ -79,6 +82,9 @@ def _terms():
 
 TERMS = _terms()
 
+# the factor of i of each term's class: 0-19 1, 20-27 i, 28-32 -1, 33-36 i, 37 -1
+PHASES = [1] * 20 + [1j] * 8 + [-1] * 5 + [1j] * 4 + [-1]
+
 
 def _generators(G):
     T = np.array(G.gell_mann_half(), dtype=complex)          # [8][3][3]
@@ -119,10 +125,14 @@ def colour_values(G):
 
 
 def projection(G):
-    """W [rank][38] complex with sum_r |sum_d W_rd A_d|^2 the colour sum."""
+    """W [rank][38] real with sum_r |sum_d W_rd a_d|^2 the colour sum of the
+    class-phase-free Lorentz parts a_d, and K (with the phases)."""
     C = colour_values(G)
-    K = C.T @ C.conj()
-    # K = U diag(lam) U^dagger, so A^T K conj(A) = sum_r lam_r |sum_d U_dr A_d|^2
+    ph = np.array(PHASES, dtype=complex)
+    K = ph[:, None] * (C.T @ C.conj()) * ph.conj()[None, :]
+    assert np.abs(K.imag).max() < 1e-12 * np.abs(K).max(), "colour matrix with the class phases is not real"
+    K = K.real
+    # K = U diag(lam) U^T, so a^T K conj(a) = sum_r lam_r |sum_d U_dr a_d|^2
     lam, U = np.linalg.eigh(K)
     keep = lam > 1e-9 * lam.max()
     W = np.sqrt(lam[keep])[:, None] * U[:, keep].T
@@ -135,9 +145,9 @@ def generate(G):
     lines = ["// Generated by gen_qqbar.py: colour projection of q qbar -> t tbar g g.",
              f"constexpr int QQ4_RANK = {r};",
              f"constexpr int QQ4_TERMS = {len(TERMS)};",
-             "// W[r][d] = (re, im): the colour sum is sum_r |sum_d W[r][d] A_d|^2",
-             f"static constexpr double QQ4_W[{r}][{len(TERMS)}][2] = {{"]
+             "// the colour sum is sum_r |sum_d W[r][d] a_d|^2, a_d without the class phases",
+             f"static constexpr double QQ4_W[{r}][{len(TERMS)}] = {{"]
     for row in W:
-        lines.append("    {" + ", ".join(f"{{{z.real:.17g}, {z.imag:.17g}}}" for z in row) + "},")
+        lines.append("    {" + ", ".join(f"{z:.17g}" for z in row) + "},")
     lines.append("};")
     return "\n".join(lines) + "\n"

@@ -1519,12 +1519,15 @@ __global__ void __launch_bounds__(kBlock) qqbar_ttxg_me_kernel(const double* __r
 // p p -> t tbar g g: the q qbar amplitudes of the batch's live events, one
 // one-wave workgroup per event.  The wave first builds the event's 344
 // helicity-recycled objects (currents and line chains, mf_qqbar_ttxgg.hpp)
-// into LDS, then lane = orientation x 32 + configuration (the 32 with the
-// antiquark spin opposite the quark's) contracts them; the sums go to
-// me_q[e] (quark along +z) and me_q[count + e].
+// into LDS in two passes of all 64 lanes, then lane = orientation x 32 +
+// configuration (the 32 with the antiquark spin opposite the quark's)
+// contracts them; the sums go to me_q[e] (quark along +z) and
+// me_q[count + e].
 __global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(2))) qqbar_ttxgg_kernel(StageParams S)
 {
     __shared__ __align__(16) cplx<double> s_ob[kQ4Objects][4];
+    __shared__ __align__(16) cplx<double> s_j12[4][4];
+    __shared__ double s_eps[4][4];
     __shared__ double s_mom[17];
     const int lane = threadIdx.x;
     const uint64_t i = blockIdx.x;
@@ -1536,15 +1539,11 @@ __global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(2)))
         s_mom[lane] = S.mom[e * 17 + lane];
     __syncthreads();
     const Q4Kin kin = q4_kinematics(s_mom, s_mom[16], S.P.m_top, S.P.mw);
-    // one object type per pass of the wave, so that its lanes do not diverge
-    // between the types' code
-    constexpr int kTypeStart[9] = {kQ4J, kQ4Q1, kQ4T2, kQ4Q3, kQ4T3, kQ4Q7, kQ4T7, kQ4V5, kQ4Objects};
-#pragma unroll 1
-    for (int t = 0; t < 8; ++t)
-        for (int idx = kTypeStart[t] + lane; idx < kTypeStart[t + 1]; idx += kWave)
-            q4_object(kin, idx, s_ob[idx]);
+    q4_objects_pass1(kin, lane, s_ob, s_eps, s_j12);
     __syncthreads();
-    double v = q4_config_from_objects(kin, s_ob, lane & 31, lane >> 5);
+    q4_objects_pass2(kin, lane, s_ob);           // synchronises between its reads and writes
+    __syncthreads();
+    double v = q4_config_from_objects(kin, s_ob, s_eps, s_j12, lane & 31, lane >> 5);
     v = group_sum(v, 32);
     if ((lane & 31) == 0)
         S.me_q[(uint64_t)(lane >> 5) * S.count + e] = v;

@@ -20,7 +20,8 @@
 //   33-37  the composite on the quark line (2), the top line (2), the spine
 // Feynman gauge, vertex and propagator factors of i counted per class: terms
 // 0-19 carry 1, 20-27 and 33-36 i, 28-32 and 37 -1 (a common factor
-// dropped).  Three-gluon vertex with the spine current J (momentum P into
+// dropped); these phases sit in the colour projection, which is real with
+// them.  Three-gluon vertex with the spine current J (momentum P into
 // the vertex), a gluon or the composite e (momentum k out of it):
 // (J.e)(P + k) + e J.(P - 2k) + J e.(k - 2P), the spine continuing with
 // P - k.  The composite: [e1 e2.(K + k3) + e1.e2 (k4 - k3) - e2 e1.(K + k4)]
@@ -139,21 +140,15 @@ __host__ __device__ __forceinline__ void q4_set_open(Q4Att& a, const double* q)
     }
 }
 
-// Adds factor * A to the colour projections.
+// Adds the term d's Lorentz part A (without its class phase) to the colour
+// projections; the weights are real.
 __host__ __device__ __forceinline__ void q4_project(int d, cplx<double> A, cplx<double>* proj)
 {
 #pragma unroll
     for (int r = 0; r < QQ4_RANK; ++r) {
-        const cplx<double> w(QQ4_W[r][d][0], QQ4_W[r][d][1]);
-        const cplx<double> p = cmul(w, A);
-        proj[r] = cplx<double>(proj[r].x + p.x, proj[r].y + p.y);
+        const double w = QQ4_W[r][d];
+        proj[r] = cplx<double>(proj[r].x + w * A.x, proj[r].y + w * A.y);
     }
-}
-
-__host__ __device__ __forceinline__ cplx<double> q4_times(cplx<double> a, int f)
-{
-    // f = 0: 1, 1: i, 2: -1
-    return f == 0 ? a : (f == 1 ? cplx<double>(-a.y, a.x) : cplx<double>(-a.x, -a.y));
 }
 
 // |M|^2 (g = 1, colour-summed) of configuration c of q qbar -> t tbar g g:
@@ -315,7 +310,7 @@ __host__ __device__ __forceinline__ double qqbar_ttxgg_config(const double* __re
                 q4_chain<2, 0>(vb, u, pa, 0.0, 0.0, qa, Xq);
             q4_v3(Xq, Pq, eps[ga], kg[ga], J1);
             const cplx<double> A = qq_dot(J1, Xt);
-            q4_project(d++, q4_times(cplx<double>(A.x / den, A.y / den), 1), proj);
+            q4_project(d++, cplx<double>(A.x / den, A.y / den), proj);
         }
     }
     // terms 24-27: ga on the spine, gb on the top line; the quark line is J
@@ -340,7 +335,7 @@ __host__ __device__ __forceinline__ double qqbar_ttxgg_config(const double* __re
             else
                 q4_chain<2, 0>(ub, v, mk2, mt, mw, ta, Xt);
             const cplx<double> A = qq_dot(J1, Xt);
-            q4_project(d++, q4_times(cplx<double>(A.x / den, A.y / den), 1), proj);
+            q4_project(d++, cplx<double>(A.x / den, A.y / den), proj);
         }
     }
     // terms 28-32: both on the spine (Xq = J with P0, Xt = K with Q)
@@ -356,16 +351,16 @@ __host__ __device__ __forceinline__ double qqbar_ttxgg_config(const double* __re
         q4_v3(J1, P1, eps[gb], kg[gb], J2);
         const double den = P02 * qq_m2(P1) * Q2;
         const cplx<double> A = qq_dot(J2, Xt);
-        q4_project(d++, q4_times(cplx<double>(A.x / den, A.y / den), 2), proj);
+        q4_project(d++, cplx<double>(A.x / den, A.y / den), proj);
     }
     {
         const cplx<double> q2 = qq_dot(Xq, eps[1]), q1 = qq_dot(Xq, eps[0]), qt = qq_dot(Xq, Xt);
         const cplx<double> t1 = qq_dot(eps[0], Xt), t2 = qq_dot(eps[1], Xt), e12 = qq_dot(eps[0], eps[1]);
         const double den = P02 * Q2;
         const cplx<double> a1 = cmul(q2, t1), a2 = cmul(qt, e12), a3 = cmul(q1, t2);
-        q4_project(d++, q4_times(cplx<double>((a1.x - a2.x) / den, (a1.y - a2.y) / den), 2), proj);
-        q4_project(d++, q4_times(cplx<double>((a3.x - a2.x) / den, (a3.y - a2.y) / den), 2), proj);
-        q4_project(d++, q4_times(cplx<double>((a3.x - a1.x) / den, (a3.y - a1.y) / den), 2), proj);
+        q4_project(d++, cplx<double>((a1.x - a2.x) / den, (a1.y - a2.y) / den), proj);
+        q4_project(d++, cplx<double>((a3.x - a2.x) / den, (a3.y - a2.y) / den), proj);
+        q4_project(d++, cplx<double>((a3.x - a1.x) / den, (a3.y - a1.y) / den), proj);
     }
     // terms 33-37: the composite
 #pragma unroll
@@ -377,7 +372,7 @@ __host__ __device__ __forceinline__ double qqbar_ttxgg_config(const double* __re
         else
             q4_chain<2, 0>(vb, u, pa, 0.0, 0.0, qa, J1);
         const cplx<double> A = qq_dot(J1, Xt);
-        q4_project(d++, q4_times(cplx<double>(A.x / Q2, A.y / Q2), 1), proj);
+        q4_project(d++, cplx<double>(A.x / Q2, A.y / Q2), proj);
     }
 #pragma unroll
     for (int ot = 0; ot < 2; ++ot) {        // on the top line; the quark line is J (Xq)
@@ -388,13 +383,13 @@ __host__ __device__ __forceinline__ double qqbar_ttxgg_config(const double* __re
         else
             q4_chain<2, 0>(ub, v, mk2, mt, mw, ta, J1);
         const cplx<double> A = qq_dot(Xq, J1);
-        q4_project(d++, q4_times(cplx<double>(A.x / P02, A.y / P02), 1), proj);
+        q4_project(d++, cplx<double>(A.x / P02, A.y / P02), proj);
     }
     {                                       // on the spine
         q4_v3(Xq, P0, J12, K, J1);
         const double den = P02 * Q2;
         const cplx<double> A = qq_dot(J1, Xt);
-        q4_project(d++, q4_times(cplx<double>(A.x / den, A.y / den), 2), proj);
+        q4_project(d++, cplx<double>(A.x / den, A.y / den), proj);
     }
     double sum = 0.0;
     for (int r = 0; r < QQ4_RANK; ++r)
@@ -415,8 +410,17 @@ namespace mf {
 // its polarisation), with the composite (order x orientation, quark spin,
 // polarisations); the top-line chains likewise (top spins in place of
 // orientation and quark spin); J after a three-gluon vertex with one gluon.
-// One wave per event builds these 348 objects into LDS, then each lane
+// One wave per event builds these 344 objects into LDS, then each lane
 // contracts them for one configuration.
+//
+// The chains share their ends.  From the column end, R[x] = S(p0 - q_x)
+// e_x-slash col and R[x, y] = S(p0 - q_x - q_y) e_y-slash R[x]; from the row
+// end, L[z] = row e_z-slash S(p_end + q_z) and L[z, y] = L[z] e_y-slash
+// S(p_end + q_z + q_y), with p_end the momentum that leaves at the row end
+// (-p_b on the quark line, k1 on the top line).  A chain with the open
+// (spine) slot between them is bilinear(L..., R...): spine last
+// bilinear(row, R[x, y]), in the middle bilinear(L[z], R[x]), first
+// bilinear(L[z, y], col); likewise with one gluon or the composite.
 // ---------------------------------------------------------------------------
 constexpr int kQ4J = 0, kQ4K = 4, kQ4Q1 = 8, kQ4T2 = 104, kQ4Q3 = 200, kQ4T3 = 232, kQ4Q7 = 264, kQ4T7 = 296,
               kQ4V5 = 328, kQ4Objects = 344;
@@ -429,25 +433,12 @@ struct Q4Kin {
     double P0[4], Q[4], K[4], mk2[4];
 };
 
-// kin.kg[g] without indexing the struct's array by a run-time value (which
-// would place the struct in scratch memory)
+// kin.kg[g] by address arithmetic (the momenta are contiguous: t, tbar,
+// g1, g2, as q4_kinematics sets them): indexing kin.kg by a run-time value,
+// or selecting between its two members, would place kin in scratch memory
 __host__ __device__ __forceinline__ const double* q4_kg(const Q4Kin& kin, int g)
 {
-    return g ? kin.kg[1] : kin.kg[0];
-}
-
-__host__ __device__ __forceinline__ void q4_beam_spinors(const Q4Kin& kin, int rev, int sq, cplx<double>* u,
-                                                         cplx<double>* vb, const double*& pa)
-{
-    const double pz[4] = {kin.eb, 0.0, 0.0, kin.eb}, mz[4] = {kin.eb, 0.0, 0.0, -kin.eb};
-    cplx<double> a[4], b[4];
-    spinor_ubar<double>(rev ? mz : pz, 0.0, sq, a);
-    spinor_v<double>(rev ? pz : mz, 0.0, sq ^ 1, b);
-    for (int i = 0; i < 4; ++i) {
-        u[i] = cplx<double>(a[(i + 2) & 3].x, -a[(i + 2) & 3].y);
-        vb[i] = cplx<double>(b[(i + 2) & 3].x, -b[(i + 2) & 3].y);
-    }
-    (void)pa;
+    return kin.k1 + 8 + 4 * g;
 }
 
 __host__ __device__ __forceinline__ void q4_pol(const Q4Kin& kin, int g, int h, cplx<double>* e)
@@ -477,253 +468,298 @@ __host__ __device__ __forceinline__ void q4_composite(const Q4Kin& kin, int h1, 
     }
 }
 
-// A chain with both gluons and the spine (momentum q_spine) in order O of
-// perm3 (0, 1: the gluons, 2: the spine), compile-time so that every array
-// index is static.
-template <int O>
-__device__ __forceinline__ void q4_chain3(const Q4Kin& kin, const cplx<double>* row, const cplx<double>* col,
-                                          const double* p0, double m, double mw, const cplx<double> (*eps)[4],
-                                          const double* qs, cplx<double>* out)
+// One line's ends: line 0 the quark line vbar(p_b) ... u(p_a) with
+// s = orientation << 1 | quark spin, line 1 the top line ubar(k1) ... v(k2)
+// with s = top spin << 1 | antitop spin.
+struct Q4Line {
+    cplx<double> row[4], col[4];
+    double p0[4], pend[4];
+    double m, mw;
+};
+
+__device__ __forceinline__ void q4_line(const Q4Kin& kin, int line, int s, Q4Line& L)
 {
-    constexpr int perm3[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
-    constexpr int S = perm3[O][0] == 2 ? 0 : (perm3[O][1] == 2 ? 1 : 2);
-    Q4Att at[3];
+    const bool top = line != 0;
+    const int hi = s >> 1, lo = s & 1;
+    double pA[4], pB[4];
 #pragma unroll
-    for (int t = 0; t < 3; ++t) {
-        const int x = perm3[O][t];
-        if (x < 2)
-            q4_set(at[t], eps[x], q4_kg(kin, x));
-        else
-            q4_set_open(at[t], qs);
+    for (int mu = 0; mu < 4; ++mu) {
+        const double z = mu == 3 ? (hi ? -kin.eb : kin.eb) : (mu == 0 ? kin.eb : 0.0);   // the quark's p_a
+        pA[mu] = top ? kin.k1[mu] : z;
+        pB[mu] = top ? kin.k2[mu] : (mu == 3 ? -z : z);
     }
-    q4_chain<3, S>(row, col, p0, m, mw, at, out);
+    const double m = top ? kin.mt : 0.0;
+    // the quark line's u and vbar are the conjugate-swapped ubar(p_a) and v(p_b)
+    cplx<double> a[4], b[4];
+    spinor_ubar<double>(pA, m, top ? hi : lo, a);
+    spinor_v<double>(pB, m, top ? lo : (lo ^ 1), b);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const cplx<double> ca(a[(i + 2) & 3].x, -a[(i + 2) & 3].y), cb(b[(i + 2) & 3].x, -b[(i + 2) & 3].y);
+        L.row[i] = top ? a[i] : cb;
+        L.col[i] = top ? b[i] : ca;
+    }
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+        L.p0[mu] = top ? -kin.k2[mu] : pA[mu];
+        L.pend[mu] = top ? kin.k1[mu] : -pB[mu];
+    }
+    L.m = m;
+    L.mw = top ? kin.mw : 0.0;
 }
 
-__device__ __forceinline__ void q4_chain3_any(int o, const Q4Kin& kin, const cplx<double>* row,
-                                              const cplx<double>* col, const double* p0, double m, double mw,
-                                              const cplx<double> (*eps)[4], const double* qs, cplx<double>* out)
+// One vertex and propagator from the column end (in -> S(P) e-slash in) and
+// from the row end (in -> in e-slash S(P)).
+__device__ __forceinline__ void q4_step_col(const double* P, double m, double mw, const cplx<double>* e,
+                                            const cplx<double>* in, cplx<double>* out)
 {
-    switch (o) {
-    case 0: q4_chain3<0>(kin, row, col, p0, m, mw, eps, qs, out); break;
-    case 1: q4_chain3<1>(kin, row, col, p0, m, mw, eps, qs, out); break;
-    case 2: q4_chain3<2>(kin, row, col, p0, m, mw, eps, qs, out); break;
-    case 3: q4_chain3<3>(kin, row, col, p0, m, mw, eps, qs, out); break;
-    case 4: q4_chain3<4>(kin, row, col, p0, m, mw, eps, qs, out); break;
-    default: q4_chain3<5>(kin, row, col, p0, m, mw, eps, qs, out); break;
+    cplx<double> t[4];
+    qq_slash_col(e, in, t);
+    q4_prop_col(P, m, mw, t, out);
+}
+
+__device__ __forceinline__ void q4_step_row(const double* P, double m, double mw, const cplx<double>* e,
+                                            const cplx<double>* in, cplx<double>* out)
+{
+    cplx<double> t[4];
+    qq_row_slash(in, e, t);
+    q4_prop_row(P, m, mw, t, out);
+}
+
+__device__ __forceinline__ void q4_store(cplx<double>* dst, const cplx<double>* v)
+{
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        dst[i] = v[i];
+}
+
+__device__ __forceinline__ void q4_load(const cplx<double>* src, cplx<double>* v)
+{
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        v[i] = src[i];
+}
+
+// First pass of a wave over the event, lane = line << 5 | s << 3 | k: k < 4
+// the gluon k >> 1 with polarisation k & 1, k >= 4 the composite of
+// polarisations (k >> 1 & 1, k & 1).  Each lane forms R and L of its
+// attachment and the two chains with it and the spine (one-gluon and
+// composite objects); the one-gluon R and L go to the slots of the
+// both-gluon chains of orders 1 and 3, which the second pass fills last.
+// Also J or K (k == 0), J after a three-gluon vertex (quark line, k < 4),
+// the polarisations and composites (line 0, s == 0) into eps and j12.
+__device__ __forceinline__ void q4_objects_pass1(const Q4Kin& kin, int lane, cplx<double> (*ob)[4], double (*eps)[4],
+                                                 cplx<double> (*j12)[4])
+{
+    const int line = lane >> 5, s = (lane >> 3) & 3, k = lane & 7;
+    const bool comp = k >= 4;
+    const int g = (k >> 1) & 1, lam = k & 1;
+    Q4Line L;
+    q4_line(kin, line, s, L);
+    cplx<double> e[4];
+    if (comp)
+        q4_composite(kin, g, lam, e);
+    else
+        q4_pol(kin, g, lam, e);
+    double Pr[4], Pl[4];
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+        const double q = comp ? kin.kg[0][mu] + kin.kg[1][mu] : q4_kg(kin, g)[mu];   // K or k_g
+        Pr[mu] = L.p0[mu] - q;
+        Pl[mu] = L.pend[mu] + q;
+    }
+    cplx<double> R[4], Lp[4], X[4];
+    q4_step_col(Pr, L.m, L.mw, e, L.col, R);
+    q4_step_row(Pl, L.m, L.mw, e, L.row, Lp);
+    const int b1 = line ? kQ4T2 : kQ4Q1, b3 = line ? kQ4T3 : kQ4Q3, b7 = line ? kQ4T7 : kQ4Q7;
+    // attachment first from the column end, then the spine; and the reverse
+    bilinear(L.row, R, X);
+    q4_store(ob[comp ? b7 + (s << 2) + (k & 3) : b3 + 16 * g + ((s << 1) | lam)], X);
+    bilinear(Lp, L.col, X);
+    q4_store(ob[comp ? b7 + 16 + (s << 2) + (k & 3) : b3 + 16 * g + 8 + ((s << 1) | lam)], X);
+    if (!comp) {
+        q4_store(ob[b1 + 16 + ((s << 2) | k)], R);
+        q4_store(ob[b1 + 48 + ((s << 2) | k)], Lp);
+    }
+    bilinear(L.row, L.col, X);                      // J (line 0) or K (line 1)
+    if (k == 0)
+        q4_store(ob[(line ? kQ4K : kQ4J) + s], X);
+    if (line == 0 && !comp) {
+        cplx<double> V[4];
+        q4_v3(X, kin.P0, e, q4_kg(kin, g), V);
+        q4_store(ob[kQ4V5 + 8 * g + ((s << 1) | lam)], V);
+    }
+    if (line == 0 && s == 0) {
+        if (comp) {
+            q4_store(j12[k & 3], e);
+        } else {
+#pragma unroll
+            for (int mu = 0; mu < 4; ++mu)
+                eps[k][mu] = e[mu].x;
+        }
     }
 }
 
-// A chain with one attachment (polarisation or current e, momentum q) at
-// slot first ? 0 : 1 and the spine (momentum qs) at the other.
-__device__ __forceinline__ void q4_chain2_any(bool first, const cplx<double>* row, const cplx<double>* col,
-                                              const double* p0, double m, double mw, const cplx<double>* e,
-                                              const double* q, const double* qs, cplx<double>* out)
+// Second pass, lane = line << 5 | s << 3 | a << 2 | l1 << 1 | l2: with gluon
+// a first from the column end R[a, 1 - a] (orders 0, 2: spine last), with a
+// first from the row end L[a, 1 - a] (orders 5, 4: spine first), and
+// bilinear(L[1 - a], R[a]) (orders 1, 3: spine in the middle), whose slots
+// held the one-gluon R and L: every lane reads before any writes.
+__device__ __forceinline__ void q4_objects_pass2(const Q4Kin& kin, int lane, cplx<double> (*ob)[4])
 {
-    Q4Att at[2];
-    if (first) {
-        q4_set(at[0], e, q);
-        q4_set_open(at[1], qs);
-        q4_chain<2, 1>(row, col, p0, m, mw, at, out);
-    } else {
-        q4_set_open(at[0], qs);
-        q4_set(at[1], e, q);
-        q4_chain<2, 0>(row, col, p0, m, mw, at, out);
+    const int line = lane >> 5, s = (lane >> 3) & 3, a = (lane >> 2) & 1, ll = lane & 3;
+    const int la = a ? (ll & 1) : (ll >> 1), lb = a ? (ll >> 1) : (ll & 1);   // polarisations of a, 1 - a
+    const int b1 = line ? kQ4T2 : kQ4Q1;
+    cplx<double> Ra[4], La[4], Lb[4];
+    q4_load(ob[b1 + 16 + ((s << 2) | (a << 1) | la)], Ra);
+    q4_load(ob[b1 + 48 + ((s << 2) | (a << 1) | la)], La);
+    q4_load(ob[b1 + 48 + ((s << 2) | ((1 - a) << 1) | lb)], Lb);
+    __syncthreads();
+    Q4Line L;
+    q4_line(kin, line, s, L);
+    cplx<double> e[4];
+    q4_pol(kin, 1 - a, lb, e);
+    const double* ka = q4_kg(kin, a);
+    const double* kb = q4_kg(kin, 1 - a);
+    double Pr[4], Pl[4];
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+        Pr[mu] = (L.p0[mu] - ka[mu]) - kb[mu];
+        Pl[mu] = (L.pend[mu] + ka[mu]) + kb[mu];
     }
+    cplx<double> Y[4], X[4];
+    q4_step_col(Pr, L.m, L.mw, e, Ra, Y);
+    bilinear(L.row, Y, X);
+    q4_store(ob[b1 + 16 * (a ? 2 : 0) + ((s << 2) | ll)], X);
+    q4_step_row(Pl, L.m, L.mw, e, La, Y);
+    bilinear(Y, L.col, X);
+    q4_store(ob[b1 + 16 * (a ? 4 : 5) + ((s << 2) | ll)], X);
+    bilinear(Lb, Ra, X);
+    q4_store(ob[b1 + 16 * (a ? 3 : 1) + ((s << 2) | ll)], X);
 }
 
-// Object idx (0 .. kQ4Objects - 1) of the event into out.
-__device__ __forceinline__ void q4_object(const Q4Kin& kin, int idx, cplx<double>* out)
+// The amplitude of three-gluon vertex v3(X, P, e, k) (see q4_v3) contracted
+// with the current Y, by linearity without forming the vertex's output:
+// (X.e)((P + k).Y) + (e.Y)(X.(P - 2k)) + (X.Y)(e.(k - 2P)), e real.
+__device__ __forceinline__ cplx<double> q4_v3_dot(const cplx<double>* X, const double* P, const double* e,
+                                                  const double* k, const cplx<double>* Y, cplx<double> eY,
+                                                  cplx<double> XY)
 {
-    cplx<double> u[4], vb[4], ub[4], v[4];
-    const double* pa_unused = nullptr;
-    const double pz[4] = {kin.eb, 0.0, 0.0, kin.eb}, mz[4] = {kin.eb, 0.0, 0.0, -kin.eb};
-    if (idx < kQ4K) {                                   // J (orientation, quark spin)
-        q4_beam_spinors(kin, idx >> 1, idx & 1, u, vb, pa_unused);
-        bilinear(vb, u, out);
-    } else if (idx < kQ4Q1) {                           // K (top, antitop spin)
-        const int i = idx - kQ4K;
-        spinor_ubar<double>(kin.k1, kin.mt, i >> 1, ub);
-        spinor_v<double>(kin.k2, kin.mt, i & 1, v);
-        bilinear(ub, v, out);
-    } else if (idx < kQ4T2) {                           // quark line: both gluons, 6 orders
-        const int i = idx - kQ4Q1, o = i >> 4, b = i & 15;
-        const int rev = b >> 3, sq = (b >> 2) & 1;
-        q4_beam_spinors(kin, rev, sq, u, vb, pa_unused);
-        cplx<double> eps[2][4];
-        q4_pol(kin, 0, (b >> 1) & 1, eps[0]);
-        q4_pol(kin, 1, b & 1, eps[1]);
-        q4_chain3_any(o, kin, vb, u, rev ? mz : pz, 0.0, 0.0, eps, kin.Q, out);
-    } else if (idx < kQ4Q3) {                           // top line: both gluons, 6 orders
-        const int i = idx - kQ4T2, o = i >> 4, b = i & 15;
-        spinor_ubar<double>(kin.k1, kin.mt, b >> 3, ub);
-        spinor_v<double>(kin.k2, kin.mt, (b >> 2) & 1, v);
-        cplx<double> eps[2][4];
-        q4_pol(kin, 0, (b >> 1) & 1, eps[0]);
-        q4_pol(kin, 1, b & 1, eps[1]);
-        double mP0[4];
-        for (int mu = 0; mu < 4; ++mu)
-            mP0[mu] = -kin.P0[mu];
-        q4_chain3_any(o, kin, ub, v, kin.mk2, kin.mt, kin.mw, eps, mP0, out);
-    } else if (idx < kQ4T3) {                           // quark line: gluon g at slot oq, spine P0 - k_g
-        const int i = idx - kQ4Q3, g = i >> 4, oq = (i >> 3) & 1, b = i & 7;
-        const int rev = b >> 2, sq = (b >> 1) & 1;
-        q4_beam_spinors(kin, rev, sq, u, vb, pa_unused);
-        cplx<double> e[4];
-        q4_pol(kin, g, b & 1, e);
-        double Pq[4];
-        for (int mu = 0; mu < 4; ++mu)
-            Pq[mu] = kin.P0[mu] - q4_kg(kin, g)[mu];
-        q4_chain2_any(oq == 0, vb, u, rev ? mz : pz, 0.0, 0.0, e, q4_kg(kin, g), Pq, out);
-    } else if (idx < kQ4Q7) {                           // top line: gluon g at slot ot, spine -(P0 - k_other)
-        const int i = idx - kQ4T3, g = i >> 4, ot = (i >> 3) & 1, b = i & 7;
-        spinor_ubar<double>(kin.k1, kin.mt, b >> 2, ub);
-        spinor_v<double>(kin.k2, kin.mt, (b >> 1) & 1, v);
-        cplx<double> e[4];
-        q4_pol(kin, g, b & 1, e);
-        double mPt[4];
-        for (int mu = 0; mu < 4; ++mu)
-            mPt[mu] = -(kin.P0[mu] - q4_kg(kin, 1 - g)[mu]);
-        q4_chain2_any(ot == 0, ub, v, kin.mk2, kin.mt, kin.mw, e, q4_kg(kin, g), mPt, out);
-    } else if (idx < kQ4T7) {                           // quark line: the composite at slot oq, spine Q
-        const int i = idx - kQ4Q7, oq = i >> 4, b = i & 15;
-        const int rev = b >> 3, sq = (b >> 2) & 1;
-        q4_beam_spinors(kin, rev, sq, u, vb, pa_unused);
-        cplx<double> J12[4];
-        q4_composite(kin, (b >> 1) & 1, b & 1, J12);
-        q4_chain2_any(oq == 0, vb, u, rev ? mz : pz, 0.0, 0.0, J12, kin.K, kin.Q, out);
-    } else if (idx < kQ4V5) {                           // top line: the composite at slot ot, spine -P0
-        const int i = idx - kQ4T7, ot = i >> 4, b = i & 15;
-        spinor_ubar<double>(kin.k1, kin.mt, b >> 3, ub);
-        spinor_v<double>(kin.k2, kin.mt, (b >> 2) & 1, v);
-        cplx<double> J12[4];
-        q4_composite(kin, (b >> 1) & 1, b & 1, J12);
-        double mP0[4];
-        for (int mu = 0; mu < 4; ++mu)
-            mP0[mu] = -kin.P0[mu];
-        q4_chain2_any(ot == 0, ub, v, kin.mk2, kin.mt, kin.mw, J12, kin.K, mP0, out);
-    } else {                                            // J after gluon g: v3(J, P0, eps_g, k_g)
-        const int i = idx - kQ4V5, g = i >> 3, b = i & 7;
-        q4_beam_spinors(kin, b >> 2, (b >> 1) & 1, u, vb, pa_unused);
-        cplx<double> J[4], e[4];
-        bilinear(vb, u, J);
-        q4_pol(kin, g, b & 1, e);
-        q4_v3(J, kin.P0, e, q4_kg(kin, g), out);
+    double Pk[4], P2k[4], k2P[4];
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+        Pk[mu] = P[mu] + k[mu];
+        P2k[mu] = P[mu] - 2.0 * k[mu];
+        k2P[mu] = k[mu] - 2.0 * P[mu];
     }
+    const cplx<double> Xe = qq_dotr(X, e), PkY = qq_dotr(Y, Pk), XP = qq_dotr(X, P2k);
+    const double ek = e[0] * k2P[0] - e[1] * k2P[1] - e[2] * k2P[2] - e[3] * k2P[3];
+    const cplx<double> t1 = cmul(Xe, PkY), t2 = cmul(eY, XP);
+    return cplx<double>(t1.x + t2.x + XY.x * ek, t1.y + t2.y + XY.y * ek);
+}
+
+__device__ __forceinline__ cplx<double> q4_scale(cplx<double> a, double r)
+{
+    return cplx<double>(a.x * r, a.y * r);
 }
 
 // |M|^2 of configuration c (bits as qqbar_ttxgg_config), orientation rev,
-// from the event's objects in LDS.
-__device__ __forceinline__ double q4_config_from_objects(const Q4Kin& kin, const cplx<double> (*ob)[4], int c, int rev)
+// from the event's objects, polarisations eps[g << 1 | h] and composites
+// j12[h1 << 1 | h2] in LDS.
+__device__ __forceinline__ double q4_config_from_objects(const Q4Kin& kin, const cplx<double> (*ob)[4],
+                                                         const double (*eps)[4], const cplx<double> (*j12)[4], int c,
+                                                         int rev)
 {
     const int l1 = c & 1, l2 = (c >> 1) & 1, stb = (c >> 2) & 1, st = (c >> 3) & 1, sq = (c >> 4) & 1;
-    const int lam[2] = {l1, l2};
     const int bq = (rev << 3) | (sq << 2) | (l1 << 1) | l2;
     const int bt = (st << 3) | (stb << 2) | (l1 << 1) | l2;
     const cplx<double>* J = ob[kQ4J + ((rev << 1) | sq)];
     const cplx<double>* K = ob[kQ4K + ((st << 1) | stb)];
-    cplx<double> eps[2][4];
-    q4_pol(kin, 0, l1, eps[0]);
-    q4_pol(kin, 1, l2, eps[1]);
-    const double P02 = qq_m2(kin.P0), Q2 = qq_m2(kin.Q);
+    const double* e1 = eps[l1];
+    const double* e2 = eps[2 + l2];
+    const double rP02 = 1.0 / qq_m2(kin.P0), rQ2 = 1.0 / qq_m2(kin.Q);
+    double Pg[2][4], rPg[2];                            // P0 - k_g and 1 / its square
+#pragma unroll
+    for (int g = 0; g < 2; ++g) {
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu)
+            Pg[g][mu] = kin.P0[mu] - q4_kg(kin, g)[mu];
+        rPg[g] = 1.0 / qq_m2(Pg[g]);
+    }
+    // currents dotted with the polarisations and with each other
+    const cplx<double> qt = qq_dot(J, K);
+    const cplx<double> eK[2] = {qq_dotr(K, e1), qq_dotr(K, e2)};
+    const cplx<double> q1 = qq_dotr(J, e1), q2 = qq_dotr(J, e2);
     cplx<double> proj[QQ4_RANK];
 #pragma unroll
     for (int r = 0; r < QQ4_RANK; ++r)
         proj[r] = cplx<double>(0.0, 0.0);
-    cplx<double> J1[4], J2[4];
     int d = 0;
 #pragma unroll
-    for (int o = 0; o < 6; ++o) {
-        const cplx<double> A = qq_dot(ob[kQ4Q1 + 16 * o + bq], K);
-        q4_project(d++, cplx<double>(A.x / Q2, A.y / Q2), proj);
-    }
+    for (int o = 0; o < 6; ++o)                         // terms 0-5
+        q4_project(d++, q4_scale(qq_dot(ob[kQ4Q1 + 16 * o + bq], K), rQ2), proj);
 #pragma unroll
-    for (int o = 0; o < 6; ++o) {
-        const cplx<double> A = qq_dot(J, ob[kQ4T2 + 16 * o + bt]);
-        q4_project(d++, cplx<double>(A.x / P02, A.y / P02), proj);
-    }
+    for (int o = 0; o < 6; ++o)                         // terms 6-11
+        q4_project(d++, q4_scale(qq_dot(J, ob[kQ4T2 + 16 * o + bt]), rP02), proj);
     // the one-gluon chains: quark (g, oq; rev, sq, lam_g), top (g, ot; st, stb, lam_g)
-    auto qidx = [&](int g, int oq) { return kQ4Q3 + 16 * g + 8 * oq + ((rev << 2) | (sq << 1) | lam[g]); };
-    auto tidx = [&](int g, int ot) { return kQ4T3 + 16 * g + 8 * ot + ((st << 2) | (stb << 1) | lam[g]); };
+    auto qidx = [&](int g, int oq) { return kQ4Q3 + 16 * g + 8 * oq + ((rev << 2) | (sq << 1) | (g ? l2 : l1)); };
+    auto tidx = [&](int g, int ot) { return kQ4T3 + 16 * g + 8 * ot + ((st << 2) | (stb << 1) | (g ? l2 : l1)); };
 #pragma unroll
-    for (int ga = 0; ga < 2; ++ga) {                    // terms 12-19
-        const int gb = 1 - ga;
-        double Pq[4];
-        for (int mu = 0; mu < 4; ++mu)
-            Pq[mu] = kin.P0[mu] - q4_kg(kin, ga)[mu];
-        const double Pq2 = qq_m2(Pq);
+    for (int ga = 0; ga < 2; ++ga)                      // terms 12-19
 #pragma unroll
         for (int oq = 0; oq < 2; ++oq)
 #pragma unroll
-            for (int ot = 0; ot < 2; ++ot) {
-                const cplx<double> A = qq_dot(ob[qidx(ga, oq)], ob[tidx(gb, ot)]);
-                q4_project(d++, cplx<double>(A.x / Pq2, A.y / Pq2), proj);
-            }
-    }
+            for (int ot = 0; ot < 2; ++ot)
+                q4_project(d++, q4_scale(qq_dot(ob[qidx(ga, oq)], ob[tidx(1 - ga, ot)]), rPg[ga]), proj);
 #pragma unroll
     for (int ga = 0; ga < 2; ++ga) {                    // terms 20-23
         const int gb = 1 - ga;
-        double Pq[4];
-        for (int mu = 0; mu < 4; ++mu)
-            Pq[mu] = kin.P0[mu] - q4_kg(kin, gb)[mu];
-        const double den = qq_m2(Pq) * Q2;
 #pragma unroll
         for (int oq = 0; oq < 2; ++oq) {
-            q4_v3(ob[qidx(gb, oq)], Pq, eps[ga], q4_kg(kin, ga), J1);
-            const cplx<double> A = qq_dot(J1, K);
-            q4_project(d++, q4_times(cplx<double>(A.x / den, A.y / den), 1), proj);
+            const cplx<double>* X = ob[qidx(gb, oq)];
+            const cplx<double> A = q4_v3_dot(X, Pg[gb], ga ? e2 : e1, q4_kg(kin, ga), K, eK[ga], qq_dot(X, K));
+            q4_project(d++, q4_scale(A, rPg[gb] * rQ2), proj);
         }
     }
-    auto vidx = [&](int g) { return kQ4V5 + 8 * g + ((rev << 2) | (sq << 1) | lam[g]); };
+    auto vidx = [&](int g) { return kQ4V5 + 8 * g + ((rev << 2) | (sq << 1) | (g ? l2 : l1)); };
 #pragma unroll
-    for (int ga = 0; ga < 2; ++ga) {                    // terms 24-27
-        const int gb = 1 - ga;
-        double Pt[4];
-        for (int mu = 0; mu < 4; ++mu)
-            Pt[mu] = kin.P0[mu] - q4_kg(kin, ga)[mu];
-        const double den = P02 * qq_m2(Pt);
+    for (int ga = 0; ga < 2; ++ga)                      // terms 24-27
 #pragma unroll
-        for (int ot = 0; ot < 2; ++ot) {
-            const cplx<double> A = qq_dot(ob[vidx(ga)], ob[tidx(gb, ot)]);
-            q4_project(d++, q4_times(cplx<double>(A.x / den, A.y / den), 1), proj);
-        }
-    }
+        for (int ot = 0; ot < 2; ++ot)
+            q4_project(d++, q4_scale(qq_dot(ob[vidx(ga)], ob[tidx(1 - ga, ot)]), rP02 * rPg[ga]), proj);
 #pragma unroll
     for (int ga = 0; ga < 2; ++ga) {                    // terms 28-29
         const int gb = 1 - ga;
-        double P1[4];
-        for (int mu = 0; mu < 4; ++mu)
-            P1[mu] = kin.P0[mu] - q4_kg(kin, ga)[mu];
-        q4_v3(ob[vidx(ga)], P1, eps[gb], q4_kg(kin, gb), J2);
-        const double den = P02 * qq_m2(P1) * Q2;
-        const cplx<double> A = qq_dot(J2, K);
-        q4_project(d++, q4_times(cplx<double>(A.x / den, A.y / den), 2), proj);
+        const cplx<double>* V = ob[vidx(ga)];
+        const cplx<double> A = q4_v3_dot(V, Pg[ga], gb ? e2 : e1, q4_kg(kin, gb), K, eK[gb], qq_dot(V, K));
+        q4_project(d++, q4_scale(A, rP02 * rPg[ga] * rQ2), proj);
     }
     {                                                   // terms 30-32
-        const cplx<double> q2 = qq_dot(J, eps[1]), q1 = qq_dot(J, eps[0]), qt = qq_dot(J, K);
-        const cplx<double> t1 = qq_dot(eps[0], K), t2 = qq_dot(eps[1], K), e12 = qq_dot(eps[0], eps[1]);
-        const double den = P02 * Q2;
-        const cplx<double> a1 = cmul(q2, t1), a2 = cmul(qt, e12), a3 = cmul(q1, t2);
-        q4_project(d++, q4_times(cplx<double>((a1.x - a2.x) / den, (a1.y - a2.y) / den), 2), proj);
-        q4_project(d++, q4_times(cplx<double>((a3.x - a2.x) / den, (a3.y - a2.y) / den), 2), proj);
-        q4_project(d++, q4_times(cplx<double>((a3.x - a1.x) / den, (a3.y - a1.y) / den), 2), proj);
+        const double e12 = e1[0] * e2[0] - e1[1] * e2[1] - e1[2] * e2[2] - e1[3] * e2[3];
+        const double r = rP02 * rQ2;
+        const cplx<double> a1 = cmul(q2, eK[0]), a2(qt.x * e12, qt.y * e12), a3 = cmul(q1, eK[1]);
+        q4_project(d++, q4_scale(cplx<double>(a1.x - a2.x, a1.y - a2.y), r), proj);
+        q4_project(d++, q4_scale(cplx<double>(a3.x - a2.x, a3.y - a2.y), r), proj);
+        q4_project(d++, q4_scale(cplx<double>(a3.x - a1.x, a3.y - a1.y), r), proj);
     }
 #pragma unroll
-    for (int oq = 0; oq < 2; ++oq) {                    // terms 33-34
-        const cplx<double> A = qq_dot(ob[kQ4Q7 + 16 * oq + bq], K);
-        q4_project(d++, q4_times(cplx<double>(A.x / Q2, A.y / Q2), 1), proj);
-    }
+    for (int oq = 0; oq < 2; ++oq)                      // terms 33-34
+        q4_project(d++, q4_scale(qq_dot(ob[kQ4Q7 + 16 * oq + bq], K), rQ2), proj);
 #pragma unroll
-    for (int ot = 0; ot < 2; ++ot) {                    // terms 35-36
-        const cplx<double> A = qq_dot(J, ob[kQ4T7 + 16 * ot + bt]);
-        q4_project(d++, q4_times(cplx<double>(A.x / P02, A.y / P02), 1), proj);
-    }
-    {                                                   // term 37
-        cplx<double> J12[4];
-        q4_composite(kin, l1, l2, J12);
-        q4_v3(J, kin.P0, J12, kin.K, J1);
-        const double den = P02 * Q2;
-        const cplx<double> A = qq_dot(J1, K);
-        q4_project(d++, q4_times(cplx<double>(A.x / den, A.y / den), 2), proj);
+    for (int ot = 0; ot < 2; ++ot)                      // terms 35-36
+        q4_project(d++, q4_scale(qq_dot(J, ob[kQ4T7 + 16 * ot + bt]), rP02), proj);
+    {                                                   // term 37: v3(J, P0, J12, K) . K
+        const cplx<double>* J12 = j12[(l1 << 1) | l2];
+        double Pk[4], P2k[4], k2P[4];
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu) {
+            Pk[mu] = kin.P0[mu] + kin.K[mu];
+            P2k[mu] = kin.P0[mu] - 2.0 * kin.K[mu];
+            k2P[mu] = kin.K[mu] - 2.0 * kin.P0[mu];
+        }
+        const cplx<double> t1 = cmul(qq_dot(J, J12), qq_dotr(K, Pk)), t2 = cmul(qq_dot(J12, K), qq_dotr(J, P2k));
+        const cplx<double> t3 = cmul(qt, qq_dotr(J12, k2P));
+        q4_project(d++, q4_scale(cplx<double>(t1.x + t2.x + t3.x, t1.y + t2.y + t3.y), rP02 * rQ2), proj);
     }
     double sum = 0.0;
 #pragma unroll
