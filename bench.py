@@ -51,14 +51,18 @@ QQBAR_FLOPS = 8 * (2 * 14 + 64 + 11) + 15
 # of 312 (four chain contractions, the three-gluon term, the 5 x 5 colour
 # form) after a per-lane setup of 47, and two 8-lane sums.
 QQBAR_TTXG_FLOPS = 8 * (478 + 555) + 8 * 64 + 8 * 47 + 32 * 312 + 14
-# p p -> t tbar g g: 64 lanes per event (32 configurations per beam
-# orientation), each evaluating the 38 terms of the 36 diagrams on its own.
-# Its source repeats chains that the compiler shares between terms (the same
-# line with the same gluon appears in several classes), so the count is the
-# one measured: SQ_INSTS_VALU_FLOPS_FP64 x 64 per passing event (rocprofv3
-# over four 1e6-event launches, 3.03e12 flops for 3.65e6 events), below the
-# 1.19e6 that the source's operations add up to.
-QQBAR_TTXGG_FLOPS = 831_000
+# p p -> t tbar g g, helicity-recycled, one wave per event.  First pass, 64
+# lanes (line x spinor pair x attachment): the line's two spinors (28), the
+# momenta (8), one vertex-and-propagator step from each end (2 x 187: slash
+# 64, propagator 123), three bilinears (3 x 64); the attachment a gluon
+# polarisation (13) on 32 lanes, the composite current (184) on 32; J after a
+# three-gluon vertex (150) on 16.  Second pass, 64 lanes: spinors 28,
+# polarisation 13, momenta 16, two steps 374, three bilinears 192.  Then 64
+# configurations of 3645: reciprocals and momenta 40, the current products
+# 86, the 38 terms' contractions and scalings (384 + 256 + 480 + 132 + 242 +
+# 34 + 128 + 147), the real rank-11 colour projection (38 x 11 x 4) and the
+# squares (44); two 32-lane sums.
+QQBAR_TTXGG_FLOPS = (64 * 602 + 32 * 13 + 32 * 184 + 16 * 150) + 64 * 623 + 64 * 3645 + 62
 
 WORKLOADS = {
     "ttx": dict(process="gg_ttx", n_g=2, cuts={}, events=1_000_000),

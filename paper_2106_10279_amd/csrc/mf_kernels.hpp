@@ -1539,10 +1539,13 @@ __global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(2)))
         s_mom[lane] = S.mom[e * 17 + lane];
     __syncthreads();
     const Q4Kin kin = q4_kinematics(s_mom, s_mom[16], S.P.m_top, S.P.mw);
+    __builtin_amdgcn_sched_barrier(0);
     q4_objects_pass1(kin, lane, s_ob, s_eps, s_j12);
     __syncthreads();
+    __builtin_amdgcn_sched_barrier(0);
     q4_objects_pass2(kin, lane, s_ob);           // synchronises between its reads and writes
     __syncthreads();
+    __builtin_amdgcn_sched_barrier(0);
     double v = q4_config_from_objects(kin, s_ob, s_eps, s_j12, lane & 31, lane >> 5);
     v = group_sum(v, 32);
     if ((lane & 31) == 0)

@@ -665,7 +665,9 @@ __device__ __forceinline__ cplx<double> q4_scale(cplx<double> a, double r)
 
 // |M|^2 of configuration c (bits as qqbar_ttxgg_config), orientation rev,
 // from the event's objects, polarisations eps[g << 1 | h] and composites
-// j12[h1 << 1 | h2] in LDS.
+// j12[h1 << 1 | h2] in LDS.  Scheduling barriers between the term groups
+// keep the compiler from hoisting every group's LDS loads to the top (which
+// spills registers).
 __device__ __forceinline__ double q4_config_from_objects(const Q4Kin& kin, const cplx<double> (*ob)[4],
                                                          const double (*eps)[4], const cplx<double> (*j12)[4], int c,
                                                          int rev)
@@ -698,9 +700,11 @@ __device__ __forceinline__ double q4_config_from_objects(const Q4Kin& kin, const
 #pragma unroll
     for (int o = 0; o < 6; ++o)                         // terms 0-5
         q4_project(d++, q4_scale(qq_dot(ob[kQ4Q1 + 16 * o + bq], K), rQ2), proj);
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int o = 0; o < 6; ++o)                         // terms 6-11
         q4_project(d++, q4_scale(qq_dot(J, ob[kQ4T2 + 16 * o + bt]), rP02), proj);
+    __builtin_amdgcn_sched_barrier(0);
     // the one-gluon chains: quark (g, oq; rev, sq, lam_g), top (g, ot; st, stb, lam_g)
     auto qidx = [&](int g, int oq) { return kQ4Q3 + 16 * g + 8 * oq + ((rev << 2) | (sq << 1) | (g ? l2 : l1)); };
     auto tidx = [&](int g, int ot) { return kQ4T3 + 16 * g + 8 * ot + ((st << 2) | (stb << 1) | (g ? l2 : l1)); };
@@ -711,6 +715,7 @@ __device__ __forceinline__ double q4_config_from_objects(const Q4Kin& kin, const
 #pragma unroll
             for (int ot = 0; ot < 2; ++ot)
                 q4_project(d++, q4_scale(qq_dot(ob[qidx(ga, oq)], ob[tidx(1 - ga, ot)]), rPg[ga]), proj);
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int ga = 0; ga < 2; ++ga) {                    // terms 20-23
         const int gb = 1 - ga;
@@ -721,12 +726,14 @@ __device__ __forceinline__ double q4_config_from_objects(const Q4Kin& kin, const
             q4_project(d++, q4_scale(A, rPg[gb] * rQ2), proj);
         }
     }
+    __builtin_amdgcn_sched_barrier(0);
     auto vidx = [&](int g) { return kQ4V5 + 8 * g + ((rev << 2) | (sq << 1) | (g ? l2 : l1)); };
 #pragma unroll
     for (int ga = 0; ga < 2; ++ga)                      // terms 24-27
 #pragma unroll
         for (int ot = 0; ot < 2; ++ot)
             q4_project(d++, q4_scale(qq_dot(ob[vidx(ga)], ob[tidx(1 - ga, ot)]), rP02 * rPg[ga]), proj);
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int ga = 0; ga < 2; ++ga) {                    // terms 28-29
         const int gb = 1 - ga;
@@ -734,6 +741,7 @@ __device__ __forceinline__ double q4_config_from_objects(const Q4Kin& kin, const
         const cplx<double> A = q4_v3_dot(V, Pg[ga], gb ? e2 : e1, q4_kg(kin, gb), K, eK[gb], qq_dot(V, K));
         q4_project(d++, q4_scale(A, rP02 * rPg[ga] * rQ2), proj);
     }
+    __builtin_amdgcn_sched_barrier(0);
     {                                                   // terms 30-32
         const double e12 = e1[0] * e2[0] - e1[1] * e2[1] - e1[2] * e2[2] - e1[3] * e2[3];
         const double r = rP02 * rQ2;
@@ -742,12 +750,14 @@ __device__ __forceinline__ double q4_config_from_objects(const Q4Kin& kin, const
         q4_project(d++, q4_scale(cplx<double>(a3.x - a2.x, a3.y - a2.y), r), proj);
         q4_project(d++, q4_scale(cplx<double>(a3.x - a1.x, a3.y - a1.y), r), proj);
     }
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int oq = 0; oq < 2; ++oq)                      // terms 33-34
         q4_project(d++, q4_scale(qq_dot(ob[kQ4Q7 + 16 * oq + bq], K), rQ2), proj);
 #pragma unroll
     for (int ot = 0; ot < 2; ++ot)                      // terms 35-36
         q4_project(d++, q4_scale(qq_dot(J, ob[kQ4T7 + 16 * ot + bt]), rP02), proj);
+    __builtin_amdgcn_sched_barrier(0);
     {                                                   // term 37: v3(J, P0, J12, K) . K
         const cplx<double>* J12 = j12[(l1 << 1) | l2];
         double Pk[4], P2k[4], k2P[4];
