@@ -265,7 +265,10 @@ mf_status mf_colour_matrix(int process_id, double *C);
  * (the MF_PP_ processes: the q qbar channel, the quark along +z, FP64):
  *   mom: device [n][4 (t) + 4 (tbar) + 4 (n_g-2) (final gluons)] in the
  *        partonic CM frame with the beams along +z/-z; eb: device [n] beam
- *        energies sqrt(s_hat)/2.  out: device [n]. */
+ *        energies sqrt(s_hat)/2.  out: device [n].
+ * MF_EINVAL for an unknown process or precision, a null pointer, n outside
+ * [1, 2^40] (outside [1, 2^31 - 1] for MF_PP_TTXGG: one workgroup per event)
+ * or m_top, w_top out of range. */
 mf_status mf_matrix_element(int process_id, mf_precision precision, const double *mom,
                             const double *eb, uint64_t n, double m_top, double w_top,
                             double *out, void *stream);

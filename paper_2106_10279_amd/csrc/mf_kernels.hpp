@@ -1516,18 +1516,32 @@ __global__ void __launch_bounds__(kBlock) qqbar_ttxg_me_kernel(const double* __r
         out[e] = v;
 }
 
-// p p -> t tbar g g: the q qbar amplitudes of the batch's live events, one
-// one-wave workgroup per event.  The wave first builds the event's 344
+// The q qbar -> t tbar g g |M|^2 (g = 1) of one event by one wave: the 344
 // helicity-recycled objects (currents and line chains, mf_qqbar_ttxgg.hpp)
-// into LDS in two passes of all 64 lanes, then lane = orientation x 32 +
-// configuration (the 32 with the antiquark spin opposite the quark's)
-// contracts them; the sums go to me_q[e] (quark along +z) and
-// me_q[count + e].
-__global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(2))) qqbar_ttxgg_kernel(StageParams S)
+// built into LDS in two passes of all 64 lanes, then lane = orientation x 32
+// + configuration (the 32 with the antiquark spin opposite the quark's)
+// contracting them.  Returns the sum over the lane's 32-lane half (quark
+// along +z for lanes 0-31, along -z for 32-63).  mom: LDS [t, tbar, g1, g2,
+// sqrt(s)/2].
+__device__ __forceinline__ double qqbar_ttxgg_event(const double* mom, double mt, double mw, int lane)
 {
     __shared__ __align__(16) cplx<double> s_ob[kQ4Objects][4];
     __shared__ __align__(16) cplx<double> s_j12[4][4];
     __shared__ double s_eps[4][4];
+    const Q4Kin kin = q4_kinematics(mom, mom[16], mt, mw);
+    q4_objects_pass1(kin, lane, s_ob, s_eps, s_j12);
+    __syncthreads();
+    q4_objects_pass2(kin, lane, s_ob);           // synchronises between its reads and writes
+    __syncthreads();
+    const double v = q4_config_from_objects(kin, s_ob, s_eps, s_j12, lane & 31, lane >> 5);
+    return group_sum(v, 32);
+}
+
+// p p -> t tbar g g: the q qbar amplitudes of the batch's live events, one
+// one-wave workgroup per event; the sums go to me_q[e] (quark along +z) and
+// me_q[count + e].
+__global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(2))) qqbar_ttxgg_kernel(StageParams S)
+{
     __shared__ double s_mom[17];
     const int lane = threadIdx.x;
     const uint64_t i = blockIdx.x;
@@ -1538,33 +1552,30 @@ __global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(2)))
     if (lane < 17)
         s_mom[lane] = S.mom[e * 17 + lane];
     __syncthreads();
-    const Q4Kin kin = q4_kinematics(s_mom, s_mom[16], S.P.m_top, S.P.mw);
-    __builtin_amdgcn_sched_barrier(0);
-    q4_objects_pass1(kin, lane, s_ob, s_eps, s_j12);
-    __syncthreads();
-    __builtin_amdgcn_sched_barrier(0);
-    q4_objects_pass2(kin, lane, s_ob);           // synchronises between its reads and writes
-    __syncthreads();
-    __builtin_amdgcn_sched_barrier(0);
-    double v = q4_config_from_objects(kin, s_ob, s_eps, s_j12, lane & 31, lane >> 5);
-    v = group_sum(v, 32);
+    const double v = qqbar_ttxgg_event(s_mom, S.P.m_top, S.P.mw, lane);
     if ((lane & 31) == 0)
         S.me_q[(uint64_t)(lane >> 5) * S.count + e] = v;
 }
 
 // q qbar -> t tbar g g |M|^2 (g = 1) for explicit momenta [n][16] (t, tbar,
-// g1, g2), the quark along +z; 32 lanes per event.
-__global__ void __launch_bounds__(kBlock) qqbar_ttxgg_me_kernel(const double* __restrict__ mom,
-                                                                const double* __restrict__ eb, uint64_t n,
-                                                                double mt, double mw, double* __restrict__ out)
+// g1, g2), the quark along +z: the integrand's evaluation, one one-wave
+// workgroup per event.
+__global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(2))) qqbar_ttxgg_me_kernel(
+    const double* __restrict__ mom, const double* __restrict__ eb, uint64_t n, double mt, double mw,
+    double* __restrict__ out)
 {
-    const uint64_t e = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) >> 5;
-    const int c = threadIdx.x & 31;
-    double v = 0.0;
-    if (e < n)
-        v = qqbar_ttxgg_config(mom + 16 * e, eb[e], mt, mw, c, 0);
-    v = group_sum(v, 32);
-    if (e < n && c == 0)
+    __shared__ double s_mom[17];
+    const int lane = threadIdx.x;
+    const uint64_t e = blockIdx.x;
+    if (e >= n)
+        return;                                  // uniform over the workgroup
+    if (lane < 16)
+        s_mom[lane] = mom[16 * e + lane];
+    else if (lane == 16)
+        s_mom[16] = eb[e];
+    __syncthreads();
+    const double v = qqbar_ttxgg_event(s_mom, mt, mw, lane);
+    if (lane == 0)
         out[e] = v;
 }
 

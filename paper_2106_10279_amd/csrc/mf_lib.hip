@@ -1621,11 +1621,10 @@ mf_status mf_matrix_element(int process_id, mf_precision precision, const double
     if (ng == 5)
         return matrix_element_ng5(precision, mom, eb, n, m_top, w_top, out, s);
     if (process_id == MF_PP_TTXGG) {
-        // the q qbar channel (quark along +z), FP64
-        const uint64_t qb = (n * 32 + mf::kBlock - 1) / mf::kBlock;
-        if (n > (1ull << 36) || qb > 0x7FFFFFFFull)
+        // the q qbar channel (quark along +z), FP64, one wave per event
+        if (n > 0x7FFFFFFFull)
             return fail(MF_EINVAL, "too many events for one launch");
-        hipLaunchKernelGGL(mf::qqbar_ttxgg_me_kernel, dim3((unsigned)qb), dim3(mf::kBlock), 0, s, mom, eb, n, m_top,
+        hipLaunchKernelGGL(mf::qqbar_ttxgg_me_kernel, dim3((unsigned)n), dim3(mf::kWave), 0, s, mom, eb, n, m_top,
                            m_top * w_top, out);
         MF_HIP(hipGetLastError());
         MF_HIP(hipStreamSynchronize(s));
