@@ -389,18 +389,27 @@ def flop_record(n_g):
     return mod.flop_count(n_g)
 
 
-def ttxggg_leg(api, torch, n_events, n_iter, precision):
+# Leading colour of t tbar g g g: each of the 120 x 128 partial amplitudes
+# squared and added (4 flop) in place of the colour sum.
+LC_FLOPS_NG5 = 120 * 128 * 4
+
+
+def ttxggg_leg(api, torch, n_events, n_iter, precision, colour="full"):
     """g g -> t tbar g g g (five gluons): one warm-up iteration, then n_iter
     timed ones.  Two rooflines from the library's HIP-event timing of every
     launch: the amplitude kernel (object stages and partial amplitudes of the
     passing events, VALU) and the matrix-core colour sum (algorithmic flops of
-    the symmetric quadratic form, 29040 per helicity configuration)."""
+    the symmetric quadratic form, 29040 per helicity configuration).  With
+    the leading-colour sum the amplitude kernel squares and adds the
+    amplitudes itself (LC_FLOPS_NG5 more per event) and a short kernel adds
+    its 20 partial sums per event; there is no colour roofline."""
     import workloads as W
     wl = WORKLOADS["ttxggg"]
     pdf = W.synthetic_pdf()
     proc = api.Process(wl["process"], **wl["cuts"])
     c = flop_record(5)
-    r, wall, _ = timed_run(api, torch, proc, pdf, n_events, n_iter, 1, precision, 0)
+    lc = colour == "leading"
+    r, wall, _ = timed_run(api, torch, proc, pdf, n_events, n_iter, 1, precision, 0, colour=colour)
     n_pass = float(np.sum(r.iter_pass))
     launches = len(r.iter_event_ms) * r.n_batches
     t_amp = float(np.sum(r.iter_amp_ms)) / 1e3
@@ -409,23 +418,29 @@ def ttxggg_leg(api, torch, n_events, n_iter, precision):
     f32 = precision != "fp64"
     vpeak = PEAK_FP32_TFLOPS if f32 else PEAK_FP64_TFLOPS
     mpeak = 157.3 if f32 else 78.6        # dense matrix-core FP32 / FP64
-    amp_fl = n_pass * c["amplitudes"]
+    amp_per_event = c["amplitudes"] + (LC_FLOPS_NG5 if lc else 0)
+    amp_fl = n_pass * amp_per_event
     col_fl = n_pass * c["colour"]
     out = {"workload": f"gg_ttxggg at 13 TeV (pT > 20 GeV, Delta R > 0.4 on the gluons), {n_events} events x "
-                       f"{n_iter} iterations, amplitudes {precision}",
+                       f"{n_iter} iterations, amplitudes {precision}"
+                       + (", leading-colour sum" if lc else ""),
            "value": round(n_events * n_iter / wall, 2), "unit": "events/s",
            "ms_per_step": round(wall / n_iter * 1e3, 3), "sigma_pb": r.sigma, "sigma_err_pb": r.sigma_err,
            "pass_fraction": round(n_pass / (n_iter * n_events), 4), "batches_per_iteration": r.n_batches,
-           "flops_per_passing_event": {"amplitudes": c["amplitudes"], "colour": c["colour"]},
+           "flops_per_passing_event": ({"amplitudes_and_squares": amp_per_event} if lc
+                                       else {"amplitudes": c["amplitudes"], "colour": c["colour"]}),
            "roofline": {"bound": "alu", "achieved": round(amp_fl / t_amp / 1e12, 3), "peak": vpeak,
                         "unit": "TFLOP/s", "frac": round(amp_fl / t_amp / 1e12 / vpeak, 4), "traffic": None,
                         "kernel": "amp_kernel_ng5", "launches": launches,
                         "avg_launch_ms": round(t_amp * 1e3 / launches, 3)},
-           "colour_roofline": {"bound": "mfma", "achieved": round(col_fl / t_col / 1e12, 3), "peak": mpeak,
+           "colour_roofline": None if lc else
+                              {"bound": "mfma", "achieved": round(col_fl / t_col / 1e12, 3), "peak": mpeak,
                                "unit": "TFLOP/s", "frac": round(col_fl / t_col / 1e12 / mpeak, 4),
                                "traffic": None, "kernel": "colour_kernel_ng5", "launches": launches,
                                "avg_launch_ms": round(t_col * 1e3 / launches, 3)},
            "per_event_kernels_ms_per_iteration": round(t_all * 1e3 / n_iter, 3)}
+    if lc:
+        out["lc_sum_ms_per_launch"] = round(t_col * 1e3 / launches, 4)
     del r
     torch.cuda.empty_cache()
     return out
@@ -495,6 +510,9 @@ def main():
         for prec in ("fp64",) + (() if args.no_fp32 else ("fp32_kahan",)):
             log(f"[bench] g g -> t tbar g g g, {args.ttxggg_events} events x {args.ttxggg_steps} iterations, {prec}")
             legs[f"ttxggg_{prec}"] = ttxggg_leg(api, torch, args.ttxggg_events, args.ttxggg_steps, prec)
+        log(f"[bench] g g -> t tbar g g g, leading colour, {args.ttxggg_events} events x {args.ttxggg_steps} "
+            f"iterations, fp64")
+        legs["ttxggg_lc_fp64"] = ttxggg_leg(api, torch, args.ttxggg_events, args.ttxggg_steps, "fp64", "leading")
         print(json.dumps(legs), flush=True)
         return
 
@@ -645,6 +663,9 @@ def main():
             log(f"[bench] g g -> t tbar g g g, {args.ttxggg_events} events x {args.ttxggg_steps} iterations, {prec}")
             out[f"ttxggg_{prec}"] = ttxggg_leg(api, torch, args.ttxggg_events, args.ttxggg_steps, prec)
             log(f"[bench] ttxggg {prec} done: {out[f'ttxggg_{prec}']['value']:.4g} events/s")
+        log(f"[bench] g g -> t tbar g g g, leading colour, fp64")
+        out["ttxggg_lc_fp64"] = ttxggg_leg(api, torch, args.ttxggg_events, args.ttxggg_steps, "fp64", "leading")
+        log(f"[bench] ttxggg leading colour done: {out['ttxggg_lc_fp64']['value']:.4g} events/s")
     if not args.no_adjoint:
         log(f"[bench] adjoint: gg_ttx forward + gradient, {args.adjoint_events} events x 3 iterations")
         out["adjoint"] = adjoint_run(api, torch, pdf, args.adjoint_events, 3, args.seed)

@@ -42,11 +42,13 @@ typedef enum {
 
 /* Processes: g g -> t tbar + (n_g - 2) gluons.  MF_GG_TTXGGG (five gluons,
  * the gluon channel of the paper's largest process, Sec. 3.2 and Fig. 4)
- * runs with the full colour and helicity sums only (MF_COLOUR_FULL,
- * MF_HELICITY_SUM), not in mf_integrate_static, and with at most 2^15
- * events per batch: each event's 120 x 128 complex partial amplitudes
- * (240 KB in FP64, 120 KB in FP32) pass through device memory between the
- * amplitude kernel and the matrix-core colour sum. */
+ * runs with the full helicity sum (MF_HELICITY_SUM) and the full or the
+ * leading-colour sum (MF_COLOUR_FULL, MF_COLOUR_LEADING with c_LC = 20.25),
+ * not in mf_integrate_static, and with at most 2^15 events per batch: for
+ * the full sum each event's 120 x 128 complex partial amplitudes (240 KB in
+ * FP64, 120 KB in FP32) pass through device memory between the amplitude
+ * kernel and the matrix-core colour sum; for the leading-colour sum only 20
+ * partial sums per event do.  mf_matrix_element gives the full sum. */
 /* MF_PP_TTX, MF_PP_TTXG and MF_PP_TTXGG are p p -> t tbar (g (g)) as in
  * Sec. 3 and Table 1: the g g channel plus the q qbar channels u ubar,
  * ubar u, d dbar, dbar d (1, 5 and 36 diagrams per quark group; 7, 36 and
@@ -66,7 +68,7 @@ typedef enum { MF_FP64 = 0, MF_FP32_KAHAN = 1 } mf_precision;
 /* Colour sum of |M|^2.  MF_COLOUR_LEADING is the leading-colour
  * approximation that Sec. 3.2 names for high multiplicities (on Fig. 4): in the colour
  * basis (T^{a_s1} ... T^{a_sn})_{i_t j_tbar}, T = lambda/2, the colour matrix
- * is replaced by c_LC = (N^2 - 1) N^(n_g - 1) / 2^n_g (N = 3: 6, 9, 13.5)
+ * is replaced by c_LC = (N^2 - 1) N^(n_g - 1) / 2^n_g (N = 3: 6, 9, 13.5, 20.25)
  * times the identity, the leading power of N of its diagonal; it changes the
  * integrand (by O(1/N^2)), not only its variance. */
 /* MF_COLOUR_SAMPLED is the Monte Carlo over colours that Sec. 3.2 names as

@@ -521,7 +521,9 @@ def emit_amplitudes(st, K, den, perms):
             a("    }")
             # orderings complete after this group go to memory at once
             for k in sorted(k for k, g in last.items() if g == gi):
-                a(f"    stj(J + (size_t)(c * {CHUNK} + {k}) * {2 * NHEL} + 2 * hel, Ar[{loc[k]}], Ai[{loc[k]}]);")
+                i = loc[k]
+                a(f"    if constexpr (LC) lc += (double)Ar[{i}] * (double)Ar[{i}] + (double)Ai[{i}] * (double)Ai[{i}];")
+                a(f"    else stj(J + (size_t)(c * {CHUNK} + {k}) * {2 * NHEL} + 2 * hel, Ar[{i}], Ai[{i}]);")
             if gi + 1 == len(keys) or keys[gi + 1][1] != Y:
                 a("    }")
         a("    }")
@@ -640,11 +642,12 @@ __device__ __forceinline__ void coop_stages_ng5(const T* __restrict__ tab, T* __
 
 // The partial amplitudes of pass `pass` of chunk c (orderings whose
 // first gluon is c) for helicity configuration hel, into their rows of the
-// event's amplitude block J ([row][hel][re, im], rows 24 c .. 24 c + 23).
-// c and pass are uniform over the wave.
-template <typename T>
+// event's amplitude block J ([row][hel][re, im], rows 24 c .. 24 c + 23);
+// with LC (the leading-colour sum) their squared moduli are added to lc
+// instead and nothing is stored.  c and pass are uniform over the wave.
+template <typename T, bool LC = false>
 __device__ __forceinline__ void coop_amp_ng5(const T* __restrict__ tab, const T* __restrict__ obj, int hel, int c,
-                                            int pass, T* __restrict__ J)
+                                            int pass, T* __restrict__ J, double& lc)
 {{
 {amp}
 }}

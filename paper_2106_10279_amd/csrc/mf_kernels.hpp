@@ -1237,7 +1237,12 @@ constexpr int kBlockNg5 = 512;
 constexpr int kAmpRowNg5 = 2 * 128;                        // T per row: 128 helicities x (re, im)
 constexpr size_t kAmpEventNg5 = (size_t)NPERM_NG5 * kAmpRowNg5;  // T per event
 
-template <typename T>
+// LC: the leading-colour sum instead (the colour matrix replaced by
+// kColourLcNg5 times the identity): each amplitude item adds its squared
+// moduli over the wave and stores that one value, slot `item` of the event's
+// AMP_ITEMS_NG5 doubles at the start of S.amps; lc_kernel_ng5 adds them in
+// item order, so the result does not depend on which wave took which item.
+template <typename T, bool LC = false>
 __global__ void __launch_bounds__(kBlockNg5) amp_kernel_ng5(StageParams S)
 {
     using L = Layout<5>;
@@ -1283,7 +1288,18 @@ __global__ void __launch_bounds__(kBlockNg5) amp_kernel_ng5(StageParams S)
                 if (item >= (unsigned)AMP_ITEMS_NG5)
                     break;
                 const int c = (int)(item % 5u), rest = (int)(item / 5u);
-                coop_amp_ng5<T>(s_tab, s_obj, 64 * (rest & 1) + (tid & 63), c, rest >> 1, J + e * kAmpEventNg5);
+                double lc = 0.0;
+                coop_amp_ng5<T, LC>(s_tab, s_obj, 64 * (rest & 1) + (tid & 63), c, rest >> 1,
+                                    J + e * kAmpEventNg5, lc);
+                if constexpr (LC) {
+                    // every lane stores the wave's sum (one address, one
+                    // value): a store by lane 0 alone, branching on the same
+                    // condition as the claim above, lets the compiler fold
+                    // the two into a loop that lanes leave one by one, whose
+                    // other lanes then read an item from an inactive lane 0
+                    lc = __shfl(group_sum(lc, kWave), 0);
+                    static_cast<double*>(S.amps)[e * AMP_ITEMS_NG5 + item] = lc;
+                }
             }
         }
         __syncthreads();
@@ -1409,6 +1425,24 @@ __global__ void __launch_bounds__(kBlock) colour_kernel_ng5(StageParams S)
         if (lane == 0)
             S.me[e] = acc / COLOUR_DEN_NG5;
     }
+}
+
+// Leading colour of t tbar g g g: c_LC = (N^2 - 1) N^4 / 2^5 with N = 3,
+// the leading power of N of the colour matrix's diagonal N C_F^5.
+constexpr double kColourLcNg5 = 8.0 * 81.0 / 32.0;
+
+// The leading-colour |M|^2 of the batch's events from the amplitude kernel's
+// per-item sums (added in item order), one thread per event.
+__global__ void __launch_bounds__(kBlock) lc_kernel_ng5(StageParams S)
+{
+    const uint64_t e = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (e >= S.count || S.pref[e] == 0.0)
+        return;
+    const double* q = static_cast<const double*>(S.amps) + e * AMP_ITEMS_NG5;
+    double s = 0.0;
+    for (int i = 0; i < AMP_ITEMS_NG5; ++i)
+        s += q[i];
+    S.me[e] = kColourLcNg5 * s;
 }
 
 // mf_matrix_element for t tbar g g g: the caller's momenta [n][20] and beam

@@ -482,14 +482,15 @@ mf_status launch_stages_prec(mf_precision prec, const mf::StageParams& S, int ki
 
 // t tbar g g g: phase space, amplitudes (one ten-wave workgroup per event,
 // as many as fit at once), colour sum on the matrix cores, accumulation.
-template <typename T>
+// LC: the leading-colour sum (lc_kernel_ng5 in place of the colour kernel).
+template <typename T, bool LC = false>
 mf_status launch_stages_ng5(const mf::StageParams& S, int kin_blocks, int n_cu, hipStream_t stream,
                             hipEvent_t amp_begin, hipEvent_t amp_end, bool accumulate, hipEvent_t col_begin = nullptr,
                             hipEvent_t col_end = nullptr)
 {
     constexpr int D = 2 + 3 * 5 - 4;
     int per_cu = 0, col_per_cu = 0;
-    MF_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, mf::amp_kernel_ng5<T>, mf::kBlockNg5, 0));
+    MF_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, mf::amp_kernel_ng5<T, LC>, mf::kBlockNg5, 0));
     MF_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&col_per_cu, mf::colour_kernel_ng5<T>, mf::kBlock, 0));
     if (per_cu < 1)
         return fail(MF_EDEVICE, "the t tbar g g g amplitude kernel does not fit a compute unit");
@@ -504,13 +505,18 @@ mf_status launch_stages_ng5(const mf::StageParams& S, int kin_blocks, int n_cu, 
     MF_HIP(hipGetLastError());
     if (amp_begin)
         MF_HIP(hipEventRecord(amp_begin, stream));
-    hipLaunchKernelGGL((mf::amp_kernel_ng5<T>), dim3(amp_grid), dim3(mf::kBlockNg5), 0, stream, S);
+    hipLaunchKernelGGL((mf::amp_kernel_ng5<T, LC>), dim3(amp_grid), dim3(mf::kBlockNg5), 0, stream, S);
     MF_HIP(hipGetLastError());
     if (amp_end)
         MF_HIP(hipEventRecord(amp_end, stream));
     if (col_begin)
         MF_HIP(hipEventRecord(col_begin, stream));
-    hipLaunchKernelGGL((mf::colour_kernel_ng5<T>), dim3(col_grid), dim3(mf::kBlock), 0, stream, S);
+    if constexpr (LC) {
+        const unsigned lb = (unsigned)((S.count + mf::kBlock - 1) / mf::kBlock);
+        hipLaunchKernelGGL(mf::lc_kernel_ng5, dim3(lb), dim3(mf::kBlock), 0, stream, S);
+    } else {
+        hipLaunchKernelGGL((mf::colour_kernel_ng5<T>), dim3(col_grid), dim3(mf::kBlock), 0, stream, S);
+    }
     MF_HIP(hipGetLastError());
     if (col_end)
         MF_HIP(hipEventRecord(col_end, stream));
@@ -530,8 +536,11 @@ mf_status dispatch_stages(int ng, mf_precision prec, mf_colour col, const mf::St
                           hipEvent_t d = nullptr)
 {
     if (ng == 5) {
+        if (col == MF_COLOUR_LEADING)
+            return prec == MF_FP32_KAHAN ? launch_stages_ng5<float, true>(S, kin_blocks, n_cu, s, a, b, true, c, d)
+                                         : launch_stages_ng5<double, true>(S, kin_blocks, n_cu, s, a, b, true, c, d);
         if (col != MF_COLOUR_FULL)
-            return fail(MF_EUNSUPPORTED, "g g -> t tbar g g g runs with the full colour sum only");
+            return fail(MF_EUNSUPPORTED, "g g -> t tbar g g g runs with the full or the leading-colour sum");
         return prec == MF_FP32_KAHAN ? launch_stages_ng5<float>(S, kin_blocks, n_cu, s, a, b, true, c, d)
                                      : launch_stages_ng5<double>(S, kin_blocks, n_cu, s, a, b, true, c, d);
     }
@@ -691,8 +700,8 @@ mf_status integrate_impl(const mf_process* proc, double sqrt_s, const mf_pdf_gri
     if ((opt->colour == MF_COLOUR_SAMPLED || opt->colour == MF_COLOUR_FLOW) && ng == 2)
         return fail(MF_EUNSUPPORTED, "the Monte Carlo over colours runs for g g -> t tbar g (g) only");
     if (ng == 5) {
-        if (opt->colour != MF_COLOUR_FULL)
-            return fail(MF_EUNSUPPORTED, "g g -> t tbar g g g runs with the full colour sum only");
+        if (opt->colour != MF_COLOUR_FULL && opt->colour != MF_COLOUR_LEADING)
+            return fail(MF_EUNSUPPORTED, "g g -> t tbar g g g runs with the full or the leading-colour sum");
         if (opt->helicity != MF_HELICITY_SUM)
             return fail(MF_EUNSUPPORTED, "g g -> t tbar g g g runs with the full helicity sum only");
         if (fixed_scratch)
@@ -1199,7 +1208,8 @@ mf_status stage_buffers_ng5(Workspace& ws, uint64_t b0, mf_precision prec, mf::S
 // which writes the weights (and the records' |M|^2).
 mf_status evaluate_staged(Setup& S, const mf_options* opt, uint64_t n)
 {
-    if (opt->colour != MF_COLOUR_FULL)
+    const bool lc = S.ng == 5 && opt->colour == MF_COLOUR_LEADING;
+    if (opt->colour != MF_COLOUR_FULL && !lc)
         return fail(MF_EUNSUPPORTED, "this process runs with the full colour sum only");
     if (opt->helicity != MF_HELICITY_SUM)
         return fail(MF_EUNSUPPORTED, "this process runs with the full helicity sum only");
@@ -1243,7 +1253,11 @@ mf_status evaluate_staged(Setup& S, const mf_options* opt, uint64_t n)
         SP.count = n - first < batch ? n - first : batch;
         SP.P.n_waves = waves_for((SP.count + mf::kWave - 1) / mf::kWave, S.ws->n_cu);
         const int kin_blocks = SP.P.n_waves / mf::kWavesPerBlock;
-        if (S.ng == 5)
+        if (S.ng == 5 && lc)
+            st = opt->precision == MF_FP32_KAHAN
+                     ? launch_stages_ng5<float, true>(SP, kin_blocks, S.ws->n_cu, S.stream, nullptr, nullptr, false)
+                     : launch_stages_ng5<double, true>(SP, kin_blocks, S.ws->n_cu, S.stream, nullptr, nullptr, false);
+        else if (S.ng == 5)
             st = opt->precision == MF_FP32_KAHAN
                      ? launch_stages_ng5<float>(SP, kin_blocks, S.ws->n_cu, S.stream, nullptr, nullptr, false)
                      : launch_stages_ng5<double>(SP, kin_blocks, S.ws->n_cu, S.stream, nullptr, nullptr, false);

@@ -134,9 +134,55 @@ def test_batches_give_identical_weights(api, pdf_table):
     assert rb.sigma == pytest.approx(r1.sigma, rel=1e-14)
 
 
+def refined_grid(D, seed):
+    rng = np.random.default_rng(seed)
+    return np.sort(np.concatenate([np.zeros((D, 1)), rng.uniform(0, 1, (D, 49)), np.ones((D, 1))], axis=1), axis=1)
+
+
+@pytest.mark.parametrize("precision,bar", [("fp64", 1e-12), ("fp32_kahan", 2e-4)])
+def test_leading_colour_weights_match_oracle(api, pdf_table, precision, bar):
+    """The leading-colour sum c_LC sum_sigma |A(sigma)|^2 (c_LC = 20.25; the
+    amplitude kernel adds the squares per item and stores no amplitudes):
+    per-event weights on a refined grid against the oracle; on the same
+    events the ratio to the full-colour weight stays within the range that
+    1/N^2 corrections allow."""
+    n = 203
+    grid = refined_grid(13, 56)
+    say(f"\n  leading-colour weights t tbar g g g {precision}: {n} events")
+    w = api.evaluate_weights(gproc(api), SQRT_S, pdf_table, n, seed=4, it=1, grid=grid, precision=precision,
+                             colour="leading").cpu().numpy()
+    w_o, flags, kap = O.event_weights(oproc(colour="leading"), SQRT_S, pdf_table, grid, 4, 1, np.arange(n),
+                                      return_kappa=True)
+    skip = (flags & (8 | 16)) != 0
+    zero = (w_o == 0.0) & ~skip
+    assert np.all(w[zero] == 0.0)
+    use = ~skip & ~zero
+    rel = np.abs(w - w_o)[use] / np.abs(w_o[use])
+    cond = (flags[use] & 64) != 0
+    limit = np.where(cond, np.maximum(bar, newton_bar(kap[use], 5)), bar)
+    say(f"  {int(use.sum())} nonzero, max rel {rel.max():.3e}")
+    assert use.sum() > 40 and np.all(rel <= limit)
+    if precision == "fp64":
+        wf = api.evaluate_weights(gproc(api), SQRT_S, pdf_table, n, seed=4, it=1, grid=grid).cpu().numpy()
+        r = w[use] / wf[use]
+        say(f"  leading / full colour in [{r.min():.4f}, {r.max():.4f}]")
+        assert np.all((r > 0.5) & (r < 2.0)) and r.max() - r.min() > 0.01
+
+
+def test_leading_colour_integration_matches_oracle(api, pdf_table):
+    n, iters = 420, 2
+    say(f"\n  integrate t tbar g g g, leading colour, n={n} iters={iters}")
+    g = api.integrate(gproc(api), SQRT_S, pdf_table, n, iters, seed=1, colour="leading")
+    o = O.integrate(oproc(colour="leading"), SQRT_S, pdf_table, n, iters, seed=1)
+    say(f"  gpu {g.sigma:.8g} +- {g.sigma_err:.3g}, oracle {o.sigma:.8g} +- {o.sigma_err:.3g}")
+    assert_integration_parity(g, o, n, say=say)
+    np.testing.assert_allclose(g.weights.cpu().numpy(), o.weights_last, rtol=1e-11, atol=0)
+    assert g.n_pass == o.n_pass
+
+
 def test_unsupported_requests(api, pdf_table):
     from paper_2106_10279_amd import _lib as L
-    for kw in (dict(colour="leading"), dict(colour="sampled"), dict(helicity="sampled"),
+    for kw in (dict(colour="sampled"), dict(colour="flow"), dict(helicity="sampled"),
                dict(static_scratch=True)):
         with pytest.raises(L.MFError) as e:
             api.integrate(gproc(api), SQRT_S, pdf_table, 100, 1, seed=0, **kw)

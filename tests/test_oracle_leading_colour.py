@@ -37,7 +37,7 @@ def test_lc_coefficient_is_the_leading_power_of_the_colour_diagonal():
     """N C_F^n = c_LC (1 - 1/N^2)^(n - 1): the brute-force SU(3) colour
     matrix's diagonal and c_LC agree in their leading power of N."""
     N = 3.0
-    for n_g, expect in ((2, 6.0), (3, 9.0), (4, 13.5)):
+    for n_g, expect in ((2, 6.0), (3, 9.0), (4, 13.5), (5, 20.25)):
         assert O.colour_lc(n_g) == expect
         diag = np.diag(O.colour_matrix(n_g))
         assert np.allclose(diag, expect * (1 - 1 / N**2) ** (n_g - 1), rtol=1e-14, atol=0)
