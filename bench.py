@@ -58,11 +58,12 @@ QQBAR_TTXG_FLOPS = 8 * (478 + 555) + 8 * 64 + 8 * 47 + 32 * 312 + 14
 # polarisation (13) on 32 lanes, the composite current (184) on 32; J after a
 # three-gluon vertex (150) on 16.  Second pass, 64 lanes: spinors 28,
 # polarisation 13, momenta 16, two steps 374, three bilinears 192.  Then 64
-# configurations of 3645: reciprocals and momenta 40, the current products
+# configurations of 2495: reciprocals and momenta 40, the current products
 # 86, the 38 terms' contractions and scalings (384 + 256 + 480 + 132 + 242 +
-# 34 + 128 + 147), the real rank-11 colour projection (38 x 11 x 4) and the
-# squares (44); two 32-lane sums.
-QQBAR_TTXGG_FLOPS = (64 * 602 + 32 * 13 + 32 * 184 + 16 * 150) + 64 * 623 + 64 * 3645 + 62
+# 34 + 128 + 147), their signed additions into the 11 colour-basis sums
+# (112 x 2) and the colour sum with the 11 x 11 Gram matrix (342); two 32-lane
+# sums.
+QQBAR_TTXGG_FLOPS = (64 * 602 + 32 * 13 + 32 * 184 + 16 * 150) + 64 * 623 + 64 * 2495 + 62
 
 WORKLOADS = {
     "ttx": dict(process="gg_ttx", n_g=2, cuts={}, events=1_000_000),

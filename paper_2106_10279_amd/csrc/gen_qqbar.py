@@ -139,15 +139,50 @@ def projection(G):
     return W, K
 
 
+def sparse_basis(G):
+    """An 11-term colour basis among the terms themselves: the first terms
+    whose colour factors (with their class phases) are linearly independent.
+    Every term's factor is then an integer combination of the basis factors
+    (entries +-1), B [11][38], and the colour sum is
+    sum_rs Gm_rs b_r conj(b_s) with b = B a and Gm the real Gram matrix of
+    the basis factors (integers over den = 36).  Returns basis, B, den * Gm,
+    den, and K."""
+    C = colour_values(G) * np.array(PHASES, dtype=complex)[None, :]
+    basis = []
+    for d in range(len(TERMS)):
+        if np.linalg.matrix_rank(C[:, basis + [d]], tol=1e-9) > len(basis):
+            basis.append(d)
+    E = C[:, basis]
+    B = np.linalg.lstsq(E, C, rcond=None)[0]
+    Bi = np.rint(B.real).astype(int)
+    assert np.abs(B - Bi).max() < 1e-9, "basis coefficients are not integers"
+    Gm = E.T @ E.conj()
+    assert np.abs(Gm.imag).max() < 1e-12
+    den = 36
+    Gi = np.rint(Gm.real * den).astype(int)
+    assert np.abs(Gm.real * den - Gi).max() < 1e-9, "Gram matrix not over 36"
+    K = C.T @ C.conj()
+    assert np.abs(Bi.T @ Gi @ Bi / den - K).max() < 1e-9 * np.abs(K).max()
+    return basis, Bi, Gi, den, K.real
+
+
 def generate(G):
-    W, K = projection(G)
-    r = W.shape[0]
-    lines = ["// Generated by gen_qqbar.py: colour projection of q qbar -> t tbar g g.",
+    basis, B, Gi, den, _ = sparse_basis(G)
+    r = B.shape[0]
+    lines = ["// Generated by gen_qqbar.py: colour basis of q qbar -> t tbar g g.",
              f"constexpr int QQ4_RANK = {r};",
              f"constexpr int QQ4_TERMS = {len(TERMS)};",
-             "// the colour sum is sum_r |sum_d W[r][d] a_d|^2, a_d without the class phases",
-             f"static constexpr double QQ4_W[{r}][{len(TERMS)}] = {{"]
-    for row in W:
-        lines.append("    {" + ", ".join(f"{z:.17g}" for z in row) + "},")
+             f"// basis terms {basis}; term d's colour factor (with its class phase) is",
+             "// sum_r QQ4_B[r][d] times that of basis term r; the colour sum of the",
+             "// class-phase-free Lorentz parts a_d is sum_rs QQ4_G[r][s] b_r conj(b_s) / QQ4_GDEN",
+             "// with b_r = sum_d QQ4_B[r][d] a_d",
+             f"constexpr int QQ4_GDEN = {den};",
+             f"static constexpr signed char QQ4_B[{r}][{len(TERMS)}] = {{"]
+    for row in B:
+        lines.append("    {" + ", ".join(str(int(v)) for v in row) + "},")
+    lines.append("};")
+    lines.append(f"static constexpr int QQ4_G[{r}][{r}] = {{")
+    for row in Gi:
+        lines.append("    {" + ", ".join(str(int(v)) for v in row) + "},")
     lines.append("};")
     return "\n".join(lines) + "\n"

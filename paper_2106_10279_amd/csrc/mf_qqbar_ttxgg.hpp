@@ -8,8 +8,8 @@
 // spine seen from the quark line: the momentum it carries to the top side,
 // seen from the top line: minus that; the pair g1 g2 joined at a
 // three-gluon vertex, "composite": K = k3 + k4).  The 38 terms, in the
-// order of gen_qqbar.py's TERMS (their colour projection QQ4_W is generated
-// there):
+// order of gen_qqbar.py's TERMS (their colour basis QQ4_B, QQ4_G is
+// generated there):
 //    0- 5  both gluons and the spine on the quark line (3! orders)
 //    6-11  both on the top line
 //   12-19  gluon ga on the quark line, gb on the top line (2 x 2 orders)
@@ -20,8 +20,8 @@
 //   33-37  the composite on the quark line (2), the top line (2), the spine
 // Feynman gauge, vertex and propagator factors of i counted per class: terms
 // 0-19 carry 1, 20-27 and 33-36 i, 28-32 and 37 -1 (a common factor
-// dropped); these phases sit in the colour projection, which is real with
-// them.  Three-gluon vertex with the spine current J (momentum P into
+// dropped); these phases sit in the colour basis (gen_qqbar.py), in which
+// every term's colour factor is a sum of basis factors with signs.  Three-gluon vertex with the spine current J (momentum P into
 // the vertex), a gluon or the composite e (momentum k out of it):
 // (J.e)(P + k) + e J.(P - 2k) + J e.(k - 2P), the spine continuing with
 // P - k.  The composite: [e1 e2.(K + k3) + e1.e2 (k4 - k3) - e2 e1.(K + k4)]
@@ -73,17 +73,42 @@ __host__ __device__ __forceinline__ void q4_v3(const cplx<double>* J, const doub
     }
 }
 
-// Adds the term d's Lorentz part A (without its class phase) to the colour
-// projections; the weights are real.
-__host__ __device__ __forceinline__ void q4_project(int d, cplx<double> A, cplx<double>* proj)
+// Adds term d's Lorentz part A (without its class phase) to the colour-basis
+// sums b_r = sum_d QQ4_B[r][d] a_d; the entries are +-1 or 0 and known at
+// compile time once the caller's loops over the terms are unrolled, so only
+// the additions remain.
+__device__ __forceinline__ void q4_project(int d, cplx<double> A, cplx<double>* b)
 {
 #pragma unroll
     for (int r = 0; r < QQ4_RANK; ++r) {
-        const double w = QQ4_W[r][d];
-        proj[r] = cplx<double>(proj[r].x + w * A.x, proj[r].y + w * A.y);
+        const int c = QQ4_B[r][d];
+        if (c > 0)
+            b[r] = cplx<double>(b[r].x + A.x, b[r].y + A.y);
+        else if (c < 0)
+            b[r] = cplx<double>(b[r].x - A.x, b[r].y - A.y);
     }
+    // the additions happen here: without the pin the compiler defers them
+    // to the colour sum and keeps every term's A live (spilling)
+#pragma unroll
+    for (int r = 0; r < QQ4_RANK; ++r)
+        asm volatile("" : "+v"(b[r].x), "+v"(b[r].y));
 }
 
+// The colour sum sum_rs QQ4_G[r][s] Re(b_r conj(b_s)) / QQ4_GDEN (the Gram
+// matrix of the basis terms' colour factors, real and symmetric).
+__device__ __forceinline__ double q4_colour_sum(const cplx<double>* b)
+{
+    double s = 0.0;
+#pragma unroll
+    for (int r = 0; r < QQ4_RANK; ++r) {
+        double t = (double)QQ4_G[r][r] * (b[r].x * b[r].x + b[r].y * b[r].y);
+#pragma unroll
+        for (int q = 0; q < r; ++q)
+            t += (double)(2 * QQ4_G[r][q]) * (b[r].x * b[q].x + b[r].y * b[q].y);
+        s += t;
+    }
+    return s / (double)QQ4_GDEN;
+}
 
 // ---------------------------------------------------------------------------
 // Helicity recycling.  The terms depend on the helicity configuration only
@@ -457,11 +482,7 @@ __device__ __forceinline__ double q4_config_from_objects(const Q4Kin& kin, const
         const cplx<double> t3 = cmul(qt, qq_dotr(J12, k2P));
         q4_project(d++, q4_scale(cplx<double>(t1.x + t2.x + t3.x, t1.y + t2.y + t3.y), rP02 * rQ2), proj);
     }
-    double sum = 0.0;
-#pragma unroll
-    for (int r = 0; r < QQ4_RANK; ++r)
-        sum += proj[r].x * proj[r].x + proj[r].y * proj[r].y;
-    return sum;
+    return q4_colour_sum(proj);
 }
 
 __host__ __device__ __forceinline__ Q4Kin q4_kinematics(const double* mom, double eb, double mt, double mw)
