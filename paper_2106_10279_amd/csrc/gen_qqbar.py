@@ -7,15 +7,19 @@ configuration (the 36 diagrams, the four-gluon vertex split into its three
 colour structures), in the order of TERMS below, without the factors of i
 that the Feynman rules give each class (PHASES below: 1, i or -1).  The
 colour sum sum_colours |sum_d C_d phi_d a_d|^2 = sum_de a_d K_de conj(a_e),
-K_de = phi_d conj(phi_e) sum_colours C_d conj(C_e), is Hermitian, positive
-semi-definite and of low rank; with the class phases inside, K is real, so
-K = sum_r lam_r v_r v_r^T with real v_r and the colour sum is
-sum_r |sum_d W_rd a_d|^2 with the real W_rd = sqrt(lam_r) v_r[d], over the r
-with lam_r > 0.  The colour factors come from an
-explicit sum over the 3^4 8^2 colour assignments of each term's colour
-factor: products of T = lambda/2 along the quark line (v-bar index j to u
-index i) and the top line (u-bar index k to v index l) and structure
-constants f^{abc} = -2i Tr([T^a, T^b] T^c), internal indices summed.
+K_de = phi_d conj(phi_e) sum_colours C_d conj(C_e), is real with the class
+phases inside and of rank 11.  The kernel uses a basis of 11 of the terms
+themselves (sparse_basis): every term's phased colour factor is a sum of
+the basis terms' with signs, B [11][38], so K = B^T G B with G the basis
+terms' Gram matrix (integers over 36), and the colour sum is
+sum_rs G_rs Re(b_r conj(b_s)) with b = B a: additions per term and one
+11 x 11 quadratic form.  (projection() gives the equivalent real rank-11
+projection W with W^T W = K, the kernel's first form.)  The colour factors
+come from an explicit sum over the 3^4 8^2 colour assignments of each
+term's colour factor: products of T = lambda/2 along the quark line (v-bar
+index j to u index i) and the top line (u-bar index k to v index l) and
+structure constants f^{abc} = -2i Tr([T^a, T^b] T^c), internal indices
+summed.
 
 Colour slots: 0, 1 the gluons' adjoint indices; 2 + x internal index x.
 A term: (quark-line slots from the u end, top-line slots from the v end,
