@@ -77,7 +77,7 @@ __host__ __device__ __forceinline__ void q4_v3(const cplx<double>* J, const doub
 // sums b_r = sum_d QQ4_B[r][d] a_d; the entries are +-1 or 0 and known at
 // compile time once the caller's loops over the terms are unrolled, so only
 // the additions remain.
-__device__ __forceinline__ void q4_project(int d, cplx<double> A, cplx<double>* b)
+__device__ __forceinline__ void q4_basis_add(int d, cplx<double> A, cplx<double>* b)
 {
 #pragma unroll
     for (int r = 0; r < QQ4_RANK; ++r) {
@@ -403,18 +403,18 @@ __device__ __forceinline__ double q4_config_from_objects(const Q4Kin& kin, const
     const cplx<double> qt = qq_dot(J, K);
     const cplx<double> eK[2] = {qq_dotr(K, e1), qq_dotr(K, e2)};
     const cplx<double> q1 = qq_dotr(J, e1), q2 = qq_dotr(J, e2);
-    cplx<double> proj[QQ4_RANK];
+    cplx<double> bsum[QQ4_RANK];                      // the colour-basis sums
 #pragma unroll
     for (int r = 0; r < QQ4_RANK; ++r)
-        proj[r] = cplx<double>(0.0, 0.0);
+        bsum[r] = cplx<double>(0.0, 0.0);
     int d = 0;
 #pragma unroll
     for (int o = 0; o < 6; ++o)                         // terms 0-5
-        q4_project(d++, q4_scale(qq_dot(ob[kQ4Q1 + 16 * o + bq], K), rQ2), proj);
+        q4_basis_add(d++, q4_scale(qq_dot(ob[kQ4Q1 + 16 * o + bq], K), rQ2), bsum);
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int o = 0; o < 6; ++o)                         // terms 6-11
-        q4_project(d++, q4_scale(qq_dot(J, ob[kQ4T2 + 16 * o + bt]), rP02), proj);
+        q4_basis_add(d++, q4_scale(qq_dot(J, ob[kQ4T2 + 16 * o + bt]), rP02), bsum);
     __builtin_amdgcn_sched_barrier(0);
     // the one-gluon chains: quark (g, oq; rev, sq, lam_g), top (g, ot; st, stb, lam_g)
     auto qidx = [&](int g, int oq) { return kQ4Q3 + 16 * g + 8 * oq + ((rev << 2) | (sq << 1) | (g ? l2 : l1)); };
@@ -425,7 +425,7 @@ __device__ __forceinline__ double q4_config_from_objects(const Q4Kin& kin, const
         for (int oq = 0; oq < 2; ++oq)
 #pragma unroll
             for (int ot = 0; ot < 2; ++ot)
-                q4_project(d++, q4_scale(qq_dot(ob[qidx(ga, oq)], ob[tidx(1 - ga, ot)]), rPg[ga]), proj);
+                q4_basis_add(d++, q4_scale(qq_dot(ob[qidx(ga, oq)], ob[tidx(1 - ga, ot)]), rPg[ga]), bsum);
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int ga = 0; ga < 2; ++ga) {                    // terms 20-23
@@ -434,7 +434,7 @@ __device__ __forceinline__ double q4_config_from_objects(const Q4Kin& kin, const
         for (int oq = 0; oq < 2; ++oq) {
             const cplx<double>* X = ob[qidx(gb, oq)];
             const cplx<double> A = q4_v3_dot(X, Pg[gb], ga ? e2 : e1, q4_kg(kin, ga), K, eK[ga], qq_dot(X, K));
-            q4_project(d++, q4_scale(A, rPg[gb] * rQ2), proj);
+            q4_basis_add(d++, q4_scale(A, rPg[gb] * rQ2), bsum);
         }
     }
     __builtin_amdgcn_sched_barrier(0);
@@ -443,31 +443,31 @@ __device__ __forceinline__ double q4_config_from_objects(const Q4Kin& kin, const
     for (int ga = 0; ga < 2; ++ga)                      // terms 24-27
 #pragma unroll
         for (int ot = 0; ot < 2; ++ot)
-            q4_project(d++, q4_scale(qq_dot(ob[vidx(ga)], ob[tidx(1 - ga, ot)]), rP02 * rPg[ga]), proj);
+            q4_basis_add(d++, q4_scale(qq_dot(ob[vidx(ga)], ob[tidx(1 - ga, ot)]), rP02 * rPg[ga]), bsum);
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int ga = 0; ga < 2; ++ga) {                    // terms 28-29
         const int gb = 1 - ga;
         const cplx<double>* V = ob[vidx(ga)];
         const cplx<double> A = q4_v3_dot(V, Pg[ga], gb ? e2 : e1, q4_kg(kin, gb), K, eK[gb], qq_dot(V, K));
-        q4_project(d++, q4_scale(A, rP02 * rPg[ga] * rQ2), proj);
+        q4_basis_add(d++, q4_scale(A, rP02 * rPg[ga] * rQ2), bsum);
     }
     __builtin_amdgcn_sched_barrier(0);
     {                                                   // terms 30-32
         const double e12 = e1[0] * e2[0] - e1[1] * e2[1] - e1[2] * e2[2] - e1[3] * e2[3];
         const double r = rP02 * rQ2;
         const cplx<double> a1 = cmul(q2, eK[0]), a2(qt.x * e12, qt.y * e12), a3 = cmul(q1, eK[1]);
-        q4_project(d++, q4_scale(cplx<double>(a1.x - a2.x, a1.y - a2.y), r), proj);
-        q4_project(d++, q4_scale(cplx<double>(a3.x - a2.x, a3.y - a2.y), r), proj);
-        q4_project(d++, q4_scale(cplx<double>(a3.x - a1.x, a3.y - a1.y), r), proj);
+        q4_basis_add(d++, q4_scale(cplx<double>(a1.x - a2.x, a1.y - a2.y), r), bsum);
+        q4_basis_add(d++, q4_scale(cplx<double>(a3.x - a2.x, a3.y - a2.y), r), bsum);
+        q4_basis_add(d++, q4_scale(cplx<double>(a3.x - a1.x, a3.y - a1.y), r), bsum);
     }
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int oq = 0; oq < 2; ++oq)                      // terms 33-34
-        q4_project(d++, q4_scale(qq_dot(ob[kQ4Q7 + 16 * oq + bq], K), rQ2), proj);
+        q4_basis_add(d++, q4_scale(qq_dot(ob[kQ4Q7 + 16 * oq + bq], K), rQ2), bsum);
 #pragma unroll
     for (int ot = 0; ot < 2; ++ot)                      // terms 35-36
-        q4_project(d++, q4_scale(qq_dot(J, ob[kQ4T7 + 16 * ot + bt]), rP02), proj);
+        q4_basis_add(d++, q4_scale(qq_dot(J, ob[kQ4T7 + 16 * ot + bt]), rP02), bsum);
     __builtin_amdgcn_sched_barrier(0);
     {                                                   // term 37: v3(J, P0, J12, K) . K
         const cplx<double>* J12 = j12[(l1 << 1) | l2];
@@ -480,9 +480,9 @@ __device__ __forceinline__ double q4_config_from_objects(const Q4Kin& kin, const
         }
         const cplx<double> t1 = cmul(qq_dot(J, J12), qq_dotr(K, Pk)), t2 = cmul(qq_dot(J12, K), qq_dotr(J, P2k));
         const cplx<double> t3 = cmul(qt, qq_dotr(J12, k2P));
-        q4_project(d++, q4_scale(cplx<double>(t1.x + t2.x + t3.x, t1.y + t2.y + t3.y), rP02 * rQ2), proj);
+        q4_basis_add(d++, q4_scale(cplx<double>(t1.x + t2.x + t3.x, t1.y + t2.y + t3.y), rP02 * rQ2), bsum);
     }
-    return q4_colour_sum(proj);
+    return q4_colour_sum(bsum);
 }
 
 __host__ __device__ __forceinline__ Q4Kin q4_kinematics(const double* mom, double eb, double mt, double mw)
