@@ -103,6 +103,39 @@ def test_event_weights_match_oracle(api, pp_table, process, precision, bar):
     assert np.mean(np.abs(q_o) > 1e-3 * np.abs(w_og[use])) > 0.9
 
 
+def test_pp_ttxgg_1e6_sampled_events_and_properties(api, pp_table):
+    """p p -> t tbar g g at the size bench.py times (1e6 events per
+    iteration, the live-event lists and the one-wave-per-event q qbar
+    kernel as launched there): 1500 events sampled over the whole second
+    iteration against the oracle on that iteration's grid, and on all events
+    finite weights, one nonzero weight per passing event and the mean equal
+    to the iteration's estimate."""
+    import torch
+    n_g, cuts = 4, CASES["pp_ttxgg"][1]
+    proc = api.Process("pp_ttxgg", **cuts)
+    N = 1_000_000
+    g1 = api.integrate(proc, SQRT_S, pp_table, N, 1, 0, keep_weights=False).grid
+    r = api.integrate(proc, SQRT_S, pp_table, N, 2, 0, keep_weights=True)
+    w = r.weights
+    assert torch.isfinite(w).all()
+    assert int((w != 0).sum()) == r.n_pass
+    assert float(w.sum().item()) / N == pytest.approx(r.iter_sigma[-1], rel=1e-12)
+    ids = np.sort(np.random.default_rng(12).choice(N, size=1500, replace=False))
+    w_o, flags, kap = O.event_weights(O.Process(n_g=n_g, initial="pp", **cuts), SQRT_S, pp_table, g1, 0, 1, ids,
+                                      return_kappa=True)
+    w_og, _ = O.event_weights(O.Process(n_g=n_g, **cuts), SQRT_S, pp_table, g1, 0, 1, ids)
+    wg = w[torch.as_tensor(ids, device=w.device)].cpu().numpy()
+    skip = (flags & (8 | 16)) != 0
+    zero = (w_o == 0.0) & ~skip
+    assert np.all(wg[zero] == 0.0)
+    use = ~skip & ~zero
+    rel = np.abs(wg - w_o)[use] / (np.abs(w_og) + np.abs(w_o - w_og))[use]
+    limit = np.where((flags[use] & 64) != 0, np.maximum(1e-12, newton_bar(kap[use], n_g)), 1e-12)
+    say(f"\n  p p -> t tbar g g 1e6: {int(use.sum())} of 1500 sampled events up to id {ids.max()}, "
+        f"max rel {rel.max():.2e}, {int(skip.sum())} at a cut edge or ill-conditioned")
+    assert use.sum() > 1000 and np.all(rel <= limit)
+
+
 @pytest.mark.parametrize("process", sorted(CASES))
 def test_integration_matches_oracle(api, pp_table, process):
     n_g, cuts, _, n = CASES[process]
