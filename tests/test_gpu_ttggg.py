@@ -180,6 +180,35 @@ def test_leading_colour_integration_matches_oracle(api, pdf_table):
     assert g.n_pass == o.n_pass
 
 
+@pytest.mark.parametrize("colour", ["full", "leading"])
+def test_1e6_sampled_events_and_properties(api, pdf_table, colour):
+    """At the size bench.py times (1e6 events per iteration in 31 batches
+    of up to 32 768): 400 events sampled over the second iteration against
+    the oracle on that iteration's grid; on all events finite weights, one
+    nonzero weight per passing event and the mean equal to the iteration's
+    estimate."""
+    import torch
+    N = 1_000_000
+    g1 = api.integrate(gproc(api), SQRT_S, pdf_table, N, 1, 0, keep_weights=False, colour=colour).grid
+    r = api.integrate(gproc(api), SQRT_S, pdf_table, N, 2, 0, keep_weights=True, colour=colour)
+    w = r.weights
+    assert torch.isfinite(w).all()
+    assert int((w != 0).sum()) == r.n_pass
+    assert float(w.sum().item()) / N == pytest.approx(r.iter_sigma[-1], rel=1e-12)
+    ids = np.sort(np.random.default_rng(13).choice(N, size=400, replace=False))
+    w_o, flags, kap = O.event_weights(oproc(colour=colour), SQRT_S, pdf_table, g1, 0, 1, ids, return_kappa=True)
+    wg = w[torch.as_tensor(ids, device=w.device)].cpu().numpy()
+    skip = (flags & (8 | 16)) != 0
+    zero = (w_o == 0.0) & ~skip
+    assert np.all(wg[zero] == 0.0)
+    use = ~skip & ~zero
+    rel = np.abs(wg - w_o)[use] / np.abs(w_o[use])
+    limit = np.where((flags[use] & 64) != 0, np.maximum(1e-12, newton_bar(kap[use], 5)), 1e-12)
+    say(f"\n  t tbar g g g {colour} colour 1e6: {int(use.sum())} of 400 sampled events up to id {ids.max()}, "
+        f"max rel {rel.max():.2e}, {r.n_batches} batches")
+    assert use.sum() > 250 and np.all(rel <= limit)
+
+
 def test_unsupported_requests(api, pdf_table):
     from paper_2106_10279_amd import _lib as L
     for kw in (dict(colour="sampled"), dict(colour="flow"), dict(helicity="sampled"),
